@@ -1,0 +1,90 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+Holds no arithmetic of the solver: it only produces densities, Dirichlet
+masks, loads and random vectors.  Conventions: node (i,j,k) has index
+i + (nx+1)*(j + (ny+1)*k), DOF 3*node + c, element ex + nx*(ey + ny*ez).
+
+Recipes (the paper uses no external dataset, Sec. 6 data statement):
+  * uniform cantilever: rho = 0.5 everywhere (Sec. 4.4, E2), x = 0 face
+    clamped, unit -z load spread over the nodes (nx, j, 0);
+  * Gaussian random field: N(0,1) white noise per element from
+    numpy.random.default_rng(seed), separable Gaussian filter with standard
+    deviation ``corr_len`` elements (truncate 4 sigma, reflecting boundary),
+    standardised, then rho = rho_min + (1 - rho_min) / (1 + exp(-gain * g));
+  * random face loads: on one of the five unclamped faces, k random nodes
+    with random unit directions, scaled to unit total magnitude.
+"""
+import numpy as np
+
+
+def n_nodes(dims):
+    nx, ny, nz = dims
+    return (nx + 1) * (ny + 1) * (nz + 1)
+
+
+def n_elems(dims):
+    nx, ny, nz = dims
+    return nx * ny * nz
+
+
+def uniform_rho(dims, value=0.5):
+    return np.full(n_elems(dims), float(value))
+
+
+def cantilever_fixed(dims):
+    """uint8 mask over all DOFs, 1 where the node lies on the x = 0 face."""
+    nx, ny, nz = dims
+    i = np.arange(n_nodes(dims)) % (nx + 1)
+    return np.repeat((i == 0).astype(np.uint8), 3)
+
+
+def edge_load(dims):
+    nx, ny, nz = dims
+    f = np.zeros(3 * n_nodes(dims))
+    for j in range(ny + 1):
+        f[3 * (nx + (nx + 1) * j) + 2] = -1.0 / (ny + 1)
+    return f
+
+
+def grf_rho(dims, seed, corr_len=4.0, gain=3.0, rho_min=1e-3):
+    from scipy.ndimage import gaussian_filter
+    nx, ny, nz = dims
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((nz, ny, nx))
+    g = gaussian_filter(g, sigma=corr_len, mode="reflect", truncate=4.0)
+    g = (g - g.mean()) / max(g.std(), 1e-300)
+    rho = rho_min + (1.0 - rho_min) / (1.0 + np.exp(-gain * g))
+    return rho.reshape(-1)
+
+
+def random_face_load(dims, rng, max_nodes=8):
+    """One load case: k ~ U{1..max_nodes} nodes on a random unclamped face."""
+    nx, ny, nz = dims
+    face = int(rng.integers(0, 5))
+    f = np.zeros(3 * n_nodes(dims))
+    k = int(rng.integers(1, max_nodes + 1))
+    for _ in range(k):
+        a, b = rng.integers(0, 10**9, size=2)
+        if face == 0:
+            i, j, kk = nx, a % (ny + 1), b % (nz + 1)
+        elif face == 1:
+            i, j, kk = 1 + a % nx, 0, b % (nz + 1)
+        elif face == 2:
+            i, j, kk = 1 + a % nx, ny, b % (nz + 1)
+        elif face == 3:
+            i, j, kk = 1 + a % nx, b % (ny + 1), 0
+        else:
+            i, j, kk = 1 + a % nx, b % (ny + 1), nz
+        v = rng.standard_normal(3)
+        v /= np.linalg.norm(v)
+        node = i + (nx + 1) * (j + (ny + 1) * kk)
+        f[3 * node:3 * node + 3] += v
+    return f / np.linalg.norm(f.reshape(-1, 3).sum(axis=0)) if np.linalg.norm(f.reshape(-1, 3).sum(axis=0)) > 1e-12 else f / np.abs(f).sum()
+
+
+def random_vector(n, seed, fixed=None):
+    """Standard normal vector, zero on fixed DOFs when a mask is given."""
+    v = np.random.default_rng(seed).standard_normal(n)
+    if fixed is not None:
+        v[np.asarray(fixed).astype(bool)] = 0.0
+    return v
