@@ -1,0 +1,174 @@
+/*
+ * simpgmg.h - C ABI of the MI355X (gfx950) matrix-free Galerkin multigrid
+ * PCG solver for 3D hex8 SIMP linear elasticity.
+ *
+ * Method (arXiv:2604.26441):
+ *   Sec. 3.1 (Eq. simp_filter, Eq. state_eq): E_e = Emin + (E0 - Emin) rho_e^p,
+ *     K = sum_e E_e K_e, solve the free-DOF system K_ff u_f = f_f.
+ *   Sec. 3.2 (Eq. vcycle): V-cycle preconditioner.
+ *   Sec. 3.3 (Eq. trilinear_weights, vector_prolongation, mf_matvec,
+ *     galerkin_level1): 2:1 trilinear transfers, Dirichlet masks inherited by
+ *     injection, matrix-free level 0, level 1 by local Galerkin aggregation,
+ *     deeper levels by Galerkin triple products.
+ *   Sec. 3.4 (Alg. cheb): Chebyshev-Jacobi smoother; Sec. 3.5: precision
+ *     descent, BF16 semantics, power-iteration lambda_max estimates.
+ *   Sec. 3.6: outer PCG, acceptance on the true relative residual.
+ *
+ * Conventions shared by every entry point
+ *   Mesh: nx*ny*nz unit hexahedra.  Node (i,j,k) has index
+ *     i + (nx+1)*(j + (ny+1)*k); DOF index 3*node + c, c in {x,y,z}.
+ *     Element (ex,ey,ez) has index ex + nx*(ey + ny*ez).
+ *   Vectors: device pointers in the full-DOF layout of their level, length
+ *     3*(nx+1)*(ny+1)*(nz+1).  Fixed (Dirichlet) DOFs carry zeros on input
+ *     and are written as zeros on output; the operators act as M K M with M
+ *     the free-DOF selector, which is the free-DOF system K_ff in full-length
+ *     form.
+ *   Ownership: the caller allocates and owns every vector passed in.  The
+ *     library allocates the hierarchy (operators, work vectors, scratch) in
+ *     setup and frees it in sgmg_destroy.  No pointer passed in is retained
+ *     after a call returns.
+ *   Streams: every call is ordered on the given HIP stream (0 = the null
+ *     stream).  sgmg_setup_hierarchy and sgmg_update_moduli synchronise the
+ *     stream before returning; sgmg_pcg_solve synchronises at every outer
+ *     iteration to read the residual; sgmg_apply_K and sgmg_vcycle are
+ *     asynchronous.  Calls on one hierarchy must not overlap.
+ *   Errors: 0 = success; SGMG_EINVAL (-1) invalid argument or a mesh that
+ *     cannot be coarsened to the requested depth; SGMG_EHIP (-2) a HIP runtime
+ *     error; SGMG_ENOMEM (-3) device allocation failed; SGMG_EFACTOR (-4) the
+ *     coarsest factorisation met a non-positive pivot after regularisation.
+ *     sgmg_last_error() returns a thread-local message for the last failure.
+ *     Non-convergence of a solve is not an error: it is reported in
+ *     sgmg_solve_info.status.
+ */
+#ifndef SIMPGMG_H
+#define SIMPGMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SGMG_EINVAL  (-1)
+#define SGMG_EHIP    (-2)
+#define SGMG_ENOMEM  (-3)
+#define SGMG_EFACTOR (-4)
+
+/* Arithmetic of an operator application.
+ *   F64    : FP64 vectors and arithmetic.
+ *   F32    : FP32 vectors, FP32 vector-ALU arithmetic.
+ *   BF16   : FP32 vectors; element input tile rounded to BF16, element matrix
+ *            exact in BF16, FP32 accumulation on MFMA, E_e applied in FP32
+ *            (Sec. 3.5, BF16 numerical semantics).  Level 0 only.
+ *   BF16X3 : FP32 vectors; the input tile is split into three BF16 terms whose
+ *            sum carries the FP32 significand, each term multiplied on MFMA
+ *            with FP32 accumulation (FP32-accurate).  Level 0 only.       */
+typedef enum { SGMG_F64 = 0, SGMG_F32 = 1, SGMG_BF16 = 2, SGMG_BF16X3 = 3 } sgmg_prec;
+
+/* Solve status (Sec. 3.6 failure classes). */
+typedef enum {
+  SGMG_CONVERGED = 0,  /* FP64 true relative residual below rtol            */
+  SGMG_MAXIT = 1,      /* iteration cap reached                              */
+  SGMG_STAGNATED = 2,  /* stagnation window enabled and tripped              */
+  SGMG_NONFINITE = 3,  /* a non-finite scalar or residual appeared           */
+  SGMG_BREAKDOWN = 4   /* p.q <= 0 or r.z <= 0                               */
+} sgmg_status;
+
+typedef struct {
+  int nx, ny, nz;            /* elements per axis, each >= 1                         */
+  double nu, E0, Emin, penal;/* Poisson ratio 0.3, E0 1, Emin 1e-9, SIMP penalty p   */
+  int input_is_modulus;      /* 0: the setup array is rho (SIMP map applied);
+                                1: it is E_e directly                                */
+  int n_levels;              /* >= 2; 0 = fewest levels whose coarsest free-DOF
+                                count is <= dense_max (at most 8)                    */
+  int fine_smoother;         /* 0 Chebyshev (Alg. cheb), 1 damped Jacobi             */
+  int fine_degree;           /* Chebyshev degree / Jacobi sweeps on level 0 (2)      */
+  int coarse_sweeps;         /* damped-Jacobi pre and post sweeps on levels >= 1 (2) */
+  double cheb_alpha;         /* lower end of the Chebyshev interval, 1/30            */
+  double jacobi_omega_max;   /* damping cap 0.5; omega = min(cap, 4/(3 lambda))      */
+  double lambda_safety;      /* smoothers use lambda_safety * estimate (1.1)         */
+  int power_iters_fine;      /* power iterations on level 0 (20)                     */
+  int power_iters_coarse;    /* power iterations on levels >= 1 (10)                 */
+  sgmg_prec fine_prec;       /* level-0 smoother/residual arithmetic                 */
+  sgmg_prec level1_prec;     /* F64 or F32: storage and arithmetic of level 1        */
+  int dense_max;             /* coarsest dense-solve limit on free DOFs (5000)       */
+  int coarse_pcg_iters;      /* reserved: iterative coarsest solve (80)              */
+  uint64_t seed;             /* power-iteration start vector: SplitMix64(seed+level) */
+  int flexible_beta;         /* 1: Polak-Ribiere beta in PCG, 0: Fletcher-Reeves     */
+  int stag_window;           /* 0 = off; else stagnation window in iterations        */
+  const double* lambda_override; /* host array of n_levels-1 raw estimates, or NULL  */
+} sgmg_options;
+
+typedef struct {
+  int status;                /* sgmg_status                                          */
+  int iters;                 /* outer PCG iterations (products with K on level 0)    */
+  double rel_res_true;       /* ||f - K u||_2 / ||f||_2 in FP64 at exit              */
+  double rel_res_recur;      /* recursive residual norm / ||f|| at exit              */
+  double* history;           /* caller-owned host buffer of history_cap doubles, or
+                                NULL; entry k = recursive ||r_k|| / ||f||            */
+  int history_cap;
+  double solve_ms;           /* wall time of the solve on the stream (HIP events)    */
+} sgmg_solve_info;
+
+typedef struct sgmg_hierarchy sgmg_hierarchy;
+
+/* Fills *o with the paper's defaults (Table repro_defaults) for an nx*ny*nz
+ * mesh: nu 0.3, E0 1, Emin 1e-9, p 3, 4 levels, Chebyshev degree 2, 2 coarse
+ * sweeps, alpha 1/30, omega cap 0.5, 20/10 power iterations, level-0 F32,
+ * level-1 F64, dense_max 5000, seed 0, lambda_safety 1.1. */
+void sgmg_default_options(sgmg_options* o, int nx, int ny, int nz);
+
+/* Builds the hierarchy for one frozen modulus field (Sec. 3.3, 3.5).
+ *   rho_or_E : device, nx*ny*nz doubles in element order (rho in [0,1] or E_e).
+ *   fixed_dof: device, 3*n_nodes bytes, nonzero = DOF fixed; NULL = clamp the
+ *              x = 0 face (cantilever).
+ *   out      : receives the handle (NULL on failure).
+ * Work: SIMP map, masks by injection, diagonals, level-1 local Galerkin
+ * aggregation, deeper Galerkin products, power iterations, coarsest dense
+ * factorisation (explicit inverse of K_L + eps I, eps = max(mean diag * 1e-8,
+ * 1e-14)).  Returns SGMG_EINVAL if a coarse level would have no elements or
+ * the coarsest free-DOF count exceeds dense_max. */
+int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E,
+                         const uint8_t* fixed_dof, void* stream, sgmg_hierarchy** out);
+
+/* Re-assembles every E-dependent operator for a new field on the same mesh
+ * and masks; lambda estimates are recomputed only if max_e E_e moved by more
+ * than 10% since they were last estimated (Sec. 3.5). */
+int sgmg_update_moduli(sgmg_hierarchy* h, const double* rho_or_E, void* stream);
+
+/* y = M K^level M u.  level 0: the matrix-free fine operator in precision
+ * prec (u, y are double* for F64, float* otherwise).  level >= 1: the stored
+ * Galerkin operator; prec must be F64 (double vectors) or F32 (float vectors),
+ * F32 only if that level is stored in FP32.  u and y must not alias. */
+int sgmg_apply_K(const sgmg_hierarchy* h, int level, sgmg_prec prec,
+                 const void* u, void* y, void* stream);
+
+/* z = V(r): one V-cycle of Eq. vcycle on level 0 (double vectors). */
+int sgmg_vcycle(const sgmg_hierarchy* h, const double* r, double* z, void* stream);
+
+/* PCG on K u = f (Sec. 3.6).  precond: 0 none, 1 Jacobi (D^-1 of level 0),
+ * 2 the V-cycle.  u: in = x0 (zeros for a cold start), out = the iterate at
+ * exit.  Converged only if the FP64 true residual passes rtol; the recursive
+ * residual triggers the check and a failed check replaces r by the true
+ * residual.  info may be NULL. */
+int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u,
+                   double rtol, int maxit, sgmg_solve_info* info, void* stream);
+
+/* Introspection for tests and reports. */
+int sgmg_num_levels(const sgmg_hierarchy* h);
+/* dims[3] elements of level l, free DOF count, raw lambda estimate. */
+int sgmg_level_info(const sgmg_hierarchy* h, int level, int* dims, int* n_free, double* lambda);
+/* Copies the level's 27-point block stencil (level >= 1) to a host buffer of
+ * 243*n_nodes doubles laid out [o][d][d'][node], o = (ox+1)+3(oy+1)+9(oz+1),
+ * entry = K[3*node+d, 3*(node+o)+d']. */
+int sgmg_copy_stencil(const sgmg_hierarchy* h, int level, double* host_out);
+/* Copies diag(K^level) (zeros on fixed DOFs) to a host buffer. */
+int sgmg_copy_diagonal(const sgmg_hierarchy* h, int level, double* host_out);
+
+void sgmg_destroy(sgmg_hierarchy* h);
+const char* sgmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIMPGMG_H */

@@ -1,0 +1,96 @@
+// Host-side launchers of the HIP kernels (one declaration per entry).
+#pragma once
+#include "common.hpp"
+
+namespace sgmg {
+
+// ---- fine level (kernels_fine.hip) -----------------------------------------
+void launch_simp(const double* in, double* E64, float* E32, int nel, int is_modulus,
+                 double E0, double Emin, double p, hipStream_t s);
+void launch_mask_from_dofs(const uint8_t* fixed_dof, uint8_t* fixn, int Nn, hipStream_t s);
+void launch_mask_cantilever(const Grid& g, uint8_t* fixn, hipStream_t s);
+void launch_mask_inject(const Grid& fine, const Grid& coarse, const uint8_t* ffix,
+                        uint8_t* cfix, hipStream_t s);
+void launch_diag_fine(const Grid& g, const double* E, const double* ke, const uint8_t* fixn,
+                      double* d, hipStream_t s);
+template <typename T>
+void launch_apply_fine_node(const Grid& g, const T* E, const T* ke, const T* u,
+                            const uint8_t* fixn, const Epi<T>& ep, hipStream_t s);
+// Fixed-point/BF16 MFMA element kernel (kernels_mfma.hip); nsplit = 1 or 3.
+void launch_apply_fine_mfma(const Grid& g, int nsplit, const float* Escaled, const void* kbf16,
+                            const float* u, const uint8_t* fixn, const Epi<float>& ep,
+                            hipStream_t s);
+size_t apply_fine_mfma_blocks(const Grid& g);
+
+// ---- stencil levels (kernels_stencil.hip) ----------------------------------
+// Level-1 Galerkin aggregation: S1 = M1 sum_e E_e P_e^T (M_e K_e M_e) P_e M1.
+// gtab: 27 pattern products G_p = P_p^T K_e P_p (24x24 each, pattern index
+// px + 3 py + 9 pz), ke: K_e for the masked-child path.
+void launch_galerkin_l1(const Grid& fine, const Grid& coarse, const double* E,
+                        const double* gtab, const double* ke, const uint8_t* ffix,
+                        const uint8_t* cfix, double* S, hipStream_t s);
+void launch_galerkin_stencil(const Grid& fine, const Grid& coarse, const double* Sf,
+                             const uint8_t* cfix, double* Sc, hipStream_t s);
+void launch_stencil_diag(const Grid& g, const double* S, double* d, hipStream_t s);
+void launch_stencil_to_f32(const double* S, float* S32, size_t n, hipStream_t s);
+template <typename T>
+void launch_stencil_apply(const Grid& g, const T* S, const T* u, const uint8_t* fixn,
+                          const Epi<T>& ep, hipStream_t s);
+size_t stencil_apply_blocks(const Grid& g);
+// Restriction b_c = M_c P^T r_f; optionally x_c = c0 * Dinv_c * b_c (first
+// smoothing step from zero) and d_c = x_c.
+template <typename TF, typename TC>
+void launch_restrict(const Grid& fine, const Grid& coarse, const TF* rf, const uint8_t* cfix,
+                     TC* bc, const TC* dinv_c, double c0, TC* xc, TC* dc, hipStream_t s);
+// Prolongation x_f += M_f P e_c.
+template <typename TF, typename TC>
+void launch_prolong_add(const Grid& fine, const Grid& coarse, const TC* ec, const uint8_t* ffix,
+                        TF* xf, hipStream_t s);
+
+// ---- vectors and reductions (kernels_vec.hip) ------------------------------
+void launch_power_start(double* x, const uint8_t* fixn, int Nn, uint64_t seed, hipStream_t s);
+// out[0] = sum a*b (b == NULL: sum a*a; w != NULL: sum w*a*b)
+void launch_dot(const double* a, const double* b, const double* w, int n, RedWs ws,
+                double* out, hipStream_t s);
+// y = Dinv * w ; out = ||y||^2
+void launch_scale_dinv_norm(const double* dinv, const double* w, double* y, int n, RedWs ws,
+                            double* out, hipStream_t s);
+// x = y / sqrt(*nrm2)
+void launch_normalize(const double* y, const double* nrm2, double* x, int n, hipStream_t s);
+// V-cycle entry on level 0: b = (T) r ; d = c0 * Dinv * b ; x = d
+template <typename T>
+void launch_vcycle_entry(const double* r, T* b, const T* dinv, double c0, T* x, T* d, int n,
+                         hipStream_t s);
+void launch_d2f(const double* in, float* out, int n, hipStream_t s);
+void launch_f2d(const float* in, double* out, int n, hipStream_t s);
+void launch_copy(const double* in, double* out, int n, hipStream_t s);
+
+// PCG pieces; sc = device scalar block (see runtime.hip for slots)
+void launch_pcg_init(const double* f, const double* Ax0, int have_x0, double* r, int n,
+                     RedWs ws, double* sc_ff_rr, hipStream_t s);
+void launch_pcg_update_xr(double* x, double* r, double* r_old, const double* p, const double* q,
+                          const double* sc, int slot_rz, int slot_pq, int n, RedWs ws,
+                          double* sc_rr, hipStream_t s);
+void launch_pcg_dot_rz(const double* r, const double* z, const double* r_old, int n, RedWs ws,
+                       double* sc_out2, hipStream_t s);
+void launch_pcg_update_p(double* p, const double* z, const double* sc, int slot_num,
+                         int slot_sub, int slot_den, int n, hipStream_t s);
+// *out = max over (free) entries of a non-negative vector (fixn may be NULL)
+void launch_max_nonneg(const double* a, const uint8_t* fixn, int n, double* out, hipStream_t s);
+void launch_diag_finalize(double* d, double* dinv64, float* dinv32, const uint8_t* fixn, int n,
+                          const double* dmax, hipStream_t s);
+void launch_apply_dinv(const double* dinv, const double* r, double* z, int n, hipStream_t s);
+void launch_residual(const double* f, const double* Ax, double* r, int n, RedWs ws,
+                     double* out_rr, hipStream_t s);
+
+// ---- coarsest dense solve (kernels_dense.hip) ------------------------------
+void launch_dense_assemble(const Grid& g, const double* S, const int* free_idx, int nf,
+                           double* A, hipStream_t s);
+void launch_dense_add_diag(double* A, int nf, const double* mean_diag_sum, hipStream_t s,
+                           double* eps_out);
+void launch_dense_diag_sum(const double* A, int nf, RedWs ws, double* out, hipStream_t s);
+int dense_spd_inverse(double* A, int nf, double* scratch, int* d_flag, hipStream_t s);
+void launch_dense_solve(const double* Ainv, const int* free_idx, int nf, const double* r,
+                        double* rc, double* z, hipStream_t s);
+
+}  // namespace sgmg

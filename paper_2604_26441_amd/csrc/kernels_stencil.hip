@@ -1,0 +1,365 @@
+// Galerkin levels (l >= 1): assembly into a structured 27-point block
+// stencil, its application, and the trilinear transfer kernels.
+#include "kernels.hpp"
+
+namespace sgmg {
+
+// 1D local pattern of a fine element inside its coarse element (Sec. 3.3):
+// pattern p = fine index - 2 * coarse index in {0, 1, 2}; entry [dx][cx] is
+// the weight of coarse local node cx at fine local node dx.  Pattern 2 is the
+// last fine element of an odd axis, whose two nodes both map onto the last
+// coarse node (trailing-node weight 1).
+__device__ __constant__ double c_pat[3][2][2] = {
+    {{1.0, 0.0}, {0.5, 0.5}}, {{0.5, 0.5}, {0.0, 1.0}}, {{0.0, 1.0}, {0.0, 1.0}}};
+
+__device__ inline bool elem_has_fixed(const Grid& f, const uint8_t* ffix, int ex, int ey, int ez) {
+  unsigned any = 0;
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+    any |= ffix[(ex + (a & 1)) + f.Nx * ((ey + ((a >> 1) & 1)) + f.Ny * (ez + (a >> 2)))];
+  return any != 0;
+}
+
+// Level-1 Galerkin aggregation (Eq. galerkin_level1).  Thread (I, o) owns the
+// 3x3 block K^1[I, I+o]: it visits the coarse elements that contain both
+// nodes and their fine children, adding E_child * G_p[rows of I, cols of J]
+// where G_p = P_p^T K_e P_p is the precomputed local triple product of the
+// child's pattern.  Children touching a fixed fine DOF use M_e K_e M_e,
+// formed on the fly.  Finally rows/columns of fixed coarse DOFs are zeroed.
+__global__ __launch_bounds__(256) void k_galerkin_l1(Grid f, Grid c, const double* __restrict__ E,
+                                                     const double* __restrict__ gtab,
+                                                     const double* __restrict__ ke,
+                                                     const uint8_t* __restrict__ ffix,
+                                                     const uint8_t* __restrict__ cfix,
+                                                     double* __restrict__ S) {
+  const int I = blockIdx.x * 256 + threadIdx.x;
+  const int o = blockIdx.y;
+  if (I >= c.Nn) return;
+  const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+  const int Ix = I % c.Nx, t = I / c.Nx, Iy = t % c.Ny, Iz = t / c.Ny;
+  const int Jx = Ix + ox, Jy = Iy + oy, Jz = Iz + oz;
+  double acc[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+  const bool jok = (unsigned)Jx < (unsigned)c.Nx && (unsigned)Jy < (unsigned)c.Ny &&
+                   (unsigned)Jz < (unsigned)c.Nz;
+  if (jok) {
+    // coarse elements containing both I and J, per axis
+    const int cx0 = max(max(Ix, Jx) - 1, 0), cx1 = min(min(Ix, Jx), c.nx - 1);
+    const int cy0 = max(max(Iy, Jy) - 1, 0), cy1 = min(min(Iy, Jy), c.ny - 1);
+    const int cz0 = max(max(Iz, Jz) - 1, 0), cz1 = min(min(Iz, Jz), c.nz - 1);
+    for (int cz = cz0; cz <= cz1; ++cz)
+      for (int cy = cy0; cy <= cy1; ++cy)
+        for (int cx = cx0; cx <= cx1; ++cx) {
+          const int aI = (Ix - cx) + 2 * (Iy - cy) + 4 * (Iz - cz);
+          const int aJ = (Jx - cx) + 2 * (Jy - cy) + 4 * (Jz - cz);
+          const int npx = (cx == c.nx - 1 && (f.nx & 1)) ? 3 : 2;
+          const int npy = (cy == c.ny - 1 && (f.ny & 1)) ? 3 : 2;
+          const int npz = (cz == c.nz - 1 && (f.nz & 1)) ? 3 : 2;
+          for (int pz = 0; pz < npz; ++pz)
+            for (int py = 0; py < npy; ++py)
+              for (int px = 0; px < npx; ++px) {
+                const int ex = 2 * cx + px, ey = 2 * cy + py, ez = 2 * cz + pz;
+                const double Ee = E[ex + f.nx * (ey + f.ny * ez)];
+                const int p = px + 3 * py + 9 * pz;
+                if (!elem_has_fixed(f, ffix, ex, ey, ez)) {
+                  const double* G = gtab + (size_t)p * 576;
+#pragma unroll
+                  for (int d = 0; d < 3; ++d)
+#pragma unroll
+                    for (int e = 0; e < 3; ++e)
+                      acc[3 * d + e] += Ee * G[(3 * aI + d) * 24 + 3 * aJ + e];
+                } else {
+                  // masked child: sum_{alpha,beta} W(alpha,aI) W(beta,aJ) m K_e m
+                  for (int al = 0; al < 8; ++al) {
+                    const double wa = c_pat[px][al & 1][aI & 1] *
+                                      c_pat[py][(al >> 1) & 1][(aI >> 1) & 1] *
+                                      c_pat[pz][al >> 2][aI >> 2];
+                    if (wa == 0.0) continue;
+                    const unsigned fa = ffix[(ex + (al & 1)) + f.Nx * ((ey + ((al >> 1) & 1)) +
+                                                                        f.Ny * (ez + (al >> 2)))];
+                    for (int be = 0; be < 8; ++be) {
+                      const double wb = c_pat[px][be & 1][aJ & 1] *
+                                        c_pat[py][(be >> 1) & 1][(aJ >> 1) & 1] *
+                                        c_pat[pz][be >> 2][aJ >> 2];
+                      if (wb == 0.0) continue;
+                      const unsigned fb =
+                          ffix[(ex + (be & 1)) +
+                               f.Nx * ((ey + ((be >> 1) & 1)) + f.Ny * (ez + (be >> 2)))];
+                      for (int d = 0; d < 3; ++d) {
+                        if ((fa >> d) & 1u) continue;
+                        for (int e = 0; e < 3; ++e) {
+                          if ((fb >> e) & 1u) continue;
+                          acc[3 * d + e] += Ee * wa * wb * ke[(3 * al + d) * 24 + 3 * be + e];
+                        }
+                      }
+                    }
+                  }
+                }
+              }
+        }
+  }
+  const unsigned fI = cfix[I];
+  const unsigned fJ = jok ? cfix[Jx + c.Nx * (Jy + c.Ny * Jz)] : 7u;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const bool z = ((fI >> d) & 1u) || ((fJ >> e) & 1u);
+      S[(size_t)(o * 9 + 3 * d + e) * c.Nn + I] = z ? 0.0 : acc[3 * d + e];
+    }
+}
+
+void launch_galerkin_l1(const Grid& fine, const Grid& coarse, const double* E, const double* gtab,
+                        const double* ke, const uint8_t* ffix, const uint8_t* cfix, double* S,
+                        hipStream_t s) {
+  dim3 grid(div_up(coarse.Nn, 256), 27);
+  k_galerkin_l1<<<grid, 256, 0, s>>>(fine, coarse, E, gtab, ke, ffix, cfix, S);
+}
+
+// Deeper Galerkin product K^{l+1} = M P^T K^l P M on stencils (Sec. 3.3).
+// Thread (I, o): sum over fine nodes i interpolating from I (<= 3 per axis)
+// and fine stencil neighbours j of i of w(i,I) w(j,J) K^l[i, j].  K^l is
+// stored masked, so only the coarse mask is applied here.
+__global__ __launch_bounds__(256) void k_galerkin_stencil(Grid f, Grid c,
+                                                          const double* __restrict__ Sf,
+                                                          const uint8_t* __restrict__ cfix,
+                                                          double* __restrict__ Sc) {
+  const int I = blockIdx.x * 256 + threadIdx.x;
+  const int o = blockIdx.y;
+  if (I >= c.Nn) return;
+  const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+  const int Ix = I % c.Nx, t = I / c.Nx, Iy = t % c.Ny, Iz = t / c.Ny;
+  const int Jx = Ix + ox, Jy = Iy + oy, Jz = Iz + oz;
+  double acc[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+  const bool jok = (unsigned)Jx < (unsigned)c.Nx && (unsigned)Jy < (unsigned)c.Ny &&
+                   (unsigned)Jz < (unsigned)c.Nz;
+  if (jok) {
+    for (int iz = 2 * Iz - 1; iz <= 2 * Iz + 1; ++iz) {
+      if (iz < 0 || iz >= f.Nz) continue;
+      const double wz = w1d(iz, Iz, f.nz);
+      if (wz == 0.0) continue;
+      for (int iy = 2 * Iy - 1; iy <= 2 * Iy + 1; ++iy) {
+        if (iy < 0 || iy >= f.Ny) continue;
+        const double wy = w1d(iy, Iy, f.ny);
+        if (wy == 0.0) continue;
+        for (int ix = 2 * Ix - 1; ix <= 2 * Ix + 1; ++ix) {
+          if (ix < 0 || ix >= f.Nx) continue;
+          const double wx = w1d(ix, Ix, f.nx);
+          if (wx == 0.0) continue;
+          const double wi = wx * wy * wz;
+          const int i = ix + f.Nx * (iy + f.Ny * iz);
+          for (int q = 0; q < 27; ++q) {
+            const int jx = ix + q % 3 - 1, jy = iy + (q / 3) % 3 - 1, jz = iz + q / 9 - 1;
+            if ((unsigned)jx >= (unsigned)f.Nx || (unsigned)jy >= (unsigned)f.Ny ||
+                (unsigned)jz >= (unsigned)f.Nz)
+              continue;
+            const double wj = w1d(jx, Jx, f.nx) * w1d(jy, Jy, f.ny) * w1d(jz, Jz, f.nz);
+            if (wj == 0.0) continue;
+            const double w = wi * wj;
+#pragma unroll
+            for (int de = 0; de < 9; ++de) acc[de] += w * Sf[(size_t)(q * 9 + de) * f.Nn + i];
+          }
+        }
+      }
+    }
+  }
+  const unsigned fI = cfix[I];
+  const unsigned fJ = jok ? cfix[Jx + c.Nx * (Jy + c.Ny * Jz)] : 7u;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const bool z = ((fI >> d) & 1u) || ((fJ >> e) & 1u);
+      Sc[(size_t)(o * 9 + 3 * d + e) * c.Nn + I] = z ? 0.0 : acc[3 * d + e];
+    }
+}
+
+void launch_galerkin_stencil(const Grid& fine, const Grid& coarse, const double* Sf,
+                             const uint8_t* cfix, double* Sc, hipStream_t s) {
+  dim3 grid(div_up(coarse.Nn, 256), 27);
+  k_galerkin_stencil<<<grid, 256, 0, s>>>(fine, coarse, Sf, cfix, Sc);
+}
+
+__global__ void k_stencil_diag(Grid g, const double* __restrict__ S, double* __restrict__ d) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.Nn) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) d[3 * n + c] = S[(size_t)(13 * 9 + 4 * c) * g.Nn + n];
+}
+
+void launch_stencil_diag(const Grid& g, const double* S, double* d, hipStream_t s) {
+  k_stencil_diag<<<div_up(g.Nn, 256), 256, 0, s>>>(g, S, d);
+}
+
+__global__ void k_stencil_to_f32(const double* __restrict__ S, float* __restrict__ S32, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) S32[i] = (float)S[i];
+}
+
+void launch_stencil_to_f32(const double* S, float* S32, size_t n, hipStream_t s) {
+  k_stencil_to_f32<<<div_up((long)n, 256), 256, 0, s>>>(S, S32, n);
+}
+
+// y = K^l u on the stored stencil, thread per node, with a fused epilogue.
+template <typename T>
+__global__ __launch_bounds__(256) void k_stencil_apply(Grid g, const T* __restrict__ S,
+                                                       const T* __restrict__ u,
+                                                       const uint8_t* __restrict__ fixn,
+                                                       Epi<T> ep) {
+  const int node = blockIdx.x * 256 + threadIdx.x;
+  double dot = 0.0;
+  if (node < g.Nn) {
+    const int i = node % g.Nx, t = node / g.Nx, j = t % g.Ny, k = t / g.Ny;
+    T acc[3] = {(T)0, (T)0, (T)0};
+#pragma unroll
+    for (int o = 0; o < 27; ++o) {
+      const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+      const bool ok = (unsigned)(i + ox) < (unsigned)g.Nx && (unsigned)(j + oy) < (unsigned)g.Ny &&
+                      (unsigned)(k + oz) < (unsigned)g.Nz;
+      if (!ok) continue;
+      const size_t nb = 3 * (size_t)(node + ox + g.Nx * (oy + g.Ny * oz));
+      const T u0 = u[nb], u1 = u[nb + 1], u2 = u[nb + 2];
+      const T* Sb = S + (size_t)o * 9 * g.Nn + node;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        acc[d] += Sb[(3 * d) * (size_t)g.Nn] * u0 + Sb[(3 * d + 1) * (size_t)g.Nn] * u1 +
+                  Sb[(3 * d + 2) * (size_t)g.Nn] * u2;
+    }
+    const double y[3] = {(double)acc[0], (double)acc[1], (double)acc[2]};
+    const T xo[3] = {u[3 * (size_t)node], u[3 * (size_t)node + 1], u[3 * (size_t)node + 2]};
+    dot = epilogue3(ep, node, fixn[node], xo, y);
+  }
+  if (ep.want_dot) {
+    const double v[1] = {dot};
+    grid_sum<1>(v, ep.ws, ep.dot_out);
+  }
+}
+
+size_t stencil_apply_blocks(const Grid& g) { return div_up(g.Nn, 256); }
+
+template <typename T>
+void launch_stencil_apply(const Grid& g, const T* S, const T* u, const uint8_t* fixn,
+                          const Epi<T>& ep, hipStream_t s) {
+  k_stencil_apply<T><<<div_up(g.Nn, 256), 256, 0, s>>>(g, S, u, fixn, ep);
+}
+template void launch_stencil_apply<double>(const Grid&, const double*, const double*,
+                                           const uint8_t*, const Epi<double>&, hipStream_t);
+template void launch_stencil_apply<float>(const Grid&, const float*, const float*, const uint8_t*,
+                                          const Epi<float>&, hipStream_t);
+
+// Restriction (R = P^T, Eq. vector_prolongation): coarse node I gathers the
+// <= 27 fine nodes that interpolate from it.  Optional fused first smoothing
+// step from a zero iterate: x_c = c0 * Dinv_c * b_c, d_c = x_c.
+template <typename TF, typename TC>
+__global__ void k_restrict(Grid f, Grid c, const TF* __restrict__ rf,
+                           const uint8_t* __restrict__ cfix, TC* __restrict__ bc,
+                           const TC* __restrict__ dinv_c, double c0, TC* __restrict__ xc,
+                           TC* __restrict__ dc) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= c.Nn) return;
+  const int Ix = I % c.Nx, t = I / c.Nx, Iy = t % c.Ny, Iz = t / c.Ny;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int iz = 2 * Iz - 1; iz <= 2 * Iz + 1; ++iz) {
+    if (iz < 0 || iz >= f.Nz) continue;
+    const double wz = w1d(iz, Iz, f.nz);
+    if (wz == 0.0) continue;
+    for (int iy = 2 * Iy - 1; iy <= 2 * Iy + 1; ++iy) {
+      if (iy < 0 || iy >= f.Ny) continue;
+      const double wy = w1d(iy, Iy, f.ny) * wz;
+      if (wy == 0.0) continue;
+      for (int ix = 2 * Ix - 1; ix <= 2 * Ix + 1; ++ix) {
+        if (ix < 0 || ix >= f.Nx) continue;
+        const double w = w1d(ix, Ix, f.nx) * wy;
+        if (w == 0.0) continue;
+        const size_t b = 3 * (size_t)(ix + f.Nx * (iy + f.Ny * iz));
+        acc[0] += w * (double)rf[b];
+        acc[1] += w * (double)rf[b + 1];
+        acc[2] += w * (double)rf[b + 2];
+      }
+    }
+  }
+  const unsigned fx = cfix[I];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const TC v = (fx >> k) & 1u ? (TC)0 : (TC)acc[k];
+    bc[3 * (size_t)I + k] = v;
+    if (xc) {
+      const TC x = (TC)c0 * dinv_c[3 * (size_t)I + k] * v;
+      xc[3 * (size_t)I + k] = x;
+      if (dc) dc[3 * (size_t)I + k] = x;
+    }
+  }
+}
+
+template <typename TF, typename TC>
+void launch_restrict(const Grid& fine, const Grid& coarse, const TF* rf, const uint8_t* cfix,
+                     TC* bc, const TC* dinv_c, double c0, TC* xc, TC* dc, hipStream_t s) {
+  k_restrict<TF, TC><<<div_up(coarse.Nn, 256), 256, 0, s>>>(fine, coarse, rf, cfix, bc, dinv_c,
+                                                            c0, xc, dc);
+}
+template void launch_restrict<float, double>(const Grid&, const Grid&, const float*,
+                                             const uint8_t*, double*, const double*, double,
+                                             double*, double*, hipStream_t);
+template void launch_restrict<float, float>(const Grid&, const Grid&, const float*,
+                                            const uint8_t*, float*, const float*, double, float*,
+                                            float*, hipStream_t);
+template void launch_restrict<double, double>(const Grid&, const Grid&, const double*,
+                                              const uint8_t*, double*, const double*, double,
+                                              double*, double*, hipStream_t);
+template void launch_restrict<double, float>(const Grid&, const Grid&, const double*,
+                                             const uint8_t*, float*, const float*, double,
+                                             float*, float*, hipStream_t);
+
+// Prolongation and correction x_f += M_f P e_c: fine node i reads the <= 8
+// coarse nodes it interpolates from.
+template <typename TF, typename TC>
+__global__ void k_prolong_add(Grid f, Grid c, const TC* __restrict__ ec,
+                              const uint8_t* __restrict__ ffix, TF* __restrict__ xf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= f.Nn) return;
+  const int ix = i % f.Nx, t = i / f.Nx, iy = t % f.Ny, iz = t / f.Ny;
+  int cx[2], cy[2], cz[2];
+  double wx[2], wy[2], wz[2];
+  auto cand = [](int fi, int nf, int* ci, double* w) {
+    const int nc = nf >> 1;
+    if ((fi & 1) == 0) { ci[0] = fi >> 1; w[0] = 1.0; ci[1] = 0; w[1] = 0.0; }
+    else if (fi < 2 * nc) { ci[0] = (fi - 1) >> 1; ci[1] = (fi + 1) >> 1; w[0] = w[1] = 0.5; }
+    else { ci[0] = nc; w[0] = 1.0; ci[1] = 0; w[1] = 0.0; }
+  };
+  cand(ix, f.nx, cx, wx);
+  cand(iy, f.ny, cy, wy);
+  cand(iz, f.nz, cz, wz);
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const double w = wx[a & 1] * wy[(a >> 1) & 1] * wz[a >> 2];
+    if (w == 0.0) continue;
+    const size_t b = 3 * (size_t)(cx[a & 1] + c.Nx * (cy[(a >> 1) & 1] + c.Ny * cz[a >> 2]));
+    acc[0] += w * (double)ec[b];
+    acc[1] += w * (double)ec[b + 1];
+    acc[2] += w * (double)ec[b + 2];
+  }
+  const unsigned fx = ffix[i];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (!((fx >> k) & 1u)) xf[3 * (size_t)i + k] = (TF)((double)xf[3 * (size_t)i + k] + acc[k]);
+}
+
+template <typename TF, typename TC>
+void launch_prolong_add(const Grid& fine, const Grid& coarse, const TC* ec, const uint8_t* ffix,
+                        TF* xf, hipStream_t s) {
+  k_prolong_add<TF, TC><<<div_up(fine.Nn, 256), 256, 0, s>>>(fine, coarse, ec, ffix, xf);
+}
+template void launch_prolong_add<float, double>(const Grid&, const Grid&, const double*,
+                                                const uint8_t*, float*, hipStream_t);
+template void launch_prolong_add<float, float>(const Grid&, const Grid&, const float*,
+                                               const uint8_t*, float*, hipStream_t);
+template void launch_prolong_add<double, double>(const Grid&, const Grid&, const double*,
+                                                 const uint8_t*, double*, hipStream_t);
+template void launch_prolong_add<double, float>(const Grid&, const Grid&, const float*,
+                                                const uint8_t*, double*, hipStream_t);
+
+}  // namespace sgmg

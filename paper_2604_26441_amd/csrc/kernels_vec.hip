@@ -1,0 +1,300 @@
+// Vector kernels: deterministic dot products, PCG updates, casts, power
+// iteration helpers.
+#include "kernels.hpp"
+
+namespace sgmg {
+
+constexpr int kVecBlock = 256;
+constexpr int kVecGrid = 1024;  // grid-stride: fixed grid -> fixed summation order
+
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): output i of the stream with
+// seed s is the variant-13 finaliser of s + (i+1) * golden.  Mapped to
+// [-1, 1) with 53 bits.  Used only for the power-iteration start vector.
+__device__ inline uint64_t splitmix64(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_power_start(double* __restrict__ x, const uint8_t* __restrict__ fixn, int Nn,
+                              uint64_t seed) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * Nn) return;
+  const double v = (double)(splitmix64(seed, (uint64_t)i) >> 11) * 0x1.0p-52 - 1.0;
+  x[i] = ((fixn[i / 3] >> (i % 3)) & 1u) ? 0.0 : v;
+}
+
+void launch_power_start(double* x, const uint8_t* fixn, int Nn, uint64_t seed, hipStream_t s) {
+  k_power_start<<<div_up(3L * Nn, 256), 256, 0, s>>>(x, fixn, Nn, seed);
+}
+
+__global__ __launch_bounds__(kVecBlock) void k_dot(const double* __restrict__ a,
+                                                   const double* __restrict__ b,
+                                                   const double* __restrict__ w, int n, RedWs ws,
+                                                   double* out) {
+  double s = 0.0;
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n; i += gridDim.x * kVecBlock) {
+    double t = a[i] * (b ? b[i] : a[i]);
+    if (w) t *= w[i];
+    s += t;
+  }
+  const double v[1] = {s};
+  grid_sum<1>(v, ws, out);
+}
+
+static unsigned vec_grid(int n) {
+  const unsigned g = div_up(n, kVecBlock);
+  return g < (unsigned)kVecGrid ? (g ? g : 1u) : (unsigned)kVecGrid;
+}
+
+void launch_dot(const double* a, const double* b, const double* w, int n, RedWs ws, double* out,
+                hipStream_t s) {
+  k_dot<<<vec_grid(n), kVecBlock, 0, s>>>(a, b, w, n, ws, out);
+}
+
+__global__ __launch_bounds__(kVecBlock) void k_scale_dinv_norm(const double* __restrict__ dinv,
+                                                               const double* __restrict__ w,
+                                                               double* __restrict__ y, int n,
+                                                               RedWs ws, double* out) {
+  double s = 0.0;
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n; i += gridDim.x * kVecBlock) {
+    const double v = dinv[i] * w[i];
+    y[i] = v;
+    s += v * v;
+  }
+  const double v[1] = {s};
+  grid_sum<1>(v, ws, out);
+}
+
+void launch_scale_dinv_norm(const double* dinv, const double* w, double* y, int n, RedWs ws,
+                            double* out, hipStream_t s) {
+  k_scale_dinv_norm<<<vec_grid(n), kVecBlock, 0, s>>>(dinv, w, y, n, ws, out);
+}
+
+__global__ void k_normalize(const double* __restrict__ y, const double* __restrict__ nrm2,
+                            double* __restrict__ x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double s = *nrm2 > 0.0 ? 1.0 / sqrt(*nrm2) : 0.0;
+  x[i] = y[i] * s;
+}
+
+void launch_normalize(const double* y, const double* nrm2, double* x, int n, hipStream_t s) {
+  k_normalize<<<div_up(n, 256), 256, 0, s>>>(y, nrm2, x, n);
+}
+
+template <typename T>
+__global__ void k_vcycle_entry(const double* __restrict__ r, T* __restrict__ b,
+                               const T* __restrict__ dinv, double c0, T* __restrict__ x,
+                               T* __restrict__ d, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T bv = (T)r[i];
+  b[i] = bv;
+  const T xv = (T)c0 * dinv[i] * bv;
+  x[i] = xv;
+  if (d) d[i] = xv;
+}
+
+template <typename T>
+void launch_vcycle_entry(const double* r, T* b, const T* dinv, double c0, T* x, T* d, int n,
+                         hipStream_t s) {
+  k_vcycle_entry<T><<<div_up(n, 256), 256, 0, s>>>(r, b, dinv, c0, x, d, n);
+}
+template void launch_vcycle_entry<float>(const double*, float*, const float*, double, float*,
+                                         float*, int, hipStream_t);
+template void launch_vcycle_entry<double>(const double*, double*, const double*, double, double*,
+                                          double*, int, hipStream_t);
+
+__global__ void k_d2f(const double* __restrict__ in, float* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+__global__ void k_f2d(const float* __restrict__ in, double* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (double)in[i];
+}
+__global__ void k_copy(const double* __restrict__ in, double* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i];
+}
+void launch_d2f(const double* in, float* out, int n, hipStream_t s) {
+  k_d2f<<<div_up(n, 256), 256, 0, s>>>(in, out, n);
+}
+void launch_f2d(const float* in, double* out, int n, hipStream_t s) {
+  k_f2d<<<div_up(n, 256), 256, 0, s>>>(in, out, n);
+}
+void launch_copy(const double* in, double* out, int n, hipStream_t s) {
+  k_copy<<<div_up(n, 256), 256, 0, s>>>(in, out, n);
+}
+
+// r = f - Ax0 (or f); out = (f.f, r.r)
+__global__ __launch_bounds__(kVecBlock) void k_pcg_init(const double* __restrict__ f,
+                                                        const double* __restrict__ Ax0,
+                                                        int have_x0, double* __restrict__ r,
+                                                        int n, RedWs ws, double* out) {
+  double ff = 0.0, rr = 0.0;
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n; i += gridDim.x * kVecBlock) {
+    const double fv = f[i];
+    const double rv = have_x0 ? fv - Ax0[i] : fv;
+    r[i] = rv;
+    ff += fv * fv;
+    rr += rv * rv;
+  }
+  const double v[2] = {ff, rr};
+  grid_sum<2>(v, ws, out);
+}
+
+void launch_pcg_init(const double* f, const double* Ax0, int have_x0, double* r, int n, RedWs ws,
+                     double* sc_ff_rr, hipStream_t s) {
+  k_pcg_init<<<vec_grid(n), kVecBlock, 0, s>>>(f, Ax0, have_x0, r, n, ws, sc_ff_rr);
+}
+
+// alpha = sc[rz] / sc[pq]; x += alpha p; r -= alpha q; out = r.r
+__global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(double* __restrict__ x,
+                                                             double* __restrict__ r,
+                                                             double* __restrict__ r_old,
+                                                             const double* __restrict__ p,
+                                                             const double* __restrict__ q,
+                                                             const double* __restrict__ sc,
+                                                             int slot_rz, int slot_pq, int n,
+                                                             RedWs ws, double* out) {
+  const double pq = sc[slot_pq];
+  const double alpha = sc[slot_rz] / pq;
+  // a failed step (p.q <= 0 or non-finite) leaves x and r untouched
+  const bool ok = pq > 0.0 && isfinite(alpha);
+  double rr = 0.0;
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n; i += gridDim.x * kVecBlock) {
+    const double ro = r[i];
+    double rv = ro;
+    if (ok) {
+      x[i] += alpha * p[i];
+      if (r_old) r_old[i] = ro;
+      rv = ro - alpha * q[i];
+      r[i] = rv;
+    }
+    rr += rv * rv;
+  }
+  const double v[1] = {rr};
+  grid_sum<1>(v, ws, out);
+}
+
+void launch_pcg_update_xr(double* x, double* r, double* r_old, const double* p, const double* q,
+                          const double* sc, int slot_rz, int slot_pq, int n, RedWs ws,
+                          double* sc_rr, hipStream_t s) {
+  k_pcg_update_xr<<<vec_grid(n), kVecBlock, 0, s>>>(x, r, r_old, p, q, sc, slot_rz, slot_pq, n,
+                                                    ws, sc_rr);
+}
+
+// out[0] = r.z ; out[1] = r_old.z (flexible beta numerator r.z - r_old.z)
+__global__ __launch_bounds__(kVecBlock) void k_pcg_dot_rz(const double* __restrict__ r,
+                                                          const double* __restrict__ z,
+                                                          const double* __restrict__ r_old, int n,
+                                                          RedWs ws, double* out) {
+  double a = 0.0, b = 0.0;
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n; i += gridDim.x * kVecBlock) {
+    const double zv = z[i];
+    a += r[i] * zv;
+    if (r_old) b += r_old[i] * zv;
+  }
+  const double v[2] = {a, b};
+  grid_sum<2>(v, ws, out);
+}
+
+void launch_pcg_dot_rz(const double* r, const double* z, const double* r_old, int n, RedWs ws,
+                       double* sc_out2, hipStream_t s) {
+  k_pcg_dot_rz<<<vec_grid(n), kVecBlock, 0, s>>>(r, z, r_old, n, ws, sc_out2);
+}
+
+// p = z + beta p with beta = (sc[num] - sc[sub]) / sc[den]  (sub < 0: no term)
+__global__ void k_pcg_update_p(double* __restrict__ p, const double* __restrict__ z,
+                               const double* __restrict__ sc, int slot_num, int slot_sub,
+                               int slot_den, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double num = sc[slot_num] - (slot_sub >= 0 ? sc[slot_sub] : 0.0);
+  const double beta = num / sc[slot_den];
+  p[i] = z[i] + beta * p[i];
+}
+
+void launch_pcg_update_p(double* p, const double* z, const double* sc, int slot_num, int slot_sub,
+                         int slot_den, int n, hipStream_t s) {
+  k_pcg_update_p<<<div_up(n, 256), 256, 0, s>>>(p, z, sc, slot_num, slot_sub, slot_den, n);
+}
+
+// Largest value of a (non-negative entries, or masked by fixn when given).
+// Max is order independent, so the atomic on the IEEE bit pattern (monotone
+// for non-negative doubles) is deterministic.
+__global__ void k_max_nonneg(const double* __restrict__ a, const uint8_t* __restrict__ fixn, int n,
+                             unsigned long long* __restrict__ out) {
+  double m = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if (fixn && ((fixn[i / 3] >> (i % 3)) & 1u)) continue;
+    m = fmax(m, a[i]);
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+void launch_max_nonneg(const double* a, const uint8_t* fixn, int n, double* out, hipStream_t s) {
+  hipMemsetAsync(out, 0, sizeof(double), s);
+  k_max_nonneg<<<vec_grid(n), kVecBlock, 0, s>>>(a, fixn, n, (unsigned long long*)out);
+}
+
+// Diagonal floor and inverse (Sec. 3.5: floored away from zero): free DOFs
+// D = max(D, 1e-30 max D), Dinv = 1/D; fixed DOFs D = Dinv = 0.
+__global__ void k_diag_finalize(double* __restrict__ d, double* __restrict__ dinv64,
+                                float* __restrict__ dinv32, const uint8_t* __restrict__ fixn, int n,
+                                const double* __restrict__ dmax) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool fixed = (fixn[i / 3] >> (i % 3)) & 1u;
+  double v = d[i], iv = 0.0;
+  if (fixed) {
+    v = 0.0;
+  } else {
+    v = fmax(v, 1e-30 * *dmax);
+    iv = 1.0 / v;
+  }
+  d[i] = v;
+  dinv64[i] = iv;
+  dinv32[i] = (float)iv;
+}
+
+void launch_diag_finalize(double* d, double* dinv64, float* dinv32, const uint8_t* fixn, int n,
+                          const double* dmax, hipStream_t s) {
+  k_diag_finalize<<<div_up(n, 256), 256, 0, s>>>(d, dinv64, dinv32, fixn, n, dmax);
+}
+
+__global__ void k_apply_dinv(const double* __restrict__ dinv, const double* __restrict__ r,
+                             double* __restrict__ z, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = dinv[i] * r[i];
+}
+
+void launch_apply_dinv(const double* dinv, const double* r, double* z, int n, hipStream_t s) {
+  k_apply_dinv<<<div_up(n, 256), 256, 0, s>>>(dinv, r, z, n);
+}
+
+// r = f - Ax ; out = r.r
+__global__ __launch_bounds__(kVecBlock) void k_residual(const double* __restrict__ f,
+                                                        const double* __restrict__ Ax,
+                                                        double* __restrict__ r, int n, RedWs ws,
+                                                        double* out) {
+  double rr = 0.0;
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n; i += gridDim.x * kVecBlock) {
+    const double v = f[i] - Ax[i];
+    if (r) r[i] = v;
+    rr += v * v;
+  }
+  const double v[1] = {rr};
+  grid_sum<1>(v, ws, out);
+}
+
+void launch_residual(const double* f, const double* Ax, double* r, int n, RedWs ws,
+                     double* out_rr, hipStream_t s) {
+  k_residual<<<vec_grid(n), kVecBlock, 0, s>>>(f, Ax, r, n, ws, out_rr);
+}
+
+}  // namespace sgmg

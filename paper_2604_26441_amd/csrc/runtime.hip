@@ -1,0 +1,837 @@
+// C ABI of libsimpgmg: hierarchy setup, operator application, V-cycle and
+// PCG orchestration on one HIP stream.  All arithmetic runs in the kernels of
+// this library; host code only sequences launches and reads back scalars.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <type_traits>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace sgmg {
+
+static thread_local std::string g_err;
+void set_error(const std::string& m) { g_err = m; }
+
+// Device scalar slots.
+enum Slot {
+  SC_FF = 0, SC_RR0 = 1,     // pcg init: f.f, r.r (adjacent: one 2-sum)
+  SC_PQ = 2, SC_RR = 3,
+  SC_RZ0 = 4, SC_ROZ0 = 5,   // r.z, r_old.z for even iterations (adjacent)
+  SC_RZ1 = 6, SC_ROZ1 = 7,   // odd iterations
+  SC_TRUE = 8,               // true residual norm^2
+  SC_XW = 9, SC_XDX = 10, SC_NRM = 11, SC_DSUM = 12, SC_EPS = 13, SC_MAX = 14,
+  SC_COUNT = 16
+};
+
+struct Level {
+  Grid g{};
+  bool f32 = false;          // work vectors of this level are float
+  uint8_t* fixn = nullptr;
+  double* d64 = nullptr;
+  double* dinv64 = nullptr;
+  float* dinv32 = nullptr;
+  double* S64 = nullptr;     // l >= 1
+  float* S32 = nullptr;      // l >= 1 when stored in FP32
+  double lam = 0.0;          // raw power-iteration estimate
+  int n_free = 0;
+  void* b = nullptr;         // work vectors (T = float or double)
+  void* x[2] = {nullptr, nullptr};
+  void* dv = nullptr;
+  void* r = nullptr;
+};
+
+}  // namespace sgmg
+
+using namespace sgmg;
+
+struct sgmg_hierarchy {
+  sgmg_options o{};
+  int L = 0;
+  Level lev[8];
+  KeTables kt{};
+  std::vector<void*> allocs;
+  double* ke64 = nullptr;
+  float* ke32 = nullptr;
+  double* gtab = nullptr;
+  double* E64 = nullptr;
+  float* E32 = nullptr;
+  double maxE_lambda = 0.0;  // max E when lambdas were estimated
+  int nL = 0;
+  int* free_idx = nullptr;
+  double* Ainv = nullptr;
+  double* rc = nullptr;
+  double coarse_eps = 0.0;
+  RedWs ws{};
+  double* sc = nullptr;
+  double* h_sc = nullptr;    // pinned mirror of sc
+  int* d_flag = nullptr;
+  double* r = nullptr;
+  double* z = nullptr;
+  double* p = nullptr;
+  double* q = nullptr;
+  double* r_old = nullptr;
+  double* tmp = nullptr;
+  double* gj_scratch = nullptr;
+};
+
+namespace {
+
+constexpr size_t kMinPartials = 1 << 16;
+
+int dalloc(sgmg_hierarchy* h, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    *p = nullptr;
+    return SGMG_ENOMEM;
+  }
+  h->allocs.push_back(*p);
+  return 0;
+}
+
+template <typename T>
+int dalloc_t(sgmg_hierarchy* h, T** p, size_t count) {
+  void* v = nullptr;
+  int rc = dalloc(h, &v, count * sizeof(T));
+  *p = (T*)v;
+  return rc;
+}
+
+#define TRY(x)                 \
+  do {                         \
+    int _rc = (x);             \
+    if (_rc) return _rc;       \
+  } while (0)
+
+hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+int check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(std::string("kernel launch: ") + hipGetErrorString(e));
+    return SGMG_EHIP;
+  }
+  return 0;
+}
+
+// Local prolongation of pattern p (px + 3 py + 9 pz): rows fine local DOFs,
+// columns coarse local DOFs (see the device table of the same name).
+const double kPat[3][2][2] = {{{1.0, 0.0}, {0.5, 0.5}}, {{0.5, 0.5}, {0.0, 1.0}},
+                              {{0.0, 1.0}, {0.0, 1.0}}};
+
+void build_gtab(const KeTables& kt, std::vector<double>& g) {
+  g.assign(27 * 576, 0.0);
+  for (int p = 0; p < 27; ++p) {
+    const int px = p % 3, py = (p / 3) % 3, pz = p / 9;
+    double P[24][24] = {};
+    for (int a = 0; a < 8; ++a)
+      for (int b = 0; b < 8; ++b) {
+        const double w = kPat[px][a & 1][b & 1] * kPat[py][(a >> 1) & 1][(b >> 1) & 1] *
+                         kPat[pz][a >> 2][b >> 2];
+        for (int c = 0; c < 3; ++c) P[3 * a + c][3 * b + c] = w;
+      }
+    // G = P^T K P
+    static double KP[24][24];
+    for (int i = 0; i < 24; ++i)
+      for (int j = 0; j < 24; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < 24; ++k) s += kt.ke[i * 24 + k] * P[k][j];
+        KP[i][j] = s;
+      }
+    for (int i = 0; i < 24; ++i)
+      for (int j = 0; j < 24; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < 24; ++k) s += P[k][i] * KP[k][j];
+        g[(size_t)p * 576 + i * 24 + j] = s;
+      }
+  }
+}
+
+template <typename T>
+Epi<T> epi_store(T* out, RedWs ws = {}, double* dot_out = nullptr) {
+  Epi<T> e{};
+  e.mode = EPI_STORE;
+  e.out = out;
+  e.want_dot = dot_out != nullptr;
+  e.ws = ws;
+  e.dot_out = dot_out;
+  return e;
+}
+
+template <typename T>
+Epi<T> epi_resid(T* out, const T* b) {
+  Epi<T> e{};
+  e.mode = EPI_RESID;
+  e.out = out;
+  e.b = b;
+  return e;
+}
+
+template <typename T>
+Epi<T> epi_smooth(T* xout, const T* b, const T* dinv, T* d, double c1, double c2, int store_d,
+                  double* out64) {
+  Epi<T> e{};
+  e.mode = EPI_SMOOTH;
+  e.out = xout;
+  e.b = b;
+  e.dinv = dinv;
+  e.d = d;
+  e.c1 = c1;
+  e.c2 = c2;
+  e.store_d = store_d;
+  e.out64 = out64;
+  return e;
+}
+
+// y-side operator application on level l in the level's own precision.
+template <typename T>
+int apply_level(const sgmg_hierarchy* h, int l, sgmg_prec prec, const T* x, const Epi<T>& ep,
+                hipStream_t s);
+
+template <>
+int apply_level<double>(const sgmg_hierarchy* h, int l, sgmg_prec prec, const double* x,
+                        const Epi<double>& ep, hipStream_t s) {
+  const Level& L = h->lev[l];
+  if (prec != SGMG_F64) {
+    set_error("double vectors require SGMG_F64");
+    return SGMG_EINVAL;
+  }
+  if (l == 0)
+    launch_apply_fine_node<double>(L.g, h->E64, h->ke64, x, L.fixn, ep, s);
+  else
+    launch_stencil_apply<double>(L.g, L.S64, x, L.fixn, ep, s);
+  return check_launch();
+}
+
+template <>
+int apply_level<float>(const sgmg_hierarchy* h, int l, sgmg_prec prec, const float* x,
+                       const Epi<float>& ep, hipStream_t s) {
+  const Level& L = h->lev[l];
+  if (l == 0) {
+    if (prec == SGMG_F32) {
+      launch_apply_fine_node<float>(L.g, h->E32, h->ke32, x, L.fixn, ep, s);
+    } else {
+      set_error("precision not available for the fine operator in this build");
+      return SGMG_EINVAL;
+    }
+  } else {
+    if (!L.S32 || prec != SGMG_F32) {
+      set_error("level is not stored in FP32");
+      return SGMG_EINVAL;
+    }
+    launch_stencil_apply<float>(L.g, L.S32, x, L.fixn, ep, s);
+  }
+  return check_launch();
+}
+
+sgmg_prec level_prec(const sgmg_hierarchy* h, int l) {
+  if (l == 0) return h->o.fine_prec;
+  if (l == 1 && l < h->L - 1) return h->o.level1_prec;
+  return SGMG_F64;
+}
+
+// ---------------------------------------------------------------------------
+// Power iteration for lambda_max(D^-1 K^l) in FP64 (Sec. 3.5).
+int power_lambda(sgmg_hierarchy* h, int l, int iters, hipStream_t s, double* out) {
+  Level& L = h->lev[l];
+  const int n = L.g.n;
+  double* x = h->p;
+  double* w = h->q;
+  double* y = h->z;
+  launch_power_start(x, L.fixn, L.g.Nn, h->o.seed + (uint64_t)l, s);
+  launch_dot(x, nullptr, nullptr, n, h->ws, h->sc + SC_NRM, s);
+  launch_normalize(x, h->sc + SC_NRM, x, n, s);
+  for (int k = 0; k < iters; ++k) {
+    TRY(apply_level<double>(h, l, SGMG_F64, x, epi_store<double>(w, h->ws, h->sc + SC_XW), s));
+    if (k == iters - 1) {
+      launch_dot(x, x, L.d64, n, h->ws, h->sc + SC_XDX, s);
+    } else {
+      launch_scale_dinv_norm(L.dinv64, w, y, n, h->ws, h->sc + SC_NRM, s);
+      launch_normalize(y, h->sc + SC_NRM, x, n, s);
+    }
+  }
+  TRY(check_launch());
+  SGMG_HIP(hipMemcpyAsync(h->h_sc, h->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+  SGMG_HIP(hipStreamSynchronize(s));
+  double lam = iters > 0 ? h->h_sc[SC_XW] / h->h_sc[SC_XDX] : 0.0;
+  if (!(lam > 1e-6) || !std::isfinite(lam)) lam = 1e-6;
+  *out = lam;
+  return 0;
+}
+
+// All E-dependent parts: moduli, diagonals, Galerkin operators, coarsest inverse.
+int assemble_operators(sgmg_hierarchy* h, const double* rho_or_E, hipStream_t s) {
+  const sgmg_options& o = h->o;
+  Level& L0 = h->lev[0];
+  launch_simp(rho_or_E, h->E64, h->E32, L0.g.nel, o.input_is_modulus, o.E0, o.Emin, o.penal, s);
+  launch_diag_fine(L0.g, h->E64, h->ke64, L0.fixn, L0.d64, s);
+  for (int l = 1; l < h->L; ++l) {
+    Level& F = h->lev[l - 1];
+    Level& C = h->lev[l];
+    if (l == 1)
+      launch_galerkin_l1(F.g, C.g, h->E64, h->gtab, h->ke64, F.fixn, C.fixn, C.S64, s);
+    else
+      launch_galerkin_stencil(F.g, C.g, F.S64, C.fixn, C.S64, s);
+    launch_stencil_diag(C.g, C.S64, C.d64, s);
+    if (C.S32) launch_stencil_to_f32(C.S64, C.S32, (size_t)kStencil * C.g.Nn, s);
+  }
+  TRY(check_launch());
+  // D^-1 with the floor max(D, 1e-30 max D) on free DOFs, 0 on fixed DOFs.
+  for (int l = 0; l < h->L; ++l) {
+    Level& L = h->lev[l];
+    launch_max_nonneg(L.d64, L.fixn, L.g.n, h->sc + SC_MAX, s);
+    launch_diag_finalize(L.d64, L.dinv64, L.dinv32, L.fixn, L.g.n, h->sc + SC_MAX, s);
+  }
+  TRY(check_launch());
+  // coarsest: dense K_L + eps I and its explicit inverse
+  Level& C = h->lev[h->L - 1];
+  const int nf = h->nL;
+  if (nf > 0) {
+    launch_dense_assemble(C.g, C.S64, h->free_idx, nf, h->Ainv, s);
+    launch_dense_diag_sum(h->Ainv, nf, h->ws, h->sc + SC_DSUM, s);
+    launch_dense_add_diag(h->Ainv, nf, h->sc + SC_DSUM, s, h->sc + SC_EPS);
+    SGMG_HIP(hipMemsetAsync(h->d_flag, 0, sizeof(int), s));
+    dense_spd_inverse(h->Ainv, nf, h->gj_scratch, h->d_flag, s);
+    TRY(check_launch());
+    int flag = 0;
+    SGMG_HIP(hipMemcpyAsync(&flag, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    SGMG_HIP(hipMemcpyAsync(h->h_sc, h->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+    SGMG_HIP(hipStreamSynchronize(s));
+    h->coarse_eps = h->h_sc[SC_EPS];
+    if (flag) {
+      set_error("coarsest factorisation met a non-positive pivot");
+      return SGMG_EFACTOR;
+    }
+  }
+  return 0;
+}
+
+double max_modulus(sgmg_hierarchy* h, hipStream_t s) {
+  launch_max_nonneg(h->E64, nullptr, h->lev[0].g.nel, h->sc + SC_MAX, s);
+  double m = 0.0;
+  if (hipMemcpyAsync(&m, h->sc + SC_MAX, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return 0.0;
+  return m;
+}
+
+int estimate_lambdas(sgmg_hierarchy* h, hipStream_t s) {
+  for (int l = 0; l < h->L - 1; ++l) {
+    if (h->o.lambda_override) {
+      h->lev[l].lam = h->o.lambda_override[l];
+      continue;
+    }
+    const int it = l == 0 ? h->o.power_iters_fine : h->o.power_iters_coarse;
+    TRY(power_lambda(h, l, it, s, &h->lev[l].lam));
+  }
+  h->maxE_lambda = max_modulus(h, s);
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle (Eq. vcycle).  On entry lev[l].b holds the right-hand side and
+// lev[l].x[0] the first smoothing step from zero (written by the producer).
+// On exit lev[l].x[*cur] holds V^l(b).
+struct Smoother {
+  bool cheb;
+  int steps;
+  double omega, theta, delta, sigma1;
+};
+
+Smoother smoother_of(const sgmg_hierarchy* h, int l) {
+  Smoother sm{};
+  const double lam = h->o.lambda_safety * h->lev[l].lam;
+  sm.cheb = (l == 0 && h->o.fine_smoother == 0);
+  sm.steps = l == 0 ? h->o.fine_degree : h->o.coarse_sweeps;
+  sm.omega = std::min(h->o.jacobi_omega_max, 4.0 / (3.0 * lam));
+  sm.theta = 0.5 * lam * (1.0 + h->o.cheb_alpha);
+  sm.delta = 0.5 * lam * (1.0 - h->o.cheb_alpha);
+  sm.sigma1 = sm.theta / sm.delta;
+  return sm;
+}
+
+double first_step_coef(const Smoother& sm) { return sm.cheb ? 1.0 / sm.theta : sm.omega; }
+
+int vcycle_level(const sgmg_hierarchy* h, int l, int* cur, double* out64, hipStream_t s);
+
+template <typename TF, typename TC>
+int descend(const sgmg_hierarchy* h, int l, const TF* r, hipStream_t s) {
+  const Level& F = h->lev[l];
+  const Level& C = h->lev[l + 1];
+  if (l + 1 == h->L - 1) {
+    launch_restrict<TF, TC>(F.g, C.g, r, C.fixn, (TC*)C.b, nullptr, 0.0, nullptr, nullptr, s);
+  } else {
+    const Smoother cs = smoother_of(h, l + 1);
+    const TC* dinv = std::is_same<TC, float>::value ? (const TC*)C.dinv32 : (const TC*)C.dinv64;
+    launch_restrict<TF, TC>(F.g, C.g, r, C.fixn, (TC*)C.b, dinv, first_step_coef(cs),
+                            (TC*)C.x[0], cs.cheb ? (TC*)C.dv : nullptr, s);
+  }
+  return check_launch();
+}
+
+template <typename T>
+int smooth_and_recurse(const sgmg_hierarchy* h, int l, int* cur, double* out64, hipStream_t s) {
+  const Level& L = h->lev[l];
+  const Smoother sm = smoother_of(h, l);
+  const sgmg_prec prec = level_prec(h, l);
+  const T* b = (const T*)L.b;
+  const T* dinv = std::is_same<T, float>::value ? (const T*)L.dinv32 : (const T*)L.dinv64;
+  T* d = (T*)L.dv;
+  int c = 0;  // x[0] holds the first pre-smoothing step
+  double rho = sm.cheb ? 1.0 / sm.sigma1 : 0.0;
+  for (int k = 1; k < sm.steps; ++k) {
+    double c1 = 0.0, c2 = sm.omega;
+    if (sm.cheb) {
+      const double rn = 1.0 / (2.0 * sm.sigma1 - rho);
+      c1 = rn * rho;
+      c2 = 2.0 * rn / sm.delta;
+      rho = rn;
+    }
+    TRY(apply_level<T>(h, l, prec, (const T*)L.x[c],
+                       epi_smooth<T>((T*)L.x[1 - c], b, dinv, d, c1, c2, sm.cheb, nullptr), s));
+    c = 1 - c;
+  }
+  // residual, restriction, coarse correction
+  TRY(apply_level<T>(h, l, prec, (const T*)L.x[c], epi_resid<T>((T*)L.r, b), s));
+  const Level& C = h->lev[l + 1];
+  if (C.f32) TRY((descend<T, float>(h, l, (const T*)L.r, s)));
+  else TRY((descend<T, double>(h, l, (const T*)L.r, s)));
+  int cc = 0;
+  TRY(vcycle_level(h, l + 1, &cc, nullptr, s));
+  if (C.f32) launch_prolong_add<T, float>(L.g, C.g, (const float*)C.x[cc], L.fixn, (T*)L.x[c], s);
+  else launch_prolong_add<T, double>(L.g, C.g, (const double*)C.x[cc], L.fixn, (T*)L.x[c], s);
+  TRY(check_launch());
+  // post-smoothing from the corrected iterate
+  rho = sm.cheb ? 1.0 / sm.sigma1 : 0.0;
+  for (int k = 0; k < sm.steps; ++k) {
+    double c1 = 0.0, c2 = sm.omega;
+    if (sm.cheb) {
+      if (k == 0) {
+        c2 = 1.0 / sm.theta;
+      } else {
+        const double rn = 1.0 / (2.0 * sm.sigma1 - rho);
+        c1 = rn * rho;
+        c2 = 2.0 * rn / sm.delta;
+        rho = rn;
+      }
+    }
+    double* o64 = (k == sm.steps - 1) ? out64 : nullptr;
+    TRY(apply_level<T>(h, l, prec, (const T*)L.x[c],
+                       epi_smooth<T>((T*)L.x[1 - c], b, dinv, d, c1, c2, sm.cheb, o64), s));
+    c = 1 - c;
+  }
+  *cur = c;
+  return 0;
+}
+
+int vcycle_level(const sgmg_hierarchy* h, int l, int* cur, double* out64, hipStream_t s) {
+  const Level& L = h->lev[l];
+  if (l == h->L - 1) {
+    launch_dense_solve(h->Ainv, h->free_idx, h->nL, (const double*)L.b, h->rc, (double*)L.x[0], s);
+    *cur = 0;
+    return check_launch();
+  }
+  if (L.f32) return smooth_and_recurse<float>(h, l, cur, out64, s);
+  return smooth_and_recurse<double>(h, l, cur, out64, s);
+}
+
+int vcycle_full(const sgmg_hierarchy* h, const double* r, double* z, hipStream_t s) {
+  const Level& L = h->lev[0];
+  const Smoother sm = smoother_of(h, 0);
+  const double c0 = first_step_coef(sm);
+  if (L.f32)
+    launch_vcycle_entry<float>(r, (float*)L.b, L.dinv32, c0, (float*)L.x[0],
+                               sm.cheb ? (float*)L.dv : nullptr, L.g.n, s);
+  else
+    launch_vcycle_entry<double>(r, (double*)L.b, L.dinv64, c0, (double*)L.x[0],
+                                sm.cheb ? (double*)L.dv : nullptr, L.g.n, s);
+  TRY(check_launch());
+  int cur = 0;
+  return vcycle_level(h, 0, &cur, z, s);
+}
+
+int validate(const sgmg_options* o) {
+  if (!o) { set_error("options is NULL"); return SGMG_EINVAL; }
+  if (o->nx < 1 || o->ny < 1 || o->nz < 1) { set_error("mesh dims must be >= 1"); return SGMG_EINVAL; }
+  if ((long)(o->nx + 1) * (o->ny + 1) * (o->nz + 1) * 3 > 0x7fffffffL) {
+    set_error("mesh too large for 32-bit DOF indexing");
+    return SGMG_EINVAL;
+  }
+  if (o->n_levels == 1 || o->n_levels < 0 || o->n_levels > 8) {
+    set_error("n_levels must be 0 (auto) or 2..8");
+    return SGMG_EINVAL;
+  }
+  if (o->fine_degree < 1 || o->coarse_sweeps < 1) { set_error("smoothing steps must be >= 1"); return SGMG_EINVAL; }
+  if (o->fine_prec < SGMG_F64 || o->fine_prec > SGMG_BF16X3) { set_error("bad fine_prec"); return SGMG_EINVAL; }
+  if (o->level1_prec != SGMG_F64 && o->level1_prec != SGMG_F32) { set_error("level1_prec must be F64 or F32"); return SGMG_EINVAL; }
+  if (!(o->cheb_alpha > 0.0 && o->cheb_alpha < 1.0)) { set_error("cheb_alpha must be in (0,1)"); return SGMG_EINVAL; }
+  if (!(o->lambda_safety > 0.0)) { set_error("lambda_safety must be > 0"); return SGMG_EINVAL; }
+  return 0;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* sgmg_last_error(void) { return g_err.c_str(); }
+
+void sgmg_default_options(sgmg_options* o, int nx, int ny, int nz) {
+  std::memset(o, 0, sizeof(*o));
+  o->nx = nx; o->ny = ny; o->nz = nz;
+  o->nu = 0.3; o->E0 = 1.0; o->Emin = 1e-9; o->penal = 3.0;
+  o->input_is_modulus = 0;
+  o->n_levels = 4;
+  o->fine_smoother = 0;
+  o->fine_degree = 2;
+  o->coarse_sweeps = 2;
+  o->cheb_alpha = 1.0 / 30.0;
+  o->jacobi_omega_max = 0.5;
+  o->lambda_safety = 1.1;
+  o->power_iters_fine = 20;
+  o->power_iters_coarse = 10;
+  o->fine_prec = SGMG_F32;
+  o->level1_prec = SGMG_F64;
+  o->dense_max = 5000;
+  o->coarse_pcg_iters = 80;
+  o->seed = 0;
+  o->flexible_beta = 0;
+  o->stag_window = 0;
+  o->lambda_override = nullptr;
+}
+
+void sgmg_destroy(sgmg_hierarchy* h) {
+  if (!h) return;
+  for (void* p : h->allocs) hipFree(p);
+  if (h->h_sc) hipHostFree(h->h_sc);
+  delete h;
+}
+
+int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const uint8_t* fixed_dof,
+                         void* stream, sgmg_hierarchy** out) {
+  if (out) *out = nullptr;
+  TRY(validate(opts));
+  if (!rho_or_E || !out) { set_error("NULL argument"); return SGMG_EINVAL; }
+  hipStream_t s = as_stream(stream);
+  sgmg_hierarchy* h = new (std::nothrow) sgmg_hierarchy();
+  if (!h) { set_error("host allocation failed"); return SGMG_ENOMEM; }
+  h->o = *opts;
+  h->o.lambda_override = nullptr;
+  int rc = 0;
+  auto fail = [&](int code) { sgmg_destroy(h); return code; };
+
+  compute_ke(opts->nu, &h->kt);
+  // level dims by floor coarsening and masks by injection
+  Grid g0 = make_grid(opts->nx, opts->ny, opts->nz);
+  int maxL = opts->n_levels ? opts->n_levels : 8;
+  std::vector<Grid> grids{g0};
+  for (int l = 1; l < maxL; ++l) {
+    const Grid& f = grids.back();
+    if (f.nx / 2 < 1 || f.ny / 2 < 1 || f.nz / 2 < 1) break;
+    grids.push_back(make_grid(f.nx / 2, f.ny / 2, f.nz / 2));
+  }
+  if (opts->n_levels && (int)grids.size() < opts->n_levels) {
+    set_error("mesh cannot be coarsened to the requested number of levels");
+    return fail(SGMG_EINVAL);
+  }
+  // masks on the device, free counts on the host
+  std::vector<uint8_t*> masks;
+  for (size_t l = 0; l < grids.size(); ++l) {
+    uint8_t* m = nullptr;
+    if ((rc = dalloc_t(h, &m, grids[l].Nn))) return fail(rc);
+    masks.push_back(m);
+  }
+  if (fixed_dof) launch_mask_from_dofs(fixed_dof, masks[0], g0.Nn, s);
+  else launch_mask_cantilever(g0, masks[0], s);
+  for (size_t l = 1; l < grids.size(); ++l)
+    launch_mask_inject(grids[l - 1], grids[l], masks[l - 1], masks[l], s);
+  if ((rc = check_launch())) return fail(rc);
+  std::vector<int> nfree(grids.size());
+  for (size_t l = 0; l < grids.size(); ++l) {
+    std::vector<uint8_t> fx(grids[l].Nn);
+    if (hipMemcpyAsync(fx.data(), masks[l], grids[l].Nn, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      set_error("mask download failed");
+      return fail(SGMG_EHIP);
+    }
+    int c = 0;
+    for (uint8_t v : fx) c += 3 - __builtin_popcount(v & 7);
+    nfree[l] = c;
+  }
+  int L = opts->n_levels;
+  if (!L) {
+    L = (int)grids.size();
+    for (int k = 2; k <= (int)grids.size(); ++k)
+      if (nfree[k - 1] <= opts->dense_max) { L = k; break; }
+  }
+  if (nfree[L - 1] > opts->dense_max) {
+    set_error("coarsest level has " + std::to_string(nfree[L - 1]) +
+              " free DOFs, more than dense_max; add levels");
+    return fail(SGMG_EINVAL);
+  }
+  h->L = L;
+  h->o.n_levels = L;
+  size_t maxn = 0;
+  for (int l = 0; l < L; ++l) {
+    Level& V = h->lev[l];
+    V.g = grids[l];
+    V.fixn = masks[l];
+    V.n_free = nfree[l];
+    const sgmg_prec p = level_prec(h, l);
+    V.f32 = (l < L - 1) && p != SGMG_F64;
+    const size_t n = V.g.n;
+    maxn = std::max(maxn, n);
+    if ((rc = dalloc_t(h, &V.d64, n)) || (rc = dalloc_t(h, &V.dinv64, n)) ||
+        (rc = dalloc_t(h, &V.dinv32, n)))
+      return fail(rc);
+    if (l >= 1) {
+      if ((rc = dalloc_t(h, &V.S64, (size_t)kStencil * V.g.Nn))) return fail(rc);
+      if (l == 1 && V.f32 && (rc = dalloc_t(h, &V.S32, (size_t)kStencil * V.g.Nn))) return fail(rc);
+    }
+    const size_t es = V.f32 ? sizeof(float) : sizeof(double);
+    if ((rc = dalloc(h, &V.b, n * es)) || (rc = dalloc(h, &V.x[0], n * es)) ||
+        (rc = dalloc(h, &V.x[1], n * es)) || (rc = dalloc(h, &V.dv, n * es)) ||
+        (rc = dalloc(h, &V.r, n * es)))
+      return fail(rc);
+    hipMemsetAsync(V.x[0], 0, n * es, s);
+    hipMemsetAsync(V.x[1], 0, n * es, s);
+  }
+  for (size_t l = L; l < masks.size(); ++l) { /* unused coarser masks stay allocated */ }
+  // constants
+  if ((rc = dalloc_t(h, &h->ke64, 576)) || (rc = dalloc_t(h, &h->ke32, 576)) ||
+      (rc = dalloc_t(h, &h->gtab, 27 * 576)))
+    return fail(rc);
+  std::vector<double> gt;
+  build_gtab(h->kt, gt);
+  hipMemcpyAsync(h->ke64, h->kt.ke, 576 * sizeof(double), hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(h->ke32, h->kt.ke32, 576 * sizeof(float), hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(h->gtab, gt.data(), gt.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  if ((rc = dalloc_t(h, &h->E64, g0.nel)) || (rc = dalloc_t(h, &h->E32, g0.nel))) return fail(rc);
+  // reductions, scalars, PCG vectors
+  // one partial per block of the largest reduction grid (fused dots run one
+  // block per 256 nodes; vector reductions use at most 2 x 1024 slots)
+  const size_t npart = std::max(kMinPartials, (size_t)div_up(g0.Nn, 256) + 2048);
+  if ((rc = dalloc_t(h, &h->ws.partials, npart)) || (rc = dalloc_t(h, &h->ws.counter, 1)) ||
+      (rc = dalloc_t(h, &h->sc, SC_COUNT)) || (rc = dalloc_t(h, &h->d_flag, 1)))
+    return fail(rc);
+  hipMemsetAsync(h->ws.counter, 0, sizeof(unsigned), s);
+  hipMemsetAsync(h->sc, 0, SC_COUNT * sizeof(double), s);
+  if (hipHostMalloc((void**)&h->h_sc, SC_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    set_error("pinned allocation failed");
+    return fail(SGMG_ENOMEM);
+  }
+  for (double** v : {&h->r, &h->z, &h->p, &h->q, &h->r_old, &h->tmp})
+    if ((rc = dalloc_t(h, v, maxn))) return fail(rc);
+  // coarsest free index list
+  {
+    Level& C = h->lev[L - 1];
+    std::vector<uint8_t> fx(C.g.Nn);
+    hipMemcpyAsync(fx.data(), C.fixn, C.g.Nn, hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess) { set_error("sync failed"); return fail(SGMG_EHIP); }
+    std::vector<int> idx;
+    for (int i = 0; i < C.g.n; ++i)
+      if (!((fx[i / 3] >> (i % 3)) & 1)) idx.push_back(i);
+    h->nL = (int)idx.size();
+    if ((rc = dalloc_t(h, &h->free_idx, std::max<size_t>(idx.size(), 1))) ||
+        (rc = dalloc_t(h, &h->Ainv, std::max<size_t>((size_t)h->nL * h->nL, 1))) ||
+        (rc = dalloc_t(h, &h->rc, std::max(h->nL, 1))) ||
+        (rc = dalloc_t(h, &h->gj_scratch, (size_t)std::max(h->nL, 1) * 64 + 64 * 64)))
+      return fail(rc);
+    if (!idx.empty())
+      hipMemcpyAsync(h->free_idx, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  }
+  if ((rc = assemble_operators(h, rho_or_E, s))) return fail(rc);
+  if (opts->lambda_override) h->o.lambda_override = opts->lambda_override;
+  rc = estimate_lambdas(h, s);
+  h->o.lambda_override = nullptr;
+  if (rc) return fail(rc);
+  if (hipStreamSynchronize(s) != hipSuccess) { set_error("sync failed"); return fail(SGMG_EHIP); }
+  *out = h;
+  return 0;
+}
+
+int sgmg_update_moduli(sgmg_hierarchy* h, const double* rho_or_E, void* stream) {
+  if (!h || !rho_or_E) { set_error("NULL argument"); return SGMG_EINVAL; }
+  hipStream_t s = as_stream(stream);
+  TRY(assemble_operators(h, rho_or_E, s));
+  const double m = max_modulus(h, s);
+  if (h->maxE_lambda <= 0.0 || std::fabs(m - h->maxE_lambda) > 0.1 * h->maxE_lambda)
+    TRY(estimate_lambdas(h, s));
+  SGMG_HIP(hipStreamSynchronize(s));
+  return 0;
+}
+
+int sgmg_apply_K(const sgmg_hierarchy* h, int level, sgmg_prec prec, const void* u, void* y,
+                 void* stream) {
+  if (!h || !u || !y) { set_error("NULL argument"); return SGMG_EINVAL; }
+  if (level < 0 || level >= h->L) { set_error("level out of range"); return SGMG_EINVAL; }
+  if (u == y) { set_error("u and y must not alias"); return SGMG_EINVAL; }
+  hipStream_t s = as_stream(stream);
+  if (prec == SGMG_F64)
+    return apply_level<double>(h, level, prec, (const double*)u, epi_store<double>((double*)y), s);
+  return apply_level<float>(h, level, prec, (const float*)u, epi_store<float>((float*)y), s);
+}
+
+int sgmg_vcycle(const sgmg_hierarchy* h, const double* r, double* z, void* stream) {
+  if (!h || !r || !z) { set_error("NULL argument"); return SGMG_EINVAL; }
+  return vcycle_full(h, r, z, as_stream(stream));
+}
+
+int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, double rtol,
+                   int maxit, sgmg_solve_info* info, void* stream) {
+  if (!h || !f || !u) { set_error("NULL argument"); return SGMG_EINVAL; }
+  if (precond < 0 || precond > 2 || maxit < 0) { set_error("bad precond or maxit"); return SGMG_EINVAL; }
+  hipStream_t s = as_stream(stream);
+  const Level& L0 = h->lev[0];
+  const int n = L0.g.n;
+  double* sc = h->sc;
+  double* hs = h->h_sc;
+  hipEvent_t e0, e1;
+  SGMG_HIP(hipEventCreate(&e0));
+  SGMG_HIP(hipEventCreate(&e1));
+  SGMG_HIP(hipEventRecord(e0, s));
+  auto K64 = [&](const double* x, double* y, double* dot_out) {
+    return apply_level<double>(h, 0, SGMG_F64, x,
+                               epi_store<double>(y, h->ws, dot_out), s);
+  };
+  auto precondition = [&](const double* r, double* z) -> int {
+    if (precond == 2) return vcycle_full(h, r, z, s);
+    if (precond == 1) launch_apply_dinv(L0.dinv64, r, z, n, s);
+    else launch_copy(r, z, n, s);
+    return check_launch();
+  };
+  auto readsc = [&]() -> int {
+    SGMG_HIP(hipMemcpyAsync(hs, sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+    SGMG_HIP(hipStreamSynchronize(s));
+    return 0;
+  };
+  const bool flex = h->o.flexible_beta != 0;
+  int status = SGMG_MAXIT, iters = 0;
+  double rel = 0.0, rel_true = -1.0, nf = 0.0;
+  std::vector<double> hist;
+  int rc = 0;
+  do {
+    if ((rc = K64(u, h->q, nullptr))) break;
+    launch_pcg_init(f, h->q, 1, h->r, n, h->ws, sc + SC_FF, s);
+    if ((rc = readsc())) break;
+    nf = std::sqrt(hs[SC_FF]);
+    if (nf == 0.0) {
+      SGMG_HIP(hipMemsetAsync(u, 0, n * sizeof(double), s));
+      status = SGMG_CONVERGED; rel = 0.0; rel_true = 0.0;
+      hist.push_back(0.0);
+      break;
+    }
+    rel = std::sqrt(hs[SC_RR0]) / nf;
+    hist.push_back(rel);
+    if (!std::isfinite(rel)) { status = SGMG_NONFINITE; break; }
+    if (rel < rtol) { status = SGMG_CONVERGED; rel_true = rel; break; }
+    if ((rc = precondition(h->r, h->z))) break;
+    launch_pcg_dot_rz(h->r, h->z, nullptr, n, h->ws, sc + SC_RZ0, s);
+    launch_copy(h->z, h->p, n, s);
+    if ((rc = readsc())) break;
+    if (!std::isfinite(hs[SC_RZ0])) { status = SGMG_NONFINITE; break; }
+    if (hs[SC_RZ0] <= 0.0) { status = SGMG_BREAKDOWN; break; }
+    int slot = SC_RZ0;
+    for (int it = 1; it <= maxit; ++it) {
+      if ((rc = K64(h->p, h->q, sc + SC_PQ))) break;
+      launch_pcg_update_xr(u, h->r, flex ? h->r_old : nullptr, h->p, h->q, sc, slot, SC_PQ, n,
+                           h->ws, sc + SC_RR, s);
+      if ((rc = readsc())) break;
+      const double pq = hs[SC_PQ];
+      if (!std::isfinite(pq)) { status = SGMG_NONFINITE; iters = it - 1; break; }
+      if (pq <= 0.0) { status = SGMG_BREAKDOWN; iters = it - 1; break; }
+      iters = it;
+      rel = std::sqrt(hs[SC_RR]) / nf;
+      if (!std::isfinite(rel)) { hist.push_back(rel); status = SGMG_NONFINITE; break; }
+      if (rel < rtol) {
+        if ((rc = K64(u, h->tmp, nullptr))) break;
+        launch_residual(f, h->tmp, h->tmp, n, h->ws, sc + SC_TRUE, s);
+        if ((rc = readsc())) break;
+        const double rt = std::sqrt(hs[SC_TRUE]) / nf;
+        if (rt < rtol) { hist.push_back(rel); status = SGMG_CONVERGED; rel_true = rt; break; }
+        launch_copy(h->tmp, h->r, n, s);  // residual replacement
+        rel = rt;
+      }
+      hist.push_back(rel);
+      const int w = h->o.stag_window;
+      if (w > 0 && it >= w) {
+        const double recent = *std::min_element(hist.end() - w, hist.end());
+        const double before = *std::min_element(hist.begin(), hist.end() - w);
+        if (recent > 0.99 * before) { status = SGMG_STAGNATED; break; }
+      }
+      if (it == maxit) { status = SGMG_MAXIT; break; }
+      if ((rc = precondition(h->r, h->z))) break;
+      const int nslot = slot == SC_RZ0 ? SC_RZ1 : SC_RZ0;
+      launch_pcg_dot_rz(h->r, h->z, flex ? h->r_old : nullptr, n, h->ws, sc + nslot, s);
+      if ((rc = readsc())) break;
+      const double rz = hs[nslot];
+      if (!std::isfinite(rz)) { status = SGMG_NONFINITE; break; }
+      if (rz <= 0.0) { status = SGMG_BREAKDOWN; break; }
+      launch_pcg_update_p(h->p, h->z, sc, nslot, flex ? nslot + 1 : -1, slot, n, s);
+      if ((rc = check_launch())) break;
+      slot = nslot;
+    }
+    if (maxit == 0) status = SGMG_MAXIT;
+  } while (0);
+  if (rc) {
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc;
+  }
+  SGMG_HIP(hipEventRecord(e1, s));
+  if (rel_true < 0.0) {
+    TRY(K64(u, h->tmp, nullptr));
+    launch_residual(f, h->tmp, nullptr, n, h->ws, sc + SC_TRUE, s);
+    TRY(readsc());
+    rel_true = std::sqrt(hs[SC_TRUE]) / (nf > 0 ? nf : 1.0);
+  }
+  SGMG_HIP(hipStreamSynchronize(s));
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (info) {
+    info->status = status;
+    info->iters = iters;
+    info->rel_res_true = rel_true;
+    info->rel_res_recur = rel;
+    info->solve_ms = ms;
+    if (info->history && info->history_cap > 0) {
+      const int m = std::min<int>(info->history_cap, (int)hist.size());
+      for (int i = 0; i < m; ++i) info->history[i] = hist[i];
+      for (int i = m; i < info->history_cap; ++i) info->history[i] = 0.0;
+    }
+  }
+  return 0;
+}
+
+int sgmg_num_levels(const sgmg_hierarchy* h) { return h ? h->L : 0; }
+
+int sgmg_level_info(const sgmg_hierarchy* h, int level, int* dims, int* n_free, double* lambda) {
+  if (!h || level < 0 || level >= h->L) { set_error("bad level"); return SGMG_EINVAL; }
+  const Level& L = h->lev[level];
+  if (dims) { dims[0] = L.g.nx; dims[1] = L.g.ny; dims[2] = L.g.nz; }
+  if (n_free) *n_free = L.n_free;
+  if (lambda) *lambda = L.lam;
+  return 0;
+}
+
+int sgmg_copy_stencil(const sgmg_hierarchy* h, int level, double* host_out) {
+  if (!h || level < 1 || level >= h->L || !host_out) { set_error("bad level"); return SGMG_EINVAL; }
+  const Level& L = h->lev[level];
+  SGMG_HIP(hipMemcpy(host_out, L.S64, (size_t)kStencil * L.g.Nn * sizeof(double),
+                     hipMemcpyDeviceToHost));
+  return 0;
+}
+
+int sgmg_copy_diagonal(const sgmg_hierarchy* h, int level, double* host_out) {
+  if (!h || level < 0 || level >= h->L || !host_out) { set_error("bad level"); return SGMG_EINVAL; }
+  const Level& L = h->lev[level];
+  SGMG_HIP(hipMemcpy(host_out, L.d64, (size_t)L.g.n * sizeof(double), hipMemcpyDeviceToHost));
+  return 0;
+}
+
+}  // extern "C"

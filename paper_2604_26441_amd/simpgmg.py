@@ -1,0 +1,242 @@
+"""ctypes binding of libsimpgmg (include/simpgmg.h).
+
+Argument marshalling only: tensors are passed as device pointers together
+with the current HIP stream of torch; every step of the solver runs in the
+library's HIP kernels.  Importing this module raises if the built library is
+missing; there is no fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libsimpgmg.so")
+
+F64, F32, BF16, BF16X3 = 0, 1, 2, 3
+PRECISIONS = {"f64": F64, "f32": F32, "bf16": BF16, "bf16x3": BF16X3}
+STATUS = {0: "converged", 1: "maxit", 2: "stagnated", 3: "nonfinite", 4: "breakdown"}
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_VCYCLE = 0, 1, 2
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("nu", ctypes.c_double), ("E0", ctypes.c_double), ("Emin", ctypes.c_double),
+        ("penal", ctypes.c_double),
+        ("input_is_modulus", ctypes.c_int),
+        ("n_levels", ctypes.c_int),
+        ("fine_smoother", ctypes.c_int),
+        ("fine_degree", ctypes.c_int),
+        ("coarse_sweeps", ctypes.c_int),
+        ("cheb_alpha", ctypes.c_double),
+        ("jacobi_omega_max", ctypes.c_double),
+        ("lambda_safety", ctypes.c_double),
+        ("power_iters_fine", ctypes.c_int),
+        ("power_iters_coarse", ctypes.c_int),
+        ("fine_prec", ctypes.c_int),
+        ("level1_prec", ctypes.c_int),
+        ("dense_max", ctypes.c_int),
+        ("coarse_pcg_iters", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+        ("flexible_beta", ctypes.c_int),
+        ("stag_window", ctypes.c_int),
+        ("lambda_override", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int), ("iters", ctypes.c_int),
+        ("rel_res_true", ctypes.c_double), ("rel_res_recur", ctypes.c_double),
+        ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int),
+        ("solve_ms", ctypes.c_double),
+    ]
+
+
+EXPORTS = [
+    "sgmg_default_options", "sgmg_setup_hierarchy", "sgmg_update_moduli", "sgmg_apply_K",
+    "sgmg_vcycle", "sgmg_pcg_solve", "sgmg_num_levels", "sgmg_level_info",
+    "sgmg_copy_stencil", "sgmg_copy_diagonal", "sgmg_destroy", "sgmg_last_error",
+]
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"libsimpgmg.so not built ({_LIB_PATH}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    H = ctypes.c_void_p
+    lib.sgmg_default_options.argtypes = [ctypes.POINTER(Options), i, i, i]
+    lib.sgmg_default_options.restype = None
+    lib.sgmg_setup_hierarchy.argtypes = [ctypes.POINTER(Options), vp, vp, vp, ctypes.POINTER(H)]
+    lib.sgmg_update_moduli.argtypes = [H, vp, vp]
+    lib.sgmg_apply_K.argtypes = [H, i, i, vp, vp, vp]
+    lib.sgmg_vcycle.argtypes = [H, vp, vp, vp]
+    lib.sgmg_pcg_solve.argtypes = [H, i, vp, vp, d, i, ctypes.POINTER(SolveInfo), vp]
+    lib.sgmg_num_levels.argtypes = [H]
+    lib.sgmg_level_info.argtypes = [H, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_double)]
+    lib.sgmg_copy_stencil.argtypes = [H, i, ctypes.POINTER(ctypes.c_double)]
+    lib.sgmg_copy_diagonal.argtypes = [H, i, ctypes.POINTER(ctypes.c_double)]
+    lib.sgmg_destroy.argtypes = [H]
+    lib.sgmg_destroy.restype = None
+    lib.sgmg_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        getattr(lib, name)
+    return lib
+
+
+_lib = _load()
+
+
+def library_path():
+    return _LIB_PATH
+
+
+class SimpGmgError(RuntimeError):
+    pass
+
+
+def _check(rc):
+    if rc != 0:
+        raise SimpGmgError(f"libsimpgmg error {rc}: {_lib.sgmg_last_error().decode()}")
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, dtype, numel=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_options(nx, ny, nz, **kw):
+    o = Options()
+    _lib.sgmg_default_options(ctypes.byref(o), nx, ny, nz)
+    for k, v in kw.items():
+        if k in ("fine_prec", "level1_prec") and isinstance(v, str):
+            v = PRECISIONS[v]
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def n_nodes(o):
+    return (o.nx + 1) * (o.ny + 1) * (o.nz + 1)
+
+
+class Hierarchy:
+    """Owns an sgmg_hierarchy handle."""
+
+    def __init__(self, handle, opts):
+        self._h = handle
+        self.opts = opts
+        self.n_dof = 3 * n_nodes(opts)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _lib.sgmg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def num_levels(self):
+        return _lib.sgmg_num_levels(self._h)
+
+    def level_info(self, level):
+        dims = (ctypes.c_int * 3)()
+        nf = ctypes.c_int()
+        lam = ctypes.c_double()
+        _check(_lib.sgmg_level_info(self._h, level, dims, ctypes.byref(nf), ctypes.byref(lam)))
+        return {"dims": tuple(dims), "n_free": nf.value, "lambda": lam.value}
+
+    def stencil(self, level):
+        import numpy as np
+        dims = self.level_info(level)["dims"]
+        nn = (dims[0] + 1) * (dims[1] + 1) * (dims[2] + 1)
+        out = np.zeros(243 * nn)
+        _check(_lib.sgmg_copy_stencil(self._h, level, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out.reshape(27, 3, 3, nn)
+
+    def diagonal(self, level):
+        import numpy as np
+        dims = self.level_info(level)["dims"]
+        nn = (dims[0] + 1) * (dims[1] + 1) * (dims[2] + 1)
+        out = np.zeros(3 * nn)
+        _check(_lib.sgmg_copy_diagonal(self._h, level, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+
+def setup_hierarchy(opts, rho_or_E, fixed_dof=None, lambda_override=None, stream=None):
+    nel = opts.nx * opts.ny * opts.nz
+    p_rho = _ptr(rho_or_E, torch.float64, nel, "rho_or_E")
+    p_fix = None
+    if fixed_dof is not None:
+        p_fix = _ptr(fixed_dof, torch.uint8, 3 * n_nodes(opts), "fixed_dof")
+    keep = None
+    if lambda_override is not None:
+        keep = (ctypes.c_double * len(lambda_override))(*lambda_override)
+        opts.lambda_override = ctypes.cast(keep, ctypes.POINTER(ctypes.c_double))
+    h = ctypes.c_void_p()
+    try:
+        _check(_lib.sgmg_setup_hierarchy(ctypes.byref(opts), p_rho, p_fix, _stream(stream), ctypes.byref(h)))
+    finally:
+        opts.lambda_override = None
+    return Hierarchy(h, opts)
+
+
+def update_moduli(h, rho_or_E, stream=None):
+    nel = h.opts.nx * h.opts.ny * h.opts.nz
+    _check(_lib.sgmg_update_moduli(h.handle, _ptr(rho_or_E, torch.float64, nel, "rho_or_E"), _stream(stream)))
+
+
+def apply_K(h, level, prec, u, y, stream=None):
+    if isinstance(prec, str):
+        prec = PRECISIONS[prec]
+    dt = torch.float64 if prec == F64 else torch.float32
+    info = h.level_info(level)
+    d = info["dims"]
+    n = 3 * (d[0] + 1) * (d[1] + 1) * (d[2] + 1)
+    _check(_lib.sgmg_apply_K(h.handle, level, prec, _ptr(u, dt, n, "u"), _ptr(y, dt, n, "y"), _stream(stream)))
+
+
+def vcycle(h, r, z, stream=None):
+    _check(_lib.sgmg_vcycle(h.handle, _ptr(r, torch.float64, h.n_dof, "r"),
+                            _ptr(z, torch.float64, h.n_dof, "z"), _stream(stream)))
+
+
+def pcg_solve(h, f, u, rtol=1e-6, maxit=200, precond=PRECOND_VCYCLE, history_cap=0, stream=None):
+    info = SolveInfo()
+    hist = None
+    if history_cap:
+        hist = (ctypes.c_double * history_cap)()
+        info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+        info.history_cap = history_cap
+    _check(_lib.sgmg_pcg_solve(h.handle, precond, _ptr(f, torch.float64, h.n_dof, "f"),
+                               _ptr(u, torch.float64, h.n_dof, "u"), rtol, maxit, ctypes.byref(info),
+                               _stream(stream)))
+    out = {"status": STATUS.get(info.status, info.status), "status_code": info.status,
+           "iters": info.iters, "rel_res_true": info.rel_res_true,
+           "rel_res_recur": info.rel_res_recur, "solve_ms": info.solve_ms}
+    if hist is not None:
+        out["history"] = list(hist)[: info.iters + 1]
+    return out

@@ -1,0 +1,53 @@
+"""The C-ABI library loads and exports every entry point its header declares (CPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "simpgmg.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sgmg_[A-Za-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2604_26441_amd import simpgmg
+    lib = ctypes.CDLL(simpgmg.library_path())
+    names = _declared()
+    assert "sgmg_pcg_solve" in names and "sgmg_vcycle" in names
+    for n in names:
+        getattr(lib, n)                    # raises AttributeError if missing
+    assert set(names) == set(simpgmg.EXPORTS)
+
+
+def test_default_options_match_paper_defaults():
+    from paper_2604_26441_amd import simpgmg
+    o = simpgmg.default_options(16, 8, 8)
+    assert (o.nx, o.ny, o.nz) == (16, 8, 8)
+    assert o.nu == 0.3 and o.Emin == 1e-9 and o.penal == 3.0
+    assert o.n_levels == 4 and o.fine_degree == 2 and o.coarse_sweeps == 2
+    assert abs(o.cheb_alpha - 1 / 30) < 1e-16 and o.jacobi_omega_max == 0.5
+    assert o.power_iters_fine == 20 and o.power_iters_coarse == 10
+    assert o.dense_max == 5000 and o.coarse_pcg_iters == 80
+
+
+def test_struct_layout_matches_header(tmp_path):
+    from paper_2604_26441_amd import simpgmg
+    c = tmp_path / "sz.c"
+    c.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "%s"\n'
+                 'int main(){printf("%%zu %%zu %%zu %%zu\\n", sizeof(sgmg_options),'
+                 ' offsetof(sgmg_options, seed), offsetof(sgmg_options, lambda_override),'
+                 ' sizeof(sgmg_solve_info)); return 0;}\n' % HEADER)
+    exe = tmp_path / "sz"
+    r = subprocess.run(["gcc", str(c), "-o", str(exe)], capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("no host C compiler: " + r.stderr[:200])
+    vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert vals == [ctypes.sizeof(simpgmg.Options), simpgmg.Options.seed.offset,
+                    simpgmg.Options.lambda_override.offset, ctypes.sizeof(simpgmg.SolveInfo)]

@@ -1,0 +1,96 @@
+"""GPU parity of the operators against the oracle (through the C-ABI).
+
+Sizes span several 256-node tiles with ragged tails; one odd-dimension mesh
+exercises the trailing-node coarsening.  Tolerances: FP64 1e-13 and FP32 2e-6
+relative to |K||u| entry-wise magnitudes (FP32 unit roundoff 6e-8 times
+<= 216 accumulated terms).
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import galerkin, mesh, multigrid, smoothers
+from tests.gpu_util import np64, rel_err, t32, t64
+
+pytestmark = pytest.mark.gpu
+
+CASES = [((16, 8, 8), 3, 0), ((24, 12, 12), 4, 1), ((9, 7, 5), 3, 2)]
+
+
+def _inputs(dims, seed):
+    g = np.random.default_rng(seed)
+    rho = g.uniform(0.05, 1.0, np.prod(dims))
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    return rho, fixed
+
+
+def _gpu_h(dims, L, rho, **kw):
+    from paper_2604_26441_amd import simpgmg
+    o = simpgmg.default_options(*dims, n_levels=L, **kw)
+    return simpgmg.setup_hierarchy(o, t64(rho))
+
+
+@pytest.mark.parametrize("dims,L,seed", CASES)
+def test_fine_apply_f64_f32(dims, L, seed):
+    from paper_2604_26441_amd import simpgmg
+    rho, fixed = _inputs(dims, seed)
+    E = mesh.simp_modulus(rho, 3)
+    K = mesh.assemble(dims, E, fixed=fixed)
+    h = _gpu_h(dims, L, rho)
+    u = workloads.random_vector(fixed.size, seed + 10, fixed)
+    ref = K @ u
+    scale = abs(K) @ np.abs(u)
+    y = t64(np.zeros_like(u))
+    simpgmg.apply_K(h, 0, "f64", t64(u), y)
+    assert rel_err(np64(y), ref, scale) < 1e-13
+    y32 = t32(np.zeros_like(u))
+    simpgmg.apply_K(h, 0, "f32", t32(u), y32)
+    ref32 = K @ u.astype(np.float32).astype(np.float64)
+    assert rel_err(np64(y32), ref32, scale) < 2e-6
+    assert np.all(np64(y)[fixed] == 0) and np.all(np64(y32)[fixed] == 0)
+
+
+@pytest.mark.parametrize("dims,L,seed", CASES)
+def test_galerkin_levels_and_diagonals(dims, L, seed):
+    rho, fixed = _inputs(dims, seed)
+    E = mesh.simp_modulus(rho, 3)
+    oh = multigrid.build(dims, E, fixed, multigrid.Options(n_levels=L, lambdas=[1.0] * (L - 1)))
+    h = _gpu_h(dims, L, rho)
+    assert h.num_levels() == L
+    for l in range(L):
+        info = h.level_info(l)
+        assert info["dims"] == oh.levels[l].dims
+        assert info["n_free"] == int((~oh.levels[l].fixed).sum())
+        d = h.diagonal(l)
+        assert np.abs(d - oh.levels[l].d).max() <= 1e-13 * np.abs(oh.levels[l].d).max()
+    for l in range(1, L):
+        S = h.stencil(l)                                       # [27,3,3,nn]
+        ref = galerkin.stencil_blocks(oh.levels[l].K, oh.levels[l].dims)   # [nn,27,3,3]
+        ref = np.transpose(ref, (1, 2, 3, 0))
+        assert np.abs(S - ref).max() <= 1e-13 * np.abs(ref).max(), l
+
+
+@pytest.mark.parametrize("dims,L,seed", CASES[:2])
+def test_stencil_apply(dims, L, seed):
+    from paper_2604_26441_amd import simpgmg
+    rho, fixed = _inputs(dims, seed)
+    E = mesh.simp_modulus(rho, 3)
+    oh = multigrid.build(dims, E, fixed, multigrid.Options(n_levels=L, lambdas=[1.0] * (L - 1)))
+    h = _gpu_h(dims, L, rho)
+    for l in range(1, L):
+        K = oh.levels[l].K
+        u = workloads.random_vector(K.shape[0], seed + l, oh.levels[l].fixed)
+        y = t64(np.zeros_like(u))
+        simpgmg.apply_K(h, l, "f64", t64(u), y)
+        assert rel_err(np64(y), K @ u, abs(K) @ np.abs(u)) < 1e-13
+
+
+@pytest.mark.parametrize("dims,L,seed", CASES)
+def test_power_iteration_lambdas(dims, L, seed):
+    rho, fixed = _inputs(dims, seed)
+    E = mesh.simp_modulus(rho, 3)
+    oh = multigrid.build(dims, E, fixed, multigrid.Options(n_levels=L))
+    h = _gpu_h(dims, L, rho)
+    for l in range(L - 1):
+        lam = h.level_info(l)["lambda"]
+        assert abs(lam - oh.levels[l].lam) <= 1e-10 * oh.levels[l].lam, (l, lam, oh.levels[l].lam)

@@ -1,0 +1,112 @@
+"""GPU parity of the V-cycle and PCG against the oracle (through the C-ABI)."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import krylov, mesh, multigrid
+from tests.gpu_util import np64, rel_err, t64
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(dims, L, rho, fine_prec, fine_smoother=0, lambdas=None, level1_prec="f64"):
+    from paper_2604_26441_amd import simpgmg
+    o = simpgmg.default_options(*dims, n_levels=L, fine_prec=fine_prec,
+                                fine_smoother=fine_smoother, level1_prec=level1_prec)
+    return simpgmg.setup_hierarchy(o, t64(rho), lambda_override=lambdas)
+
+
+@pytest.mark.parametrize("dims,L,smoother", [((16, 8, 8), 3, 0), ((24, 12, 12), 4, 0),
+                                             ((16, 8, 8), 3, 1), ((9, 7, 5), 3, 0)])
+def test_vcycle_f64_matches_oracle(dims, L, smoother):
+    from paper_2604_26441_amd import simpgmg
+    g = np.random.default_rng(3)
+    rho = g.uniform(0.1, 1.0, np.prod(dims))
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    E = mesh.simp_modulus(rho, 3)
+    oh = multigrid.build(dims, E, fixed, multigrid.Options(
+        n_levels=L, fine_smoother="chebyshev" if smoother == 0 else "jacobi"))
+    lams = [lv.lam for lv in oh.levels[:-1]]
+    h = _setup(dims, L, rho, "f64", smoother, lams)
+    r = workloads.random_vector(fixed.size, 5, fixed)
+    z = t64(np.zeros_like(r))
+    simpgmg.vcycle(h, t64(r), z)
+    ref = multigrid.vcycle(oh, r)
+    assert rel_err(np64(z), ref, ref) < 1e-11
+
+
+def test_vcycle_f32_close_to_oracle():
+    from paper_2604_26441_amd import simpgmg
+    dims, L = (24, 12, 12), 4
+    rho = np.random.default_rng(4).uniform(0.1, 1.0, np.prod(dims))
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    oh = multigrid.build(dims, mesh.simp_modulus(rho, 3), fixed, multigrid.Options(n_levels=L))
+    lams = [lv.lam for lv in oh.levels[:-1]]
+    h = _setup(dims, L, rho, "f32", 0, lams)
+    r = workloads.random_vector(fixed.size, 6, fixed)
+    z = t64(np.zeros_like(r))
+    simpgmg.vcycle(h, t64(r), z)
+    ref = multigrid.vcycle(oh, r)
+    assert rel_err(np64(z), ref, ref) < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_config0_pcg(prec):
+    """16x8x8 cantilever, rho = 0.5, p = 3, 3 levels, rtol 1e-6, cap 200."""
+    from paper_2604_26441_amd import simpgmg
+    dims = (16, 8, 8)
+    rho = workloads.uniform_rho(dims)
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    f = workloads.edge_load(dims)
+    E = mesh.simp_modulus(rho, 3)
+    K = mesh.assemble(dims, E, fixed=fixed)
+    oh = multigrid.build(dims, E, fixed, multigrid.Options(n_levels=3))
+    xo, st, it_o, _ = krylov.pcg(lambda v: K @ v, f, lambda r: multigrid.vcycle(oh, r), rtol=1e-6, maxit=200)
+    h = _setup(dims, 3, rho, prec)
+    u = t64(np.zeros_like(f))
+    res = simpgmg.pcg_solve(h, t64(f), u, rtol=1e-6, maxit=200, history_cap=256)
+    assert res["status"] == "converged"
+    x = np64(u)
+    assert krylov.true_rel_residual(lambda v: K @ v, f, x) < 1e-6
+    assert abs(res["rel_res_true"] - krylov.true_rel_residual(lambda v: K @ v, f, x)) < 1e-9
+    if prec == "f64":
+        assert abs(res["iters"] - it_o) <= 1
+    else:
+        assert abs(res["iters"] - it_o) <= max(1, int(0.15 * it_o))
+    # compliance against the oracle's converged solution
+    assert abs(f @ x - f @ xo) <= 1e-5 * abs(f @ xo)
+
+
+def test_jacobi_pcg_matches_oracle():
+    from paper_2604_26441_amd import simpgmg
+    dims = (16, 8, 8)
+    rho = workloads.uniform_rho(dims)
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    f = workloads.edge_load(dims)
+    K = mesh.assemble(dims, mesh.simp_modulus(rho, 3), fixed=fixed)
+    oh = multigrid.build(dims, mesh.simp_modulus(rho, 3), fixed, multigrid.Options(n_levels=3))
+    _, st, it_o, hist_o = krylov.pcg(lambda v: K @ v, f, lambda r: oh.levels[0].dinv * r,
+                                     rtol=1e-6, maxit=500)
+    h = _setup(dims, 3, rho, "f64")
+    u = t64(np.zeros_like(f))
+    res = simpgmg.pcg_solve(h, t64(f), u, rtol=1e-6, maxit=500, precond=1, history_cap=600)
+    assert res["status"] == "converged" and abs(res["iters"] - it_o) <= 1
+    n = min(len(hist_o), len(res["history"])) - 2
+    assert np.allclose(res["history"][:n], hist_o[:n], rtol=1e-6)
+
+
+def test_failure_statuses():
+    from paper_2604_26441_amd import simpgmg
+    dims = (16, 8, 8)
+    rho = workloads.uniform_rho(dims)
+    f = workloads.edge_load(dims)
+    h = _setup(dims, 3, rho, "f32")
+    u = t64(np.zeros_like(f))
+    assert simpgmg.pcg_solve(h, t64(f), u, maxit=1)["status"] == "maxit"
+    fn = f.copy()
+    fn[-1] = np.nan
+    u = t64(np.zeros_like(f))
+    assert simpgmg.pcg_solve(h, t64(fn), u, maxit=5)["status"] == "nonfinite"
+    u = t64(np.zeros_like(f))
+    res = simpgmg.pcg_solve(h, t64(np.zeros_like(f)), u, maxit=5)
+    assert res["status"] == "converged" and res["iters"] == 0
