@@ -1,0 +1,178 @@
+"""Benchmark: FP32-GMG PCG solve of the 80^3 hex8 SIMP cantilever on one MI355X.
+
+One step = setup_hierarchy + pcg_solve (cold start) of the 512k-element
+cantilever (rho = 0.5, p = 3, x = 0 clamped, unit -z edge load), 4 levels,
+rtol 1e-6 on the FP64 true residual, cap 200.  ``value`` is the mean solve
+time in ms (HIP events around the solve on the solver's stream).  The line
+also carries the roofline of the dominant kernel, timed with HIP events on
+the stream it runs on, and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK = 78.6      # TFLOP/s without packed FP32 (256 CU x 64 lanes x 2 x 2.4 GHz)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=80, help="elements per axis of the cube")
+    ap.add_argument("--fine-prec", default=os.environ.get("SGMG_FINE_PREC", "f32"))
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip FP64-GMG and Jacobi-PCG comparisons")
+    return ap.parse_args()
+
+
+def cpu_baseline(n, iters_full, sample_iters=3):
+    """Oracle FP64 PCG-GMG on the same n^3 workload, one thread: the first
+    ``sample_iters`` PCG iterations are timed (hierarchy setup untimed) and the
+    per-iteration cost is scaled to ``iters_full`` iterations."""
+    from threadpoolctl import threadpool_limits
+    import workloads
+    from oracle import krylov, mesh, multigrid
+    dims = (n, n, n)
+    with threadpool_limits(limits=1):
+        rho = workloads.uniform_rho(dims)
+        fixed = workloads.cantilever_fixed(dims).astype(bool)
+        f = workloads.edge_load(dims)
+        E = mesh.simp_modulus(rho, 3)
+        oh = multigrid.build(dims, E, fixed, multigrid.Options(n_levels=4))
+        K = oh.levels[0].K
+        t0 = time.perf_counter()
+        krylov.pcg(lambda v: K @ v, f, lambda r: multigrid.vcycle(oh, r), rtol=1e-6,
+                   maxit=sample_iters)
+        t = time.perf_counter() - t0
+    per_it = t / sample_iters
+    return {"value": round(per_it * iters_full * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample_iters} iterations of the oracle FP64 PCG-GMG solve of the same "
+                      f"{n}^3 cantilever ({t:.1f} s, setup untimed), scaled per iteration to the "
+                      f"{iters_full} iterations of the measured solve"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: the solver runs on one GPU; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads
+    from paper_2604_26441_amd import simpgmg
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = args.n
+    dims = (n, n, n)
+    rho = torch.tensor(workloads.uniform_rho(dims), dtype=torch.float64, device=dev)
+    f = torch.tensor(workloads.edge_load(dims), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def opts(**kw):
+        return simpgmg.default_options(*dims, n_levels=4, **kw)
+
+    def step(o, precond=2, maxit=200):
+        t0 = time.perf_counter()
+        h = simpgmg.setup_hierarchy(o, rho)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        u = torch.zeros_like(f)
+        res = simpgmg.pcg_solve(h, f, u, rtol=1e-6, maxit=maxit, precond=precond)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return h, res, (t1 - t0) * 1e3, (t2 - t1) * 1e3
+
+    o32 = opts(fine_prec=args.fine_prec)
+    for _ in range(args.warmup):
+        h, res, _, _ = step(o32)
+        h.close()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    solve_ms, setup_ms, iters, status, relres = [], [], [], [], []
+    for k in range(args.steps):
+        h, res, su, _ = step(o32)
+        solve_ms.append(res["solve_ms"])
+        setup_ms.append(su)
+        iters.append(res["iters"])
+        status.append(res["status"])
+        relres.append(res["rel_res_true"])
+        if k != args.steps - 1:
+            h.close()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t_start) * 1e3
+
+    # dominant-kernel timing: the fine K.u in the smoother precision, 200
+    # back-to-back launches on torch's current stream, HIP events around them
+    prec = simpgmg.PRECISIONS[args.fine_prec]
+    dt = torch.float64 if prec == simpgmg.F64 else torch.float32
+    fixed = torch.tensor(workloads.cantilever_fixed(dims), device=dev).bool()
+    uk = torch.ones(3 * (n + 1) ** 3, dtype=dt, device=dev).masked_fill_(fixed, 0)
+    yk = torch.empty_like(uk)
+    for _ in range(5):
+        simpgmg.apply_K(h, 0, prec, uk, yk)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.kernel_reps):
+        simpgmg.apply_K(h, 0, prec, uk, yk)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ku_us = ev0.elapsed_time(ev1) * 1e3 / args.kernel_reps
+    es = 8 if prec == simpgmg.F64 else 4
+    nodes, nel = (n + 1) ** 3, n ** 3
+    ku_bytes = 2 * 3 * nodes * es + nel * es          # read u, write y, read E
+    ku_flop = 2 * 24 * 24 * nel
+    achieved = ku_bytes / (ku_us * 1e-6) / 1e9
+    h.close()
+
+    extra = {}
+    if not args.no_compare:
+        h, r64, su64, _ = step(opts(fine_prec="f64"))
+        h.close()
+        h, rj, suj, _ = step(opts(fine_prec="f64", n_levels=2), precond=1, maxit=200)
+        h.close()
+        extra = {"fp64_gmg": {"solve_ms": round(r64["solve_ms"], 3), "iters": r64["iters"],
+                              "status": r64["status"]},
+                 "jacobi_pcg_cap200": {"solve_ms": round(rj["solve_ms"], 3), "iters": rj["iters"],
+                                       "status": rj["status"], "rel_res_true": rj["rel_res_true"]}}
+
+    mean_solve = float(np.mean(solve_ms))
+    line = {
+        "metric": "PCG-GMG solve ms at 512k elems @1e-6 rel-res; K·u HBM GB/s; iters vs warm-start",
+        "value": round(mean_solve, 3),
+        "unit": "ms",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "f64": "f64", "bf16": "bf16", "bf16x3": "f32"}[args.fine_prec],
+        "data": "synthetic",
+        "config": {"workload": f"hex8 SIMP cantilever {n}x{n}x{n} ({nel} elements), rho=0.5, p=3, "
+                               f"FP32-GMG-PCG, 4 levels, Chebyshev deg 2, rtol 1e-6, cap 200",
+                   "fine_prec": args.fine_prec},
+        "solve_ms_std": round(float(np.std(solve_ms)), 3),
+        "setup_ms": round(float(np.mean(setup_ms)), 3),
+        "iters": iters, "status": status, "rel_res_true": relres,
+        "ku": {"kernel": "fine K.u (sgmg_apply_K level 0)", "us": round(ku_us, 3),
+               "GBs": round(achieved, 1), "GFLOPs": round(ku_flop / (ku_us * 1e-6) / 1e9, 1)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        **extra,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(n, int(round(np.mean(iters))))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

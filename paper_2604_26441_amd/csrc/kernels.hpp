@@ -16,11 +16,13 @@ void launch_diag_fine(const Grid& g, const double* E, const double* ke, const ui
 template <typename T>
 void launch_apply_fine_node(const Grid& g, const T* E, const T* ke, const T* u,
                             const uint8_t* fixn, const Epi<T>& ep, hipStream_t s);
-// Fixed-point/BF16 MFMA element kernel (kernels_mfma.hip); nsplit = 1 or 3.
-void launch_apply_fine_mfma(const Grid& g, int nsplit, const float* Escaled, const void* kbf16,
+// BF16 MFMA element kernel (kernels_mfma.hip); nsplit = 1 (BF16) or 3 (BF16X3).
+void launch_apply_fine_mfma(const Grid& g, int nsplit, const float* Escaled, const void* atab,
                             const float* u, const uint8_t* fixn, const Epi<float>& ep,
                             hipStream_t s);
 size_t apply_fine_mfma_blocks(const Grid& g);
+void launch_scale_E(const double* E, float* Es, int nel, double inv_s, hipStream_t s);
+void build_mfma_atab(const KeTables& kt, uint16_t* out /* 2 * 64 * 8 */);
 
 // ---- stencil levels (kernels_stencil.hip) ----------------------------------
 // Level-1 Galerkin aggregation: S1 = M1 sum_e E_e P_e^T (M_e K_e M_e) P_e M1.

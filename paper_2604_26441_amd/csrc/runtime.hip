@@ -58,6 +58,8 @@ struct sgmg_hierarchy {
   double* gtab = nullptr;
   double* E64 = nullptr;
   float* E32 = nullptr;
+  float* E32s = nullptr;     // E / s for the MFMA kernel
+  uint16_t* atab = nullptr;  // MFMA A-operand table (BF16 bits)
   double maxE_lambda = 0.0;  // max E when lambdas were estimated
   int nL = 0;
   int* free_idx = nullptr;
@@ -213,8 +215,14 @@ int apply_level<float>(const sgmg_hierarchy* h, int l, sgmg_prec prec, const flo
   if (l == 0) {
     if (prec == SGMG_F32) {
       launch_apply_fine_node<float>(L.g, h->E32, h->ke32, x, L.fixn, ep, s);
+    } else if (prec == SGMG_BF16 || prec == SGMG_BF16X3) {
+      if (!h->kt.integral) {
+        set_error("BF16 MFMA path needs s*K_e integral (nu = 0.3 family); use F32");
+        return SGMG_EINVAL;
+      }
+      launch_apply_fine_mfma(L.g, prec == SGMG_BF16 ? 1 : 3, h->E32s, h->atab, x, L.fixn, ep, s);
     } else {
-      set_error("precision not available for the fine operator in this build");
+      set_error("float vectors need F32, BF16 or BF16X3");
       return SGMG_EINVAL;
     }
   } else {
@@ -267,6 +275,7 @@ int assemble_operators(sgmg_hierarchy* h, const double* rho_or_E, hipStream_t s)
   const sgmg_options& o = h->o;
   Level& L0 = h->lev[0];
   launch_simp(rho_or_E, h->E64, h->E32, L0.g.nel, o.input_is_modulus, o.E0, o.Emin, o.penal, s);
+  launch_scale_E(h->E64, h->E32s, L0.g.nel, 1.0 / h->kt.kscale, s);
   launch_diag_fine(L0.g, h->E64, h->ke64, L0.fixn, L0.d64, s);
   for (int l = 1; l < h->L; ++l) {
     Level& F = h->lev[l - 1];
@@ -609,7 +618,15 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
   hipMemcpyAsync(h->ke64, h->kt.ke, 576 * sizeof(double), hipMemcpyHostToDevice, s);
   hipMemcpyAsync(h->ke32, h->kt.ke32, 576 * sizeof(float), hipMemcpyHostToDevice, s);
   hipMemcpyAsync(h->gtab, gt.data(), gt.size() * sizeof(double), hipMemcpyHostToDevice, s);
-  if ((rc = dalloc_t(h, &h->E64, g0.nel)) || (rc = dalloc_t(h, &h->E32, g0.nel))) return fail(rc);
+  if ((rc = dalloc_t(h, &h->E64, g0.nel)) || (rc = dalloc_t(h, &h->E32, g0.nel)) ||
+      (rc = dalloc_t(h, &h->E32s, g0.nel)) || (rc = dalloc_t(h, &h->atab, 2 * 64 * 8)))
+    return fail(rc);
+  {
+    std::vector<uint16_t> at(2 * 64 * 8);
+    build_mfma_atab(h->kt, at.data());
+    hipMemcpyAsync(h->atab, at.data(), at.size() * sizeof(uint16_t), hipMemcpyHostToDevice, s);
+    if (hipStreamSynchronize(s) != hipSuccess) { set_error("sync failed"); return fail(SGMG_EHIP); }
+  }
   // reductions, scalars, PCG vectors
   // one partial per block of the largest reduction grid (fused dots run one
   // block per 256 nodes; vector reductions use at most 2 x 1024 slots)

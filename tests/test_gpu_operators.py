@@ -94,3 +94,43 @@ def test_power_iteration_lambdas(dims, L, seed):
     for l in range(L - 1):
         lam = h.level_info(l)["lambda"]
         assert abs(lam - oh.levels[l].lam) <= 1e-10 * oh.levels[l].lam, (l, lam, oh.levels[l].lam)
+
+
+MFMA_CASES = [((16, 8, 8), 0), ((9, 7, 5), 1), ((31, 6, 20), 2), ((24, 12, 12), 3)]
+
+
+@pytest.mark.parametrize("dims,seed", MFMA_CASES)
+def test_fine_apply_mfma_bf16x3_and_bf16(dims, seed):
+    """MFMA K.u: BF16X3 is FP32-accurate; BF16 equals the BF16 semantic model
+    (input rounded to BF16, exact element matrix, FP32 accumulation)."""
+    from oracle import bf16
+    from paper_2604_26441_amd import simpgmg
+    rho, fixed = _inputs(dims, seed)
+    E = mesh.simp_modulus(rho, 3)
+    K = mesh.assemble(dims, E, fixed=fixed)
+    h = _gpu_h(dims, 2, rho)
+    u = workloads.random_vector(fixed.size, seed + 20, fixed).astype(np.float32).astype(np.float64)
+    scale = abs(K) @ np.abs(u)
+    y3 = t32(np.zeros_like(u))
+    simpgmg.apply_K(h, 0, "bf16x3", t32(u), y3)
+    assert rel_err(np64(y3), K @ u, scale) < 2e-6
+    y1 = t32(np.zeros_like(u))
+    simpgmg.apply_K(h, 0, "bf16", t32(u), y1)
+    ref1 = bf16.apply_K_bf16_model(dims, E, u, fixed)
+    assert rel_err(np64(y1), ref1, scale) < 2e-6
+    assert rel_err(np64(y1), K @ u, scale) < 2.0 ** -8
+    assert np.all(np64(y3)[fixed] == 0) and np.all(np64(y1)[fixed] == 0)
+
+
+def test_fine_apply_deterministic():
+    """Owner-computes scatter: two applications are bitwise identical."""
+    from paper_2604_26441_amd import simpgmg
+    dims = (24, 12, 12)
+    rho, fixed = _inputs(dims, 9)
+    h = _gpu_h(dims, 2, rho)
+    u = t32(workloads.random_vector(fixed.size, 9, fixed))
+    for prec in ("bf16x3", "bf16", "f32"):
+        a, b = t32(np.zeros(fixed.size)), t32(np.zeros(fixed.size))
+        simpgmg.apply_K(h, 0, prec, u, a)
+        simpgmg.apply_K(h, 0, prec, u, b)
+        assert np.array_equal(np64(a), np64(b)), prec
