@@ -29,9 +29,10 @@
  *     after a call returns.
  *   Streams: every call is ordered on the given HIP stream (0 = the null
  *     stream).  sgmg_setup_hierarchy and sgmg_update_moduli synchronise the
- *     stream before returning; sgmg_pcg_solve synchronises at every outer
- *     iteration to read the residual; sgmg_apply_K and sgmg_vcycle are
- *     asynchronous.  Calls on one hierarchy must not overlap.
+ *     stream before returning; sgmg_pcg_solve synchronises once per outer
+ *     iteration to read its scalars; sgmg_apply_K and sgmg_vcycle are
+ *     asynchronous.  Calls on one hierarchy must not overlap (they share the
+ *     hierarchy's work vectors).
  *   Errors: 0 = success; SGMG_EINVAL (-1) invalid argument or a mesh that
  *     cannot be coarsened to the requested depth; SGMG_EHIP (-2) a HIP runtime
  *     error; SGMG_ENOMEM (-3) device allocation failed; SGMG_EFACTOR (-4) the
@@ -97,6 +98,9 @@ typedef struct {
   int flexible_beta;         /* 1: Polak-Ribiere beta in PCG, 0: Fletcher-Reeves     */
   int stag_window;           /* 0 = off; else stagnation window in iterations        */
   const double* lambda_override; /* host array of n_levels-1 raw estimates, or NULL  */
+  int use_graphs;            /* 1: each PCG iteration (K.p, updates, V-cycle) is
+                                replayed from a HIP graph captured once per
+                                hierarchy; 0: direct launches (same results)      */
 } sgmg_options;
 
 typedef struct {

@@ -7,7 +7,7 @@ V-cycle (or D^-1, or nothing) as preconditioner; convergence is
 ||f - K x||_2 / ||f||_2 < rtol checked on the true residual; iteration caps,
 stagnation and non-finite iterates are failures.  Readings: the recursive
 residual triggers the true-residual check, a failed check replaces r by the
-true residual; stagnation (opt-in, window w, the paper's Jacobi-PCG runs reach
+true residual and restarts the recurrence (beta = 0); stagnation (opt-in, window w, the paper's Jacobi-PCG runs reach
 the cap rather than stop early) = the best relative residual of the last w
 iterations is not 1% below the best before them; beta is Fletcher-Reeves, or
 Polak-Ribiere (flexible) on request.
@@ -63,6 +63,9 @@ def pcg(apply_A, f, precond=None, x0=None, rtol=1e-6, maxit=200, flexible=False,
                 return x, CONVERGED, it, hist
             r = rt
             rel = rel_true
+            restart = True
+        else:
+            restart = False
         hist.append(rel)
         if stag_window and it >= stag_window:
             if min(hist[-stag_window:]) > 0.99 * min(hist[:-stag_window]):
@@ -73,7 +76,9 @@ def pcg(apply_A, f, precond=None, x0=None, rtol=1e-6, maxit=200, flexible=False,
             return x, NONFINITE, it, hist
         if rz_new <= 0:
             return x, BREAKDOWN, it, hist
-        if flexible:
+        if restart:
+            beta = 0.0
+        elif flexible:
             beta = float(z @ (r - r_old)) / rz
         else:
             beta = rz_new / rz

@@ -76,7 +76,10 @@ struct sgmg_hierarchy {
   double* q = nullptr;
   double* r_old = nullptr;
   double* tmp = nullptr;
+  double* xs = nullptr;      // solver-owned copy of the iterate (graphs bind it)
   double* gj_scratch = nullptr;
+  hipStream_t cap = nullptr; // capture stream
+  hipGraphExec_t iter_graph[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
 };
 
 namespace {
@@ -510,10 +513,15 @@ void sgmg_default_options(sgmg_options* o, int nx, int ny, int nz) {
   o->flexible_beta = 0;
   o->stag_window = 0;
   o->lambda_override = nullptr;
+  o->use_graphs = 1;
 }
 
 void sgmg_destroy(sgmg_hierarchy* h) {
   if (!h) return;
+  for (auto& row : h->iter_graph)
+    for (auto& g : row)
+      if (g) hipGraphExecDestroy(g);
+  if (h->cap) hipStreamDestroy(h->cap);
   for (void* p : h->allocs) hipFree(p);
   if (h->h_sc) hipHostFree(h->h_sc);
   delete h;
@@ -640,7 +648,7 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
     set_error("pinned allocation failed");
     return fail(SGMG_ENOMEM);
   }
-  for (double** v : {&h->r, &h->z, &h->p, &h->q, &h->r_old, &h->tmp})
+  for (double** v : {&h->r, &h->z, &h->p, &h->q, &h->r_old, &h->tmp, &h->xs})
     if ((rc = dalloc_t(h, v, maxn))) return fail(rc);
   // coarsest free index list
   {
@@ -673,6 +681,9 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
 int sgmg_update_moduli(sgmg_hierarchy* h, const double* rho_or_E, void* stream) {
   if (!h || !rho_or_E) { set_error("NULL argument"); return SGMG_EINVAL; }
   hipStream_t s = as_stream(stream);
+  for (auto& row : h->iter_graph)
+    for (auto& g : row)
+      if (g) { hipGraphExecDestroy(g); g = nullptr; }
   TRY(assemble_operators(h, rho_or_E, s));
   const double m = max_modulus(h, s);
   if (h->maxE_lambda <= 0.0 || std::fabs(m - h->maxE_lambda) > 0.1 * h->maxE_lambda)
@@ -697,6 +708,49 @@ int sgmg_vcycle(const sgmg_hierarchy* h, const double* r, double* z, void* strea
   return vcycle_full(h, r, z, as_stream(stream));
 }
 
+// One PCG iteration on device buffers only (so it can be captured):
+// q = K p (p.q), x += alpha p, r -= alpha q (r.r), z = M r, r.z (and r_old.z),
+// p = z + beta p.  Scalars stay on the device in slot pairs that alternate
+// with the iteration parity.
+static int pcg_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
+  const Level& L0 = h->lev[0];
+  const int n = L0.g.n;
+  double* sc = h->sc;
+  const bool flex = h->o.flexible_beta != 0;
+  const int nslot = slot == SC_RZ0 ? SC_RZ1 : SC_RZ0;
+  TRY(apply_level<double>(h, 0, SGMG_F64, h->p, epi_store<double>(h->q, h->ws, sc + SC_PQ), s));
+  launch_pcg_update_xr(h->xs, h->r, flex ? h->r_old : nullptr, h->p, h->q, sc, slot, SC_PQ, n,
+                       h->ws, sc + SC_RR, s);
+  if (precond == 2) TRY(vcycle_full(h, h->r, h->z, s));
+  else if (precond == 1) launch_apply_dinv(L0.dinv64, h->r, h->z, n, s);
+  else launch_copy(h->r, h->z, n, s);
+  launch_pcg_dot_rz(h->r, h->z, flex ? h->r_old : nullptr, n, h->ws, sc + nslot, s);
+  launch_pcg_update_p(h->p, h->z, sc, nslot, flex ? nslot + 1 : -1, slot, n, s);
+  return check_launch();
+}
+
+static int run_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
+  if (!h->o.use_graphs) return pcg_body(h, precond, slot, s);
+  const int par = slot == SC_RZ0 ? 0 : 1;
+  hipGraphExec_t& ge = h->iter_graph[precond][par];
+  if (!ge) {
+    if (!h->cap) SGMG_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    // the capture stream must not run ahead of work already queued on s
+    SGMG_HIP(hipStreamSynchronize(s));
+    SGMG_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = pcg_body(h, precond, slot, h->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->cap, &g);
+    if (rc) { if (g) hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) { set_error(std::string("graph capture: ") + hipGetErrorString(e)); return SGMG_EHIP; }
+    const hipError_t e2 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e2 != hipSuccess) { ge = nullptr; set_error(std::string("graph instantiate: ") + hipGetErrorString(e2)); return SGMG_EHIP; }
+  }
+  SGMG_HIP(hipGraphLaunch(ge, s));
+  return 0;
+}
+
 int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, double rtol,
                    int maxit, sgmg_solve_info* info, void* stream) {
   if (!h || !f || !u) { set_error("NULL argument"); return SGMG_EINVAL; }
@@ -711,8 +765,7 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
   SGMG_HIP(hipEventCreate(&e1));
   SGMG_HIP(hipEventRecord(e0, s));
   auto K64 = [&](const double* x, double* y, double* dot_out) {
-    return apply_level<double>(h, 0, SGMG_F64, x,
-                               epi_store<double>(y, h->ws, dot_out), s);
+    return apply_level<double>(h, 0, SGMG_F64, x, epi_store<double>(y, h->ws, dot_out), s);
   };
   auto precondition = [&](const double* r, double* z) -> int {
     if (precond == 2) return vcycle_full(h, r, z, s);
@@ -725,18 +778,18 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
     SGMG_HIP(hipStreamSynchronize(s));
     return 0;
   };
-  const bool flex = h->o.flexible_beta != 0;
   int status = SGMG_MAXIT, iters = 0;
   double rel = 0.0, rel_true = -1.0, nf = 0.0;
   std::vector<double> hist;
   int rc = 0;
+  launch_copy(u, h->xs, n, s);
   do {
-    if ((rc = K64(u, h->q, nullptr))) break;
+    if ((rc = K64(h->xs, h->q, nullptr))) break;
     launch_pcg_init(f, h->q, 1, h->r, n, h->ws, sc + SC_FF, s);
     if ((rc = readsc())) break;
     nf = std::sqrt(hs[SC_FF]);
     if (nf == 0.0) {
-      SGMG_HIP(hipMemsetAsync(u, 0, n * sizeof(double), s));
+      SGMG_HIP(hipMemsetAsync(h->xs, 0, n * sizeof(double), s));
       status = SGMG_CONVERGED; rel = 0.0; rel_true = 0.0;
       hist.push_back(0.0);
       break;
@@ -745,6 +798,7 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
     hist.push_back(rel);
     if (!std::isfinite(rel)) { status = SGMG_NONFINITE; break; }
     if (rel < rtol) { status = SGMG_CONVERGED; rel_true = rel; break; }
+    if (maxit == 0) { status = SGMG_MAXIT; break; }
     if ((rc = precondition(h->r, h->z))) break;
     launch_pcg_dot_rz(h->r, h->z, nullptr, n, h->ws, sc + SC_RZ0, s);
     launch_copy(h->z, h->p, n, s);
@@ -753,9 +807,8 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
     if (hs[SC_RZ0] <= 0.0) { status = SGMG_BREAKDOWN; break; }
     int slot = SC_RZ0;
     for (int it = 1; it <= maxit; ++it) {
-      if ((rc = K64(h->p, h->q, sc + SC_PQ))) break;
-      launch_pcg_update_xr(u, h->r, flex ? h->r_old : nullptr, h->p, h->q, sc, slot, SC_PQ, n,
-                           h->ws, sc + SC_RR, s);
+      const int nslot = slot == SC_RZ0 ? SC_RZ1 : SC_RZ0;
+      if ((rc = run_body(h, precond, slot, s))) break;
       if ((rc = readsc())) break;
       const double pq = hs[SC_PQ];
       if (!std::isfinite(pq)) { status = SGMG_NONFINITE; iters = it - 1; break; }
@@ -763,13 +816,20 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
       iters = it;
       rel = std::sqrt(hs[SC_RR]) / nf;
       if (!std::isfinite(rel)) { hist.push_back(rel); status = SGMG_NONFINITE; break; }
+      bool restarted = false;
       if (rel < rtol) {
-        if ((rc = K64(u, h->tmp, nullptr))) break;
+        if ((rc = K64(h->xs, h->tmp, nullptr))) break;
         launch_residual(f, h->tmp, h->tmp, n, h->ws, sc + SC_TRUE, s);
         if ((rc = readsc())) break;
         const double rt = std::sqrt(hs[SC_TRUE]) / nf;
         if (rt < rtol) { hist.push_back(rel); status = SGMG_CONVERGED; rel_true = rt; break; }
-        launch_copy(h->tmp, h->r, n, s);  // residual replacement
+        // residual replacement with a restart of the recurrence (beta = 0)
+        launch_copy(h->tmp, h->r, n, s);
+        if ((rc = precondition(h->r, h->z))) break;
+        launch_pcg_dot_rz(h->r, h->z, nullptr, n, h->ws, sc + nslot, s);
+        launch_copy(h->z, h->p, n, s);
+        if ((rc = readsc())) break;
+        restarted = true;
         rel = rt;
       }
       hist.push_back(rel);
@@ -780,27 +840,22 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
         if (recent > 0.99 * before) { status = SGMG_STAGNATED; break; }
       }
       if (it == maxit) { status = SGMG_MAXIT; break; }
-      if ((rc = precondition(h->r, h->z))) break;
-      const int nslot = slot == SC_RZ0 ? SC_RZ1 : SC_RZ0;
-      launch_pcg_dot_rz(h->r, h->z, flex ? h->r_old : nullptr, n, h->ws, sc + nslot, s);
-      if ((rc = readsc())) break;
       const double rz = hs[nslot];
       if (!std::isfinite(rz)) { status = SGMG_NONFINITE; break; }
       if (rz <= 0.0) { status = SGMG_BREAKDOWN; break; }
-      launch_pcg_update_p(h->p, h->z, sc, nslot, flex ? nslot + 1 : -1, slot, n, s);
-      if ((rc = check_launch())) break;
+      (void)restarted;
       slot = nslot;
     }
-    if (maxit == 0) status = SGMG_MAXIT;
   } while (0);
   if (rc) {
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     return rc;
   }
+  launch_copy(h->xs, u, n, s);
   SGMG_HIP(hipEventRecord(e1, s));
   if (rel_true < 0.0) {
-    TRY(K64(u, h->tmp, nullptr));
+    TRY(K64(h->xs, h->tmp, nullptr));
     launch_residual(f, h->tmp, nullptr, n, h->ws, sc + SC_TRUE, s);
     TRY(readsc());
     rel_true = std::sqrt(hs[SC_TRUE]) / (nf > 0 ? nf : 1.0);

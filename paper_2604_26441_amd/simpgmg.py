@@ -41,6 +41,7 @@ class Options(ctypes.Structure):
         ("flexible_beta", ctypes.c_int),
         ("stag_window", ctypes.c_int),
         ("lambda_override", ctypes.POINTER(ctypes.c_double)),
+        ("use_graphs", ctypes.c_int),
     ]
 
 

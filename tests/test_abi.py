@@ -42,7 +42,7 @@ def test_struct_layout_matches_header(tmp_path):
     c = tmp_path / "sz.c"
     c.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "%s"\n'
                  'int main(){printf("%%zu %%zu %%zu %%zu\\n", sizeof(sgmg_options),'
-                 ' offsetof(sgmg_options, seed), offsetof(sgmg_options, lambda_override),'
+                 ' offsetof(sgmg_options, seed), offsetof(sgmg_options, use_graphs),'
                  ' sizeof(sgmg_solve_info)); return 0;}\n' % HEADER)
     exe = tmp_path / "sz"
     r = subprocess.run(["gcc", str(c), "-o", str(exe)], capture_output=True, text=True)
@@ -50,4 +50,4 @@ def test_struct_layout_matches_header(tmp_path):
         pytest.skip("no host C compiler: " + r.stderr[:200])
     vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     assert vals == [ctypes.sizeof(simpgmg.Options), simpgmg.Options.seed.offset,
-                    simpgmg.Options.lambda_override.offset, ctypes.sizeof(simpgmg.SolveInfo)]
+                    simpgmg.Options.use_graphs.offset, ctypes.sizeof(simpgmg.SolveInfo)]

@@ -132,3 +132,25 @@ def test_bf16_smoother_solve_reaches_fp64_tolerance():
     simpgmg.pcg_solve(h64, t64(f), u64, rtol=1e-10, maxit=200)
     c, c64 = f @ np64(u), f @ np64(u64)
     assert abs(c - c64) <= 1e-4 * abs(c64)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_graph_replay_equals_direct_launches(prec):
+    """Each iteration is one replay of a captured graph, with the host's scalar
+    readback between replays: the history and solution must be bitwise equal
+    to direct launches."""
+    from paper_2604_26441_amd import simpgmg
+    dims = (24, 12, 12)
+    rho = np.random.default_rng(8).uniform(0.2, 1.0, np.prod(dims))
+    f = workloads.edge_load(dims)
+    out = []
+    for g in (0, 1, 1):                      # graphs reused by the second solve
+        o = simpgmg.default_options(*dims, n_levels=4, fine_prec=prec, use_graphs=g)
+        h = simpgmg.setup_hierarchy(o, t64(rho)) if g == 0 or len(out) == 1 else h
+        u = t64(np.zeros_like(f))
+        res = simpgmg.pcg_solve(h, t64(f), u, rtol=1e-8, maxit=100, history_cap=128)
+        out.append((res["iters"], res["history"], np64(u)))
+    for it, hist, x in out[1:]:
+        assert it == out[0][0]
+        assert hist == out[0][1]
+        assert np.array_equal(x, out[0][2])
