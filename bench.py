@@ -28,7 +28,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=80, help="elements per axis of the cube")
-    ap.add_argument("--fine-prec", default=os.environ.get("SGMG_FINE_PREC", "f32"))
+    ap.add_argument("--fine-prec", default=os.environ.get("SGMG_FINE_PREC", "bf16x3"))
+    ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip FP64-GMG and Jacobi-PCG comparisons")
@@ -79,7 +80,8 @@ def main():
     stream = torch.cuda.current_stream()
 
     def opts(**kw):
-        return simpgmg.default_options(*dims, n_levels=4, **kw)
+        kw.setdefault("n_levels", args.levels)
+        return simpgmg.default_options(*dims, **kw)
 
     def step(o, precond=2, maxit=200):
         t0 = time.perf_counter()
@@ -93,6 +95,11 @@ def main():
         return h, res, (t1 - t0) * 1e3, (t2 - t1) * 1e3
 
     o32 = opts(fine_prec=args.fine_prec)
+    tuned = None
+    if args.fine_prec in ("bf16", "bf16x3"):
+        h = simpgmg.setup_hierarchy(o32, rho)      # launch-shape autotuning, untimed
+        tuned = simpgmg.autotune(h)
+        h.close()
     for _ in range(args.warmup):
         h, res, _, _ = step(o32)
         h.close()
@@ -138,7 +145,7 @@ def main():
     if not args.no_compare:
         h, r64, su64, _ = step(opts(fine_prec="f64"))
         h.close()
-        h, rj, suj, _ = step(opts(fine_prec="f64", n_levels=2), precond=1, maxit=200)
+        h, rj, suj, _ = step(opts(fine_prec="f64"), precond=1, maxit=200)
         h.close()
         extra = {"fp64_gmg": {"solve_ms": round(r64["solve_ms"], 3), "iters": r64["iters"],
                               "status": r64["status"]},
@@ -158,8 +165,8 @@ def main():
         "dtype": {"f32": "f32", "f64": "f64", "bf16": "bf16", "bf16x3": "f32"}[args.fine_prec],
         "data": "synthetic",
         "config": {"workload": f"hex8 SIMP cantilever {n}x{n}x{n} ({nel} elements), rho=0.5, p=3, "
-                               f"FP32-GMG-PCG, 4 levels, Chebyshev deg 2, rtol 1e-6, cap 200",
-                   "fine_prec": args.fine_prec},
+                               f"FP32-GMG-PCG, {args.levels} levels, Chebyshev deg 2, rtol 1e-6, cap 200",
+                   "fine_prec": args.fine_prec, "mfma_zchunk_bf16_bf16x3": tuned},
         "solve_ms_std": round(float(np.std(solve_ms)), 3),
         "setup_ms": round(float(np.mean(setup_ms)), 3),
         "iters": iters, "status": status, "rel_res_true": relres,

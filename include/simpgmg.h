@@ -158,6 +158,16 @@ int sgmg_vcycle(const sgmg_hierarchy* h, const double* r, double* z, void* strea
 int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u,
                    double rtol, int maxit, sgmg_solve_info* info, void* stream);
 
+/* Autotuner of the MFMA fine operator's launch shape: times each candidate
+ * z-chunk (owned node planes per workgroup: 2, 4, 8, 16, 32) on this
+ * hierarchy's mesh for the BF16 and BF16X3 kernels, keeps the fastest in h
+ * and in a process-wide cache keyed by (nx, ny, nz, variant) that later
+ * setups of the same mesh read.  zchunk_out (host, 2 ints, may be NULL)
+ * receives the BF16 and BF16X3 choices.  Allocates two temporary vectors and
+ * synchronises the stream.  The launch shape changes only which workgroup
+ * computes a node, never the arithmetic: results are bitwise identical. */
+int sgmg_autotune(sgmg_hierarchy* h, int* zchunk_out, void* stream);
+
 /* Introspection for tests and reports. */
 int sgmg_num_levels(const sgmg_hierarchy* h);
 /* dims[3] elements of level l, free DOF count, raw lambda estimate. */

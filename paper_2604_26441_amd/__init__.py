@@ -1,9 +1,18 @@
 """MI355X-native matrix-free Galerkin multigrid PCG for 3D hex8 SIMP elasticity.
 
 The solver lives in the HIP library built from csrc/ (C ABI in
-include/simpgmg.h); ``simpgmg`` is its ctypes binding.
+include/simpgmg.h); ``paper_2604_26441_amd.simpgmg`` is its ctypes binding.
+The binding is imported on first attribute access, so ``build`` runs without
+a built library.
 """
-from .simpgmg import (  # noqa: F401
-    F64, F32, BF16, BF16X3, Options, Hierarchy, SimpGmgError, default_options, setup_hierarchy,
-    update_moduli, apply_K, vcycle, pcg_solve, library_path, EXPORTS,
-)
+import importlib
+
+_BINDING = {"F64", "F32", "BF16", "BF16X3", "Options", "Hierarchy", "SimpGmgError",
+            "default_options", "setup_hierarchy", "update_moduli", "apply_K", "vcycle",
+            "pcg_solve", "autotune", "library_path", "EXPORTS"}
+
+
+def __getattr__(name):
+    if name in _BINDING:
+        return getattr(importlib.import_module(".simpgmg", __name__), name)
+    raise AttributeError(name)

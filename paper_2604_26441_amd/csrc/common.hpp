@@ -46,14 +46,11 @@ __host__ __device__ inline double w1d(int i, int ic, int nf) {
 }
 
 // ----------------------------------------------------------------------------
-// Deterministic reductions.  Each block reduces its values to one double
-// (fixed tree), writes it to partials[blockIdx.x]; the last block to finish
-// (counter) sums the partials in index order and stores the total.  The
-// counter is reset by that block, so consecutive reductions on one stream can
-// share a workspace.
+// Deterministic reductions: a fixed tree inside each block, then a fixed-order
+// sum of the block partials in a second kernel.
 struct RedWs {
-  double* partials;    // >= max grid size used with this workspace
-  unsigned* counter;   // one word, zero between reductions
+  double* partials;    // >= NV * (largest grid used with this workspace)
+  unsigned* counter;   // unused (kept for layout)
 };
 
 __device__ inline double wave_sum(double v) {
@@ -77,37 +74,22 @@ __device__ inline double block_sum(double v, double* lds /* >= 16 */) {
   return t;
 }
 
-// Up to NV simultaneous sums.  After the call, on the last block only,
-// out[k] receives the total of v[k] over the grid.  The workspace needs
-// NV * gridDim.x partial slots.
+// Up to NV simultaneous sums, first phase: each block writes its NV block
+// totals to ws.partials[k * gridDim.x + blockIdx.x].  A separate one-block
+// kernel (launch_finalize) adds the partials in index order and writes the
+// totals.  The kernel boundary makes the partials visible, so no device-scope
+// fence is issued per block (on a multi-XCD part such a fence writes back the
+// L2 of every block's XCD).
 template <int NV>
-__device__ inline void grid_sum(const double (&v)[NV], RedWs ws, double* out) {
+__device__ inline void grid_sum(const double (&v)[NV], RedWs ws) {
   __shared__ double lds[16 * NV];
-  __shared__ bool last;
   double tot[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) tot[k] = block_sum(v[k], lds + 16 * k);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) ws.partials[(size_t)k * gridDim.x + blockIdx.x] = tot[k];
-    __threadfence();
-    const unsigned prev = atomicAdd(ws.counter, 1u);
-    last = (prev == gridDim.x - 1);
   }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // last block: fixed-order sum of the partials (strided per thread, then tree)
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double s = 0.0;
-    for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
-      s += __hip_atomic_load(ws.partials + (size_t)k * gridDim.x + b, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    s = block_sum(s, lds + 16 * k);
-    if (threadIdx.x == 0) out[k] = s;
-  }
-  if (threadIdx.x == 0) *ws.counter = 0u;
 }
 
 // ----------------------------------------------------------------------------
@@ -130,7 +112,7 @@ struct Epi {
   int store_d;
   int want_dot;        // STORE: accumulate x.y into dot
   RedWs ws;
-  double* dot_out;
+  double* dot_out;     // finalized by the launcher after the kernel
 };
 
 template <typename T>
@@ -159,6 +141,44 @@ __device__ inline double epilogue3(const Epi<T>& ep, int node, unsigned fx, cons
         const T r = (T)((double)ep.b[base + c] - y[c]);
         const T dp = ep.c1 != 0.0 ? ep.d[base + c] : (T)0;
         dd = (T)ep.c1 * dp + (T)ep.c2 * ep.dinv[base + c] * r;
+        xo = x[c] + dd;
+      }
+      if (ep.store_d) ep.d[base + c] = dd;
+      ep.out[base + c] = xo;
+      if (ep.out64) ep.out64[base + c] = (double)xo;
+    }
+  }
+  return dot;
+}
+
+// Same epilogue with the node's operands already loaded (x, b, dinv, d_prev);
+// used by kernels that prefetch them ahead of the contraction.
+template <typename T>
+__device__ inline double epilogue3_pre(const Epi<T>& ep, int node, unsigned fx, const T (&x)[3],
+                                       const double (&y)[3], const T (&b)[3], const T (&dinv)[3],
+                                       const T (&dprev)[3]) {
+  double dot = 0.0;
+  const size_t base = 3 * (size_t)node;
+  if (ep.mode == EPI_STORE) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double v = (fx >> c) & 1u ? 0.0 : y[c];
+      ep.out[base + c] = (T)v;
+      dot += (double)x[c] * v;
+    }
+  } else if (ep.mode == EPI_RESID) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      ep.out[base + c] = (fx >> c) & 1u ? (T)0 : (T)((double)b[c] - y[c]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T xo, dd;
+      if ((fx >> c) & 1u) {
+        xo = (T)0; dd = (T)0;
+      } else {
+        const T r = (T)((double)b[c] - y[c]);
+        dd = (T)ep.c1 * dprev[c] + (T)ep.c2 * dinv[c] * r;
         xo = x[c] + dd;
       }
       if (ep.store_d) ep.d[base + c] = dd;

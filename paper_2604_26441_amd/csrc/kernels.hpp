@@ -16,11 +16,12 @@ void launch_diag_fine(const Grid& g, const double* E, const double* ke, const ui
 template <typename T>
 void launch_apply_fine_node(const Grid& g, const T* E, const T* ke, const T* u,
                             const uint8_t* fixn, const Epi<T>& ep, hipStream_t s);
-// BF16 MFMA element kernel (kernels_mfma.hip); nsplit = 1 (BF16) or 3 (BF16X3).
-void launch_apply_fine_mfma(const Grid& g, int nsplit, const float* Escaled, const void* atab,
-                            const float* u, const uint8_t* fixn, const Epi<float>& ep,
-                            hipStream_t s);
-size_t apply_fine_mfma_blocks(const Grid& g);
+// BF16 MFMA element kernel (kernels_mfma.hip); nsplit = 1 (BF16) or 3 (BF16X3);
+// zchunk = owned node planes per workgroup (tuned per mesh).
+void launch_apply_fine_mfma(const Grid& g, int nsplit, int zchunk, const float* Escaled,
+                            const void* atab, const float* u, const uint8_t* fixn,
+                            const Epi<float>& ep, hipStream_t s);
+size_t apply_fine_mfma_blocks(const Grid& g, int zchunk);
 void launch_scale_E(const double* E, float* Es, int nel, double inv_s, hipStream_t s);
 void build_mfma_atab(const KeTables& kt, uint16_t* out /* 2 * 64 * 8 */);
 
@@ -50,6 +51,8 @@ void launch_prolong_add(const Grid& fine, const Grid& coarse, const TC* ec, cons
                         TF* xf, hipStream_t s);
 
 // ---- vectors and reductions (kernels_vec.hip) ------------------------------
+// out[k] = sum of partials[k * nblocks + b] over b (k < nv), one block.
+void launch_finalize(RedWs ws, int nblocks, int nv, double* out, hipStream_t s);
 void launch_power_start(double* x, const uint8_t* fixn, int Nn, uint64_t seed, hipStream_t s);
 // out[0] = sum a*b (b == NULL: sum a*a; w != NULL: sum w*a*b)
 void launch_dot(const double* a, const double* b, const double* w, int n, RedWs ws,

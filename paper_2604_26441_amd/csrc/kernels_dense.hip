@@ -35,11 +35,12 @@ __global__ void k_dense_diag_sum(const double* __restrict__ A, int nf, RedWs ws,
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += gridDim.x * blockDim.x)
     s += A[(size_t)i * nf + i];
   const double v[1] = {s};
-  grid_sum<1>(v, ws, out);
+  grid_sum<1>(v, ws);
 }
 
 void launch_dense_diag_sum(const double* A, int nf, RedWs ws, double* out, hipStream_t s) {
   k_dense_diag_sum<<<1, 256, 0, s>>>(A, nf, ws, out);
+  launch_finalize(ws, 1, 1, out, s);
 }
 
 // eps = max(mean diag * 1e-8, 1e-14) added to the diagonal (Sec. 4.1).
@@ -72,23 +73,22 @@ __global__ void k_gj_copy_col(const double* __restrict__ A, int n, int k0, int n
 __global__ __launch_bounds__(256) void k_gj_pivot(double* __restrict__ A, int n, int k0, int nb,
                                                   double* __restrict__ Q, int* __restrict__ flag) {
   __shared__ double P[kNB][kNB + 1];
-  for (int t = threadIdx.x; t < nb * nb; t += 256) {
-    const int r = t / nb, c = t % nb;
-    P[r][c] = A[(size_t)(k0 + r) * n + k0 + c];
+  constexpr int kPer = kNB * kNB / 256;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int t = threadIdx.x + 256 * q, r = t / kNB, c = t % kNB;
+    P[r][c] = (r < nb && c < nb) ? A[(size_t)(k0 + r) * n + k0 + c] : 0.0;
   }
   __syncthreads();
-  constexpr int kPer = kNB * kNB / 256;
-  double nv[kPer];
   for (int piv = 0; piv < nb; ++piv) {
     const double pv = P[piv][piv];
-    if (!(pv > 0.0)) {
-      if (threadIdx.x == 0) *flag = 1;
-    }
+    if (!(pv > 0.0) && threadIdx.x == 0) *flag = 1;
     const double inv = 1.0 / pv;
-    int q = 0;
-    for (int t = threadIdx.x; t < kNB * kNB; t += 256, ++q) {
-      const int r = t / kNB, c = t % kNB;
-      double v = 0.0;
+    double nv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int t = threadIdx.x + 256 * q, r = t / kNB, c = t % kNB;
+      double v = P[r][c];
       if (r < nb && c < nb) {
         if (r == piv && c == piv) v = inv;
         else if (r == piv) v = inv * P[piv][c];
@@ -98,24 +98,28 @@ __global__ __launch_bounds__(256) void k_gj_pivot(double* __restrict__ A, int n,
       nv[q] = v;
     }
     __syncthreads();
-    q = 0;
-    for (int t = threadIdx.x; t < kNB * kNB; t += 256, ++q) {
-      const int r = t / kNB, c = t % kNB;
-      if (r < nb && c < nb) P[r][c] = nv[q];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int t = threadIdx.x + 256 * q;
+      P[t / kNB][t % kNB] = nv[q];
     }
     __syncthreads();
   }
-  for (int t = threadIdx.x; t < kNB * kNB; t += 256) {
-    const int r = t / kNB, c = t % kNB;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int t = threadIdx.x + 256 * q, r = t / kNB, c = t % kNB;
     const double v = (r < nb && c < nb) ? P[r][c] : 0.0;
     Q[t] = v;
     if (r < nb && c < nb) A[(size_t)(k0 + r) * n + k0 + c] = v;
   }
 }
 
-// A_KJ <- Q A_KJ for every column j outside the panel.
-__global__ void k_gj_rowpanel(double* __restrict__ A, int n, int k0, int nb,
-                              const double* __restrict__ Q) {
+// A_KJ <- Q A_KJ for every column j outside the panel (Q staged in LDS).
+__global__ __launch_bounds__(64) void k_gj_rowpanel(double* __restrict__ A, int n, int k0, int nb,
+                                                    const double* __restrict__ Q) {
+  __shared__ double Qs[kNB * kNB];
+  for (int t = threadIdx.x; t < kNB * kNB; t += 64) Qs[t] = Q[t];
+  __syncthreads();
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n || (j >= k0 && j < k0 + nb)) return;
   double v[kNB];
@@ -124,7 +128,7 @@ __global__ void k_gj_rowpanel(double* __restrict__ A, int n, int k0, int nb,
   for (int r = 0; r < nb; ++r) {
     double s = 0.0;
 #pragma unroll
-    for (int t = 0; t < kNB; ++t) s += Q[r * kNB + t] * v[t];
+    for (int t = 0; t < kNB; ++t) s += Qs[r * kNB + t] * v[t];
     A[(size_t)(k0 + r) * n + j] = s;
   }
 }

@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void k_apply_fine_node(Grid g, const T* __rest
   }
   if (ep.want_dot) {
     const double v[1] = {dot};
-    grid_sum<1>(v, ep.ws, ep.dot_out);
+    grid_sum<1>(v, ep.ws);
   }
 }
 
@@ -201,6 +201,7 @@ template <typename T>
 void launch_apply_fine_node(const Grid& g, const T* E, const T* ke, const T* u,
                             const uint8_t* fixn, const Epi<T>& ep, hipStream_t s) {
   k_apply_fine_node<T><<<div_up(g.Nn, 256), 256, 0, s>>>(g, E, ke, u, fixn, ep);
+  if (ep.want_dot) launch_finalize(ep.ws, div_up(g.Nn, 256), 1, ep.dot_out, s);
 }
 
 template void launch_apply_fine_node<double>(const Grid&, const double*, const double*,

@@ -29,7 +29,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaWaves = 4;   // waves per workgroup (owned node rows + 1)
-constexpr int kZChunk = 16;     // owned node planes per workgroup
 
 // A operand table: [h][lane][8] BF16 bit patterns, built on the host.
 // Row m = lane % 16 = 4 * (dx + 2 dy) + c of output node (dx, dy, dz = h);
@@ -39,7 +38,7 @@ constexpr int kZChunk = 16;     // owned node planes per workgroup
 template <int NSPLIT, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_apply_fine_mfma(
     Grid g, const float* __restrict__ Es, const uint16_t* __restrict__ atab,
-    const float* __restrict__ u, const uint8_t* __restrict__ fixn, Epi<float> ep) {
+    const float* __restrict__ u, const uint8_t* __restrict__ fixn, Epi<float> ep, int zchunk) {
   __shared__ float plane[WAVES + 1][16][3];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -47,7 +46,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_apply_fine_mfma(
   const int n = lane & 15;            // element position in the x-batch
   const int xs = blockIdx.x * 15;     // first owned node in x
   const int ys = blockIdx.y * (WAVES - 1);
-  const int zs = blockIdx.z * kZChunk;
+  const int zs = blockIdx.z * zchunk;
   const int ex = xs - 1 + n;
   const int ey = ys - 1 + w;
   const bool exy_ok = ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny;
@@ -64,56 +63,98 @@ __global__ __launch_bounds__(64 * WAVES) void k_apply_fine_mfma(
     }
   }
 
-  // element plane ez -> (acc for node plane ez, acc for node plane ez+1)
-  auto element_plane = [&](int ez, f32x4& c0, f32x4& c1) {
-    c0 = f32x4{0.f, 0.f, 0.f, 0.f};
-    c1 = f32x4{0.f, 0.f, 0.f, 0.f};
+  // raw operands of element plane ez (6 input values, E / s)
+  struct In { float v[6]; float es; };
+  auto load_in = [&](int ez, In& in) {
     const bool ok = exy_ok && ez >= 0 && ez < g.nz;
-    float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float es = 0.f;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) in.v[j] = 0.f;
+    in.es = 0.f;
     if (ok) {
       const size_t base = 3 * (size_t)(ex + g.Nx * ((ey + dy_in) + g.Ny * (ez + dz_in)));
 #pragma unroll
-      for (int j = 0; j < 6; ++j) v[j] = u[base + j];
-      es = Es[ex + g.nx * (ey + g.ny * ez)];
+      for (int j = 0; j < 6; ++j) in.v[j] = u[base + j];
+      in.es = Es[ex + g.nx * (ey + g.ny * ez)];
     }
+  };
+  // contraction: acc for node plane ez (c0) and ez+1 (c1), scaled by E / s
+  auto contract = [&](const In& in, f32x4& c0, f32x4& c1) {
+    c0 = f32x4{0.f, 0.f, 0.f, 0.f};
+    c1 = f32x4{0.f, 0.f, 0.f, 0.f};
     bf16x8 b[NSPLIT];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      float r = v[j];
+      float r = in.v[j];
 #pragma unroll
-      for (int s = 0; s < NSPLIT; ++s) {
+      for (int sp = 0; sp < NSPLIT; ++sp) {
         const __bf16 t = (__bf16)r;
-        b[s][j] = t;
+        b[sp][j] = t;
         r -= (float)t;
       }
     }
 #pragma unroll
-    for (int s = 0; s < NSPLIT; ++s) {
-      b[s][6] = (__bf16)0.f;
-      b[s][7] = (__bf16)0.f;
+    for (int sp = 0; sp < NSPLIT; ++sp) {
+      b[sp][6] = (__bf16)0.f;
+      b[sp][7] = (__bf16)0.f;
     }
-    // smallest terms first
 #pragma unroll
-    for (int s = NSPLIT - 1; s >= 0; --s) {
-      c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b[s], c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[s], c1, 0, 0, 0);
+    for (int sp = NSPLIT - 1; sp >= 0; --sp) {    // smallest terms first
+      c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b[sp], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[sp], c1, 0, 0, 0);
     }
     // column n of the result (lane % 16) is element n, whose E / s every lane
     // of that column loaded itself
-    c0 *= es;
-    c1 *= es;
+    c0 *= in.es;
+    c1 *= in.es;
   };
 
+  // the epilogue node of this thread (rows 1..WAVES-1, positions 1..15)
+  const int t = threadIdx.x;
+  const int er = 1 + t / 15, eq = 1 + t % 15;
+  const int enx = xs - 1 + eq, eny = ys - 1 + er;
+  const bool e_own = t < 15 * (WAVES - 1) && enx < g.Nx && eny < g.Ny;
+  const bool need_b = ep.mode != EPI_STORE;
+  const bool need_sm = ep.mode == EPI_SMOOTH;
+  const bool need_d = need_sm && ep.c1 != 0.0;
+
+  In cur, nxt;
   f32x4 carry, dummy;
-  element_plane(zs - 1, dummy, carry);   // prologue: dz = 1 half of the plane below
+  load_in(zs - 1, cur);
+  load_in(zs, nxt);
+  contract(cur, dummy, carry);   // prologue: dz = 1 half of the plane below
   double dot = 0.0;
   const int dx = grp & 1, dyo = grp >> 1;
   const int src = ((grp | 1) << 4) + ((n + 15) & 15);   // lane of (dx = 1, same dy, n - 1)
-  const int zend = min(zs + kZChunk, g.Nz);
+  const int zend = min(zs + zchunk, g.Nz);
   for (int ez = zs; ez < zend; ++ez) {
+    cur = nxt;
+    if (ez + 1 < zend) load_in(ez + 1, nxt);           // prefetch the next plane
+    // prefetch the epilogue operands of this plane
+    float ex_[3] = {0.f, 0.f, 0.f}, eb[3] = {0.f, 0.f, 0.f}, edi[3] = {0.f, 0.f, 0.f},
+          edp[3] = {0.f, 0.f, 0.f};
+    unsigned efx = 7u;
+    int node = 0;
+    if (e_own) {
+      node = enx + g.Nx * (eny + g.Ny * ez);
+      const size_t b3 = 3 * (size_t)node;
+      efx = fixn[node];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ex_[c] = u[b3 + c];
+      if (need_b) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) eb[c] = ep.b[b3 + c];
+      }
+      if (need_sm) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) edi[c] = ep.dinv[b3 + c];
+      }
+      if (need_d) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) edp[c] = ep.d[b3 + c];
+      }
+    }
     f32x4 c0, c1;
-    element_plane(ez, c0, c1);
+    contract(cur, c0, c1);
     const float v0 = c0[0] + carry[0], v1 = c0[1] + carry[1], v2 = c0[2] + carry[2];
     carry = c1;
     // x: node (xs - 1 + n) gets dx = 0 of element n and dx = 1 of element n - 1
@@ -133,47 +174,42 @@ __global__ __launch_bounds__(64 * WAVES) void k_apply_fine_mfma(
       plane[w + 1][n][2] += v2 + p2;
     }
     __syncthreads();
-    // epilogue on the owned nodes of this plane: rows 1..WAVES-1, positions 1..15
-    const int t = threadIdx.x;
-    if (t < 15 * (WAVES - 1)) {
-      const int r = 1 + t / 15, q = 1 + t % 15;
-      const int nx_ = xs - 1 + q, ny_ = ys - 1 + r;
-      if (nx_ < g.Nx && ny_ < g.Ny) {
-        const int node = nx_ + g.Nx * (ny_ + g.Ny * ez);
-        const double y[3] = {(double)plane[r][q][0], (double)plane[r][q][1],
-                             (double)plane[r][q][2]};
-        const float xo[3] = {u[3 * (size_t)node], u[3 * (size_t)node + 1],
-                             u[3 * (size_t)node + 2]};
-        dot += epilogue3(ep, node, fixn[node], xo, y);
-      }
+    if (e_own) {
+      const double y[3] = {(double)plane[er][eq][0], (double)plane[er][eq][1],
+                           (double)plane[er][eq][2]};
+      dot += epilogue3_pre(ep, node, efx, ex_, y, eb, edi, edp);
     }
     __syncthreads();
   }
   if (ep.want_dot) {
     const double vv[1] = {dot};
-    grid_sum<1>(vv, ep.ws, ep.dot_out);
+    grid_sum<1>(vv, ep.ws);
   }
 }
 
-static dim3 mfma_grid(const Grid& g) {
-  return dim3(div_up(g.Nx, 15), div_up(g.Ny, kMfmaWaves - 1), div_up(g.Nz, kZChunk));
+static dim3 mfma_grid(const Grid& g, int zchunk) {
+  return dim3(div_up(g.Nx, 15), div_up(g.Ny, kMfmaWaves - 1), div_up(g.Nz, zchunk));
 }
 
-size_t apply_fine_mfma_blocks(const Grid& g) {
-  const dim3 d = mfma_grid(g);
+size_t apply_fine_mfma_blocks(const Grid& g, int zchunk) {
+  const dim3 d = mfma_grid(g, zchunk);
   return (size_t)d.x * d.y * d.z;
 }
 
-void launch_apply_fine_mfma(const Grid& g, int nsplit, const float* Escaled, const void* atab,
-                            const float* u, const uint8_t* fixn, const Epi<float>& ep,
-                            hipStream_t s) {
-  const dim3 grid = mfma_grid(g);
+void launch_apply_fine_mfma(const Grid& g, int nsplit, int zchunk, const float* Escaled,
+                            const void* atab, const float* u, const uint8_t* fixn,
+                            const Epi<float>& ep, hipStream_t s) {
+  if (zchunk < 1) zchunk = 1;
+  const int g_zchunk = zchunk;
+  const dim3 grid = mfma_grid(g, zchunk);
   const dim3 block(64 * kMfmaWaves);
   const uint16_t* at = (const uint16_t*)atab;
   if (nsplit == 3)
-    k_apply_fine_mfma<3, kMfmaWaves><<<grid, block, 0, s>>>(g, Escaled, at, u, fixn, ep);
+    k_apply_fine_mfma<3, kMfmaWaves><<<grid, block, 0, s>>>(g, Escaled, at, u, fixn, ep, g_zchunk);
   else
-    k_apply_fine_mfma<1, kMfmaWaves><<<grid, block, 0, s>>>(g, Escaled, at, u, fixn, ep);
+    k_apply_fine_mfma<1, kMfmaWaves><<<grid, block, 0, s>>>(g, Escaled, at, u, fixn, ep, g_zchunk);
+  if (ep.want_dot)
+    launch_finalize(ep.ws, (int)(grid.x * grid.y * grid.z), 1, ep.dot_out, s);
 }
 
 // E / s in FP32 for the MFMA kernel.

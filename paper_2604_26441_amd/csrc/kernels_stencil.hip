@@ -204,6 +204,12 @@ void launch_stencil_to_f32(const double* S, float* S32, size_t n, hipStream_t s)
 }
 
 // y = K^l u on the stored stencil, thread per node, with a fused epilogue.
+// Only the upper half of the stencil is read: block o >= 13 (offsets that are
+// lexicographically >= 0) of node n, and for the lower offsets the transpose
+// of the mirrored block of the neighbour, A[n, n+o] = A[n+o, n]^T =
+// (S_{26-o}[n+o])^T.  The neighbour's block is that neighbour's own upper
+// block, so the second read is served from cache: about half the HBM bytes of
+// the full stencil, and the applied operator is exactly symmetric.
 template <typename T>
 __global__ __launch_bounds__(256) void k_stencil_apply(Grid g, const T* __restrict__ S,
                                                        const T* __restrict__ u,
@@ -214,19 +220,27 @@ __global__ __launch_bounds__(256) void k_stencil_apply(Grid g, const T* __restri
   if (node < g.Nn) {
     const int i = node % g.Nx, t = node / g.Nx, j = t % g.Ny, k = t / g.Ny;
     T acc[3] = {(T)0, (T)0, (T)0};
+    const size_t Nn = g.Nn;
 #pragma unroll
     for (int o = 0; o < 27; ++o) {
       const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
       const bool ok = (unsigned)(i + ox) < (unsigned)g.Nx && (unsigned)(j + oy) < (unsigned)g.Ny &&
                       (unsigned)(k + oz) < (unsigned)g.Nz;
       if (!ok) continue;
-      const size_t nb = 3 * (size_t)(node + ox + g.Nx * (oy + g.Ny * oz));
-      const T u0 = u[nb], u1 = u[nb + 1], u2 = u[nb + 2];
-      const T* Sb = S + (size_t)o * 9 * g.Nn + node;
+      const int nb = node + ox + g.Nx * (oy + g.Ny * oz);
+      const size_t b3 = 3 * (size_t)nb;
+      const T u0 = u[b3], u1 = u[b3 + 1], u2 = u[b3 + 2];
+      if (o >= 13) {
+        const T* Sb = S + (size_t)o * 9 * Nn + node;
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
-        acc[d] += Sb[(3 * d) * (size_t)g.Nn] * u0 + Sb[(3 * d + 1) * (size_t)g.Nn] * u1 +
-                  Sb[(3 * d + 2) * (size_t)g.Nn] * u2;
+        for (int d = 0; d < 3; ++d)
+          acc[d] += Sb[(3 * d) * Nn] * u0 + Sb[(3 * d + 1) * Nn] * u1 + Sb[(3 * d + 2) * Nn] * u2;
+      } else {
+        const T* Sb = S + (size_t)(26 - o) * 9 * Nn + nb;     // neighbour's block, transposed
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          acc[d] += Sb[d * Nn] * u0 + Sb[(3 + d) * Nn] * u1 + Sb[(6 + d) * Nn] * u2;
+      }
     }
     const double y[3] = {(double)acc[0], (double)acc[1], (double)acc[2]};
     const T xo[3] = {u[3 * (size_t)node], u[3 * (size_t)node + 1], u[3 * (size_t)node + 2]};
@@ -234,7 +248,7 @@ __global__ __launch_bounds__(256) void k_stencil_apply(Grid g, const T* __restri
   }
   if (ep.want_dot) {
     const double v[1] = {dot};
-    grid_sum<1>(v, ep.ws, ep.dot_out);
+    grid_sum<1>(v, ep.ws);
   }
 }
 
@@ -244,6 +258,7 @@ template <typename T>
 void launch_stencil_apply(const Grid& g, const T* S, const T* u, const uint8_t* fixn,
                           const Epi<T>& ep, hipStream_t s) {
   k_stencil_apply<T><<<div_up(g.Nn, 256), 256, 0, s>>>(g, S, u, fixn, ep);
+  if (ep.want_dot) launch_finalize(ep.ws, div_up(g.Nn, 256), 1, ep.dot_out, s);
 }
 template void launch_stencil_apply<double>(const Grid&, const double*, const double*,
                                            const uint8_t*, const Epi<double>&, hipStream_t);

@@ -40,7 +40,24 @@ __global__ __launch_bounds__(kVecBlock) void k_dot(const double* __restrict__ a,
     s += t;
   }
   const double v[1] = {s};
-  grid_sum<1>(v, ws, out);
+  grid_sum<1>(v, ws);
+}
+
+// Second phase of every reduction: one block adds the block partials of
+// each of the nv sums in index order (fixed order: bitwise deterministic).
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partials, int nblocks,
+                                                  int nv, double* __restrict__ out) {
+  __shared__ double lds[16];
+  for (int k = 0; k < nv; ++k) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += partials[(size_t)k * nblocks + b];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) out[k] = s;
+  }
+}
+
+void launch_finalize(RedWs ws, int nblocks, int nv, double* out, hipStream_t s) {
+  k_finalize<<<1, 256, 0, s>>>(ws.partials, nblocks, nv, out);
 }
 
 static unsigned vec_grid(int n) {
@@ -51,6 +68,7 @@ static unsigned vec_grid(int n) {
 void launch_dot(const double* a, const double* b, const double* w, int n, RedWs ws, double* out,
                 hipStream_t s) {
   k_dot<<<vec_grid(n), kVecBlock, 0, s>>>(a, b, w, n, ws, out);
+  launch_finalize(ws, vec_grid(n), 1, out, s);
 }
 
 __global__ __launch_bounds__(kVecBlock) void k_scale_dinv_norm(const double* __restrict__ dinv,
@@ -64,12 +82,13 @@ __global__ __launch_bounds__(kVecBlock) void k_scale_dinv_norm(const double* __r
     s += v * v;
   }
   const double v[1] = {s};
-  grid_sum<1>(v, ws, out);
+  grid_sum<1>(v, ws);
 }
 
 void launch_scale_dinv_norm(const double* dinv, const double* w, double* y, int n, RedWs ws,
                             double* out, hipStream_t s) {
   k_scale_dinv_norm<<<vec_grid(n), kVecBlock, 0, s>>>(dinv, w, y, n, ws, out);
+  launch_finalize(ws, vec_grid(n), 1, out, s);
 }
 
 __global__ void k_normalize(const double* __restrict__ y, const double* __restrict__ nrm2,
@@ -143,12 +162,13 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_init(const double* __restrict
     rr += rv * rv;
   }
   const double v[2] = {ff, rr};
-  grid_sum<2>(v, ws, out);
+  grid_sum<2>(v, ws);
 }
 
 void launch_pcg_init(const double* f, const double* Ax0, int have_x0, double* r, int n, RedWs ws,
                      double* sc_ff_rr, hipStream_t s) {
   k_pcg_init<<<vec_grid(n), kVecBlock, 0, s>>>(f, Ax0, have_x0, r, n, ws, sc_ff_rr);
+  launch_finalize(ws, vec_grid(n), 2, sc_ff_rr, s);
 }
 
 // alpha = sc[rz] / sc[pq]; x += alpha p; r -= alpha q; out = r.r
@@ -177,7 +197,7 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(double* __restrict_
     rr += rv * rv;
   }
   const double v[1] = {rr};
-  grid_sum<1>(v, ws, out);
+  grid_sum<1>(v, ws);
 }
 
 void launch_pcg_update_xr(double* x, double* r, double* r_old, const double* p, const double* q,
@@ -185,6 +205,7 @@ void launch_pcg_update_xr(double* x, double* r, double* r_old, const double* p, 
                           double* sc_rr, hipStream_t s) {
   k_pcg_update_xr<<<vec_grid(n), kVecBlock, 0, s>>>(x, r, r_old, p, q, sc, slot_rz, slot_pq, n,
                                                     ws, sc_rr);
+  launch_finalize(ws, vec_grid(n), 1, sc_rr, s);
 }
 
 // out[0] = r.z ; out[1] = r_old.z (flexible beta numerator r.z - r_old.z)
@@ -199,12 +220,13 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_dot_rz(const double* __restri
     if (r_old) b += r_old[i] * zv;
   }
   const double v[2] = {a, b};
-  grid_sum<2>(v, ws, out);
+  grid_sum<2>(v, ws);
 }
 
 void launch_pcg_dot_rz(const double* r, const double* z, const double* r_old, int n, RedWs ws,
                        double* sc_out2, hipStream_t s) {
   k_pcg_dot_rz<<<vec_grid(n), kVecBlock, 0, s>>>(r, z, r_old, n, ws, sc_out2);
+  launch_finalize(ws, vec_grid(n), 2, sc_out2, s);
 }
 
 // p = z + beta p with beta = (sc[num] - sc[sub]) / sc[den]  (sub < 0: no term)
@@ -289,12 +311,13 @@ __global__ __launch_bounds__(kVecBlock) void k_residual(const double* __restrict
     rr += v * v;
   }
   const double v[1] = {rr};
-  grid_sum<1>(v, ws, out);
+  grid_sum<1>(v, ws);
 }
 
 void launch_residual(const double* f, const double* Ax, double* r, int n, RedWs ws,
                      double* out_rr, hipStream_t s) {
   k_residual<<<vec_grid(n), kVecBlock, 0, s>>>(f, Ax, r, n, ws, out_rr);
+  launch_finalize(ws, vec_grid(n), 1, out_rr, s);
 }
 
 }  // namespace sgmg

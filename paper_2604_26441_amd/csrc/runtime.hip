@@ -4,7 +4,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -59,6 +62,7 @@ struct sgmg_hierarchy {
   double* E64 = nullptr;
   float* E32 = nullptr;
   float* E32s = nullptr;     // E / s for the MFMA kernel
+  int mfma_zchunk[2] = {8, 8};  // [nsplit == 3]: tuned or default z-chunk
   uint16_t* atab = nullptr;  // MFMA A-operand table (BF16 bits)
   double maxE_lambda = 0.0;  // max E when lambdas were estimated
   int nL = 0;
@@ -85,6 +89,16 @@ struct sgmg_hierarchy {
 namespace {
 
 constexpr size_t kMinPartials = 1 << 16;
+
+// Process-wide autotuning results: (nx, ny, nz, nsplit) -> MFMA z-chunk.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tune;
+
+int tuned_zchunk(int nx, int ny, int nz, int nsplit) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(std::make_tuple(nx, ny, nz, nsplit));
+  return it == g_tune.end() ? 8 : it->second;
+}
 
 int dalloc(sgmg_hierarchy* h, void** p, size_t bytes) {
   if (bytes == 0) bytes = 8;
@@ -223,7 +237,8 @@ int apply_level<float>(const sgmg_hierarchy* h, int l, sgmg_prec prec, const flo
         set_error("BF16 MFMA path needs s*K_e integral (nu = 0.3 family); use F32");
         return SGMG_EINVAL;
       }
-      launch_apply_fine_mfma(L.g, prec == SGMG_BF16 ? 1 : 3, h->E32s, h->atab, x, L.fixn, ep, s);
+      const int ns = prec == SGMG_BF16 ? 1 : 3;
+      launch_apply_fine_mfma(L.g, ns, h->mfma_zchunk[ns == 3], h->E32s, h->atab, x, L.fixn, ep, s);
     } else {
       set_error("float vectors need F32, BF16 or BF16X3");
       return SGMG_EINVAL;
@@ -541,6 +556,8 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
   auto fail = [&](int code) { sgmg_destroy(h); return code; };
 
   compute_ke(opts->nu, &h->kt);
+  h->mfma_zchunk[0] = tuned_zchunk(opts->nx, opts->ny, opts->nz, 1);
+  h->mfma_zchunk[1] = tuned_zchunk(opts->nx, opts->ny, opts->nz, 3);
   // level dims by floor coarsening and masks by injection
   Grid g0 = make_grid(opts->nx, opts->ny, opts->nz);
   int maxL = opts->n_levels ? opts->n_levels : 8;
@@ -878,6 +895,60 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
     }
   }
   return 0;
+}
+
+int sgmg_autotune(sgmg_hierarchy* h, int* zchunk_out, void* stream) {
+  if (!h) { set_error("NULL argument"); return SGMG_EINVAL; }
+  if (!h->kt.integral) { set_error("MFMA path unavailable for this nu"); return SGMG_EINVAL; }
+  hipStream_t s = as_stream(stream);
+  const Level& L0 = h->lev[0];
+  float *u = nullptr, *y = nullptr;
+  SGMG_HIP(hipMalloc(&u, (size_t)L0.g.n * sizeof(float)));
+  if (hipMalloc(&y, (size_t)L0.g.n * sizeof(float)) != hipSuccess) {
+    hipFree(u);
+    set_error("autotune allocation failed");
+    return SGMG_ENOMEM;
+  }
+  hipMemsetAsync(u, 0, (size_t)L0.g.n * sizeof(float), s);
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  const int cands[] = {2, 4, 8, 16, 32};
+  int rc = 0;
+  for (int q = 0; q < 2 && !rc; ++q) {
+    const int ns = q ? 3 : 1;
+    int best = 8;
+    float best_ms = 1e30f;
+    for (int z : cands) {
+      if (z > L0.g.Nz && z != cands[0]) continue;
+      const Epi<float> ep = epi_store<float>(y);
+      for (int w = 0; w < 3; ++w)
+        launch_apply_fine_mfma(L0.g, ns, z, h->E32s, h->atab, u, L0.fixn, ep, s);
+      hipEventRecord(e0, s);
+      for (int r = 0; r < 20; ++r)
+        launch_apply_fine_mfma(L0.g, ns, z, h->E32s, h->atab, u, L0.fixn, ep, s);
+      hipEventRecord(e1, s);
+      if ((rc = check_launch())) break;
+      if (hipEventSynchronize(e1) != hipSuccess) { rc = SGMG_EHIP; set_error("autotune sync failed"); break; }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best_ms) { best_ms = ms; best = z; }
+    }
+    h->mfma_zchunk[q] = best;
+    if (zchunk_out) zchunk_out[q] = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[std::make_tuple(L0.g.nx, L0.g.ny, L0.g.nz, ns)] = best;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipStreamSynchronize(s);
+  hipFree(u);
+  hipFree(y);
+  // captured iteration graphs hold the old launch shape
+  for (auto& row : h->iter_graph)
+    for (auto& g : row)
+      if (g) { hipGraphExecDestroy(g); g = nullptr; }
+  return rc;
 }
 
 int sgmg_num_levels(const sgmg_hierarchy* h) { return h ? h->L : 0; }

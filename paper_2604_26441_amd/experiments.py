@@ -1,0 +1,109 @@
+"""Experiment drivers for the solver (GPU), printing one JSON record per run.
+
+  python -m paper_2604_26441_amd.experiments sizes   # uniform cantilevers 40^3/60^3/80^3:
+                                                     # FP32-GMG vs FP64-GMG vs Jacobi-PCG
+  python -m paper_2604_26441_amd.experiments kernels # fine K.u and level-1 stencil timings
+
+Timing protocol: 2 warm-up solves, then 5 timed solves (HIP events inside
+sgmg_pcg_solve); setup is timed separately with host clocks around a
+synchronised setup call.
+"""
+import json
+import sys
+import time
+
+import numpy as np
+import torch
+
+import workloads
+from . import simpgmg
+
+
+def _solve(dims, precond=2, maxit=200, trials=5, warmup=2, **kw):
+    dev = "cuda:0"
+    rho = torch.tensor(workloads.uniform_rho(dims), dtype=torch.float64, device=dev)
+    f = torch.tensor(workloads.edge_load(dims), dtype=torch.float64, device=dev)
+    o = simpgmg.default_options(*dims, **kw)
+    if kw.get("fine_prec") in ("bf16", "bf16x3"):
+        h = simpgmg.setup_hierarchy(o, rho)
+        simpgmg.autotune(h)
+        h.close()
+    times, setups, res = [], [], None
+    for k in range(warmup + trials):
+        t0 = time.perf_counter()
+        h = simpgmg.setup_hierarchy(o, rho)
+        torch.cuda.synchronize()
+        su = (time.perf_counter() - t0) * 1e3
+        u = torch.zeros_like(f)
+        res = simpgmg.pcg_solve(h, f, u, rtol=1e-6, maxit=maxit, precond=precond)
+        if k >= warmup:
+            times.append(res["solve_ms"])
+            setups.append(su)
+        h.close()
+    return {"solve_ms_mean": float(np.mean(times)), "solve_ms_std": float(np.std(times)),
+            "setup_ms_mean": float(np.mean(setups)), "iters": res["iters"], "status": res["status"],
+            "rel_res_true": res["rel_res_true"]}
+
+
+def sizes():
+    for n in (40, 60, 80):
+        dims = (n, n, n)
+        rec = {"dims": dims}
+        rec["fp32_gmg_bf16x3"] = _solve(dims, fine_prec="bf16x3")
+        rec["fp32_gmg_f32valu"] = _solve(dims, fine_prec="f32")
+        rec["fp64_gmg"] = _solve(dims, fine_prec="f64")
+        rec["bf16_gmg_flex"] = _solve(dims, fine_prec="bf16", flexible_beta=1)
+        rec["jacobi_pcg_cap200"] = _solve(dims, precond=1, maxit=200, fine_prec="f64")
+        rec["jacobi_pcg_to_1e-6"] = _solve(dims, precond=1, maxit=20000, fine_prec="f64", trials=1, warmup=0)
+        print(json.dumps(rec), flush=True)
+
+
+def kernels():
+    dev = "cuda:0"
+    for n in (40, 60, 80, 128):
+        dims = (n, n, n)
+        o = simpgmg.default_options(*dims, n_levels=0)     # fewest levels with n_L <= 5000
+        rho = torch.tensor(workloads.uniform_rho(dims), dtype=torch.float64, device=dev)
+        h = simpgmg.setup_hierarchy(o, rho)
+        fixed = torch.tensor(workloads.cantilever_fixed(dims), device=dev).bool()
+        rec = {"dims": dims, "mfma_zchunk_bf16_bf16x3": simpgmg.autotune(h)}
+        for prec in ("f64", "f32", "bf16x3", "bf16"):
+            dt = torch.float64 if prec == "f64" else torch.float32
+            u = torch.ones(fixed.numel(), dtype=dt, device=dev).masked_fill_(fixed, 0)
+            y = torch.empty_like(u)
+            for _ in range(5):
+                simpgmg.apply_K(h, 0, prec, u, y)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(200):
+                simpgmg.apply_K(h, 0, prec, u, y)
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / 200
+            es = 8 if prec == "f64" else 4
+            byts = 2 * fixed.numel() * es + n ** 3 * es
+            rec[f"ku_{prec}_us"] = round(us, 2)
+            rec[f"ku_{prec}_GBs"] = round(byts / us / 1e3, 1)
+        info = h.level_info(1)
+        d = info["dims"]
+        n1 = 3 * (d[0] + 1) * (d[1] + 1) * (d[2] + 1)
+        u1 = torch.ones(n1, dtype=torch.float64, device=dev)
+        y1 = torch.empty_like(u1)
+        for _ in range(5):
+            simpgmg.apply_K(h, 1, "f64", u1, y1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(100):
+            simpgmg.apply_K(h, 1, "f64", u1, y1)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / 100
+        nn1 = n1 // 3
+        rec["l1_stencil_f64_us"] = round(us, 2)
+        rec["l1_stencil_f64_GBs"] = round((243 * 8 * nn1 + 2 * 8 * n1) / us / 1e3, 1)
+        h.close()
+        print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    {"sizes": sizes, "kernels": kernels}[sys.argv[1]]()

@@ -58,6 +58,7 @@ EXPORTS = [
     "sgmg_default_options", "sgmg_setup_hierarchy", "sgmg_update_moduli", "sgmg_apply_K",
     "sgmg_vcycle", "sgmg_pcg_solve", "sgmg_num_levels", "sgmg_level_info",
     "sgmg_copy_stencil", "sgmg_copy_diagonal", "sgmg_destroy", "sgmg_last_error",
+    "sgmg_autotune",
 ]
 
 
@@ -74,6 +75,7 @@ def _load():
     lib.sgmg_apply_K.argtypes = [H, i, i, vp, vp, vp]
     lib.sgmg_vcycle.argtypes = [H, vp, vp, vp]
     lib.sgmg_pcg_solve.argtypes = [H, i, vp, vp, d, i, ctypes.POINTER(SolveInfo), vp]
+    lib.sgmg_autotune.argtypes = [H, ctypes.POINTER(ctypes.c_int), vp]
     lib.sgmg_num_levels.argtypes = [H]
     lib.sgmg_level_info.argtypes = [H, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                     ctypes.POINTER(ctypes.c_double)]
@@ -203,6 +205,13 @@ def setup_hierarchy(opts, rho_or_E, fixed_dof=None, lambda_override=None, stream
     finally:
         opts.lambda_override = None
     return Hierarchy(h, opts)
+
+
+def autotune(h, stream=None):
+    """Tune the MFMA fine operator's z-chunk for this mesh; returns (bf16, bf16x3)."""
+    z = (ctypes.c_int * 2)()
+    _check(_lib.sgmg_autotune(h.handle, z, _stream(stream)))
+    return int(z[0]), int(z[1])
 
 
 def update_moduli(h, rho_or_E, stream=None):

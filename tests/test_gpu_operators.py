@@ -134,3 +134,23 @@ def test_fine_apply_deterministic():
         simpgmg.apply_K(h, 0, prec, u, a)
         simpgmg.apply_K(h, 0, prec, u, b)
         assert np.array_equal(np64(a), np64(b)), prec
+
+
+def test_autotune_keeps_results_bitwise():
+    """The tuned launch shape moves work between workgroups only."""
+    from paper_2604_26441_amd import simpgmg
+    dims = (31, 6, 20)
+    rho, fixed = _inputs(dims, 11)
+    h = _gpu_h(dims, 2, rho)
+    u = t32(workloads.random_vector(fixed.size, 12, fixed))
+    before = {}
+    for prec in ("bf16", "bf16x3"):
+        y = t32(np.zeros(fixed.size))
+        simpgmg.apply_K(h, 0, prec, u, y)
+        before[prec] = np64(y)
+    z = simpgmg.autotune(h)
+    assert all(v in (2, 4, 8, 16, 32) for v in z)
+    for prec in ("bf16", "bf16x3"):
+        y = t32(np.zeros(fixed.size))
+        simpgmg.apply_K(h, 0, prec, u, y)
+        assert np.array_equal(np64(y), before[prec]), prec
