@@ -87,7 +87,7 @@ typedef struct {
   int coarse_sweeps;         /* damped-Jacobi pre and post sweeps on levels >= 1 (2) */
   double cheb_alpha;         /* lower end of the Chebyshev interval, 1/30            */
   double jacobi_omega_max;   /* damping cap 0.5; omega = min(cap, 4/(3 lambda))      */
-  double lambda_safety;      /* smoothers use lambda_safety * estimate (1.1)         */
+  double lambda_safety;      /* smoothers use lambda_safety * estimate (1.3)         */
   int power_iters_fine;      /* power iterations on level 0 (20)                     */
   int power_iters_coarse;    /* power iterations on levels >= 1 (10)                 */
   sgmg_prec fine_prec;       /* level-0 smoother/residual arithmetic                 */
@@ -119,7 +119,7 @@ typedef struct sgmg_hierarchy sgmg_hierarchy;
 /* Fills *o with the paper's defaults (Table repro_defaults) for an nx*ny*nz
  * mesh: nu 0.3, E0 1, Emin 1e-9, p 3, 4 levels, Chebyshev degree 2, 2 coarse
  * sweeps, alpha 1/30, omega cap 0.5, 20/10 power iterations, level-0 F32,
- * level-1 F64, dense_max 5000, seed 0, lambda_safety 1.1. */
+ * level-1 F64, dense_max 5000, seed 0, lambda_safety 1.3. */
 void sgmg_default_options(sgmg_options* o, int nx, int ny, int nz);
 
 /* Builds the hierarchy for one frozen modulus field (Sec. 3.3, 3.5).
@@ -178,6 +178,41 @@ int sgmg_level_info(const sgmg_hierarchy* h, int level, int* dims, int* n_free, 
 int sgmg_copy_stencil(const sgmg_hierarchy* h, int level, double* host_out);
 /* Copies diag(K^level) (zeros on fixed DOFs) to a host buffer. */
 int sgmg_copy_diagonal(const sgmg_hierarchy* h, int level, double* host_out);
+
+/* ---- Batched persistent solve (extension: many uneven systems, one launch) ----
+ * Not a passage of the paper: many independent cantilevers and load cases
+ * solved by one persistent kernel launch replayed from a captured HIP graph.
+ * Each workgroup takes (system, load case) work items from a device queue,
+ * largest systems first, and runs the complete FP64-outer PCG with the
+ * V-cycle (FP32 Chebyshev on level 0, FP64 Jacobi on the Galerkin levels,
+ * dense coarsest solve) of its item at block level, with the same acceptance
+ * rule as sgmg_pcg_solve.  The block size is picked by timing 256 and 512
+ * threads on the first solve of a batch. */
+typedef struct sgmg_batch sgmg_batch;
+
+/* Builds one hierarchy per system with sgmg_setup_hierarchy.
+ *   opts      : host array of nsys options (each with its own mesh).
+ *   rho_or_E  : host array of nsys device pointers (element fields).
+ *   fixed_dof : host array of nsys device masks, NULL entries (or NULL) for
+ *               the cantilever clamp.                                      */
+int sgmg_setup_batch(int nsys, const sgmg_options* opts, const double* const* rho_or_E,
+                     const uint8_t* const* fixed_dof, void* stream, sgmg_batch** out);
+
+/* Solves nitems load cases: item i is system item_sys[i] with right-hand
+ * side f[i] and iterate u[i] (host arrays of device pointers, full-DOF
+ * layout of that system; u[i]: in x0, out solution).  infos (host, nitems,
+ * may be NULL) receives each item's status, iterations and residuals;
+ * *total_ms (may be NULL) the wall time of the launch.  Work vectors are
+ * allocated on the first call for an item set and reused.  Synchronises. */
+int sgmg_pcg_solve_batch(sgmg_batch* b, int nitems, const int* item_sys, const double* const* f,
+                         double* const* u, double rtol, int maxit, sgmg_solve_info* infos,
+                         double* total_ms, void* stream);
+
+/* Borrowed handle of system s (owned by the batch), e.g. for single solves. */
+sgmg_hierarchy* sgmg_batch_hierarchy(sgmg_batch* b, int s);
+/* Block size chosen by the autotuner (0 before the first solve). */
+int sgmg_batch_block_size(const sgmg_batch* b);
+void sgmg_batch_destroy(sgmg_batch* b);
 
 void sgmg_destroy(sgmg_hierarchy* h);
 const char* sgmg_last_error(void);

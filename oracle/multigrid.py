@@ -9,11 +9,12 @@ of K_L + eps I (n_L <= 5000, eps = max(mean diag * 1e-8, 1e-14), Sec. 4.1)
 or by a fixed number of PCG steps (Table repro_defaults: 80).  Level 0 uses
 the Chebyshev (or damped-Jacobi) smoother of degree nu = 2, levels 1..L-1 use
 damped Jacobi with 2 pre and 2 post sweeps (Table repro_defaults; reading).
-Reading: the smoothers use 1.1 times the power-iteration estimate as the
+Reading: the smoothers use 1.3 times the power-iteration estimate as the
 upper end of the spectrum.  The estimate approaches lambda_max from below
-(about 8% low after 20 steps on a 20^3 cantilever), and degree-2 Chebyshev
-amplifies eigenvalues above its interval, which makes PCG break down on such
-meshes; the margin is an option (1.0 gives the literal form).
+(about 8% low after 20 steps on a uniform 20^3 cantilever, 20% low on a
+48x24x24 random-field cantilever with rho in [1e-3, 1]), and degree-2
+Chebyshev amplifies eigenvalues above its interval, which makes PCG break
+down; the margin is an option (1.0 gives the literal form).
 Level 0 is the assembled fine operator here, which the matrix-free action
 equals exactly (Eq. mf_matvec).
 """
@@ -41,7 +42,7 @@ class Options:
     dense_max: int = 5000
     coarse_pcg_iters: int = 80
     seed: int = 0
-    lambda_safety: float = 1.1            # smoothers use lambda_safety * estimate (reading)
+    lambda_safety: float = 1.3            # smoothers use lambda_safety * estimate (reading)
     lambdas: list = None                  # optional override of the raw estimates
 
 

@@ -3,6 +3,7 @@
 #include <cmath>
 
 #include "kernels.hpp"
+#include "node_ops.hpp"
 
 namespace sgmg {
 
@@ -151,44 +152,9 @@ __global__ __launch_bounds__(256) void k_apply_fine_node(Grid g, const T* __rest
   const int node = blockIdx.x * 256 + threadIdx.x;
   double dot = 0.0;
   if (node < g.Nn) {
-    const int i = node % g.Nx, t = node / g.Nx, j = t % g.Ny, k = t / g.Ny;
-    T un[27][3];
-#pragma unroll
-    for (int o = 0; o < 27; ++o) {
-      const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-      const bool ok = (unsigned)(i + ox) < (unsigned)g.Nx && (unsigned)(j + oy) < (unsigned)g.Ny &&
-                      (unsigned)(k + oz) < (unsigned)g.Nz;
-      const size_t nb = 3 * (size_t)(node + ox + g.Nx * (oy + g.Ny * oz));
-#pragma unroll
-      for (int c = 0; c < 3; ++c) un[o][c] = ok ? u[nb + c] : (T)0;
-    }
-    T acc[3] = {(T)0, (T)0, (T)0};
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int kx = q & 1, ky = (q >> 1) & 1, kz = q >> 2;
-      const int ex = i - 1 + kx, ey = j - 1 + ky, ez = k - 1 + kz;
-      if (ex < 0 || ey < 0 || ez < 0 || ex >= g.nx || ey >= g.ny || ez >= g.nz) continue;
-      const T Ee = E[ex + g.nx * (ey + g.ny * ez)];
-      const int a = 7 - q;  // local index of this node in the element
-      T s0 = (T)0, s1 = (T)0, s2 = (T)0;
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
-        const int o = (kx + bx) + 3 * (ky + by) + 9 * (kz + bz);
-#pragma unroll
-        for (int dd = 0; dd < 3; ++dd) {
-          const T uv = un[o][dd];
-          s0 += ke[(3 * a + 0) * 24 + 3 * b + dd] * uv;
-          s1 += ke[(3 * a + 1) * 24 + 3 * b + dd] * uv;
-          s2 += ke[(3 * a + 2) * 24 + 3 * b + dd] * uv;
-        }
-      }
-      acc[0] += Ee * s0;
-      acc[1] += Ee * s1;
-      acc[2] += Ee * s2;
-    }
+    T acc[3], xo[3];
+    fine_node_Ku<T>(g, E, ke, u, node, acc, xo);
     const double y[3] = {(double)acc[0], (double)acc[1], (double)acc[2]};
-    const T xo[3] = {un[13][0], un[13][1], un[13][2]};
     dot = epilogue3(ep, node, fixn[node], xo, y);
   }
   if (ep.want_dot) {

@@ -1,6 +1,7 @@
 // Galerkin levels (l >= 1): assembly into a structured 27-point block
 // stencil, its application, and the trilinear transfer kernels.
 #include "kernels.hpp"
+#include "node_ops.hpp"
 
 namespace sgmg {
 
@@ -218,30 +219,8 @@ __global__ __launch_bounds__(256) void k_stencil_apply(Grid g, const T* __restri
   const int node = blockIdx.x * 256 + threadIdx.x;
   double dot = 0.0;
   if (node < g.Nn) {
-    const int i = node % g.Nx, t = node / g.Nx, j = t % g.Ny, k = t / g.Ny;
-    T acc[3] = {(T)0, (T)0, (T)0};
-    const size_t Nn = g.Nn;
-#pragma unroll
-    for (int o = 0; o < 27; ++o) {
-      const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-      const bool ok = (unsigned)(i + ox) < (unsigned)g.Nx && (unsigned)(j + oy) < (unsigned)g.Ny &&
-                      (unsigned)(k + oz) < (unsigned)g.Nz;
-      if (!ok) continue;
-      const int nb = node + ox + g.Nx * (oy + g.Ny * oz);
-      const size_t b3 = 3 * (size_t)nb;
-      const T u0 = u[b3], u1 = u[b3 + 1], u2 = u[b3 + 2];
-      if (o >= 13) {
-        const T* Sb = S + (size_t)o * 9 * Nn + node;
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-          acc[d] += Sb[(3 * d) * Nn] * u0 + Sb[(3 * d + 1) * Nn] * u1 + Sb[(3 * d + 2) * Nn] * u2;
-      } else {
-        const T* Sb = S + (size_t)(26 - o) * 9 * Nn + nb;     // neighbour's block, transposed
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-          acc[d] += Sb[d * Nn] * u0 + Sb[(3 + d) * Nn] * u1 + Sb[(6 + d) * Nn] * u2;
-      }
-    }
+    T acc[3];
+    stencil_node_Ku<T>(g, S, u, node, acc);
     const double y[3] = {(double)acc[0], (double)acc[1], (double)acc[2]};
     const T xo[3] = {u[3 * (size_t)node], u[3 * (size_t)node + 1], u[3 * (size_t)node + 2]};
     dot = epilogue3(ep, node, fixn[node], xo, y);
@@ -275,27 +254,8 @@ __global__ void k_restrict(Grid f, Grid c, const TF* __restrict__ rf,
                            TC* __restrict__ dc) {
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= c.Nn) return;
-  const int Ix = I % c.Nx, t = I / c.Nx, Iy = t % c.Ny, Iz = t / c.Ny;
-  double acc[3] = {0.0, 0.0, 0.0};
-  for (int iz = 2 * Iz - 1; iz <= 2 * Iz + 1; ++iz) {
-    if (iz < 0 || iz >= f.Nz) continue;
-    const double wz = w1d(iz, Iz, f.nz);
-    if (wz == 0.0) continue;
-    for (int iy = 2 * Iy - 1; iy <= 2 * Iy + 1; ++iy) {
-      if (iy < 0 || iy >= f.Ny) continue;
-      const double wy = w1d(iy, Iy, f.ny) * wz;
-      if (wy == 0.0) continue;
-      for (int ix = 2 * Ix - 1; ix <= 2 * Ix + 1; ++ix) {
-        if (ix < 0 || ix >= f.Nx) continue;
-        const double w = w1d(ix, Ix, f.nx) * wy;
-        if (w == 0.0) continue;
-        const size_t b = 3 * (size_t)(ix + f.Nx * (iy + f.Ny * iz));
-        acc[0] += w * (double)rf[b];
-        acc[1] += w * (double)rf[b + 1];
-        acc[2] += w * (double)rf[b + 2];
-      }
-    }
-  }
+  double acc[3];
+  restrict_node<TF>(f, c, rf, I, acc);
   const unsigned fx = cfix[I];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -335,28 +295,8 @@ __global__ void k_prolong_add(Grid f, Grid c, const TC* __restrict__ ec,
                               const uint8_t* __restrict__ ffix, TF* __restrict__ xf) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= f.Nn) return;
-  const int ix = i % f.Nx, t = i / f.Nx, iy = t % f.Ny, iz = t / f.Ny;
-  int cx[2], cy[2], cz[2];
-  double wx[2], wy[2], wz[2];
-  auto cand = [](int fi, int nf, int* ci, double* w) {
-    const int nc = nf >> 1;
-    if ((fi & 1) == 0) { ci[0] = fi >> 1; w[0] = 1.0; ci[1] = 0; w[1] = 0.0; }
-    else if (fi < 2 * nc) { ci[0] = (fi - 1) >> 1; ci[1] = (fi + 1) >> 1; w[0] = w[1] = 0.5; }
-    else { ci[0] = nc; w[0] = 1.0; ci[1] = 0; w[1] = 0.0; }
-  };
-  cand(ix, f.nx, cx, wx);
-  cand(iy, f.ny, cy, wy);
-  cand(iz, f.nz, cz, wz);
-  double acc[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    const double w = wx[a & 1] * wy[(a >> 1) & 1] * wz[a >> 2];
-    if (w == 0.0) continue;
-    const size_t b = 3 * (size_t)(cx[a & 1] + c.Nx * (cy[(a >> 1) & 1] + c.Ny * cz[a >> 2]));
-    acc[0] += w * (double)ec[b];
-    acc[1] += w * (double)ec[b + 1];
-    acc[2] += w * (double)ec[b + 2];
-  }
+  double acc[3];
+  prolong_node<TC>(f, c, ec, i, acc);
   const unsigned fx = ffix[i];
 #pragma unroll
   for (int k = 0; k < 3; ++k)

@@ -11,6 +11,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "batch.hpp"
 #include "kernels.hpp"
 
 namespace sgmg {
@@ -517,7 +518,7 @@ void sgmg_default_options(sgmg_options* o, int nx, int ny, int nz) {
   o->coarse_sweeps = 2;
   o->cheb_alpha = 1.0 / 30.0;
   o->jacobi_omega_max = 0.5;
-  o->lambda_safety = 1.1;
+  o->lambda_safety = 1.3;
   o->power_iters_fine = 20;
   o->power_iters_coarse = 10;
   o->fine_prec = SGMG_F32;
@@ -952,6 +953,281 @@ int sgmg_autotune(sgmg_hierarchy* h, int* zchunk_out, void* stream) {
 }
 
 int sgmg_num_levels(const sgmg_hierarchy* h) { return h ? h->L : 0; }
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched persistent solver (BASELINE extension: many systems, one launch)
+struct sgmg_batch {
+  std::vector<sgmg_hierarchy*> hs;
+  BSys* d_sys = nullptr;
+  // work vectors of the cached item set
+  std::vector<int> items_sys;
+  std::vector<void*> item_mem;
+  std::vector<BItem> h_items;     // in execution (largest-first) order
+  std::vector<int> order;         // execution slot -> caller item index
+  BItem* d_items = nullptr;
+  int* d_queue = nullptr;
+  BOut* d_out = nullptr;
+  BOut* h_out = nullptr;
+  int bs = 0;                     // tuned block size (0: not tuned yet)
+  hipStream_t cap = nullptr;
+  hipGraphExec_t graph = nullptr;
+  int g_nitems = -1, g_maxit = -1, g_bs = -1;
+  double g_rtol = -1.0;
+};
+
+namespace {
+
+void batch_drop_graph(sgmg_batch* b) {
+  if (b->graph) hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+}
+
+void batch_free_items(sgmg_batch* b) {
+  for (void* p : b->item_mem) hipFree(p);
+  b->item_mem.clear();
+  b->h_items.clear();
+  b->items_sys.clear();
+  if (b->d_items) hipFree(b->d_items);
+  if (b->d_out) hipFree(b->d_out);
+  if (b->h_out) hipHostFree(b->h_out);
+  b->d_items = nullptr;
+  b->d_out = nullptr;
+  b->h_out = nullptr;
+  batch_drop_graph(b);
+}
+
+BSys make_bsys(const sgmg_hierarchy* h) {
+  BSys S{};
+  S.L = h->L;
+  for (int l = 0; l < h->L; ++l) {
+    const Level& V = h->lev[l];
+    BLevel& B = S.lev[l];
+    B.g = V.g;
+    B.fixn = V.fixn;
+    B.dinv64 = V.dinv64;
+    B.dinv32 = V.dinv32;
+    B.S64 = V.S64;
+    if (l < h->L - 1) {
+      const Smoother sm = smoother_of(h, l);
+      B.cheb = sm.cheb;
+      B.steps = sm.steps;
+      B.omega = sm.omega;
+      B.theta = sm.theta;
+      B.delta = sm.delta;
+      B.sigma1 = sm.sigma1;
+    }
+  }
+  S.E32 = h->E32;
+  S.ke32 = h->ke32;
+  S.E64 = h->E64;
+  S.ke64 = h->ke64;
+  S.nL = h->nL;
+  S.free_idx = h->free_idx;
+  S.Ainv = h->Ainv;
+  return S;
+}
+
+// (Re)allocates the work vectors when the item set changes.
+int batch_prepare_items(sgmg_batch* b, int nitems, const int* item_sys, hipStream_t s) {
+  std::vector<int> key(item_sys, item_sys + nitems);
+  if (key == b->items_sys && b->d_items) return 0;
+  batch_free_items(b);
+  b->items_sys = key;
+  // largest systems first (longest-processing-time order for the queue)
+  b->order.resize(nitems);
+  for (int i = 0; i < nitems; ++i) b->order[i] = i;
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int a, int c) {
+    return b->hs[item_sys[a]]->lev[0].g.n > b->hs[item_sys[c]]->lev[0].g.n;
+  });
+  b->h_items.assign(nitems, BItem{});
+  for (int k = 0; k < nitems; ++k) {
+    const int sys = item_sys[b->order[k]];
+    const sgmg_hierarchy* h = b->hs[sys];
+    BItem& I = b->h_items[k];
+    I.sys = sys;
+    const size_t n0 = h->lev[0].g.n;
+    size_t bytes = 5 * n0 * sizeof(double) + 5 * n0 * sizeof(float);
+    for (int l = 1; l < h->L; ++l) bytes += 4 * (size_t)h->lev[l].g.n * sizeof(double);
+    bytes += (size_t)std::max(h->nL, 1) * sizeof(double) + 64 * 32;
+    void* mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) { set_error("batch work allocation failed"); return SGMG_ENOMEM; }
+    b->item_mem.push_back(mem);
+    SGMG_HIP(hipMemsetAsync(mem, 0, bytes, s));
+    char* c = (char*)mem;
+    auto take = [&](size_t nbytes) { char* r = c; c += (nbytes + 255) & ~(size_t)255; return (void*)r; };
+    I.r = (double*)take(n0 * 8); I.z = (double*)take(n0 * 8); I.p = (double*)take(n0 * 8);
+    I.q = (double*)take(n0 * 8); I.t = (double*)take(n0 * 8);
+    I.b0 = (float*)take(n0 * 4); I.d0 = (float*)take(n0 * 4); I.r0 = (float*)take(n0 * 4);
+    I.x0[0] = (float*)take(n0 * 4); I.x0[1] = (float*)take(n0 * 4);
+    for (int l = 1; l < h->L; ++l) {
+      const size_t nl = h->lev[l].g.n;
+      I.lb[l] = (double*)take(nl * 8);
+      I.lx[l][0] = (double*)take(nl * 8);
+      I.lx[l][1] = (double*)take(nl * 8);
+      I.lr[l] = (double*)take(nl * 8);
+    }
+    I.rc = (double*)take((size_t)std::max(h->nL, 1) * 8);
+  }
+  SGMG_HIP(hipMalloc(&b->d_items, nitems * sizeof(BItem)));
+  SGMG_HIP(hipMalloc(&b->d_out, nitems * sizeof(BOut)));
+  SGMG_HIP(hipHostMalloc((void**)&b->h_out, nitems * sizeof(BOut), hipHostMallocDefault));
+  SGMG_HIP(hipStreamSynchronize(s));
+  return 0;
+}
+
+int batch_launch(sgmg_batch* b, int nitems, double rtol, int maxit, int bs, hipStream_t s) {
+  const int grid = std::min(nitems, 1024);
+  const bool same = b->graph && b->g_nitems == nitems && b->g_rtol == rtol &&
+                    b->g_maxit == maxit && b->g_bs == bs;
+  if (!same) {
+    batch_drop_graph(b);
+    if (!b->cap) SGMG_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    SGMG_HIP(hipStreamSynchronize(s));
+    SGMG_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    launch_batch_pcg(bs, grid, b->d_sys, b->d_items, nitems, b->d_queue, b->d_out, rtol, maxit,
+                     b->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (e != hipSuccess) { set_error(std::string("batch capture: ") + hipGetErrorString(e)); return SGMG_EHIP; }
+    const hipError_t e2 = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e2 != hipSuccess) { b->graph = nullptr; set_error("batch graph instantiate failed"); return SGMG_EHIP; }
+    b->g_nitems = nitems; b->g_rtol = rtol; b->g_maxit = maxit; b->g_bs = bs;
+  }
+  SGMG_HIP(hipGraphLaunch(b->graph, s));
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sgmg_batch_destroy(sgmg_batch* b) {
+  if (!b) return;
+  batch_free_items(b);
+  for (sgmg_hierarchy* h : b->hs) sgmg_destroy(h);
+  if (b->d_sys) hipFree(b->d_sys);
+  if (b->d_queue) hipFree(b->d_queue);
+  if (b->cap) hipStreamDestroy(b->cap);
+  delete b;
+}
+
+int sgmg_setup_batch(int nsys, const sgmg_options* opts, const double* const* rho_or_E,
+                     const uint8_t* const* fixed_dof, void* stream, sgmg_batch** out) {
+  if (out) *out = nullptr;
+  if (nsys < 1 || !opts || !rho_or_E || !out) { set_error("bad batch arguments"); return SGMG_EINVAL; }
+  hipStream_t s = as_stream(stream);
+  sgmg_batch* b = new (std::nothrow) sgmg_batch();
+  if (!b) { set_error("host allocation failed"); return SGMG_ENOMEM; }
+  for (int i = 0; i < nsys; ++i) {
+    sgmg_hierarchy* h = nullptr;
+    const int rc = sgmg_setup_hierarchy(&opts[i], rho_or_E[i], fixed_dof ? fixed_dof[i] : nullptr,
+                                        stream, &h);
+    if (rc) { sgmg_batch_destroy(b); return rc; }
+    b->hs.push_back(h);
+  }
+  std::vector<BSys> hsys;
+  for (auto* h : b->hs) hsys.push_back(make_bsys(h));
+  if (hipMalloc(&b->d_sys, hsys.size() * sizeof(BSys)) != hipSuccess ||
+      hipMalloc(&b->d_queue, sizeof(int)) != hipSuccess) {
+    sgmg_batch_destroy(b);
+    set_error("batch allocation failed");
+    return SGMG_ENOMEM;
+  }
+  hipMemcpyAsync(b->d_sys, hsys.data(), hsys.size() * sizeof(BSys), hipMemcpyHostToDevice, s);
+  if (hipStreamSynchronize(s) != hipSuccess) { sgmg_batch_destroy(b); set_error("sync failed"); return SGMG_EHIP; }
+  *out = b;
+  return 0;
+}
+
+sgmg_hierarchy* sgmg_batch_hierarchy(sgmg_batch* b, int sys) {
+  if (!b || sys < 0 || sys >= (int)b->hs.size()) return nullptr;
+  return b->hs[sys];
+}
+
+int sgmg_batch_block_size(const sgmg_batch* b) { return b ? b->bs : 0; }
+
+int sgmg_pcg_solve_batch(sgmg_batch* b, int nitems, const int* item_sys, const double* const* f,
+                         double* const* u, double rtol, int maxit, sgmg_solve_info* infos,
+                         double* total_ms, void* stream) {
+  if (!b || nitems < 1 || !item_sys || !f || !u || maxit < 0) { set_error("bad batch solve arguments"); return SGMG_EINVAL; }
+  for (int i = 0; i < nitems; ++i)
+    if (item_sys[i] < 0 || item_sys[i] >= (int)b->hs.size() || !f[i] || !u[i]) {
+      set_error("bad item " + std::to_string(i));
+      return SGMG_EINVAL;
+    }
+  hipStream_t s = as_stream(stream);
+  TRY(batch_prepare_items(b, nitems, item_sys, s));
+  for (int k = 0; k < nitems; ++k) {
+    b->h_items[k].f = f[b->order[k]];
+    b->h_items[k].u = u[b->order[k]];
+  }
+  SGMG_HIP(hipMemcpyAsync(b->d_items, b->h_items.data(), nitems * sizeof(BItem), hipMemcpyHostToDevice, s));
+  if (b->bs == 0) {
+    // autotune the block size on this batch (2 iterations per candidate), then restore u
+    std::vector<double*> saved(nitems, nullptr);
+    int rc = 0;
+    for (int k = 0; k < nitems && !rc; ++k) {
+      const size_t n = b->hs[b->h_items[k].sys]->lev[0].g.n;
+      if (hipMalloc(&saved[k], n * sizeof(double)) != hipSuccess) { rc = SGMG_ENOMEM; break; }
+      hipMemcpyAsync(saved[k], b->h_items[k].u, n * sizeof(double), hipMemcpyDeviceToDevice, s);
+    }
+    float best = 1e30f;
+    int best_bs = 256;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    for (int bs : {256, 512}) {
+      if (rc) break;
+      hipEventRecord(e0, s);
+      launch_batch_pcg(bs, std::min(nitems, 1024), b->d_sys, b->d_items, nitems, b->d_queue,
+                       b->d_out, rtol, 2, s);
+      hipEventRecord(e1, s);
+      if ((rc = check_launch())) break;
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) { best = ms; best_bs = bs; }
+      for (int k = 0; k < nitems; ++k) {
+        const size_t n = b->hs[b->h_items[k].sys]->lev[0].g.n;
+        hipMemcpyAsync(b->h_items[k].u, saved[k], n * sizeof(double), hipMemcpyDeviceToDevice, s);
+      }
+    }
+    hipStreamSynchronize(s);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    for (double* p : saved) if (p) hipFree(p);
+    if (rc) return rc;
+    b->bs = best_bs;
+  }
+  hipEvent_t e0, e1;
+  SGMG_HIP(hipEventCreate(&e0));
+  SGMG_HIP(hipEventCreate(&e1));
+  SGMG_HIP(hipEventRecord(e0, s));
+  const int rc = batch_launch(b, nitems, rtol, maxit, b->bs, s);
+  if (rc) { hipEventDestroy(e0); hipEventDestroy(e1); return rc; }
+  SGMG_HIP(hipEventRecord(e1, s));
+  SGMG_HIP(hipMemcpyAsync(b->h_out, b->d_out, nitems * sizeof(BOut), hipMemcpyDeviceToHost, s));
+  SGMG_HIP(hipStreamSynchronize(s));
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (total_ms) *total_ms = ms;
+  if (infos) {
+    for (int k = 0; k < nitems; ++k) {
+      sgmg_solve_info& inf = infos[b->order[k]];
+      inf.status = b->h_out[k].status;
+      inf.iters = b->h_out[k].iters;
+      inf.rel_res_true = b->h_out[k].rel_true;
+      inf.rel_res_recur = b->h_out[k].rel_recur;
+      inf.solve_ms = ms;
+    }
+  }
+  return 0;
+}
 
 int sgmg_level_info(const sgmg_hierarchy* h, int level, int* dims, int* n_free, double* lambda) {
   if (!h || level < 0 || level >= h->L) { set_error("bad level"); return SGMG_EINVAL; }

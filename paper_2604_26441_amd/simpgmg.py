@@ -58,7 +58,8 @@ EXPORTS = [
     "sgmg_default_options", "sgmg_setup_hierarchy", "sgmg_update_moduli", "sgmg_apply_K",
     "sgmg_vcycle", "sgmg_pcg_solve", "sgmg_num_levels", "sgmg_level_info",
     "sgmg_copy_stencil", "sgmg_copy_diagonal", "sgmg_destroy", "sgmg_last_error",
-    "sgmg_autotune",
+    "sgmg_autotune", "sgmg_setup_batch", "sgmg_pcg_solve_batch", "sgmg_batch_hierarchy",
+    "sgmg_batch_block_size", "sgmg_batch_destroy",
 ]
 
 
@@ -76,6 +77,16 @@ def _load():
     lib.sgmg_vcycle.argtypes = [H, vp, vp, vp]
     lib.sgmg_pcg_solve.argtypes = [H, i, vp, vp, d, i, ctypes.POINTER(SolveInfo), vp]
     lib.sgmg_autotune.argtypes = [H, ctypes.POINTER(ctypes.c_int), vp]
+    lib.sgmg_setup_batch.argtypes = [i, ctypes.POINTER(Options), ctypes.POINTER(vp),
+                                     ctypes.POINTER(vp), vp, ctypes.POINTER(H)]
+    lib.sgmg_pcg_solve_batch.argtypes = [H, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp),
+                                         ctypes.POINTER(vp), d, i, ctypes.POINTER(SolveInfo),
+                                         ctypes.POINTER(ctypes.c_double), vp]
+    lib.sgmg_batch_hierarchy.argtypes = [H, i]
+    lib.sgmg_batch_hierarchy.restype = ctypes.c_void_p
+    lib.sgmg_batch_block_size.argtypes = [H]
+    lib.sgmg_batch_destroy.argtypes = [H]
+    lib.sgmg_batch_destroy.restype = None
     lib.sgmg_num_levels.argtypes = [H]
     lib.sgmg_level_info.argtypes = [H, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                     ctypes.POINTER(ctypes.c_double)]
@@ -140,21 +151,22 @@ def n_nodes(o):
 
 
 class Hierarchy:
-    """Owns an sgmg_hierarchy handle."""
+    """Owns an sgmg_hierarchy handle (or borrows one from a batch)."""
 
-    def __init__(self, handle, opts):
+    def __init__(self, handle, opts, owner=None):
         self._h = handle
         self.opts = opts
         self.n_dof = 3 * n_nodes(opts)
+        self._owner = owner            # a Batch keeps borrowed handles alive
 
     @property
     def handle(self):
         return self._h
 
     def close(self):
-        if self._h:
+        if self._h and self._owner is None:
             _lib.sgmg_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         try:
@@ -250,3 +262,67 @@ def pcg_solve(h, f, u, rtol=1e-6, maxit=200, precond=PRECOND_VCYCLE, history_cap
     if hist is not None:
         out["history"] = list(hist)[: info.iters + 1]
     return out
+
+
+class Batch:
+    """Owns an sgmg_batch handle (systems of possibly different meshes)."""
+
+    def __init__(self, handle, opts_list):
+        self._b = handle
+        self.opts = list(opts_list)
+
+    @property
+    def handle(self):
+        return self._b
+
+    def close(self):
+        if self._b:
+            _lib.sgmg_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def hierarchy(self, s):
+        h = _lib.sgmg_batch_hierarchy(self._b, s)
+        if not h:
+            raise SimpGmgError("bad system index")
+        return Hierarchy(ctypes.c_void_p(h), self.opts[s], owner=self)
+
+    def block_size(self):
+        return _lib.sgmg_batch_block_size(self._b)
+
+
+def setup_batch(opts_list, rho_list, fixed_list=None, stream=None):
+    n = len(opts_list)
+    arr = (Options * n)(*opts_list)
+    rho = (ctypes.c_void_p * n)(*[_ptr(r, torch.float64, o.nx * o.ny * o.nz, "rho").value
+                                  for r, o in zip(rho_list, opts_list)])
+    fix = None
+    if fixed_list is not None:
+        fix = (ctypes.c_void_p * n)(*[None if m is None else
+                                      _ptr(m, torch.uint8, 3 * n_nodes(o), "fixed").value
+                                      for m, o in zip(fixed_list, opts_list)])
+    b = ctypes.c_void_p()
+    _check(_lib.sgmg_setup_batch(n, arr, rho, fix, _stream(stream), ctypes.byref(b)))
+    return Batch(b, opts_list)
+
+
+def pcg_solve_batch(batch, item_sys, f_list, u_list, rtol=1e-6, maxit=200, stream=None):
+    """Solves every item (system index, f, u); returns (list of dicts, total ms)."""
+    m = len(item_sys)
+    sysarr = (ctypes.c_int * m)(*item_sys)
+    fa = (ctypes.c_void_p * m)(*[_ptr(f, torch.float64, 3 * n_nodes(batch.opts[s]), "f").value
+                                 for f, s in zip(f_list, item_sys)])
+    ua = (ctypes.c_void_p * m)(*[_ptr(u, torch.float64, 3 * n_nodes(batch.opts[s]), "u").value
+                                 for u, s in zip(u_list, item_sys)])
+    infos = (SolveInfo * m)()
+    ms = ctypes.c_double()
+    _check(_lib.sgmg_pcg_solve_batch(batch.handle, m, sysarr, fa, ua, rtol, maxit, infos,
+                                     ctypes.byref(ms), _stream(stream)))
+    out = [{"status": STATUS.get(i.status, i.status), "iters": i.iters,
+            "rel_res_true": i.rel_res_true, "rel_res_recur": i.rel_res_recur} for i in infos]
+    return out, ms.value

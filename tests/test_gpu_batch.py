@@ -1,0 +1,81 @@
+"""GPU parity of the persistent batched solve (BASELINE extension 2).
+
+Each item of one persistent launch must reproduce the single-system solve of
+the same hierarchy with FP32 vector-ALU smoothing (same operators, same
+algorithm; only dot-product summation order differs): equal status, equal
+iteration count (+-1), FP64 true residual below rtol, solutions within the
+solver tolerance.  The oracle's own solve fixes the expected compliance.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import krylov, mesh, multigrid
+from tests.gpu_util import np64, t64
+
+pytestmark = pytest.mark.gpu
+
+
+def _systems():
+    dims = [(16, 8, 8), (20, 10, 10), (12, 6, 6), (24, 12, 12)]
+    rhos = [workloads.grf_rho(d, seed=100 + i) for i, d in enumerate(dims)]
+    return dims, rhos
+
+
+def test_batch_matches_single_solves_and_oracle():
+    import torch
+    from paper_2604_26441_amd import simpgmg
+    dims, rhos = _systems()
+    opts = [simpgmg.default_options(*d, n_levels=0, dense_max=1000, fine_prec="f32") for d in dims]
+    b = simpgmg.setup_batch(opts, [t64(r) for r in rhos])
+    rng = np.random.default_rng(7)
+    item_sys, fs = [], []
+    for s, d in enumerate(dims):
+        for k in range(1 + s % 3):                       # 1..3 load cases per system
+            item_sys.append(s)
+            fs.append(workloads.random_face_load(d, rng) if k else workloads.edge_load(d))
+    us = [t64(np.zeros_like(f)) for f in fs]
+    res, ms = simpgmg.pcg_solve_batch(b, item_sys, [t64(f) for f in fs], us, rtol=1e-6, maxit=300)
+    assert ms > 0 and b.block_size() in (256, 512)
+    for i, (s, f) in enumerate(zip(item_sys, fs)):
+        h = b.hierarchy(s)
+        u1 = t64(np.zeros_like(f))
+        single = simpgmg.pcg_solve(h, t64(f), u1, rtol=1e-6, maxit=300)
+        assert res[i]["status"] == "converged" == single["status"], (i, res[i], single)
+        assert abs(res[i]["iters"] - single["iters"]) <= 1
+        assert res[i]["rel_res_true"] < 1e-6
+        xb, xs = np64(us[i]), np64(u1)
+        assert np.linalg.norm(xb - xs) <= 1e-5 * np.linalg.norm(xs)
+    # oracle: compliance of the first item of the first system
+    d = dims[0]
+    fixed = workloads.cantilever_fixed(d).astype(bool)
+    E = mesh.simp_modulus(rhos[0], 3)
+    K = mesh.assemble(d, E, fixed=fixed)
+    fr = ~fixed
+    import scipy.sparse.linalg as spla
+    ustar = np.zeros(fixed.size)
+    ustar[fr] = spla.spsolve(K[fr][:, fr].tocsc(), fs[0][fr])
+    x0 = np64(us[0])
+    assert abs(fs[0] @ x0 - fs[0] @ ustar) <= 1e-5 * abs(fs[0] @ ustar)
+    assert krylov.true_rel_residual(lambda v: K @ v, fs[0], x0) < 1e-6
+
+
+def test_batch_graph_replays_agree():
+    """The captured launch replayed three times (host work in between) gives
+    the same results as the first, eager-tuned, solve."""
+    from paper_2604_26441_amd import simpgmg
+    dims, rhos = _systems()
+    opts = [simpgmg.default_options(*d, n_levels=0, dense_max=1000, fine_prec="f32") for d in dims]
+    b = simpgmg.setup_batch(opts, [t64(r) for r in rhos])
+    fs = [workloads.edge_load(d) for d in dims]
+    first = None
+    for rep in range(3):
+        us = [t64(np.zeros_like(f)) for f in fs]
+        res, _ = simpgmg.pcg_solve_batch(b, list(range(len(dims))), [t64(f) for f in fs], us)
+        xs = [np64(u) for u in us]
+        if first is None:
+            first = (res, xs)
+        else:
+            assert [r["iters"] for r in res] == [r["iters"] for r in first[0]]
+            for a, c in zip(xs, first[1]):
+                assert np.array_equal(a, c)

@@ -58,13 +58,15 @@ def grf_rho(dims, seed, corr_len=4.0, gain=3.0, rho_min=1e-3):
 
 
 def random_face_load(dims, rng, max_nodes=8):
-    """One load case: k ~ U{1..max_nodes} nodes on a random unclamped face."""
+    """One load case: k ~ U{1..max_nodes} nodes on a random unclamped face,
+    each with a random unit direction; scaled so the nodal force magnitudes
+    sum to 1."""
     nx, ny, nz = dims
     face = int(rng.integers(0, 5))
     f = np.zeros(3 * n_nodes(dims))
     k = int(rng.integers(1, max_nodes + 1))
     for _ in range(k):
-        a, b = rng.integers(0, 10**9, size=2)
+        a, b = (int(v) for v in rng.integers(0, 10**9, size=2))
         if face == 0:
             i, j, kk = nx, a % (ny + 1), b % (nz + 1)
         elif face == 1:
@@ -76,10 +78,26 @@ def random_face_load(dims, rng, max_nodes=8):
         else:
             i, j, kk = 1 + a % nx, b % (ny + 1), nz
         v = rng.standard_normal(3)
-        v /= np.linalg.norm(v)
         node = i + (nx + 1) * (j + (ny + 1) * kk)
-        f[3 * node:3 * node + 3] += v
-    return f / np.linalg.norm(f.reshape(-1, 3).sum(axis=0)) if np.linalg.norm(f.reshape(-1, 3).sum(axis=0)) > 1e-12 else f / np.abs(f).sum()
+        f[3 * node:3 * node + 3] += v / np.linalg.norm(v)
+    return f / np.linalg.norm(f.reshape(-1, 3), axis=1).sum()
+
+
+def batch_config(n_systems=32, seed=1000, m_choices=tuple(range(8, 25, 2)), max_loads=4):
+    """Uneven cantilever batch: system s has m ~ U(m_choices), mesh (2m, m, m),
+    a random-field rho (seed + s, p = 3 in the solver) and 1..max_loads load
+    cases.  Returns (dims list, rho list, item_sys list, f list)."""
+    rng = np.random.default_rng(seed)
+    dims, rhos, item_sys, fs = [], [], [], []
+    for s in range(n_systems):
+        m = int(rng.choice(m_choices))
+        d = (2 * m, m, m)
+        dims.append(d)
+        rhos.append(grf_rho(d, seed + s))
+        for _ in range(int(rng.integers(1, max_loads + 1))):
+            item_sys.append(s)
+            fs.append(random_face_load(d, rng))
+    return dims, rhos, item_sys, fs
 
 
 def random_vector(n, seed, fixed=None):
