@@ -214,6 +214,56 @@ sgmg_hierarchy* sgmg_batch_hierarchy(sgmg_batch* b, int s);
 int sgmg_batch_block_size(const sgmg_batch* b);
 void sgmg_batch_destroy(sgmg_batch* b);
 
+/* ---- Learned warm start (extension: a 3D U-Net predicts the initial guess) ----
+ * Not a passage of the paper.  Network on the node grid padded to multiples
+ * of 8 (volume N x C x D x H x W, x fastest; D, H, W = padded z, y, x node
+ * counts): e1 = relu(c1(x)), e2 = relu(c2(pool e1)), e3 = relu(c3(pool e2)),
+ * b = relu(c4(pool e3)), d3 = relu(c5(up b)) + e3, d2 = relu(c6(up d3)) + e2,
+ * d1 = relu(c7(up d2)) + e1, y = c8(d1); c1..c7 3x3x3 convolutions with
+ * channels 5->16->32->64->128->64->32->16, c8 1x1x1 16->3, pool = 2x2x2 mean,
+ * up = nearest x2.  Weights are rounded to BF16 for compute (FP32 master
+ * copy for Adam), accumulation is FP32.  Input channels: density averaged to
+ * nodes, load / max|f| (3), clamp mask.  The prediction's scale is set by
+ * sgmg_warm_start_scale, and PCG-GMG to the same tolerance is both fallback
+ * and judge of the result. */
+typedef struct sgmg_unet sgmg_unet;
+int sgmg_unet_create(uint64_t seed, sgmg_unet** out);   /* He-normal init, zero bias */
+int sgmg_unet_num_params(void);
+/* Host buffer, per layer w[co][ci][kz][ky][kx] then b[co] (FP32). */
+int sgmg_unet_set_params(sgmg_unet* u, const float* host, void* stream);
+int sgmg_unet_get_params(sgmg_unet* u, int quantized, float* host, void* stream);
+/* out (device, N x 3 x D x H x W) = network(in (device, N x 5 x D x H x W)). */
+int sgmg_unet_forward(sgmg_unet* u, int N, int D, int H, int W, const float* in, float* out,
+                      void* stream);
+/* Masked MSE sum(m (y - t)^2) / sum(m) (mask N x D x H x W broadcast over the
+ * 3 channels, NULL = all ones), its gradients (host, parameter layout), no
+ * update. */
+int sgmg_unet_grad(sgmg_unet* u, int N, int D, int H, int W, const float* in, const float* target,
+                   const float* mask, float* loss, float* grads_host, void* stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the same loss; *loss before
+ * the step.  Synchronises. */
+int sgmg_unet_train_step(sgmg_unet* u, int N, int D, int H, int W, const float* in,
+                         const float* target, const float* mask, float lr, float* loss,
+                         void* stream);
+/* Network input for hierarchy h's mesh: rho (device, elements), f (device,
+ * DOFs) -> in (device, 5 x Dp x Hp x Wp, zero padded). */
+int sgmg_unet_input(const sgmg_hierarchy* h, const double* rho, const double* f, int Dp, int Hp,
+                    int Wp, float* in, void* stream);
+/* Network output (device, 3 x Dp x Hp x Wp) -> u0 (device, DOFs, FP64, zero on
+ * clamped DOFs). */
+int sgmg_unet_output(const sgmg_hierarchy* h, const float* out, int Dp, int Hp, int Wp, double* u0,
+                     void* stream);
+/* Training target for a solved displacement u (device, DOFs): t (device,
+ * 3 x Dp x Hp x Wp) = u / max|u| on the mesh nodes, 0 in the padding; mask
+ * (device, Dp x Hp x Wp, may be NULL) = 1 on the mesh nodes. */
+int sgmg_unet_target(const sgmg_hierarchy* h, const double* u, int Dp, int Hp, int Wp, float* t,
+                     float* mask, void* stream);
+/* u0 <- alpha u0 with alpha = (f . u0) / (u0 . K u0), the minimiser of the
+ * energy norm of the error along u0; *alpha (host, may be NULL). */
+int sgmg_warm_start_scale(sgmg_hierarchy* h, const double* f, double* u0, double* alpha,
+                          void* stream);
+void sgmg_unet_destroy(sgmg_unet* u);
+
 void sgmg_destroy(sgmg_hierarchy* h);
 const char* sgmg_last_error(void);
 

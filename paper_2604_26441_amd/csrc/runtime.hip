@@ -13,6 +13,7 @@
 
 #include "batch.hpp"
 #include "kernels.hpp"
+#include "unet.hpp"
 
 namespace sgmg {
 
@@ -953,6 +954,49 @@ int sgmg_autotune(sgmg_hierarchy* h, int* zchunk_out, void* stream) {
 }
 
 int sgmg_num_levels(const sgmg_hierarchy* h) { return h ? h->L : 0; }
+
+int sgmg_unet_input(const sgmg_hierarchy* h, const double* rho, const double* f, int Dp, int Hp,
+                    int Wp, float* in, void* stream) {
+  if (!h || !rho || !f || !in) { set_error("NULL argument"); return SGMG_EINVAL; }
+  const Grid& g = h->lev[0].g;
+  if (Dp < g.Nz || Hp < g.Ny || Wp < g.Nx) { set_error("padded volume smaller than the node grid"); return SGMG_EINVAL; }
+  launch_unet_input(g, rho, f, h->lev[0].fixn, h->sc + SC_MAX, Dp, Hp, Wp, in, as_stream(stream));
+  return check_launch();
+}
+
+int sgmg_unet_output(const sgmg_hierarchy* h, const float* out, int Dp, int Hp, int Wp, double* u0,
+                     void* stream) {
+  if (!h || !out || !u0) { set_error("NULL argument"); return SGMG_EINVAL; }
+  const Grid& g = h->lev[0].g;
+  if (Dp < g.Nz || Hp < g.Ny || Wp < g.Nx) { set_error("padded volume smaller than the node grid"); return SGMG_EINVAL; }
+  launch_unet_output(g, out, h->lev[0].fixn, Dp, Hp, Wp, u0, as_stream(stream));
+  return check_launch();
+}
+
+int sgmg_unet_target(const sgmg_hierarchy* h, const double* u, int Dp, int Hp, int Wp, float* t,
+                     float* mask, void* stream) {
+  if (!h || !u || !t) { set_error("NULL argument"); return SGMG_EINVAL; }
+  const Grid& g = h->lev[0].g;
+  if (Dp < g.Nz || Hp < g.Ny || Wp < g.Nx) { set_error("padded volume smaller than the node grid"); return SGMG_EINVAL; }
+  launch_unet_target(g, u, h->sc + SC_MAX, Dp, Hp, Wp, t, mask, as_stream(stream));
+  return check_launch();
+}
+
+int sgmg_warm_start_scale(sgmg_hierarchy* h, const double* f, double* u0, double* alpha,
+                          void* stream) {
+  if (!h || !f || !u0) { set_error("NULL argument"); return SGMG_EINVAL; }
+  hipStream_t s = as_stream(stream);
+  const int n = h->lev[0].g.n;
+  launch_dot(f, u0, nullptr, n, h->ws, h->sc + SC_XW, s);
+  TRY(apply_level<double>(h, 0, SGMG_F64, u0, epi_store<double>(h->tmp, h->ws, h->sc + SC_XDX), s));
+  launch_scale_by_ratio(u0, n, h->sc + SC_XW, h->sc + SC_XDX, h->sc + SC_NRM, s);
+  TRY(check_launch());
+  if (alpha) {
+    SGMG_HIP(hipMemcpyAsync(alpha, h->sc + SC_NRM, sizeof(double), hipMemcpyDeviceToHost, s));
+    SGMG_HIP(hipStreamSynchronize(s));
+  }
+  return 0;
+}
 
 }  // extern "C"
 

@@ -60,6 +60,9 @@ EXPORTS = [
     "sgmg_copy_stencil", "sgmg_copy_diagonal", "sgmg_destroy", "sgmg_last_error",
     "sgmg_autotune", "sgmg_setup_batch", "sgmg_pcg_solve_batch", "sgmg_batch_hierarchy",
     "sgmg_batch_block_size", "sgmg_batch_destroy",
+    "sgmg_unet_create", "sgmg_unet_num_params", "sgmg_unet_set_params", "sgmg_unet_get_params",
+    "sgmg_unet_forward", "sgmg_unet_grad", "sgmg_unet_train_step", "sgmg_unet_input",
+    "sgmg_unet_output", "sgmg_unet_target", "sgmg_warm_start_scale", "sgmg_unet_destroy",
 ]
 
 
@@ -87,6 +90,20 @@ def _load():
     lib.sgmg_batch_block_size.argtypes = [H]
     lib.sgmg_batch_destroy.argtypes = [H]
     lib.sgmg_batch_destroy.restype = None
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.sgmg_unet_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(H)]
+    lib.sgmg_unet_num_params.argtypes = []
+    lib.sgmg_unet_set_params.argtypes = [H, fp, vp]
+    lib.sgmg_unet_get_params.argtypes = [H, i, fp, vp]
+    lib.sgmg_unet_forward.argtypes = [H, i, i, i, i, vp, vp, vp]
+    lib.sgmg_unet_grad.argtypes = [H, i, i, i, i, vp, vp, vp, fp, fp, vp]
+    lib.sgmg_unet_train_step.argtypes = [H, i, i, i, i, vp, vp, vp, ctypes.c_float, fp, vp]
+    lib.sgmg_unet_input.argtypes = [H, vp, vp, i, i, i, vp, vp]
+    lib.sgmg_unet_output.argtypes = [H, vp, i, i, i, vp, vp]
+    lib.sgmg_unet_target.argtypes = [H, vp, i, i, i, vp, vp, vp]
+    lib.sgmg_warm_start_scale.argtypes = [H, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.sgmg_unet_destroy.argtypes = [H]
+    lib.sgmg_unet_destroy.restype = None
     lib.sgmg_num_levels.argtypes = [H]
     lib.sgmg_level_info.argtypes = [H, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                     ctypes.POINTER(ctypes.c_double)]
@@ -326,3 +343,104 @@ def pcg_solve_batch(batch, item_sys, f_list, u_list, rtol=1e-6, maxit=200, strea
     out = [{"status": STATUS.get(i.status, i.status), "iters": i.iters,
             "rel_res_true": i.rel_res_true, "rel_res_recur": i.rel_res_recur} for i in infos]
     return out, ms.value
+
+
+def padded_grid(opts, multiple=8):
+    """(Dp, Hp, Wp): node counts (z, y, x) rounded up to a multiple."""
+    r = lambda v: (v + multiple - 1) // multiple * multiple
+    return r(opts.nz + 1), r(opts.ny + 1), r(opts.nx + 1)
+
+
+class UNet:
+    """Owns an sgmg_unet (the warm-start network)."""
+
+    def __init__(self, seed=0):
+        self._u = ctypes.c_void_p()
+        _check(_lib.sgmg_unet_create(seed, ctypes.byref(self._u)))
+
+    def close(self):
+        if self._u:
+            _lib.sgmg_unet_destroy(self._u)
+            self._u = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def num_params():
+        return _lib.sgmg_unet_num_params()
+
+    def set_params(self, flat, stream=None):
+        import numpy as np
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        assert a.size == self.num_params()
+        _check(_lib.sgmg_unet_set_params(self._u, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                         _stream(stream)))
+
+    def get_params(self, quantized=False, stream=None):
+        import numpy as np
+        a = np.zeros(self.num_params(), dtype=np.float32)
+        _check(_lib.sgmg_unet_get_params(self._u, int(quantized),
+                                         a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream(stream)))
+        return a
+
+    def forward(self, x, stream=None):
+        N, C, D, H, W = x.shape
+        out = torch.empty((N, 3, D, H, W), dtype=torch.float32, device=x.device)
+        _check(_lib.sgmg_unet_forward(self._u, N, D, H, W, _ptr(x, torch.float32, name="in"),
+                                      _ptr(out, torch.float32, name="out"), _stream(stream)))
+        return out
+
+    def grad(self, x, t, mask=None, stream=None):
+        import numpy as np
+        N, C, D, H, W = x.shape
+        g = np.zeros(self.num_params(), dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(_lib.sgmg_unet_grad(self._u, N, D, H, W, _ptr(x, torch.float32), _ptr(t, torch.float32),
+                                   None if mask is None else _ptr(mask, torch.float32), ctypes.byref(loss),
+                                   g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream(stream)))
+        return loss.value, g
+
+    def train_step(self, x, t, mask=None, lr=1e-3, stream=None):
+        N, C, D, H, W = x.shape
+        loss = ctypes.c_float()
+        _check(_lib.sgmg_unet_train_step(self._u, N, D, H, W, _ptr(x, torch.float32),
+                                         _ptr(t, torch.float32),
+                                         None if mask is None else _ptr(mask, torch.float32), lr,
+                                         ctypes.byref(loss), _stream(stream)))
+        return loss.value
+
+
+def unet_input(h, rho, f, stream=None):
+    Dp, Hp, Wp = padded_grid(h.opts)
+    x = torch.empty((1, 5, Dp, Hp, Wp), dtype=torch.float32, device=rho.device)
+    _check(_lib.sgmg_unet_input(h.handle, _ptr(rho, torch.float64), _ptr(f, torch.float64), Dp, Hp, Wp,
+                                _ptr(x, torch.float32), _stream(stream)))
+    return x
+
+
+def unet_target(h, u, stream=None):
+    Dp, Hp, Wp = padded_grid(h.opts)
+    t = torch.empty((1, 3, Dp, Hp, Wp), dtype=torch.float32, device=u.device)
+    m = torch.empty((1, 1, Dp, Hp, Wp), dtype=torch.float32, device=u.device)
+    _check(_lib.sgmg_unet_target(h.handle, _ptr(u, torch.float64), Dp, Hp, Wp, _ptr(t, torch.float32),
+                                 _ptr(m, torch.float32), _stream(stream)))
+    return t, m
+
+
+def unet_output(h, y, stream=None):
+    Dp, Hp, Wp = padded_grid(h.opts)
+    u0 = torch.empty(h.n_dof, dtype=torch.float64, device=y.device)
+    _check(_lib.sgmg_unet_output(h.handle, _ptr(y, torch.float32), Dp, Hp, Wp, _ptr(u0, torch.float64),
+                                 _stream(stream)))
+    return u0
+
+
+def warm_start_scale(h, f, u0, stream=None):
+    a = ctypes.c_double()
+    _check(_lib.sgmg_warm_start_scale(h.handle, _ptr(f, torch.float64, h.n_dof), _ptr(u0, torch.float64, h.n_dof),
+                                      ctypes.byref(a), _stream(stream)))
+    return a.value
