@@ -166,7 +166,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"hex8 SIMP cantilever {n}x{n}x{n} ({nel} elements), rho=0.5, p=3, "
                                f"FP32-GMG-PCG, {args.levels} levels, Chebyshev deg 2, rtol 1e-6, cap 200",
-                   "fine_prec": args.fine_prec, "mfma_zchunk_bf16_bf16x3": tuned},
+                   "fine_prec": args.fine_prec, "mfma_shape_bf16_bf16x3": tuned},
         "solve_ms_std": round(float(np.std(solve_ms)), 3),
         "setup_ms": round(float(np.mean(setup_ms)), 3),
         "iters": iters, "status": status, "rel_res_true": relres,

@@ -158,15 +158,23 @@ int sgmg_vcycle(const sgmg_hierarchy* h, const double* r, double* z, void* strea
 int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u,
                    double rtol, int maxit, sgmg_solve_info* info, void* stream);
 
-/* Autotuner of the MFMA fine operator's launch shape: times each candidate
- * z-chunk (owned node planes per workgroup: 2, 4, 8, 16, 32) on this
- * hierarchy's mesh for the BF16 and BF16X3 kernels, keeps the fastest in h
- * and in a process-wide cache keyed by (nx, ny, nz, variant) that later
- * setups of the same mesh read.  zchunk_out (host, 2 ints, may be NULL)
- * receives the BF16 and BF16X3 choices.  Allocates two temporary vectors and
- * synchronises the stream.  The launch shape changes only which workgroup
- * computes a node, never the arithmetic: results are bitwise identical. */
-int sgmg_autotune(sgmg_hierarchy* h, int* zchunk_out, void* stream);
+/* Autotuner of the MFMA fine operators' launch shape: times each candidate
+ * (element rows per wave tile: 4, 8; owned node planes per wave: 2, 4, 8,
+ * 16, 32) on this hierarchy's mesh for the BF16, BF16X3 and FP64 kernels,
+ * keeps the fastest in h and in a process-wide cache keyed by (nx, ny, nz,
+ * variant) that later setups of the same mesh read.  shape_out (host, 6
+ * ints, may be NULL) receives (rows, planes) for BF16, BF16X3, then FP64;
+ * for FP64 the vector-ALU node kernel is a candidate too, reported as (0, 0)
+ * (also the FP64 choice of an untuned mesh).
+ * Allocates four temporary vectors and synchronises the stream.  The launch
+ * shape changes only which wave computes a node, never the arithmetic:
+ * results are bitwise identical. */
+int sgmg_autotune(sgmg_hierarchy* h, int* shape_out, void* stream);
+/* Pins the launch shape of one fine-operator variant (0 BF16, 1 BF16X3, 2
+ * FP64) on h, e.g. to reuse a shape tuned earlier: rows 4 or 8, planes >= 1;
+ * FP64 also accepts (0, 0), the vector-ALU node kernel.  Returns SGMG_EINVAL
+ * for other values.  No device work. */
+int sgmg_set_launch_shape(sgmg_hierarchy* h, int variant, int rows, int planes);
 
 /* Introspection for tests and reports. */
 int sgmg_num_levels(const sgmg_hierarchy* h);

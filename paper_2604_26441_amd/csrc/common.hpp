@@ -189,6 +189,43 @@ __device__ inline double epilogue3_pre(const Epi<T>& ep, int node, unsigned fx, 
   return dot;
 }
 
+// The same epilogue for one component c of a node (thread per DOF kernels).
+template <typename T>
+__device__ inline double epilogue1(const Epi<T>& ep, size_t dof, bool fixed, T x, double y) {
+  if (ep.mode == EPI_STORE) {
+    const double v = fixed ? 0.0 : y;
+    ep.out[dof] = (T)v;
+    return (double)x * v;
+  }
+  if (ep.mode == EPI_RESID) {
+    ep.out[dof] = fixed ? (T)0 : (T)((double)ep.b[dof] - y);
+    return 0.0;
+  }
+  T xo = (T)0, dd = (T)0;
+  if (!fixed) {
+    const T r = (T)((double)ep.b[dof] - y);
+    const T dp = ep.c1 != 0.0 ? ep.d[dof] : (T)0;
+    dd = (T)ep.c1 * dp + (T)ep.c2 * ep.dinv[dof] * r;
+    xo = x + dd;
+  }
+  if (ep.store_d) ep.d[dof] = dd;
+  ep.out[dof] = xo;
+  if (ep.out64) ep.out64[dof] = (double)xo;
+  return 0.0;
+}
+
+// Workgroups of a 1D launch are dispatched round-robin over the 8 XCDs of
+// the chip, each with its own L2.  Remapping the block index so that XCD x
+// receives one contiguous range of logical blocks keeps neighbouring node
+// planes (read by stencil-type kernels) in the same L2.  A bijection of
+// [0, nblk) for any nblk.
+constexpr int kNumXcd = 8;
+__device__ inline int xcd_block(int b, int nblk) {
+  const int xcd = b % kNumXcd, idx = b / kNumXcd;
+  const int per = nblk / kNumXcd, rem = nblk % kNumXcd;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
 // ----------------------------------------------------------------------------
 // Element stiffness tables computed on the host at setup.
 struct KeTables {

@@ -17,11 +17,21 @@ template <typename T>
 void launch_apply_fine_node(const Grid& g, const T* E, const T* ke, const T* u,
                             const uint8_t* fixn, const Epi<T>& ep, hipStream_t s);
 // BF16 MFMA element kernel (kernels_mfma.hip); nsplit = 1 (BF16) or 3 (BF16X3);
-// zchunk = owned node planes per workgroup (tuned per mesh).
-void launch_apply_fine_mfma(const Grid& g, int nsplit, int zchunk, const float* Escaled,
+// Launch shape (tuned per mesh): rows = element rows per wave tile (4 or 8),
+// zchunk = owned node planes per wave.
+void launch_apply_fine_mfma(const Grid& g, int nsplit, int rows, int zchunk, const float* Escaled,
                             const void* atab, const float* u, const uint8_t* fixn,
                             const Epi<float>& ep, hipStream_t s);
-size_t apply_fine_mfma_blocks(const Grid& g, int zchunk);
+size_t apply_fine_mfma_blocks(const Grid& g, int rows, int zchunk);
+bool mfma_shape_valid(int rows, int zchunk);
+// The MFMA kernel addresses vectors with 32-bit byte offsets (< 2^31).
+bool mfma_size_ok(const Grid& g);
+// FP64 fine operator on the FP64 MFMA (same launch shapes).
+void launch_apply_fine_mfma64(const Grid& g, int rows, int zchunk, const double* E,
+                              const double* atab64, const double* u, const uint8_t* fixn,
+                              const Epi<double>& ep, hipStream_t s);
+bool mfma64_size_ok(const Grid& g);
+void build_mfma_atab64(const KeTables& kt, double* out /* 2 * 6 * 64 */);
 void launch_scale_E(const double* E, float* Es, int nel, double inv_s, hipStream_t s);
 void build_mfma_atab(const KeTables& kt, uint16_t* out /* 2 * 64 * 8 */);
 

@@ -204,23 +204,35 @@ __global__ void k_dense_gather(const double* __restrict__ r, const int* __restri
   if (i < nf) rc[i] = r[free_idx[i]];
 }
 
+// One wave per row of the explicit inverse (4 rows per block): each lane
+// streams the row with stride 64 and four independent partial sums, then a
+// fixed-order wave reduction.  No block barrier (a wave past the last row
+// simply exits).
 __global__ __launch_bounds__(256) void k_dense_gemv(const double* __restrict__ Ainv,
                                                     const double* __restrict__ rc,
                                                     const int* __restrict__ free_idx, int nf,
                                                     double* __restrict__ z) {
-  __shared__ double lds[16];
-  const int i = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= nf) return;
   const double* row = Ainv + (size_t)i * nf;
-  double s = 0.0;
-  for (int j = threadIdx.x; j < nf; j += 256) s += row[j] * rc[j];
-  s = block_sum(s, lds);
-  if (threadIdx.x == 0) z[free_idx[i]] = s;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int j = lane;
+  for (; j + 192 < nf; j += 256) {
+    s0 += row[j] * rc[j];
+    s1 += row[j + 64] * rc[j + 64];
+    s2 += row[j + 128] * rc[j + 128];
+    s3 += row[j + 192] * rc[j + 192];
+  }
+  for (; j < nf; j += 64) s0 += row[j] * rc[j];
+  const double s = wave_sum((s0 + s1) + (s2 + s3));
+  if (lane == 0) z[free_idx[i]] = s;
 }
 
 void launch_dense_solve(const double* Ainv, const int* free_idx, int nf, const double* r,
                         double* rc, double* z, hipStream_t s) {
   k_dense_gather<<<div_up(nf, 256), 256, 0, s>>>(r, free_idx, nf, rc);
-  k_dense_gemv<<<nf, 256, 0, s>>>(Ainv, rc, free_idx, nf, z);
+  k_dense_gemv<<<div_up(nf, 4), 256, 0, s>>>(Ainv, rc, free_idx, nf, z);
 }
 
 }  // namespace sgmg

@@ -5,20 +5,29 @@
 // FP32 significand (NSPLIT = 3).  Products are exact and accumulate in FP32 on
 // v_mfma_f32_16x16x32_bf16; E_e / s is applied in FP32 afterwards.
 //
-// Work decomposition (one workgroup = WAVES waves):
-//   * a wave owns one element row (fixed ey) of a 16-element x-batch and
-//     marches along z; the MFMA output rows are laid out as
-//     [dz (M half)] x [dx + 2 dy (lane group)] x [component], so the dz = 1
-//     half of plane ez and the dz = 0 half of plane ez+1 meet in the same
-//     lane: z-neighbour sums are a register carry;
-//   * x-neighbours (dx = 1 of element n, dx = 0 of element n+1) are combined
-//     with one ds_bpermute;
-//   * y-neighbours (dy = 1 of row ey, dy = 0 of row ey+1) are combined in LDS
-//     in two fixed-order sub-steps (first every wave's dy = 0 writes, then the
-//     dy = 1 adds): a colored, atomic-free, deterministic scatter.
-//   The workgroup recomputes one halo element on the low side in x and y so
-//   that every node it writes is complete: 15 owned nodes per 16-element
-//   batch in x, WAVES-1 owned node rows in y.
+// Work decomposition: one wave owns a tile of 16 elements in x (the MFMA's
+// N dimension, one element per lane column) by YC element rows in y, and
+// marches along z over a chunk of node planes.  Nothing is shared between
+// waves: there is no LDS traffic and no barrier in the main loop.
+//   * MFMA h = 0 produces the rows of the element's dy = 0 nodes, h = 1 those
+//     of its dy = 1 nodes.  In both, lane group g = dx + 2 dz of column n
+//     holds the 3 components (row 4g + c, c = 3 is padding) of node
+//     (dx, dy, dz) of element n.
+//   * y: the dy = 1 rows of element row ey and the dy = 0 rows of row ey + 1
+//     sit in the same lanes: an in-register carry from row to row.
+//   * x: dx = 1 of element n - 1 meets dx = 0 of element n after one
+//     v_permlane16_swap (group 1 -> 0, 3 -> 2) and a DPP row shift by one
+//     lane fused into the add.
+//   * z: dz = 1 of plane ez meets dz = 0 of plane ez + 1 after one
+//     v_permlane32_swap (groups 2, 3 -> 0, 1) and a per-row carry across
+//     planes.
+//   After the three steps the 16 lanes of group 0 hold complete nodes.  A
+//   wave recomputes one halo element on the low side of each axis so that
+//   every node it writes is complete (15 owned nodes in x, YC - 1 node rows,
+//   all planes of its chunk).  Every node sums its 8 element contributions in
+//   the same order whatever the tile shape: results are bitwise independent
+//   of the launch shape.
+#include <climits>
 #include <cstring>
 
 #include "kernels.hpp"
@@ -28,29 +37,164 @@ namespace sgmg {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMfmaWaves = 4;   // waves per workgroup (owned node rows + 1)
+constexpr int kMfmaWavesPerBlock = 4;
 
 // A operand table: [h][lane][8] BF16 bit patterns, built on the host.
-// Row m = lane % 16 = 4 * (dx + 2 dy) + c of output node (dx, dy, dz = h);
-// slot j of lane group g = lane / 16 is input node (j / 3, g & 1, g >> 1),
-// component j % 3 (slots 6, 7 and c = 3 are zero padding).
+// Row m = lane % 16 = 4 (dx + 2 dz) + c of output node (dx, h, dz); slot j of
+// lane group q = lane / 16 is input node (j / 3, q & 1, q >> 1), component
+// j % 3 (slots 6, 7 and c = 3 are zero padding).
 
-template <int NSPLIT, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_apply_fine_mfma(
+// x-combination for lane groups 0 and 2: v + (v of group 1 / 3, one lane to
+// the left).  v_permlane16_swap(v, v) leaves v in the even rows of its first
+// result and moves the odd rows into the even rows of its second.
+__device__ inline float x_combine(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false,
+                                                  false);
+  return __uint_as_float(r[0]) +
+         __int_as_float(__builtin_amdgcn_update_dpp(0, (int)r[1], 0x111, 0xf, 0xf, true));
+}
+// z-split: lo = v (valid in lanes 0..31), hi = lanes 32..63 of v moved to 0..31.
+__device__ inline void z_split(float v, float& lo, float& hi) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false,
+                                                  false);
+  lo = __uint_as_float(r[0]);
+  hi = __uint_as_float(r[1]);
+}
+__device__ inline double x_combine(double v) {
+  const int h = __double2hiint(v), l = __double2loint(v);
+  const auto rh = __builtin_amdgcn_permlane16_swap((unsigned)h, (unsigned)h, false, false);
+  const auto rl = __builtin_amdgcn_permlane16_swap((unsigned)l, (unsigned)l, false, false);
+  const int sh = __builtin_amdgcn_update_dpp(0, (int)rh[1], 0x111, 0xf, 0xf, true);
+  const int sl = __builtin_amdgcn_update_dpp(0, (int)rl[1], 0x111, 0xf, 0xf, true);
+  return __hiloint2double((int)rh[0], (int)rl[0]) + __hiloint2double(sh, sl);
+}
+__device__ inline void z_split(double v, double& lo, double& hi) {
+  const int h = __double2hiint(v), l = __double2loint(v);
+  const auto rh = __builtin_amdgcn_permlane32_swap((unsigned)h, (unsigned)h, false, false);
+  const auto rl = __builtin_amdgcn_permlane32_swap((unsigned)l, (unsigned)l, false, false);
+  lo = __hiloint2double((int)rh[0], (int)rl[0]);
+  hi = __hiloint2double((int)rh[1], (int)rl[1]);
+}
+
+__device__ inline int ep_node(const Grid& g, int x, int y, int z) { return x + g.Nx * (y + g.Ny * z); }
+
+// Epilogue operands of one owned node, fetched a step ahead of their use.
+template <typename T>
+struct EpIn { T x[3], b[3], di[3], dp[3]; unsigned fx; };
+
+// Raw buffer loads: an offset past the buffer's byte size returns zeros, so
+// halo and out-of-mesh operands need no branch (straight-line code keeps the
+// compiler's load-counter waits exact across the software pipeline).  Offsets
+// are 32-bit: the launcher rejects vectors of 2^31 bytes or more, and
+// kNoOffset (2^31) is past every buffer.
+constexpr int kNoOffset = INT_MIN;
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline float bload(__amdgpu_buffer_rsrc_t r, int off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ inline void bload3(__amdgpu_buffer_rsrc_t r, int off, float* v) {
+  const auto t = __builtin_amdgcn_raw_buffer_load_b96(r, off, 0, 0);
+  // (__builtin_bit_cast on an element of the returned vector loses elements)
+  v[0] = __uint_as_float(t[0]);
+  v[1] = __uint_as_float(t[1]);
+  v[2] = __uint_as_float(t[2]);
+}
+
+__device__ inline void bload3(__amdgpu_buffer_rsrc_t r, int off, double* v) {
+  const auto t = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+  const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off == kNoOffset ? kNoOffset : off + 16, 0, 0);
+  v[0] = __hiloint2double((int)t[1], (int)t[0]);
+  v[1] = __hiloint2double((int)t[3], (int)t[2]);
+  v[2] = __hiloint2double((int)w[1], (int)w[0]);
+}
+
+// Kernel-internal epilogue variant: EPI_STORE plus the x.y dot product.
+constexpr int kStoreDot = 3;
+
+struct EpRsrc { __amdgpu_buffer_rsrc_t u, fix, b, di, d, out; };
+
+// off3 = byte offset of the node's 3 components (kNoOffset: not owned)
+template <typename T, int MODE>
+__device__ inline void load_ep(const Epi<T>& ep, const EpRsrc& rs, int node, int off3,
+                               EpIn<T>& e) {
+  e.fx = __builtin_amdgcn_raw_buffer_load_b8(rs.fix, off3 == kNoOffset ? kNoOffset : node, 0, 0);
+  if (MODE == kStoreDot) bload3(rs.u, off3, e.x);
+  if (MODE == EPI_SMOOTH) bload3(rs.u, off3, e.x);
+  if (MODE == EPI_RESID || MODE == EPI_SMOOTH) bload3(rs.b, off3, e.b);
+  if (MODE == EPI_SMOOTH) {
+    bload3(rs.di, off3, e.di);
+    bload3(rs.d, ep.c1 != 0.0 ? off3 : kNoOffset, e.dp);
+  }
+}
+
+__device__ inline void bstore3(__amdgpu_buffer_rsrc_t r, int off, float a, float b, float c) {
+  typedef unsigned u32x3 __attribute__((ext_vector_type(3)));
+  const u32x3 v = {__float_as_uint(a), __float_as_uint(b), __float_as_uint(c)};
+  __builtin_amdgcn_raw_buffer_store_b96(v, r, off, 0, 0);
+}
+
+__device__ inline void bstore3(__amdgpu_buffer_rsrc_t r, int off, double a, double b, double c) {
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+  const u32x4 v = {(unsigned)__double2loint(a), (unsigned)__double2hiint(a),
+                   (unsigned)__double2loint(b), (unsigned)__double2hiint(b)};
+  const u32x2 w = {(unsigned)__double2loint(c), (unsigned)__double2hiint(c)};
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(w, r, off == kNoOffset ? kNoOffset : off + 16, 0, 0);
+}
+
+// Same arithmetic as the generic epilogue, specialised.  off3
+// = kNoOffset makes the stores fall outside the buffers (dropped) and the
+// returned dot term zero.
+template <typename T, int MODE>
+__device__ inline double store_ep(const Epi<T>& ep, const EpRsrc& rs, int off3, const EpIn<T>& e,
+                                  const T (&y)[3]) {
+  double dot = 0.0;
+  T o[3], dd[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const bool fixed = (e.fx >> c) & 1u;
+    if (MODE == EPI_STORE || MODE == kStoreDot) {
+      o[c] = fixed ? (T)0 : y[c];
+      if (MODE == kStoreDot) dot += (double)e.x[c] * (double)o[c];
+    } else if (MODE == EPI_RESID) {
+      o[c] = fixed ? (T)0 : e.b[c] - y[c];
+    } else {
+      const T r = e.b[c] - y[c];
+      dd[c] = fixed ? (T)0 : (T)ep.c1 * e.dp[c] + (T)ep.c2 * e.di[c] * r;
+      o[c] = fixed ? (T)0 : e.x[c] + dd[c];
+    }
+  }
+  bstore3(rs.out, off3, o[0], o[1], o[2]);
+  if (MODE == EPI_SMOOTH) {
+    if (ep.store_d) bstore3(rs.d, off3, dd[0], dd[1], dd[2]);
+    if (ep.out64 && off3 != kNoOffset) {
+      const size_t b3 = (size_t)(off3 / (int)sizeof(T));
+      ep.out64[b3] = (double)o[0];
+      ep.out64[b3 + 1] = (double)o[1];
+      ep.out64[b3 + 2] = (double)o[2];
+    }
+  }
+  return off3 == kNoOffset ? 0.0 : dot;
+}
+
+template <int NSPLIT, int YC, int MODE>
+__global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
     Grid g, const float* __restrict__ Es, const uint16_t* __restrict__ atab,
-    const float* __restrict__ u, const uint8_t* __restrict__ fixn, Epi<float> ep, int zchunk) {
-  __shared__ float plane[WAVES + 1][16][3];
+    const float* __restrict__ u, const uint8_t* __restrict__ fixn, Epi<float> ep, int zchunk,
+    int ntx, int nty, int ntiles) {
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
-  const int grp = lane >> 4;          // input edge (dy_in, dz_in) / output (dx, dy)
-  const int n = lane & 15;            // element position in the x-batch
-  const int xs = blockIdx.x * 15;     // first owned node in x
-  const int ys = blockIdx.y * (WAVES - 1);
-  const int zs = blockIdx.z * zchunk;
+  // wave index made wave-uniform, so all tile arithmetic stays scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tile = xcd_block(blockIdx.x, gridDim.x) * kMfmaWavesPerBlock + wave;
+  const int tx = tile % ntx, tt = tile / ntx, ty = tt % nty, tz = tt / nty;
+  const int grp = lane >> 4, n = lane & 15;
+  const int xs = tx * 15, ys = ty * (YC - 1), zs = tz * zchunk;
   const int ex = xs - 1 + n;
-  const int ey = ys - 1 + w;
-  const bool exy_ok = ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny;
   const int dy_in = grp & 1, dz_in = grp >> 1;
+  const bool x_ok = ex >= 0 && ex < g.nx;
 
   bf16x8 a0, a1;
   {
@@ -63,21 +207,28 @@ __global__ __launch_bounds__(64 * WAVES) void k_apply_fine_mfma(
     }
   }
 
-  // raw operands of element plane ez (6 input values, E / s)
   struct In { float v[6]; float es; };
-  auto load_in = [&](int ez, In& in) {
-    const bool ok = exy_ok && ez >= 0 && ez < g.nz;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) in.v[j] = 0.f;
-    in.es = 0.f;
-    if (ok) {
-      const size_t base = 3 * (size_t)(ex + g.Nx * ((ey + dy_in) + g.Ny * (ez + dz_in)));
-#pragma unroll
-      for (int j = 0; j < 6; ++j) in.v[j] = u[base + j];
-      in.es = Es[ex + g.nx * (ey + g.ny * ez)];
-    }
+  const int zend = tile < ntiles ? min(zs + zchunk, g.Nz) : zs - 1;
+  // inputs of element (ex, ey, ez) for this lane's node pair; zero outside
+  const size_t nvec = (size_t)g.n * sizeof(float);
+  const __amdgpu_buffer_rsrc_t ru = make_rsrc(u, nvec);
+  const __amdgpu_buffer_rsrc_t re = make_rsrc(Es, (size_t)g.nel * sizeof(float));
+  EpRsrc rs;
+  rs.u = ru;
+  rs.fix = make_rsrc(fixn, (size_t)g.Nn);
+  rs.b = make_rsrc(ep.b, MODE == EPI_RESID || MODE == EPI_SMOOTH ? nvec : 0);
+  rs.di = make_rsrc(ep.dinv, MODE == EPI_SMOOTH ? nvec : 0);
+  rs.d = make_rsrc(ep.d, MODE == EPI_SMOOTH ? nvec : 0);
+  rs.out = make_rsrc(ep.out, nvec);
+  // inputs of element (ex, ey, ez) for this lane's node pair; zero outside
+  auto load_in = [&](int ey, int ez, In& in) {
+    const bool ok = x_ok && ey >= 0 && ey < g.ny && ez >= 0 && ez < g.nz && ez < zend;
+    const int node = ex + g.Nx * ((ey + dy_in) + g.Ny * (ez + dz_in));
+    const int off = ok ? node * 12 : kNoOffset;
+    bload3(ru, off, in.v);
+    bload3(ru, ok ? off + 12 : kNoOffset, in.v + 3);
+    in.es = bload(re, ok ? 4 * (ex + g.nx * (ey + g.ny * ez)) : kNoOffset);
   };
-  // contraction: acc for node plane ez (c0) and ez+1 (c1), scaled by E / s
   auto contract = [&](const In& in, f32x4& c0, f32x4& c1) {
     c0 = f32x4{0.f, 0.f, 0.f, 0.f};
     c1 = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -102,114 +253,310 @@ __global__ __launch_bounds__(64 * WAVES) void k_apply_fine_mfma(
       c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b[sp], c0, 0, 0, 0);
       c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[sp], c1, 0, 0, 0);
     }
-    // column n of the result (lane % 16) is element n, whose E / s every lane
-    // of that column loaded itself
-    c0 *= in.es;
+    c0 *= in.es;   // column n is element n, whose E / s every lane of it loaded
     c1 *= in.es;
   };
 
-  // the epilogue node of this thread (rows 1..WAVES-1, positions 1..15)
-  const int t = threadIdx.x;
-  const int er = 1 + t / 15, eq = 1 + t % 15;
-  const int enx = xs - 1 + eq, eny = ys - 1 + er;
-  const bool e_own = t < 15 * (WAVES - 1) && enx < g.Nx && eny < g.Ny;
-  const bool need_b = ep.mode != EPI_STORE;
-  const bool need_sm = ep.mode == EPI_SMOOTH;
-  const bool need_d = need_sm && ep.c1 != 0.0;
+  // node (ex, ys - 1 + r, ez) is written by this lane
+  const bool ep_lane = grp == 0 && n >= 1 && ex < g.Nx;
+  auto owns = [&](int r, int ez) {
+    return r >= 1 && ep_lane && ez >= zs && ez < zend && ys - 1 + r < g.Ny;
+  };
 
-  In cur, nxt;
-  f32x4 carry, dummy;
-  load_in(zs - 1, cur);
-  load_in(zs, nxt);
-  contract(cur, dummy, carry);   // prologue: dz = 1 half of the plane below
+  float zc[YC][3];
+#pragma unroll
+  for (int r = 0; r < YC; ++r) zc[r][0] = zc[r][1] = zc[r][2] = 0.f;
   double dot = 0.0;
-  const int dx = grp & 1, dyo = grp >> 1;
-  const int src = ((grp | 1) << 4) + ((n + 15) & 15);   // lane of (dx = 1, same dy, n - 1)
-  const int zend = min(zs + zchunk, g.Nz);
-  for (int ez = zs; ez < zend; ++ez) {
-    cur = nxt;
-    if (ez + 1 < zend) load_in(ez + 1, nxt);           // prefetch the next plane
-    // prefetch the epilogue operands of this plane
-    float ex_[3] = {0.f, 0.f, 0.f}, eb[3] = {0.f, 0.f, 0.f}, edi[3] = {0.f, 0.f, 0.f},
-          edp[3] = {0.f, 0.f, 0.f};
-    unsigned efx = 7u;
-    int node = 0;
-    if (e_own) {
-      node = enx + g.Nx * (eny + g.Ny * ez);
-      const size_t b3 = 3 * (size_t)node;
-      efx = fixn[node];
+  // Software pipeline over the (plane, row) steps, in rings of 4 slots
+  // indexed by row % 4 (YC is a multiple of 4, so slot indices are
+  // compile-time): element inputs are loaded 3 steps ahead of their use,
+  // epilogue operands 2 steps ahead.
+  In p[4];
+  EpIn<float> e[4];
+  auto fetch_in = [&](int r, int ez) {          // step (ez, r + 3)
+    const int rr = r + 3 < YC ? r + 3 : r + 3 - YC;
+    load_in(ys - 1 + rr, r + 3 < YC ? ez : ez + 1, p[(r + 3) & 3]);
+  };
+  auto fetch_ep = [&](int r, int ez) {          // step (ez, r + 2)
+    const int rr = r + 2 < YC ? r + 2 : r + 2 - YC;
+    const int zz = r + 2 < YC ? ez : ez + 1;
+    const int nd = ep_node(g, ex, ys - 1 + rr, zz);
+    load_ep<float, MODE>(ep, rs, nd, owns(rr, zz) ? 12 * nd : kNoOffset, e[(r + 2) & 3]);
+  };
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ex_[c] = u[b3 + c];
-      if (need_b) {
+  for (int r = 0; r < 3; ++r) load_in(ys - 1 + r, zs - 1, p[r]);
+  e[0].fx = e[1].fx = 7u;                       // plane zs - 1 owns no node
+  for (int ez = zs - 1; ez < zend; ++ez) {
+    float yc[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int c = 0; c < 3; ++c) eb[c] = ep.b[b3 + c];
+    for (int r = 0; r < YC; ++r) {
+      fetch_in(r, ez);
+      fetch_ep(r, ez);
+      f32x4 v0, v1;
+      contract(p[r & 3], v0, v1);
+      float yv[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        yv[c] = v0[c] + yc[c];     // y: dy = 0 of this row + dy = 1 of the row below
+        yc[c] = v1[c];
       }
-      if (need_sm) {
+      if (r >= 1) {
+        float fin[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) edi[c] = ep.dinv[b3 + c];
+        for (int c = 0; c < 3; ++c) {
+          float lo, hi;
+          z_split(x_combine(yv[c]), lo, hi);      // x, then z: plane ez + plane ez - 1
+          fin[c] = lo + zc[r][c];
+          zc[r][c] = hi;
+        }
+        const int nd = ep_node(g, ex, ys - 1 + r, ez);
+        dot += store_ep<float, MODE>(ep, rs, owns(r, ez) ? 12 * nd : kNoOffset, e[r & 3], fin);
       }
-      if (need_d) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) edp[c] = ep.d[b3 + c];
-      }
     }
-    f32x4 c0, c1;
-    contract(cur, c0, c1);
-    const float v0 = c0[0] + carry[0], v1 = c0[1] + carry[1], v2 = c0[2] + carry[2];
-    carry = c1;
-    // x: node (xs - 1 + n) gets dx = 0 of element n and dx = 1 of element n - 1
-    const float p0 = __int_as_float(__builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(v0)));
-    const float p1 = __int_as_float(__builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(v1)));
-    const float p2 = __int_as_float(__builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(v2)));
-    // y: two colored sub-steps in LDS (rows are ey + dy - (ys - 1))
-    if (dx == 0 && dyo == 0) {
-      plane[w][n][0] = v0 + p0;
-      plane[w][n][1] = v1 + p1;
-      plane[w][n][2] = v2 + p2;
-    }
-    __syncthreads();
-    if (dx == 0 && dyo == 1) {
-      plane[w + 1][n][0] += v0 + p0;
-      plane[w + 1][n][1] += v1 + p1;
-      plane[w + 1][n][2] += v2 + p2;
-    }
-    __syncthreads();
-    if (e_own) {
-      const double y[3] = {(double)plane[er][eq][0], (double)plane[er][eq][1],
-                           (double)plane[er][eq][2]};
-      dot += epilogue3_pre(ep, node, efx, ex_, y, eb, edi, edp);
-    }
-    __syncthreads();
   }
-  if (ep.want_dot) {
+  if (MODE == kStoreDot) {
     const double vv[1] = {dot};
     grid_sum<1>(vv, ep.ws);
   }
 }
 
-static dim3 mfma_grid(const Grid& g, int zchunk) {
-  return dim3(div_up(g.Nx, 15), div_up(g.Ny, kMfmaWaves - 1), div_up(g.Nz, zchunk));
+// ---------------------------------------------------------------------------
+// FP64 fine operator on v_mfma_f64_16x16x4_f64 (outer PCG products, FP64
+// smoothing), same tiles, carries and ownership as the BF16 kernel.  K = 24
+// inputs take six k-steps of 4: at step s, lane group q supplies value s of
+// its node pair, so A holds K_e[row m][input (q, s)] per (h, s).  With the
+// row order of the A table (build_mfma_atab64), lane group g holds node g's
+// components in registers 0..2 as in the FP32 kernel, so the x/y/z
+// combination is the same.  Exact products, FP64 accumulation.
+template <int YC, int MODE>
+__global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma64(
+    Grid g, const double* __restrict__ E, const double* __restrict__ atab,
+    const double* __restrict__ u, const uint8_t* __restrict__ fixn, Epi<double> ep, int zchunk,
+    int ntx, int nty, int ntiles) {
+  typedef double f64x4 __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63;
+  // wave index made wave-uniform, so all tile arithmetic stays scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tile = xcd_block(blockIdx.x, gridDim.x) * kMfmaWavesPerBlock + wave;
+  const int tx = tile % ntx, tt = tile / ntx, ty = tt % nty, tz = tt / nty;
+  const int grp = lane >> 4, n = lane & 15;
+  const int xs = tx * 15, ys = ty * (YC - 1), zs = tz * zchunk;
+  const int ex = xs - 1 + n;
+  const int dy_in = grp & 1, dz_in = grp >> 1;
+  const bool x_ok = ex >= 0 && ex < g.nx;
+
+  double a0[6], a1[6];
+#pragma unroll
+  for (int st = 0; st < 6; ++st) {
+    a0[st] = atab[st * 64 + lane];
+    a1[st] = atab[(6 + st) * 64 + lane];
+  }
+
+  struct In { double v[6]; double es; };
+  const int zend = tile < ntiles ? min(zs + zchunk, g.Nz) : zs - 1;
+  const size_t nvec = (size_t)g.n * sizeof(double);
+  const __amdgpu_buffer_rsrc_t ru = make_rsrc(u, nvec);
+  const __amdgpu_buffer_rsrc_t re = make_rsrc(E, (size_t)g.nel * sizeof(double));
+  EpRsrc rs;
+  rs.u = ru;
+  rs.fix = make_rsrc(fixn, (size_t)g.Nn);
+  rs.b = make_rsrc(ep.b, MODE == EPI_RESID || MODE == EPI_SMOOTH ? nvec : 0);
+  rs.di = make_rsrc(ep.dinv, MODE == EPI_SMOOTH ? nvec : 0);
+  rs.d = make_rsrc(ep.d, MODE == EPI_SMOOTH ? nvec : 0);
+  rs.out = make_rsrc(ep.out, nvec);
+  auto load_in = [&](int ey, int ez, In& in) {
+    const bool ok = x_ok && ey >= 0 && ey < g.ny && ez >= 0 && ez < g.nz && ez < zend;
+    const int node = ex + g.Nx * ((ey + dy_in) + g.Ny * (ez + dz_in));
+    const int off = ok ? node * 24 : kNoOffset;
+    bload3(ru, off, in.v);
+    bload3(ru, ok ? off + 24 : kNoOffset, in.v + 3);
+    const auto t = __builtin_amdgcn_raw_buffer_load_b64(
+        re, ok ? 8 * (ex + g.nx * (ey + g.ny * ez)) : kNoOffset, 0, 0);
+    in.es = __hiloint2double((int)t[1], (int)t[0]);
+  };
+  auto contract = [&](const In& in, f64x4& c0, f64x4& c1) {
+    c0 = f64x4{0.0, 0.0, 0.0, 0.0};
+    c1 = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[st], in.v[st], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[st], in.v[st], c1, 0, 0, 0);
+    }
+    c0 *= in.es;
+    c1 *= in.es;
+  };
+  const bool ep_lane = grp == 0 && n >= 1 && ex < g.Nx;
+  auto owns = [&](int r, int ez) {
+    return r >= 1 && ep_lane && ez >= zs && ez < zend && ys - 1 + r < g.Ny;
+  };
+
+  double zc[YC][3];
+#pragma unroll
+  for (int r = 0; r < YC; ++r) zc[r][0] = zc[r][1] = zc[r][2] = 0.0;
+  double dot = 0.0;
+  // inputs 2 steps ahead, epilogue operands 2 steps ahead (rings of 4 slots)
+  In p[4];
+  EpIn<double> e[4];
+  auto fetch_in = [&](int r, int ez) {
+    const int rr = r + 2 < YC ? r + 2 : r + 2 - YC;
+    load_in(ys - 1 + rr, r + 2 < YC ? ez : ez + 1, p[(r + 2) & 3]);
+  };
+  auto fetch_ep = [&](int r, int ez) {
+    const int rr = r + 2 < YC ? r + 2 : r + 2 - YC;
+    const int zz = r + 2 < YC ? ez : ez + 1;
+    const int nd = ep_node(g, ex, ys - 1 + rr, zz);
+    load_ep<double, MODE>(ep, rs, nd, owns(rr, zz) ? 24 * nd : kNoOffset, e[(r + 2) & 3]);
+  };
+  load_in(ys - 1, zs - 1, p[0]);
+  load_in(ys, zs - 1, p[1]);
+  e[0].fx = e[1].fx = 7u;
+  for (int ez = zs - 1; ez < zend; ++ez) {
+    double yc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < YC; ++r) {
+      fetch_in(r, ez);
+      fetch_ep(r, ez);
+      f64x4 v0, v1;
+      contract(p[r & 3], v0, v1);
+      double yv[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        yv[c] = v0[c] + yc[c];
+        yc[c] = v1[c];
+      }
+      if (r >= 1) {
+        double fin[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          double lo, hi;
+          z_split(x_combine(yv[c]), lo, hi);
+          fin[c] = lo + zc[r][c];
+          zc[r][c] = hi;
+        }
+        const int nd = ep_node(g, ex, ys - 1 + r, ez);
+        dot += store_ep<double, MODE>(ep, rs, owns(r, ez) ? 24 * nd : kNoOffset, e[r & 3], fin);
+      }
+    }
+  }
+  if (MODE == kStoreDot) {
+    const double vv[1] = {dot};
+    grid_sum<1>(vv, ep.ws);
+  }
 }
 
-size_t apply_fine_mfma_blocks(const Grid& g, int zchunk) {
-  const dim3 d = mfma_grid(g, zchunk);
-  return (size_t)d.x * d.y * d.z;
+namespace {
+struct MfmaLaunch { int ntx, nty, ntz, ntiles, blocks; };
+MfmaLaunch mfma_launch(const Grid& g, int rows, int zchunk) {
+  MfmaLaunch m;
+  m.ntx = div_up(g.Nx, 15);
+  m.nty = div_up(g.Ny, rows - 1);
+  m.ntz = div_up(g.Nz, zchunk);
+  m.ntiles = m.ntx * m.nty * m.ntz;
+  m.blocks = div_up(m.ntiles, kMfmaWavesPerBlock);
+  return m;
+}
+}  // namespace
+
+bool mfma_size_ok(const Grid& g) {
+  return (size_t)g.n * sizeof(float) < ((size_t)1 << 31) - 64;
 }
 
-void launch_apply_fine_mfma(const Grid& g, int nsplit, int zchunk, const float* Escaled,
+bool mfma_shape_valid(int rows, int zchunk) {
+  return (rows == 4 || rows == 8) && zchunk >= 1;
+}
+
+size_t apply_fine_mfma_blocks(const Grid& g, int rows, int zchunk) {
+  return (size_t)mfma_launch(g, rows, zchunk).blocks;
+}
+
+template <int NSPLIT, int YC>
+static void launch_shape(const Grid& g, const MfmaLaunch& m, int zchunk, const float* Es,
+                         const uint16_t* at, const float* u, const uint8_t* fixn,
+                         const Epi<float>& ep, hipStream_t s) {
+  const dim3 grid(m.blocks), block(64 * kMfmaWavesPerBlock);
+  if (ep.mode == EPI_STORE && ep.want_dot)
+    k_apply_fine_mfma<NSPLIT, YC, kStoreDot><<<grid, block, 0, s>>>(g, Es, at, u, fixn, ep, zchunk,
+                                                                   m.ntx, m.nty, m.ntiles);
+  else if (ep.mode == EPI_STORE)
+    k_apply_fine_mfma<NSPLIT, YC, EPI_STORE><<<grid, block, 0, s>>>(g, Es, at, u, fixn, ep, zchunk,
+                                                                   m.ntx, m.nty, m.ntiles);
+  else if (ep.mode == EPI_RESID)
+    k_apply_fine_mfma<NSPLIT, YC, EPI_RESID><<<grid, block, 0, s>>>(g, Es, at, u, fixn, ep, zchunk,
+                                                                   m.ntx, m.nty, m.ntiles);
+  else
+    k_apply_fine_mfma<NSPLIT, YC, EPI_SMOOTH><<<grid, block, 0, s>>>(
+        g, Es, at, u, fixn, ep, zchunk, m.ntx, m.nty, m.ntiles);
+}
+
+void launch_apply_fine_mfma(const Grid& g, int nsplit, int rows, int zchunk, const float* Escaled,
                             const void* atab, const float* u, const uint8_t* fixn,
                             const Epi<float>& ep, hipStream_t s) {
   if (zchunk < 1) zchunk = 1;
-  const int g_zchunk = zchunk;
-  const dim3 grid = mfma_grid(g, zchunk);
-  const dim3 block(64 * kMfmaWaves);
+  if (rows != 4) rows = 8;
+  const MfmaLaunch m = mfma_launch(g, rows, zchunk);
   const uint16_t* at = (const uint16_t*)atab;
-  if (nsplit == 3)
-    k_apply_fine_mfma<3, kMfmaWaves><<<grid, block, 0, s>>>(g, Escaled, at, u, fixn, ep, g_zchunk);
+  if (nsplit == 3) {
+    if (rows == 4) launch_shape<3, 4>(g, m, zchunk, Escaled, at, u, fixn, ep, s);
+    else launch_shape<3, 8>(g, m, zchunk, Escaled, at, u, fixn, ep, s);
+  } else {
+    if (rows == 4) launch_shape<1, 4>(g, m, zchunk, Escaled, at, u, fixn, ep, s);
+    else launch_shape<1, 8>(g, m, zchunk, Escaled, at, u, fixn, ep, s);
+  }
+  if (ep.mode == EPI_STORE && ep.want_dot) launch_finalize(ep.ws, m.blocks, 1, ep.dot_out, s);
+}
+
+template <int YC>
+static void launch_shape64(const Grid& g, const MfmaLaunch& m, int zchunk, const double* E,
+                           const double* at, const double* u, const uint8_t* fixn,
+                           const Epi<double>& ep, hipStream_t s) {
+  const dim3 grid(m.blocks), block(64 * kMfmaWavesPerBlock);
+  if (ep.mode == EPI_STORE && ep.want_dot)
+    k_apply_fine_mfma64<YC, kStoreDot><<<grid, block, 0, s>>>(g, E, at, u, fixn, ep, zchunk, m.ntx,
+                                                              m.nty, m.ntiles);
+  else if (ep.mode == EPI_STORE)
+    k_apply_fine_mfma64<YC, EPI_STORE><<<grid, block, 0, s>>>(g, E, at, u, fixn, ep, zchunk, m.ntx,
+                                                              m.nty, m.ntiles);
+  else if (ep.mode == EPI_RESID)
+    k_apply_fine_mfma64<YC, EPI_RESID><<<grid, block, 0, s>>>(g, E, at, u, fixn, ep, zchunk, m.ntx,
+                                                              m.nty, m.ntiles);
   else
-    k_apply_fine_mfma<1, kMfmaWaves><<<grid, block, 0, s>>>(g, Escaled, at, u, fixn, ep, g_zchunk);
-  if (ep.want_dot)
-    launch_finalize(ep.ws, (int)(grid.x * grid.y * grid.z), 1, ep.dot_out, s);
+    k_apply_fine_mfma64<YC, EPI_SMOOTH><<<grid, block, 0, s>>>(g, E, at, u, fixn, ep, zchunk, m.ntx,
+                                                               m.nty, m.ntiles);
+}
+
+void launch_apply_fine_mfma64(const Grid& g, int rows, int zchunk, const double* E,
+                              const double* atab64, const double* u, const uint8_t* fixn,
+                              const Epi<double>& ep, hipStream_t s) {
+  if (zchunk < 1) zchunk = 1;
+  if (rows != 4) rows = 8;
+  const MfmaLaunch m = mfma_launch(g, rows, zchunk);
+  if (rows == 4) launch_shape64<4>(g, m, zchunk, E, atab64, u, fixn, ep, s);
+  else launch_shape64<8>(g, m, zchunk, E, atab64, u, fixn, ep, s);
+  if (ep.mode == EPI_STORE && ep.want_dot) launch_finalize(ep.ws, m.blocks, 1, ep.dot_out, s);
+}
+
+bool mfma64_size_ok(const Grid& g) {
+  return (size_t)g.n * sizeof(double) < ((size_t)1 << 31) - 64;
+}
+
+// Host: FP64 A operand, [h][step][lane]: row m = lane % 16 of half h, input
+// (q = lane / 16, step) = node (step / 3, q & 1, q >> 1) component step % 3.
+// The FP64 MFMA returns row m in lane group m % 4, register m / 4 (measured
+// on gfx950; the FP32 16x16 layout is group m / 4, register m % 4), so row
+// m = (dx + 2 dz) + 4 c carries node (dx, h, dz), component c: the lane group
+// then holds one node's 3 components, as in the BF16 kernel.
+void build_mfma_atab64(const KeTables& kt, double* out /* 2*6*64 */) {
+  for (int h = 0; h < 2; ++h)
+    for (int st = 0; st < 6; ++st)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int m = lane & 15, q = lane >> 4;
+        const int go = m & 3, c = m >> 2;
+        const int dx = go & 1, dz = go >> 1;
+        const int aout = dx + 2 * h + 4 * dz;
+        const int bin = (st / 3) + 2 * (q & 1) + 4 * (q >> 1);
+        out[(h * 6 + st) * 64 + lane] =
+            c < 3 ? kt.ke[(3 * aout + c) * 24 + 3 * bin + (st % 3)] : 0.0;
+      }
 }
 
 // E / s in FP32 for the MFMA kernel.
@@ -227,14 +574,14 @@ void launch_scale_E(const double* E, float* Es, int nel, double inv_s, hipStream
 void build_mfma_atab(const KeTables& kt, uint16_t* out /* 2*64*8 */) {
   for (int h = 0; h < 2; ++h)
     for (int lane = 0; lane < 64; ++lane) {
-      const int m = lane & 15, gq = lane >> 4;
+      const int m = lane & 15, q = lane >> 4;
       const int go = m >> 2, c = m & 3;
-      const int dx = go & 1, dy = go >> 1;
-      const int aout = dx + 2 * dy + 4 * h;
+      const int dx = go & 1, dz = go >> 1;
+      const int aout = dx + 2 * h + 4 * dz;
       for (int j = 0; j < 8; ++j) {
         float v = 0.f;
         if (c < 3 && j < 6) {
-          const int bin = (j / 3) + 2 * (gq & 1) + 4 * (gq >> 1);
+          const int bin = (j / 3) + 2 * (q & 1) + 4 * (q >> 1);
           v = (float)kt.kint[(3 * aout + c) * 24 + 3 * bin + (j % 3)];
         }
         uint32_t bits;

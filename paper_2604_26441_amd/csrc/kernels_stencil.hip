@@ -204,26 +204,50 @@ void launch_stencil_to_f32(const double* S, float* S32, size_t n, hipStream_t s)
   k_stencil_to_f32<<<div_up((long)n, 256), 256, 0, s>>>(S, S32, n);
 }
 
-// y = K^l u on the stored stencil, thread per node, with a fused epilogue.
+// y = K^l u on the stored stencil with a fused epilogue.
 // Only the upper half of the stencil is read: block o >= 13 (offsets that are
 // lexicographically >= 0) of node n, and for the lower offsets the transpose
 // of the mirrored block of the neighbour, A[n, n+o] = A[n+o, n]^T =
 // (S_{26-o}[n+o])^T.  The neighbour's block is that neighbour's own upper
 // block, so the second read is served from cache: about half the HBM bytes of
 // the full stencil, and the applied operator is exactly symmetric.
+// One thread per (node, output component): a block is 64 consecutive nodes x
+// 3 components, one wave per component, so every stencil load of a wave is
+// 64 consecutive values of one slot.  Three times the threads of the
+// node-per-thread form: the Galerkin levels are small (level 1 of an 80^3
+// mesh has 68,921 nodes) and need the extra waves to cover HBM latency.  The
+// block index is remapped per XCD so each L2 sees a contiguous node range.
 template <typename T>
-__global__ __launch_bounds__(256) void k_stencil_apply(Grid g, const T* __restrict__ S,
-                                                       const T* __restrict__ u,
-                                                       const uint8_t* __restrict__ fixn,
-                                                       Epi<T> ep) {
-  const int node = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(192) void k_stencil_apply_c(Grid g, const T* __restrict__ S,
+                                                        const T* __restrict__ u,
+                                                        const uint8_t* __restrict__ fixn,
+                                                        Epi<T> ep) {
+  const int lane = threadIdx.x & 63, d = threadIdx.x >> 6;
+  const int node = xcd_block(blockIdx.x, gridDim.x) * 64 + lane;
   double dot = 0.0;
   if (node < g.Nn) {
-    T acc[3];
-    stencil_node_Ku<T>(g, S, u, node, acc);
-    const double y[3] = {(double)acc[0], (double)acc[1], (double)acc[2]};
-    const T xo[3] = {u[3 * (size_t)node], u[3 * (size_t)node + 1], u[3 * (size_t)node + 2]};
-    dot = epilogue3(ep, node, fixn[node], xo, y);
+    const int i = node % g.Nx, t = node / g.Nx, j = t % g.Ny, k = t / g.Ny;
+    const size_t Nn = g.Nn;
+    T acc = (T)0;
+#pragma unroll
+    for (int o = 0; o < 27; ++o) {
+      const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+      const bool ok = (unsigned)(i + ox) < (unsigned)g.Nx && (unsigned)(j + oy) < (unsigned)g.Ny &&
+                      (unsigned)(k + oz) < (unsigned)g.Nz;
+      if (!ok) continue;
+      const int nb = node + ox + g.Nx * (oy + g.Ny * oz);
+      const size_t b3 = 3 * (size_t)nb;
+      const T u0 = u[b3], u1 = u[b3 + 1], u2 = u[b3 + 2];
+      if (o >= 13) {
+        const T* Sb = S + ((size_t)o * 9 + 3 * d) * Nn + node;
+        acc += Sb[0] * u0 + Sb[Nn] * u1 + Sb[2 * Nn] * u2;
+      } else {
+        const T* Sb = S + ((size_t)(26 - o) * 9 + d) * Nn + nb;
+        acc += Sb[0] * u0 + Sb[3 * Nn] * u1 + Sb[6 * Nn] * u2;
+      }
+    }
+    const size_t dof = 3 * (size_t)node + d;
+    dot = epilogue1(ep, dof, (fixn[node] >> d) & 1u, u[dof], (double)acc);
   }
   if (ep.want_dot) {
     const double v[1] = {dot};
@@ -231,13 +255,14 @@ __global__ __launch_bounds__(256) void k_stencil_apply(Grid g, const T* __restri
   }
 }
 
-size_t stencil_apply_blocks(const Grid& g) { return div_up(g.Nn, 256); }
+size_t stencil_apply_blocks(const Grid& g) { return div_up(g.Nn, 64); }
 
 template <typename T>
 void launch_stencil_apply(const Grid& g, const T* S, const T* u, const uint8_t* fixn,
                           const Epi<T>& ep, hipStream_t s) {
-  k_stencil_apply<T><<<div_up(g.Nn, 256), 256, 0, s>>>(g, S, u, fixn, ep);
-  if (ep.want_dot) launch_finalize(ep.ws, div_up(g.Nn, 256), 1, ep.dot_out, s);
+  const int nb = (int)stencil_apply_blocks(g);
+  k_stencil_apply_c<T><<<nb, 192, 0, s>>>(g, S, u, fixn, ep);
+  if (ep.want_dot) launch_finalize(ep.ws, nb, 1, ep.dot_out, s);
 }
 template void launch_stencil_apply<double>(const Grid&, const double*, const double*,
                                            const uint8_t*, const Epi<double>&, hipStream_t);
@@ -247,33 +272,63 @@ template void launch_stencil_apply<float>(const Grid&, const float*, const float
 // Restriction (R = P^T, Eq. vector_prolongation): coarse node I gathers the
 // <= 27 fine nodes that interpolate from it.  Optional fused first smoothing
 // step from a zero iterate: x_c = c0 * Dinv_c * b_c, d_c = x_c.
+// 1D weights of fine nodes 2I - 1, 2I, 2I + 1 towards coarse node I on an
+// axis of nf fine elements (the closed form of w1d for those three nodes).
+__device__ inline void restrict_w1d(int I, int nf, double (&w)[3]) {
+  const int nc = nf >> 1;
+  w[0] = I >= 1 ? 0.5 : 0.0;
+  w[1] = 1.0;
+  w[2] = 2 * I + 1 < 2 * nc ? 0.5 : (2 * I + 1 == nf ? 1.0 : 0.0);
+}
+
+// Thread per (coarse node, component), 64 coarse nodes per block, block index
+// remapped per XCD.  The 27 fine values are read unconditionally at clamped
+// indices and weighted (zero weights for nodes outside the grid).
 template <typename TF, typename TC>
-__global__ void k_restrict(Grid f, Grid c, const TF* __restrict__ rf,
-                           const uint8_t* __restrict__ cfix, TC* __restrict__ bc,
-                           const TC* __restrict__ dinv_c, double c0, TC* __restrict__ xc,
-                           TC* __restrict__ dc) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(192) void k_restrict(Grid f, Grid c, const TF* __restrict__ rf,
+                                                  const uint8_t* __restrict__ cfix,
+                                                  TC* __restrict__ bc,
+                                                  const TC* __restrict__ dinv_c, double c0,
+                                                  TC* __restrict__ xc, TC* __restrict__ dc) {
+  const int k = threadIdx.x >> 6;
+  const int I = xcd_block(blockIdx.x, gridDim.x) * 64 + (threadIdx.x & 63);
   if (I >= c.Nn) return;
-  double acc[3];
-  restrict_node<TF>(f, c, rf, I, acc);
-  const unsigned fx = cfix[I];
+  const int Ix = I % c.Nx, t = I / c.Nx, Iy = t % c.Ny, Iz = t / c.Ny;
+  double wx[3], wy[3], wz[3];
+  restrict_w1d(Ix, f.nx, wx);
+  restrict_w1d(Iy, f.ny, wy);
+  restrict_w1d(Iz, f.nz, wz);
+  double acc = 0.0;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const TC v = (fx >> k) & 1u ? (TC)0 : (TC)acc[k];
-    bc[3 * (size_t)I + k] = v;
-    if (xc) {
-      const TC x = (TC)c0 * dinv_c[3 * (size_t)I + k] * v;
-      xc[3 * (size_t)I + k] = x;
-      if (dc) dc[3 * (size_t)I + k] = x;
+  for (int cz = 0; cz < 3; ++cz) {
+    const int iz = min(max(2 * Iz - 1 + cz, 0), f.Nz - 1);
+#pragma unroll
+    for (int cy = 0; cy < 3; ++cy) {
+      const int iy = min(max(2 * Iy - 1 + cy, 0), f.Ny - 1);
+      const double wyz = wy[cy] * wz[cz];
+      const size_t row = (size_t)f.Nx * (iy + (size_t)f.Ny * iz);
+#pragma unroll
+      for (int cx = 0; cx < 3; ++cx) {
+        const int ix = min(max(2 * Ix - 1 + cx, 0), f.Nx - 1);
+        acc += wx[cx] * wyz * (double)rf[3 * (row + ix) + k];
+      }
     }
+  }
+  const size_t dof = 3 * (size_t)I + k;
+  const TC v = (cfix[I] >> k) & 1u ? (TC)0 : (TC)acc;
+  bc[dof] = v;
+  if (xc) {
+    const TC x = (TC)c0 * dinv_c[dof] * v;
+    xc[dof] = x;
+    if (dc) dc[dof] = x;
   }
 }
 
 template <typename TF, typename TC>
 void launch_restrict(const Grid& fine, const Grid& coarse, const TF* rf, const uint8_t* cfix,
                      TC* bc, const TC* dinv_c, double c0, TC* xc, TC* dc, hipStream_t s) {
-  k_restrict<TF, TC><<<div_up(coarse.Nn, 256), 256, 0, s>>>(fine, coarse, rf, cfix, bc, dinv_c,
-                                                            c0, xc, dc);
+  k_restrict<TF, TC><<<div_up(coarse.Nn, 64), 192, 0, s>>>(fine, coarse, rf, cfix, bc, dinv_c, c0,
+                                                           xc, dc);
 }
 template void launch_restrict<float, double>(const Grid&, const Grid&, const float*,
                                              const uint8_t*, double*, const double*, double,
@@ -289,14 +344,38 @@ template void launch_restrict<double, float>(const Grid&, const Grid&, const dou
                                              float*, float*, hipStream_t);
 
 // Prolongation and correction x_f += M_f P e_c: fine node i reads the <= 8
-// coarse nodes it interpolates from.
+// coarse nodes it interpolates from.  Per axis the two candidates and their
+// weights are in closed form (even node: its coarse node, weight 1; odd
+// interior node: both neighbours, 1/2 each; trailing odd node: the last
+// coarse node, weight 1); the 8 corners are read unconditionally at valid
+// indices with zero weights where a candidate does not exist.
+__device__ inline void prolong_w1d(int i, int nf, int (&ci)[2], double (&w)[2]) {
+  const int nc = nf >> 1;
+  if ((i & 1) == 0) { ci[0] = ci[1] = i >> 1; w[0] = 1.0; w[1] = 0.0; }
+  else if (i < 2 * nc) { ci[0] = (i - 1) >> 1; ci[1] = (i + 1) >> 1; w[0] = w[1] = 0.5; }
+  else { ci[0] = ci[1] = nc; w[0] = 1.0; w[1] = 0.0; }
+}
+
 template <typename TF, typename TC>
 __global__ void k_prolong_add(Grid f, Grid c, const TC* __restrict__ ec,
                               const uint8_t* __restrict__ ffix, TF* __restrict__ xf) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= f.Nn) return;
-  double acc[3];
-  prolong_node<TC>(f, c, ec, i, acc);
+  const int ix = i % f.Nx, t = i / f.Nx, iy = t % f.Ny, iz = t / f.Ny;
+  int cx[2], cy[2], cz[2];
+  double wx[2], wy[2], wz[2];
+  prolong_w1d(ix, f.nx, cx, wx);
+  prolong_w1d(iy, f.ny, cy, wy);
+  prolong_w1d(iz, f.nz, cz, wz);
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const double w = wx[a & 1] * wy[(a >> 1) & 1] * wz[a >> 2];
+    const size_t b = 3 * (size_t)(cx[a & 1] + c.Nx * (cy[(a >> 1) & 1] + (size_t)c.Ny * cz[a >> 2]));
+    acc[0] += w * (double)ec[b];
+    acc[1] += w * (double)ec[b + 1];
+    acc[2] += w * (double)ec[b + 2];
+  }
   const unsigned fx = ffix[i];
 #pragma unroll
   for (int k = 0; k < 3; ++k)

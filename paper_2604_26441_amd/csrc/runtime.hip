@@ -64,8 +64,12 @@ struct sgmg_hierarchy {
   double* E64 = nullptr;
   float* E32 = nullptr;
   float* E32s = nullptr;     // E / s for the MFMA kernel
-  int mfma_zchunk[2] = {8, 8};  // [nsplit == 3]: tuned or default z-chunk
+  // MFMA launch shape [nsplit == 3]: element rows per wave tile, node planes
+  // per wave (tuned per mesh, or the default)
+  int mfma_rows[3] = {4, 4, 0};     // [BF16, BF16X3, FP64]; FP64 rows 0: node kernel
+  int mfma_zchunk[3] = {4, 4, 0};
   uint16_t* atab = nullptr;  // MFMA A-operand table (BF16 bits)
+  double* atab64 = nullptr;  // FP64 MFMA A-operand table
   double maxE_lambda = 0.0;  // max E when lambdas were estimated
   int nL = 0;
   int* free_idx = nullptr;
@@ -92,14 +96,15 @@ namespace {
 
 constexpr size_t kMinPartials = 1 << 16;
 
-// Process-wide autotuning results: (nx, ny, nz, nsplit) -> MFMA z-chunk.
+// Process-wide autotuning results: (nx, ny, nz, variant) -> MFMA launch shape
+// (rows, z-chunk); variant 1 = BF16, 3 = BF16X3, 64 = FP64.
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, int> g_tune;
+std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tune;
 
-int tuned_zchunk(int nx, int ny, int nz, int nsplit) {
+std::pair<int, int> tuned_shape(int nx, int ny, int nz, int variant, std::pair<int, int> dflt) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tune.find(std::make_tuple(nx, ny, nz, nsplit));
-  return it == g_tune.end() ? 8 : it->second;
+  auto it = g_tune.find(std::make_tuple(nx, ny, nz, variant));
+  return it == g_tune.end() ? dflt : it->second;
 }
 
 int dalloc(sgmg_hierarchy* h, void** p, size_t bytes) {
@@ -220,7 +225,10 @@ int apply_level<double>(const sgmg_hierarchy* h, int l, sgmg_prec prec, const do
     set_error("double vectors require SGMG_F64");
     return SGMG_EINVAL;
   }
-  if (l == 0)
+  if (l == 0 && h->mfma_rows[2] > 0 && mfma64_size_ok(L.g))
+    launch_apply_fine_mfma64(L.g, h->mfma_rows[2], h->mfma_zchunk[2], h->E64, h->atab64, x, L.fixn,
+                             ep, s);
+  else if (l == 0)
     launch_apply_fine_node<double>(L.g, h->E64, h->ke64, x, L.fixn, ep, s);
   else
     launch_stencil_apply<double>(L.g, L.S64, x, L.fixn, ep, s);
@@ -239,8 +247,13 @@ int apply_level<float>(const sgmg_hierarchy* h, int l, sgmg_prec prec, const flo
         set_error("BF16 MFMA path needs s*K_e integral (nu = 0.3 family); use F32");
         return SGMG_EINVAL;
       }
+      if (!mfma_size_ok(L.g)) {
+        set_error("BF16 MFMA path: level-0 vector of 2^31 bytes or more; use F32");
+        return SGMG_EINVAL;
+      }
       const int ns = prec == SGMG_BF16 ? 1 : 3;
-      launch_apply_fine_mfma(L.g, ns, h->mfma_zchunk[ns == 3], h->E32s, h->atab, x, L.fixn, ep, s);
+      launch_apply_fine_mfma(L.g, ns, h->mfma_rows[ns == 3], h->mfma_zchunk[ns == 3], h->E32s,
+                             h->atab, x, L.fixn, ep, s);
     } else {
       set_error("float vectors need F32, BF16 or BF16X3");
       return SGMG_EINVAL;
@@ -558,8 +571,13 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
   auto fail = [&](int code) { sgmg_destroy(h); return code; };
 
   compute_ke(opts->nu, &h->kt);
-  h->mfma_zchunk[0] = tuned_zchunk(opts->nx, opts->ny, opts->nz, 1);
-  h->mfma_zchunk[1] = tuned_zchunk(opts->nx, opts->ny, opts->nz, 3);
+  for (int q = 0; q < 3; ++q) {
+    // FP64 defaults to the vector-ALU node kernel (rows 0) until tuned
+    const auto sh = tuned_shape(opts->nx, opts->ny, opts->nz, q == 2 ? 64 : (q ? 3 : 1),
+                                q == 2 ? std::make_pair(0, 0) : std::make_pair(4, 4));
+    h->mfma_rows[q] = sh.first;
+    h->mfma_zchunk[q] = sh.second;
+  }
   // level dims by floor coarsening and masks by injection
   Grid g0 = make_grid(opts->nx, opts->ny, opts->nz);
   int maxL = opts->n_levels ? opts->n_levels : 8;
@@ -646,18 +664,24 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
   hipMemcpyAsync(h->ke32, h->kt.ke32, 576 * sizeof(float), hipMemcpyHostToDevice, s);
   hipMemcpyAsync(h->gtab, gt.data(), gt.size() * sizeof(double), hipMemcpyHostToDevice, s);
   if ((rc = dalloc_t(h, &h->E64, g0.nel)) || (rc = dalloc_t(h, &h->E32, g0.nel)) ||
-      (rc = dalloc_t(h, &h->E32s, g0.nel)) || (rc = dalloc_t(h, &h->atab, 2 * 64 * 8)))
+      (rc = dalloc_t(h, &h->E32s, g0.nel)) || (rc = dalloc_t(h, &h->atab, 2 * 64 * 8)) ||
+      (rc = dalloc_t(h, &h->atab64, 2 * 6 * 64)))
     return fail(rc);
   {
     std::vector<uint16_t> at(2 * 64 * 8);
     build_mfma_atab(h->kt, at.data());
     hipMemcpyAsync(h->atab, at.data(), at.size() * sizeof(uint16_t), hipMemcpyHostToDevice, s);
+    std::vector<double> at64(2 * 6 * 64);
+    build_mfma_atab64(h->kt, at64.data());
+    hipMemcpyAsync(h->atab64, at64.data(), at64.size() * sizeof(double), hipMemcpyHostToDevice, s);
     if (hipStreamSynchronize(s) != hipSuccess) { set_error("sync failed"); return fail(SGMG_EHIP); }
   }
   // reductions, scalars, PCG vectors
   // one partial per block of the largest reduction grid (fused dots run one
   // block per 256 nodes; vector reductions use at most 2 x 1024 slots)
-  const size_t npart = std::max(kMinPartials, (size_t)div_up(g0.Nn, 256) + 2048);
+  // (the MFMA kernel's largest grid is its smallest tile shape: 4 rows, 1 plane)
+  const size_t npart = std::max({kMinPartials, (size_t)div_up(g0.Nn, 256) + 2048,
+                                 apply_fine_mfma_blocks(g0, 4, 1)});
   if ((rc = dalloc_t(h, &h->ws.partials, npart)) || (rc = dalloc_t(h, &h->ws.counter, 1)) ||
       (rc = dalloc_t(h, &h->sc, SC_COUNT)) || (rc = dalloc_t(h, &h->d_flag, 1)))
     return fail(rc);
@@ -899,7 +923,23 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
   return 0;
 }
 
-int sgmg_autotune(sgmg_hierarchy* h, int* zchunk_out, void* stream) {
+int sgmg_set_launch_shape(sgmg_hierarchy* h, int variant, int rows, int planes) {
+  if (!h) { set_error("NULL argument"); return SGMG_EINVAL; }
+  if (variant < 0 || variant > 2) { set_error("variant must be 0 (BF16), 1 (BF16X3) or 2 (FP64)"); return SGMG_EINVAL; }
+  const bool node64 = variant == 2 && rows == 0 && planes == 0;
+  if (!node64 && !mfma_shape_valid(rows, planes)) {
+    set_error("shape must have rows 4 or 8 and planes >= 1 (FP64 also (0, 0))");
+    return SGMG_EINVAL;
+  }
+  h->mfma_rows[variant] = rows;
+  h->mfma_zchunk[variant] = planes;
+  for (auto& row : h->iter_graph)        // captured graphs hold the old launch shape
+    for (auto& g : row)
+      if (g) { hipGraphExecDestroy(g); g = nullptr; }
+  return 0;
+}
+
+int sgmg_autotune(sgmg_hierarchy* h, int* shape_out, void* stream) {
   if (!h) { set_error("NULL argument"); return SGMG_EINVAL; }
   if (!h->kt.integral) { set_error("MFMA path unavailable for this nu"); return SGMG_EINVAL; }
   hipStream_t s = as_stream(stream);
@@ -915,32 +955,77 @@ int sgmg_autotune(sgmg_hierarchy* h, int* zchunk_out, void* stream) {
   hipEvent_t e0, e1;
   hipEventCreate(&e0);
   hipEventCreate(&e1);
-  const int cands[] = {2, 4, 8, 16, 32};
+  const int rows_c[] = {4, 8};
+  const int z_c[] = {2, 4, 8, 16, 32};
+  double* u64 = nullptr;
+  double* y64 = nullptr;
   int rc = 0;
-  for (int q = 0; q < 2 && !rc; ++q) {
-    const int ns = q ? 3 : 1;
-    int best = 8;
+  if (hipMalloc(&u64, (size_t)L0.g.n * sizeof(double)) != hipSuccess ||
+      hipMalloc(&y64, (size_t)L0.g.n * sizeof(double)) != hipSuccess) {
+    set_error("autotune allocation failed");
+    rc = SGMG_ENOMEM;
+  } else {
+    hipMemsetAsync(u64, 0, (size_t)L0.g.n * sizeof(double), s);
+  }
+  // variant q: 0 BF16, 1 BF16X3, 2 FP64
+  for (int q = 0; q < 3 && !rc; ++q) {
+    if (q == 2 && !mfma64_size_ok(L0.g)) break;
+    const int key = q == 2 ? 64 : (q ? 3 : 1);
+    int best_r = 8, best_z = 8;
     float best_ms = 1e30f;
-    for (int z : cands) {
-      if (z > L0.g.Nz && z != cands[0]) continue;
-      const Epi<float> ep = epi_store<float>(y);
+    if (q == 2) {                                 // vector-ALU node kernel (rows 0)
       for (int w = 0; w < 3; ++w)
-        launch_apply_fine_mfma(L0.g, ns, z, h->E32s, h->atab, u, L0.fixn, ep, s);
+        launch_apply_fine_node<double>(L0.g, h->E64, h->ke64, u64, L0.fixn, epi_store<double>(y64), s);
       hipEventRecord(e0, s);
       for (int r = 0; r < 20; ++r)
-        launch_apply_fine_mfma(L0.g, ns, z, h->E32s, h->atab, u, L0.fixn, ep, s);
+        launch_apply_fine_node<double>(L0.g, h->E64, h->ke64, u64, L0.fixn, epi_store<double>(y64), s);
       hipEventRecord(e1, s);
       if ((rc = check_launch())) break;
-      if (hipEventSynchronize(e1) != hipSuccess) { rc = SGMG_EHIP; set_error("autotune sync failed"); break; }
-      float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best_ms) { best_ms = ms; best = z; }
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        rc = SGMG_EHIP;
+        set_error("autotune sync failed");
+        break;
+      }
+      hipEventElapsedTime(&best_ms, e0, e1);
+      best_r = best_z = 0;
     }
-    h->mfma_zchunk[q] = best;
-    if (zchunk_out) zchunk_out[q] = best;
+    for (int rows : rows_c) {
+      for (int z : z_c) {
+        if (z > L0.g.Nz && z != z_c[0]) continue;
+        auto launch = [&]() {
+          if (q == 2)
+            launch_apply_fine_mfma64(L0.g, rows, z, h->E64, h->atab64, u64, L0.fixn,
+                                     epi_store<double>(y64), s);
+          else
+            launch_apply_fine_mfma(L0.g, key, rows, z, h->E32s, h->atab, u, L0.fixn,
+                                   epi_store<float>(y), s);
+        };
+        for (int w = 0; w < 3; ++w) launch();
+        hipEventRecord(e0, s);
+        for (int r = 0; r < 20; ++r) launch();
+        hipEventRecord(e1, s);
+        if ((rc = check_launch())) break;
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          rc = SGMG_EHIP;
+          set_error("autotune sync failed");
+          break;
+        }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) { best_ms = ms; best_r = rows; best_z = z; }
+      }
+      if (rc) break;
+    }
+    if (rc) break;
+    h->mfma_rows[q] = best_r;
+    h->mfma_zchunk[q] = best_z;
+    if (shape_out) { shape_out[2 * q] = best_r; shape_out[2 * q + 1] = best_z; }
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[std::make_tuple(L0.g.nx, L0.g.ny, L0.g.nz, ns)] = best;
+    g_tune[std::make_tuple(L0.g.nx, L0.g.ny, L0.g.nz, key)] = std::make_pair(best_r, best_z);
   }
+  hipStreamSynchronize(s);
+  if (u64) hipFree(u64);
+  if (y64) hipFree(y64);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   hipStreamSynchronize(s);

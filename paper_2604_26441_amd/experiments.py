@@ -66,7 +66,7 @@ def kernels():
         rho = torch.tensor(workloads.uniform_rho(dims), dtype=torch.float64, device=dev)
         h = simpgmg.setup_hierarchy(o, rho)
         fixed = torch.tensor(workloads.cantilever_fixed(dims), device=dev).bool()
-        rec = {"dims": dims, "mfma_zchunk_bf16_bf16x3": simpgmg.autotune(h)}
+        rec = {"dims": dims, "mfma_shape_bf16_bf16x3": simpgmg.autotune(h)}
         for prec in ("f64", "f32", "bf16x3", "bf16"):
             dt = torch.float64 if prec == "f64" else torch.float32
             u = torch.ones(fixed.numel(), dtype=dt, device=dev).masked_fill_(fixed, 0)
@@ -233,5 +233,39 @@ def warmstart(n_train=2000, train_seconds=120.0, batch_size=8, lr=1e-3):
     print(json.dumps(rec), flush=True)
 
 
+def traffic(n=80, reps=20):
+    """Workload for HBM-traffic counters: the 80^3 fine K.u (BF16X3, BF16,
+    FP64), the level-1 stencil apply, and a plain device copy of 64 MiB (the
+    calibration kernel: its FETCH_SIZE / WRITE_SIZE per dispatch are compared
+    with the 64 MiB it moves)."""
+    dev = "cuda:0"
+    dims = (n, n, n)
+    rho = torch.tensor(workloads.uniform_rho(dims), dtype=torch.float64, device=dev)
+    h = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, n_levels=4), rho)
+    shapes = simpgmg.autotune(h)
+    fixed = torch.tensor(workloads.cantilever_fixed(dims), device=dev).bool()
+    u32 = torch.ones(fixed.numel(), dtype=torch.float32, device=dev).masked_fill_(fixed, 0)
+    u64 = u32.double()
+    y32, y64 = torch.empty_like(u32), torch.empty_like(u64)
+    for prec, u, y in (("bf16x3", u32, y32), ("bf16", u32, y32), ("f64", u64, y64)):
+        for _ in range(reps):
+            simpgmg.apply_K(h, 0, prec, u, y)
+    info = h.level_info(1)
+    d = info["dims"]
+    n1 = 3 * (d[0] + 1) * (d[1] + 1) * (d[2] + 1)
+    u1 = torch.ones(n1, dtype=torch.float64, device=dev)
+    y1 = torch.empty_like(u1)
+    for _ in range(reps):
+        simpgmg.apply_K(h, 1, "f64", u1, y1)
+    a = torch.ones(16 * 1024 * 1024, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"dims": dims, "shapes": shapes, "reps": reps, "copy_bytes": a.numel() * 4,
+                      "level1_nodes": n1 // 3}), flush=True)
+
+
 if __name__ == "__main__":
-    {"sizes": sizes, "kernels": kernels, "batch": batch, "warmstart": warmstart}[sys.argv[1]]()
+    {"sizes": sizes, "kernels": kernels, "batch": batch, "warmstart": warmstart,
+     "traffic": traffic}[sys.argv[1]]()

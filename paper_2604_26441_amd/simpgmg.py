@@ -58,7 +58,7 @@ EXPORTS = [
     "sgmg_default_options", "sgmg_setup_hierarchy", "sgmg_update_moduli", "sgmg_apply_K",
     "sgmg_vcycle", "sgmg_pcg_solve", "sgmg_num_levels", "sgmg_level_info",
     "sgmg_copy_stencil", "sgmg_copy_diagonal", "sgmg_destroy", "sgmg_last_error",
-    "sgmg_autotune", "sgmg_setup_batch", "sgmg_pcg_solve_batch", "sgmg_batch_hierarchy",
+    "sgmg_autotune", "sgmg_set_launch_shape", "sgmg_setup_batch", "sgmg_pcg_solve_batch", "sgmg_batch_hierarchy",
     "sgmg_batch_block_size", "sgmg_batch_destroy",
     "sgmg_unet_create", "sgmg_unet_num_params", "sgmg_unet_set_params", "sgmg_unet_get_params",
     "sgmg_unet_forward", "sgmg_unet_grad", "sgmg_unet_train_step", "sgmg_unet_input",
@@ -80,6 +80,7 @@ def _load():
     lib.sgmg_vcycle.argtypes = [H, vp, vp, vp]
     lib.sgmg_pcg_solve.argtypes = [H, i, vp, vp, d, i, ctypes.POINTER(SolveInfo), vp]
     lib.sgmg_autotune.argtypes = [H, ctypes.POINTER(ctypes.c_int), vp]
+    lib.sgmg_set_launch_shape.argtypes = [H, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.sgmg_setup_batch.argtypes = [i, ctypes.POINTER(Options), ctypes.POINTER(vp),
                                      ctypes.POINTER(vp), vp, ctypes.POINTER(H)]
     lib.sgmg_pcg_solve_batch.argtypes = [H, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp),
@@ -237,10 +238,20 @@ def setup_hierarchy(opts, rho_or_E, fixed_dof=None, lambda_override=None, stream
 
 
 def autotune(h, stream=None):
-    """Tune the MFMA fine operator's z-chunk for this mesh; returns (bf16, bf16x3)."""
-    z = (ctypes.c_int * 2)()
+    """Tune the MFMA fine operators' launch shapes for this mesh; returns
+    ((rows, planes) for bf16, for bf16x3, for f64)."""
+    z = (ctypes.c_int * 6)()
     _check(_lib.sgmg_autotune(h.handle, z, _stream(stream)))
-    return int(z[0]), int(z[1])
+    return tuple((int(z[2 * q]), int(z[2 * q + 1])) for q in range(3))
+
+
+VARIANTS = {"bf16": 0, "bf16x3": 1, "f64": 2}
+
+
+def set_launch_shape(h, variant, rows, planes):
+    """Pin the fine operator's launch shape for variant 'bf16', 'bf16x3' or
+    'f64' ((0, 0) selects the FP64 vector-ALU node kernel)."""
+    _check(_lib.sgmg_set_launch_shape(h.handle, VARIANTS[variant], rows, planes))
 
 
 def update_moduli(h, rho_or_E, stream=None):

@@ -102,7 +102,8 @@ MFMA_CASES = [((16, 8, 8), 0), ((9, 7, 5), 1), ((31, 6, 20), 2), ((24, 12, 12), 
 @pytest.mark.parametrize("dims,seed", MFMA_CASES)
 def test_fine_apply_mfma_bf16x3_and_bf16(dims, seed):
     """MFMA K.u: BF16X3 is FP32-accurate; BF16 equals the BF16 semantic model
-    (input rounded to BF16, exact element matrix, FP32 accumulation)."""
+    (input rounded to BF16, exact element matrix, FP32 accumulation); FP64 is
+    FP64-accurate."""
     from oracle import bf16
     from paper_2604_26441_amd import simpgmg
     rho, fixed = _inputs(dims, seed)
@@ -120,6 +121,14 @@ def test_fine_apply_mfma_bf16x3_and_bf16(dims, seed):
     assert rel_err(np64(y1), ref1, scale) < 2e-6
     assert rel_err(np64(y1), K @ u, scale) < 2.0 ** -8
     assert np.all(np64(y3)[fixed] == 0) and np.all(np64(y1)[fixed] == 0)
+    # FP64 operator on the FP64 matrix cores, same tiles (two shapes)
+    u64 = workloads.random_vector(fixed.size, seed + 30, fixed)
+    for shape in ((4, 2), (8, 5)):
+        simpgmg.set_launch_shape(h, "f64", *shape)
+        y64 = t64(np.zeros_like(u64))
+        simpgmg.apply_K(h, 0, "f64", t64(u64), y64)
+        assert rel_err(np64(y64), K @ u64, abs(K) @ np.abs(u64)) < 1e-13, shape
+        assert np.all(np64(y64)[fixed] == 0)
 
 
 def test_fine_apply_deterministic():
@@ -144,13 +153,18 @@ def test_autotune_keeps_results_bitwise():
     h = _gpu_h(dims, 2, rho)
     u = t32(workloads.random_vector(fixed.size, 12, fixed))
     before = {}
-    for prec in ("bf16", "bf16x3"):
-        y = t32(np.zeros(fixed.size))
-        simpgmg.apply_K(h, 0, prec, u, y)
+    u64 = t64(np64(u))
+    simpgmg.set_launch_shape(h, "f64", 4, 3)
+    for prec in ("bf16", "bf16x3", "f64"):
+        y = t64(np.zeros(fixed.size)) if prec == "f64" else t32(np.zeros(fixed.size))
+        simpgmg.apply_K(h, 0, prec, u64 if prec == "f64" else u, y)
         before[prec] = np64(y)
     z = simpgmg.autotune(h)
-    assert all(v in (2, 4, 8, 16, 32) for v in z)
-    for prec in ("bf16", "bf16x3"):
-        y = t32(np.zeros(fixed.size))
-        simpgmg.apply_K(h, 0, prec, u, y)
+    assert all(r in (4, 8) and p in (2, 4, 8, 16, 32) for r, p in z[:2])
+    assert z[2] == (0, 0) or (z[2][0] in (4, 8) and z[2][1] in (2, 4, 8, 16, 32))
+    if z[2] == (0, 0):                      # the tuner chose the node kernel:
+        simpgmg.set_launch_shape(h, "f64", 8, 16)   # compare another MFMA shape
+    for prec in ("bf16", "bf16x3", "f64"):
+        y = t64(np.zeros(fixed.size)) if prec == "f64" else t32(np.zeros(fixed.size))
+        simpgmg.apply_K(h, 0, prec, u64 if prec == "f64" else u, y)
         assert np.array_equal(np64(y), before[prec]), prec

@@ -16,9 +16,12 @@ def _setup(dims, L, rho, fine_prec, fine_smoother=0, lambdas=None, level1_prec="
     return simpgmg.setup_hierarchy(o, t64(rho), lambda_override=lambdas)
 
 
-@pytest.mark.parametrize("dims,L,smoother", [((16, 8, 8), 3, 0), ((24, 12, 12), 4, 0),
-                                             ((16, 8, 8), 3, 1), ((9, 7, 5), 3, 0)])
-def test_vcycle_f64_matches_oracle(dims, L, smoother):
+@pytest.mark.parametrize("dims,L,smoother,shape", [((16, 8, 8), 3, 0, None), ((24, 12, 12), 4, 0, None),
+                                                   ((16, 8, 8), 3, 1, None), ((9, 7, 5), 3, 0, None),
+                                                   ((24, 12, 12), 4, 0, (4, 3)), ((16, 8, 8), 3, 1, (8, 4))])
+def test_vcycle_f64_matches_oracle(dims, L, smoother, shape):
+    """shape None: FP64 vector-ALU fine operator; (rows, planes): the FP64
+    MFMA fine operator (residual and smoothing epilogues)."""
     from paper_2604_26441_amd import simpgmg
     g = np.random.default_rng(3)
     rho = g.uniform(0.1, 1.0, np.prod(dims))
@@ -28,6 +31,8 @@ def test_vcycle_f64_matches_oracle(dims, L, smoother):
         n_levels=L, fine_smoother="chebyshev" if smoother == 0 else "jacobi"))
     lams = [lv.lam for lv in oh.levels[:-1]]
     h = _setup(dims, L, rho, "f64", smoother, lams)
+    if shape:
+        simpgmg.set_launch_shape(h, "f64", *shape)
     r = workloads.random_vector(fixed.size, 5, fixed)
     z = t64(np.zeros_like(r))
     simpgmg.vcycle(h, t64(r), z)
@@ -51,7 +56,7 @@ def test_vcycle_f32_close_to_oracle(prec):
     assert rel_err(np64(z), ref, ref) < 1e-4
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "f64-mfma"])
 def test_config0_pcg(prec):
     """16x8x8 cantilever, rho = 0.5, p = 3, 3 levels, rtol 1e-6, cap 200."""
     from paper_2604_26441_amd import simpgmg
@@ -63,7 +68,11 @@ def test_config0_pcg(prec):
     K = mesh.assemble(dims, E, fixed=fixed)
     oh = multigrid.build(dims, E, fixed, multigrid.Options(n_levels=3))
     xo, st, it_o, _ = krylov.pcg(lambda v: K @ v, f, lambda r: multigrid.vcycle(oh, r), rtol=1e-6, maxit=200)
+    mfma64 = prec == "f64-mfma"
+    prec = "f64" if mfma64 else prec
     h = _setup(dims, 3, rho, prec)
+    if mfma64:                           # FP64 MFMA for the outer K.p and FP64 smoothing
+        simpgmg.set_launch_shape(h, "f64", 4, 4)
     u = t64(np.zeros_like(f))
     res = simpgmg.pcg_solve(h, t64(f), u, rtol=1e-6, maxit=200, history_cap=256)
     assert res["status"] == "converged"
