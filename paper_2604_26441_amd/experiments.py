@@ -235,9 +235,10 @@ def warmstart(n_train=2000, train_seconds=120.0, batch_size=8, lr=1e-3):
 
 def traffic(n=80, reps=20):
     """Workload for HBM-traffic counters: the 80^3 fine K.u (BF16X3, BF16,
-    FP64), the level-1 stencil apply, and a plain device copy of 64 MiB (the
+    FP64), the level-1 stencil apply, and a plain device copy of 1 GiB (the
     calibration kernel: its FETCH_SIZE / WRITE_SIZE per dispatch are compared
-    with the 64 MiB it moves)."""
+    with the 1 GiB it moves; at that size the 8 x 4 MiB of L2 cannot hold a
+    useful part of the source)."""
     dev = "cuda:0"
     dims = (n, n, n)
     rho = torch.tensor(workloads.uniform_rho(dims), dtype=torch.float64, device=dev)
@@ -257,9 +258,9 @@ def traffic(n=80, reps=20):
     y1 = torch.empty_like(u1)
     for _ in range(reps):
         simpgmg.apply_K(h, 1, "f64", u1, y1)
-    a = torch.ones(16 * 1024 * 1024, dtype=torch.float32, device=dev)
+    a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
-    for _ in range(reps):
+    for _ in range(4):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"dims": dims, "shapes": shapes, "reps": reps, "copy_bytes": a.numel() * 4,
