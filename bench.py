@@ -33,6 +33,9 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip FP64-GMG and Jacobi-PCG comparisons")
+    ap.add_argument("--warm-pairs", type=int, default=300,
+                    help="solver-generated 32^3 training pairs for the warm-start comparison (0: skip)")
+    ap.add_argument("--warm-train-s", type=float, default=20.0)
     return ap.parse_args()
 
 
@@ -151,6 +154,17 @@ def main():
                               "status": r64["status"]},
                  "jacobi_pcg_cap200": {"solve_ms": round(rj["solve_ms"], 3), "iters": rj["iters"],
                                        "status": rj["status"], "rel_res_true": rj["rel_res_true"]}}
+
+    if args.warm_pairs > 0:
+        # learned warm start on the same solve: network trained here on
+        # solver-generated 32^3 random-field pairs, then zero start vs scaled
+        # prediction, same tolerance
+        from paper_2604_26441_amd import experiments
+        net, rec = experiments.train_warm_start(args.warm_pairs, args.warm_train_s, progress=False)
+        h = simpgmg.setup_hierarchy(o32, rho)
+        extra["warm_start"] = {"train": rec, **experiments.warm_vs_cold(net, h, rho, f)}
+        h.close()
+        net.close()
 
     mean_solve = float(np.mean(solve_ms))
     line = {

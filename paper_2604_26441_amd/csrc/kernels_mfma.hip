@@ -35,7 +35,10 @@
 namespace sgmg {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaWavesPerBlock = 4;
 
@@ -232,26 +235,30 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
   auto contract = [&](const In& in, f32x4& c0, f32x4& c1) {
     c0 = f32x4{0.f, 0.f, 0.f, 0.f};
     c1 = f32x4{0.f, 0.f, 0.f, 0.f};
-    bf16x8 b[NSPLIT];
+    // split the 6 inputs, as 3 pairs, into NSPLIT packed BF16 terms: one
+    // v_cvt_pk_bf16_f32 per pair and term; the FP32 value of a packed term
+    // is its half shifted into the high bits, and the residual is exact
+    u32x4 w[NSPLIT];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      float r = in.v[j];
+    for (int q = 0; q < 3; ++q) {
+      float lo = in.v[2 * q], hi = in.v[2 * q + 1];
 #pragma unroll
       for (int sp = 0; sp < NSPLIT; ++sp) {
-        const __bf16 t = (__bf16)r;
-        b[sp][j] = t;
-        r -= (float)t;
+        const f32x2 pr = {lo, hi};
+        const unsigned bits = __builtin_bit_cast(unsigned, __builtin_convertvector(pr, bf16x2));
+        w[sp][q] = bits;
+        if (sp + 1 < NSPLIT) {
+          lo -= __uint_as_float(bits << 16);
+          hi -= __uint_as_float(bits & 0xffff0000u);
+        }
       }
     }
 #pragma unroll
-    for (int sp = 0; sp < NSPLIT; ++sp) {
-      b[sp][6] = (__bf16)0.f;
-      b[sp][7] = (__bf16)0.f;
-    }
-#pragma unroll
     for (int sp = NSPLIT - 1; sp >= 0; --sp) {    // smallest terms first
-      c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b[sp], c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[sp], c1, 0, 0, 0);
+      w[sp][3] = 0u;
+      const bf16x8 b = __builtin_bit_cast(bf16x8, w[sp]);
+      c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, c1, 0, 0, 0);
     }
     c0 *= in.es;   // column n is element n, whose E / s every lane of it loaded
     c1 *= in.es;

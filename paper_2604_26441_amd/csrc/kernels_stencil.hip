@@ -211,43 +211,58 @@ void launch_stencil_to_f32(const double* S, float* S32, size_t n, hipStream_t s)
 // (S_{26-o}[n+o])^T.  The neighbour's block is that neighbour's own upper
 // block, so the second read is served from cache: about half the HBM bytes of
 // the full stencil, and the applied operator is exactly symmetric.
-// One thread per (node, output component): a block is 64 consecutive nodes x
-// 3 components, one wave per component, so every stencil load of a wave is
-// 64 consecutive values of one slot.  Three times the threads of the
-// node-per-thread form: the Galerkin levels are small (level 1 of an 80^3
-// mesh has 68,921 nodes) and need the extra waves to cover HBM latency.  The
-// block index is remapped per XCD so each L2 sees a contiguous node range.
-template <typename T>
-__global__ __launch_bounds__(192) void k_stencil_apply_c(Grid g, const T* __restrict__ S,
-                                                        const T* __restrict__ u,
-                                                        const uint8_t* __restrict__ fixn,
-                                                        Epi<T> ep) {
-  const int lane = threadIdx.x & 63, d = threadIdx.x >> 6;
+// One thread per (node, output component[, stencil plane]): a block is 64
+// consecutive nodes x 3 components (x 3 planes when NZ = 3; wave = component
+// + 3 plane), so every stencil load of a wave is 64 consecutive values of one
+// slot.  With NZ = 3 the three plane partials are added in LDS in a fixed
+// order: nine times the threads of a node-per-thread form, for the small
+// Galerkin levels (level 2 of an 80^3 mesh has 9,261 nodes) that need the
+// waves to cover memory latency; large levels are bandwidth-bound and use
+// NZ = 1.  The block index is remapped per XCD so each L2 sees a contiguous
+// node range.
+template <typename T, int NZ>
+__global__ __launch_bounds__(192 * NZ) void k_stencil_apply_c(Grid g, const T* __restrict__ S,
+                                                             const T* __restrict__ u,
+                                                             const uint8_t* __restrict__ fixn,
+                                                             Epi<T> ep) {
+  __shared__ double part[NZ][3][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int d = w % 3, pz = NZ == 1 ? 0 : w / 3;
   const int node = xcd_block(blockIdx.x, gridDim.x) * 64 + lane;
-  double dot = 0.0;
-  if (node < g.Nn) {
+  const bool in = node < g.Nn;
+  if (in) {
     const int i = node % g.Nx, t = node / g.Nx, j = t % g.Ny, k = t / g.Ny;
     const size_t Nn = g.Nn;
     T acc = (T)0;
 #pragma unroll
-    for (int o = 0; o < 27; ++o) {
+    for (int q = 0; q < 27 / NZ; ++q) {
+      const int o = NZ == 1 ? q : 9 * pz + q;
       const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-      const bool ok = (unsigned)(i + ox) < (unsigned)g.Nx && (unsigned)(j + oy) < (unsigned)g.Ny &&
-                      (unsigned)(k + oz) < (unsigned)g.Nz;
-      if (!ok) continue;
-      const int nb = node + ox + g.Nx * (oy + g.Ny * oz);
-      const size_t b3 = 3 * (size_t)nb;
-      const T u0 = u[b3], u1 = u[b3 + 1], u2 = u[b3 + 2];
-      if (o >= 13) {
-        const T* Sb = S + ((size_t)o * 9 + 3 * d) * Nn + node;
-        acc += Sb[0] * u0 + Sb[Nn] * u1 + Sb[2 * Nn] * u2;
-      } else {
-        const T* Sb = S + ((size_t)(26 - o) * 9 + d) * Nn + nb;
-        acc += Sb[0] * u0 + Sb[3 * Nn] * u1 + Sb[6 * Nn] * u2;
+      {
+        const bool ok = (unsigned)(i + ox) < (unsigned)g.Nx && (unsigned)(j + oy) < (unsigned)g.Ny &&
+                        (unsigned)(k + oz) < (unsigned)g.Nz;
+        if (!ok) continue;
+        const int nb = node + ox + g.Nx * (oy + g.Ny * oz);
+        const size_t b3 = 3 * (size_t)nb;
+        const T u0 = u[b3], u1 = u[b3 + 1], u2 = u[b3 + 2];
+        if (o >= 13) {
+          const T* Sb = S + ((size_t)o * 9 + 3 * d) * Nn + node;
+          acc += Sb[0] * u0 + Sb[Nn] * u1 + Sb[2 * Nn] * u2;
+        } else {
+          const T* Sb = S + ((size_t)(26 - o) * 9 + d) * Nn + nb;
+          acc += Sb[0] * u0 + Sb[3 * Nn] * u1 + Sb[6 * Nn] * u2;
+        }
       }
     }
+    part[pz][d][lane] = (double)acc;
+  }
+  if (NZ > 1) __syncthreads();
+  double dot = 0.0;
+  if (in && pz == NZ / 2) {
+    const double y = NZ == 1 ? part[0][d][lane]
+                             : (part[0][d][lane] + part[NZ / 2][d][lane]) + part[NZ - 1][d][lane];
     const size_t dof = 3 * (size_t)node + d;
-    dot = epilogue1(ep, dof, (fixn[node] >> d) & 1u, u[dof], (double)acc);
+    dot = epilogue1(ep, dof, (fixn[node] >> d) & 1u, u[dof], y);
   }
   if (ep.want_dot) {
     const double v[1] = {dot};
@@ -255,13 +270,19 @@ __global__ __launch_bounds__(192) void k_stencil_apply_c(Grid g, const T* __rest
   }
 }
 
+// levels with fewer nodes use the plane-split form
+constexpr int kStencilSplitNodes = 40000;
+
 size_t stencil_apply_blocks(const Grid& g) { return div_up(g.Nn, 64); }
 
 template <typename T>
 void launch_stencil_apply(const Grid& g, const T* S, const T* u, const uint8_t* fixn,
                           const Epi<T>& ep, hipStream_t s) {
   const int nb = (int)stencil_apply_blocks(g);
-  k_stencil_apply_c<T><<<nb, 192, 0, s>>>(g, S, u, fixn, ep);
+  if (g.Nn >= kStencilSplitNodes)
+    k_stencil_apply_c<T, 1><<<nb, 192, 0, s>>>(g, S, u, fixn, ep);
+  else
+    k_stencil_apply_c<T, 3><<<nb, 576, 0, s>>>(g, S, u, fixn, ep);
   if (ep.want_dot) launch_finalize(ep.ws, nb, 1, ep.dot_out, s);
 }
 template void launch_stencil_apply<double>(const Grid&, const double*, const double*,

@@ -150,13 +150,13 @@ def batch():
     print(json.dumps(rec), flush=True)
 
 
-def warmstart(n_train=2000, train_seconds=120.0, batch_size=8, lr=1e-3):
-    """Learned warm start: U-Net trained on solver-generated 32^3 random-field
-    pairs (GRF seeds 10000+, p = 3, random face loads), then 100^3 uniform and
-    random-field cantilevers solved by FP32-GMG-PCG to 1e-6 from zero and from
-    the scaled prediction (warm time includes input, network and scaling)."""
+def train_warm_start(n_train=2000, train_seconds=120.0, batch_size=8, lr=1e-3, seed=2024,
+                     progress=True):
+    """U-Net trained on solver-generated 32^3 random-field pairs (GRF seeds
+    10000+, p = 3, random face loads, FP32-GMG-PCG to 1e-8).  Returns the
+    network and a record of the data generation and training."""
     dev = "cuda:0"
-    rng = np.random.default_rng(2024)
+    rng = np.random.default_rng(seed)
     dims = (32, 32, 32)
     t0 = time.perf_counter()
     X, T, M = [], [], []
@@ -173,6 +173,8 @@ def warmstart(n_train=2000, train_seconds=120.0, batch_size=8, lr=1e-3):
         T.append(t)
         M.append(m)
         h.close()
+        if progress and (k + 1) % 250 == 0:
+            print(json.dumps({"pairs": k + 1, "s": round(time.perf_counter() - t0, 1)}), flush=True)
     X, T, M = torch.cat(X), torch.cat(T), torch.cat(M)
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
@@ -183,53 +185,70 @@ def warmstart(n_train=2000, train_seconds=120.0, batch_size=8, lr=1e-3):
         idx = torch.as_tensor(rng.choice(n_train, size=batch_size, replace=False), device=dev)
         losses.append(net.train_step(X[idx].contiguous(), T[idx].contiguous(), M[idx].contiguous(), lr=lr))
         steps += 1
+        if progress and steps % 500 == 0:
+            print(json.dumps({"step": steps, "loss": float(np.mean(losses[-50:]))}), flush=True)
     train_s = time.perf_counter() - t0
-    rec = {"n_train": n_train, "train_pairs_gen_s": gen_s, "train_solve_iters_mean": float(np.mean(iters)),
-           "train_steps": steps, "train_s": train_s, "batch": batch_size,
+    rec = {"n_train": n_train, "train_pairs_gen_s": round(gen_s, 2),
+           "train_solve_iters_mean": float(np.mean(iters)), "train_steps": steps,
+           "train_s": round(train_s, 2), "batch": batch_size,
            "loss_first10": float(np.mean(losses[:10])), "loss_last10": float(np.mean(losses[-10:])),
-           "params": simpgmg.UNet.num_params(), "tests": []}
-    del X, T, M
+           "params": simpgmg.UNet.num_params()}
+    return net, rec
+
+
+def warm_vs_cold(net, h, rho, f, rtol=1e-6, maxit=500, reps=3):
+    """Zero start against the scaled network start on hierarchy h (same
+    tolerance); warm time includes input assembly, inference and scaling."""
+    for _ in range(2):                                     # warm-up (graph capture)
+        u = torch.zeros_like(f)
+        simpgmg.pcg_solve(h, f, u, rtol=rtol, maxit=maxit)
+    cold_ms, warm_ms, net_ms = [], [], []
+    for _ in range(reps):
+        u = torch.zeros_like(f)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cold = simpgmg.pcg_solve(h, f, u, rtol=rtol, maxit=maxit)
+        torch.cuda.synchronize()
+        cold_ms.append((time.perf_counter() - t1) * 1e3)
+        t1 = time.perf_counter()
+        x = simpgmg.unet_input(h, rho, f)
+        u0 = simpgmg.unet_output(h, net.forward(x))
+        alpha = simpgmg.warm_start_scale(h, f, u0)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        warm = simpgmg.pcg_solve(h, f, u0, rtol=rtol, maxit=maxit, history_cap=1)
+        torch.cuda.synchronize()
+        warm_ms.append((time.perf_counter() - t1) * 1e3)
+        net_ms.append((t2 - t1) * 1e3)
+    return {"cold_iters": cold["iters"], "cold_status": cold["status"],
+            "cold_ms": round(float(np.mean(cold_ms)), 3),
+            "warm_iters": warm["iters"], "warm_status": warm["status"],
+            "warm_rel_res_true": warm["rel_res_true"],
+            "warm_ms_total": round(float(np.mean(warm_ms)), 3),
+            "warm_ms_network": round(float(np.mean(net_ms)), 3),
+            "warm_initial_rel_res": warm["history"][0], "alpha": alpha}
+
+
+def warmstart(n_train=2000, train_seconds=120.0):
+    """Learned warm start: the network of train_warm_start, then 100^3
+    uniform and random-field cantilevers (edge load) solved by
+    FP32-GMG-PCG to 1e-6 from zero and from the scaled prediction."""
+    dev = "cuda:0"
+    net, rec = train_warm_start(n_train, train_seconds)
+    rec["tests"] = []
     n = 100
     tdims = (n, n, n)
     cases = [("uniform", workloads.uniform_rho(tdims))] + \
             [(f"grf{s}", workloads.grf_rho(tdims, s)) for s in range(5)]
-    f_np = workloads.edge_load(tdims)
-    f = torch.tensor(f_np, dtype=torch.float64, device=dev)
+    f = torch.tensor(workloads.edge_load(tdims), dtype=torch.float64, device=dev)
     for name, rho_np in cases:
         rho = torch.tensor(rho_np, dtype=torch.float64, device=dev)
         h = simpgmg.setup_hierarchy(simpgmg.default_options(*tdims, n_levels=0), rho)
         simpgmg.autotune(h)
-        for _ in range(2):                                   # warm-up (graph capture)
-            u = torch.zeros_like(f)
-            cold = simpgmg.pcg_solve(h, f, u, rtol=1e-6, maxit=500)
-        u = torch.zeros_like(f)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        cold = simpgmg.pcg_solve(h, f, u, rtol=1e-6, maxit=500)
-        torch.cuda.synchronize()
-        cold_ms = (time.perf_counter() - t1) * 1e3
-        warm_runs = []
-        for rep in range(3):
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            x = simpgmg.unet_input(h, rho, f)
-            y = net.forward(x)
-            u0 = simpgmg.unet_output(h, y)
-            alpha = simpgmg.warm_start_scale(h, f, u0)
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            warm = simpgmg.pcg_solve(h, f, u0, rtol=1e-6, maxit=500, history_cap=1)
-            torch.cuda.synchronize()
-            t3 = time.perf_counter()
-            warm_runs.append(((t3 - t1) * 1e3, (t2 - t1) * 1e3))
-        rec["tests"].append({"case": name, "cold_iters": cold["iters"], "cold_ms": cold_ms,
-                             "cold_status": cold["status"], "warm_iters": warm["iters"],
-                             "warm_status": warm["status"], "warm_rel_res_true": warm["rel_res_true"],
-                             "warm_ms_total": float(np.mean([w[0] for w in warm_runs[1:]])),
-                             "warm_ms_network": float(np.mean([w[1] for w in warm_runs[1:]])),
-                             "warm_initial_rel_res": warm["history"][0], "alpha": alpha})
+        r = {"case": name, **warm_vs_cold(net, h, rho, f)}
+        rec["tests"].append(r)
         h.close()
-        print(json.dumps(rec["tests"][-1]), flush=True)
+        print(json.dumps(r), flush=True)
     print(json.dumps(rec), flush=True)
 
 
