@@ -39,6 +39,32 @@ def parse():
     return ap.parse_args()
 
 
+TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "fine_ku_bf16x3_80cube_traffic.md")
+KU_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2604_26441_amd", "csrc",
+                         "kernels_mfma.hip")
+
+
+def measured_traffic(shape):
+    """Calibrated HBM bytes per launch of the BF16X3 fine K.u at 80^3 for the
+    given launch shape, from the committed rocprofv3 counter summary; None if
+    the kernel source changed since the counters were taken, or the shape is
+    not in the table."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha1(open(KU_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if f"kernel_source_sha1: {src}" not in text:
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 5 and cells[0].isdigit() and (int(cells[0]), int(cells[1])) == tuple(shape):
+            return int(cells[4])
+    return None
+
+
 def cpu_baseline(n, iters_full, sample_iters=3):
     """Oracle FP64 PCG-GMG on the same n^3 workload, one thread: the first
     ``sample_iters`` PCG iterations are timed (hierarchy setup untimed) and the
@@ -166,6 +192,10 @@ def main():
         h.close()
         net.close()
 
+    traffic = None
+    if n == 80 and args.fine_prec == "bf16x3" and tuned is not None:
+        traffic = measured_traffic(tuned[1])
+
     mean_solve = float(np.mean(solve_ms))
     line = {
         "metric": "PCG-GMG solve ms at 512k elems @1e-6 rel-res; K·u HBM GB/s; iters vs warm-start",
@@ -187,7 +217,8 @@ def main():
         "ku": {"kernel": "fine K.u (sgmg_apply_K level 0)", "us": round(ku_us, 3),
                "GBs": round(achieved, 1), "GFLOPs": round(ku_flop / (ku_us * 1e-6) / 1e9, 1)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
         **extra,
     }
     if not args.no_cpu_baseline:

@@ -58,6 +58,46 @@ def sizes():
         print(json.dumps(rec), flush=True)
 
 
+def hetero(n=60, seeds=9, maxit=500):
+    """Heterogeneous 60^3 cantilevers (GRF rho, correlation length 4
+    elements, logistic map to [1e-3, 1]) for p in {1, 2, 3} and 9 seeds:
+    FP64-GMG, FP32-GMG (BF16X3 fine operator), FP32-GMG on the FP32 vector
+    ALU and BF16-GMG (flexible PCG) to rtol 1e-6, cap 500; errors against an
+    FP64-GMG solve to 1e-10 of the same system (compliance and solution)."""
+    dev = "cuda:0"
+    dims = (n, n, n)
+    f = torch.tensor(workloads.edge_load(dims), dtype=torch.float64, device=dev)
+    variants = {"fp64_gmg": {"fine_prec": "f64"}, "fp32_gmg_bf16x3": {"fine_prec": "bf16x3"},
+                "fp32_gmg_f32valu": {"fine_prec": "f32"},
+                "bf16_gmg_flex": {"fine_prec": "bf16", "flexible_beta": 1}}
+    tuned = False
+    for p in (1, 2, 3):
+        for seed in range(seeds):
+            rho = torch.tensor(workloads.grf_rho(dims, seed), dtype=torch.float64, device=dev)
+            h = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, penal=float(p), fine_prec="f64"), rho)
+            uref = torch.zeros_like(f)
+            ref = simpgmg.pcg_solve(h, f, uref, rtol=1e-10, maxit=4000)
+            h.close()
+            cref = float(f @ uref)
+            rec = {"p": p, "seed": seed, "ref": {"status": ref["status"], "iters": ref["iters"],
+                                                  "rel_res_true": ref["rel_res_true"]}}
+            for name, kw in variants.items():
+                h = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, penal=float(p), **kw), rho)
+                if not tuned and kw["fine_prec"] in ("bf16", "bf16x3"):
+                    simpgmg.autotune(h)
+                    tuned = True
+                for _ in range(2):
+                    u = torch.zeros_like(f)
+                    r = simpgmg.pcg_solve(h, f, u, rtol=1e-6, maxit=maxit)
+                c = float(f @ u)
+                rec[name] = {"status": r["status"], "iters": r["iters"], "solve_ms": round(r["solve_ms"], 3),
+                             "rel_res_true": r["rel_res_true"],
+                             "compliance_rel_err": abs(c - cref) / abs(cref),
+                             "u_rel_err": float(torch.linalg.norm(u - uref) / torch.linalg.norm(uref))}
+                h.close()
+            print(json.dumps(rec), flush=True)
+
+
 def kernels():
     dev = "cuda:0"
     for n in (40, 60, 80, 128):
@@ -252,22 +292,32 @@ def warmstart(n_train=2000, train_seconds=120.0):
     print(json.dumps(rec), flush=True)
 
 
+TRAFFIC_SHAPES = [(r, z) for r in (4, 8) for z in (2, 4, 8, 16, 32)]
+
+
 def traffic(n=80, reps=20):
-    """Workload for HBM-traffic counters: the 80^3 fine K.u (BF16X3, BF16,
-    FP64), the level-1 stencil apply, and a plain device copy of 1 GiB (the
-    calibration kernel: its FETCH_SIZE / WRITE_SIZE per dispatch are compared
-    with the 1 GiB it moves; at that size the 8 x 4 MiB of L2 cannot hold a
-    useful part of the source)."""
+    """Workload for HBM-traffic counters: the 80^3 fine K.u in BF16X3 for
+    every launch shape the autotuner can pick (TRAFFIC_SHAPES, in this order,
+    reps launches each), then BF16 and FP64 at shape (4, 4), the
+    level-1 stencil apply, and a plain device copy of 1 GiB (the calibration
+    kernel: its FETCH_SIZE / WRITE_SIZE per dispatch are compared with the
+    1 GiB it moves; at that size the 8 x 4 MiB of L2 cannot hold a useful
+    part of the source)."""
     dev = "cuda:0"
     dims = (n, n, n)
     rho = torch.tensor(workloads.uniform_rho(dims), dtype=torch.float64, device=dev)
     h = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, n_levels=4), rho)
-    shapes = simpgmg.autotune(h)
+    simpgmg.set_launch_shape(h, "bf16", 4, 4)           # no autotuning: the dispatch order
+    simpgmg.set_launch_shape(h, "f64", 4, 4)            # of the K.u launches is fixed
     fixed = torch.tensor(workloads.cantilever_fixed(dims), device=dev).bool()
     u32 = torch.ones(fixed.numel(), dtype=torch.float32, device=dev).masked_fill_(fixed, 0)
     u64 = u32.double()
     y32, y64 = torch.empty_like(u32), torch.empty_like(u64)
-    for prec, u, y in (("bf16x3", u32, y32), ("bf16", u32, y32), ("f64", u64, y64)):
+    for r, z in TRAFFIC_SHAPES:
+        simpgmg.set_launch_shape(h, "bf16x3", r, z)
+        for _ in range(reps):
+            simpgmg.apply_K(h, 0, "bf16x3", u32, y32)
+    for prec, u, y in (("bf16", u32, y32), ("f64", u64, y64)):
         for _ in range(reps):
             simpgmg.apply_K(h, 0, prec, u, y)
     info = h.level_info(1)
@@ -282,10 +332,10 @@ def traffic(n=80, reps=20):
     for _ in range(4):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"dims": dims, "shapes": shapes, "reps": reps, "copy_bytes": a.numel() * 4,
-                      "level1_nodes": n1 // 3}), flush=True)
+    print(json.dumps({"dims": dims, "reps": reps, "copy_bytes": a.numel() * 4,
+                      "bf16x3_shapes": TRAFFIC_SHAPES, "level1_nodes": n1 // 3}), flush=True)
 
 
 if __name__ == "__main__":
-    {"sizes": sizes, "kernels": kernels, "batch": batch, "warmstart": warmstart,
+    {"sizes": sizes, "hetero": hetero, "kernels": kernels, "batch": batch, "warmstart": warmstart,
      "traffic": traffic}[sys.argv[1]]()

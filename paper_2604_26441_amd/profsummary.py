@@ -2,6 +2,7 @@
 
   python -m paper_2604_26441_amd.profsummary RESULTS_DB [--match NAME --last N]
   python -m paper_2604_26441_amd.profsummary --counters COUNTER_CSV
+  python -m paper_2604_26441_amd.profsummary --traffic FETCH_CSV WRITE_CSV
 
 Prints the per-kernel totals (calls, total, average, share) and, with
 --match, the average duration of the last N dispatches whose kernel name
@@ -13,6 +14,38 @@ import argparse
 import csv
 import sqlite3
 from collections import defaultdict
+
+
+def _dispatches(path, counter):
+    rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return rows
+
+
+def traffic(fetch_csv, write_csv, reps, shapes):
+    """Per launch shape of the BF16X3 fine K.u (dispatch groups in the order
+    the traffic workload ran them), and for the 1 GiB copy: mean FETCH_SIZE
+    and WRITE_SIZE (KiB per dispatch), the calibration factors (bytes moved /
+    counter bytes, from the copy) and the calibrated HBM bytes per launch."""
+    f = _dispatches(fetch_csv, "FETCH_SIZE")
+    w = _dispatches(write_csv, "WRITE_SIZE")
+    def pick(rows, pred):
+        return [float(r["Counter_Value"]) for r in rows if pred(r["Kernel_Name"], int(r["Grid_Size"]))]
+    big_copy = lambda n, g: "copyBuffer" in n and g >= 131072
+    cf = 1048576.0 / (sum(pick(f, big_copy)) / len(pick(f, big_copy)))
+    cw = 1048576.0 / (sum(pick(w, big_copy)) / len(pick(w, big_copy)))
+    print(f"calibration: 1 GiB copy, FETCH factor {cf:.4f}, WRITE factor {cw:.4f}")
+    ku = lambda n, g: "k_apply_fine_mfma<3," in n and ", 0>" in n
+    fk, wk = pick(f, ku), pick(w, ku)
+    print("| rows | planes | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | calibrated bytes per launch |")
+    print("|---|---|---|---|---|")
+    for i, (r, z) in enumerate(shapes):
+        a = fk[i * reps:(i + 1) * reps]
+        b = wk[i * reps:(i + 1) * reps]
+        if len(a) < reps or len(b) < reps:
+            break
+        fa, wb = sum(a) / reps, sum(b) / reps
+        print(f"| {r} | {z} | {fa:.1f} | {wb:.1f} | {round(1024 * (fa * cf + wb * cw))} |")
 
 
 def counters(path):
@@ -34,12 +67,19 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("db", nargs="?")
     ap.add_argument("--counters", default=None)
+    ap.add_argument("--traffic", nargs=2, default=None, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--match", default=None)
     ap.add_argument("--last", type=int, default=200)
     ap.add_argument("--top", type=int, default=25)
     a = ap.parse_args()
     if a.counters:
         counters(a.counters)
+        return
+    if a.traffic:
+        # the shape order of experiments.TRAFFIC_SHAPES
+        shapes = [(r, z) for r in (4, 8) for z in (2, 4, 8, 16, 32)]
+        traffic(a.traffic[0], a.traffic[1], a.reps, shapes)
         return
     c = sqlite3.connect(a.db)
     rows = list(c.execute("select name, total_calls, total_duration, average, percentage "
