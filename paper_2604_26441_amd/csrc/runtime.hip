@@ -160,7 +160,7 @@ void build_gtab(const KeTables& kt, std::vector<double>& g) {
         for (int c = 0; c < 3; ++c) P[3 * a + c][3 * b + c] = w;
       }
     // G = P^T K P
-    static double KP[24][24];
+    double KP[24][24];
     for (int i = 0; i < 24; ++i)
       for (int j = 0; j < 24; ++j) {
         double s = 0.0;

@@ -148,7 +148,9 @@ def kernels():
 def batch():
     """32 uneven cantilevers (2m x m x m, m in 8..24), random-field rho, p = 3,
     1-4 face load cases each, FP32 smoothing, rtol 1e-6: one persistent launch
-    against the same items solved one after another with sgmg_pcg_solve."""
+    against the same items solved one after another with sgmg_pcg_solve, and
+    from 2, 4, 8 host threads with a stream each (after the one-after-another
+    pass, so every iteration graph is already captured)."""
     dev = "cuda:0"
     dims, rhos, item_sys, fs = workloads.batch_config()
     opts = [simpgmg.default_options(*d, n_levels=0, dense_max=1000, fine_prec="f32") for d in dims]
@@ -187,6 +189,45 @@ def batch():
     rec["sequential_iters"] = its
     rec["sequential_all_converged"] = ok
     rec["speedup_vs_sequential"] = rec["sequential_f32_ms"] / rec["batched_ms"]
+    # the same solves from host threads, one stream each (systems spread by
+    # total elements x items, largest first; a system's items stay on one
+    # stream since they share its hierarchy)
+    import threading
+    for nthreads in (2, 4, 8):
+        work = {}
+        for i, sidx in enumerate(item_sys):
+            work.setdefault(sidx, []).append(i)
+        order = sorted(work, key=lambda q: -dims[q][0] * dims[q][1] * dims[q][2] * len(work[q]))
+        lanes, load = [[] for _ in range(nthreads)], [0] * nthreads
+        for q in order:
+            k = load.index(min(load))
+            lanes[k].append(q)
+            load[k] += dims[q][0] * dims[q][1] * dims[q][2] * len(work[q])
+        streams = [torch.cuda.Stream() for _ in range(nthreads)]
+        status = []
+
+        def run(k):
+            with torch.cuda.stream(streams[k]):
+                for q in lanes[k]:
+                    for i in work[q]:
+                        u = torch.zeros_like(ft[i])
+                        r = simpgmg.pcg_solve(hs[q], ft[i], u, rtol=1e-6, maxit=300, stream=streams[k])
+                        status.append(r["status"])
+                streams[k].synchronize()
+        times = []
+        for rep in range(2):
+            status.clear()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            th = [threading.Thread(target=run, args=(k,)) for k in range(nthreads)]
+            for t in th:
+                t.start()
+            for t in th:
+                t.join()
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        rec[f"streams{nthreads}_ms"] = times[-1]
+        rec[f"streams{nthreads}_all_converged"] = all(x == "converged" for x in status) and len(status) == len(item_sys)
     print(json.dumps(rec), flush=True)
 
 
