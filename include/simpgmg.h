@@ -158,6 +158,23 @@ int sgmg_vcycle(const sgmg_hierarchy* h, const double* r, double* z, void* strea
 int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u,
                    double rtol, int maxit, sgmg_solve_info* info, void* stream);
 
+/* Restarted right-preconditioned flexible GMRES on K u = f (Sec. 3.6: the
+ * outer solver of the paper's BF16, large-scale and robustness runs), FP64.
+ * precond as for sgmg_pcg_solve (2: the V-cycle, which may use any fine
+ * precision); restart 1..63 (the paper's default 32, 50 for large scale).
+ * Each cycle starts from the FP64 true residual; step j stores
+ * z_j = M(v_j), forms w = K z_j, orthogonalises it against v_0..v_j
+ * (classical Gram-Schmidt applied twice: the j + 1 dot products of a pass
+ * are one kernel), and updates the Hessenberg QR with a Givens rotation on
+ * the host (one readback per step).  A new Hessenberg entry below 1e-14
+ * (happy breakdown), the residual estimate below rtol or `restart` steps
+ * end the cycle with x += Z y.  Converged only if the next cycle's true
+ * residual passes rtol.  info->iters counts Arnoldi steps; history holds the
+ * true relative residual at each cycle start and the estimate after each
+ * step.  Allocates (2 restart + 1) FP64 vectors on first use (kept by h). */
+int sgmg_fgmres_solve(sgmg_hierarchy* h, int precond, int restart, const double* f, double* u,
+                      double rtol, int maxit, sgmg_solve_info* info, void* stream);
+
 /* Autotuner of the MFMA fine operators' launch shape: times each candidate
  * (element rows per wave tile: 4, 8; owned node planes per wave: 2, 4, 8,
  * 16, 32) on this hierarchy's mesh for the BF16, BF16X3 and FP64 kernels,

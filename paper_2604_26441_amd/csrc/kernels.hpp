@@ -108,4 +108,14 @@ int dense_spd_inverse(double* A, int nf, double* scratch, int* d_flag, hipStream
 void launch_dense_solve(const double* Ainv, const int* free_idx, int nf, const double* r,
                         double* rc, double* z, hipStream_t s);
 
+// ---- flexible GMRES basis operations (kernels_krylov.hip) --------------------
+void launch_basis_dots(const double* V, int ncols, const double* w, int n, RedWs ws, double* h_out,
+                       hipStream_t s);
+void launch_basis_update(double* w, const double* V, int ncols, const double* h, int n,
+                         int next_dots, RedWs ws, double* out, hipStream_t s);
+void launch_scale_inv_sqrt(const double* w, double* v, const double* nrm2, int n, hipStream_t s);
+void launch_basis_combine(double* x, const double* Z, int k, const double* y, int n, hipStream_t s);
+int basis_max_cols();
+size_t basis_partials(int ncols);
+
 }  // namespace sgmg

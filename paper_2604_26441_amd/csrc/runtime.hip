@@ -87,6 +87,11 @@ struct sgmg_hierarchy {
   double* r_old = nullptr;
   double* tmp = nullptr;
   double* xs = nullptr;      // solver-owned copy of the iterate (graphs bind it)
+  // flexible GMRES: basis V (kry_cols + 1 columns), Z (kry_cols columns) and
+  // small device arrays for the Hessenberg column and y; sized on first use
+  double* kry = nullptr;
+  double* kry_small = nullptr;
+  int kry_cols = 0;
   double* gj_scratch = nullptr;
   hipStream_t cap = nullptr; // capture stream
   hipGraphExec_t iter_graph[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
@@ -553,6 +558,8 @@ void sgmg_destroy(sgmg_hierarchy* h) {
       if (g) hipGraphExecDestroy(g);
   if (h->cap) hipStreamDestroy(h->cap);
   for (void* p : h->allocs) hipFree(p);
+  if (h->kry) hipFree(h->kry);
+  if (h->kry_small) hipFree(h->kry_small);
   if (h->h_sc) hipHostFree(h->h_sc);
   delete h;
 }
@@ -918,6 +925,180 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
       const int m = std::min<int>(info->history_cap, (int)hist.size());
       for (int i = 0; i < m; ++i) info->history[i] = hist[i];
       for (int i = m; i < info->history_cap; ++i) info->history[i] = 0.0;
+    }
+  }
+  return 0;
+}
+
+int sgmg_fgmres_solve(sgmg_hierarchy* h, int precond, int restart, const double* f, double* u,
+                      double rtol, int maxit, sgmg_solve_info* info, void* stream) {
+  if (!h || !f || !u) { set_error("NULL argument"); return SGMG_EINVAL; }
+  if (precond < 0 || precond > 2 || maxit < 0) { set_error("bad precond or maxit"); return SGMG_EINVAL; }
+  if (restart < 1 || restart >= basis_max_cols()) {
+    set_error("restart must be in 1.." + std::to_string(basis_max_cols() - 1));
+    return SGMG_EINVAL;
+  }
+  hipStream_t s = as_stream(stream);
+  const Level& L0 = h->lev[0];
+  const int n = L0.g.n;
+  const int m = restart;
+  if (h->kry_cols < m) {
+    if (h->kry) hipFree(h->kry);
+    h->kry = nullptr;
+    h->kry_cols = 0;
+    if (hipMalloc(&h->kry, (size_t)(2 * m + 1) * n * sizeof(double)) != hipSuccess) {
+      h->kry = nullptr;
+      set_error("FGMRES basis allocation failed");
+      return SGMG_ENOMEM;
+    }
+    h->kry_cols = m;
+  }
+  if (!h->kry_small && hipMalloc(&h->kry_small, 4 * 64 * sizeof(double)) != hipSuccess) {
+    h->kry_small = nullptr;
+    set_error("FGMRES allocation failed");
+    return SGMG_ENOMEM;
+  }
+  double* V = h->kry;                                  // columns 0..m
+  double* Z = h->kry + (size_t)(m + 1) * n;            // columns 0..m-1
+  double* h1 = h->kry_small;                            // first Gram-Schmidt pass
+  double* h2 = h->kry_small + 64;                       // second pass
+  double* hw = h->kry_small + 128;                      // ||w||^2 ; ||r||^2 at cycle starts
+  double* yd = h->kry_small + 192;
+  double hbuf[193];
+  hipEvent_t e0, e1;
+  SGMG_HIP(hipEventCreate(&e0));
+  SGMG_HIP(hipEventCreate(&e1));
+  SGMG_HIP(hipEventRecord(e0, s));
+  auto K64 = [&](const double* x, double* y) {
+    return apply_level<double>(h, 0, SGMG_F64, x, epi_store<double>(y), s);
+  };
+  auto precondition = [&](const double* r, double* z) -> int {
+    if (precond == 2) return vcycle_full(h, r, z, s);
+    if (precond == 1) launch_apply_dinv(L0.dinv64, r, z, n, s);
+    else launch_copy(r, z, n, s);
+    return check_launch();
+  };
+  auto read = [&](const double* src, int count, double* dst) -> int {
+    SGMG_HIP(hipMemcpyAsync(dst, src, count * sizeof(double), hipMemcpyDeviceToHost, s));
+    SGMG_HIP(hipStreamSynchronize(s));
+    return 0;
+  };
+  int rc = 0, status = SGMG_MAXIT, it = 0;
+  double nf = 0.0, rel = 0.0, rel_true = -1.0;
+  std::vector<double> hist;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  auto Hat = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+  launch_copy(u, h->xs, n, s);
+  launch_dot(f, f, nullptr, n, h->ws, hw, s);
+  if ((rc = check_launch()) || (rc = read(hw, 1, hbuf))) goto done;
+  nf = std::sqrt(hbuf[0]);
+  if (nf == 0.0) {
+    SGMG_HIP(hipMemsetAsync(h->xs, 0, (size_t)n * sizeof(double), s));
+    status = SGMG_CONVERGED; rel = rel_true = 0.0;
+    hist.push_back(0.0);
+    goto done;
+  }
+  for (;;) {
+    // cycle start: true residual into V_0
+    if ((rc = K64(h->xs, h->tmp))) break;
+    launch_residual(f, h->tmp, V, n, h->ws, hw, s);
+    if ((rc = check_launch()) || (rc = read(hw, 1, hbuf))) break;
+    const double beta = std::sqrt(hbuf[0]);
+    rel = rel_true = beta / nf;
+    hist.push_back(rel);
+    if (!std::isfinite(rel)) { status = SGMG_NONFINITE; break; }
+    if (rel < rtol) { status = SGMG_CONVERGED; break; }
+    if (it >= maxit) { status = SGMG_MAXIT; break; }
+    launch_scale_inv_sqrt(V, V, hw, n, s);
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    bool bad = false;
+    for (int j = 0; j < m && it < maxit; ++j) {
+      double* vj = V + (size_t)j * n;
+      double* zj = Z + (size_t)j * n;
+      double* w = V + (size_t)(j + 1) * n;
+      if ((rc = precondition(vj, zj))) break;
+      if ((rc = K64(zj, w))) break;
+      // classical Gram-Schmidt with one reorthogonalisation (two passes)
+      launch_basis_dots(V, j + 1, w, n, h->ws, h1, s);
+      launch_basis_update(w, V, j + 1, h1, n, 1, h->ws, h2, s);
+      launch_basis_update(w, V, j + 1, h2, n, 0, h->ws, hw, s);
+      if ((rc = check_launch()) || (rc = read(h->kry_small, 129, hbuf))) break;
+      for (int i = 0; i <= j; ++i) Hat(i, j) = hbuf[i] + hbuf[64 + i];
+      const double hnext = std::sqrt(hbuf[128]);
+      Hat(j + 1, j) = hnext;
+      ++it;
+      k = j + 1;
+      for (int i = 0; i < j; ++i) {                    // earlier rotations on column j
+        const double a = Hat(i, j), b = Hat(i + 1, j);
+        Hat(i, j) = cs[i] * a + sn[i] * b;
+        Hat(i + 1, j) = -sn[i] * a + cs[i] * b;
+      }
+      const double a = Hat(j, j), b = Hat(j + 1, j);
+      const double d = std::hypot(a, b);
+      cs[j] = d > 0.0 ? a / d : 1.0;
+      sn[j] = d > 0.0 ? b / d : 0.0;
+      Hat(j, j) = d;
+      Hat(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      rel = std::fabs(g[j + 1]) / nf;
+      hist.push_back(rel);
+      if (!std::isfinite(rel)) { bad = true; break; }
+      if (hnext < 1e-14 || rel < rtol) break;
+      launch_scale_inv_sqrt(w, w, hw, n, s);
+    }
+    if (rc) break;
+    if (bad) { status = SGMG_NONFINITE; break; }
+    if (k == 0) break;
+    // R y = g (back substitution; least squares on a singular diagonal)
+    bool singular = false;
+    for (int i = 0; i < k; ++i) singular = singular || Hat(i, i) == 0.0;
+    if (!singular) {
+      for (int i = k - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int c = i + 1; c < k; ++c) t -= Hat(i, c) * y[c];
+        y[i] = t / Hat(i, i);
+      }
+    } else {
+      // rank-deficient R (an exactly vanishing rotated diagonal): a basic
+      // least-squares solution, the columns with R_ii = 0 left out
+      for (int i = k - 1; i >= 0; --i) {
+        if (Hat(i, i) == 0.0) { y[i] = 0.0; continue; }
+        double t = g[i];
+        for (int c = i + 1; c < k; ++c) t -= Hat(i, c) * y[c];
+        y[i] = t / Hat(i, i);
+      }
+    }
+    SGMG_HIP(hipMemcpyAsync(yd, y.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_basis_combine(h->xs, Z, k, yd, n, s);
+    if ((rc = check_launch())) break;
+  }
+done:
+  if (rc) {
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc;
+  }
+  launch_copy(h->xs, u, n, s);
+  SGMG_HIP(hipEventRecord(e1, s));
+  SGMG_HIP(hipStreamSynchronize(s));
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (info) {
+    info->status = status;
+    info->iters = it;
+    info->rel_res_true = rel_true;
+    info->rel_res_recur = rel;
+    info->solve_ms = ms;
+    if (info->history && info->history_cap > 0) {
+      const int mm = std::min<int>(info->history_cap, (int)hist.size());
+      for (int i = 0; i < mm; ++i) info->history[i] = hist[i];
+      for (int i = mm; i < info->history_cap; ++i) info->history[i] = 0.0;
     }
   }
   return 0;

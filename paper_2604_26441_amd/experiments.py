@@ -98,6 +98,53 @@ def hetero(n=60, seeds=9, maxit=500):
             print(json.dumps(rec), flush=True)
 
 
+def large(trials=5, warmup=2):
+    """The paper's large-scale table (Table e7) like for like: 2:1:1 boxes
+    100x50x25 (125k), 160x80x40 (512k), 200x100x50 (1M) with uniform modulus
+    E_e = 0.5, FP32-GMG (fine K.u BF16X3 on MFMA), 4 levels, restarted FGMRES
+    (restart 50), rtol 1e-6; setup and solve wall times, iterations, the
+    device-memory delta of the setup; PCG on the same systems beside it."""
+    dev = "cuda:0"
+    for dims in ((100, 50, 25), (160, 80, 40), (200, 100, 50)):
+        nel = dims[0] * dims[1] * dims[2]
+        E = torch.full((nel,), 0.5, dtype=torch.float64, device=dev)
+        f = torch.tensor(workloads.edge_load(dims), dtype=torch.float64, device=dev)
+        o = simpgmg.default_options(*dims, n_levels=4, fine_prec="bf16x3", input_is_modulus=1)
+        h = simpgmg.setup_hierarchy(o, E)
+        simpgmg.autotune(h)
+        h.close()
+        rec = {"dims": dims, "elements": nel}
+        for solver in ("fgmres50", "pcg"):
+            setups, solves, its, st, mem = [], [], [], [], []
+            for k in range(warmup + trials):
+                torch.cuda.synchronize()
+                free0 = torch.cuda.mem_get_info()[0]
+                t0 = time.perf_counter()
+                h = simpgmg.setup_hierarchy(o, E)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                free1 = torch.cuda.mem_get_info()[0]
+                u = torch.zeros_like(f)
+                if solver == "pcg":
+                    r = simpgmg.pcg_solve(h, f, u, rtol=1e-6, maxit=500)
+                else:
+                    r = simpgmg.fgmres_solve(h, f, u, rtol=1e-6, maxit=500, restart=50)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                if k >= warmup:
+                    setups.append((t1 - t0) * 1e3)
+                    solves.append((t2 - t1) * 1e3)
+                    its.append(r["iters"])
+                    st.append(r["status"])
+                    mem.append((free0 - free1) / 2**20)
+                h.close()
+            rec[solver] = {"setup_ms_mean": float(np.mean(setups)), "setup_ms_std": float(np.std(setups)),
+                           "solve_ms_mean": float(np.mean(solves)), "solve_ms_std": float(np.std(solves)),
+                           "iters": its[-1], "status": st[-1], "rel_res_true": r["rel_res_true"],
+                           "setup_mem_MiB": float(np.mean(mem))}
+        print(json.dumps(rec), flush=True)
+
+
 def kernels():
     dev = "cuda:0"
     for n in (40, 60, 80, 128):
@@ -378,5 +425,5 @@ def traffic(n=80, reps=20):
 
 
 if __name__ == "__main__":
-    {"sizes": sizes, "hetero": hetero, "kernels": kernels, "batch": batch, "warmstart": warmstart,
-     "traffic": traffic}[sys.argv[1]]()
+    {"sizes": sizes, "hetero": hetero, "large": large, "kernels": kernels, "batch": batch,
+     "warmstart": warmstart, "traffic": traffic}[sys.argv[1]]()

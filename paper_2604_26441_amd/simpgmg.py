@@ -56,7 +56,7 @@ class SolveInfo(ctypes.Structure):
 
 EXPORTS = [
     "sgmg_default_options", "sgmg_setup_hierarchy", "sgmg_update_moduli", "sgmg_apply_K",
-    "sgmg_vcycle", "sgmg_pcg_solve", "sgmg_num_levels", "sgmg_level_info",
+    "sgmg_vcycle", "sgmg_pcg_solve", "sgmg_fgmres_solve", "sgmg_num_levels", "sgmg_level_info",
     "sgmg_copy_stencil", "sgmg_copy_diagonal", "sgmg_destroy", "sgmg_last_error",
     "sgmg_autotune", "sgmg_set_launch_shape", "sgmg_setup_batch", "sgmg_pcg_solve_batch", "sgmg_batch_hierarchy",
     "sgmg_batch_block_size", "sgmg_batch_destroy",
@@ -79,6 +79,7 @@ def _load():
     lib.sgmg_apply_K.argtypes = [H, i, i, vp, vp, vp]
     lib.sgmg_vcycle.argtypes = [H, vp, vp, vp]
     lib.sgmg_pcg_solve.argtypes = [H, i, vp, vp, d, i, ctypes.POINTER(SolveInfo), vp]
+    lib.sgmg_fgmres_solve.argtypes = [H, i, i, vp, vp, d, i, ctypes.POINTER(SolveInfo), vp]
     lib.sgmg_autotune.argtypes = [H, ctypes.POINTER(ctypes.c_int), vp]
     lib.sgmg_set_launch_shape.argtypes = [H, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.sgmg_setup_batch.argtypes = [i, ctypes.POINTER(Options), ctypes.POINTER(vp),
@@ -323,6 +324,28 @@ class Batch:
     def block_size(self):
         return _lib.sgmg_batch_block_size(self._b)
 
+
+
+def fgmres_solve(h, f, u, rtol=1e-6, maxit=200, restart=32, precond=PRECOND_VCYCLE, history_cap=0,
+                 stream=None):
+    """Restarted right-preconditioned flexible GMRES (see sgmg_fgmres_solve);
+    same return fields as pcg_solve, iters = Arnoldi steps, history = true
+    relative residual at each cycle start and the estimate after each step."""
+    info = SolveInfo()
+    hist = None
+    if history_cap:
+        hist = (ctypes.c_double * history_cap)()
+        info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+        info.history_cap = history_cap
+    _check(_lib.sgmg_fgmres_solve(h.handle, precond, restart, _ptr(f, torch.float64, h.n_dof, "f"),
+                                  _ptr(u, torch.float64, h.n_dof, "u"), rtol, maxit, ctypes.byref(info),
+                                  _stream(stream)))
+    out = {"status": STATUS.get(info.status, info.status), "status_code": info.status,
+           "iters": info.iters, "rel_res_true": info.rel_res_true,
+           "rel_res_recur": info.rel_res_recur, "solve_ms": info.solve_ms}
+    if hist is not None:
+        out["history"] = list(hist)
+    return out
 
 def setup_batch(opts_list, rho_list, fixed_list=None, stream=None):
     n = len(opts_list)
