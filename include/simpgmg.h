@@ -81,7 +81,8 @@ typedef struct {
   int input_is_modulus;      /* 0: the setup array is rho (SIMP map applied);
                                 1: it is E_e directly                                */
   int n_levels;              /* >= 2; 0 = fewest levels whose coarsest free-DOF
-                                count is <= dense_max (at most 8)                    */
+                                count is <= dense_max (at most 8; if none is, all
+                                levels down to one element per axis)                 */
   int fine_smoother;         /* 0 Chebyshev (Alg. cheb), 1 damped Jacobi             */
   int fine_degree;           /* Chebyshev degree / Jacobi sweeps on level 0 (2)      */
   int coarse_sweeps;         /* damped-Jacobi pre and post sweeps on levels >= 1 (2) */
@@ -93,7 +94,8 @@ typedef struct {
   sgmg_prec fine_prec;       /* level-0 smoother/residual arithmetic                 */
   sgmg_prec level1_prec;     /* F64 or F32: storage and arithmetic of level 1        */
   int dense_max;             /* coarsest dense-solve limit on free DOFs (5000)       */
-  int coarse_pcg_iters;      /* reserved: iterative coarsest solve (80)              */
+  int coarse_pcg_iters;      /* Jacobi-PCG steps of the coarsest solve when its
+                                free-DOF count exceeds dense_max (80)                */
   uint64_t seed;             /* power-iteration start vector: SplitMix64(seed+level) */
   int flexible_beta;         /* 1: Polak-Ribiere beta in PCG, 0: Fletcher-Reeves     */
   int stag_window;           /* 0 = off; else stagnation window in iterations        */
@@ -130,8 +132,12 @@ void sgmg_default_options(sgmg_options* o, int nx, int ny, int nz);
  * Work: SIMP map, masks by injection, diagonals, level-1 local Galerkin
  * aggregation, deeper Galerkin products, power iterations, coarsest dense
  * factorisation (explicit inverse of K_L + eps I, eps = max(mean diag * 1e-8,
- * 1e-14)).  Returns SGMG_EINVAL if a coarse level would have no elements or
- * the coarsest free-DOF count exceeds dense_max. */
+ * 1e-14)).  When the coarsest free-DOF count exceeds dense_max, the coarsest
+ * solve is instead coarse_pcg_iters steps of Jacobi-PCG on K_L from zero,
+ * stopping early only on p.Kp <= 0 or r.z = 0 (Sec. 3.2, Table
+ * repro_defaults); one workgroup runs them in one launch.  Returns SGMG_EINVAL
+ * if a coarse level would have no elements, or if the iterative coarsest
+ * solve is needed and coarse_pcg_iters < 1. */
 int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E,
                          const uint8_t* fixed_dof, void* stream, sgmg_hierarchy** out);
 
@@ -219,7 +225,9 @@ typedef struct sgmg_batch sgmg_batch;
  *   opts      : host array of nsys options (each with its own mesh).
  *   rho_or_E  : host array of nsys device pointers (element fields).
  *   fixed_dof : host array of nsys device masks, NULL entries (or NULL) for
- *               the cantilever clamp.                                      */
+ *               the cantilever clamp.
+ * Returns SGMG_EINVAL if a system's coarsest level exceeds dense_max (the
+ * batched V-cycle has only the dense coarsest solve).                      */
 int sgmg_setup_batch(int nsys, const sgmg_options* opts, const double* const* rho_or_E,
                      const uint8_t* const* fixed_dof, void* stream, sgmg_batch** out);
 

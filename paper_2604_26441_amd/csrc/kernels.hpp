@@ -108,6 +108,14 @@ int dense_spd_inverse(double* A, int nf, double* scratch, int* d_flag, hipStream
 void launch_dense_solve(const double* Ainv, const int* free_idx, int nf, const double* r,
                         double* rc, double* z, hipStream_t s);
 
+// Fixed-count Jacobi-PCG on the coarsest stencil from x = 0: 1 + 2 iters
+// launches; r, z, the ping-pong pair p0/p1 and q each g.n doubles; scratch
+// holds coarse_pcg_scratch(g, iters) doubles and done iters + 1 ints.
+size_t coarse_pcg_scratch(const Grid& g, int iters);
+void launch_coarse_pcg(const Grid& g, const double* S, const double* dinv, const uint8_t* fixn,
+                       const double* b, double* x, double* r, double* z, double* p0, double* p1,
+                       double* q, double* scratch, int* done, int iters, hipStream_t s);
+
 // ---- flexible GMRES basis operations (kernels_krylov.hip) --------------------
 void launch_basis_dots(const double* V, int ncols, const double* w, int n, RedWs ws, double* h_out,
                        hipStream_t s);

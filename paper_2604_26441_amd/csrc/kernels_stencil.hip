@@ -417,4 +417,182 @@ template void launch_prolong_add<double, double>(const Grid&, const Grid&, const
 template void launch_prolong_add<double, float>(const Grid&, const Grid&, const float*,
                                                 const uint8_t*, double*, hipStream_t);
 
+// ---------------------------------------------------------------------------
+// Iterative coarsest solve (Sec. 3.2; Table repro_defaults: above the dense
+// cutoff, a fixed number of PCG steps): Jacobi-preconditioned CG on the
+// coarsest stencil from x = 0, `iters` steps, stopping early only when
+// p.Kp <= 0 or r.z = 0.
+//
+// Each step is two launches over the whole chip (a single workgroup would
+// stream the coarsest stencil through one CU).  Every reduction is written
+// as per-block partials into a slot of its own step, and every block of the
+// next launch re-sums those partials in one fixed order, so all blocks see
+// bit-identical scalars and take the same early-stop decision without any
+// grid-wide synchronisation or host round trip:
+//   prz[k][b]  block partials of r_k . z_k, z_k = D^-1 r_k   (k = 0..iters)
+//   ppq[k][b]  block partials of p_k . K p_k                  (k = 0..iters-1)
+//   done[k]    1 when an earlier step stopped; later steps change nothing.
+// The apply launch forms p_k = z_k + beta_k p_{k-1} (beta_k = rz_k / rz_{k-1};
+// p_0 = z_0) on the fly for its node and the 26 neighbours, writes p_k into
+// the other half of a ping-pong pair and q = K p_k; the update launch forms
+// x += a p_k, r -= a q, z = D^-1 r with a = rz_k / pq_k.  Both kernels issue
+// their vector and stencil loads before they read the flag and the partials,
+// so the chain of dependent memory round trips per launch stays short.
+
+// Sum of n values in a fixed order: lane-strided partial sums, then the
+// butterfly (every lane of every wave ends with the same bits).
+__device__ inline double wave_total(const double* __restrict__ v, int n) {
+  double t = 0.0;
+  for (int i = threadIdx.x & 63; i < n; i += 64) t += v[i];
+  return wave_sum(t);
+}
+
+__global__ __launch_bounds__(256) void k_cpcg_init(int n, const double* __restrict__ b,
+                                                   const double* __restrict__ dinv,
+                                                   double* __restrict__ x, double* __restrict__ r,
+                                                   double* __restrict__ z,
+                                                   double* __restrict__ prz, int* __restrict__ done) {
+  __shared__ double lds[16];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double part = 0.0;
+  if (i < n) {
+    const double ri = b[i], zi = dinv[i] * ri;
+    x[i] = 0.0;
+    r[i] = ri;
+    z[i] = zi;
+    part = ri * zi;
+  }
+  const double t = block_sum(part, lds);
+  if (threadIdx.x == 0) {
+    prz[blockIdx.x] = t;
+    if (blockIdx.x == 0) done[0] = 0;
+  }
+}
+
+// 576 threads: 64 nodes x 3 rows x 3 groups of 9 stencil offsets.  Offsets
+// outside the grid read the node itself (a valid address) and add nothing.
+// K p_k is accumulated as K z_k + beta_k (K p_{k-1}) (the same product up
+// to rounding), so the stencil and vector loads need no beta and are all in
+// flight before the partials that give beta arrive.  Step 0 passes pold = z
+// and beta = 0: fma(0, z, z) = z exactly.
+__global__ __launch_bounds__(576) void k_cpcg_apply(Grid g, const double* __restrict__ S,
+                                                    const uint8_t* __restrict__ fixn,
+                                                    const double* __restrict__ z,
+                                                    const double* __restrict__ pold,
+                                                    double* __restrict__ pnew, double* __restrict__ q,
+                                                    const double* __restrict__ prz,
+                                                    double* __restrict__ ppq,
+                                                    const int* __restrict__ done, int k, int nbu) {
+  __shared__ double part[2][3][3][64];
+  __shared__ double lds[16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int d = w % 3, pz = w / 3;
+  const int node0 = blockIdx.x * 64 + lane;
+  const bool in = node0 < g.Nn;
+  const int node = in ? node0 : g.Nn - 1;
+  const int i = node % g.Nx, t = node / g.Nx, j = t % g.Ny, kk = t / g.Ny;
+  const size_t Nn = g.Nn;
+  double az = 0.0, ap = 0.0;
+#pragma unroll
+  for (int qq = 0; qq < 9; ++qq) {
+    const int o = 9 * pz + qq;
+    const int ox = qq % 3 - 1, oy = qq / 3 - 1, oz = pz - 1;
+    const bool ok = (unsigned)(i + ox) < (unsigned)g.Nx && (unsigned)(j + oy) < (unsigned)g.Ny &&
+                    (unsigned)(kk + oz) < (unsigned)g.Nz;
+    const int nb = ok ? node + ox + g.Nx * (oy + g.Ny * oz) : node;
+    const size_t b3 = 3 * (size_t)nb;
+    // upper blocks from the node, lower blocks mirrored from the neighbour
+    const double* Sb = o >= 13 ? S + ((size_t)o * 9 + 3 * d) * Nn + node
+                               : S + ((size_t)(26 - o) * 9 + d) * Nn + nb;
+    const size_t st = o >= 13 ? Nn : 3 * Nn;
+    double vz = 0.0, vp = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double cf = Sb[c * st];
+      vz += cf * z[b3 + c];
+      vp += cf * pold[b3 + c];
+    }
+    az += ok ? vz : 0.0;
+    ap += ok ? vp : 0.0;
+  }
+  part[0][pz][d][lane] = az;
+  part[1][pz][d][lane] = ap;
+  const size_t dof = 3 * (size_t)node + d;
+  const double zown = z[dof], pold_own = pold[dof];
+  const unsigned fx = fixn[node];
+  const bool stop = done[k] != 0;
+  const double beta = k > 0 ? wave_total(prz + (size_t)k * nbu, nbu) /
+                                  wave_total(prz + (size_t)(k - 1) * nbu, nbu)
+                            : 0.0;
+  if (stop) return;                                   // uniform over the grid
+  __syncthreads();
+  double dot = 0.0;
+  if (in && pz == 1) {
+    const double kz = (part[0][0][d][lane] + part[0][1][d][lane]) + part[0][2][d][lane];
+    const double kp = (part[1][0][d][lane] + part[1][1][d][lane]) + part[1][2][d][lane];
+    const double pown = __builtin_fma(beta, pold_own, zown);
+    const double y = (fx >> d) & 1u ? 0.0 : __builtin_fma(beta, kp, kz);
+    pnew[dof] = pown;
+    q[dof] = y;
+    dot = pown * y;
+  }
+  const double tot = block_sum(dot, lds);
+  if (threadIdx.x == 0) ppq[(size_t)k * gridDim.x + blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_cpcg_update(int n, const double* __restrict__ dinv,
+                                                     double* __restrict__ x, double* __restrict__ r,
+                                                     double* __restrict__ z,
+                                                     const double* __restrict__ p,
+                                                     const double* __restrict__ q,
+                                                     double* __restrict__ prz,
+                                                     const double* __restrict__ ppq,
+                                                     int* __restrict__ done, int k, int nba) {
+  __shared__ double lds[16];
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  const int i0 = blockIdx.x * 256 + threadIdx.x;
+  const bool in = i0 < n;
+  const int i = in ? i0 : n - 1;
+  const double xi = x[i], pi = p[i], qi = q[i], ri = r[i], di = dinv[i];
+  const bool was_done = done[k] != 0;
+  const double pq = wave_total(ppq + (size_t)k * nba, nba);
+  const double rz = wave_total(prz + (size_t)k * gridDim.x, gridDim.x);
+  if (was_done || !(pq > 0.0) || rz == 0.0) {         // uniform over the grid
+    if (lead) done[k + 1] = 1;
+    return;
+  }
+  const double a = rz / pq;
+  double part = 0.0;
+  if (in) {
+    const double rn = ri - a * qi, zn = di * rn;
+    x[i] = xi + a * pi;
+    r[i] = rn;
+    z[i] = zn;
+    part = rn * zn;
+  }
+  const double t = block_sum(part, lds);
+  if (threadIdx.x == 0) prz[(size_t)(k + 1) * gridDim.x + blockIdx.x] = t;
+  if (lead) done[k + 1] = 0;
+}
+
+size_t coarse_pcg_scratch(const Grid& g, int iters) {
+  const size_t nbu = div_up(g.n, 256), nba = div_up(g.Nn, 64);
+  return (size_t)(iters + 1) * nbu + (size_t)iters * nba;
+}
+
+void launch_coarse_pcg(const Grid& g, const double* S, const double* dinv, const uint8_t* fixn,
+                       const double* b, double* x, double* r, double* z, double* p0, double* p1,
+                       double* q, double* scratch, int* done, int iters, hipStream_t s) {
+  const int nbu = (int)div_up(g.n, 256), nba = (int)div_up(g.Nn, 64);
+  double* prz = scratch;
+  double* ppq = scratch + (size_t)(iters + 1) * nbu;
+  k_cpcg_init<<<nbu, 256, 0, s>>>(g.n, b, dinv, x, r, z, prz, done);
+  double* pp[2] = {p0, p1};
+  for (int k = 0; k < iters; ++k) {
+    const double* pold = k == 0 ? z : pp[(k + 1) & 1];
+    k_cpcg_apply<<<nba, 576, 0, s>>>(g, S, fixn, z, pold, pp[k & 1], q, prz, ppq, done, k, nbu);
+    k_cpcg_update<<<nbu, 256, 0, s>>>(g.n, dinv, x, r, z, pp[k & 1], q, prz, ppq, done, k, nba);
+  }
+}
+
 }  // namespace sgmg

@@ -76,6 +76,10 @@ struct sgmg_hierarchy {
   double* Ainv = nullptr;
   double* rc = nullptr;
   double coarse_eps = 0.0;
+  bool coarse_iter = false;  // coarsest solve: fixed-count PCG instead of the dense inverse
+  double* cpcg_p = nullptr;  // its second search direction and z (2 n), per-step partials, flags
+  double* cpcg_scratch = nullptr;
+  int* cpcg_done = nullptr;
   RedWs ws{};
   double* sc = nullptr;
   double* h_sc = nullptr;    // pinned mirror of sc
@@ -336,7 +340,7 @@ int assemble_operators(sgmg_hierarchy* h, const double* rho_or_E, hipStream_t s)
   // coarsest: dense K_L + eps I and its explicit inverse
   Level& C = h->lev[h->L - 1];
   const int nf = h->nL;
-  if (nf > 0) {
+  if (nf > 0 && !h->coarse_iter) {
     launch_dense_assemble(C.g, C.S64, h->free_idx, nf, h->Ainv, s);
     launch_dense_diag_sum(h->Ainv, nf, h->ws, h->sc + SC_DSUM, s);
     launch_dense_add_diag(h->Ainv, nf, h->sc + SC_DSUM, s, h->sc + SC_EPS);
@@ -477,7 +481,14 @@ int smooth_and_recurse(const sgmg_hierarchy* h, int l, int* cur, double* out64, 
 int vcycle_level(const sgmg_hierarchy* h, int l, int* cur, double* out64, hipStream_t s) {
   const Level& L = h->lev[l];
   if (l == h->L - 1) {
-    launch_dense_solve(h->Ainv, h->free_idx, h->nL, (const double*)L.b, h->rc, (double*)L.x[0], s);
+    if (h->coarse_iter)
+      launch_coarse_pcg(L.g, L.S64, L.dinv64, L.fixn, (const double*)L.b, (double*)L.x[0],
+                        (double*)L.r, h->cpcg_p + L.g.n, (double*)L.dv, h->cpcg_p, (double*)L.x[1],
+                        h->cpcg_scratch,
+                        h->cpcg_done, h->o.coarse_pcg_iters, s);
+    else
+      launch_dense_solve(h->Ainv, h->free_idx, h->nL, (const double*)L.b, h->rc,
+                         (double*)L.x[0], s);
     *cur = 0;
     return check_launch();
   }
@@ -628,9 +639,11 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
     for (int k = 2; k <= (int)grids.size(); ++k)
       if (nfree[k - 1] <= opts->dense_max) { L = k; break; }
   }
-  if (nfree[L - 1] > opts->dense_max) {
+  // Above the dense cutoff the coarsest solve is fixed-count PCG (Sec. 3.2).
+  h->coarse_iter = nfree[L - 1] > opts->dense_max;
+  if (h->coarse_iter && opts->coarse_pcg_iters < 1) {
     set_error("coarsest level has " + std::to_string(nfree[L - 1]) +
-              " free DOFs, more than dense_max; add levels");
+              " free DOFs, more than dense_max, and coarse_pcg_iters < 1");
     return fail(SGMG_EINVAL);
   }
   h->L = L;
@@ -710,13 +723,22 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
     for (int i = 0; i < C.g.n; ++i)
       if (!((fx[i / 3] >> (i % 3)) & 1)) idx.push_back(i);
     h->nL = (int)idx.size();
+    const size_t nd = h->coarse_iter ? 1 : (size_t)std::max(h->nL, 1);  // dense-solve sizes
     if ((rc = dalloc_t(h, &h->free_idx, std::max<size_t>(idx.size(), 1))) ||
-        (rc = dalloc_t(h, &h->Ainv, std::max<size_t>((size_t)h->nL * h->nL, 1))) ||
+        (rc = dalloc_t(h, &h->Ainv, nd * nd)) ||
         (rc = dalloc_t(h, &h->rc, std::max(h->nL, 1))) ||
-        (rc = dalloc_t(h, &h->gj_scratch, (size_t)std::max(h->nL, 1) * 64 + 64 * 64)))
+        (rc = dalloc_t(h, &h->gj_scratch, nd * 64 + 64 * 64)))
       return fail(rc);
     if (!idx.empty())
       hipMemcpyAsync(h->free_idx, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  }
+  if (h->coarse_iter) {
+    const Grid& cg = h->lev[L - 1].g;
+    const int it = opts->coarse_pcg_iters;
+    if ((rc = dalloc_t(h, &h->cpcg_p, 2 * (size_t)cg.n)) ||
+        (rc = dalloc_t(h, &h->cpcg_scratch, coarse_pcg_scratch(cg, it))) ||
+        (rc = dalloc_t(h, &h->cpcg_done, (size_t)it + 1)))
+      return fail(rc);
   }
   if ((rc = assemble_operators(h, rho_or_E, s))) return fail(rc);
   if (opts->lambda_override) h->o.lambda_override = opts->lambda_override;
@@ -1437,6 +1459,11 @@ int sgmg_setup_batch(int nsys, const sgmg_options* opts, const double* const* rh
                                         stream, &h);
     if (rc) { sgmg_batch_destroy(b); return rc; }
     b->hs.push_back(h);
+    if (h->coarse_iter) {
+      sgmg_batch_destroy(b);
+      set_error("batched systems need a dense coarsest solve (coarsest free DOFs <= dense_max)");
+      return SGMG_EINVAL;
+    }
   }
   std::vector<BSys> hsys;
   for (auto* h : b->hs) hsys.push_back(make_bsys(h));

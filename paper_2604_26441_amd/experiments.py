@@ -112,8 +112,10 @@ def large(trials=5, warmup=2):
         o = simpgmg.default_options(*dims, n_levels=4, fine_prec="bf16x3", input_is_modulus=1)
         h = simpgmg.setup_hierarchy(o, E)
         simpgmg.autotune(h)
+        nfc = h.level_info(3)["n_free"]
         h.close()
-        rec = {"dims": dims, "elements": nel}
+        rec = {"dims": dims, "elements": nel, "coarsest_free_dofs": nfc,
+               "coarsest_solve": "dense" if nfc <= o.dense_max else f"pcg{o.coarse_pcg_iters}"}
         for solver in ("fgmres50", "pcg"):
             setups, solves, its, st, mem = [], [], [], [], []
             for k in range(warmup + trials):

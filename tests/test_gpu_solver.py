@@ -163,3 +163,58 @@ def test_graph_replay_equals_direct_launches(prec):
         assert it == out[0][0]
         assert hist == out[0][1]
         assert np.array_equal(x, out[0][2])
+
+
+@pytest.mark.parametrize("dims,L,dense_max,iters", [((16, 8, 8), 3, 10, 1), ((16, 8, 8), 3, 10, 3),
+                                                    ((16, 8, 8), 3, 10, 80), ((24, 12, 12), 3, 100, 80),
+                                                    ((9, 7, 5), 2, 10, 20)])
+def test_vcycle_iterative_coarsest_matches_oracle(dims, L, dense_max, iters):
+    """Coarsest free DOFs above dense_max: fixed-count Jacobi-PCG on K_L."""
+    g = np.random.default_rng(4)
+    rho = g.uniform(0.1, 1.0, np.prod(dims))
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    oh = multigrid.build(dims, mesh.simp_modulus(rho, 3), fixed, multigrid.Options(
+        n_levels=L, dense_max=dense_max, coarse_pcg_iters=iters))
+    assert oh.coarse_chol is None
+    from paper_2604_26441_amd import simpgmg
+    o = simpgmg.default_options(*dims, n_levels=L, fine_prec="f64", dense_max=dense_max,
+                                coarse_pcg_iters=iters)
+    h = simpgmg.setup_hierarchy(o, t64(rho), lambda_override=[lv.lam for lv in oh.levels[:-1]])
+    r = workloads.random_vector(fixed.size, 6, fixed)
+    z = t64(np.zeros_like(r))
+    simpgmg.vcycle(h, t64(r), z)
+    ref = multigrid.vcycle(oh, r)
+    # CG iterates of two summation orders drift apart by rounding over many steps
+    assert rel_err(np64(z), ref, ref) < (1e-11 if iters <= 3 else 1e-8)
+    z2 = t64(np.zeros_like(r))
+    simpgmg.vcycle(h, t64(r), z2)                     # reruns from the same state
+    assert np.array_equal(np64(z2), np64(z))
+
+
+def test_pcg_with_iterative_coarsest_converges_like_oracle():
+    from paper_2604_26441_amd import simpgmg
+    dims = (32, 16, 16)
+    rho = workloads.uniform_rho(dims)
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    f = workloads.edge_load(dims)
+    E = mesh.simp_modulus(rho, 3)
+    K = mesh.assemble(dims, E, fixed=fixed)
+    oh = multigrid.build(dims, E, fixed, multigrid.Options(n_levels=3, dense_max=200))
+    assert oh.coarse_chol is None
+    _, st, it_o, _ = krylov.pcg(lambda v: K @ v, f, lambda r: multigrid.vcycle(oh, r),
+                                rtol=1e-6, maxit=200)
+    o = simpgmg.default_options(*dims, n_levels=3, fine_prec="f64", dense_max=200)
+    h = simpgmg.setup_hierarchy(o, t64(rho), lambda_override=[lv.lam for lv in oh.levels[:-1]])
+    u = t64(np.zeros_like(f))
+    res = simpgmg.pcg_solve(h, t64(f), u, rtol=1e-6, maxit=200)
+    assert st == krylov.CONVERGED and res["status"] == "converged"
+    assert abs(res["iters"] - it_o) <= 1
+    assert krylov.true_rel_residual(lambda v: K @ v, f, np64(u)) < 1e-6
+
+
+def test_batch_rejects_iterative_coarsest():
+    from paper_2604_26441_amd import simpgmg
+    dims = (16, 8, 8)
+    o = simpgmg.default_options(*dims, n_levels=3, dense_max=10)
+    with pytest.raises(simpgmg.SimpGmgError, match="dense coarsest"):
+        simpgmg.setup_batch([o], [t64(workloads.uniform_rho(dims))])
