@@ -25,8 +25,10 @@ lie in [lambda_min, lambda_max] of M K and move outwards as m grows, so
 kappa_m = theta_max / theta_min is a lower estimate of kappa_eff.
 
 Readings (the paper gives neither): no reorthogonalisation; m steps (50 by
-default), ending earlier when b_{j+1} <= breakdown * b_1 (an invariant
-subspace) or when r . z is not positive (M not SPD to rounding); the start
+default), ending earlier when b_{j+1} <= breakdown * max_i<=j |a_i| (an
+invariant subspace, measured against the spectral scale, so that the rule
+does not depend on the length of g) or when r . z is not positive (M not SPD
+to rounding); the start
 vector is the caller's (a seeded Gaussian on the free DOFs: the paper's
 CuPy draw cannot be reproduced).
 """
@@ -48,6 +50,7 @@ def lanczos(apply_A, precond, g, m=50, breakdown=1e-12):
     v, w = z / b1, r / b1
     w_prev = np.zeros_like(w)
     b = 0.0
+    amax = 0.0
     alpha, beta = [], []
     for _ in range(m):
         s = apply_A(v)
@@ -56,9 +59,10 @@ def lanczos(apply_A, precond, g, m=50, breakdown=1e-12):
         z = M(r)
         rz = float(r @ z)
         alpha.append(a)
+        amax = max(amax, abs(a))
         bn = np.sqrt(rz) if rz > 0.0 else 0.0
         beta.append(bn)
-        if not bn > breakdown * b1:
+        if not bn > breakdown * amax:
             break
         w_prev, w, v, b = w, r / bn, z / bn, bn
     return np.array(alpha), np.array(beta)

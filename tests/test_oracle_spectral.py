@@ -120,3 +120,12 @@ def test_breakdown_on_an_eigenvector_and_scale_invariance():
     a2, b2 = spectral.lanczos(lambda v: K @ v, None, 1e3 * g2, m=8)
     np.testing.assert_allclose(a2, a1, rtol=1e-12)
     np.testing.assert_allclose(b2, b1, rtol=1e-12)
+
+
+def test_breakdown_rule_does_not_depend_on_start_length():
+    K, h, fixed = _system((6, 4, 4), seed=4)
+    M = lambda r: multigrid.vcycle(h, r)
+    g = _start(fixed, 6)
+    a1, _ = spectral.lanczos(lambda v: K @ v, M, g, m=40, breakdown=0.18)
+    a2, _ = spectral.lanczos(lambda v: K @ v, M, 1e-6 * g, m=40, breakdown=0.18)
+    assert 1 < len(a1) < 40 and len(a2) == len(a1)
