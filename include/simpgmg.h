@@ -181,6 +181,29 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u,
 int sgmg_fgmres_solve(sgmg_hierarchy* h, int precond, int restart, const double* f, double* u,
                       double rtol, int maxit, sgmg_solve_info* info, void* stream);
 
+/* Lanczos probe of the preconditioned operator M K (Sec. 4: the kappa_eff
+ * screen of the robustness and BF16 spectral-proxy runs; Eq. kappa_bound).
+ * M as for sgmg_pcg_solve (precond 0 none, 1 Jacobi, 2 the V-cycle in the
+ * hierarchy's precision), K the FP64 fine operator.  Runs the preconditioned
+ * Lanczos process in the M^-1 inner product, carrying w_j = M^-1 v_j:
+ *   r_1 = g, z_1 = M r_1, b_1 = sqrt(r_1.z_1), v_1 = z_1/b_1, w_1 = r_1/b_1;
+ *   s = K v_j, a_j = s.v_j, r = s - a_j w_j - b_j w_{j-1}, z = M r,
+ *   b_{j+1} = sqrt(r.z), v_{j+1} = z/b_{j+1}, w_{j+1} = r/b_{j+1};
+ * without reorthogonalisation, for m steps or until b_{j+1} <= breakdown *
+ * max_i<=j |a_i| (an invariant subspace relative to the spectral scale).
+ *   g     : device, 3*n_nodes doubles, the start vector (fixed DOFs ignored).
+ *   alpha : host, m doubles: a_1..a_steps.
+ *   beta  : host, m doubles: beta[j] = b_{j+2}, the norm after step j; the
+ *           first steps-1 are the off-diagonals of the tridiagonal T.
+ *   steps : out, number of steps taken.
+ *   ritz  : host, 2 doubles or NULL: smallest and largest eigenvalue of T
+ *           (Sturm bisection); kappa_eff = ritz[1] / ritz[0].
+ * Overwrites the solver's work vectors; synchronises the stream twice per
+ * step (the dot products are read back).  Returns SGMG_EINVAL if g.Mg <= 0
+ * or a coefficient is not finite. */
+int sgmg_lanczos(sgmg_hierarchy* h, int precond, int m, const double* g, double breakdown,
+                 double* alpha, double* beta, int* steps, double* ritz, void* stream);
+
 /* Autotuner of the MFMA fine operators' launch shape: times each candidate
  * (element rows per wave tile: 4, 8; owned node planes per wave: 2, 4, 8,
  * 16, 32) on this hierarchy's mesh for the BF16, BF16X3 and FP64 kernels,

@@ -124,6 +124,13 @@ void launch_basis_update(double* w, const double* V, int ncols, const double* h,
 void launch_scale_inv_sqrt(const double* w, double* v, const double* nrm2, int n, hipStream_t s);
 void launch_basis_combine(double* x, const double* Z, int k, const double* y, int n, hipStream_t s);
 int basis_max_cols();
+
+// ---- preconditioned Lanczos vector steps (kernels_krylov.hip) ----------------
+void launch_lanczos_start(const double* g, const uint8_t* fixn, double* r, int n, hipStream_t s);
+void launch_lanczos_resid(const double* sv, const double* w, const double* wp, double a, double b,
+                          double* r, int n, hipStream_t s);
+void launch_lanczos_next(const double* r, const double* z, double b, double* w, double* v, int n,
+                         hipStream_t s);
 size_t basis_partials(int ncols);
 
 }  // namespace sgmg

@@ -126,4 +126,49 @@ void launch_basis_combine(double* x, const double* Z, int k, const double* y, in
 int basis_max_cols() { return kKryMaxCols; }
 size_t basis_partials(int ncols) { return (size_t)ncols * kKryGrid; }
 
+// ---------------------------------------------------------------------------
+// Preconditioned Lanczos probe of M K (the kappa_eff screen of Sec. 4): the
+// three vector steps around the K and M applications.
+
+// r = g with fixed DOFs zeroed
+__global__ __launch_bounds__(kKryBlock) void k_lanczos_start(const double* __restrict__ g,
+                                                            const uint8_t* __restrict__ fixn,
+                                                            double* __restrict__ r, int n) {
+  const int i = blockIdx.x * kKryBlock + threadIdx.x;
+  if (i < n) r[i] = (fixn[i / 3] >> (i % 3)) & 1u ? 0.0 : g[i];
+}
+
+// r = s - a w - b w_prev
+__global__ __launch_bounds__(kKryBlock) void k_lanczos_resid(const double* __restrict__ sv,
+                                                            const double* __restrict__ w,
+                                                            const double* __restrict__ wp, double a,
+                                                            double b, double* __restrict__ r, int n) {
+  const int i = blockIdx.x * kKryBlock + threadIdx.x;
+  if (i < n) r[i] = (sv[i] - a * w[i]) - b * wp[i];
+}
+
+// w = r / b, v = z / b
+__global__ __launch_bounds__(kKryBlock) void k_lanczos_next(const double* __restrict__ r,
+                                                           const double* __restrict__ z, double b,
+                                                           double* __restrict__ w,
+                                                           double* __restrict__ v, int n) {
+  const int i = blockIdx.x * kKryBlock + threadIdx.x;
+  if (i < n) {
+    w[i] = r[i] / b;
+    v[i] = z[i] / b;
+  }
+}
+
+void launch_lanczos_start(const double* g, const uint8_t* fixn, double* r, int n, hipStream_t s) {
+  k_lanczos_start<<<div_up(n, kKryBlock), kKryBlock, 0, s>>>(g, fixn, r, n);
+}
+void launch_lanczos_resid(const double* sv, const double* w, const double* wp, double a, double b,
+                          double* r, int n, hipStream_t s) {
+  k_lanczos_resid<<<div_up(n, kKryBlock), kKryBlock, 0, s>>>(sv, w, wp, a, b, r, n);
+}
+void launch_lanczos_next(const double* r, const double* z, double b, double* w, double* v, int n,
+                         hipStream_t s) {
+  k_lanczos_next<<<div_up(n, kKryBlock), kKryBlock, 0, s>>>(r, z, b, w, v, n);
+}
+
 }  // namespace sgmg

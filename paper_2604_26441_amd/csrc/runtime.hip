@@ -1142,6 +1142,116 @@ int sgmg_set_launch_shape(sgmg_hierarchy* h, int variant, int rows, int planes) 
   return 0;
 }
 
+namespace {
+
+// Number of eigenvalues of the symmetric tridiagonal T (diagonal d, off-
+// diagonal e) below x: the sign changes of its LDL^T pivots (Sturm count).
+int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
+  int c = 0;
+  double q = 1.0;
+  for (size_t i = 0; i < d.size(); ++i) {
+    q = d[i] - x - (i ? e[i - 1] * e[i - 1] / q : 0.0);
+    if (q == 0.0) q = -1e-300;            // x on a pivot: count it below
+    if (q < 0.0) ++c;
+  }
+  return c;
+}
+
+// k-th smallest eigenvalue (k = 1..n) by bisection inside the Gershgorin bounds.
+double tridiag_eig(const std::vector<double>& d, const std::vector<double>& e, int k) {
+  double lo = d[0], hi = d[0];
+  for (size_t i = 0; i < d.size(); ++i) {
+    const double r = (i ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < d.size() ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+  for (int it = 0; it < 400; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_count(d, e, mid) >= k) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+}  // namespace
+
+int sgmg_lanczos(sgmg_hierarchy* h, int precond, int m, const double* g, double breakdown,
+                 double* alpha, double* beta, int* steps, double* ritz, void* stream) {
+  if (!h || !g || !alpha || !beta || !steps) { set_error("NULL argument"); return SGMG_EINVAL; }
+  if (m < 1 || precond < 0 || precond > 2 || !(breakdown >= 0.0)) {
+    set_error("bad Lanczos arguments");
+    return SGMG_EINVAL;
+  }
+  *steps = 0;
+  hipStream_t s = as_stream(stream);
+  const Level& L0 = h->lev[0];
+  const int n = L0.g.n;
+  double* r = h->r;
+  double* z = h->z;
+  double* v = h->p;
+  double* w = h->r_old;
+  double* wp = h->tmp;
+  double* sv = h->q;
+  auto precondition = [&](const double* x, double* y) -> int {
+    if (precond == 2) return vcycle_full(h, x, y, s);
+    if (precond == 1) launch_apply_dinv(L0.dinv64, x, y, n, s);
+    else launch_copy(x, y, n, s);
+    return check_launch();
+  };
+  auto dot = [&](const double* a, const double* b, double* out) -> int {
+    launch_dot(a, b, nullptr, n, h->ws, h->sc + SC_XW, s);
+    TRY(check_launch());
+    SGMG_HIP(hipMemcpyAsync(h->h_sc, h->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+    SGMG_HIP(hipStreamSynchronize(s));
+    *out = h->h_sc[SC_XW];
+    return 0;
+  };
+  launch_lanczos_start(g, L0.fixn, r, n, s);
+  TRY(precondition(r, z));
+  double rz = 0.0;
+  TRY(dot(r, z, &rz));
+  if (!(rz > 0.0) || !std::isfinite(rz)) {
+    set_error("start vector has r.Mr <= 0 or is not finite");
+    return SGMG_EINVAL;
+  }
+  const double b1 = std::sqrt(rz);
+  launch_lanczos_next(r, z, b1, w, v, n, s);
+  SGMG_HIP(hipMemsetAsync(wp, 0, (size_t)n * sizeof(double), s));
+  double b = 0.0, amax = 0.0;
+  int k = 0;
+  for (; k < m;) {
+    TRY(apply_level<double>(h, 0, SGMG_F64, v, epi_store<double>(sv), s));
+    double a = 0.0;
+    TRY(dot(sv, v, &a));
+    launch_lanczos_resid(sv, w, wp, a, b, r, n, s);
+    TRY(precondition(r, z));
+    TRY(dot(r, z, &rz));
+    const double bn = rz > 0.0 ? std::sqrt(rz) : 0.0;
+    alpha[k] = a;
+    beta[k] = bn;
+    amax = std::max(amax, std::fabs(a));
+    ++k;
+    if (!std::isfinite(a) || !std::isfinite(bn)) {
+      *steps = k;
+      set_error("Lanczos produced a non-finite coefficient");
+      return SGMG_EINVAL;
+    }
+    if (!(bn > breakdown * amax)) break;
+    std::swap(w, wp);                      // w_prev <- w; w and v are rewritten below
+    launch_lanczos_next(r, z, bn, w, v, n, s);
+    b = bn;
+  }
+  *steps = k;
+  if (ritz) {
+    std::vector<double> d(alpha, alpha + k), e(beta, beta + (k > 0 ? k - 1 : 0));
+    ritz[0] = tridiag_eig(d, e, 1);
+    ritz[1] = tridiag_eig(d, e, k);
+  }
+  SGMG_HIP(hipStreamSynchronize(s));
+  return 0;
+}
+
 int sgmg_autotune(sgmg_hierarchy* h, int* shape_out, void* stream) {
   if (!h) { set_error("NULL argument"); return SGMG_EINVAL; }
   if (!h->kt.integral) { set_error("MFMA path unavailable for this nu"); return SGMG_EINVAL; }

@@ -3,6 +3,8 @@
   python -m paper_2604_26441_amd.experiments sizes   # uniform cantilevers 40^3/60^3/80^3:
                                                      # FP32-GMG vs FP64-GMG vs Jacobi-PCG
   python -m paper_2604_26441_amd.experiments kernels # fine K.u and level-1 stencil timings
+  python -m paper_2604_26441_amd.experiments e1 | spectral_proxy | robustness
+                                                     # binary-contrast and stress screens
 
 Timing protocol: 2 warm-up solves, then 5 timed solves (HIP events inside
 sgmg_pcg_solve); setup is timed separately with host clocks around a
@@ -96,6 +98,93 @@ def hetero(n=60, seeds=9, maxit=500):
                              "u_rel_err": float(torch.linalg.norm(u - uref) / torch.linalg.norm(uref))}
                 h.close()
             print(json.dumps(rec), flush=True)
+
+
+EPS_BF16 = 2.0 ** -8      # BF16 unit roundoff (8-bit significand, round to nearest)
+
+
+def _kappa(h, dims, steps=(20, 50)):
+    """Lanczos kappa_eff of the V-cycle-preconditioned fine operator after
+    each number of steps in `steps`, start vector a normalised Gaussian
+    (seed 0) on the free DOFs."""
+    fixed = workloads.cantilever_fixed(dims)
+    g = workloads.random_vector(fixed.size, 0, fixed)
+    g /= np.linalg.norm(g)
+    gd = torch.tensor(g, dtype=torch.float64, device="cuda:0")
+    return {f"kappa_eff_{m}": simpgmg.lanczos(h, gd, m=m)["kappa"] for m in steps}
+
+
+def _fgmres_run(dims, rho, p, f, fine_prec, restart, maxit):
+    o = simpgmg.default_options(*dims, penal=float(p), fine_prec=fine_prec)
+    h = simpgmg.setup_hierarchy(o, rho)
+    u = torch.zeros_like(f)
+    r = simpgmg.fgmres_solve(h, f, u, rtol=1e-6, maxit=maxit, restart=restart)
+    return h, u, r
+
+
+def e1(maxit=200):
+    """Binary-contrast sweep (Sec. 4, E1): 40^3, 60^3, 80^3 cantilevers, each
+    element solid with probability V_f in {0.2, 0.5, 0.8} else void at 1e-2
+    (Bernoulli, seed 42), p in {1.5, 3, 4.5}; FP64-GMG PCG, rtol 1e-6, cap 200."""
+    dev = "cuda:0"
+    for n in (40, 60, 80):
+        dims = (n, n, n)
+        f = torch.tensor(workloads.edge_load(dims), dtype=torch.float64, device=dev)
+        for vf in (0.2, 0.5, 0.8):
+            rho = torch.tensor(workloads.binary_rho(dims, vf, 1e-2, 42), dtype=torch.float64, device=dev)
+            for p in (1.5, 3.0, 4.5):
+                h = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, penal=p, fine_prec="f64"), rho)
+                u = torch.zeros_like(f)
+                r = simpgmg.pcg_solve(h, f, u, rtol=1e-6, maxit=maxit)
+                h.close()
+                print(json.dumps({"n": n, "vf": vf, "p": p, "status": r["status"], "iters": r["iters"],
+                                  "rel_res_true": r["rel_res_true"],
+                                  "solve_ms": round(r["solve_ms"], 3)}), flush=True)
+
+
+def spectral_proxy(maxit=500):
+    """BF16 spectral-proxy grid (Sec. 4, E5): 40^3 and 60^3 binary fields
+    (V_f in {0.2, 0.5, 0.8}, void 1e-2, seed 42) for p in {1.5, 3, 4.5}:
+    kappa_eff of the FP64 hierarchy by Lanczos (50 steps), eps_BF16 * kappa,
+    then FGMRES (restart 32, cap 500, rtol 1e-6) with the BF16 and the FP64
+    hierarchy and their compliance difference."""
+    dev = "cuda:0"
+    for n in (40, 60):
+        dims = (n, n, n)
+        f = torch.tensor(workloads.edge_load(dims), dtype=torch.float64, device=dev)
+        for vf in (0.2, 0.5, 0.8):
+            rho = torch.tensor(workloads.binary_rho(dims, vf, 1e-2, 42), dtype=torch.float64, device=dev)
+            for p in (1.5, 3.0, 4.5):
+                rec = {"n": n, "vf": vf, "p": p}
+                comp = {}
+                for prec in ("f64", "bf16"):
+                    h, u, r = _fgmres_run(dims, rho, p, f, prec, 32, maxit)
+                    if prec == "f64":
+                        kap = _kappa(h, dims)
+                        rec.update(kap, eps_kappa=EPS_BF16 * kap["kappa_eff_50"])
+                    h.close()
+                    comp[prec] = float(f @ u)
+                    rec[prec] = {"status": r["status"], "iters": r["iters"],
+                                 "rel_res_true": r["rel_res_true"], "solve_ms": round(r["solve_ms"], 3)}
+                rec["compliance_rel_diff"] = abs(comp["bf16"] - comp["f64"]) / abs(comp["f64"])
+                print(json.dumps(rec), flush=True)
+
+
+def robustness(n=40, maxit=500):
+    """The ten stress configurations of Sec. 4 (E10) on the 40^3 (64k)
+    cantilever with the FP64 hierarchy: FGMRES restart 50, cap 500, rtol
+    1e-6, and kappa_eff by Lanczos (50 steps)."""
+    dev = "cuda:0"
+    dims = (n, n, n)
+    f = torch.tensor(workloads.edge_load(dims), dtype=torch.float64, device=dev)
+    for label, rho_np, p in workloads.robustness_suite(dims):
+        rho = torch.tensor(rho_np, dtype=torch.float64, device=dev)
+        h, u, r = _fgmres_run(dims, rho, p, f, "f64", 50, maxit)
+        kap = _kappa(h, dims)
+        h.close()
+        print(json.dumps({"config": label, "p": p, "status": r["status"], "iters": r["iters"],
+                          "rel_res_true": r["rel_res_true"], "solve_ms": round(r["solve_ms"], 3),
+                          **kap}), flush=True)
 
 
 def large(trials=5, warmup=2):
@@ -428,4 +517,5 @@ def traffic(n=80, reps=20):
 
 if __name__ == "__main__":
     {"sizes": sizes, "hetero": hetero, "large": large, "kernels": kernels, "batch": batch,
+     "e1": e1, "spectral_proxy": spectral_proxy, "robustness": robustness,
      "warmstart": warmstart, "traffic": traffic}[sys.argv[1]]()

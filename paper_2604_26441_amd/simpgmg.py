@@ -56,7 +56,7 @@ class SolveInfo(ctypes.Structure):
 
 EXPORTS = [
     "sgmg_default_options", "sgmg_setup_hierarchy", "sgmg_update_moduli", "sgmg_apply_K",
-    "sgmg_vcycle", "sgmg_pcg_solve", "sgmg_fgmres_solve", "sgmg_num_levels", "sgmg_level_info",
+    "sgmg_vcycle", "sgmg_pcg_solve", "sgmg_fgmres_solve", "sgmg_lanczos", "sgmg_num_levels", "sgmg_level_info",
     "sgmg_copy_stencil", "sgmg_copy_diagonal", "sgmg_destroy", "sgmg_last_error",
     "sgmg_autotune", "sgmg_set_launch_shape", "sgmg_setup_batch", "sgmg_pcg_solve_batch", "sgmg_batch_hierarchy",
     "sgmg_batch_block_size", "sgmg_batch_destroy",
@@ -80,6 +80,8 @@ def _load():
     lib.sgmg_vcycle.argtypes = [H, vp, vp, vp]
     lib.sgmg_pcg_solve.argtypes = [H, i, vp, vp, d, i, ctypes.POINTER(SolveInfo), vp]
     lib.sgmg_fgmres_solve.argtypes = [H, i, i, vp, vp, d, i, ctypes.POINTER(SolveInfo), vp]
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.sgmg_lanczos.argtypes = [H, i, i, vp, d, dp, dp, ctypes.POINTER(ctypes.c_int), dp, vp]
     lib.sgmg_autotune.argtypes = [H, ctypes.POINTER(ctypes.c_int), vp]
     lib.sgmg_set_launch_shape.argtypes = [H, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.sgmg_setup_batch.argtypes = [i, ctypes.POINTER(Options), ctypes.POINTER(vp),
@@ -346,6 +348,21 @@ def fgmres_solve(h, f, u, rtol=1e-6, maxit=200, restart=32, precond=PRECOND_VCYC
     if hist is not None:
         out["history"] = list(hist)
     return out
+
+def lanczos(h, g, m=50, precond=PRECOND_VCYCLE, breakdown=1e-12, stream=None):
+    """Preconditioned Lanczos probe of M K (see sgmg_lanczos): returns
+    alpha, beta (lists of the steps taken), steps, theta_min, theta_max and
+    kappa = theta_max / theta_min."""
+    al = (ctypes.c_double * m)()
+    be = (ctypes.c_double * m)()
+    ritz = (ctypes.c_double * 2)()
+    steps = ctypes.c_int()
+    _check(_lib.sgmg_lanczos(h.handle, precond, m, _ptr(g, torch.float64, h.n_dof, "g"), breakdown,
+                             al, be, ctypes.byref(steps), ritz, _stream(stream)))
+    k = steps.value
+    return {"alpha": list(al)[:k], "beta": list(be)[:k], "steps": k, "theta_min": ritz[0],
+            "theta_max": ritz[1], "kappa": ritz[1] / ritz[0] if ritz[0] != 0 else float("inf")}
+
 
 def setup_batch(opts_list, rho_list, fixed_list=None, stream=None):
     n = len(opts_list)

@@ -12,7 +12,16 @@ Recipes (the paper uses no external dataset, Sec. 6 data statement):
     deviation ``corr_len`` elements (truncate 4 sigma, reflecting boundary),
     standardised, then rho = rho_min + (1 - rho_min) / (1 + exp(-gain * g));
   * random face loads: on one of the five unclamped faces, k random nodes
-    with random unit directions, scaled to unit total magnitude.
+    with random unit directions, scaled to unit total magnitude;
+  * binary-contrast fields (Sec. 4: E1, E5, E10): each element solid
+    (rho = 1) with probability V_f, otherwise void at the test floor
+    (Bernoulli placement from default_rng(seed); the paper's CuPy draws are
+    not reproducible, so its seeds 42 / 7, 11, 13, 17, 19 / 23 name our own
+    streams);
+  * the deterministic stress fields of E10: a checkerboard of solid and void
+    elements, and a layered field (solid lower half in z, void upper half);
+  * the mixed near-void field of E10: half the elements near void
+    (rho = floor * U(1, 10)), the rest U(0.2, 1), by seed.
 """
 import numpy as np
 
@@ -106,3 +115,46 @@ def random_vector(n, seed, fixed=None):
     if fixed is not None:
         v[np.asarray(fixed).astype(bool)] = 0.0
     return v
+
+
+def binary_rho(dims, vf, floor, seed):
+    """Bernoulli solid/void field: rho = 1 with probability vf, else floor."""
+    u = np.random.default_rng(seed).random(n_elems(dims))
+    return np.where(u < vf, 1.0, float(floor))
+
+
+def checkerboard_rho(dims, floor=1e-2):
+    nx, ny, nz = dims
+    ex, ey, ez = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    solid = ((ex + ey + ez) % 2 == 0).transpose(2, 1, 0).reshape(-1)
+    return np.where(solid, 1.0, float(floor))
+
+
+def layered_rho(dims, floor=1e-2):
+    """Solid lower half (element layers ez < nz/2), void upper half."""
+    nx, ny, nz = dims
+    ez = np.arange(n_elems(dims)) // (nx * ny)
+    return np.where(ez < nz // 2, 1.0, float(floor))
+
+
+def mixed_near_void_rho(dims, seed, floor=1e-3):
+    rng = np.random.default_rng(seed)
+    ne = n_elems(dims)
+    void = rng.random(ne) < 0.5
+    return np.where(void, floor * rng.uniform(1.0, 10.0, ne), rng.uniform(0.2, 1.0, ne))
+
+
+def robustness_suite(dims):
+    """The ten E10 stress configurations: (label, rho, p)."""
+    return [
+        ("uniform Vf=0.2", uniform_rho(dims, 0.2), 3.0),
+        ("uniform Vf=0.5", uniform_rho(dims, 0.5), 3.0),
+        ("uniform Vf=0.8", uniform_rho(dims, 0.8), 3.0),
+        ("binary Vf=0.2 p=1.5", binary_rho(dims, 0.2, 1e-2, 7), 1.5),
+        ("binary Vf=0.5 p=3", binary_rho(dims, 0.5, 1e-2, 11), 3.0),
+        ("binary Vf=0.8 p=4.5", binary_rho(dims, 0.8, 1e-2, 13), 4.5),
+        ("checkerboard", checkerboard_rho(dims), 3.0),
+        ("layered half solid / half void", layered_rho(dims), 3.0),
+        ("binary Vf=0.5 floor 1e-12", binary_rho(dims, 0.5, 1e-12, 17), 3.0),
+        ("mixed near-void", mixed_near_void_rho(dims, 19), 3.0),
+    ]
