@@ -181,3 +181,27 @@ def vcycle(h, r, l=0):
     ec = vcycle(h, rc, l + 1)
     x = x + prolong(h, l, ec)
     return _smooth(h, l, r, x)
+
+
+def cycle(h, r, gamma=1, l=0, x0=None):
+    """Multigrid cycle with cycle index gamma (Sec. 4 E6(c): V-cycle gamma = 1,
+    W-cycle gamma = 2; Trottenberg, Oosterlee and Schueller, Multigrid,
+    Sec. 2.4): pre-smooth from x0 (zero if None), restrict the residual,
+    approximate the coarse residual equation by gamma cycles of the coarser
+    level, each starting from the previous one's result (the coarsest level
+    is solved once: a second solve adds nothing), prolong, post-smooth.
+    gamma = 1 from zero is the V-cycle of Eq. vcycle."""
+    L = len(h.levels) - 1
+    if l == L:
+        return coarse_solve(h, r)
+    K = h.levels[l].K
+    x = _smooth(h, l, r, x0)
+    rc = restrict(h, l, r - K @ x)
+    if l + 1 == L:
+        ec = coarse_solve(h, rc)
+    else:
+        ec = None
+        for _ in range(gamma):
+            ec = cycle(h, rc, gamma, l + 1, ec)
+    x = x + prolong(h, l, ec)
+    return _smooth(h, l, r, x)
