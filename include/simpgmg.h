@@ -103,6 +103,12 @@ typedef struct {
   int use_graphs;            /* 1: each PCG iteration (K.p, updates, V-cycle) is
                                 replayed from a HIP graph captured once per
                                 hierarchy; 0: direct launches (same results)      */
+  int cycle_gamma;           /* cycle index: 1 V-cycle (default), 2 W-cycle (Sec. 4
+                                E6(c)): every level whose coarser level is not the
+                                coarsest approximates its coarse residual equation
+                                by two coarser cycles, the second starting from
+                                the first one's result; the coarsest is solved
+                                once                                              */
 } sgmg_options;
 
 typedef struct {
@@ -250,7 +256,8 @@ typedef struct sgmg_batch sgmg_batch;
  *   fixed_dof : host array of nsys device masks, NULL entries (or NULL) for
  *               the cantilever clamp.
  * Returns SGMG_EINVAL if a system's coarsest level exceeds dense_max (the
- * batched V-cycle has only the dense coarsest solve).                      */
+ * batched V-cycle has only the dense coarsest solve) or its cycle_gamma is
+ * not 1.                                                                   */
 int sgmg_setup_batch(int nsys, const sgmg_options* opts, const double* const* rho_or_E,
                      const uint8_t* const* fixed_dof, void* stream, sgmg_batch** out);
 

@@ -406,7 +406,8 @@ Smoother smoother_of(const sgmg_hierarchy* h, int l) {
 
 double first_step_coef(const Smoother& sm) { return sm.cheb ? 1.0 / sm.theta : sm.omega; }
 
-int vcycle_level(const sgmg_hierarchy* h, int l, int* cur, double* out64, hipStream_t s);
+int vcycle_level(const sgmg_hierarchy* h, int l, int* cur, double* out64, bool from_zero,
+                 hipStream_t s);
 
 template <typename TF, typename TC>
 int descend(const sgmg_hierarchy* h, int l, const TF* r, hipStream_t s) {
@@ -424,22 +425,30 @@ int descend(const sgmg_hierarchy* h, int l, const TF* r, hipStream_t s) {
 }
 
 template <typename T>
-int smooth_and_recurse(const sgmg_hierarchy* h, int l, int* cur, double* out64, hipStream_t s) {
+int smooth_and_recurse(const sgmg_hierarchy* h, int l, int* cur, double* out64, bool from_zero,
+                       hipStream_t s) {
   const Level& L = h->lev[l];
   const Smoother sm = smoother_of(h, l);
   const sgmg_prec prec = level_prec(h, l);
   const T* b = (const T*)L.b;
   const T* dinv = std::is_same<T, float>::value ? (const T*)L.dinv32 : (const T*)L.dinv64;
   T* d = (T*)L.dv;
-  int c = 0;  // x[0] holds the first pre-smoothing step
+  // From zero, x[0] already holds the first pre-smoothing step (fused into
+  // the restriction or the cycle entry); otherwise pre-smoothing starts from
+  // the iterate in x[*cur] and takes all its steps here.
+  int c = from_zero ? 0 : *cur;
   double rho = sm.cheb ? 1.0 / sm.sigma1 : 0.0;
-  for (int k = 1; k < sm.steps; ++k) {
+  for (int k = from_zero ? 1 : 0; k < sm.steps; ++k) {
     double c1 = 0.0, c2 = sm.omega;
     if (sm.cheb) {
-      const double rn = 1.0 / (2.0 * sm.sigma1 - rho);
-      c1 = rn * rho;
-      c2 = 2.0 * rn / sm.delta;
-      rho = rn;
+      if (k == 0) {
+        c2 = 1.0 / sm.theta;
+      } else {
+        const double rn = 1.0 / (2.0 * sm.sigma1 - rho);
+        c1 = rn * rho;
+        c2 = 2.0 * rn / sm.delta;
+        rho = rn;
+      }
     }
     TRY(apply_level<T>(h, l, prec, (const T*)L.x[c],
                        epi_smooth<T>((T*)L.x[1 - c], b, dinv, d, c1, c2, sm.cheb, nullptr), s));
@@ -451,7 +460,11 @@ int smooth_and_recurse(const sgmg_hierarchy* h, int l, int* cur, double* out64, 
   if (C.f32) TRY((descend<T, float>(h, l, (const T*)L.r, s)));
   else TRY((descend<T, double>(h, l, (const T*)L.r, s)));
   int cc = 0;
-  TRY(vcycle_level(h, l + 1, &cc, nullptr, s));
+  TRY(vcycle_level(h, l + 1, &cc, nullptr, true, s));
+  // W-cycle: a second coarse cycle from the first one's result, unless the
+  // coarser level is the coarsest (solved exactly once)
+  for (int g = 1; g < h->o.cycle_gamma && l + 2 < h->L; ++g)
+    TRY(vcycle_level(h, l + 1, &cc, nullptr, false, s));
   if (C.f32) launch_prolong_add<T, float>(L.g, C.g, (const float*)C.x[cc], L.fixn, (T*)L.x[c], s);
   else launch_prolong_add<T, double>(L.g, C.g, (const double*)C.x[cc], L.fixn, (T*)L.x[c], s);
   TRY(check_launch());
@@ -478,7 +491,11 @@ int smooth_and_recurse(const sgmg_hierarchy* h, int l, int* cur, double* out64, 
   return 0;
 }
 
-int vcycle_level(const sgmg_hierarchy* h, int l, int* cur, double* out64, hipStream_t s) {
+// One cycle on level l for the right-hand side in lev[l].b.  from_zero: the
+// iterate starts at zero (its first smoothing step is already in x[0]);
+// otherwise it starts from x[*cur].  The result is left in x[*cur].
+int vcycle_level(const sgmg_hierarchy* h, int l, int* cur, double* out64, bool from_zero,
+                 hipStream_t s) {
   const Level& L = h->lev[l];
   if (l == h->L - 1) {
     if (h->coarse_iter)
@@ -492,8 +509,8 @@ int vcycle_level(const sgmg_hierarchy* h, int l, int* cur, double* out64, hipStr
     *cur = 0;
     return check_launch();
   }
-  if (L.f32) return smooth_and_recurse<float>(h, l, cur, out64, s);
-  return smooth_and_recurse<double>(h, l, cur, out64, s);
+  if (L.f32) return smooth_and_recurse<float>(h, l, cur, out64, from_zero, s);
+  return smooth_and_recurse<double>(h, l, cur, out64, from_zero, s);
 }
 
 int vcycle_full(const sgmg_hierarchy* h, const double* r, double* z, hipStream_t s) {
@@ -508,7 +525,7 @@ int vcycle_full(const sgmg_hierarchy* h, const double* r, double* z, hipStream_t
                                 sm.cheb ? (double*)L.dv : nullptr, L.g.n, s);
   TRY(check_launch());
   int cur = 0;
-  return vcycle_level(h, 0, &cur, z, s);
+  return vcycle_level(h, 0, &cur, z, true, s);
 }
 
 int validate(const sgmg_options* o) {
@@ -527,6 +544,7 @@ int validate(const sgmg_options* o) {
   if (o->level1_prec != SGMG_F64 && o->level1_prec != SGMG_F32) { set_error("level1_prec must be F64 or F32"); return SGMG_EINVAL; }
   if (!(o->cheb_alpha > 0.0 && o->cheb_alpha < 1.0)) { set_error("cheb_alpha must be in (0,1)"); return SGMG_EINVAL; }
   if (!(o->lambda_safety > 0.0)) { set_error("lambda_safety must be > 0"); return SGMG_EINVAL; }
+  if (o->cycle_gamma != 1 && o->cycle_gamma != 2) { set_error("cycle_gamma must be 1 or 2"); return SGMG_EINVAL; }
   return 0;
 }
 
@@ -560,6 +578,7 @@ void sgmg_default_options(sgmg_options* o, int nx, int ny, int nz) {
   o->stag_window = 0;
   o->lambda_override = nullptr;
   o->use_graphs = 1;
+  o->cycle_gamma = 1;
 }
 
 void sgmg_destroy(sgmg_hierarchy* h) {
@@ -1572,6 +1591,11 @@ int sgmg_setup_batch(int nsys, const sgmg_options* opts, const double* const* rh
     if (h->coarse_iter) {
       sgmg_batch_destroy(b);
       set_error("batched systems need a dense coarsest solve (coarsest free DOFs <= dense_max)");
+      return SGMG_EINVAL;
+    }
+    if (h->o.cycle_gamma != 1) {
+      sgmg_batch_destroy(b);
+      set_error("batched systems use the V-cycle (cycle_gamma 1)");
       return SGMG_EINVAL;
     }
   }

@@ -187,6 +187,73 @@ def robustness(n=40, maxit=500):
                           **kap}), flush=True)
 
 
+def _timed(dims, rho, f, solver="pcg", restart=32, maxit=500, trials=3, **kw):
+    """Setup once, then `trials` solves after one warm-up: mean solve ms
+    (HIP events inside the solver), iterations, status, true residual."""
+    h = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, **kw), rho)
+    ms = []
+    for k in range(trials + 1):
+        u = torch.zeros_like(f)
+        r = (simpgmg.pcg_solve(h, f, u, rtol=1e-6, maxit=maxit) if solver == "pcg" else
+             simpgmg.fgmres_solve(h, f, u, rtol=1e-6, maxit=maxit, restart=restart))
+        if k:
+            ms.append(r["solve_ms"])
+    h.close()
+    return {"status": r["status"], "iters": r["iters"], "rel_res_true": r["rel_res_true"],
+            "solve_ms": round(float(np.mean(ms)), 3), "solve_ms_std": round(float(np.std(ms)), 3)}
+
+
+def ablations(n=60):
+    """Sec. 4 E6 on the 60^3 (216k) cantilever, rho = 0.5, p = 3, PCG rtol
+    1e-6: (a) fine precision FP64 / FP32; (b) depth 2..5 with level 1 in FP64
+    or FP32 (FP32 fine level); (c) V- vs W-cycle; (d) Chebyshev vs Jacobi
+    (degree 2); then the high-contrast smoother screen (binary fields, void
+    1e-2, seed 42, p = 3, 40^3 and 60^3, V_f 0.5 / 0.2; FP64-GMG with
+    FGMRES restart 32, cap 500) for Chebyshev and Jacobi of degree 2 and 4."""
+    dev = "cuda:0"
+    dims = (n, n, n)
+    rho = torch.tensor(workloads.uniform_rho(dims), dtype=torch.float64, device=dev)
+    f = torch.tensor(workloads.edge_load(dims), dtype=torch.float64, device=dev)
+    runs = [("a", {"fine_prec": "f64"}), ("a", {"fine_prec": "f32"})]
+    runs += [("b", {"fine_prec": "f32", "n_levels": L, "level1_prec": p1})
+             for L in (2, 3, 4, 5) for p1 in ("f64", "f32")]
+    runs += [("c", {"fine_prec": "f32", "cycle_gamma": g}) for g in (1, 2)]
+    runs += [("d", {"fine_prec": "f32", "fine_smoother": sm}) for sm in (0, 1)]
+    for tag, kw in runs:
+        print(json.dumps({"ablation": tag, **kw, **_timed(dims, rho, f, **kw)}), flush=True)
+    for m in (40, 60):
+        d2 = (m, m, m)
+        f2 = torch.tensor(workloads.edge_load(d2), dtype=torch.float64, device=dev)
+        for vf in (0.5, 0.2):
+            r2 = torch.tensor(workloads.binary_rho(d2, vf, 1e-2, 42), dtype=torch.float64, device=dev)
+            for sm, deg in ((0, 2), (0, 4), (1, 2), (1, 4)):
+                kw = {"fine_prec": "f64", "fine_smoother": sm, "fine_degree": deg}
+                print(json.dumps({"screen": "high_contrast", "n": m, "vf": vf,
+                                  "smoother": "chebyshev" if sm == 0 else "jacobi", "degree": deg,
+                                  **_timed(d2, r2, f2, solver="fgmres", trials=1, **kw)}), flush=True)
+
+
+def sensitivity(n=60):
+    """Sec. 4 E6 sensitivity surface on the 60^3 cantilever (rho = 0.5,
+    p = 3): Chebyshev degree {1, 2, 4} x depth {3, 4} x FGMRES restart
+    {16, 32, 50}, FP32-GMG (BF16X3 fine K.u) and BF16-GMG, rtol 1e-6, cap 500."""
+    dev = "cuda:0"
+    dims = (n, n, n)
+    rho = torch.tensor(workloads.uniform_rho(dims), dtype=torch.float64, device=dev)
+    f = torch.tensor(workloads.edge_load(dims), dtype=torch.float64, device=dev)
+    h = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, fine_prec="bf16x3"), rho)
+    simpgmg.autotune(h)
+    h.close()
+    for prec in ("bf16x3", "bf16"):
+        for deg in (1, 2, 4):
+            for L in (3, 4):
+                for rs in (16, 32, 50):
+                    kw = {"fine_prec": prec, "fine_degree": deg, "n_levels": L}
+                    print(json.dumps({"restart": rs, **kw,
+                                      **_timed(dims, rho, f, solver="fgmres", restart=rs, **kw)}),
+                          flush=True)
+
+
 def large(trials=5, warmup=2):
     """The paper's large-scale table (Table e7) like for like: 2:1:1 boxes
     100x50x25 (125k), 160x80x40 (512k), 200x100x50 (1M) with uniform modulus
@@ -518,4 +585,5 @@ def traffic(n=80, reps=20):
 if __name__ == "__main__":
     {"sizes": sizes, "hetero": hetero, "large": large, "kernels": kernels, "batch": batch,
      "e1": e1, "spectral_proxy": spectral_proxy, "robustness": robustness,
+     "ablations": ablations, "sensitivity": sensitivity,
      "warmstart": warmstart, "traffic": traffic}[sys.argv[1]]()

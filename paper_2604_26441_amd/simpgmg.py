@@ -42,6 +42,7 @@ class Options(ctypes.Structure):
         ("stag_window", ctypes.c_int),
         ("lambda_override", ctypes.POINTER(ctypes.c_double)),
         ("use_graphs", ctypes.c_int),
+        ("cycle_gamma", ctypes.c_int),
     ]
 
 

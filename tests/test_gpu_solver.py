@@ -218,3 +218,44 @@ def test_batch_rejects_iterative_coarsest():
     o = simpgmg.default_options(*dims, n_levels=3, dense_max=10)
     with pytest.raises(simpgmg.SimpGmgError, match="dense coarsest"):
         simpgmg.setup_batch([o], [t64(workloads.uniform_rho(dims))])
+
+
+@pytest.mark.parametrize("dims,L,smoother", [((16, 8, 8), 3, 0), ((16, 8, 8), 4, 0), ((24, 12, 12), 4, 1)])
+def test_w_cycle_matches_oracle(dims, L, smoother):
+    from paper_2604_26441_amd import simpgmg
+    g = np.random.default_rng(7)
+    rho = g.uniform(0.1, 1.0, np.prod(dims))
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    oh = multigrid.build(dims, mesh.simp_modulus(rho, 3), fixed, multigrid.Options(
+        n_levels=L, fine_smoother="chebyshev" if smoother == 0 else "jacobi"))
+    o = simpgmg.default_options(*dims, n_levels=L, fine_prec="f64", fine_smoother=smoother,
+                                cycle_gamma=2)
+    h = simpgmg.setup_hierarchy(o, t64(rho), lambda_override=[lv.lam for lv in oh.levels[:-1]])
+    r = workloads.random_vector(fixed.size, 8, fixed)
+    z = t64(np.zeros_like(r))
+    simpgmg.vcycle(h, t64(r), z)
+    ref = multigrid.cycle(oh, r, 2)
+    assert rel_err(np64(z), ref, ref) < 1e-11
+    assert rel_err(np64(z), multigrid.vcycle(oh, r), ref) > 1e-6     # it is not the V-cycle
+
+
+def test_w_cycle_pcg_graph_equals_direct_and_batch_rejects_it():
+    from paper_2604_26441_amd import simpgmg
+    dims = (24, 12, 12)
+    rho = workloads.uniform_rho(dims)
+    f = workloads.edge_load(dims)
+    out = {}
+    for graphs in (1, 0):
+        o = simpgmg.default_options(*dims, n_levels=4, fine_prec="f32", cycle_gamma=2,
+                                    use_graphs=graphs)
+        h = simpgmg.setup_hierarchy(o, t64(rho))
+        for rep in range(3):                          # replays with eager work between them
+            u = t64(np.zeros_like(f))
+            res = simpgmg.pcg_solve(h, t64(f), u, rtol=1e-8, maxit=100)
+            assert res["status"] == "converged"
+            out.setdefault(graphs, []).append((res["iters"], np64(u)))
+    for (i1, u1), (i0, u0) in zip(out[1], out[0]):
+        assert i1 == i0 and np.array_equal(u1, u0)
+    o = simpgmg.default_options(*dims, n_levels=3, cycle_gamma=2)
+    with pytest.raises(simpgmg.SimpGmgError, match="cycle_gamma"):
+        simpgmg.setup_batch([o], [t64(rho)])
