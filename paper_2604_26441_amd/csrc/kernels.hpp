@@ -86,6 +86,13 @@ void launch_pcg_init(const double* f, const double* Ax0, int have_x0, double* r,
 void launch_pcg_update_xr(double* x, double* r, double* r_old, const double* p, const double* q,
                           const double* sc, int slot_rz, int slot_pq, int n, RedWs ws,
                           double* sc_rr, hipStream_t s);
+// The same update, also writing the entry of the V-cycle that follows
+// (b = (T) r, x = c0 Dinv b, d = x when d is not NULL).
+template <typename T>
+void launch_pcg_update_xr_entry(double* x, double* r, double* r_old, const double* p,
+                                const double* q, const double* sc, int slot_rz, int slot_pq, int n,
+                                RedWs ws, double* sc_rr, T* b, const T* dinv, double c0, T* xe,
+                                T* de, hipStream_t s);
 void launch_pcg_dot_rz(const double* r, const double* z, const double* r_old, int n, RedWs ws,
                        double* sc_out2, hipStream_t s);
 void launch_pcg_update_p(double* p, const double* z, const double* sc, int slot_num,
@@ -105,8 +112,12 @@ void launch_dense_add_diag(double* A, int nf, const double* mean_diag_sum, hipSt
                            double* eps_out);
 void launch_dense_diag_sum(const double* A, int nf, RedWs ws, double* out, hipStream_t s);
 int dense_spd_inverse(double* A, int nf, double* scratch, int* d_flag, hipStream_t s);
-void launch_dense_solve(const double* Ainv, const int* free_idx, int nf, const double* r,
-                        double* rc, double* z, hipStream_t s);
+// Symmetric coarsest solve from the packed upper-triangle tiles of Ainv:
+// sym_tiles(nf) tiles of 64 x 64 doubles; partials 2 * sym_tiles(nf) * 64 doubles.
+int sym_tiles(int nf);
+void launch_dense_pack(const double* A, int nf, double* P, hipStream_t s);
+void launch_dense_symv(const double* P, const int* free_idx, int nf, const double* r,
+                       double* partials, double* z, hipStream_t s);
 
 // Fixed-count Jacobi-PCG on the coarsest stencil from x = 0: 1 + 2 iters
 // launches; r, z, the ping-pong pair p0/p1 and q each g.n doubles; scratch

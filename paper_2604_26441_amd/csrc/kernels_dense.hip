@@ -196,43 +196,140 @@ int dense_spd_inverse(double* A, int n, double* scratch, int* d_flag, hipStream_
   return 0;
 }
 
-// z[free] = Ainv rc with rc = r[free]; fixed entries of z are left untouched
-// (they are zero in the level's buffer).
-__global__ void k_dense_gather(const double* __restrict__ r, const int* __restrict__ free_idx,
-                               int nf, double* __restrict__ rc) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nf) rc[i] = r[free_idx[i]];
+// ---------------------------------------------------------------------------
+// Symmetric form of the coarsest solve.  The explicit inverse of the SPD
+// matrix K_L + eps I is symmetric, so only its upper triangle is read per
+// cycle: it is packed once per factorisation into 64 x 64 tiles (I, J),
+// I <= J, tile t(I, J) = I nb - I (I - 1) / 2 + (J - I), each tile row-major
+// and zero-padded past nf.  A cycle reads every stored coefficient once:
+//   pass 1, one workgroup per tile: row sums A_IJ x_J (towards y_I) and, off
+//           the diagonal, column sums A_IJ^T x_I (towards y_J), written as
+//           per-tile partials;
+//   pass 2, per output block I: y_I = the sum over J of the column partial
+//           of tile (J, I) for J < I and the row partial of tile (I, J) for
+//           J >= I, in a fixed order.
+// x is gathered through the free-DOF list inside pass 1, and y is scattered
+// by pass 2, so no separate gather launch remains.  Fixed summation order:
+// deterministic.
+constexpr int kTile = 64;
+
+int sym_tiles(int nf) {
+  const int nb = div_up(nf, kTile);
+  return nb * (nb + 1) / 2;
 }
 
-// One wave per row of the explicit inverse (4 rows per block): each lane
-// streams the row with stride 64 and four independent partial sums, then a
-// fixed-order wave reduction.  No block barrier (a wave past the last row
-// simply exits).
-__global__ __launch_bounds__(256) void k_dense_gemv(const double* __restrict__ Ainv,
-                                                    const double* __restrict__ rc,
-                                                    const int* __restrict__ free_idx, int nf,
-                                                    double* __restrict__ z) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= nf) return;
-  const double* row = Ainv + (size_t)i * nf;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int j = lane;
-  for (; j + 192 < nf; j += 256) {
-    s0 += row[j] * rc[j];
-    s1 += row[j + 64] * rc[j + 64];
-    s2 += row[j + 128] * rc[j + 128];
-    s3 += row[j + 192] * rc[j + 192];
+__device__ inline int tile_index(int I, int J, int nb) { return I * nb - I * (I - 1) / 2 + (J - I); }
+
+// Inverse of tile_index: the block row from the quadratic's root, corrected
+// by at most a step either way against rounding.
+__device__ inline void tile_ij(int t, int nb, int& I, int& J) {
+  const double b = 2.0 * nb + 1.0;
+  int i = (int)((b - sqrt(b * b - 8.0 * t)) * 0.5);
+  i = max(0, min(i, nb - 1));
+  while (i > 0 && tile_index(i, i, nb) > t) --i;
+  while (i + 1 < nb && tile_index(i + 1, i + 1, nb) <= t) ++i;
+  I = i;
+  J = i + (t - tile_index(i, i, nb));
+}
+
+__global__ __launch_bounds__(256) void k_dense_pack(const double* __restrict__ A, int nf, int nb,
+                                                   double* __restrict__ P) {
+  int I, J;
+  tile_ij(blockIdx.x, nb, I, J);
+  double* T = P + (size_t)blockIdx.x * kTile * kTile;
+  for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
+    const int a = e / kTile, b = e % kTile;
+    const int i = I * kTile + a, j = J * kTile + b;
+    T[e] = (i < nf && j < nf) ? A[(size_t)i * nf + j] : 0.0;
   }
-  for (; j < nf; j += 64) s0 += row[j] * rc[j];
-  const double s = wave_sum((s0 + s1) + (s2 + s3));
-  if (lane == 0) z[free_idx[i]] = s;
 }
 
-void launch_dense_solve(const double* Ainv, const int* free_idx, int nf, const double* r,
-                        double* rc, double* z, hipStream_t s) {
-  k_dense_gather<<<div_up(nf, 256), 256, 0, s>>>(r, free_idx, nf, rc);
-  k_dense_gemv<<<div_up(nf, 4), 256, 0, s>>>(Ainv, rc, free_idx, nf, z);
+__global__ __launch_bounds__(256) void k_dense_symv_tiles(const double* __restrict__ P, int nf,
+                                                         int nb, const int* __restrict__ free_idx,
+                                                         const double* __restrict__ r,
+                                                         double* __restrict__ prow,
+                                                         double* __restrict__ pcol) {
+  __shared__ double tile[kTile][kTile + 1];
+  __shared__ double xs[2][kTile];
+  __shared__ double red[4][kTile];
+  const int t = blockIdx.x;
+  int I, J;
+  tile_ij(t, nb, I, J);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const double* T = P + (size_t)t * kTile * kTile;
+  double v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = T[(w + 4 * k) * kTile + lane];
+  if (w < 2) {
+    const int i = (w == 0 ? I : J) * kTile + lane;
+    xs[w][lane] = i < nf ? r[free_idx[i]] : 0.0;
+  }
+  __syncthreads();
+  // column partial over this wave's 16 rows (towards y_J)
+  double pc = 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    pc += v[k] * xs[0][w + 4 * k];
+    tile[w + 4 * k][lane] = v[k];
+  }
+  red[w][lane] = pc;
+  __syncthreads();
+  if (w == 0 && I != J)
+    pcol[(size_t)t * kTile + lane] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+  __syncthreads();
+  // row partial: lane = row, this wave's 16 columns (towards y_I)
+  double pr = 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) pr += tile[lane][16 * w + k] * xs[1][16 * w + k];
+  red[w][lane] = pr;
+  __syncthreads();
+  if (w == 0)
+    prow[(size_t)t * kTile + lane] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
+// One block of 4 waves per output block I: wave w adds the partials of
+// J = w, w + 4, ... (tile indices in closed form, loads independent), then
+// the four wave sums are added in a fixed order.
+__global__ __launch_bounds__(256) void k_dense_symv_sum(int nf, int nb,
+                                                       const int* __restrict__ free_idx,
+                                                       const double* __restrict__ prow,
+                                                       const double* __restrict__ pcol,
+                                                       double* __restrict__ z) {
+  __shared__ double red[4][kTile];
+  const int I = blockIdx.x, a = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double y0 = 0.0, y1 = 0.0;
+  int J = w;
+  for (; J + 4 < nb; J += 8) {
+    const int J1 = J + 4;
+    y0 += J < I ? pcol[(size_t)tile_index(J, I, nb) * kTile + a]
+                : prow[(size_t)tile_index(I, J, nb) * kTile + a];
+    y1 += J1 < I ? pcol[(size_t)tile_index(J1, I, nb) * kTile + a]
+                 : prow[(size_t)tile_index(I, J1, nb) * kTile + a];
+  }
+  if (J < nb)
+    y0 += J < I ? pcol[(size_t)tile_index(J, I, nb) * kTile + a]
+                : prow[(size_t)tile_index(I, J, nb) * kTile + a];
+  red[w][a] = y0 + y1;
+  __syncthreads();
+  if (w == 0) {
+    const int i = I * kTile + a;
+    if (i < nf) z[free_idx[i]] = (red[0][a] + red[1][a]) + (red[2][a] + red[3][a]);
+  }
+}
+
+void launch_dense_pack(const double* A, int nf, double* P, hipStream_t s) {
+  if (nf <= 0) return;
+  k_dense_pack<<<sym_tiles(nf), 256, 0, s>>>(A, nf, div_up(nf, kTile), P);
+}
+
+void launch_dense_symv(const double* P, const int* free_idx, int nf, const double* r,
+                       double* partials, double* z, hipStream_t s) {
+  if (nf <= 0) return;
+  const int nb = div_up(nf, kTile), nt = sym_tiles(nf);
+  double* prow = partials;
+  double* pcol = partials + (size_t)nt * kTile;
+  k_dense_symv_tiles<<<nt, 256, 0, s>>>(P, nf, nb, free_idx, r, prow, pcol);
+  k_dense_symv_sum<<<nb, 256, 0, s>>>(nf, nb, free_idx, prow, pcol, z);
 }
 
 }  // namespace sgmg

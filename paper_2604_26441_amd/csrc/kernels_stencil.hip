@@ -302,24 +302,25 @@ __device__ inline void restrict_w1d(int I, int nf, double (&w)[3]) {
   w[2] = 2 * I + 1 < 2 * nc ? 0.5 : (2 * I + 1 == nf ? 1.0 : 0.0);
 }
 
-// Thread per (coarse node, component), 64 coarse nodes per block, block index
-// remapped per XCD.  The 27 fine values are read unconditionally at clamped
-// indices and weighted (zero weights for nodes outside the grid).
+// Thread per coarse node (all three components: each fine node is one
+// contiguous 12- or 24-byte read), 256 coarse nodes per block, block index
+// remapped per XCD.  The 27 fine nodes are read unconditionally at clamped
+// indices and weighted (zero weights for nodes outside the grid); the
+// weighted sum runs in the same order as the per-component form.
 template <typename TF, typename TC>
-__global__ __launch_bounds__(192) void k_restrict(Grid f, Grid c, const TF* __restrict__ rf,
+__global__ __launch_bounds__(256) void k_restrict(Grid f, Grid c, const TF* __restrict__ rf,
                                                   const uint8_t* __restrict__ cfix,
                                                   TC* __restrict__ bc,
                                                   const TC* __restrict__ dinv_c, double c0,
                                                   TC* __restrict__ xc, TC* __restrict__ dc) {
-  const int k = threadIdx.x >> 6;
-  const int I = xcd_block(blockIdx.x, gridDim.x) * 64 + (threadIdx.x & 63);
+  const int I = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (I >= c.Nn) return;
   const int Ix = I % c.Nx, t = I / c.Nx, Iy = t % c.Ny, Iz = t / c.Ny;
   double wx[3], wy[3], wz[3];
   restrict_w1d(Ix, f.nx, wx);
   restrict_w1d(Iy, f.ny, wy);
   restrict_w1d(Iz, f.nz, wz);
-  double acc = 0.0;
+  double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int cz = 0; cz < 3; ++cz) {
     const int iz = min(max(2 * Iz - 1 + cz, 0), f.Nz - 1);
@@ -331,25 +332,32 @@ __global__ __launch_bounds__(192) void k_restrict(Grid f, Grid c, const TF* __re
 #pragma unroll
       for (int cx = 0; cx < 3; ++cx) {
         const int ix = min(max(2 * Ix - 1 + cx, 0), f.Nx - 1);
-        acc += wx[cx] * wyz * (double)rf[3 * (row + ix) + k];
+        const TF* v = rf + 3 * (row + ix);
+        const double w = wx[cx] * wyz;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[k] += w * (double)v[k];
       }
     }
   }
-  const size_t dof = 3 * (size_t)I + k;
-  const TC v = (cfix[I] >> k) & 1u ? (TC)0 : (TC)acc;
-  bc[dof] = v;
-  if (xc) {
-    const TC x = (TC)c0 * dinv_c[dof] * v;
-    xc[dof] = x;
-    if (dc) dc[dof] = x;
+  const unsigned fx = cfix[I];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const size_t dof = 3 * (size_t)I + k;
+    const TC v = (fx >> k) & 1u ? (TC)0 : (TC)acc[k];
+    bc[dof] = v;
+    if (xc) {
+      const TC x = (TC)c0 * dinv_c[dof] * v;
+      xc[dof] = x;
+      if (dc) dc[dof] = x;
+    }
   }
 }
 
 template <typename TF, typename TC>
 void launch_restrict(const Grid& fine, const Grid& coarse, const TF* rf, const uint8_t* cfix,
                      TC* bc, const TC* dinv_c, double c0, TC* xc, TC* dc, hipStream_t s) {
-  k_restrict<TF, TC><<<div_up(coarse.Nn, 64), 192, 0, s>>>(fine, coarse, rf, cfix, bc, dinv_c, c0,
-                                                           xc, dc);
+  k_restrict<TF, TC><<<div_up(coarse.Nn, 256), 256, 0, s>>>(fine, coarse, rf, cfix, bc, dinv_c,
+                                                            c0, xc, dc);
 }
 template void launch_restrict<float, double>(const Grid&, const Grid&, const float*,
                                              const uint8_t*, double*, const double*, double,

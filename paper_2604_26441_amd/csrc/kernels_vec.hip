@@ -172,6 +172,18 @@ void launch_pcg_init(const double* f, const double* Ax0, int have_x0, double* r,
 }
 
 // alpha = sc[rz] / sc[pq]; x += alpha p; r -= alpha q; out = r.r
+// Optionally also the entry of the V-cycle that follows (the same
+// arithmetic as k_vcycle_entry): b = (T) r, x = c0 Dinv b, d = x.
+template <typename T>
+struct VEntry {
+  T* b = nullptr;
+  const T* dinv = nullptr;
+  double c0 = 0.0;
+  T* x = nullptr;
+  T* d = nullptr;
+};
+
+template <typename T>
 __global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(double* __restrict__ x,
                                                              double* __restrict__ r,
                                                              double* __restrict__ r_old,
@@ -179,7 +191,7 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(double* __restrict_
                                                              const double* __restrict__ q,
                                                              const double* __restrict__ sc,
                                                              int slot_rz, int slot_pq, int n,
-                                                             RedWs ws, double* out) {
+                                                             RedWs ws, VEntry<T> e) {
   const double pq = sc[slot_pq];
   const double alpha = sc[slot_rz] / pq;
   // a failed step (p.q <= 0 or non-finite) leaves x and r untouched
@@ -195,6 +207,13 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(double* __restrict_
       r[i] = rv;
     }
     rr += rv * rv;
+    if (e.b) {
+      const T bv = (T)rv;
+      e.b[i] = bv;
+      const T xv = (T)e.c0 * e.dinv[i] * bv;
+      e.x[i] = xv;
+      if (e.d) e.d[i] = xv;
+    }
   }
   const double v[1] = {rr};
   grid_sum<1>(v, ws);
@@ -203,10 +222,34 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(double* __restrict_
 void launch_pcg_update_xr(double* x, double* r, double* r_old, const double* p, const double* q,
                           const double* sc, int slot_rz, int slot_pq, int n, RedWs ws,
                           double* sc_rr, hipStream_t s) {
-  k_pcg_update_xr<<<vec_grid(n), kVecBlock, 0, s>>>(x, r, r_old, p, q, sc, slot_rz, slot_pq, n,
-                                                    ws, sc_rr);
+  k_pcg_update_xr<double><<<vec_grid(n), kVecBlock, 0, s>>>(x, r, r_old, p, q, sc, slot_rz,
+                                                            slot_pq, n, ws, VEntry<double>{});
   launch_finalize(ws, vec_grid(n), 1, sc_rr, s);
 }
+
+template <typename T>
+void launch_pcg_update_xr_entry(double* x, double* r, double* r_old, const double* p,
+                                const double* q, const double* sc, int slot_rz, int slot_pq, int n,
+                                RedWs ws, double* sc_rr, T* b, const T* dinv, double c0, T* xe,
+                                T* de, hipStream_t s) {
+  VEntry<T> e;
+  e.b = b;
+  e.dinv = dinv;
+  e.c0 = c0;
+  e.x = xe;
+  e.d = de;
+  k_pcg_update_xr<T><<<vec_grid(n), kVecBlock, 0, s>>>(x, r, r_old, p, q, sc, slot_rz, slot_pq,
+                                                       n, ws, e);
+  launch_finalize(ws, vec_grid(n), 1, sc_rr, s);
+}
+template void launch_pcg_update_xr_entry<float>(double*, double*, double*, const double*,
+                                                const double*, const double*, int, int, int,
+                                                RedWs, double*, float*, const float*, double,
+                                                float*, float*, hipStream_t);
+template void launch_pcg_update_xr_entry<double>(double*, double*, double*, const double*,
+                                                 const double*, const double*, int, int, int,
+                                                 RedWs, double*, double*, const double*, double,
+                                                 double*, double*, hipStream_t);
 
 // out[0] = r.z ; out[1] = r_old.z (flexible beta numerator r.z - r_old.z)
 __global__ __launch_bounds__(kVecBlock) void k_pcg_dot_rz(const double* __restrict__ r,

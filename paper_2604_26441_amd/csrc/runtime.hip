@@ -74,7 +74,8 @@ struct sgmg_hierarchy {
   int nL = 0;
   int* free_idx = nullptr;
   double* Ainv = nullptr;
-  double* rc = nullptr;
+  double* Apack = nullptr;   // upper-triangle tiles of Ainv (the per-cycle operand)
+  double* symv_part = nullptr;
   double coarse_eps = 0.0;
   bool coarse_iter = false;  // coarsest solve: fixed-count PCG instead of the dense inverse
   double* cpcg_p = nullptr;  // its second search direction and z (2 n), per-step partials, flags
@@ -356,6 +357,8 @@ int assemble_operators(sgmg_hierarchy* h, const double* rho_or_E, hipStream_t s)
       set_error("coarsest factorisation met a non-positive pivot");
       return SGMG_EFACTOR;
     }
+    launch_dense_pack(h->Ainv, nf, h->Apack, s);
+    TRY(check_launch());
   }
   return 0;
 }
@@ -504,8 +507,8 @@ int vcycle_level(const sgmg_hierarchy* h, int l, int* cur, double* out64, bool f
                         h->cpcg_scratch,
                         h->cpcg_done, h->o.coarse_pcg_iters, s);
     else
-      launch_dense_solve(h->Ainv, h->free_idx, h->nL, (const double*)L.b, h->rc,
-                         (double*)L.x[0], s);
+      launch_dense_symv(h->Apack, h->free_idx, h->nL, (const double*)L.b, h->symv_part,
+                        (double*)L.x[0], s);
     *cur = 0;
     return check_launch();
   }
@@ -745,8 +748,11 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
     const size_t nd = h->coarse_iter ? 1 : (size_t)std::max(h->nL, 1);  // dense-solve sizes
     if ((rc = dalloc_t(h, &h->free_idx, std::max<size_t>(idx.size(), 1))) ||
         (rc = dalloc_t(h, &h->Ainv, nd * nd)) ||
-        (rc = dalloc_t(h, &h->rc, std::max(h->nL, 1))) ||
         (rc = dalloc_t(h, &h->gj_scratch, nd * 64 + 64 * 64)))
+      return fail(rc);
+    const size_t nt = h->coarse_iter ? 1 : (size_t)std::max(sym_tiles(h->nL), 1);
+    if ((rc = dalloc_t(h, &h->Apack, nt * 64 * 64)) ||
+        (rc = dalloc_t(h, &h->symv_part, nt * 2 * 64)))
       return fail(rc);
     if (!idx.empty())
       hipMemcpyAsync(h->free_idx, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, s);
@@ -810,11 +816,29 @@ static int pcg_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
   const bool flex = h->o.flexible_beta != 0;
   const int nslot = slot == SC_RZ0 ? SC_RZ1 : SC_RZ0;
   TRY(apply_level<double>(h, 0, SGMG_F64, h->p, epi_store<double>(h->q, h->ws, sc + SC_PQ), s));
-  launch_pcg_update_xr(h->xs, h->r, flex ? h->r_old : nullptr, h->p, h->q, sc, slot, SC_PQ, n,
-                       h->ws, sc + SC_RR, s);
-  if (precond == 2) TRY(vcycle_full(h, h->r, h->z, s));
-  else if (precond == 1) launch_apply_dinv(L0.dinv64, h->r, h->z, n, s);
-  else launch_copy(h->r, h->z, n, s);
+  if (precond == 2) {
+    // the update also writes the V-cycle's entry (its first smoothing step)
+    const Smoother sm = smoother_of(h, 0);
+    const double c0 = first_step_coef(sm);
+    if (L0.f32)
+      launch_pcg_update_xr_entry<float>(h->xs, h->r, flex ? h->r_old : nullptr, h->p, h->q, sc,
+                                        slot, SC_PQ, n, h->ws, sc + SC_RR, (float*)L0.b,
+                                        L0.dinv32, c0, (float*)L0.x[0],
+                                        sm.cheb ? (float*)L0.dv : nullptr, s);
+    else
+      launch_pcg_update_xr_entry<double>(h->xs, h->r, flex ? h->r_old : nullptr, h->p, h->q, sc,
+                                         slot, SC_PQ, n, h->ws, sc + SC_RR, (double*)L0.b,
+                                         L0.dinv64, c0, (double*)L0.x[0],
+                                         sm.cheb ? (double*)L0.dv : nullptr, s);
+    TRY(check_launch());
+    int cur = 0;
+    TRY(vcycle_level(h, 0, &cur, h->z, true, s));
+  } else {
+    launch_pcg_update_xr(h->xs, h->r, flex ? h->r_old : nullptr, h->p, h->q, sc, slot, SC_PQ, n,
+                         h->ws, sc + SC_RR, s);
+    if (precond == 1) launch_apply_dinv(L0.dinv64, h->r, h->z, n, s);
+    else launch_copy(h->r, h->z, n, s);
+  }
   launch_pcg_dot_rz(h->r, h->z, flex ? h->r_old : nullptr, n, h->ws, sc + nslot, s);
   launch_pcg_update_p(h->p, h->z, sc, nslot, flex ? nslot + 1 : -1, slot, n, s);
   return check_launch();
@@ -1509,15 +1533,17 @@ int batch_prepare_items(sgmg_batch* b, int nitems, const int* item_sys, hipStrea
     BItem& I = b->h_items[k];
     I.sys = sys;
     const size_t n0 = h->lev[0].g.n;
-    size_t bytes = 5 * n0 * sizeof(double) + 5 * n0 * sizeof(float);
-    for (int l = 1; l < h->L; ++l) bytes += 4 * (size_t)h->lev[l].g.n * sizeof(double);
-    bytes += (size_t)std::max(h->nL, 1) * sizeof(double) + 64 * 32;
+    // every sub-buffer starts on a 256-byte boundary: size each one rounded
+    auto rounded = [](size_t nbytes) { return (nbytes + 255) & ~(size_t)255; };
+    size_t bytes = 5 * rounded(n0 * sizeof(double)) + 5 * rounded(n0 * sizeof(float));
+    for (int l = 1; l < h->L; ++l) bytes += 4 * rounded((size_t)h->lev[l].g.n * sizeof(double));
+    bytes += rounded((size_t)std::max(h->nL, 1) * sizeof(double));
     void* mem = nullptr;
     if (hipMalloc(&mem, bytes) != hipSuccess) { set_error("batch work allocation failed"); return SGMG_ENOMEM; }
     b->item_mem.push_back(mem);
     SGMG_HIP(hipMemsetAsync(mem, 0, bytes, s));
     char* c = (char*)mem;
-    auto take = [&](size_t nbytes) { char* r = c; c += (nbytes + 255) & ~(size_t)255; return (void*)r; };
+    auto take = [&](size_t nbytes) { char* r = c; c += rounded(nbytes); return (void*)r; };
     I.r = (double*)take(n0 * 8); I.z = (double*)take(n0 * 8); I.p = (double*)take(n0 * 8);
     I.q = (double*)take(n0 * 8); I.t = (double*)take(n0 * 8);
     I.b0 = (float*)take(n0 * 4); I.d0 = (float*)take(n0 * 4); I.r0 = (float*)take(n0 * 4);
@@ -1530,6 +1556,10 @@ int batch_prepare_items(sgmg_batch* b, int nitems, const int* item_sys, hipStrea
       I.lr[l] = (double*)take(nl * 8);
     }
     I.rc = (double*)take((size_t)std::max(h->nL, 1) * 8);
+    if ((size_t)(c - (char*)mem) > bytes) {
+      set_error("batch work layout exceeds its allocation");
+      return SGMG_EINVAL;
+    }
   }
   SGMG_HIP(hipMalloc(&b->d_items, nitems * sizeof(BItem)));
   SGMG_HIP(hipMalloc(&b->d_out, nitems * sizeof(BOut)));
