@@ -11,7 +11,8 @@ explicit triple products), smoothers (diagonal, power iteration, Chebyshev,
 damped Jacobi), multigrid (hierarchy, V-cycle, coarsest solve), krylov (PCG,
 FGMRES),
 bf16 (BF16 semantic model), rng (SplitMix64), unet (conv3d reference),
-spectral (Lanczos kappa_eff probe of M K).
+spectral (Lanczos kappa_eff probe of M K), simp (density filter, Heaviside
+projection, compliance sensitivities, OC update).
 
 Parity status: every function is pinned by tests/test_oracle_*.py against
 closed forms, invariants, printed values of the paper or library routines.
