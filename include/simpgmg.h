@@ -328,6 +328,70 @@ int sgmg_warm_start_scale(sgmg_hierarchy* h, const double* f, double* u0, double
 void sgmg_unet_destroy(sgmg_unet* u);
 
 void sgmg_destroy(sgmg_hierarchy* h);
+/* ---- SIMP outer loop (Sec. 3.1, Eq. simp_filter) -----------------------------
+ * Design density rho (element field, x-fastest, FP64 on the device) ->
+ * filtered rho~ = F rho -> physical rhohat = H(rho~) -> E = Emin + (E0 -
+ * Emin) rhohat^p, one frozen field per linear solve.  The filter and
+ * projection forms are the standard ones (the paper's parameters are in a
+ * companion paper): F the linear cone filter w(e, i) = max(0, rmin - |c_e -
+ * c_i|) over element centres, normalised by the row sum (rmin <= 1: no
+ * filter); H(x) = (tanh(b eta) + tanh(b (x - eta))) / (tanh(b eta) +
+ * tanh(b (1 - eta))), b = 0 the identity.  Compliance sensitivities are
+ * carried back through H' and F^T; the optimality-criteria update rho_new =
+ * clamp(rho sqrt(max(-dc, 0) / (lam dv)), rho -/+ move, [0, 1]) finds lam by
+ * bisection on [0, 1e9] until (l2 - l1) <= oc_tol (l1 + l2) so that the
+ * physical volume is volfrac * n_el. */
+typedef struct {
+  int nx, ny, nz;            /* elements per axis                                   */
+  double penal, E0, Emin;    /* SIMP map (must equal the hierarchy's)               */
+  double volfrac;            /* target physical volume fraction                     */
+  double move;               /* OC move limit                                       */
+  double rmin;               /* filter radius in elements (<= 1: no filter)         */
+  double beta, eta;          /* projection sharpness (0: none) and threshold        */
+  double oc_tol;             /* bisection stop (l2 - l1) <= oc_tol (l1 + l2)        */
+  int oc_max_halvings;
+} sgmg_simp_params;
+
+typedef struct {
+  double compliance;         /* f . u = sum_e E_e u_e^T K_e u_e of the solved state   */
+  double volume;             /* physical volume of the updated design                 */
+  double lambda;             /* OC multiplier                                         */
+  double max_change;         /* max_e |rho_new - rho|                                 */
+  int pcg_status, pcg_iters;
+  double rel_res_true, solve_ms;
+} sgmg_simp_info;
+
+typedef struct sgmg_simp sgmg_simp;
+
+/* Defaults: p 3, E0 1, Emin 1e-9, volfrac 0.5, move 0.2, rmin 1.5, beta 0,
+ * eta 0.5, oc_tol 1e-9, 200 halvings. */
+void sgmg_simp_default_params(sgmg_simp_params* p, int nx, int ny, int nz);
+/* Allocates the state (filter row sums and four element fields); SGMG_EINVAL
+ * for parameters outside their ranges (rmin in (0, 16]). */
+int sgmg_simp_create(const sgmg_simp_params* p, void* stream, sgmg_simp** out);
+void sgmg_simp_destroy(sgmg_simp* s);
+/* rhohat = H(F rho), kept in s (and copied to rhohat, device, if not NULL). */
+int sgmg_simp_physical(sgmg_simp* s, const double* rho, double* rhohat, void* stream);
+/* From the state u (device, 3*n_nodes) of the last physical field: the
+ * compliance (host), and the design sensitivities dc = dc/drho and dv =
+ * dV/drho (device, optional) that the OC update uses.  h supplies K_e and
+ * must have the same mesh.  SGMG_EINVAL if sgmg_simp_physical has not run. */
+int sgmg_simp_sensitivity(sgmg_simp* s, const sgmg_hierarchy* h, const double* u,
+                          double* compliance, double* dc, double* dv, void* stream);
+/* One OC update of rho (device, in place) from the last sensitivities; the
+ * outputs (host, optional) are the multiplier, the physical volume at it and
+ * the largest density change.  Reads back one scalar per halving. */
+int sgmg_simp_oc_update(sgmg_simp* s, double* rho, double* lambda, double* volume,
+                        double* max_change, void* stream);
+/* One SIMP iteration: physical field, sgmg_update_moduli (which re-estimates
+ * the smoother spectra only when max E moved by more than 10 %), the
+ * V-cycle-preconditioned PCG solve from the u passed in (a warm start from
+ * the previous design), sensitivities and the OC update of rho.  The
+ * hierarchy must have been set up with input_is_modulus 0 and the same
+ * penal, E0 and Emin. */
+int sgmg_simp_step(sgmg_simp* s, sgmg_hierarchy* h, double* rho, const double* f, double* u,
+                   double rtol, int maxit, sgmg_simp_info* info, void* stream);
+
 const char* sgmg_last_error(void);
 
 #ifdef __cplusplus

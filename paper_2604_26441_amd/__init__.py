@@ -11,7 +11,7 @@ _BINDING = {"F64", "F32", "BF16", "BF16X3", "Options", "Hierarchy", "SimpGmgErro
             "default_options", "setup_hierarchy", "update_moduli", "apply_K", "vcycle",
             "pcg_solve", "fgmres_solve", "lanczos", "autotune", "library_path", "EXPORTS", "Batch", "setup_batch",
             "pcg_solve_batch", "UNet", "unet_input", "unet_output", "unet_target",
-            "warm_start_scale", "padded_grid", "set_launch_shape"}
+            "warm_start_scale", "padded_grid", "set_launch_shape", "Simp", "simp_params"}
 
 
 def __getattr__(name):

@@ -144,4 +144,21 @@ void launch_lanczos_next(const double* r, const double* z, double b, double* w, 
                          hipStream_t s);
 size_t basis_partials(int ncols);
 
+// ---- SIMP outer loop (kernels_simp.hip); element fields in x-fastest order --
+void launch_filter_wsum(int nx, int ny, int nz, double rmin, double* W, hipStream_t s);
+void launch_physical(int nx, int ny, int nz, double rmin, const double* W, const double* rho,
+                     double beta, double eta, double* rhohat, double* dH, hipStream_t s);
+void launch_element_energy(const Grid& g, const double* ke, const double* rhohat, const double* dH,
+                           const double* u, double p, double E0, double Emin, double* gc,
+                           RedWs ws, double* comp_out, hipStream_t s);
+void launch_oc_ratio(int nx, int ny, int nz, double rmin, const double* W, const double* gc,
+                     const double* dH, double* ratio, double* dc_out, double* dv_out,
+                     hipStream_t s);
+void launch_oc_volume(int nx, int ny, int nz, double rmin, const double* W, const double* rho,
+                      const double* ratio, double lam, double move, double beta, double eta,
+                      RedWs ws, double* vol_out, hipStream_t s);
+int oc_apply_blocks(int n);
+void launch_oc_apply(int n, double* rho, const double* ratio, double lam, double move, RedWs ws,
+                     hipStream_t s);
+
 }  // namespace sgmg

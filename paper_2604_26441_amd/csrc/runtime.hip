@@ -1754,4 +1754,197 @@ int sgmg_copy_diagonal(const sgmg_hierarchy* h, int level, double* host_out) {
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// SIMP outer loop (Sec. 3.1, Eq. simp_filter; Sec. 3.5 drift rule through
+// sgmg_update_moduli).
+}  // extern "C"
+
+struct sgmg_simp {
+  sgmg_simp_params p{};
+  double* W = nullptr;       // filter row sums
+  double* rhohat = nullptr;
+  double* dH = nullptr;
+  double* gc = nullptr;      // dH * dc/drhohat
+  double* ratio = nullptr;   // OC ratio max(-dc, 0) / dv
+  RedWs ws{};
+  double* sc = nullptr;      // [0] compliance, [1] volume
+  double* h_sc = nullptr;
+  std::vector<double> h_part;
+  bool have_physical = false, have_ratio = false;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+int simp_alloc(sgmg_simp* s, double** p, size_t count) {
+  void* v = nullptr;
+  if (hipMalloc(&v, std::max<size_t>(count, 1) * sizeof(double)) != hipSuccess) {
+    set_error("SIMP allocation failed");
+    return SGMG_ENOMEM;
+  }
+  s->allocs.push_back(v);
+  *p = (double*)v;
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sgmg_simp_default_params(sgmg_simp_params* p, int nx, int ny, int nz) {
+  std::memset(p, 0, sizeof(*p));
+  p->nx = nx; p->ny = ny; p->nz = nz;
+  p->penal = 3.0; p->E0 = 1.0; p->Emin = 1e-9;
+  p->volfrac = 0.5; p->move = 0.2;
+  p->rmin = 1.5; p->beta = 0.0; p->eta = 0.5;
+  p->oc_tol = 1e-9; p->oc_max_halvings = 200;
+}
+
+void sgmg_simp_destroy(sgmg_simp* s) {
+  if (!s) return;
+  for (void* v : s->allocs) hipFree(v);
+  if (s->h_sc) hipHostFree(s->h_sc);
+  delete s;
+}
+
+int sgmg_simp_create(const sgmg_simp_params* p, void* stream, sgmg_simp** out) {
+  if (out) *out = nullptr;
+  if (!p || !out) { set_error("NULL argument"); return SGMG_EINVAL; }
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1 || (long)p->nx * p->ny * p->nz > 0x7fffffffL) {
+    set_error("bad SIMP mesh"); return SGMG_EINVAL;
+  }
+  if (!(p->rmin > 0.0) || p->rmin > 16.0 || !(p->volfrac > 0.0 && p->volfrac < 1.0) ||
+      !(p->move > 0.0) || !(p->beta >= 0.0) || !(p->eta > 0.0 && p->eta < 1.0) ||
+      !(p->penal >= 1.0) || !(p->oc_tol > 0.0) || p->oc_max_halvings < 1) {
+    set_error("bad SIMP parameters"); return SGMG_EINVAL;
+  }
+  sgmg_simp* s = new (std::nothrow) sgmg_simp();
+  if (!s) { set_error("host allocation failed"); return SGMG_ENOMEM; }
+  s->p = *p;
+  const size_t n = (size_t)p->nx * p->ny * p->nz;
+  const size_t nb = div_up((int)n, 256) + 2048;
+  int rc = 0;
+  if ((rc = simp_alloc(s, &s->W, n)) || (rc = simp_alloc(s, &s->rhohat, n)) ||
+      (rc = simp_alloc(s, &s->dH, n)) || (rc = simp_alloc(s, &s->gc, n)) ||
+      (rc = simp_alloc(s, &s->ratio, n)) || (rc = simp_alloc(s, &s->ws.partials, nb)) ||
+      (rc = simp_alloc(s, &s->sc, 4))) {
+    sgmg_simp_destroy(s);
+    return rc;
+  }
+  if (hipHostMalloc((void**)&s->h_sc, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    sgmg_simp_destroy(s);
+    set_error("pinned allocation failed");
+    return SGMG_ENOMEM;
+  }
+  hipStream_t st = as_stream(stream);
+  launch_filter_wsum(p->nx, p->ny, p->nz, p->rmin, s->W, st);
+  if ((rc = check_launch()) || hipStreamSynchronize(st) != hipSuccess) {
+    sgmg_simp_destroy(s);
+    if (!rc) { set_error("sync failed"); rc = SGMG_EHIP; }
+    return rc;
+  }
+  *out = s;
+  return 0;
+}
+
+int sgmg_simp_physical(sgmg_simp* s, const double* rho, double* rhohat, void* stream) {
+  if (!s || !rho) { set_error("NULL argument"); return SGMG_EINVAL; }
+  hipStream_t st = as_stream(stream);
+  const sgmg_simp_params& p = s->p;
+  launch_physical(p.nx, p.ny, p.nz, p.rmin, s->W, rho, p.beta, p.eta, s->rhohat, s->dH, st);
+  TRY(check_launch());
+  if (rhohat)
+    SGMG_HIP(hipMemcpyAsync(rhohat, s->rhohat, (size_t)p.nx * p.ny * p.nz * sizeof(double),
+                            hipMemcpyDeviceToDevice, st));
+  s->have_physical = true;
+  s->have_ratio = false;
+  return 0;
+}
+
+int sgmg_simp_sensitivity(sgmg_simp* s, const sgmg_hierarchy* h, const double* u,
+                          double* compliance, double* dc, double* dv, void* stream) {
+  if (!s || !h || !u) { set_error("NULL argument"); return SGMG_EINVAL; }
+  if (!s->have_physical) { set_error("sgmg_simp_physical must run first"); return SGMG_EINVAL; }
+  const sgmg_simp_params& p = s->p;
+  const Grid& g = h->lev[0].g;
+  if (g.nx != p.nx || g.ny != p.ny || g.nz != p.nz) { set_error("hierarchy mesh differs"); return SGMG_EINVAL; }
+  hipStream_t st = as_stream(stream);
+  launch_element_energy(g, h->ke64, s->rhohat, s->dH, u, p.penal, p.E0, p.Emin, s->gc, s->ws,
+                        s->sc, st);
+  launch_oc_ratio(p.nx, p.ny, p.nz, p.rmin, s->W, s->gc, s->dH, s->ratio, dc, dv, st);
+  TRY(check_launch());
+  SGMG_HIP(hipMemcpyAsync(s->h_sc, s->sc, sizeof(double), hipMemcpyDeviceToHost, st));
+  SGMG_HIP(hipStreamSynchronize(st));
+  if (compliance) *compliance = s->h_sc[0];
+  s->have_ratio = true;
+  return 0;
+}
+
+int sgmg_simp_oc_update(sgmg_simp* s, double* rho, double* lambda, double* volume,
+                        double* max_change, void* stream) {
+  if (!s || !rho) { set_error("NULL argument"); return SGMG_EINVAL; }
+  if (!s->have_ratio) { set_error("sgmg_simp_sensitivity must run first"); return SGMG_EINVAL; }
+  const sgmg_simp_params& p = s->p;
+  const int n = p.nx * p.ny * p.nz;
+  const double target = p.volfrac * n;
+  hipStream_t st = as_stream(stream);
+  double l1 = 0.0, l2 = 1e9, lmid = 0.5 * (l1 + l2), vol = 0.0;
+  for (int it = 0; it < p.oc_max_halvings; ++it) {
+    lmid = 0.5 * (l1 + l2);
+    launch_oc_volume(p.nx, p.ny, p.nz, p.rmin, s->W, rho, s->ratio, lmid, p.move, p.beta, p.eta,
+                     s->ws, s->sc + 1, st);
+    TRY(check_launch());
+    SGMG_HIP(hipMemcpyAsync(s->h_sc + 1, s->sc + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+    SGMG_HIP(hipStreamSynchronize(st));
+    vol = s->h_sc[1];
+    if (!std::isfinite(vol)) { set_error("OC volume is not finite"); return SGMG_EINVAL; }
+    if (vol > target) l1 = lmid;
+    else l2 = lmid;
+    if (l2 - l1 <= p.oc_tol * (l1 + l2)) break;
+  }
+  launch_oc_apply(n, rho, s->ratio, lmid, p.move, s->ws, st);
+  TRY(check_launch());
+  const int nb = oc_apply_blocks(n);
+  s->h_part.resize(nb);
+  SGMG_HIP(hipMemcpyAsync(s->h_part.data(), s->ws.partials, nb * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+  SGMG_HIP(hipStreamSynchronize(st));
+  double m = 0.0;
+  for (double v : s->h_part) m = std::max(m, v);
+  if (lambda) *lambda = lmid;
+  if (volume) *volume = vol;
+  if (max_change) *max_change = m;
+  s->have_physical = s->have_ratio = false;
+  return 0;
+}
+
+int sgmg_simp_step(sgmg_simp* s, sgmg_hierarchy* h, double* rho, const double* f, double* u,
+                   double rtol, int maxit, sgmg_simp_info* info, void* stream) {
+  if (!s || !h || !rho || !f || !u) { set_error("NULL argument"); return SGMG_EINVAL; }
+  const sgmg_simp_params& p = s->p;
+  const sgmg_options& o = h->o;
+  if (o.input_is_modulus || o.penal != p.penal || o.E0 != p.E0 || o.Emin != p.Emin) {
+    set_error("hierarchy SIMP map (input_is_modulus 0, penal, E0, Emin) differs from the SIMP parameters");
+    return SGMG_EINVAL;
+  }
+  TRY(sgmg_simp_physical(s, rho, nullptr, stream));
+  TRY(sgmg_update_moduli(h, s->rhohat, stream));
+  sgmg_solve_info si{};
+  TRY(sgmg_pcg_solve(h, 2, f, u, rtol, maxit, &si, stream));
+  double c = 0.0, lam = 0.0, vol = 0.0, chg = 0.0;
+  TRY(sgmg_simp_sensitivity(s, h, u, &c, nullptr, nullptr, stream));
+  TRY(sgmg_simp_oc_update(s, rho, &lam, &vol, &chg, stream));
+  if (info) {
+    info->compliance = c;
+    info->volume = vol;
+    info->lambda = lam;
+    info->max_change = chg;
+    info->pcg_status = si.status;
+    info->pcg_iters = si.iters;
+    info->rel_res_true = si.rel_res_true;
+    info->solve_ms = si.solve_ms;
+  }
+  return 0;
+}
+
 }  // extern "C"

@@ -55,6 +55,24 @@ class SolveInfo(ctypes.Structure):
     ]
 
 
+class SimpParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("penal", ctypes.c_double), ("E0", ctypes.c_double), ("Emin", ctypes.c_double),
+        ("volfrac", ctypes.c_double), ("move", ctypes.c_double), ("rmin", ctypes.c_double),
+        ("beta", ctypes.c_double), ("eta", ctypes.c_double), ("oc_tol", ctypes.c_double),
+        ("oc_max_halvings", ctypes.c_int),
+    ]
+
+
+class SimpInfo(ctypes.Structure):
+    _fields_ = [
+        ("compliance", ctypes.c_double), ("volume", ctypes.c_double), ("lambda_", ctypes.c_double),
+        ("max_change", ctypes.c_double), ("pcg_status", ctypes.c_int), ("pcg_iters", ctypes.c_int),
+        ("rel_res_true", ctypes.c_double), ("solve_ms", ctypes.c_double),
+    ]
+
+
 EXPORTS = [
     "sgmg_default_options", "sgmg_setup_hierarchy", "sgmg_update_moduli", "sgmg_apply_K",
     "sgmg_vcycle", "sgmg_pcg_solve", "sgmg_fgmres_solve", "sgmg_lanczos", "sgmg_num_levels", "sgmg_level_info",
@@ -64,6 +82,8 @@ EXPORTS = [
     "sgmg_unet_create", "sgmg_unet_num_params", "sgmg_unet_set_params", "sgmg_unet_get_params",
     "sgmg_unet_forward", "sgmg_unet_grad", "sgmg_unet_train_step", "sgmg_unet_input",
     "sgmg_unet_output", "sgmg_unet_target", "sgmg_warm_start_scale", "sgmg_unet_destroy",
+    "sgmg_simp_default_params", "sgmg_simp_create", "sgmg_simp_destroy", "sgmg_simp_physical",
+    "sgmg_simp_sensitivity", "sgmg_simp_oc_update", "sgmg_simp_step",
 ]
 
 
@@ -109,6 +129,16 @@ def _load():
     lib.sgmg_warm_start_scale.argtypes = [H, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
     lib.sgmg_unet_destroy.argtypes = [H]
     lib.sgmg_unet_destroy.restype = None
+    SP = ctypes.POINTER(SimpParams)
+    lib.sgmg_simp_default_params.argtypes = [SP, i, i, i]
+    lib.sgmg_simp_default_params.restype = None
+    lib.sgmg_simp_create.argtypes = [SP, vp, ctypes.POINTER(H)]
+    lib.sgmg_simp_destroy.argtypes = [H]
+    lib.sgmg_simp_destroy.restype = None
+    lib.sgmg_simp_physical.argtypes = [H, vp, vp, vp]
+    lib.sgmg_simp_sensitivity.argtypes = [H, H, vp, dp, vp, vp, vp]
+    lib.sgmg_simp_oc_update.argtypes = [H, vp, dp, dp, dp, vp]
+    lib.sgmg_simp_step.argtypes = [H, H, vp, vp, vp, d, i, ctypes.POINTER(SimpInfo), vp]
     lib.sgmg_num_levels.argtypes = [H]
     lib.sgmg_level_info.argtypes = [H, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                     ctypes.POINTER(ctypes.c_double)]
@@ -496,3 +526,66 @@ def warm_start_scale(h, f, u0, stream=None):
     _check(_lib.sgmg_warm_start_scale(h.handle, _ptr(f, torch.float64, h.n_dof), _ptr(u0, torch.float64, h.n_dof),
                                       ctypes.byref(a), _stream(stream)))
     return a.value
+
+
+def simp_params(nx, ny, nz, **kw):
+    p = SimpParams()
+    _lib.sgmg_simp_default_params(ctypes.byref(p), nx, ny, nz)
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+class Simp:
+    """SIMP outer-loop state (see sgmg_simp_*): density filter row sums and
+    the element work fields."""
+
+    def __init__(self, params, stream=None):
+        self.params = params
+        self.n_el = params.nx * params.ny * params.nz
+        self.handle = ctypes.c_void_p()
+        _check(_lib.sgmg_simp_create(ctypes.byref(params), _stream(stream), ctypes.byref(self.handle)))
+
+    def close(self):
+        if self.handle:
+            _lib.sgmg_simp_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def physical(self, rho, rhohat=None, stream=None):
+        _check(_lib.sgmg_simp_physical(self.handle, _ptr(rho, torch.float64, self.n_el, "rho"),
+                                       None if rhohat is None else
+                                       _ptr(rhohat, torch.float64, self.n_el, "rhohat"),
+                                       _stream(stream)))
+
+    def sensitivity(self, h, u, dc=None, dv=None, stream=None):
+        c = ctypes.c_double()
+        _check(_lib.sgmg_simp_sensitivity(self.handle, h.handle, _ptr(u, torch.float64, h.n_dof, "u"),
+                                          ctypes.byref(c),
+                                          None if dc is None else _ptr(dc, torch.float64, self.n_el, "dc"),
+                                          None if dv is None else _ptr(dv, torch.float64, self.n_el, "dv"),
+                                          _stream(stream)))
+        return c.value
+
+    def oc_update(self, rho, stream=None):
+        lam, vol, chg = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(_lib.sgmg_simp_oc_update(self.handle, _ptr(rho, torch.float64, self.n_el, "rho"),
+                                        ctypes.byref(lam), ctypes.byref(vol), ctypes.byref(chg),
+                                        _stream(stream)))
+        return {"lambda": lam.value, "volume": vol.value, "max_change": chg.value}
+
+    def step(self, h, rho, f, u, rtol=1e-6, maxit=200, stream=None):
+        info = SimpInfo()
+        _check(_lib.sgmg_simp_step(self.handle, h.handle, _ptr(rho, torch.float64, self.n_el, "rho"),
+                                   _ptr(f, torch.float64, h.n_dof, "f"), _ptr(u, torch.float64, h.n_dof, "u"),
+                                   rtol, maxit, ctypes.byref(info), _stream(stream)))
+        return {"compliance": info.compliance, "volume": info.volume, "lambda": info.lambda_,
+                "max_change": info.max_change, "pcg_status": STATUS.get(info.pcg_status, info.pcg_status),
+                "pcg_iters": info.pcg_iters, "rel_res_true": info.rel_res_true, "solve_ms": info.solve_ms}
