@@ -384,13 +384,14 @@ int sgmg_simp_sensitivity(sgmg_simp* s, const sgmg_hierarchy* h, const double* u
 int sgmg_simp_oc_update(sgmg_simp* s, double* rho, double* lambda, double* volume,
                         double* max_change, void* stream);
 /* One SIMP iteration: physical field, sgmg_update_moduli (which re-estimates
- * the smoother spectra only when max E moved by more than 10 %), the
- * V-cycle-preconditioned PCG solve from the u passed in (a warm start from
- * the previous design), sensitivities and the OC update of rho.  The
- * hierarchy must have been set up with input_is_modulus 0 and the same
- * penal, E0 and Emin. */
-int sgmg_simp_step(sgmg_simp* s, sgmg_hierarchy* h, double* rho, const double* f, double* u,
-                   double rtol, int maxit, sgmg_simp_info* info, void* stream);
+ * the smoother spectra only when max E moved by more than 10 %), the PCG
+ * solve (precond as for sgmg_pcg_solve: 2 the V-cycle, 1 Jacobi) from the u
+ * passed in (a warm start from the previous design), sensitivities and the
+ * OC update of rho.  The hierarchy must have been set up with
+ * input_is_modulus 0 and the same penal, E0 and Emin.  A PCG solve that
+ * does not converge is reported in info, not as an error. */
+int sgmg_simp_step(sgmg_simp* s, sgmg_hierarchy* h, int precond, double* rho, const double* f,
+                   double* u, double rtol, int maxit, sgmg_simp_info* info, void* stream);
 
 const char* sgmg_last_error(void);
 

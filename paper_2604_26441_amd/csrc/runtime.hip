@@ -1918,8 +1918,8 @@ int sgmg_simp_oc_update(sgmg_simp* s, double* rho, double* lambda, double* volum
   return 0;
 }
 
-int sgmg_simp_step(sgmg_simp* s, sgmg_hierarchy* h, double* rho, const double* f, double* u,
-                   double rtol, int maxit, sgmg_simp_info* info, void* stream) {
+int sgmg_simp_step(sgmg_simp* s, sgmg_hierarchy* h, int precond, double* rho, const double* f,
+                   double* u, double rtol, int maxit, sgmg_simp_info* info, void* stream) {
   if (!s || !h || !rho || !f || !u) { set_error("NULL argument"); return SGMG_EINVAL; }
   const sgmg_simp_params& p = s->p;
   const sgmg_options& o = h->o;
@@ -1930,7 +1930,7 @@ int sgmg_simp_step(sgmg_simp* s, sgmg_hierarchy* h, double* rho, const double* f
   TRY(sgmg_simp_physical(s, rho, nullptr, stream));
   TRY(sgmg_update_moduli(h, s->rhohat, stream));
   sgmg_solve_info si{};
-  TRY(sgmg_pcg_solve(h, 2, f, u, rtol, maxit, &si, stream));
+  TRY(sgmg_pcg_solve(h, precond, f, u, rtol, maxit, &si, stream));
   double c = 0.0, lam = 0.0, vol = 0.0, chg = 0.0;
   TRY(sgmg_simp_sensitivity(s, h, u, &c, nullptr, nullptr, stream));
   TRY(sgmg_simp_oc_update(s, rho, &lam, &vol, &chg, stream));

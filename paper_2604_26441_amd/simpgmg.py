@@ -138,7 +138,7 @@ def _load():
     lib.sgmg_simp_physical.argtypes = [H, vp, vp, vp]
     lib.sgmg_simp_sensitivity.argtypes = [H, H, vp, dp, vp, vp, vp]
     lib.sgmg_simp_oc_update.argtypes = [H, vp, dp, dp, dp, vp]
-    lib.sgmg_simp_step.argtypes = [H, H, vp, vp, vp, d, i, ctypes.POINTER(SimpInfo), vp]
+    lib.sgmg_simp_step.argtypes = [H, H, i, vp, vp, vp, d, i, ctypes.POINTER(SimpInfo), vp]
     lib.sgmg_num_levels.argtypes = [H]
     lib.sgmg_level_info.argtypes = [H, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                     ctypes.POINTER(ctypes.c_double)]
@@ -581,9 +581,10 @@ class Simp:
                                         _stream(stream)))
         return {"lambda": lam.value, "volume": vol.value, "max_change": chg.value}
 
-    def step(self, h, rho, f, u, rtol=1e-6, maxit=200, stream=None):
+    def step(self, h, rho, f, u, rtol=1e-6, maxit=200, precond=PRECOND_VCYCLE, stream=None):
         info = SimpInfo()
-        _check(_lib.sgmg_simp_step(self.handle, h.handle, _ptr(rho, torch.float64, self.n_el, "rho"),
+        _check(_lib.sgmg_simp_step(self.handle, h.handle, precond,
+                                   _ptr(rho, torch.float64, self.n_el, "rho"),
                                    _ptr(f, torch.float64, h.n_dof, "f"), _ptr(u, torch.float64, h.n_dof, "u"),
                                    rtol, maxit, ctypes.byref(info), _stream(stream)))
         return {"compliance": info.compliance, "volume": info.volume, "lambda": info.lambda_,

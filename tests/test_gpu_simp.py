@@ -3,7 +3,6 @@ update, full steps) against the oracle, through the C-ABI."""
 import numpy as np
 import pytest
 
-import workloads
 from oracle import mesh, simp
 from tests.gpu_util import np64, t64
 

@@ -21,7 +21,13 @@ Recipes (the paper uses no external dataset, Sec. 6 data statement):
   * the deterministic stress fields of E10: a checkerboard of solid and void
     elements, and a layered field (solid lower half in z, void upper half);
   * the mixed near-void field of E10: half the elements near void
-    (rho = floor * U(1, 10)), the rest U(0.2, 1), by seed.
+    (rho = floor * U(1, 10)), the rest U(0.2, 1), by seed;
+  * the two small benchmarks of the auxiliary OC schedule (App. e3_aux),
+    which the paper names only: an MBB half-beam (symmetry u_x = 0 on the
+    x = 0 face, a roller u_y = u_z = 0 along the bottom edge at x = nx, unit
+    -z load along the top edge at x = 0) and a torsion bar (clamped x = 0
+    face, unit torque about the bar axis on the x = nx face, nodal forces
+    perpendicular to the radius and proportional to it).
 """
 import numpy as np
 
@@ -158,3 +164,39 @@ def robustness_suite(dims):
         ("binary Vf=0.5 floor 1e-12", binary_rho(dims, 0.5, 1e-12, 17), 3.0),
         ("mixed near-void", mixed_near_void_rho(dims, 19), 3.0),
     ]
+
+
+def _node_ijk(dims):
+    nx, ny, nz = dims
+    n = np.arange(n_nodes(dims))
+    return n % (nx + 1), (n // (nx + 1)) % (ny + 1), n // ((nx + 1) * (ny + 1))
+
+
+def mbb_fixed(dims):
+    nx, ny, nz = dims
+    i, j, k = _node_ijk(dims)
+    m = np.zeros((n_nodes(dims), 3), dtype=np.uint8)
+    m[i == 0, 0] = 1
+    roller = (i == nx) & (k == 0)
+    m[roller, 1] = 1
+    m[roller, 2] = 1
+    return m.reshape(-1)
+
+
+def mbb_load(dims):
+    nx, ny, nz = dims
+    i, j, k = _node_ijk(dims)
+    f = np.zeros((n_nodes(dims), 3))
+    f[(i == 0) & (k == nz), 2] = -1.0 / (ny + 1)
+    return f.reshape(-1)
+
+
+def torsion_load(dims):
+    nx, ny, nz = dims
+    i, j, k = _node_ijk(dims)
+    face = i == nx
+    y, z = j[face] - ny / 2.0, k[face] - nz / 2.0
+    f = np.zeros((n_nodes(dims), 3))
+    f[face, 1] = -z
+    f[face, 2] = y
+    return f.reshape(-1) / float(np.sum(y * y + z * z))
