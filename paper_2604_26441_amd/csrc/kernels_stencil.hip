@@ -228,9 +228,16 @@ __global__ __launch_bounds__(192 * NZ) void k_stencil_apply_c(Grid g, const T* _
   __shared__ double part[NZ][3][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int d = w % 3, pz = NZ == 1 ? 0 : w / 3;
-  const int node = xcd_block(blockIdx.x, gridDim.x) * 64 + lane;
-  const bool in = node < g.Nn;
-  if (in) {
+  const int node0 = xcd_block(blockIdx.x, gridDim.x) * 64 + lane;
+  const bool in = node0 < g.Nn;
+  // Lanes past the grid work on the last node and store nothing.  The
+  // plane-split form (9 offsets per wave) is branch-free: offsets outside
+  // the grid read the node itself (a valid address) and add zero, so all of
+  // a wave's loads can be in flight at once.  The 27-offset form keeps the
+  // branch: hoisting all of its loads would need more than 128 registers
+  // (one wave per SIMD, or spills under a cap), which is slower.
+  const int node = in ? node0 : g.Nn - 1;
+  {
     const int i = node % g.Nx, t = node / g.Nx, j = t % g.Ny, k = t / g.Ny;
     const size_t Nn = g.Nn;
     T acc = (T)0;
@@ -238,21 +245,21 @@ __global__ __launch_bounds__(192 * NZ) void k_stencil_apply_c(Grid g, const T* _
     for (int q = 0; q < 27 / NZ; ++q) {
       const int o = NZ == 1 ? q : 9 * pz + q;
       const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-      {
-        const bool ok = (unsigned)(i + ox) < (unsigned)g.Nx && (unsigned)(j + oy) < (unsigned)g.Ny &&
-                        (unsigned)(k + oz) < (unsigned)g.Nz;
-        if (!ok) continue;
-        const int nb = node + ox + g.Nx * (oy + g.Ny * oz);
-        const size_t b3 = 3 * (size_t)nb;
-        const T u0 = u[b3], u1 = u[b3 + 1], u2 = u[b3 + 2];
-        if (o >= 13) {
-          const T* Sb = S + ((size_t)o * 9 + 3 * d) * Nn + node;
-          acc += Sb[0] * u0 + Sb[Nn] * u1 + Sb[2 * Nn] * u2;
-        } else {
-          const T* Sb = S + ((size_t)(26 - o) * 9 + d) * Nn + nb;
-          acc += Sb[0] * u0 + Sb[3 * Nn] * u1 + Sb[6 * Nn] * u2;
-        }
+      const bool ok = (unsigned)(i + ox) < (unsigned)g.Nx && (unsigned)(j + oy) < (unsigned)g.Ny &&
+                      (unsigned)(k + oz) < (unsigned)g.Nz;
+      if (NZ == 1 && !ok) continue;
+      const int nb = ok ? node + ox + g.Nx * (oy + g.Ny * oz) : node;
+      const size_t b3 = 3 * (size_t)nb;
+      const T u0 = u[b3], u1 = u[b3 + 1], u2 = u[b3 + 2];
+      T v;
+      if (o >= 13) {
+        const T* Sb = S + ((size_t)o * 9 + 3 * d) * Nn + node;
+        v = Sb[0] * u0 + Sb[Nn] * u1 + Sb[2 * Nn] * u2;
+      } else {
+        const T* Sb = S + ((size_t)(26 - o) * 9 + d) * Nn + nb;
+        v = Sb[0] * u0 + Sb[3 * Nn] * u1 + Sb[6 * Nn] * u2;
       }
+      acc += ok ? v : (T)0;
     }
     part[pz][d][lane] = (double)acc;
   }
