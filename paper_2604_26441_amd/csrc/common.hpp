@@ -103,7 +103,7 @@ enum EpiMode { EPI_STORE = 0, EPI_RESID = 1, EPI_SMOOTH = 2 };
 template <typename T>
 struct Epi {
   int mode;
-  T* out;              // STORE/RESID output, SMOOTH: x_out
+  T* out;              // STORE/RESID output, SMOOTH: x_out (may be NULL when out64 is set)
   const T* b;
   const T* dinv;
   T* d;                // SMOOTH direction (read if c1 != 0, written if store_d)
@@ -144,7 +144,7 @@ __device__ inline double epilogue3(const Epi<T>& ep, int node, unsigned fx, cons
         xo = x[c] + dd;
       }
       if (ep.store_d) ep.d[base + c] = dd;
-      ep.out[base + c] = xo;
+      if (ep.out) ep.out[base + c] = xo;
       if (ep.out64) ep.out64[base + c] = (double)xo;
     }
   }
@@ -182,7 +182,7 @@ __device__ inline double epilogue3_pre(const Epi<T>& ep, int node, unsigned fx, 
         xo = x[c] + dd;
       }
       if (ep.store_d) ep.d[base + c] = dd;
-      ep.out[base + c] = xo;
+      if (ep.out) ep.out[base + c] = xo;
       if (ep.out64) ep.out64[base + c] = (double)xo;
     }
   }
@@ -209,7 +209,7 @@ __device__ inline double epilogue1(const Epi<T>& ep, size_t dof, bool fixed, T x
     xo = x + dd;
   }
   if (ep.store_d) ep.d[dof] = dd;
-  ep.out[dof] = xo;
+  if (ep.out) ep.out[dof] = xo;
   if (ep.out64) ep.out64[dof] = (double)xo;
   return 0.0;
 }

@@ -222,7 +222,7 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
   rs.b = make_rsrc(ep.b, MODE == EPI_RESID || MODE == EPI_SMOOTH ? nvec : 0);
   rs.di = make_rsrc(ep.dinv, MODE == EPI_SMOOTH ? nvec : 0);
   rs.d = make_rsrc(ep.d, MODE == EPI_SMOOTH ? nvec : 0);
-  rs.out = make_rsrc(ep.out, nvec);
+  rs.out = make_rsrc(ep.out, ep.out ? nvec : 0);   // no output: every store is dropped
   // inputs of element (ex, ey, ez) for this lane's node pair; zero outside
   auto load_in = [&](int ey, int ez, In& in) {
     const bool ok = x_ok && ey >= 0 && ey < g.ny && ez >= 0 && ez < g.nz && ez < zend;
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma64(
   rs.b = make_rsrc(ep.b, MODE == EPI_RESID || MODE == EPI_SMOOTH ? nvec : 0);
   rs.di = make_rsrc(ep.dinv, MODE == EPI_SMOOTH ? nvec : 0);
   rs.d = make_rsrc(ep.d, MODE == EPI_SMOOTH ? nvec : 0);
-  rs.out = make_rsrc(ep.out, nvec);
+  rs.out = make_rsrc(ep.out, ep.out ? nvec : 0);   // no output: every store is dropped
   auto load_in = [&](int ey, int ez, In& in) {
     const bool ok = x_ok && ey >= 0 && ey < g.ny && ez >= 0 && ez < g.nz && ez < zend;
     const int node = ex + g.Nx * ((ey + dy_in) + g.Ny * (ez + dz_in));

@@ -453,8 +453,11 @@ int smooth_and_recurse(const sgmg_hierarchy* h, int l, int* cur, double* out64, 
         rho = rn;
       }
     }
+    // the pass's last direction is never read again (the next pass starts
+    // with c1 = 0), so it is not stored
+    const int store_d = sm.cheb && k < sm.steps - 1;
     TRY(apply_level<T>(h, l, prec, (const T*)L.x[c],
-                       epi_smooth<T>((T*)L.x[1 - c], b, dinv, d, c1, c2, sm.cheb, nullptr), s));
+                       epi_smooth<T>((T*)L.x[1 - c], b, dinv, d, c1, c2, store_d, nullptr), s));
     c = 1 - c;
   }
   // residual, restriction, coarse correction
@@ -485,9 +488,13 @@ int smooth_and_recurse(const sgmg_hierarchy* h, int l, int* cur, double* out64, 
         rho = rn;
       }
     }
-    double* o64 = (k == sm.steps - 1) ? out64 : nullptr;
+    const bool last = k == sm.steps - 1;
+    double* o64 = last ? out64 : nullptr;
+    // the cycle's result leaves through out64 only: the level's own copy of
+    // the last iterate is not written
+    T* xout = last && out64 ? nullptr : (T*)L.x[1 - c];
     TRY(apply_level<T>(h, l, prec, (const T*)L.x[c],
-                       epi_smooth<T>((T*)L.x[1 - c], b, dinv, d, c1, c2, sm.cheb, o64), s));
+                       epi_smooth<T>(xout, b, dinv, d, c1, c2, sm.cheb && !last, o64), s));
     c = 1 - c;
   }
   *cur = c;

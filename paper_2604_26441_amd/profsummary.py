@@ -1,12 +1,16 @@
 """Summarise a rocprofv3 kernel-trace database (rocpd SQLite) as Markdown.
 
-  python -m paper_2604_26441_amd.profsummary RESULTS_DB [--match NAME --last N]
+  python -m paper_2604_26441_amd.profsummary RESULTS_DB [--match NAME --last N] [--solve]
   python -m paper_2604_26441_amd.profsummary --counters COUNTER_CSV
   python -m paper_2604_26441_amd.profsummary --traffic FETCH_CSV WRITE_CSV
 
 Prints the per-kernel totals (calls, total, average, share) and, with
 --match, the average duration of the last N dispatches whose kernel name
 contains NAME (for example the back-to-back timing loop of one kernel).
+With --solve, also the kernels of the last PCG solve in the trace (from its
+k_pcg_init dispatch up to the first later dispatch that is not the
+library's, a new k_pcg_init, or a STORE-mode K.u timing launch):
+their count, kernel time and first-start to last-end span, per kernel.
 With --counters, reads a rocprofv3 --pmc CSV (counter_collection.csv) and
 prints, per kernel, the dispatch count and the mean of each counter.
 """
@@ -63,6 +67,37 @@ def counters(path):
         print(f"| `{name}` | {nd} | " + " | ".join(f"{v:.1f}" for v in vals) + " |")
 
 
+def last_solve(c):
+    rows = list(c.execute("select name, start, end from kernels order by start"))
+    starts = [i for i, r in enumerate(rows) if "k_pcg_init" in r[0]]
+    if not starts:
+        return
+    i0 = starts[-1]
+    seg = rows[i0:]
+    # the solve ends before the first kernel that is not the library's (the
+    # caller's own work), a new solve, or a timing loop of STORE K.u
+    end = len(seg)
+    for k, r in enumerate(seg[1:], 1):
+        if ("sgmg::" not in r[0] and "rocclr" not in r[0]) or "k_pcg_init" in r[0] or \
+                "mfma<3, 4, 0>" in r[0] or "mfma<3, 8, 0>" in r[0]:
+            end = k
+            break
+    seg = seg[:end]
+    busy = sum(e - s for _, s, e in seg)
+    span = seg[-1][2] - seg[0][1]
+    tot = defaultdict(lambda: [0, 0])
+    for n, s, e in seg:
+        k = n.replace("sgmg::", "").split("(")[0]
+        tot[k][0] += 1
+        tot[k][1] += e - s
+    print(f"\nLast solve: {len(seg)} kernels, {busy / 1e3:.0f} us of kernel time in "
+          f"{span / 1e3:.0f} us from the first kernel's start to the last one's end.\n")
+    print("| kernel | calls | total (us) | average (us) | share of kernel time |")
+    print("|---|---|---|---|---|")
+    for k, (n, t) in sorted(tot.items(), key=lambda kv: -kv[1][1]):
+        print(f"| `{k}` | {n} | {t / 1e3:.1f} | {t / n / 1e3:.2f} | {100 * t / busy:.1f}% |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("db", nargs="?")
@@ -72,6 +107,7 @@ def main():
     ap.add_argument("--match", default=None)
     ap.add_argument("--last", type=int, default=200)
     ap.add_argument("--top", type=int, default=25)
+    ap.add_argument("--solve", action="store_true")
     a = ap.parse_args()
     if a.counters:
         counters(a.counters)
@@ -89,6 +125,8 @@ def main():
     for name, calls, tot, avg, pct in rows[: a.top]:
         short = name.replace("sgmg::", "").split("(")[0]
         print(f"| `{short}` | {calls} | {tot / 1e3:.3f} | {avg:.3f} | {pct:.1f}% |")
+    if a.solve:
+        last_solve(c)
     if a.match:
         durs = [r[0] for r in c.execute(
             "select duration from kernels where name like ? order by start", (f"%{a.match}%",))]
