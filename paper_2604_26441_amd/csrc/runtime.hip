@@ -565,6 +565,8 @@ extern "C" {
 
 const char* sgmg_last_error(void) { return g_err.c_str(); }
 
+static int capture_vcycle_graphs(sgmg_hierarchy* h, hipStream_t s);
+
 void sgmg_default_options(sgmg_options* o, int nx, int ny, int nz) {
   std::memset(o, 0, sizeof(*o));
   o->nx = nx; o->ny = ny; o->nz = nz;
@@ -777,6 +779,7 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
   rc = estimate_lambdas(h, s);
   h->o.lambda_override = nullptr;
   if (rc) return fail(rc);
+  if ((rc = capture_vcycle_graphs(h, s))) return fail(rc);
   if (hipStreamSynchronize(s) != hipSuccess) { set_error("sync failed"); return fail(SGMG_EHIP); }
   *out = h;
   return 0;
@@ -785,13 +788,17 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
 int sgmg_update_moduli(sgmg_hierarchy* h, const double* rho_or_E, void* stream) {
   if (!h || !rho_or_E) { set_error("NULL argument"); return SGMG_EINVAL; }
   hipStream_t s = as_stream(stream);
-  for (auto& row : h->iter_graph)
-    for (auto& g : row)
-      if (g) { hipGraphExecDestroy(g); g = nullptr; }
   TRY(assemble_operators(h, rho_or_E, s));
   const double m = max_modulus(h, s);
-  if (h->maxE_lambda <= 0.0 || std::fabs(m - h->maxE_lambda) > 0.1 * h->maxE_lambda)
+  if (h->maxE_lambda <= 0.0 || std::fabs(m - h->maxE_lambda) > 0.1 * h->maxE_lambda) {
+    // new spectral estimates change the smoothing coefficients that the
+    // iteration graphs hold; the operators themselves stay in place
+    for (auto& row : h->iter_graph)
+      for (auto& g : row)
+        if (g) { hipGraphExecDestroy(g); g = nullptr; }
     TRY(estimate_lambdas(h, s));
+  }
+  TRY(capture_vcycle_graphs(h, s));
   SGMG_HIP(hipStreamSynchronize(s));
   return 0;
 }
@@ -851,9 +858,10 @@ static int pcg_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
   return check_launch();
 }
 
-static int run_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
-  if (!h->o.use_graphs) return pcg_body(h, precond, slot, s);
-  const int par = slot == SC_RZ0 ? 0 : 1;
+// Captures (once) the graph of one PCG iteration for a preconditioner and
+// slot parity.  Capture records the launches without running them.
+static int ensure_graph(sgmg_hierarchy* h, int precond, int par, hipStream_t s) {
+  const int slot = par == 0 ? SC_RZ0 : SC_RZ1;
   hipGraphExec_t& ge = h->iter_graph[precond][par];
   if (!ge) {
     if (!h->cap) SGMG_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
@@ -869,8 +877,23 @@ static int run_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
     hipGraphDestroy(g);
     if (e2 != hipSuccess) { ge = nullptr; set_error(std::string("graph instantiate: ") + hipGetErrorString(e2)); return SGMG_EHIP; }
   }
-  SGMG_HIP(hipGraphLaunch(ge, s));
   return 0;
+}
+
+static int run_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
+  if (!h->o.use_graphs) return pcg_body(h, precond, slot, s);
+  const int par = slot == SC_RZ0 ? 0 : 1;
+  TRY(ensure_graph(h, precond, par, s));
+  SGMG_HIP(hipGraphLaunch(h->iter_graph[precond][par], s));
+  return 0;
+}
+
+// The V-cycle-preconditioned iteration graphs are part of the hierarchy:
+// captured at setup and after every re-assembly, so a solve only launches.
+static int capture_vcycle_graphs(sgmg_hierarchy* h, hipStream_t s) {
+  if (!h->o.use_graphs) return 0;
+  TRY(ensure_graph(h, 2, 0, s));
+  return ensure_graph(h, 2, 1, s);
 }
 
 int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, double rtol,
