@@ -83,20 +83,26 @@ void launch_copy(const double* in, double* out, int n, hipStream_t s);
 // PCG pieces; sc = device scalar block (see runtime.hip for slots)
 void launch_pcg_init(const double* f, const double* Ax0, int have_x0, double* r, int n,
                      RedWs ws, double* sc_ff_rr, hipStream_t s);
-void launch_pcg_update_xr(double* x, double* r, double* r_old, const double* p, const double* q,
-                          const double* sc, int slot_rz, int slot_pq, int n, RedWs ws,
-                          double* sc_rr, hipStream_t s);
-// The same update, also writing the entry of the V-cycle that follows
-// (b = (T) r, x = c0 Dinv b, d = x when d is not NULL).
+// x += alpha p, r -= alpha q (alpha = sc[slot_rz] / sc[slot_pq]; a failed
+// step leaves both), r.r; with b not NULL also the entry of the V-cycle that
+// follows (b = (T) r, x = c0 Dinv b, d = x when d is not NULL).  sc_rr NULL:
+// the r.r partials stay in ws for launch_pcg_update_p_red.
 template <typename T>
 void launch_pcg_update_xr_entry(double* x, double* r, double* r_old, const double* p,
                                 const double* q, const double* sc, int slot_rz, int slot_pq, int n,
                                 RedWs ws, double* sc_rr, T* b, const T* dinv, double c0, T* xe,
                                 T* de, hipStream_t s);
+// (sc_out2 NULL: partials only, for launch_pcg_update_p_red)
 void launch_pcg_dot_rz(const double* r, const double* z, const double* r_old, int n, RedWs ws,
                        double* sc_out2, hipStream_t s);
-void launch_pcg_update_p(double* p, const double* z, const double* sc, int slot_num,
-                         int slot_sub, int slot_den, int n, hipStream_t s);
+// Block count (= partials per reduced value) of the vector kernels above.
+int pcg_vec_partials(int n);
+// p = z + beta p with the r.z partials added in every block (no finalize
+// launch); block 0 stores r.z [and r_old.z] at sc[slot_num] [slot_num + 1]
+// and the sum of the r.r partials at sc[slot_rr].
+void launch_pcg_update_p_red(double* p, const double* z, const double* rz_part,
+                             const double* rr_part, double* sc, int slot_num, int flex,
+                             int slot_den, int slot_rr, int n, hipStream_t s);
 // *out = max over (free) entries of a non-negative vector (fixn may be NULL)
 void launch_max_nonneg(const double* a, const uint8_t* fixn, int n, double* out, hipStream_t s);
 void launch_diag_finalize(double* d, double* dinv64, float* dinv32, const uint8_t* fixn, int n,

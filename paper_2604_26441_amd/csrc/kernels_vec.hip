@@ -219,14 +219,6 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(double* __restrict_
   grid_sum<1>(v, ws);
 }
 
-void launch_pcg_update_xr(double* x, double* r, double* r_old, const double* p, const double* q,
-                          const double* sc, int slot_rz, int slot_pq, int n, RedWs ws,
-                          double* sc_rr, hipStream_t s) {
-  k_pcg_update_xr<double><<<vec_grid(n), kVecBlock, 0, s>>>(x, r, r_old, p, q, sc, slot_rz,
-                                                            slot_pq, n, ws, VEntry<double>{});
-  launch_finalize(ws, vec_grid(n), 1, sc_rr, s);
-}
-
 template <typename T>
 void launch_pcg_update_xr_entry(double* x, double* r, double* r_old, const double* p,
                                 const double* q, const double* sc, int slot_rz, int slot_pq, int n,
@@ -240,7 +232,7 @@ void launch_pcg_update_xr_entry(double* x, double* r, double* r_old, const doubl
   e.d = de;
   k_pcg_update_xr<T><<<vec_grid(n), kVecBlock, 0, s>>>(x, r, r_old, p, q, sc, slot_rz, slot_pq,
                                                        n, ws, e);
-  launch_finalize(ws, vec_grid(n), 1, sc_rr, s);
+  if (sc_rr) launch_finalize(ws, vec_grid(n), 1, sc_rr, s);
 }
 template void launch_pcg_update_xr_entry<float>(double*, double*, double*, const double*,
                                                 const double*, const double*, int, int, int,
@@ -269,23 +261,52 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_dot_rz(const double* __restri
 void launch_pcg_dot_rz(const double* r, const double* z, const double* r_old, int n, RedWs ws,
                        double* sc_out2, hipStream_t s) {
   k_pcg_dot_rz<<<vec_grid(n), kVecBlock, 0, s>>>(r, z, r_old, n, ws, sc_out2);
-  launch_finalize(ws, vec_grid(n), 2, sc_out2, s);
+  if (sc_out2) launch_finalize(ws, vec_grid(n), 2, sc_out2, s);
 }
 
-// p = z + beta p with beta = (sc[num] - sc[sub]) / sc[den]  (sub < 0: no term)
-__global__ void k_pcg_update_p(double* __restrict__ p, const double* __restrict__ z,
-                               const double* __restrict__ sc, int slot_num, int slot_sub,
-                               int slot_den, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double num = sc[slot_num] - (slot_sub >= 0 ? sc[slot_sub] : 0.0);
-  const double beta = num / sc[slot_den];
-  p[i] = z[i] + beta * p[i];
+int pcg_vec_partials(int n) { return (int)vec_grid(n); }
+
+// p = z + beta p where the block partials of r.z (and r_old.z) from
+// k_pcg_dot_rz are added here, by every block in the same order, instead of
+// by a separate finalize launch: beta = (rz - [r_old.z]) / sc[slot_den].
+// Block 0 also stores rz (and r_old.z) into sc[slot_num] (sc[slot_num + 1])
+// and the sum of the r.r partials of the preceding update into sc[slot_rr].
+__global__ __launch_bounds__(kVecBlock) void k_pcg_update_p_red(
+    double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ rz_part,
+    const double* __restrict__ rr_part, int nb, double* __restrict__ sc, int slot_num, int flex,
+    int slot_den, int slot_rr, int n) {
+  __shared__ double lds[3][16];
+  __shared__ double tot[3];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kVecBlock) {
+    a += rz_part[i];
+    if (flex) b += rz_part[nb + i];
+    if (blockIdx.x == 0) c += rr_part[i];
+  }
+  a = block_sum(a, lds[0]);
+  b = block_sum(b, lds[1]);
+  c = block_sum(c, lds[2]);
+  if (threadIdx.x == 0) {
+    tot[0] = a;
+    tot[1] = b;
+    tot[2] = c;
+    if (blockIdx.x == 0) {
+      sc[slot_num] = a;
+      if (flex) sc[slot_num + 1] = b;
+      sc[slot_rr] = c;
+    }
+  }
+  __syncthreads();
+  const double beta = (tot[0] - (flex ? tot[1] : 0.0)) / sc[slot_den];
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n; i += gridDim.x * kVecBlock)
+    p[i] = z[i] + beta * p[i];
 }
 
-void launch_pcg_update_p(double* p, const double* z, const double* sc, int slot_num, int slot_sub,
-                         int slot_den, int n, hipStream_t s) {
-  k_pcg_update_p<<<div_up(n, 256), 256, 0, s>>>(p, z, sc, slot_num, slot_sub, slot_den, n);
+void launch_pcg_update_p_red(double* p, const double* z, const double* rz_part,
+                             const double* rr_part, double* sc, int slot_num, int flex,
+                             int slot_den, int slot_rr, int n, hipStream_t s) {
+  k_pcg_update_p_red<<<vec_grid(n), kVecBlock, 0, s>>>(p, z, rz_part, rr_part, (int)vec_grid(n),
+                                                       sc, slot_num, flex, slot_den, slot_rr, n);
 }
 
 // Largest value of a (non-negative entries, or masked by fixn when given).

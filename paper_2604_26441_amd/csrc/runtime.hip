@@ -829,6 +829,12 @@ static int pcg_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
   double* sc = h->sc;
   const bool flex = h->o.flexible_beta != 0;
   const int nslot = slot == SC_RZ0 ? SC_RZ1 : SC_RZ0;
+  // The r.r partials of the update and the r.z partials after the
+  // preconditioner are summed inside the p update (no finalize launches);
+  // they sit in disjoint parts of the workspace.
+  const int nb = pcg_vec_partials(n);
+  RedWs ws_rr = h->ws;
+  ws_rr.partials = h->ws.partials + 2 * (size_t)nb;
   TRY(apply_level<double>(h, 0, SGMG_F64, h->p, epi_store<double>(h->q, h->ws, sc + SC_PQ), s));
   if (precond == 2) {
     // the update also writes the V-cycle's entry (its first smoothing step)
@@ -836,25 +842,27 @@ static int pcg_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
     const double c0 = first_step_coef(sm);
     if (L0.f32)
       launch_pcg_update_xr_entry<float>(h->xs, h->r, flex ? h->r_old : nullptr, h->p, h->q, sc,
-                                        slot, SC_PQ, n, h->ws, sc + SC_RR, (float*)L0.b,
+                                        slot, SC_PQ, n, ws_rr, nullptr, (float*)L0.b,
                                         L0.dinv32, c0, (float*)L0.x[0],
                                         sm.cheb ? (float*)L0.dv : nullptr, s);
     else
       launch_pcg_update_xr_entry<double>(h->xs, h->r, flex ? h->r_old : nullptr, h->p, h->q, sc,
-                                         slot, SC_PQ, n, h->ws, sc + SC_RR, (double*)L0.b,
+                                         slot, SC_PQ, n, ws_rr, nullptr, (double*)L0.b,
                                          L0.dinv64, c0, (double*)L0.x[0],
                                          sm.cheb ? (double*)L0.dv : nullptr, s);
     TRY(check_launch());
     int cur = 0;
     TRY(vcycle_level(h, 0, &cur, h->z, true, s));
   } else {
-    launch_pcg_update_xr(h->xs, h->r, flex ? h->r_old : nullptr, h->p, h->q, sc, slot, SC_PQ, n,
-                         h->ws, sc + SC_RR, s);
+    launch_pcg_update_xr_entry<double>(h->xs, h->r, flex ? h->r_old : nullptr, h->p, h->q, sc,
+                                       slot, SC_PQ, n, ws_rr, nullptr, nullptr, nullptr, 0.0,
+                                       nullptr, nullptr, s);
     if (precond == 1) launch_apply_dinv(L0.dinv64, h->r, h->z, n, s);
     else launch_copy(h->r, h->z, n, s);
   }
-  launch_pcg_dot_rz(h->r, h->z, flex ? h->r_old : nullptr, n, h->ws, sc + nslot, s);
-  launch_pcg_update_p(h->p, h->z, sc, nslot, flex ? nslot + 1 : -1, slot, n, s);
+  launch_pcg_dot_rz(h->r, h->z, flex ? h->r_old : nullptr, n, h->ws, nullptr, s);
+  launch_pcg_update_p_red(h->p, h->z, h->ws.partials, ws_rr.partials, sc, nslot, flex ? 1 : 0,
+                          slot, SC_RR, n, s);
   return check_launch();
 }
 
