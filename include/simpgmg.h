@@ -92,7 +92,9 @@ typedef struct {
   int power_iters_fine;      /* power iterations on level 0 (20)                     */
   int power_iters_coarse;    /* power iterations on levels >= 1 (10)                 */
   sgmg_prec fine_prec;       /* level-0 smoother/residual arithmetic                 */
-  sgmg_prec level1_prec;     /* F64 or F32: storage and arithmetic of level 1        */
+  sgmg_prec level1_prec;     /* F64 or F32: storage and arithmetic of level 1 (the
+                                paper's BF16 schedule, Eq. prec_schedule, uses F32;
+                                its FP32-GMG runs F64)                               */
   int dense_max;             /* coarsest dense-solve limit on free DOFs (5000)       */
   int coarse_pcg_iters;      /* Jacobi-PCG steps of the coarsest solve when its
                                 free-DOF count exceeds dense_max (80)                */

@@ -225,7 +225,11 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
   rs.out = make_rsrc(ep.out, ep.out ? nvec : 0);   // no output: every store is dropped
   // inputs of element (ex, ey, ez) for this lane's node pair; zero outside
   auto load_in = [&](int ey, int ez, In& in) {
-    const bool ok = x_ok && ey >= 0 && ey < g.ny && ez >= 0 && ez < g.nz && ez < zend;
+    // row and plane tests are wave-uniform (one scalar condition); combining
+    // them with the lane's x test by a non-short-circuit & keeps the
+    // address selection a per-lane select instead of masked control flow
+    const bool yz_ok = (unsigned)ey < (unsigned)g.ny && (unsigned)ez < (unsigned)g.nz && ez < zend;
+    const bool ok = x_ok & yz_ok;
     const int node = ex + g.Nx * ((ey + dy_in) + g.Ny * (ez + dz_in));
     const int off = ok ? node * 12 : kNoOffset;
     bload3(ru, off, in.v);
@@ -267,7 +271,8 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
   // node (ex, ys - 1 + r, ez) is written by this lane
   const bool ep_lane = grp == 0 && n >= 1 && ex < g.Nx;
   auto owns = [&](int r, int ez) {
-    return r >= 1 && ep_lane && ez >= zs && ez < zend && ys - 1 + r < g.Ny;
+    const bool uni = r >= 1 && ez >= zs && ez < zend && ys - 1 + r < g.Ny;   // wave-uniform
+    return ep_lane & uni;
   };
 
   float zc[YC][3];
@@ -372,7 +377,8 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma64(
   rs.d = make_rsrc(ep.d, MODE == EPI_SMOOTH ? nvec : 0);
   rs.out = make_rsrc(ep.out, ep.out ? nvec : 0);   // no output: every store is dropped
   auto load_in = [&](int ey, int ez, In& in) {
-    const bool ok = x_ok && ey >= 0 && ey < g.ny && ez >= 0 && ez < g.nz && ez < zend;
+    const bool yz_ok = (unsigned)ey < (unsigned)g.ny && (unsigned)ez < (unsigned)g.nz && ez < zend;
+    const bool ok = x_ok & yz_ok;     // as in the FP32 kernel: one per-lane select
     const int node = ex + g.Nx * ((ey + dy_in) + g.Ny * (ez + dz_in));
     const int off = ok ? node * 24 : kNoOffset;
     bload3(ru, off, in.v);
@@ -394,7 +400,8 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma64(
   };
   const bool ep_lane = grp == 0 && n >= 1 && ex < g.Nx;
   auto owns = [&](int r, int ez) {
-    return r >= 1 && ep_lane && ez >= zs && ez < zend && ys - 1 + r < g.Ny;
+    const bool uni = r >= 1 && ez >= zs && ez < zend && ys - 1 + r < g.Ny;   // wave-uniform
+    return ep_lane & uni;
   };
 
   double zc[YC][3];

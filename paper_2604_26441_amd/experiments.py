@@ -21,11 +21,19 @@ import workloads
 from . import simpgmg
 
 
+def _schedule(kw):
+    """Eq. prec_schedule: the BF16 path runs level 1 in FP32 (levels >= 2
+    stay FP64); FP32-GMG keeps every level >= 1 in FP64."""
+    if kw.get("fine_prec") == "bf16":
+        kw.setdefault("level1_prec", "f32")
+    return kw
+
+
 def _solve(dims, precond=2, maxit=200, trials=5, warmup=2, **kw):
     dev = "cuda:0"
     rho = torch.tensor(workloads.uniform_rho(dims), dtype=torch.float64, device=dev)
     f = torch.tensor(workloads.edge_load(dims), dtype=torch.float64, device=dev)
-    o = simpgmg.default_options(*dims, **kw)
+    o = simpgmg.default_options(*dims, **_schedule(kw))
     if kw.get("fine_prec") in ("bf16", "bf16x3"):
         h = simpgmg.setup_hierarchy(o, rho)
         simpgmg.autotune(h)
@@ -84,7 +92,8 @@ def hetero(n=60, seeds=9, maxit=500):
             rec = {"p": p, "seed": seed, "ref": {"status": ref["status"], "iters": ref["iters"],
                                                   "rel_res_true": ref["rel_res_true"]}}
             for name, kw in variants.items():
-                h = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, penal=float(p), **kw), rho)
+                h = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, penal=float(p),
+                                                                    **_schedule(dict(kw))), rho)
                 if not tuned and kw["fine_prec"] in ("bf16", "bf16x3"):
                     simpgmg.autotune(h)
                     tuned = True
@@ -115,7 +124,7 @@ def _kappa(h, dims, steps=(20, 50)):
 
 
 def _fgmres_run(dims, rho, p, f, fine_prec, restart, maxit):
-    o = simpgmg.default_options(*dims, penal=float(p), fine_prec=fine_prec)
+    o = simpgmg.default_options(*dims, penal=float(p), **_schedule({"fine_prec": fine_prec}))
     h = simpgmg.setup_hierarchy(o, rho)
     u = torch.zeros_like(f)
     r = simpgmg.fgmres_solve(h, f, u, rtol=1e-6, maxit=maxit, restart=restart)
@@ -190,7 +199,7 @@ def robustness(n=40, maxit=500):
 def _timed(dims, rho, f, solver="pcg", restart=32, maxit=500, trials=3, **kw):
     """Setup once, then `trials` solves after one warm-up: mean solve ms
     (HIP events inside the solver), iterations, status, true residual."""
-    h = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, **kw), rho)
+    h = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, **_schedule(dict(kw))), rho)
     ms = []
     for k in range(trials + 1):
         u = torch.zeros_like(f)
