@@ -63,8 +63,11 @@ extern "C" {
  *            (Sec. 3.5, BF16 numerical semantics).  Level 0 only.
  *   BF16X3 : FP32 vectors; the input tile is split into three BF16 terms whose
  *            sum carries the FP32 significand, each term multiplied on MFMA
- *            with FP32 accumulation (FP32-accurate).  Level 0 only.       */
-typedef enum { SGMG_F64 = 0, SGMG_F32 = 1, SGMG_BF16 = 2, SGMG_BF16X3 = 3 } sgmg_prec;
+ *            with FP32 accumulation (FP32-accurate).  Level 0 only.
+ *   BF16X2 : as BF16X3 with two terms (about 16 significant bits of the
+ *            input); runs on BF16X3's launch shape.  Level 0 only.        */
+typedef enum { SGMG_F64 = 0, SGMG_F32 = 1, SGMG_BF16 = 2, SGMG_BF16X3 = 3,
+               SGMG_BF16X2 = 4 } sgmg_prec;
 
 /* Solve status (Sec. 3.6 failure classes). */
 typedef enum {

@@ -7,7 +7,7 @@ a built library.
 """
 import importlib
 
-_BINDING = {"F64", "F32", "BF16", "BF16X3", "Options", "Hierarchy", "SimpGmgError",
+_BINDING = {"F64", "F32", "BF16", "BF16X3", "BF16X2", "Options", "Hierarchy", "SimpGmgError",
             "default_options", "setup_hierarchy", "update_moduli", "apply_K", "vcycle",
             "pcg_solve", "fgmres_solve", "lanczos", "autotune", "library_path", "EXPORTS", "Batch", "setup_batch",
             "pcg_solve_batch", "UNet", "unet_input", "unet_output", "unet_target",

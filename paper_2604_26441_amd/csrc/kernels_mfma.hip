@@ -512,6 +512,9 @@ void launch_apply_fine_mfma(const Grid& g, int nsplit, int rows, int zchunk, con
   if (nsplit == 3) {
     if (rows == 4) launch_shape<3, 4>(g, m, zchunk, Escaled, at, u, fixn, ep, s);
     else launch_shape<3, 8>(g, m, zchunk, Escaled, at, u, fixn, ep, s);
+  } else if (nsplit == 2) {
+    if (rows == 4) launch_shape<2, 4>(g, m, zchunk, Escaled, at, u, fixn, ep, s);
+    else launch_shape<2, 8>(g, m, zchunk, Escaled, at, u, fixn, ep, s);
   } else {
     if (rows == 4) launch_shape<1, 4>(g, m, zchunk, Escaled, at, u, fixn, ep, s);
     else launch_shape<1, 8>(g, m, zchunk, Escaled, at, u, fixn, ep, s);

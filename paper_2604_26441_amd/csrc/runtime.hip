@@ -252,7 +252,7 @@ int apply_level<float>(const sgmg_hierarchy* h, int l, sgmg_prec prec, const flo
   if (l == 0) {
     if (prec == SGMG_F32) {
       launch_apply_fine_node<float>(L.g, h->E32, h->ke32, x, L.fixn, ep, s);
-    } else if (prec == SGMG_BF16 || prec == SGMG_BF16X3) {
+    } else if (prec == SGMG_BF16 || prec == SGMG_BF16X3 || prec == SGMG_BF16X2) {
       if (!h->kt.integral) {
         set_error("BF16 MFMA path needs s*K_e integral (nu = 0.3 family); use F32");
         return SGMG_EINVAL;
@@ -261,8 +261,8 @@ int apply_level<float>(const sgmg_hierarchy* h, int l, sgmg_prec prec, const flo
         set_error("BF16 MFMA path: level-0 vector of 2^31 bytes or more; use F32");
         return SGMG_EINVAL;
       }
-      const int ns = prec == SGMG_BF16 ? 1 : 3;
-      launch_apply_fine_mfma(L.g, ns, h->mfma_rows[ns == 3], h->mfma_zchunk[ns == 3], h->E32s,
+      const int ns = prec == SGMG_BF16 ? 1 : prec == SGMG_BF16X2 ? 2 : 3;
+      launch_apply_fine_mfma(L.g, ns, h->mfma_rows[ns >= 2], h->mfma_zchunk[ns >= 2], h->E32s,
                              h->atab, x, L.fixn, ep, s);
     } else {
       set_error("float vectors need F32, BF16 or BF16X3");
@@ -550,7 +550,7 @@ int validate(const sgmg_options* o) {
     return SGMG_EINVAL;
   }
   if (o->fine_degree < 1 || o->coarse_sweeps < 1) { set_error("smoothing steps must be >= 1"); return SGMG_EINVAL; }
-  if (o->fine_prec < SGMG_F64 || o->fine_prec > SGMG_BF16X3) { set_error("bad fine_prec"); return SGMG_EINVAL; }
+  if (o->fine_prec < SGMG_F64 || o->fine_prec > SGMG_BF16X2) { set_error("bad fine_prec"); return SGMG_EINVAL; }
   if (o->level1_prec != SGMG_F64 && o->level1_prec != SGMG_F32) { set_error("level1_prec must be F64 or F32"); return SGMG_EINVAL; }
   if (!(o->cheb_alpha > 0.0 && o->cheb_alpha < 1.0)) { set_error("cheb_alpha must be in (0,1)"); return SGMG_EINVAL; }
   if (!(o->lambda_safety > 0.0)) { set_error("lambda_safety must be > 0"); return SGMG_EINVAL; }

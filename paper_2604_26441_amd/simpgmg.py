@@ -12,8 +12,8 @@ import torch
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libsimpgmg.so")
 
-F64, F32, BF16, BF16X3 = 0, 1, 2, 3
-PRECISIONS = {"f64": F64, "f32": F32, "bf16": BF16, "bf16x3": BF16X3}
+F64, F32, BF16, BF16X3, BF16X2 = 0, 1, 2, 3, 4
+PRECISIONS = {"f64": F64, "f32": F32, "bf16": BF16, "bf16x3": BF16X3, "bf16x2": BF16X2}
 STATUS = {0: "converged", 1: "maxit", 2: "stagnated", 3: "nonfinite", 4: "breakdown"}
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_VCYCLE = 0, 1, 2
 

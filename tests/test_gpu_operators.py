@@ -121,6 +121,12 @@ def test_fine_apply_mfma_bf16x3_and_bf16(dims, seed):
     assert rel_err(np64(y1), ref1, scale) < 2e-6
     assert rel_err(np64(y1), K @ u, scale) < 2.0 ** -8
     assert np.all(np64(y3)[fixed] == 0) and np.all(np64(y1)[fixed] == 0)
+    # BF16X2: two round-to-nearest terms carry the input to about 2^-17 (a
+    # dropped term would leave 2^-9)
+    y2 = t32(np.zeros_like(u))
+    simpgmg.apply_K(h, 0, "bf16x2", t32(u), y2)
+    e2 = rel_err(np64(y2), K @ u, scale)
+    assert e2 < 2.0 ** -15 and np.all(np64(y2)[fixed] == 0)
     # FP64 operator on the FP64 matrix cores, same tiles (two shapes)
     u64 = workloads.random_vector(fixed.size, seed + 30, fixed)
     for shape in ((4, 2), (8, 5)):

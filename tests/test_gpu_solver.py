@@ -56,7 +56,7 @@ def test_vcycle_f32_close_to_oracle(prec):
     assert rel_err(np64(z), ref, ref) < 1e-4
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "f64-mfma"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "bf16x2", "f64-mfma"])
 def test_config0_pcg(prec):
     """16x8x8 cantilever, rho = 0.5, p = 3, 3 levels, rtol 1e-6, cap 200."""
     from paper_2604_26441_amd import simpgmg
