@@ -276,6 +276,21 @@ int sgmg_pcg_solve_batch(sgmg_batch* b, int nitems, const int* item_sys, const d
                          double* const* u, double rtol, int maxit, sgmg_solve_info* infos,
                          double* total_ms, void* stream);
 
+/* The same items solved by nworkers host threads (1..16), each with a HIP
+ * stream of its own: a worker takes whole systems, largest DOFs x load
+ * cases first, and solves that system's items in item order with
+ * sgmg_pcg_solve (the V-cycle preconditioner; the system's hierarchy, its
+ * work vectors and its captured iteration graphs are used by one worker at
+ * a time).  Each item's result is bitwise that of a lone sgmg_pcg_solve
+ * from the same u.  infos (host, nitems, may be NULL; a history buffer in
+ * an entry is filled) and *total_ms (host wall time) as above.  The caller's
+ * stream is synchronised before the workers start; all work has finished
+ * when the call returns.  The first failing solve's error is returned. */
+int sgmg_pcg_solve_batch_concurrent(sgmg_batch* b, int nitems, const int* item_sys,
+                                    const double* const* f, double* const* u, double rtol,
+                                    int maxit, int nworkers, sgmg_solve_info* infos,
+                                    double* total_ms, void* stream);
+
 /* Borrowed handle of system s (owned by the batch), e.g. for single solves. */
 sgmg_hierarchy* sgmg_batch_hierarchy(sgmg_batch* b, int s);
 /* Block size chosen by the autotuner (0 before the first solve). */

@@ -10,7 +10,7 @@ import importlib
 _BINDING = {"F64", "F32", "BF16", "BF16X3", "BF16X2", "Options", "Hierarchy", "SimpGmgError",
             "default_options", "setup_hierarchy", "update_moduli", "apply_K", "vcycle",
             "pcg_solve", "fgmres_solve", "lanczos", "autotune", "library_path", "EXPORTS", "Batch", "setup_batch",
-            "pcg_solve_batch", "UNet", "unet_input", "unet_output", "unet_target",
+            "pcg_solve_batch", "pcg_solve_batch_concurrent", "UNet", "unet_input", "unet_output", "unet_target",
             "warm_start_scale", "padded_grid", "set_launch_shape", "Simp", "simp_params"}
 
 

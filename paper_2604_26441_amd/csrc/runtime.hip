@@ -2,11 +2,14 @@
 // PCG orchestration on one HIP stream.  All arithmetic runs in the kernels of
 // this library; host code only sequences launches and reads back scalars.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <tuple>
 #include <type_traits>
 #include <vector>
@@ -1764,6 +1767,80 @@ int sgmg_pcg_solve_batch(sgmg_batch* b, int nitems, const int* item_sys, const d
       inf.rel_res_recur = b->h_out[k].rel_recur;
       inf.solve_ms = ms;
     }
+  }
+  return 0;
+}
+
+int sgmg_pcg_solve_batch_concurrent(sgmg_batch* b, int nitems, const int* item_sys,
+                                    const double* const* f, double* const* u, double rtol,
+                                    int maxit, int nworkers, sgmg_solve_info* infos,
+                                    double* total_ms, void* stream) {
+  if (!b || nitems < 1 || !item_sys || !f || !u || maxit < 0 || nworkers < 1 || nworkers > 16) {
+    set_error("bad batch solve arguments");
+    return SGMG_EINVAL;
+  }
+  const int nsys = (int)b->hs.size();
+  std::vector<std::vector<int>> by_sys(nsys);
+  for (int i = 0; i < nitems; ++i) {
+    if (item_sys[i] < 0 || item_sys[i] >= nsys || !f[i] || !u[i]) {
+      set_error("bad item " + std::to_string(i));
+      return SGMG_EINVAL;
+    }
+    by_sys[item_sys[i]].push_back(i);
+  }
+  // systems largest work first (DOFs x load cases), so the long solves start
+  // first and the short ones fill the tail
+  std::vector<int> order;
+  for (int k = 0; k < nsys; ++k)
+    if (!by_sys[k].empty()) order.push_back(k);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    return (double)b->hs[a]->lev[0].g.n * by_sys[a].size() >
+           (double)b->hs[c]->lev[0].g.n * by_sys[c].size();
+  });
+  int dev = 0;
+  SGMG_HIP(hipGetDevice(&dev));
+  SGMG_HIP(hipStreamSynchronize(as_stream(stream)));   // the inputs are ready
+  std::atomic<int> next{0};
+  std::atomic<int> failed{0};
+  std::mutex mu;
+  std::string first_err;
+  auto worker = [&]() {
+    if (hipSetDevice(dev) != hipSuccess) { failed = SGMG_EHIP; return; }
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      std::lock_guard<std::mutex> lk(mu);
+      if (!failed) { failed = SGMG_EHIP; first_err = "worker stream creation failed"; }
+      return;
+    }
+    for (;;) {
+      const int k = next.fetch_add(1);
+      if (k >= (int)order.size() || failed) break;
+      sgmg_hierarchy* h = b->hs[order[k]];
+      for (int i : by_sys[order[k]]) {      // one system's load cases in order
+        sgmg_solve_info local{};
+        sgmg_solve_info* inf = infos ? &infos[i] : &local;
+        const int rc = sgmg_pcg_solve(h, 2, f[i], u[i], rtol, maxit, inf, st);
+        if (rc) {
+          std::lock_guard<std::mutex> lk(mu);
+          if (!failed) { failed = rc; first_err = sgmg_last_error(); }
+          break;
+        }
+      }
+    }
+    hipStreamSynchronize(st);
+    hipStreamDestroy(st);
+  };
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<std::thread> pool;
+  const int nw = std::min<int>(nworkers, (int)order.size());
+  for (int w = 0; w < nw; ++w) pool.emplace_back(worker);
+  for (auto& t : pool) t.join();
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (total_ms) *total_ms = ms;
+  if (failed) {
+    set_error(first_err.empty() ? "concurrent batch solve failed" : first_err);
+    return failed;
   }
   return 0;
 }

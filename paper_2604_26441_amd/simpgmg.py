@@ -77,7 +77,8 @@ EXPORTS = [
     "sgmg_default_options", "sgmg_setup_hierarchy", "sgmg_update_moduli", "sgmg_apply_K",
     "sgmg_vcycle", "sgmg_pcg_solve", "sgmg_fgmres_solve", "sgmg_lanczos", "sgmg_num_levels", "sgmg_level_info",
     "sgmg_copy_stencil", "sgmg_copy_diagonal", "sgmg_destroy", "sgmg_last_error",
-    "sgmg_autotune", "sgmg_set_launch_shape", "sgmg_setup_batch", "sgmg_pcg_solve_batch", "sgmg_batch_hierarchy",
+    "sgmg_autotune", "sgmg_set_launch_shape", "sgmg_setup_batch", "sgmg_pcg_solve_batch",
+    "sgmg_pcg_solve_batch_concurrent", "sgmg_batch_hierarchy",
     "sgmg_batch_block_size", "sgmg_batch_destroy",
     "sgmg_unet_create", "sgmg_unet_num_params", "sgmg_unet_set_params", "sgmg_unet_get_params",
     "sgmg_unet_forward", "sgmg_unet_grad", "sgmg_unet_train_step", "sgmg_unet_input",
@@ -110,6 +111,10 @@ def _load():
     lib.sgmg_pcg_solve_batch.argtypes = [H, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp),
                                          ctypes.POINTER(vp), d, i, ctypes.POINTER(SolveInfo),
                                          ctypes.POINTER(ctypes.c_double), vp]
+    lib.sgmg_pcg_solve_batch_concurrent.argtypes = [H, i, ctypes.POINTER(ctypes.c_int),
+                                                    ctypes.POINTER(vp), ctypes.POINTER(vp), d, i, i,
+                                                    ctypes.POINTER(SolveInfo),
+                                                    ctypes.POINTER(ctypes.c_double), vp]
     lib.sgmg_batch_hierarchy.argtypes = [H, i]
     lib.sgmg_batch_hierarchy.restype = ctypes.c_void_p
     lib.sgmg_batch_block_size.argtypes = [H]
@@ -422,6 +427,25 @@ def pcg_solve_batch(batch, item_sys, f_list, u_list, rtol=1e-6, maxit=200, strea
     ms = ctypes.c_double()
     _check(_lib.sgmg_pcg_solve_batch(batch.handle, m, sysarr, fa, ua, rtol, maxit, infos,
                                      ctypes.byref(ms), _stream(stream)))
+    out = [{"status": STATUS.get(i.status, i.status), "iters": i.iters,
+            "rel_res_true": i.rel_res_true, "rel_res_recur": i.rel_res_recur} for i in infos]
+    return out, ms.value
+
+
+def pcg_solve_batch_concurrent(batch, item_sys, f_list, u_list, rtol=1e-6, maxit=200, workers=4,
+                               stream=None):
+    """The same items solved by `workers` host threads with a stream each
+    (see sgmg_pcg_solve_batch_concurrent); returns (list of dicts, total ms)."""
+    m = len(item_sys)
+    sysarr = (ctypes.c_int * m)(*item_sys)
+    fa = (ctypes.c_void_p * m)(*[_ptr(f, torch.float64, 3 * n_nodes(batch.opts[s]), "f").value
+                                 for f, s in zip(f_list, item_sys)])
+    ua = (ctypes.c_void_p * m)(*[_ptr(u, torch.float64, 3 * n_nodes(batch.opts[s]), "u").value
+                                 for u, s in zip(u_list, item_sys)])
+    infos = (SolveInfo * m)()
+    ms = ctypes.c_double()
+    _check(_lib.sgmg_pcg_solve_batch_concurrent(batch.handle, m, sysarr, fa, ua, rtol, maxit, workers,
+                                                infos, ctypes.byref(ms), _stream(stream)))
     out = [{"status": STATUS.get(i.status, i.status), "iters": i.iters,
             "rel_res_true": i.rel_res_true, "rel_res_recur": i.rel_res_recur} for i in infos]
     return out, ms.value

@@ -79,3 +79,32 @@ def test_batch_graph_replays_agree():
             assert [r["iters"] for r in res] == [r["iters"] for r in first[0]]
             for a, c in zip(xs, first[1]):
                 assert np.array_equal(a, c)
+
+
+@pytest.mark.parametrize("workers", [1, 3])
+def test_concurrent_batch_equals_single_solves(workers):
+    """Worker threads with their own streams: every item bitwise equal to a
+    lone single solve on the same hierarchy (items of one system in order)."""
+    from paper_2604_26441_amd import simpgmg
+    dims, rhos = _systems()
+    opts = [simpgmg.default_options(*d, n_levels=0, dense_max=1000, fine_prec="f32") for d in dims]
+    b = simpgmg.setup_batch(opts, [t64(r) for r in rhos])
+    rng = np.random.default_rng(11)
+    item_sys, fs = [], []
+    for s, d in enumerate(dims):
+        for k in range(1 + (s + 1) % 3):
+            item_sys.append(s)
+            fs.append(workloads.random_face_load(d, rng) if k else workloads.edge_load(d))
+    us = [t64(np.zeros_like(f)) for f in fs]
+    res, ms = simpgmg.pcg_solve_batch_concurrent(b, item_sys, [t64(f) for f in fs], us,
+                                                 rtol=1e-6, maxit=300, workers=workers)
+    assert ms > 0
+    for i, (s, f) in enumerate(zip(item_sys, fs)):
+        h = b.hierarchy(s)
+        u1 = t64(np.zeros_like(f))
+        r1 = simpgmg.pcg_solve(h, t64(f), u1, rtol=1e-6, maxit=300)
+        assert res[i]["status"] == r1["status"] == "converged"
+        assert res[i]["iters"] == r1["iters"]
+        assert np.array_equal(np64(us[i]), np64(u1))
+    with pytest.raises(simpgmg.SimpGmgError):
+        simpgmg.pcg_solve_batch_concurrent(b, item_sys, [t64(f) for f in fs], us, workers=0)
