@@ -70,47 +70,57 @@ __global__ void k_gj_copy_col(const double* __restrict__ A, int n, int k0, int n
   C[t] = c < nb ? A[(size_t)i * n + k0 + c] : 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_gj_pivot(double* __restrict__ A, int n, int k0, int nb,
-                                                  double* __restrict__ Q, int* __restrict__ flag) {
-  __shared__ double P[kNB][kNB + 1];
-  constexpr int kPer = kNB * kNB / 256;
+// Inverse of the nb x nb pivot block by in-place Gauss-Jordan (SPD: no
+// pivoting), one wave: lane r keeps row r in registers, rotated so that at
+// step p its register c holds column (p + c) mod 64 (the pivot column is
+// always register 0, every register index is a compile-time constant and
+// the step loop need not be unrolled).  At step p lane p publishes its row
+// in LDS (one wave: no barrier, only the LDS counter wait) and every lane
+// updates its row with it:
+//   r == p : a_pc <- a_pc / a_pp (c != p),  a_pp <- 1 / a_pp
+//   r != p : a_rc <- a_rc - (a_rp / a_pp) a_pc (c != p),  a_rp <- -a_rp / a_pp
+// then rotates by one.  After 64 steps the rotation is back to the identity.
+// The block is zero-padded to 64 x 64 with a unit diagonal, so padded rows
+// and columns stay decoupled.
+__global__ __launch_bounds__(64) void k_gj_pivot(double* __restrict__ A, int n, int k0, int nb,
+                                                 double* __restrict__ Q, int* __restrict__ flag) {
+  __shared__ double row[kNB];
+  const int r = threadIdx.x;
+  double v[kNB];
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int t = threadIdx.x + 256 * q, r = t / kNB, c = t % kNB;
-    P[r][c] = (r < nb && c < nb) ? A[(size_t)(k0 + r) * n + k0 + c] : 0.0;
-  }
-  __syncthreads();
-  for (int piv = 0; piv < nb; ++piv) {
-    const double pv = P[piv][piv];
-    if (!(pv > 0.0) && threadIdx.x == 0) *flag = 1;
+  for (int c = 0; c < kNB; ++c)
+    v[c] = (r < nb && c < nb) ? A[(size_t)(k0 + r) * n + k0 + c] : (r == c ? 1.0 : 0.0);
+  bool bad = false;
+  for (int p = 0; p < kNB; ++p) {
+    if (r == p) {
+#pragma unroll
+      for (int c = 0; c < kNB; ++c) row[c] = v[c];
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);              // lgkmcnt(0): the row is in LDS
+    __builtin_amdgcn_wave_barrier();
+    const double pv = row[0];
+    bad |= !(pv > 0.0);
     const double inv = 1.0 / pv;
-    double nv[kPer];
+    const bool me = r == p;
+    const double g = v[0] * inv;                      // a_rp / a_pp
+    double w[kNB];
+    w[0] = me ? inv : -g;
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int t = threadIdx.x + 256 * q, r = t / kNB, c = t % kNB;
-      double v = P[r][c];
-      if (r < nb && c < nb) {
-        if (r == piv && c == piv) v = inv;
-        else if (r == piv) v = inv * P[piv][c];
-        else if (c == piv) v = -P[r][piv] * inv;
-        else v = P[r][c] - P[r][piv] * inv * P[piv][c];
-      }
-      nv[q] = v;
+    for (int c = 1; c < kNB; ++c) {
+      const double rc = row[c];
+      w[c] = me ? rc * inv : __builtin_fma(-g, rc, v[c]);
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();                  // row is rewritten next step
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int t = threadIdx.x + 256 * q;
-      P[t / kNB][t % kNB] = nv[q];
-    }
-    __syncthreads();
+    for (int c = 0; c < kNB; ++c) v[c] = w[(c + 1) % kNB];   // rotate by one column
   }
+  if (bad && r == 0) *flag = 1;
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int t = threadIdx.x + 256 * q, r = t / kNB, c = t % kNB;
-    const double v = (r < nb && c < nb) ? P[r][c] : 0.0;
-    Q[t] = v;
-    if (r < nb && c < nb) A[(size_t)(k0 + r) * n + k0 + c] = v;
+  for (int c = 0; c < kNB; ++c) {
+    const bool in = r < nb && c < nb;
+    const double x = in ? v[c] : 0.0;
+    Q[r * kNB + c] = x;
+    if (in) A[(size_t)(k0 + r) * n + k0 + c] = x;
   }
 }
 
@@ -188,7 +198,7 @@ int dense_spd_inverse(double* A, int n, double* scratch, int* d_flag, hipStream_
   for (int k0 = 0; k0 < n; k0 += kNB) {
     const int nb = (n - k0) < kNB ? (n - k0) : kNB;
     k_gj_copy_col<<<div_up((long)n * kNB, 256), 256, 0, s>>>(A, n, k0, nb, C);
-    k_gj_pivot<<<1, 256, 0, s>>>(A, n, k0, nb, Q, d_flag);
+    k_gj_pivot<<<1, 64, 0, s>>>(A, n, k0, nb, Q, d_flag);
     k_gj_rowpanel<<<div_up(n, 64), 64, 0, s>>>(A, n, k0, nb, Q);
     dim3 grid(div_up(n, 64), div_up(n, 64));
     k_gj_update<<<grid, 256, 0, s>>>(A, n, k0, nb, C, Q);
