@@ -143,46 +143,60 @@ __global__ __launch_bounds__(64) void k_gj_rowpanel(double* __restrict__ A, int 
   }
 }
 
-// Rank-nb update of all rows outside the panel, 64x64 output tile per block.
+// Rank-nb update of all rows outside the panel: A_IJ -= C_I R_J with R_J =
+// A_KJ (new) for columns outside the panel and R_J = -Q for the panel's own
+// columns, which receive -C_I Q (stored, not subtracted).  A 128 x 128 output
+// tile per 256-thread block, 8 x 8 outputs per thread (rows tr + 16q,
+// columns tc + 16w), the K dimension streamed through LDS in chunks of 16:
+// 16 LDS reads per 64 FMAs.
+constexpr int kUpdTile = 128, kUpdK = 16;
+
 __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, int n, int k0, int nb,
                                                    const double* __restrict__ C,
                                                    const double* __restrict__ Q) {
-  __shared__ double Cs[64][kNB + 1];
-  __shared__ double Rs[kNB][64 + 1];
-  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-  for (int t = threadIdx.x; t < 64 * kNB; t += 256) {
-    const int r = t / kNB, c = t % kNB;
-    const int i = i0 + r;
-    Cs[r][c] = (i < n) ? C[(size_t)i * kNB + c] : 0.0;
-  }
-  for (int t = threadIdx.x; t < kNB * 64; t += 256) {
-    const int r = t / 64, c = t % 64;
-    const int j = j0 + c;
-    double v = 0.0;
-    if (r < nb && j < n) {
-      if (j >= k0 && j < k0 + nb) v = -Q[r * kNB + (j - k0)];   // A_IK <- -C Q
-      else v = A[(size_t)(k0 + r) * n + j];                     // A_KJ (new)
-    }
-    Rs[r][c] = v;
-  }
-  __syncthreads();
+  __shared__ double Cs[kUpdTile][kUpdK + 1];
+  __shared__ double Rs[kUpdK][kUpdTile + 1];
+  const int i0 = blockIdx.y * kUpdTile, j0 = blockIdx.x * kUpdTile;
   const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
-  double acc[4][4] = {};
-  for (int t = 0; t < nb; ++t) {
-    double a[4], b[4];
+  double acc[8][8] = {};
+  for (int t0 = 0; t0 < nb; t0 += kUpdK) {
+    for (int e = threadIdx.x; e < kUpdTile * kUpdK; e += 256) {
+      const int r = e / kUpdK, c = e % kUpdK;
+      const int i = i0 + r, t = t0 + c;
+      Cs[r][c] = (i < n && t < nb) ? C[(size_t)i * kNB + t] : 0.0;
+    }
+    for (int e = threadIdx.x; e < kUpdK * kUpdTile; e += 256) {
+      const int r = e / kUpdTile, c = e % kUpdTile;
+      const int t = t0 + r, j = j0 + c;
+      double v = 0.0;
+      if (t < nb && j < n) {
+        if (j >= k0 && j < k0 + nb) v = -Q[t * kNB + (j - k0)];   // A_IK <- -C Q
+        else v = A[(size_t)(k0 + t) * n + j];                     // A_KJ (new)
+      }
+      Rs[r][c] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int t = 0; t < kUpdK; ++t) {
+      double a[8], b[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) { a[q] = Cs[tr + 16 * q][t]; b[q] = Rs[t][tc + 16 * q]; }
+      for (int q = 0; q < 8; ++q) {
+        a[q] = Cs[tr + 16 * q][t];
+        b[q] = Rs[t][tc + 16 * q];
+      }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < 8; ++q)
 #pragma unroll
-      for (int w = 0; w < 4; ++w) acc[q][w] += a[q] * b[w];
+        for (int w = 0; w < 8; ++w) acc[q][w] = __builtin_fma(a[q], b[w], acc[q][w]);
+    }
+    __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < 8; ++q) {
     const int i = i0 + tr + 16 * q;
     if (i >= n || (i >= k0 && i < k0 + nb)) continue;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < 8; ++w) {
       const int j = j0 + tc + 16 * w;
       if (j >= n) continue;
       double* dst = A + (size_t)i * n + j;
@@ -200,7 +214,7 @@ int dense_spd_inverse(double* A, int n, double* scratch, int* d_flag, hipStream_
     k_gj_copy_col<<<div_up((long)n * kNB, 256), 256, 0, s>>>(A, n, k0, nb, C);
     k_gj_pivot<<<1, 64, 0, s>>>(A, n, k0, nb, Q, d_flag);
     k_gj_rowpanel<<<div_up(n, 64), 64, 0, s>>>(A, n, k0, nb, Q);
-    dim3 grid(div_up(n, 64), div_up(n, 64));
+    dim3 grid(div_up(n, kUpdTile), div_up(n, kUpdTile));
     k_gj_update<<<grid, 256, 0, s>>>(A, n, k0, nb, C, Q);
   }
   return 0;

@@ -18,10 +18,13 @@ def _setup(dims, L, rho, fine_prec, fine_smoother=0, lambdas=None, level1_prec="
 
 @pytest.mark.parametrize("dims,L,smoother,shape", [((16, 8, 8), 3, 0, None), ((24, 12, 12), 4, 0, None),
                                                    ((16, 8, 8), 3, 1, None), ((9, 7, 5), 3, 0, None),
-                                                   ((24, 12, 12), 4, 0, (4, 3)), ((16, 8, 8), 3, 1, (8, 4))])
+                                                   ((24, 12, 12), 4, 0, (4, 3)), ((16, 8, 8), 3, 1, (8, 4)),
+                                                   ((32, 16, 16), 3, 0, None)])
 def test_vcycle_f64_matches_oracle(dims, L, smoother, shape):
     """shape None: FP64 vector-ALU fine operator; (rows, planes): the FP64
-    MFMA fine operator (residual and smoothing epilogues)."""
+    MFMA fine operator (residual and smoothing epilogues).  (32, 16, 16) on 3
+    levels has 600 free coarsest DOFs: ten 64-column Gauss-Jordan panels,
+    five 128-row update tiles with a ragged last one."""
     from paper_2604_26441_amd import simpgmg
     g = np.random.default_rng(3)
     rho = g.uniform(0.1, 1.0, np.prod(dims))
