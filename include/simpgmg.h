@@ -114,6 +114,12 @@ typedef struct {
                                 by two coarser cycles, the second starting from
                                 the first one's result; the coarsest is solved
                                 once                                              */
+  int stencil_form;          /* kernel of the Galerkin-level products (same
+                                operator, sums in another order): 0 by level size
+                                (default: the LDS-staged 27-offset form on levels
+                                of >= 40000 nodes, the plane-split form below),
+                                1 the LDS-staged form on every level, 2 the
+                                plane-split form on every level                   */
 } sgmg_options;
 
 typedef struct {

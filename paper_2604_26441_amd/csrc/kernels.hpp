@@ -46,9 +46,10 @@ void launch_galerkin_stencil(const Grid& fine, const Grid& coarse, const double*
                              const uint8_t* cfix, double* Sc, hipStream_t s);
 void launch_stencil_diag(const Grid& g, const double* S, double* d, hipStream_t s);
 void launch_stencil_to_f32(const double* S, float* S32, size_t n, hipStream_t s);
+// form: 0 by node count, 1 LDS-staged 27-offset form, 2 plane-split form.
 template <typename T>
 void launch_stencil_apply(const Grid& g, const T* S, const T* u, const uint8_t* fixn,
-                          const Epi<T>& ep, hipStream_t s);
+                          const Epi<T>& ep, int form, hipStream_t s);
 size_t stencil_apply_blocks(const Grid& g);
 // Restriction b_c = M_c P^T r_f; optionally x_c = c0 * Dinv_c * b_c (first
 // smoothing step from zero) and d_c = x_c.
@@ -83,15 +84,16 @@ void launch_copy(const double* in, double* out, int n, hipStream_t s);
 // PCG pieces; sc = device scalar block (see runtime.hip for slots)
 void launch_pcg_init(const double* f, const double* Ax0, int have_x0, double* r, int n,
                      RedWs ws, double* sc_ff_rr, hipStream_t s);
-// x += alpha p, r -= alpha q (alpha = sc[slot_rz] / sc[slot_pq]; a failed
-// step leaves both), r.r; with b not NULL also the entry of the V-cycle that
-// follows (b = (T) r, x = c0 Dinv b, d = x when d is not NULL).  sc_rr NULL:
-// the r.r partials stay in ws for launch_pcg_update_p_red.
+// x = x_in + alpha p (x_in may be x), r -= alpha q (alpha = sc[slot_rz] /
+// sc[slot_pq]; a failed step leaves r and copies x_in to x), r.r; with b not
+// NULL also the entry of the V-cycle that follows (b = (T) r, x = c0 Dinv b,
+// d = x when d is not NULL).  sc_rr NULL: the r.r partials stay in ws for
+// launch_pcg_update_p_red.
 template <typename T>
-void launch_pcg_update_xr_entry(double* x, double* r, double* r_old, const double* p,
-                                const double* q, const double* sc, int slot_rz, int slot_pq, int n,
-                                RedWs ws, double* sc_rr, T* b, const T* dinv, double c0, T* xe,
-                                T* de, hipStream_t s);
+void launch_pcg_update_xr_entry(const double* x_in, double* x, double* r, double* r_old,
+                                const double* p, const double* q, const double* sc, int slot_rz,
+                                int slot_pq, int n, RedWs ws, double* sc_rr, T* b, const T* dinv,
+                                double c0, T* xe, T* de, hipStream_t s);
 // (sc_out2 NULL: partials only, for launch_pcg_update_p_red)
 void launch_pcg_dot_rz(const double* r, const double* z, const double* r_old, int n, RedWs ws,
                        double* sc_out2, hipStream_t s);
@@ -99,10 +101,13 @@ void launch_pcg_dot_rz(const double* r, const double* z, const double* r_old, in
 int pcg_vec_partials(int n);
 // p = z + beta p with the r.z partials added in every block (no finalize
 // launch); block 0 stores r.z [and r_old.z] at sc[slot_num] [slot_num + 1]
-// and the sum of the r.r partials at sc[slot_rr].
+// and the sum of the r.r partials at sc[slot_rr]; with host not NULL (a
+// device-mapped, coherent host array in sc's layout) it also writes those
+// and sc[slot_pq] there.
 void launch_pcg_update_p_red(double* p, const double* z, const double* rz_part,
                              const double* rr_part, double* sc, int slot_num, int flex,
-                             int slot_den, int slot_rr, int n, hipStream_t s);
+                             int slot_den, int slot_rr, int slot_pq, double* host, int n,
+                             hipStream_t s);
 // *out = max over (free) entries of a non-negative vector (fixn may be NULL)
 void launch_max_nonneg(const double* a, const uint8_t* fixn, int n, double* out, hipStream_t s);
 void launch_diag_finalize(double* d, double* dinv64, float* dinv32, const uint8_t* fixn, int n,

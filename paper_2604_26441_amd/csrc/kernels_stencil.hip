@@ -211,43 +211,38 @@ void launch_stencil_to_f32(const double* S, float* S32, size_t n, hipStream_t s)
 // (S_{26-o}[n+o])^T.  The neighbour's block is that neighbour's own upper
 // block, so the second read is served from cache: about half the HBM bytes of
 // the full stencil, and the applied operator is exactly symmetric.
-// One thread per (node, output component[, stencil plane]): a block is 64
-// consecutive nodes x 3 components (x 3 planes when NZ = 3; wave = component
-// + 3 plane), so every stencil load of a wave is 64 consecutive values of one
-// slot.  With NZ = 3 the three plane partials are added in LDS in a fixed
-// order: nine times the threads of a node-per-thread form, for the small
-// Galerkin levels (level 2 of an 80^3 mesh has 9,261 nodes) that need the
-// waves to cover memory latency; large levels are bandwidth-bound and use
-// NZ = 1.  The block index is remapped per XCD so each L2 sees a contiguous
-// node range.
-template <typename T, int NZ>
-__global__ __launch_bounds__(192 * NZ) void k_stencil_apply_c(Grid g, const T* __restrict__ S,
-                                                             const T* __restrict__ u,
-                                                             const uint8_t* __restrict__ fixn,
-                                                             Epi<T> ep) {
-  __shared__ double part[NZ][3][64];
+// Two kernel forms, both with a block of 64 consecutive nodes (every stencil
+// load of a wave is 64 consecutive values of one slot) and the block index
+// remapped per XCD so each L2 sees a contiguous node range.
+//
+// Plane-split form, for small levels (level 2 of an 80^3 mesh has 9,261
+// nodes) that need many waves to cover memory latency: one thread per (node,
+// output component, stencil plane oz), wave = component + 3 plane; the nine
+// offsets of a plane are read unconditionally (offsets outside the grid read
+// the node itself, a valid address, and add zero) and the three plane
+// partials are added in LDS in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(576) void k_stencil_apply_c(Grid g, const T* __restrict__ S,
+                                                         const T* __restrict__ u,
+                                                         const uint8_t* __restrict__ fixn,
+                                                         Epi<T> ep) {
+  __shared__ double part[3][3][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int d = w % 3, pz = NZ == 1 ? 0 : w / 3;
+  const int d = w % 3, pz = w / 3;
   const int node0 = xcd_block(blockIdx.x, gridDim.x) * 64 + lane;
   const bool in = node0 < g.Nn;
-  // Lanes past the grid work on the last node and store nothing.  The
-  // plane-split form (9 offsets per wave) is branch-free: offsets outside
-  // the grid read the node itself (a valid address) and add zero, so all of
-  // a wave's loads can be in flight at once.  The 27-offset form keeps the
-  // branch: hoisting all of its loads would need more than 128 registers
-  // (one wave per SIMD, or spills under a cap), which is slower.
+  // lanes past the grid work on the last node and store nothing
   const int node = in ? node0 : g.Nn - 1;
   {
     const int i = node % g.Nx, t = node / g.Nx, j = t % g.Ny, k = t / g.Ny;
     const size_t Nn = g.Nn;
     T acc = (T)0;
 #pragma unroll
-    for (int q = 0; q < 27 / NZ; ++q) {
-      const int o = NZ == 1 ? q : 9 * pz + q;
+    for (int q = 0; q < 9; ++q) {
+      const int o = 9 * pz + q;
       const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
       const bool ok = (unsigned)(i + ox) < (unsigned)g.Nx && (unsigned)(j + oy) < (unsigned)g.Ny &&
                       (unsigned)(k + oz) < (unsigned)g.Nz;
-      if (NZ == 1 && !ok) continue;
       const int nb = ok ? node + ox + g.Nx * (oy + g.Ny * oz) : node;
       const size_t b3 = 3 * (size_t)nb;
       const T u0 = u[b3], u1 = u[b3 + 1], u2 = u[b3 + 2];
@@ -263,13 +258,101 @@ __global__ __launch_bounds__(192 * NZ) void k_stencil_apply_c(Grid g, const T* _
     }
     part[pz][d][lane] = (double)acc;
   }
-  if (NZ > 1) __syncthreads();
+  __syncthreads();
   double dot = 0.0;
-  if (in && pz == NZ / 2) {
-    const double y = NZ == 1 ? part[0][d][lane]
-                             : (part[0][d][lane] + part[NZ / 2][d][lane]) + part[NZ - 1][d][lane];
+  if (in && pz == 1) {
+    const double y = (part[0][d][lane] + part[1][d][lane]) + part[2][d][lane];
     const size_t dof = 3 * (size_t)node + d;
     dot = epilogue1(ep, dof, (fixn[node] >> d) & 1u, u[dof], y);
+  }
+  if (ep.want_dot) {
+    const double v[1] = {dot};
+    grid_sum<1>(v, ep.ws);
+  }
+}
+
+// LDS-staged form, for large levels (from kStencilSplitNodes nodes on): one
+// thread per (node, output component), all 27 offsets, neighbour values from
+// LDS.  Each block stages the u entries its 64 nodes touch once:
+// for each of the 9 (oy, oz) rows, the 66 nodes node0 - 1 + oy Nx + oz Nx Ny
+// ... node0 + 64 + oy Nx + oz Nx Ny (all three components, contiguous in
+// memory, so the staging loads are coalesced; entries outside the vector
+// are zero).  The three waves (one per output component) then read only
+// their stencil entries from memory: 3 coalesced loads per offset, no branch
+// (offsets outside the grid read valid stencil slots and are masked), so
+// the loads of many offsets are in flight together, while the
+// stride-3 neighbour reads that would otherwise triple the vector-memory
+// instructions go to LDS.
+template <typename T>
+__global__ __launch_bounds__(192) void k_stencil_apply_s(
+    Grid g, const T* __restrict__ S, const T* __restrict__ u, const uint8_t* __restrict__ fixn,
+    Epi<T> ep) {
+  constexpr int kRow = 66 * 3;
+  __shared__ T us[9][kRow];
+  const int lane = threadIdx.x & 63, d = threadIdx.x >> 6;
+  const long node0 = (long)xcd_block(blockIdx.x, gridDim.x) * 64;
+  {
+    // thread t stages entry t of each row (and entry 192 + t for t < 6);
+    // the loads read clamped indices unconditionally so that all of them
+    // are in flight together, and the value is zeroed outside the vector
+    static_assert(kRow > 192 && kRow - 192 <= 64, "row staging covers 192 + a wave");
+    const long n3 = 3L * g.Nn, plane = (long)g.Nx * g.Ny;
+    const int t = threadIdx.x;
+    long base[9];
+    T v[9];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      base[r] = 3 * (node0 - 1 + (r % 3 - 1) * (long)g.Nx + (r / 3 - 1) * plane);
+      const long i0 = base[r] + t;
+      v[r] = u[i0 < 0 ? 0 : i0 >= n3 ? n3 - 1 : i0];
+    }
+    if (t < kRow - 192) {
+      T w[9];
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
+        const long i1 = base[r] + 192 + t;
+        w[r] = u[i1 < 0 ? 0 : i1 >= n3 ? n3 - 1 : i1];
+      }
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
+        const long i1 = base[r] + 192 + t;
+        us[r][192 + t] = (i1 >= 0 && i1 < n3) ? w[r] : (T)0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      const long i0 = base[r] + t;
+      us[r][t] = (i0 >= 0 && i0 < n3) ? v[r] : (T)0;
+    }
+  }
+  __syncthreads();
+  const bool in = node0 + lane < g.Nn;
+  const int node = in ? (int)node0 + lane : g.Nn - 1;
+  const int i = node % g.Nx, tt = node / g.Nx, j = tt % g.Ny, k = tt / g.Ny;
+  const size_t Nn = g.Nn;
+  T acc = (T)0;
+#pragma unroll
+  for (int o = 0; o < 27; ++o) {
+    const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+    const bool ok = (unsigned)(i + ox) < (unsigned)g.Nx && (unsigned)(j + oy) < (unsigned)g.Ny &&
+                    (unsigned)(k + oz) < (unsigned)g.Nz;
+    const T* ur = &us[(oy + 1) + 3 * (oz + 1)][3 * (lane + 1 + ox)];
+    const T u0 = ur[0], u1 = ur[1], u2 = ur[2];
+    T v;
+    if (o >= 13) {
+      const T* Sb = S + ((size_t)o * 9 + 3 * d) * Nn + node;
+      v = Sb[0] * u0 + Sb[Nn] * u1 + Sb[2 * Nn] * u2;
+    } else {
+      const int nb = ok ? node + ox + g.Nx * (oy + g.Ny * oz) : node;
+      const T* Sb = S + ((size_t)(26 - o) * 9 + d) * Nn + nb;
+      v = Sb[0] * u0 + Sb[3 * Nn] * u1 + Sb[6 * Nn] * u2;
+    }
+    acc += ok ? v : (T)0;
+  }
+  double dot = 0.0;
+  if (in) {
+    const size_t dof = 3 * (size_t)node + d;
+    dot = epilogue1(ep, dof, (fixn[node] >> d) & 1u, us[4][3 * (lane + 1) + d], (double)acc);
   }
   if (ep.want_dot) {
     const double v[1] = {dot};
@@ -284,18 +367,19 @@ size_t stencil_apply_blocks(const Grid& g) { return div_up(g.Nn, 64); }
 
 template <typename T>
 void launch_stencil_apply(const Grid& g, const T* S, const T* u, const uint8_t* fixn,
-                          const Epi<T>& ep, hipStream_t s) {
+                          const Epi<T>& ep, int form, hipStream_t s) {
   const int nb = (int)stencil_apply_blocks(g);
-  if (g.Nn >= kStencilSplitNodes)
-    k_stencil_apply_c<T, 1><<<nb, 192, 0, s>>>(g, S, u, fixn, ep);
+  const bool staged = form == 1 || (form == 0 && g.Nn >= kStencilSplitNodes);
+  if (staged)
+    k_stencil_apply_s<T><<<nb, 192, 0, s>>>(g, S, u, fixn, ep);
   else
-    k_stencil_apply_c<T, 3><<<nb, 576, 0, s>>>(g, S, u, fixn, ep);
+    k_stencil_apply_c<T><<<nb, 576, 0, s>>>(g, S, u, fixn, ep);
   if (ep.want_dot) launch_finalize(ep.ws, nb, 1, ep.dot_out, s);
 }
 template void launch_stencil_apply<double>(const Grid&, const double*, const double*,
-                                           const uint8_t*, const Epi<double>&, hipStream_t);
+                                           const uint8_t*, const Epi<double>&, int, hipStream_t);
 template void launch_stencil_apply<float>(const Grid&, const float*, const float*, const uint8_t*,
-                                          const Epi<float>&, hipStream_t);
+                                          const Epi<float>&, int, hipStream_t);
 
 // Restriction (R = P^T, Eq. vector_prolongation): coarse node I gathers the
 // <= 27 fine nodes that interpolate from it.  Optional fused first smoothing

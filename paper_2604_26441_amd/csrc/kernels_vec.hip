@@ -184,7 +184,7 @@ struct VEntry {
 };
 
 template <typename T>
-__global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(double* __restrict__ x,
+__global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(const double* x_in, double* x,
                                                              double* __restrict__ r,
                                                              double* __restrict__ r_old,
                                                              const double* __restrict__ p,
@@ -194,14 +194,16 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(double* __restrict_
                                                              RedWs ws, VEntry<T> e) {
   const double pq = sc[slot_pq];
   const double alpha = sc[slot_rz] / pq;
-  // a failed step (p.q <= 0 or non-finite) leaves x and r untouched
+  // a failed step (p.q <= 0 or non-finite) leaves r untouched and x equal
+  // to x_in (x_in may be x itself)
   const bool ok = pq > 0.0 && isfinite(alpha);
   double rr = 0.0;
   for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n; i += gridDim.x * kVecBlock) {
     const double ro = r[i];
     double rv = ro;
+    if (!ok && x_in != x) x[i] = x_in[i];
     if (ok) {
-      x[i] += alpha * p[i];
+      x[i] = x_in[i] + alpha * p[i];
       if (r_old) r_old[i] = ro;
       rv = ro - alpha * q[i];
       r[i] = rv;
@@ -220,28 +222,28 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(double* __restrict_
 }
 
 template <typename T>
-void launch_pcg_update_xr_entry(double* x, double* r, double* r_old, const double* p,
-                                const double* q, const double* sc, int slot_rz, int slot_pq, int n,
-                                RedWs ws, double* sc_rr, T* b, const T* dinv, double c0, T* xe,
-                                T* de, hipStream_t s) {
+void launch_pcg_update_xr_entry(const double* x_in, double* x, double* r, double* r_old,
+                                const double* p, const double* q, const double* sc, int slot_rz,
+                                int slot_pq, int n, RedWs ws, double* sc_rr, T* b, const T* dinv,
+                                double c0, T* xe, T* de, hipStream_t s) {
   VEntry<T> e;
   e.b = b;
   e.dinv = dinv;
   e.c0 = c0;
   e.x = xe;
   e.d = de;
-  k_pcg_update_xr<T><<<vec_grid(n), kVecBlock, 0, s>>>(x, r, r_old, p, q, sc, slot_rz, slot_pq,
-                                                       n, ws, e);
+  k_pcg_update_xr<T><<<vec_grid(n), kVecBlock, 0, s>>>(x_in, x, r, r_old, p, q, sc, slot_rz,
+                                                       slot_pq, n, ws, e);
   if (sc_rr) launch_finalize(ws, vec_grid(n), 1, sc_rr, s);
 }
-template void launch_pcg_update_xr_entry<float>(double*, double*, double*, const double*,
-                                                const double*, const double*, int, int, int,
-                                                RedWs, double*, float*, const float*, double,
-                                                float*, float*, hipStream_t);
-template void launch_pcg_update_xr_entry<double>(double*, double*, double*, const double*,
-                                                 const double*, const double*, int, int, int,
-                                                 RedWs, double*, double*, const double*, double,
-                                                 double*, double*, hipStream_t);
+template void launch_pcg_update_xr_entry<float>(const double*, double*, double*, double*,
+                                                const double*, const double*, const double*, int,
+                                                int, int, RedWs, double*, float*, const float*,
+                                                double, float*, float*, hipStream_t);
+template void launch_pcg_update_xr_entry<double>(const double*, double*, double*, double*,
+                                                 const double*, const double*, const double*, int,
+                                                 int, int, RedWs, double*, double*, const double*,
+                                                 double, double*, double*, hipStream_t);
 
 // out[0] = r.z ; out[1] = r_old.z (flexible beta numerator r.z - r_old.z)
 __global__ __launch_bounds__(kVecBlock) void k_pcg_dot_rz(const double* __restrict__ r,
@@ -274,7 +276,7 @@ int pcg_vec_partials(int n) { return (int)vec_grid(n); }
 __global__ __launch_bounds__(kVecBlock) void k_pcg_update_p_red(
     double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ rz_part,
     const double* __restrict__ rr_part, int nb, double* __restrict__ sc, int slot_num, int flex,
-    int slot_den, int slot_rr, int n) {
+    int slot_den, int slot_rr, int slot_pq, double* host, int n) {
   __shared__ double lds[3][16];
   __shared__ double tot[3];
   double a = 0.0, b = 0.0, c = 0.0;
@@ -294,6 +296,14 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_p_red(
       sc[slot_num] = a;
       if (flex) sc[slot_num + 1] = b;
       sc[slot_rr] = c;
+      if (host) {
+        // the iteration's scalars for the host, in sc's slot layout
+        host[slot_num] = a;
+        if (flex) host[slot_num + 1] = b;
+        host[slot_rr] = c;
+        host[slot_pq] = sc[slot_pq];
+        __threadfence_system();
+      }
     }
   }
   __syncthreads();
@@ -304,9 +314,11 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_p_red(
 
 void launch_pcg_update_p_red(double* p, const double* z, const double* rz_part,
                              const double* rr_part, double* sc, int slot_num, int flex,
-                             int slot_den, int slot_rr, int n, hipStream_t s) {
+                             int slot_den, int slot_rr, int slot_pq, double* host, int n,
+                             hipStream_t s) {
   k_pcg_update_p_red<<<vec_grid(n), kVecBlock, 0, s>>>(p, z, rz_part, rr_part, (int)vec_grid(n),
-                                                       sc, slot_num, flex, slot_den, slot_rr, n);
+                                                       sc, slot_num, flex, slot_den, slot_rr,
+                                                       slot_pq, host, n);
 }
 
 // Largest value of a (non-negative entries, or masked by fixn when given).

@@ -87,6 +87,9 @@ struct sgmg_hierarchy {
   RedWs ws{};
   double* sc = nullptr;
   double* h_sc = nullptr;    // pinned mirror of sc
+  double* h_it = nullptr;    // coherent, device-mapped: the scalars of the last PCG
+                             // iteration of each slot parity (2 x SC_COUNT)
+  double* d_it = nullptr;    // device address of h_it
   int* d_flag = nullptr;
   double* r = nullptr;
   double* z = nullptr;
@@ -95,6 +98,9 @@ struct sgmg_hierarchy {
   double* r_old = nullptr;
   double* tmp = nullptr;
   double* xs = nullptr;      // solver-owned copy of the iterate (graphs bind it)
+  double* xs2 = nullptr;     // second iterate buffer: a PCG iteration of slot parity
+                             // p reads x from one buffer and writes the other, so
+                             // the previous iterate survives a queued successor
   // flexible GMRES: basis V (kry_cols + 1 columns), Z (kry_cols columns) and
   // small device arrays for the Hessenberg column and y; sized on first use
   double* kry = nullptr;
@@ -244,7 +250,7 @@ int apply_level<double>(const sgmg_hierarchy* h, int l, sgmg_prec prec, const do
   else if (l == 0)
     launch_apply_fine_node<double>(L.g, h->E64, h->ke64, x, L.fixn, ep, s);
   else
-    launch_stencil_apply<double>(L.g, L.S64, x, L.fixn, ep, s);
+    launch_stencil_apply<double>(L.g, L.S64, x, L.fixn, ep, h->o.stencil_form, s);
   return check_launch();
 }
 
@@ -276,7 +282,7 @@ int apply_level<float>(const sgmg_hierarchy* h, int l, sgmg_prec prec, const flo
       set_error("level is not stored in FP32");
       return SGMG_EINVAL;
     }
-    launch_stencil_apply<float>(L.g, L.S32, x, L.fixn, ep, s);
+    launch_stencil_apply<float>(L.g, L.S32, x, L.fixn, ep, h->o.stencil_form, s);
   }
   return check_launch();
 }
@@ -558,6 +564,7 @@ int validate(const sgmg_options* o) {
   if (!(o->cheb_alpha > 0.0 && o->cheb_alpha < 1.0)) { set_error("cheb_alpha must be in (0,1)"); return SGMG_EINVAL; }
   if (!(o->lambda_safety > 0.0)) { set_error("lambda_safety must be > 0"); return SGMG_EINVAL; }
   if (o->cycle_gamma != 1 && o->cycle_gamma != 2) { set_error("cycle_gamma must be 1 or 2"); return SGMG_EINVAL; }
+  if (o->stencil_form < 0 || o->stencil_form > 2) { set_error("stencil_form must be 0, 1 or 2"); return SGMG_EINVAL; }
   return 0;
 }
 
@@ -594,6 +601,7 @@ void sgmg_default_options(sgmg_options* o, int nx, int ny, int nz) {
   o->lambda_override = nullptr;
   o->use_graphs = 1;
   o->cycle_gamma = 1;
+  o->stencil_form = 0;
 }
 
 void sgmg_destroy(sgmg_hierarchy* h) {
@@ -606,6 +614,7 @@ void sgmg_destroy(sgmg_hierarchy* h) {
   if (h->kry) hipFree(h->kry);
   if (h->kry_small) hipFree(h->kry_small);
   if (h->h_sc) hipHostFree(h->h_sc);
+  if (h->h_it) hipHostFree(h->h_it);
   delete h;
 }
 
@@ -741,11 +750,18 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
     return fail(rc);
   hipMemsetAsync(h->ws.counter, 0, sizeof(unsigned), s);
   hipMemsetAsync(h->sc, 0, SC_COUNT * sizeof(double), s);
-  if (hipHostMalloc((void**)&h->h_sc, SC_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&h->h_it, 2 * SC_COUNT * sizeof(double),
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&h->d_it, h->h_it, 0) != hipSuccess) {
     set_error("pinned allocation failed");
     return fail(SGMG_ENOMEM);
   }
-  for (double** v : {&h->r, &h->z, &h->p, &h->q, &h->r_old, &h->tmp, &h->xs})
+  if (hipHostMalloc((void**)&h->h_sc, SC_COUNT * sizeof(double), hipHostMallocDefault) !=
+      hipSuccess) {
+    set_error("pinned allocation failed");
+    return fail(SGMG_ENOMEM);
+  }
+  for (double** v : {&h->r, &h->z, &h->p, &h->q, &h->r_old, &h->tmp, &h->xs, &h->xs2})
     if ((rc = dalloc_t(h, v, maxn))) return fail(rc);
   // coarsest free index list
   {
@@ -822,14 +838,24 @@ int sgmg_vcycle(const sgmg_hierarchy* h, const double* r, double* z, void* strea
   return vcycle_full(h, r, z, as_stream(stream));
 }
 
+// Iterate buffers of a PCG iteration with rz slot `slot`: it reads x from
+// *xin and writes *xout (parity 0 writes xs, parity 1 writes xs2).
+static void pcg_iterates(const sgmg_hierarchy* h, int slot, double** xin, double** xout) {
+  const bool even = slot == SC_RZ0;
+  *xout = even ? h->xs : h->xs2;
+  *xin = even ? h->xs2 : h->xs;
+}
+
 // One PCG iteration on device buffers only (so it can be captured):
-// q = K p (p.q), x += alpha p, r -= alpha q (r.r), z = M r, r.z (and r_old.z),
-// p = z + beta p.  Scalars stay on the device in slot pairs that alternate
-// with the iteration parity.
+// q = K p (p.q), x = x_prev + alpha p, r -= alpha q (r.r), z = M r, r.z (and
+// r_old.z), p = z + beta p.  Scalars stay on the device in slot pairs and
+// the iterate in buffers that alternate with the iteration parity.
 static int pcg_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
   const Level& L0 = h->lev[0];
   const int n = L0.g.n;
   double* sc = h->sc;
+  double *xin, *xout;
+  pcg_iterates(h, slot, &xin, &xout);
   const bool flex = h->o.flexible_beta != 0;
   const int nslot = slot == SC_RZ0 ? SC_RZ1 : SC_RZ0;
   // The r.r partials of the update and the r.z partials after the
@@ -844,28 +870,29 @@ static int pcg_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
     const Smoother sm = smoother_of(h, 0);
     const double c0 = first_step_coef(sm);
     if (L0.f32)
-      launch_pcg_update_xr_entry<float>(h->xs, h->r, flex ? h->r_old : nullptr, h->p, h->q, sc,
-                                        slot, SC_PQ, n, ws_rr, nullptr, (float*)L0.b,
+      launch_pcg_update_xr_entry<float>(xin, xout, h->r, flex ? h->r_old : nullptr, h->p, h->q,
+                                        sc, slot, SC_PQ, n, ws_rr, nullptr, (float*)L0.b,
                                         L0.dinv32, c0, (float*)L0.x[0],
                                         sm.cheb ? (float*)L0.dv : nullptr, s);
     else
-      launch_pcg_update_xr_entry<double>(h->xs, h->r, flex ? h->r_old : nullptr, h->p, h->q, sc,
-                                         slot, SC_PQ, n, ws_rr, nullptr, (double*)L0.b,
+      launch_pcg_update_xr_entry<double>(xin, xout, h->r, flex ? h->r_old : nullptr, h->p, h->q,
+                                         sc, slot, SC_PQ, n, ws_rr, nullptr, (double*)L0.b,
                                          L0.dinv64, c0, (double*)L0.x[0],
                                          sm.cheb ? (double*)L0.dv : nullptr, s);
     TRY(check_launch());
     int cur = 0;
     TRY(vcycle_level(h, 0, &cur, h->z, true, s));
   } else {
-    launch_pcg_update_xr_entry<double>(h->xs, h->r, flex ? h->r_old : nullptr, h->p, h->q, sc,
-                                       slot, SC_PQ, n, ws_rr, nullptr, nullptr, nullptr, 0.0,
+    launch_pcg_update_xr_entry<double>(xin, xout, h->r, flex ? h->r_old : nullptr, h->p, h->q,
+                                       sc, slot, SC_PQ, n, ws_rr, nullptr, nullptr, nullptr, 0.0,
                                        nullptr, nullptr, s);
     if (precond == 1) launch_apply_dinv(L0.dinv64, h->r, h->z, n, s);
     else launch_copy(h->r, h->z, n, s);
   }
   launch_pcg_dot_rz(h->r, h->z, flex ? h->r_old : nullptr, n, h->ws, nullptr, s);
   launch_pcg_update_p_red(h->p, h->z, h->ws.partials, ws_rr.partials, sc, nslot, flex ? 1 : 0,
-                          slot, SC_RR, n, s);
+                          slot, SC_RR, SC_PQ, h->d_it + SC_COUNT * (slot == SC_RZ0 ? 0 : 1), n,
+                          s);
   return check_launch();
 }
 
@@ -889,6 +916,19 @@ static int ensure_graph(sgmg_hierarchy* h, int precond, int par, hipStream_t s) 
     if (e2 != hipSuccess) { ge = nullptr; set_error(std::string("graph instantiate: ") + hipGetErrorString(e2)); return SGMG_EHIP; }
   }
   return 0;
+}
+
+// Whether the PCG loop may queue iteration it + 1 before reading back
+// iteration it, given the relative residuals rel_0 .. rel_{it-1}: only when
+// iteration it is predicted to stay above rtol by a wide margin (the last
+// step ratio, at most 1/2, applied with a further factor 1/4), so that a
+// discarded look-ahead iteration is rare.
+static bool lookahead_ok(const std::vector<double>& hist, double rtol) {
+  const size_t m = hist.size();
+  if (m == 0) return false;
+  double q = 0.5;
+  if (m >= 2 && hist[m - 2] > 0.0) q = std::min(q, hist[m - 1] / hist[m - 2]);
+  return hist[m - 1] * q * 0.25 >= rtol;
 }
 
 static int run_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
@@ -938,14 +978,27 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
   double rel = 0.0, rel_true = -1.0, nf = 0.0;
   std::vector<double> hist;
   int rc = 0;
-  launch_copy(u, h->xs, n, s);
+  // x_0 lives in xs2, where the first iteration (slot SC_RZ0) reads it
+  double* xcur = h->xs2;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  SGMG_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  SGMG_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  // The iteration of slot parity q writes its scalars to h_it + q SC_COUNT
+  // from its last kernel and is followed by ev[q].
+  auto par = [](int sl) { return sl == SC_RZ0 ? 0 : 1; };
+  auto launch_iter = [&](int sl) -> int {
+    TRY(run_body(h, precond, sl, s));
+    SGMG_HIP(hipEventRecord(ev[par(sl)], s));
+    return 0;
+  };
+  launch_copy(u, xcur, n, s);
   do {
-    if ((rc = K64(h->xs, h->q, nullptr))) break;
+    if ((rc = K64(xcur, h->q, nullptr))) break;
     launch_pcg_init(f, h->q, 1, h->r, n, h->ws, sc + SC_FF, s);
     if ((rc = readsc())) break;
     nf = std::sqrt(hs[SC_FF]);
     if (nf == 0.0) {
-      SGMG_HIP(hipMemsetAsync(h->xs, 0, n * sizeof(double), s));
+      SGMG_HIP(hipMemsetAsync(xcur, 0, n * sizeof(double), s));
       status = SGMG_CONVERGED; rel = 0.0; rel_true = 0.0;
       hist.push_back(0.0);
       break;
@@ -961,31 +1014,52 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
     if ((rc = readsc())) break;
     if (!std::isfinite(hs[SC_RZ0])) { status = SGMG_NONFINITE; break; }
     if (hs[SC_RZ0] <= 0.0) { status = SGMG_BREAKDOWN; break; }
+    // Look-ahead: iteration it + 1 is queued before the scalars of iteration
+    // it are read back whenever the residual history says that iteration it
+    // will not stop the solve, so the device does not idle while the host
+    // decides.  Iteration it + 1 reads only device state and writes the
+    // other iterate buffer, so if iteration it does stop the solve (a
+    // misprediction) x_it is intact and the queued iteration is discarded;
+    // the iterates and scalars are those of the plain loop either way.
+    bool queued = false;    // iteration `it` is already on the stream
     int slot = SC_RZ0;
     for (int it = 1; it <= maxit; ++it) {
       const int nslot = slot == SC_RZ0 ? SC_RZ1 : SC_RZ0;
-      if ((rc = run_body(h, precond, slot, s))) break;
-      if ((rc = readsc())) break;
-      const double pq = hs[SC_PQ];
+      if (!queued && (rc = launch_iter(slot))) break;
+      queued = false;
+      if (it < maxit && lookahead_ok(hist, rtol)) {
+        if ((rc = launch_iter(nslot))) break;
+        queued = true;
+      }
+      SGMG_HIP(hipEventSynchronize(ev[par(slot)]));
+      const volatile double* hi = h->h_it + SC_COUNT * par(slot);
+      double* xin;
+      pcg_iterates(h, slot, &xin, &xcur);     // a failed step copies x_{it-1} here
+      const double pq = hi[SC_PQ];
       if (!std::isfinite(pq)) { status = SGMG_NONFINITE; iters = it - 1; break; }
       if (pq <= 0.0) { status = SGMG_BREAKDOWN; iters = it - 1; break; }
       iters = it;
-      rel = std::sqrt(hs[SC_RR]) / nf;
+      rel = std::sqrt(hi[SC_RR]) / nf;
       if (!std::isfinite(rel)) { hist.push_back(rel); status = SGMG_NONFINITE; break; }
-      bool restarted = false;
+      double rz = hi[nslot];
       if (rel < rtol) {
-        if ((rc = K64(h->xs, h->tmp, nullptr))) break;
+        // (queued after a look-ahead iteration, which touches neither x_it
+        // nor tmp)
+        if ((rc = K64(xcur, h->tmp, nullptr))) break;
         launch_residual(f, h->tmp, h->tmp, n, h->ws, sc + SC_TRUE, s);
         if ((rc = readsc())) break;
         const double rt = std::sqrt(hs[SC_TRUE]) / nf;
         if (rt < rtol) { hist.push_back(rel); status = SGMG_CONVERGED; rel_true = rt; break; }
-        // residual replacement with a restart of the recurrence (beta = 0)
+        // residual replacement with a restart of the recurrence (beta = 0);
+        // it rebuilds r, z, p and r.z from x_it, so a look-ahead iteration
+        // is dropped and run again from the new state
         launch_copy(h->tmp, h->r, n, s);
         if ((rc = precondition(h->r, h->z))) break;
         launch_pcg_dot_rz(h->r, h->z, nullptr, n, h->ws, sc + nslot, s);
         launch_copy(h->z, h->p, n, s);
         if ((rc = readsc())) break;
-        restarted = true;
+        queued = false;
+        rz = hs[nslot];
         rel = rt;
       }
       hist.push_back(rel);
@@ -996,22 +1070,22 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
         if (recent > 0.99 * before) { status = SGMG_STAGNATED; break; }
       }
       if (it == maxit) { status = SGMG_MAXIT; break; }
-      const double rz = hs[nslot];
       if (!std::isfinite(rz)) { status = SGMG_NONFINITE; break; }
       if (rz <= 0.0) { status = SGMG_BREAKDOWN; break; }
-      (void)restarted;
       slot = nslot;
     }
   } while (0);
+  hipEventDestroy(ev[0]);
+  hipEventDestroy(ev[1]);
   if (rc) {
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     return rc;
   }
-  launch_copy(h->xs, u, n, s);
+  launch_copy(xcur, u, n, s);
   SGMG_HIP(hipEventRecord(e1, s));
   if (rel_true < 0.0) {
-    TRY(K64(h->xs, h->tmp, nullptr));
+    TRY(K64(xcur, h->tmp, nullptr));
     launch_residual(f, h->tmp, nullptr, n, h->ws, sc + SC_TRUE, s);
     TRY(readsc());
     rel_true = std::sqrt(hs[SC_TRUE]) / (nf > 0 ? nf : 1.0);

@@ -43,6 +43,7 @@ class Options(ctypes.Structure):
         ("lambda_override", ctypes.POINTER(ctypes.c_double)),
         ("use_graphs", ctypes.c_int),
         ("cycle_gamma", ctypes.c_int),
+        ("stencil_form", ctypes.c_int),
     ]
 
 

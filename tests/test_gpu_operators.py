@@ -70,13 +70,16 @@ def test_galerkin_levels_and_diagonals(dims, L, seed):
         assert np.abs(S - ref).max() <= 1e-13 * np.abs(ref).max(), l
 
 
-@pytest.mark.parametrize("dims,L,seed", CASES[:2])
-def test_stencil_apply(dims, L, seed):
+@pytest.mark.parametrize("form", [0, 1, 2])
+@pytest.mark.parametrize("dims,L,seed", CASES)
+def test_stencil_apply(dims, L, seed, form):
+    """form 1: LDS-staged 27-offset kernel, 2: plane-split kernel, 0: chosen
+    by level size (the plane-split kernel at these sizes)."""
     from paper_2604_26441_amd import simpgmg
     rho, fixed = _inputs(dims, seed)
     E = mesh.simp_modulus(rho, 3)
     oh = multigrid.build(dims, E, fixed, multigrid.Options(n_levels=L, lambdas=[1.0] * (L - 1)))
-    h = _gpu_h(dims, L, rho)
+    h = _gpu_h(dims, L, rho, stencil_form=form)
     for l in range(1, L):
         K = oh.levels[l].K
         u = workloads.random_vector(K.shape[0], seed + l, oh.levels[l].fixed)

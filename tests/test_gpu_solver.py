@@ -43,6 +43,35 @@ def test_vcycle_f64_matches_oracle(dims, L, smoother, shape):
     assert rel_err(np64(z), ref, ref) < 1e-11
 
 
+@pytest.mark.parametrize("dims,L", [((24, 12, 12), 4), ((9, 7, 5), 3), ((32, 16, 16), 3)])
+@pytest.mark.parametrize("form", [1, 2])
+def test_vcycle_stencil_forms_match_oracle(dims, L, form):
+    """Both Galerkin-level kernels inside the V-cycle (smoothing, residual and
+    restriction epilogues) at FP64, and the LDS-staged one with level 1 in
+    FP32."""
+    from paper_2604_26441_amd import simpgmg
+    rho = np.random.default_rng(7).uniform(0.1, 1.0, np.prod(dims))
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    oh = multigrid.build(dims, mesh.simp_modulus(rho, 3), fixed, multigrid.Options(n_levels=L))
+    lams = [lv.lam for lv in oh.levels[:-1]]
+    r = workloads.random_vector(fixed.size, 8, fixed)
+    ref = multigrid.vcycle(oh, r)
+    o = simpgmg.default_options(*dims, n_levels=L, fine_prec="f64", stencil_form=form)
+    h = simpgmg.setup_hierarchy(o, t64(rho), lambda_override=lams)
+    z = t64(np.zeros_like(r))
+    simpgmg.vcycle(h, t64(r), z)
+    assert rel_err(np64(z), ref, ref) < 1e-11
+    o = simpgmg.default_options(*dims, n_levels=L, fine_prec="f64", stencil_form=form,
+                                level1_prec="f32")
+    h = simpgmg.setup_hierarchy(o, t64(rho), lambda_override=lams)
+    z = t64(np.zeros_like(r))
+    simpgmg.vcycle(h, t64(r), z)
+    assert rel_err(np64(z), ref, ref) < 1e-4
+    with pytest.raises(simpgmg.SimpGmgError, match="stencil_form"):
+        simpgmg.setup_hierarchy(simpgmg.default_options(*dims, n_levels=L, stencil_form=3),
+                                t64(rho))
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
 def test_vcycle_f32_close_to_oracle(prec):
     from paper_2604_26441_amd import simpgmg
@@ -107,6 +136,33 @@ def test_jacobi_pcg_matches_oracle():
     # steps; the early history must agree closely, the count within 2%.
     assert res["status"] == "converged" and abs(res["iters"] - it_o) <= max(1, it_o // 50)
     assert np.allclose(res["history"][:30], hist_o[:30], rtol=1e-8)
+
+
+@pytest.mark.parametrize("use_graphs", [1, 0])
+def test_pcg_lookahead_discarded_on_sudden_convergence(use_graphs):
+    """f = K_ff (e1 + e2) for two eigenvectors of the free block: plain CG
+    from zero reaches the exact solution at iteration 2 while the residual
+    history (1, O(1)) still predicts slow progress, so iteration 3 is queued
+    ahead and must be discarded without touching the returned iterate."""
+    from paper_2604_26441_amd import simpgmg
+    dims = (4, 2, 2)
+    rho = np.random.default_rng(11).uniform(0.3, 1.0, np.prod(dims))
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    K = mesh.assemble(dims, mesh.simp_modulus(rho, 3), fixed=fixed).toarray()
+    free = ~fixed
+    w, V = np.linalg.eigh(K[np.ix_(free, free)])
+    v = np.zeros(fixed.size)
+    v[free] = V[:, 3] + V[:, -2]
+    f = K @ v
+    o = simpgmg.default_options(*dims, n_levels=2, fine_prec="f64", use_graphs=use_graphs)
+    h = simpgmg.setup_hierarchy(o, t64(rho))
+    for _ in range(2):                   # the second solve starts after a discarded iteration
+        u = t64(np.zeros_like(f))
+        res = simpgmg.pcg_solve(h, t64(f), u, rtol=1e-8, maxit=50, precond=0, history_cap=64)
+        assert res["status"] == "converged" and res["iters"] == 2, res
+        hist = res["history"]
+        assert hist[1] * min(0.5, hist[1] / hist[0]) * 0.25 >= 1e-8     # look-ahead was queued
+        np.testing.assert_allclose(np64(u), v, rtol=0, atol=1e-10 * np.abs(v).max())
 
 
 def test_failure_statuses():
