@@ -381,6 +381,26 @@ template void launch_stencil_apply<double>(const Grid&, const double*, const dou
 template void launch_stencil_apply<float>(const Grid&, const float*, const float*, const uint8_t*,
                                           const Epi<float>&, int, hipStream_t);
 
+// Restriction launch: one thread per coarse DOF.  A block covers (part of)
+// one x-row of coarse nodes, 3 Nx consecutive DOFs, so a wave's stores are
+// contiguous, the row's y and z indices are uniform over the block (no
+// per-thread division by the grid sizes), and each thread sums one component
+// in the same order as the node-level definition.
+struct RowLaunch {
+  int threads;    // per block: 3 Nx rounded up to a whole number of waves, <= 256
+  int chunks;     // blocks per row
+  int blocks;     // chunks x rows
+};
+static RowLaunch row_launch(const Grid& g) {
+  RowLaunch r;
+  const int dofs = 3 * g.Nx;
+  r.threads = div_up(dofs, 64) * 64;
+  if (r.threads > 256) r.threads = 256;
+  r.chunks = div_up(dofs, r.threads);
+  r.blocks = r.chunks * g.Ny * g.Nz;
+  return r;
+}
+
 // Restriction (R = P^T, Eq. vector_prolongation): coarse node I gathers the
 // <= 27 fine nodes that interpolate from it.  Optional fused first smoothing
 // step from a zero iterate: x_c = c0 * Dinv_c * b_c, d_c = x_c.
@@ -393,25 +413,25 @@ __device__ inline void restrict_w1d(int I, int nf, double (&w)[3]) {
   w[2] = 2 * I + 1 < 2 * nc ? 0.5 : (2 * I + 1 == nf ? 1.0 : 0.0);
 }
 
-// Thread per coarse node (all three components: each fine node is one
-// contiguous 12- or 24-byte read), 256 coarse nodes per block, block index
-// remapped per XCD.  The 27 fine nodes are read unconditionally at clamped
-// indices and weighted (zero weights for nodes outside the grid); the
-// weighted sum runs in the same order as the per-component form.
+// Thread per coarse DOF.  The 27 fine nodes are read unconditionally at
+// clamped indices and weighted (zero weights for nodes outside the grid).
 template <typename TF, typename TC>
-__global__ __launch_bounds__(256) void k_restrict(Grid f, Grid c, const TF* __restrict__ rf,
+__global__ __launch_bounds__(256) void k_restrict(Grid f, Grid c, int chunks,
+                                                  const TF* __restrict__ rf,
                                                   const uint8_t* __restrict__ cfix,
                                                   TC* __restrict__ bc,
                                                   const TC* __restrict__ dinv_c, double c0,
                                                   TC* __restrict__ xc, TC* __restrict__ dc) {
-  const int I = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  if (I >= c.Nn) return;
-  const int Ix = I % c.Nx, t = I / c.Nx, Iy = t % c.Ny, Iz = t / c.Ny;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk / chunks, q = (blk - row * chunks) * blockDim.x + threadIdx.x;
+  if (q >= 3 * c.Nx) return;
+  const int Iy = row % c.Ny, Iz = row / c.Ny;
+  const int Ix = q / 3, k = q - 3 * Ix;
   double wx[3], wy[3], wz[3];
   restrict_w1d(Ix, f.nx, wx);
   restrict_w1d(Iy, f.ny, wy);
   restrict_w1d(Iz, f.nz, wz);
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc = 0.0;
 #pragma unroll
   for (int cz = 0; cz < 3; ++cz) {
     const int iz = min(max(2 * Iz - 1 + cz, 0), f.Nz - 1);
@@ -419,36 +439,31 @@ __global__ __launch_bounds__(256) void k_restrict(Grid f, Grid c, const TF* __re
     for (int cy = 0; cy < 3; ++cy) {
       const int iy = min(max(2 * Iy - 1 + cy, 0), f.Ny - 1);
       const double wyz = wy[cy] * wz[cz];
-      const size_t row = (size_t)f.Nx * (iy + (size_t)f.Ny * iz);
+      const size_t frow = (size_t)f.Nx * (iy + (size_t)f.Ny * iz);
 #pragma unroll
       for (int cx = 0; cx < 3; ++cx) {
         const int ix = min(max(2 * Ix - 1 + cx, 0), f.Nx - 1);
-        const TF* v = rf + 3 * (row + ix);
-        const double w = wx[cx] * wyz;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) acc[k] += w * (double)v[k];
+        acc += wx[cx] * wyz * (double)rf[3 * (frow + ix) + k];
       }
     }
   }
-  const unsigned fx = cfix[I];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const size_t dof = 3 * (size_t)I + k;
-    const TC v = (fx >> k) & 1u ? (TC)0 : (TC)acc[k];
-    bc[dof] = v;
-    if (xc) {
-      const TC x = (TC)c0 * dinv_c[dof] * v;
-      xc[dof] = x;
-      if (dc) dc[dof] = x;
-    }
+  const size_t I = Ix + (size_t)c.Nx * row;
+  const size_t dof = 3 * I + k;
+  const TC v = (cfix[I] >> k) & 1u ? (TC)0 : (TC)acc;
+  bc[dof] = v;
+  if (xc) {
+    const TC x = (TC)c0 * dinv_c[dof] * v;
+    xc[dof] = x;
+    if (dc) dc[dof] = x;
   }
 }
 
 template <typename TF, typename TC>
 void launch_restrict(const Grid& fine, const Grid& coarse, const TF* rf, const uint8_t* cfix,
                      TC* bc, const TC* dinv_c, double c0, TC* xc, TC* dc, hipStream_t s) {
-  k_restrict<TF, TC><<<div_up(coarse.Nn, 256), 256, 0, s>>>(fine, coarse, rf, cfix, bc, dinv_c,
-                                                            c0, xc, dc);
+  const RowLaunch r = row_launch(coarse);
+  k_restrict<TF, TC><<<r.blocks, r.threads, 0, s>>>(fine, coarse, r.chunks, rf, cfix, bc, dinv_c,
+                                                    c0, xc, dc);
 }
 template void launch_restrict<float, double>(const Grid&, const Grid&, const float*,
                                              const uint8_t*, double*, const double*, double,
@@ -476,12 +491,19 @@ __device__ inline void prolong_w1d(int i, int nf, int (&ci)[2], double (&w)[2]) 
   else { ci[0] = ci[1] = nc; w[0] = 1.0; w[1] = 0.0; }
 }
 
+// Thread per fine node (all three components); the fine values and the mask
+// are loaded together with the coarse values, and only free components are
+// stored.
 template <typename TF, typename TC>
-__global__ void k_prolong_add(Grid f, Grid c, const TC* __restrict__ ec,
-                              const uint8_t* __restrict__ ffix, TF* __restrict__ xf) {
-  const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_prolong_add(Grid f, Grid c, const TC* __restrict__ ec,
+                                                     const uint8_t* __restrict__ ffix,
+                                                     TF* __restrict__ xf) {
+  const int i = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (i >= f.Nn) return;
   const int ix = i % f.Nx, t = i / f.Nx, iy = t % f.Ny, iz = t / f.Ny;
+  TF* xi = xf + 3 * (size_t)i;
+  const TF x0 = xi[0], x1 = xi[1], x2 = xi[2];
+  const unsigned fx = ffix[i];
   int cx[2], cy[2], cz[2];
   double wx[2], wy[2], wz[2];
   prolong_w1d(ix, f.nx, cx, wx);
@@ -496,10 +518,9 @@ __global__ void k_prolong_add(Grid f, Grid c, const TC* __restrict__ ec,
     acc[1] += w * (double)ec[b + 1];
     acc[2] += w * (double)ec[b + 2];
   }
-  const unsigned fx = ffix[i];
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
-    if (!((fx >> k) & 1u)) xf[3 * (size_t)i + k] = (TF)((double)xf[3 * (size_t)i + k] + acc[k]);
+  if (!(fx & 1u)) xi[0] = (TF)((double)x0 + acc[0]);
+  if (!(fx & 2u)) xi[1] = (TF)((double)x1 + acc[1]);
+  if (!(fx & 4u)) xi[2] = (TF)((double)x2 + acc[2]);
 }
 
 template <typename TF, typename TC>

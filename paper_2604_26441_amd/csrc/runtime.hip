@@ -108,7 +108,9 @@ struct sgmg_hierarchy {
   int kry_cols = 0;
   double* gj_scratch = nullptr;
   hipStream_t cap = nullptr; // capture stream
-  hipGraphExec_t iter_graph[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  // per preconditioner: the iteration graphs of the two slot parities and the
+  // graph of the solve prologue (z_0 = M r_0, r_0.z_0, p_0 = z_0)
+  hipGraphExec_t iter_graph[3][3] = {};
 };
 
 namespace {
@@ -896,8 +898,22 @@ static int pcg_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
   return check_launch();
 }
 
+// PCG prologue on the solver's own buffers: z = M r, r.z into sc[SC_RZ0],
+// p = z.
+static int pcg_prologue_body(sgmg_hierarchy* h, int precond, hipStream_t s) {
+  const Level& L0 = h->lev[0];
+  const int n = L0.g.n;
+  if (precond == 2) TRY(vcycle_full(h, h->r, h->z, s));
+  else if (precond == 1) launch_apply_dinv(L0.dinv64, h->r, h->z, n, s);
+  else launch_copy(h->r, h->z, n, s);
+  launch_pcg_dot_rz(h->r, h->z, nullptr, n, h->ws, h->sc + SC_RZ0, s);
+  launch_copy(h->z, h->p, n, s);
+  return check_launch();
+}
+
 // Captures (once) the graph of one PCG iteration for a preconditioner and
-// slot parity.  Capture records the launches without running them.
+// slot parity (par 0, 1), or of the prologue (par 2).  Capture records the
+// launches without running them.
 static int ensure_graph(sgmg_hierarchy* h, int precond, int par, hipStream_t s) {
   const int slot = par == 0 ? SC_RZ0 : SC_RZ1;
   hipGraphExec_t& ge = h->iter_graph[precond][par];
@@ -906,7 +922,8 @@ static int ensure_graph(sgmg_hierarchy* h, int precond, int par, hipStream_t s) 
     // the capture stream must not run ahead of work already queued on s
     SGMG_HIP(hipStreamSynchronize(s));
     SGMG_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    const int rc = pcg_body(h, precond, slot, h->cap);
+    const int rc = par == 2 ? pcg_prologue_body(h, precond, h->cap)
+                            : pcg_body(h, precond, slot, h->cap);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(h->cap, &g);
     if (rc) { if (g) hipGraphDestroy(g); return rc; }
@@ -939,12 +956,20 @@ static int run_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
   return 0;
 }
 
+static int run_prologue(sgmg_hierarchy* h, int precond, hipStream_t s) {
+  if (!h->o.use_graphs) return pcg_prologue_body(h, precond, s);
+  TRY(ensure_graph(h, precond, 2, s));
+  SGMG_HIP(hipGraphLaunch(h->iter_graph[precond][2], s));
+  return 0;
+}
+
 // The V-cycle-preconditioned iteration graphs are part of the hierarchy:
 // captured at setup and after every re-assembly, so a solve only launches.
 static int capture_vcycle_graphs(sgmg_hierarchy* h, hipStream_t s) {
   if (!h->o.use_graphs) return 0;
   TRY(ensure_graph(h, 2, 0, s));
-  return ensure_graph(h, 2, 1, s);
+  TRY(ensure_graph(h, 2, 1, s));
+  return ensure_graph(h, 2, 2, s);
 }
 
 int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, double rtol,
@@ -991,11 +1016,26 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
     SGMG_HIP(hipEventRecord(ev[par(sl)], s));
     return 0;
   };
+  hipEvent_t e_pro = nullptr;
+  SGMG_HIP(hipEventCreateWithFlags(&e_pro, hipEventDisableTiming));
   launch_copy(u, xcur, n, s);
   do {
+    // Prologue: r_0 = f - K x_0, z_0 = M r_0, p_0 = z_0 and their scalars are
+    // queued together with iteration 1 (which writes only the other iterate
+    // buffer) before the host reads the scalars, so an early exit below
+    // leaves x_0 intact and merely discards that iteration.
     if ((rc = K64(xcur, h->q, nullptr))) break;
     launch_pcg_init(f, h->q, 1, h->r, n, h->ws, sc + SC_FF, s);
-    if ((rc = readsc())) break;
+    if ((rc = run_prologue(h, precond, s))) break;
+    SGMG_HIP(hipMemcpyAsync(hs, sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+    SGMG_HIP(hipEventRecord(e_pro, s));
+    bool queued = false;    // iteration `it` is already on the stream
+    int slot = SC_RZ0;
+    if (maxit > 0) {
+      if ((rc = launch_iter(slot))) break;
+      queued = true;
+    }
+    SGMG_HIP(hipEventSynchronize(e_pro));
     nf = std::sqrt(hs[SC_FF]);
     if (nf == 0.0) {
       SGMG_HIP(hipMemsetAsync(xcur, 0, n * sizeof(double), s));
@@ -1008,10 +1048,6 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
     if (!std::isfinite(rel)) { status = SGMG_NONFINITE; break; }
     if (rel < rtol) { status = SGMG_CONVERGED; rel_true = rel; break; }
     if (maxit == 0) { status = SGMG_MAXIT; break; }
-    if ((rc = precondition(h->r, h->z))) break;
-    launch_pcg_dot_rz(h->r, h->z, nullptr, n, h->ws, sc + SC_RZ0, s);
-    launch_copy(h->z, h->p, n, s);
-    if ((rc = readsc())) break;
     if (!std::isfinite(hs[SC_RZ0])) { status = SGMG_NONFINITE; break; }
     if (hs[SC_RZ0] <= 0.0) { status = SGMG_BREAKDOWN; break; }
     // Look-ahead: iteration it + 1 is queued before the scalars of iteration
@@ -1021,8 +1057,6 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
     // other iterate buffer, so if iteration it does stop the solve (a
     // misprediction) x_it is intact and the queued iteration is discarded;
     // the iterates and scalars are those of the plain loop either way.
-    bool queued = false;    // iteration `it` is already on the stream
-    int slot = SC_RZ0;
     for (int it = 1; it <= maxit; ++it) {
       const int nslot = slot == SC_RZ0 ? SC_RZ1 : SC_RZ0;
       if (!queued && (rc = launch_iter(slot))) break;
@@ -1077,6 +1111,7 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
   } while (0);
   hipEventDestroy(ev[0]);
   hipEventDestroy(ev[1]);
+  hipEventDestroy(e_pro);
   if (rc) {
     hipEventDestroy(e0);
     hipEventDestroy(e1);
