@@ -103,11 +103,12 @@ int pcg_vec_partials(int n);
 // launch); block 0 stores r.z [and r_old.z] at sc[slot_num] [slot_num + 1]
 // and the sum of the r.r partials at sc[slot_rr]; with host not NULL (a
 // device-mapped, coherent host array in sc's layout) it also writes those
-// and sc[slot_pq] there.
+// and sc[slot_pq] there, then increments the launch counter sc[slot_seq] and
+// writes its new value to *host_seq (mapped too) after the scalars.
 void launch_pcg_update_p_red(double* p, const double* z, const double* rz_part,
                              const double* rr_part, double* sc, int slot_num, int flex,
-                             int slot_den, int slot_rr, int slot_pq, double* host, int n,
-                             hipStream_t s);
+                             int slot_den, int slot_rr, int slot_pq, int slot_seq, double* host,
+                             double* host_seq, int n, hipStream_t s);
 // *out = max over (free) entries of a non-negative vector (fixn may be NULL)
 void launch_max_nonneg(const double* a, const uint8_t* fixn, int n, double* out, hipStream_t s);
 void launch_diag_finalize(double* d, double* dinv64, float* dinv32, const uint8_t* fixn, int n,

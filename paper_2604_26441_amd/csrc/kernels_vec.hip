@@ -276,7 +276,7 @@ int pcg_vec_partials(int n) { return (int)vec_grid(n); }
 __global__ __launch_bounds__(kVecBlock) void k_pcg_update_p_red(
     double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ rz_part,
     const double* __restrict__ rr_part, int nb, double* __restrict__ sc, int slot_num, int flex,
-    int slot_den, int slot_rr, int slot_pq, double* host, int n) {
+    int slot_den, int slot_rr, int slot_pq, int slot_seq, double* host, double* host_seq, int n) {
   __shared__ double lds[3][16];
   __shared__ double tot[3];
   double a = 0.0, b = 0.0, c = 0.0;
@@ -297,11 +297,16 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_p_red(
       if (flex) sc[slot_num + 1] = b;
       sc[slot_rr] = c;
       if (host) {
-        // the iteration's scalars for the host, in sc's slot layout
+        // the iteration's scalars for the host, in sc's slot layout, then
+        // the incremented launch counter, which tells the host they are there
         host[slot_num] = a;
         if (flex) host[slot_num + 1] = b;
         host[slot_rr] = c;
         host[slot_pq] = sc[slot_pq];
+        const double seq = sc[slot_seq] + 1.0;
+        sc[slot_seq] = seq;
+        __threadfence_system();
+        *(volatile double*)host_seq = seq;
         __threadfence_system();
       }
     }
@@ -314,11 +319,11 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_p_red(
 
 void launch_pcg_update_p_red(double* p, const double* z, const double* rz_part,
                              const double* rr_part, double* sc, int slot_num, int flex,
-                             int slot_den, int slot_rr, int slot_pq, double* host, int n,
-                             hipStream_t s) {
+                             int slot_den, int slot_rr, int slot_pq, int slot_seq, double* host,
+                             double* host_seq, int n, hipStream_t s) {
   k_pcg_update_p_red<<<vec_grid(n), kVecBlock, 0, s>>>(p, z, rz_part, rr_part, (int)vec_grid(n),
                                                        sc, slot_num, flex, slot_den, slot_rr,
-                                                       slot_pq, host, n);
+                                                       slot_pq, slot_seq, host, host_seq, n);
 }
 
 // Largest value of a (non-negative entries, or masked by fixn when given).

@@ -31,6 +31,7 @@ enum Slot {
   SC_RZ1 = 6, SC_ROZ1 = 7,   // odd iterations
   SC_TRUE = 8,               // true residual norm^2
   SC_XW = 9, SC_XDX = 10, SC_NRM = 11, SC_DSUM = 12, SC_EPS = 13, SC_MAX = 14,
+  SC_SEQ = 15,               // count of PCG iterations run on this hierarchy
   SC_COUNT = 16
 };
 
@@ -88,7 +89,8 @@ struct sgmg_hierarchy {
   double* sc = nullptr;
   double* h_sc = nullptr;    // pinned mirror of sc
   double* h_it = nullptr;    // coherent, device-mapped: the scalars of the last PCG
-                             // iteration of each slot parity (2 x SC_COUNT)
+                             // iteration of each slot parity (2 x SC_COUNT), then
+                             // the iteration counter's last value
   double* d_it = nullptr;    // device address of h_it
   int* d_flag = nullptr;
   double* r = nullptr;
@@ -752,12 +754,13 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
     return fail(rc);
   hipMemsetAsync(h->ws.counter, 0, sizeof(unsigned), s);
   hipMemsetAsync(h->sc, 0, SC_COUNT * sizeof(double), s);
-  if (hipHostMalloc((void**)&h->h_it, 2 * SC_COUNT * sizeof(double),
+  if (hipHostMalloc((void**)&h->h_it, (2 * SC_COUNT + 1) * sizeof(double),
                     hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
       hipHostGetDevicePointer((void**)&h->d_it, h->h_it, 0) != hipSuccess) {
     set_error("pinned allocation failed");
     return fail(SGMG_ENOMEM);
-  }
+  }  std::memset(h->h_it, 0, (2 * SC_COUNT + 1) * sizeof(double));
+
   if (hipHostMalloc((void**)&h->h_sc, SC_COUNT * sizeof(double), hipHostMallocDefault) !=
       hipSuccess) {
     set_error("pinned allocation failed");
@@ -893,8 +896,8 @@ static int pcg_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
   }
   launch_pcg_dot_rz(h->r, h->z, flex ? h->r_old : nullptr, n, h->ws, nullptr, s);
   launch_pcg_update_p_red(h->p, h->z, h->ws.partials, ws_rr.partials, sc, nslot, flex ? 1 : 0,
-                          slot, SC_RR, SC_PQ, h->d_it + SC_COUNT * (slot == SC_RZ0 ? 0 : 1), n,
-                          s);
+                          slot, SC_RR, SC_PQ, SC_SEQ, h->d_it + SC_COUNT * (slot == SC_RZ0 ? 0 : 1),
+                          h->d_it + 2 * SC_COUNT, n, s);
   return check_launch();
 }
 
@@ -1005,15 +1008,39 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
   int rc = 0;
   // x_0 lives in xs2, where the first iteration (slot SC_RZ0) reads it
   double* xcur = h->xs2;
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  SGMG_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-  SGMG_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
   // The iteration of slot parity q writes its scalars to h_it + q SC_COUNT
-  // from its last kernel and is followed by ev[q].
+  // from its last kernel, then the hierarchy's iteration count to
+  // h_it[2 SC_COUNT].  The host waits for the count that the launch will
+  // write (no event between iteration graphs); while waiting it checks now
+  // and then that the stream still has work, so a failed launch cannot leave
+  // it spinning.
   auto par = [](int sl) { return sl == SC_RZ0 ? 0 : 1; };
+  double seq_next = 0.0;             // count the next iteration launch writes
+  double seq_of[2] = {0.0, 0.0};     // count awaited per parity
+  const volatile double* seq_host = h->h_it + 2 * SC_COUNT;
   auto launch_iter = [&](int sl) -> int {
     TRY(run_body(h, precond, sl, s));
-    SGMG_HIP(hipEventRecord(ev[par(sl)], s));
+    seq_of[par(sl)] = seq_next;
+    seq_next += 1.0;
+    return 0;
+  };
+  auto wait_iter = [&](int sl) -> int {
+    const double target = seq_of[par(sl)];
+    for (unsigned k = 1; *seq_host < target; ++k) {
+      if ((k & 4095) == 0) {
+        const hipError_t q = hipStreamQuery(s);
+        if (q == hipSuccess && *seq_host < target) {
+          set_error("PCG iteration scalars did not arrive");
+          return SGMG_EHIP;
+        }
+        if (q != hipSuccess && q != hipErrorNotReady) {
+          set_error(std::string("PCG iteration: ") + hipGetErrorString(q));
+          return SGMG_EHIP;
+        }
+      }
+      __builtin_ia32_pause();
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
     return 0;
   };
   hipEvent_t e_pro = nullptr;
@@ -1029,6 +1056,8 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
     if ((rc = run_prologue(h, precond, s))) break;
     SGMG_HIP(hipMemcpyAsync(hs, sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
     SGMG_HIP(hipEventRecord(e_pro, s));
+    // (the copy above is ordered before iteration 1, so hs[SC_SEQ] is the
+    // count before this solve's first iteration)
     bool queued = false;    // iteration `it` is already on the stream
     int slot = SC_RZ0;
     if (maxit > 0) {
@@ -1036,6 +1065,8 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
       queued = true;
     }
     SGMG_HIP(hipEventSynchronize(e_pro));
+    seq_of[0] += hs[SC_SEQ] + 1.0;
+    seq_next += hs[SC_SEQ] + 1.0;
     nf = std::sqrt(hs[SC_FF]);
     if (nf == 0.0) {
       SGMG_HIP(hipMemsetAsync(xcur, 0, n * sizeof(double), s));
@@ -1065,7 +1096,7 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
         if ((rc = launch_iter(nslot))) break;
         queued = true;
       }
-      SGMG_HIP(hipEventSynchronize(ev[par(slot)]));
+      if ((rc = wait_iter(slot))) break;
       const volatile double* hi = h->h_it + SC_COUNT * par(slot);
       double* xin;
       pcg_iterates(h, slot, &xin, &xcur);     // a failed step copies x_{it-1} here
@@ -1109,8 +1140,6 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
       slot = nslot;
     }
   } while (0);
-  hipEventDestroy(ev[0]);
-  hipEventDestroy(ev[1]);
   hipEventDestroy(e_pro);
   if (rc) {
     hipEventDestroy(e0);
