@@ -152,7 +152,7 @@ void sgmg_default_options(sgmg_options* o, int nx, int ny, int nz);
  * 1e-14)).  When the coarsest free-DOF count exceeds dense_max, the coarsest
  * solve is instead coarse_pcg_iters steps of Jacobi-PCG on K_L from zero,
  * stopping early only on p.Kp <= 0 or r.z = 0 (Sec. 3.2, Table
- * repro_defaults); one workgroup runs them in one launch.  Returns SGMG_EINVAL
+ * repro_defaults); each step is two chip-wide launches.  Returns SGMG_EINVAL
  * if a coarse level would have no elements, or if the iterative coarsest
  * solve is needed and coarse_pcg_iters < 1. */
 int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E,
@@ -177,7 +177,12 @@ int sgmg_vcycle(const sgmg_hierarchy* h, const double* r, double* z, void* strea
  * 2 the V-cycle.  u: in = x0 (zeros for a cold start), out = the iterate at
  * exit.  Converged only if the FP64 true residual passes rtol; the recursive
  * residual triggers the check and a failed check replaces r by the true
- * residual.  info may be NULL. */
+ * residual.  info may be NULL.  The host may queue iteration k + 1 before it
+ * has read iteration k's scalars (which the device writes into mapped host
+ * memory); such an iteration writes only solver-owned buffers and is
+ * discarded if iteration k ends the solve, so u, the status and the counts
+ * are those of the plain loop.  Returns after all of its work on the stream
+ * has completed.  Calls on one hierarchy must not overlap. */
 int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u,
                    double rtol, int maxit, sgmg_solve_info* info, void* stream);
 
