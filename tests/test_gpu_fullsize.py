@@ -120,3 +120,27 @@ def test_fullsize_pcg_solution():
         rel = np.linalg.norm(r) / np.linalg.norm(f)
         assert rel < 1e-6
         assert abs(res["rel_res_true"] - rel) < 1e-9
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_fullsize_heterogeneous_solves(p):
+    """The 60^3 random-field cantilever of the precision study (seed 0) at its
+    full size: FP64-GMG, FP32-GMG (BF16X3 fine level) and BF16-GMG (BF16
+    fine level, FP32 level 1, flexible PCG) must each return a u whose oracle
+    residual passes rtol, with the residual they report."""
+    from paper_2604_26441_amd import simpgmg
+    dims = (60, 60, 60)
+    rho = workloads.grf_rho(dims, 0)
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    f = workloads.edge_load(dims)
+    E = mesh.simp_modulus(rho, p)
+    variants = {"f64": {}, "bf16x3": {}, "bf16": {"flexible_beta": 1, "level1_prec": "f32"}}
+    for prec, kw in variants.items():
+        o = simpgmg.default_options(*dims, penal=float(p), fine_prec=prec, **kw)
+        h = simpgmg.setup_hierarchy(o, t64(rho))
+        u = t64(np.zeros_like(f))
+        res = simpgmg.pcg_solve(h, t64(f), u, rtol=1e-6, maxit=500)
+        assert res["status"] == "converged", (prec, res)
+        r = f - mesh.apply_K_elementwise(dims, E, np64(u), fixed=fixed)
+        rel = np.linalg.norm(r) / np.linalg.norm(f)
+        assert rel < 1e-6 and abs(res["rel_res_true"] - rel) < 1e-9, (prec, rel, res)
