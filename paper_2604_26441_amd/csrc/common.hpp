@@ -112,7 +112,8 @@ struct Epi {
   int store_d;
   int want_dot;        // STORE: accumulate x.y into dot
   RedWs ws;
-  double* dot_out;     // finalized by the launcher after the kernel
+  double* dot_out;     // finalized by the launcher after the kernel (NULL: the
+                       // block partials stay in ws.partials)
 };
 
 template <typename T>

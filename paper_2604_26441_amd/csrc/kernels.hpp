@@ -85,15 +85,17 @@ void launch_copy(const double* in, double* out, int n, hipStream_t s);
 void launch_pcg_init(const double* f, const double* Ax0, int have_x0, double* r, int n,
                      RedWs ws, double* sc_ff_rr, hipStream_t s);
 // x = x_in + alpha p (x_in may be x), r -= alpha q (alpha = sc[slot_rz] /
-// sc[slot_pq]; a failed step leaves r and copies x_in to x), r.r; with b not
-// NULL also the entry of the V-cycle that follows (b = (T) r, x = c0 Dinv b,
-// d = x when d is not NULL).  sc_rr NULL: the r.r partials stay in ws for
-// launch_pcg_update_p_red.
+// p.q; a failed step leaves r and copies x_in to x), r.r; with b not NULL
+// also the entry of the V-cycle that follows (b = (T) r, x = c0 Dinv b, d = x
+// when d is not NULL).  p.q is sc[slot_pq], or, with pq_part not NULL, the
+// sum of the npq block partials there (stored into sc[slot_pq]).  sc_rr
+// NULL: the r.r partials stay in ws for launch_pcg_update_p_red.
 template <typename T>
 void launch_pcg_update_xr_entry(const double* x_in, double* x, double* r, double* r_old,
-                                const double* p, const double* q, const double* sc, int slot_rz,
-                                int slot_pq, int n, RedWs ws, double* sc_rr, T* b, const T* dinv,
-                                double c0, T* xe, T* de, hipStream_t s);
+                                const double* p, const double* q, double* sc, int slot_rz,
+                                int slot_pq, const double* pq_part, int npq, int n, RedWs ws,
+                                double* sc_rr, T* b, const T* dinv, double c0, T* xe, T* de,
+                                hipStream_t s);
 // (sc_out2 NULL: partials only, for launch_pcg_update_p_red)
 void launch_pcg_dot_rz(const double* r, const double* z, const double* r_old, int n, RedWs ws,
                        double* sc_out2, hipStream_t s);

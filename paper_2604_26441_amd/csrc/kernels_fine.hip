@@ -167,7 +167,7 @@ template <typename T>
 void launch_apply_fine_node(const Grid& g, const T* E, const T* ke, const T* u,
                             const uint8_t* fixn, const Epi<T>& ep, hipStream_t s) {
   k_apply_fine_node<T><<<div_up(g.Nn, 256), 256, 0, s>>>(g, E, ke, u, fixn, ep);
-  if (ep.want_dot) launch_finalize(ep.ws, div_up(g.Nn, 256), 1, ep.dot_out, s);
+  if (ep.want_dot && ep.dot_out) launch_finalize(ep.ws, div_up(g.Nn, 256), 1, ep.dot_out, s);
 }
 
 template void launch_apply_fine_node<double>(const Grid&, const double*, const double*,

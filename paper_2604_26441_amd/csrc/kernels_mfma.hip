@@ -519,7 +519,8 @@ void launch_apply_fine_mfma(const Grid& g, int nsplit, int rows, int zchunk, con
     if (rows == 4) launch_shape<1, 4>(g, m, zchunk, Escaled, at, u, fixn, ep, s);
     else launch_shape<1, 8>(g, m, zchunk, Escaled, at, u, fixn, ep, s);
   }
-  if (ep.mode == EPI_STORE && ep.want_dot) launch_finalize(ep.ws, m.blocks, 1, ep.dot_out, s);
+  if (ep.mode == EPI_STORE && ep.want_dot && ep.dot_out)
+    launch_finalize(ep.ws, m.blocks, 1, ep.dot_out, s);
 }
 
 template <int YC>
@@ -549,7 +550,8 @@ void launch_apply_fine_mfma64(const Grid& g, int rows, int zchunk, const double*
   const MfmaLaunch m = mfma_launch(g, rows, zchunk);
   if (rows == 4) launch_shape64<4>(g, m, zchunk, E, atab64, u, fixn, ep, s);
   else launch_shape64<8>(g, m, zchunk, E, atab64, u, fixn, ep, s);
-  if (ep.mode == EPI_STORE && ep.want_dot) launch_finalize(ep.ws, m.blocks, 1, ep.dot_out, s);
+  if (ep.mode == EPI_STORE && ep.want_dot && ep.dot_out)
+    launch_finalize(ep.ws, m.blocks, 1, ep.dot_out, s);
 }
 
 bool mfma64_size_ok(const Grid& g) {

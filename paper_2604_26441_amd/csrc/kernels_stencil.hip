@@ -374,7 +374,7 @@ void launch_stencil_apply(const Grid& g, const T* S, const T* u, const uint8_t* 
     k_stencil_apply_s<T><<<nb, 192, 0, s>>>(g, S, u, fixn, ep);
   else
     k_stencil_apply_c<T><<<nb, 576, 0, s>>>(g, S, u, fixn, ep);
-  if (ep.want_dot) launch_finalize(ep.ws, nb, 1, ep.dot_out, s);
+  if (ep.want_dot && ep.dot_out) launch_finalize(ep.ws, nb, 1, ep.dot_out, s);
 }
 template void launch_stencil_apply<double>(const Grid&, const double*, const double*,
                                            const uint8_t*, const Epi<double>&, int, hipStream_t);

@@ -189,10 +189,29 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(const double* x_in,
                                                              double* __restrict__ r_old,
                                                              const double* __restrict__ p,
                                                              const double* __restrict__ q,
-                                                             const double* __restrict__ sc,
-                                                             int slot_rz, int slot_pq, int n,
-                                                             RedWs ws, VEntry<T> e) {
-  const double pq = sc[slot_pq];
+                                                             double* __restrict__ sc,
+                                                             int slot_rz, int slot_pq,
+                                                             const double* __restrict__ pq_part,
+                                                             int npq, int n, RedWs ws,
+                                                             VEntry<T> e) {
+  // p.q: from sc, or summed here from the K p kernel's block partials by
+  // every block in the same order (block 0 also stores it in sc)
+  double pq;
+  if (pq_part) {
+    __shared__ double lds[16];
+    __shared__ double tot;
+    double a = 0.0;
+    for (int i = threadIdx.x; i < npq; i += kVecBlock) a += pq_part[i];
+    a = block_sum(a, lds);
+    if (threadIdx.x == 0) {
+      tot = a;
+      if (blockIdx.x == 0) sc[slot_pq] = a;
+    }
+    __syncthreads();
+    pq = tot;
+  } else {
+    pq = sc[slot_pq];
+  }
   const double alpha = sc[slot_rz] / pq;
   // a failed step (p.q <= 0 or non-finite) leaves r untouched and x equal
   // to x_in (x_in may be x itself)
@@ -223,9 +242,10 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(const double* x_in,
 
 template <typename T>
 void launch_pcg_update_xr_entry(const double* x_in, double* x, double* r, double* r_old,
-                                const double* p, const double* q, const double* sc, int slot_rz,
-                                int slot_pq, int n, RedWs ws, double* sc_rr, T* b, const T* dinv,
-                                double c0, T* xe, T* de, hipStream_t s) {
+                                const double* p, const double* q, double* sc, int slot_rz,
+                                int slot_pq, const double* pq_part, int npq, int n, RedWs ws,
+                                double* sc_rr, T* b, const T* dinv, double c0, T* xe, T* de,
+                                hipStream_t s) {
   VEntry<T> e;
   e.b = b;
   e.dinv = dinv;
@@ -233,17 +253,18 @@ void launch_pcg_update_xr_entry(const double* x_in, double* x, double* r, double
   e.x = xe;
   e.d = de;
   k_pcg_update_xr<T><<<vec_grid(n), kVecBlock, 0, s>>>(x_in, x, r, r_old, p, q, sc, slot_rz,
-                                                       slot_pq, n, ws, e);
+                                                       slot_pq, pq_part, npq, n, ws, e);
   if (sc_rr) launch_finalize(ws, vec_grid(n), 1, sc_rr, s);
 }
 template void launch_pcg_update_xr_entry<float>(const double*, double*, double*, double*,
-                                                const double*, const double*, const double*, int,
-                                                int, int, RedWs, double*, float*, const float*,
-                                                double, float*, float*, hipStream_t);
+                                                const double*, const double*, double*, int, int,
+                                                const double*, int, int, RedWs, double*, float*,
+                                                const float*, double, float*, float*, hipStream_t);
 template void launch_pcg_update_xr_entry<double>(const double*, double*, double*, double*,
-                                                 const double*, const double*, const double*, int,
-                                                 int, int, RedWs, double*, double*, const double*,
-                                                 double, double*, double*, hipStream_t);
+                                                 const double*, const double*, double*, int, int,
+                                                 const double*, int, int, RedWs, double*, double*,
+                                                 const double*, double, double*, double*,
+                                                 hipStream_t);
 
 // out[0] = r.z ; out[1] = r_old.z (flexible beta numerator r.z - r_old.z)
 __global__ __launch_bounds__(kVecBlock) void k_pcg_dot_rz(const double* __restrict__ r,

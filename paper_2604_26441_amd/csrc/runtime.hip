@@ -86,6 +86,7 @@ struct sgmg_hierarchy {
   double* cpcg_scratch = nullptr;
   int* cpcg_done = nullptr;
   RedWs ws{};
+  size_t npart = 0;          // doubles in ws.partials
   double* sc = nullptr;
   double* h_sc = nullptr;    // pinned mirror of sc
   double* h_it = nullptr;    // coherent, device-mapped: the scalars of the last PCG
@@ -210,6 +211,14 @@ Epi<T> epi_store(T* out, RedWs ws = {}, double* dot_out = nullptr) {
   return e;
 }
 
+// STORE with the x.y block partials left in ws.partials (no finalize).
+template <typename T>
+Epi<T> epi_store_partials(T* out, RedWs ws) {
+  Epi<T> e = epi_store<T>(out, ws);
+  e.want_dot = 1;
+  return e;
+}
+
 template <typename T>
 Epi<T> epi_resid(T* out, const T* b) {
   Epi<T> e{};
@@ -289,6 +298,16 @@ int apply_level<float>(const sgmg_hierarchy* h, int l, sgmg_prec prec, const flo
     launch_stencil_apply<float>(L.g, L.S32, x, L.fixn, ep, h->o.stencil_form, s);
   }
   return check_launch();
+}
+
+// Block partials that the level-0 FP64 operator writes with a dot (its grid
+// size: the MFMA tile grid or one block per 256 nodes).
+int k64_dot_partials(const sgmg_hierarchy* h) {
+  const Level& L = h->lev[0];
+  if (h->mfma_rows[2] > 0 && mfma64_size_ok(L.g))
+    return (int)apply_fine_mfma_blocks(L.g, h->mfma_rows[2] == 4 ? 4 : 8,
+                                       h->mfma_zchunk[2] < 1 ? 1 : h->mfma_zchunk[2]);
+  return div_up(L.g.Nn, 256);
 }
 
 sgmg_prec level_prec(const sgmg_hierarchy* h, int l) {
@@ -747,8 +766,10 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
   // one partial per block of the largest reduction grid (fused dots run one
   // block per 256 nodes; vector reductions use at most 2 x 1024 slots)
   // (the MFMA kernel's largest grid is its smallest tile shape: 4 rows, 1 plane)
+  // (+ 4096: the PCG iteration keeps the r.r partials after the K p ones)
   const size_t npart = std::max({kMinPartials, (size_t)div_up(g0.Nn, 256) + 2048,
-                                 apply_fine_mfma_blocks(g0, 4, 1)});
+                                 apply_fine_mfma_blocks(g0, 4, 1) + 4096});
+  h->npart = npart;
   if ((rc = dalloc_t(h, &h->ws.partials, npart)) || (rc = dalloc_t(h, &h->ws.counter, 1)) ||
       (rc = dalloc_t(h, &h->sc, SC_COUNT)) || (rc = dalloc_t(h, &h->d_flag, 1)))
     return fail(rc);
@@ -866,22 +887,29 @@ static int pcg_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
   // The r.r partials of the update and the r.z partials after the
   // preconditioner are summed inside the p update (no finalize launches);
   // they sit in disjoint parts of the workspace.
+  // The K p partials (summed inside the update) come first; the r.r
+  // partials of the update start after both them and the r.z partials.
   const int nb = pcg_vec_partials(n);
+  const int npq = k64_dot_partials(h);
   RedWs ws_rr = h->ws;
-  ws_rr.partials = h->ws.partials + 2 * (size_t)nb;
-  TRY(apply_level<double>(h, 0, SGMG_F64, h->p, epi_store<double>(h->q, h->ws, sc + SC_PQ), s));
+  ws_rr.partials = h->ws.partials + std::max(2 * (size_t)nb, (size_t)npq);
+  if (std::max(2 * (size_t)nb, (size_t)npq) + nb > h->npart) {
+    set_error("reduction workspace too small");
+    return SGMG_EINVAL;
+  }
+  TRY(apply_level<double>(h, 0, SGMG_F64, h->p, epi_store_partials<double>(h->q, h->ws), s));
   if (precond == 2) {
     // the update also writes the V-cycle's entry (its first smoothing step)
     const Smoother sm = smoother_of(h, 0);
     const double c0 = first_step_coef(sm);
     if (L0.f32)
       launch_pcg_update_xr_entry<float>(xin, xout, h->r, flex ? h->r_old : nullptr, h->p, h->q,
-                                        sc, slot, SC_PQ, n, ws_rr, nullptr, (float*)L0.b,
+                                        sc, slot, SC_PQ, h->ws.partials, npq, n, ws_rr, nullptr, (float*)L0.b,
                                         L0.dinv32, c0, (float*)L0.x[0],
                                         sm.cheb ? (float*)L0.dv : nullptr, s);
     else
       launch_pcg_update_xr_entry<double>(xin, xout, h->r, flex ? h->r_old : nullptr, h->p, h->q,
-                                         sc, slot, SC_PQ, n, ws_rr, nullptr, (double*)L0.b,
+                                         sc, slot, SC_PQ, h->ws.partials, npq, n, ws_rr, nullptr, (double*)L0.b,
                                          L0.dinv64, c0, (double*)L0.x[0],
                                          sm.cheb ? (double*)L0.dv : nullptr, s);
     TRY(check_launch());
@@ -889,7 +917,7 @@ static int pcg_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
     TRY(vcycle_level(h, 0, &cur, h->z, true, s));
   } else {
     launch_pcg_update_xr_entry<double>(xin, xout, h->r, flex ? h->r_old : nullptr, h->p, h->q,
-                                       sc, slot, SC_PQ, n, ws_rr, nullptr, nullptr, nullptr, 0.0,
+                                       sc, slot, SC_PQ, h->ws.partials, npq, n, ws_rr, nullptr, nullptr, nullptr, 0.0,
                                        nullptr, nullptr, s);
     if (precond == 1) launch_apply_dinv(L0.dinv64, h->r, h->z, n, s);
     else launch_copy(h->r, h->z, n, s);
