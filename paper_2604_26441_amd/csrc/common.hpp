@@ -191,22 +191,42 @@ __device__ inline double epilogue3_pre(const Epi<T>& ep, int node, unsigned fx, 
 }
 
 // The same epilogue for one component c of a node (thread per DOF kernels).
+// Its vector operands are loaded by epilogue1_load, which a kernel issues
+// before it forms the product so that their latency overlaps the product's
+// own loads.
 template <typename T>
-__device__ inline double epilogue1(const Epi<T>& ep, size_t dof, bool fixed, T x, double y) {
+struct Epi1In {
+  T b, dinv, d;
+};
+
+template <typename T>
+__device__ inline Epi1In<T> epilogue1_load(const Epi<T>& ep, size_t dof) {
+  Epi1In<T> in{(T)0, (T)0, (T)0};
+  if (ep.mode == EPI_RESID || ep.mode == EPI_SMOOTH) in.b = ep.b[dof];
+  if (ep.mode == EPI_SMOOTH) {
+    in.dinv = ep.dinv[dof];
+    if (ep.c1 != 0.0) in.d = ep.d[dof];
+  }
+  return in;
+}
+
+template <typename T>
+__device__ inline double epilogue1(const Epi<T>& ep, size_t dof, bool fixed, T x, double y,
+                                   const Epi1In<T>& in) {
   if (ep.mode == EPI_STORE) {
     const double v = fixed ? 0.0 : y;
     ep.out[dof] = (T)v;
     return (double)x * v;
   }
   if (ep.mode == EPI_RESID) {
-    ep.out[dof] = fixed ? (T)0 : (T)((double)ep.b[dof] - y);
+    ep.out[dof] = fixed ? (T)0 : (T)((double)in.b - y);
     return 0.0;
   }
   T xo = (T)0, dd = (T)0;
   if (!fixed) {
-    const T r = (T)((double)ep.b[dof] - y);
-    const T dp = ep.c1 != 0.0 ? ep.d[dof] : (T)0;
-    dd = (T)ep.c1 * dp + (T)ep.c2 * ep.dinv[dof] * r;
+    const T r = (T)((double)in.b - y);
+    const T dp = ep.c1 != 0.0 ? in.d : (T)0;
+    dd = (T)ep.c1 * dp + (T)ep.c2 * in.dinv * r;
     xo = x + dd;
   }
   if (ep.store_d) ep.d[dof] = dd;

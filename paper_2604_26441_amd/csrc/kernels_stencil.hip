@@ -233,6 +233,17 @@ __global__ __launch_bounds__(576) void k_stencil_apply_c(Grid g, const T* __rest
   const bool in = node0 < g.Nn;
   // lanes past the grid work on the last node and store nothing
   const int node = in ? node0 : g.Nn - 1;
+  // the epilogue's operands are loaded first (one memory round trip less)
+  const size_t dof = 3 * (size_t)node + d;
+  const bool epi = in && pz == 1;
+  Epi1In<T> ein{(T)0, (T)0, (T)0};
+  unsigned fx = 0;
+  T xown = (T)0;
+  if (epi) {
+    ein = epilogue1_load(ep, dof);
+    fx = fixn[node];
+    xown = u[dof];
+  }
   {
     const int i = node % g.Nx, t = node / g.Nx, j = t % g.Ny, k = t / g.Ny;
     const size_t Nn = g.Nn;
@@ -260,10 +271,9 @@ __global__ __launch_bounds__(576) void k_stencil_apply_c(Grid g, const T* __rest
   }
   __syncthreads();
   double dot = 0.0;
-  if (in && pz == 1) {
+  if (epi) {
     const double y = (part[0][d][lane] + part[1][d][lane]) + part[2][d][lane];
-    const size_t dof = 3 * (size_t)node + d;
-    dot = epilogue1(ep, dof, (fixn[node] >> d) & 1u, u[dof], y);
+    dot = epilogue1(ep, dof, (fx >> d) & 1u, xown, y, ein);
   }
   if (ep.want_dot) {
     const double v[1] = {dot};
@@ -291,6 +301,12 @@ __global__ __launch_bounds__(192) void k_stencil_apply_s(
   __shared__ T us[9][kRow];
   const int lane = threadIdx.x & 63, d = threadIdx.x >> 6;
   const long node0 = (long)xcd_block(blockIdx.x, gridDim.x) * 64;
+  const bool in = node0 + lane < g.Nn;
+  const int node = in ? (int)node0 + lane : g.Nn - 1;
+  // the epilogue's operands are loaded first (one memory round trip less)
+  const size_t dof = 3 * (size_t)node + d;
+  const Epi1In<T> ein = epilogue1_load(ep, dof);
+  const unsigned fx = fixn[node];
   {
     // thread t stages entry t of each row (and entry 192 + t for t < 6);
     // the loads read clamped indices unconditionally so that all of them
@@ -326,8 +342,6 @@ __global__ __launch_bounds__(192) void k_stencil_apply_s(
     }
   }
   __syncthreads();
-  const bool in = node0 + lane < g.Nn;
-  const int node = in ? (int)node0 + lane : g.Nn - 1;
   const int i = node % g.Nx, tt = node / g.Nx, j = tt % g.Ny, k = tt / g.Ny;
   const size_t Nn = g.Nn;
   T acc = (T)0;
@@ -350,10 +364,7 @@ __global__ __launch_bounds__(192) void k_stencil_apply_s(
     acc += ok ? v : (T)0;
   }
   double dot = 0.0;
-  if (in) {
-    const size_t dof = 3 * (size_t)node + d;
-    dot = epilogue1(ep, dof, (fixn[node] >> d) & 1u, us[4][3 * (lane + 1) + d], (double)acc);
-  }
+  if (in) dot = epilogue1(ep, dof, (fx >> d) & 1u, us[4][3 * (lane + 1) + d], (double)acc, ein);
   if (ep.want_dot) {
     const double v[1] = {dot};
     grid_sum<1>(v, ep.ws);
@@ -427,6 +438,11 @@ __global__ __launch_bounds__(256) void k_restrict(Grid f, Grid c, int chunks,
   if (q >= 3 * c.Nx) return;
   const int Iy = row % c.Ny, Iz = row / c.Ny;
   const int Ix = q / 3, k = q - 3 * Ix;
+  // the output's mask and diagonal are loaded with the fine values
+  const size_t I = Ix + (size_t)c.Nx * row;
+  const size_t dof = 3 * I + k;
+  const unsigned fx = cfix[I];
+  const TC dv = xc ? dinv_c[dof] : (TC)0;
   double wx[3], wy[3], wz[3];
   restrict_w1d(Ix, f.nx, wx);
   restrict_w1d(Iy, f.ny, wy);
@@ -447,12 +463,10 @@ __global__ __launch_bounds__(256) void k_restrict(Grid f, Grid c, int chunks,
       }
     }
   }
-  const size_t I = Ix + (size_t)c.Nx * row;
-  const size_t dof = 3 * I + k;
-  const TC v = (cfix[I] >> k) & 1u ? (TC)0 : (TC)acc;
+  const TC v = (fx >> k) & 1u ? (TC)0 : (TC)acc;
   bc[dof] = v;
   if (xc) {
-    const TC x = (TC)c0 * dinv_c[dof] * v;
+    const TC x = (TC)c0 * dv * v;
     xc[dof] = x;
     if (dc) dc[dof] = x;
   }
