@@ -194,6 +194,21 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(const double* x_in,
                                                              const double* __restrict__ pq_part,
                                                              int npq, int n, RedWs ws,
                                                              VEntry<T> e) {
+  // The first element's operands are loaded before the p.q partials are
+  // summed (that sum is a memory round trip of its own).
+  const int i0 = blockIdx.x * kVecBlock + threadIdx.x;
+  const int stride = gridDim.x * kVecBlock;
+  const bool has0 = i0 < n;
+  double r0 = 0.0, x0 = 0.0, p0 = 0.0, q0 = 0.0;
+  T d0 = (T)0;
+  const double rz = sc[slot_rz];
+  if (has0) {
+    r0 = r[i0];
+    x0 = x_in[i0];
+    p0 = p[i0];
+    q0 = q[i0];
+    if (e.b) d0 = e.dinv[i0];
+  }
   // p.q: from sc, or summed here from the K p kernel's block partials by
   // every block in the same order (block 0 also stores it in sc)
   double pq;
@@ -212,30 +227,32 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(const double* x_in,
   } else {
     pq = sc[slot_pq];
   }
-  const double alpha = sc[slot_rz] / pq;
+  const double alpha = rz / pq;
   // a failed step (p.q <= 0 or non-finite) leaves r untouched and x equal
   // to x_in (x_in may be x itself)
   const bool ok = pq > 0.0 && isfinite(alpha);
   double rr = 0.0;
-  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n; i += gridDim.x * kVecBlock) {
-    const double ro = r[i];
+  auto element = [&](int i, double ro, double xi, double pi, double qi, T di) {
     double rv = ro;
-    if (!ok && x_in != x) x[i] = x_in[i];
+    if (!ok && x_in != x) x[i] = xi;
     if (ok) {
-      x[i] = x_in[i] + alpha * p[i];
+      x[i] = xi + alpha * pi;
       if (r_old) r_old[i] = ro;
-      rv = ro - alpha * q[i];
+      rv = ro - alpha * qi;
       r[i] = rv;
     }
     rr += rv * rv;
     if (e.b) {
       const T bv = (T)rv;
       e.b[i] = bv;
-      const T xv = (T)e.c0 * e.dinv[i] * bv;
+      const T xv = (T)e.c0 * di * bv;
       e.x[i] = xv;
       if (e.d) e.d[i] = xv;
     }
-  }
+  };
+  if (has0) element(i0, r0, x0, p0, q0, d0);
+  for (int i = i0 + stride; i < n; i += stride)
+    element(i, r[i], x_in[i], p[i], q[i], e.b ? e.dinv[i] : (T)0);
   const double v[1] = {rr};
   grid_sum<1>(v, ws);
 }
@@ -300,6 +317,15 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_p_red(
     int slot_den, int slot_rr, int slot_pq, int slot_seq, double* host, double* host_seq, int n) {
   __shared__ double lds[3][16];
   __shared__ double tot[3];
+  // the first element's operands are loaded before the partial sums
+  const int i0 = blockIdx.x * kVecBlock + threadIdx.x;
+  const int stride = gridDim.x * kVecBlock;
+  double z0 = 0.0, p0 = 0.0;
+  const double den = sc[slot_den];     // written by the previous iteration
+  if (i0 < n) {
+    z0 = z[i0];
+    p0 = p[i0];
+  }
   double a = 0.0, b = 0.0, c = 0.0;
   for (int i = threadIdx.x; i < nb; i += kVecBlock) {
     a += rz_part[i];
@@ -333,9 +359,9 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_p_red(
     }
   }
   __syncthreads();
-  const double beta = (tot[0] - (flex ? tot[1] : 0.0)) / sc[slot_den];
-  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n; i += gridDim.x * kVecBlock)
-    p[i] = z[i] + beta * p[i];
+  const double beta = (tot[0] - (flex ? tot[1] : 0.0)) / den;
+  if (i0 < n) p[i0] = z0 + beta * p0;
+  for (int i = i0 + stride; i < n; i += stride) p[i] = z[i] + beta * p[i];
 }
 
 void launch_pcg_update_p_red(double* p, const double* z, const double* rz_part,
