@@ -318,3 +318,43 @@ def test_w_cycle_pcg_graph_equals_direct_and_batch_rejects_it():
     o = simpgmg.default_options(*dims, n_levels=3, cycle_gamma=2)
     with pytest.raises(simpgmg.SimpGmgError, match="cycle_gamma"):
         simpgmg.setup_batch([o], [t64(rho)])
+
+
+def test_degenerate_and_edge_cases():
+    """The smallest hierarchy (2x2x2 elements, 2 levels: one coarse element)
+    against the oracle; a mesh that cannot be coarsened is rejected; maxit 0
+    returns x0 untouched; a start at the exact solution converges at
+    iteration 0."""
+    from paper_2604_26441_amd import simpgmg
+    dims = (2, 2, 2)
+    rho = np.random.default_rng(21).uniform(0.2, 1.0, np.prod(dims))
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    f = workloads.edge_load(dims)
+    E = mesh.simp_modulus(rho, 3)
+    K = mesh.assemble(dims, E, fixed=fixed)
+    oh = multigrid.build(dims, E, fixed, multigrid.Options(n_levels=2))
+    h = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, n_levels=2, fine_prec="f64"),
+                                t64(rho), lambda_override=[oh.levels[0].lam])
+    r = workloads.random_vector(fixed.size, 22, fixed)
+    z = t64(np.zeros_like(r))
+    simpgmg.vcycle(h, t64(r), z)
+    ref = multigrid.vcycle(oh, r)
+    assert rel_err(np64(z), ref, ref) < 1e-11
+    u = t64(np.zeros_like(f))
+    res = simpgmg.pcg_solve(h, t64(f), u, rtol=1e-10, maxit=100)
+    assert res["status"] == "converged"
+    assert krylov.true_rel_residual(lambda v: K @ v, f, np64(u)) < 1e-10
+    # maxit 0: the iterate is returned as given
+    x0 = workloads.random_vector(fixed.size, 23, fixed)
+    u0 = t64(x0)
+    res0 = simpgmg.pcg_solve(h, t64(f), u0, rtol=1e-10, maxit=0)
+    assert res0["status"] == "maxit" and res0["iters"] == 0
+    assert np.array_equal(np64(u0), x0)
+    # a start at the solution passes at iteration 0
+    ue = np64(u).copy()
+    u1 = t64(ue)
+    res1 = simpgmg.pcg_solve(h, t64(f), u1, rtol=1e-8, maxit=100)
+    assert res1["status"] == "converged" and res1["iters"] == 0
+    assert np.array_equal(np64(u1), ue)
+    with pytest.raises(simpgmg.SimpGmgError):
+        simpgmg.setup_hierarchy(simpgmg.default_options(1, 1, 1, n_levels=2), t64(np.ones(1)))
