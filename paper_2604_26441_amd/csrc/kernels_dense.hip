@@ -125,21 +125,44 @@ __global__ __launch_bounds__(64) void k_gj_pivot(double* __restrict__ A, int n, 
 }
 
 // A_KJ <- Q A_KJ for every column j outside the panel (Q staged in LDS).
-__global__ __launch_bounds__(64) void k_gj_rowpanel(double* __restrict__ A, int n, int k0, int nb,
-                                                    const double* __restrict__ Q) {
-  __shared__ double Qs[kNB * kNB];
-  for (int t = threadIdx.x; t < kNB * kNB; t += 64) Qs[t] = Q[t];
+__global__ __launch_bounds__(256) void k_gj_rowpanel(double* __restrict__ A, int n, int k0, int nb,
+                                                     const double* __restrict__ Q) {
+  // 64 columns per block: Q and the block's 64 x 64 piece of the panel rows
+  // are staged in LDS (Q zero-padded past nb), then each thread forms a
+  // 4 x 4 register tile (rows tr + 16 q, columns tc + 16 w) over the 64
+  // products in order
+  __shared__ double Qs[kNB][kNB + 1];
+  __shared__ double Vs[kNB][kNB + 1];
+  const int j0 = blockIdx.x * 64;
+  for (int e = threadIdx.x; e < kNB * kNB; e += 256) {
+    const int r = e / kNB, c = e % kNB, j = j0 + c;
+    Qs[r][c] = (r < nb && c < nb) ? Q[r * kNB + c] : 0.0;
+    Vs[r][c] = (r < nb && j < n) ? A[(size_t)(k0 + r) * n + j] : 0.0;
+  }
   __syncthreads();
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n || (j >= k0 && j < k0 + nb)) return;
-  double v[kNB];
+  const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
+  double acc[4][4] = {};
+  for (int t = 0; t < kNB; ++t) {
+    double a[4], b[4];
 #pragma unroll
-  for (int t = 0; t < kNB; ++t) v[t] = t < nb ? A[(size_t)(k0 + t) * n + j] : 0.0;
-  for (int r = 0; r < nb; ++r) {
-    double s = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      a[q] = Qs[tr + 16 * q][t];
+      b[q] = Vs[t][tc + 16 * q];
+    }
 #pragma unroll
-    for (int t = 0; t < kNB; ++t) s += Qs[r * kNB + t] * v[t];
-    A[(size_t)(k0 + r) * n + j] = s;
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int w = 0; w < 4; ++w) acc[q][w] += a[q] * b[w];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = tr + 16 * q;
+    if (r >= nb) continue;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int j = j0 + tc + 16 * w;
+      if (j < n && !(j >= k0 && j < k0 + nb)) A[(size_t)(k0 + r) * n + j] = acc[q][w];
+    }
   }
 }
 
@@ -213,7 +236,7 @@ int dense_spd_inverse(double* A, int n, double* scratch, int* d_flag, hipStream_
     const int nb = (n - k0) < kNB ? (n - k0) : kNB;
     k_gj_copy_col<<<div_up((long)n * kNB, 256), 256, 0, s>>>(A, n, k0, nb, C);
     k_gj_pivot<<<1, 64, 0, s>>>(A, n, k0, nb, Q, d_flag);
-    k_gj_rowpanel<<<div_up(n, 64), 64, 0, s>>>(A, n, k0, nb, Q);
+    k_gj_rowpanel<<<div_up(n, 64), 256, 0, s>>>(A, n, k0, nb, Q);
     dim3 grid(div_up(n, kUpdTile), div_up(n, kUpdTile));
     k_gj_update<<<grid, 256, 0, s>>>(A, n, k0, nb, C, Q);
   }
