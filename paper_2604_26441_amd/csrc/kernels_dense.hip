@@ -168,11 +168,14 @@ __global__ __launch_bounds__(256) void k_gj_rowpanel(double* __restrict__ A, int
 
 // Rank-nb update of all rows outside the panel: A_IJ -= C_I R_J with R_J =
 // A_KJ (new) for columns outside the panel and R_J = -Q for the panel's own
-// columns, which receive -C_I Q (stored, not subtracted).  A 128 x 128 output
-// tile per 256-thread block, 8 x 8 outputs per thread (rows tr + 16q,
-// columns tc + 16w), the K dimension streamed through LDS in chunks of 16:
-// 16 LDS reads per 64 FMAs.
+// columns, which receive -C_I Q (stored, not subtracted).  A 128 x 128
+// output tile per 256-thread block on the FP64 matrix cores
+// (v_mfma_f64_16x16x4_f64): each wave owns a 64 x 64 quarter as 4 x 4 MFMA
+// tiles, K streamed through LDS in chunks of 16 (4 k-steps of 4).  Operand
+// layouts: A lane l = (row l % 16, k l / 16), B lane l = (k l / 16, column
+// l % 16); result register i of lane l = (row 4 i + l / 16, column l % 16).
 constexpr int kUpdTile = 128, kUpdK = 16;
+typedef double f64x4_gj __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, int n, int k0, int nb,
                                                    const double* __restrict__ C,
@@ -180,51 +183,82 @@ __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, int n
   __shared__ double Cs[kUpdTile][kUpdK + 1];
   __shared__ double Rs[kUpdK][kUpdTile + 1];
   const int i0 = blockIdx.y * kUpdTile, j0 = blockIdx.x * kUpdTile;
-  const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
-  double acc[8][8] = {};
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wr = (wv >> 1) * 64, wc = (wv & 1) * 64;
+  const int lr = lane & 15, lk = lane >> 4;
+  f64x4_gj acc[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) acc[q][w] = f64x4_gj{0.0, 0.0, 0.0, 0.0};
   for (int t0 = 0; t0 < nb; t0 += kUpdK) {
-    for (int e = threadIdx.x; e < kUpdTile * kUpdK; e += 256) {
+    // staging: every load at a clamped, valid address, all issued before
+    // the first LDS store, the value selected afterwards
+    constexpr int kPer = kUpdTile * kUpdK / 256;
+    double cv[kPer], av[kPer], qv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = threadIdx.x + 256 * u;
       const int r = e / kUpdK, c = e % kUpdK;
-      const int i = i0 + r, t = t0 + c;
-      Cs[r][c] = (i < n && t < nb) ? C[(size_t)i * kNB + t] : 0.0;
+      cv[u] = C[(size_t)min(i0 + r, n - 1) * kNB + min(t0 + c, nb - 1)];
+      const int rr = e / kUpdTile, cc = e % kUpdTile;
+      const int t = min(t0 + rr, nb - 1), j = min(j0 + cc, n - 1);
+      av[u] = A[(size_t)(k0 + t) * n + j];
+      qv[u] = Q[t * kNB + min(max(j - k0, 0), nb - 1)];
     }
-    for (int e = threadIdx.x; e < kUpdK * kUpdTile; e += 256) {
-      const int r = e / kUpdTile, c = e % kUpdTile;
-      const int t = t0 + r, j = j0 + c;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int r = e / kUpdK, c = e % kUpdK;
+      Cs[r][c] = (i0 + r < n && t0 + c < nb) ? cv[u] : 0.0;
+      const int rr = e / kUpdTile, cc = e % kUpdTile;
+      const int t = t0 + rr, j = j0 + cc;
       double v = 0.0;
-      if (t < nb && j < n) {
-        if (j >= k0 && j < k0 + nb) v = -Q[t * kNB + (j - k0)];   // A_IK <- -C Q
-        else v = A[(size_t)(k0 + t) * n + j];                     // A_KJ (new)
-      }
-      Rs[r][c] = v;
+      if (t < nb && j < n) v = (j >= k0 && j < k0 + nb) ? -qv[u] : av[u];   // -C Q | A_KJ (new)
+      Rs[rr][cc] = v;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int t = 0; t < kUpdK; ++t) {
-      double a[8], b[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        a[q] = Cs[tr + 16 * q][t];
-        b[q] = Rs[t][tc + 16 * q];
+    for (int kk = 0; kk < kUpdK; kk += 4) {
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = Cs[wr + 16 * q + lr][kk + lk];
+        b[q] = Rs[kk + lk][wc + 16 * q + lr];
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
+      for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int w = 0; w < 8; ++w) acc[q][w] = __builtin_fma(a[q], b[w], acc[q][w]);
+        for (int w = 0; w < 4; ++w)
+          acc[q][w] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[w], acc[q][w], 0, 0, 0);
     }
     __syncthreads();
   }
+  // read-modify-write of the tile: all old values are loaded first (at
+  // clamped, valid addresses), then the stores are masked
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int i = i0 + tr + 16 * q;
-    if (i >= n || (i >= k0 && i < k0 + nb)) continue;
+  for (int q = 0; q < 4; ++q) {
+    double old[4][4];
 #pragma unroll
-    for (int w = 0; w < 8; ++w) {
-      const int j = j0 + tc + 16 * w;
-      if (j >= n) continue;
-      double* dst = A + (size_t)i * n + j;
-      if (j >= k0 && j < k0 + nb) *dst = acc[q][w];
-      else *dst -= acc[q][w];
+    for (int ii = 0; ii < 4; ++ii) {
+      const int i = min(i0 + wr + 16 * q + 4 * ii + lk, n - 1);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int j = min(j0 + wc + 16 * w + lr, n - 1);
+        old[ii][w] = A[(size_t)i * n + j];
+      }
+    }
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int i = i0 + wr + 16 * q + 4 * ii + lk;
+      const bool row_ok = i < n && !(i >= k0 && i < k0 + nb);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int j = j0 + wc + 16 * w + lr;
+        if (!row_ok || j >= n) continue;
+        const bool panel_col = j >= k0 && j < k0 + nb;
+        A[(size_t)i * n + j] = panel_col ? acc[q][w][ii] : old[ii][w] - acc[q][w][ii];
+      }
     }
   }
 }
