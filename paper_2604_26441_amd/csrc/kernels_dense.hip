@@ -71,56 +71,61 @@ __global__ void k_gj_copy_col(const double* __restrict__ A, int n, int k0, int n
 }
 
 // Inverse of the nb x nb pivot block by in-place Gauss-Jordan (SPD: no
-// pivoting), one wave: lane r keeps row r in registers, rotated so that at
-// step p its register c holds column (p + c) mod 64 (the pivot column is
-// always register 0, every register index is a compile-time constant and
-// the step loop need not be unrolled).  At step p lane p publishes its row
-// in LDS (one wave: no barrier, only the LDS counter wait) and every lane
-// updates its row with it:
+// pivoting), four waves: lane r of wave w keeps columns 16w .. 16w + 15 of
+// row r in registers.  The 16 steps whose pivot column a wave owns are
+// unrolled, so every register index is a compile-time constant.  At step p
+// the owner wave publishes column p and lane p of every wave publishes its
+// part of row p in LDS; after a block barrier every lane updates its 16
+// entries:
 //   r == p : a_pc <- a_pc / a_pp (c != p),  a_pp <- 1 / a_pp
 //   r != p : a_rc <- a_rc - (a_rp / a_pp) a_pc (c != p),  a_rp <- -a_rp / a_pp
-// then rotates by one.  After 64 steps the rotation is back to the identity.
-// The block is zero-padded to 64 x 64 with a unit diagonal, so padded rows
-// and columns stay decoupled.
-__global__ __launch_bounds__(64) void k_gj_pivot(double* __restrict__ A, int n, int k0, int nb,
-                                                 double* __restrict__ Q, int* __restrict__ flag) {
-  __shared__ double row[kNB];
-  const int r = threadIdx.x;
-  double v[kNB];
+// (the same operations, in the same precision, as one lane per row would
+// do).  The block is zero-padded to 64 x 64 with a unit diagonal, so padded
+// rows and columns stay decoupled.
+__global__ __launch_bounds__(256) void k_gj_pivot(double* __restrict__ A, int n, int k0, int nb,
+                                                  double* __restrict__ Q, int* __restrict__ flag) {
+  __shared__ double colp[2][kNB];   // column p (double-buffered over steps)
+  __shared__ double rowp[2][kNB];   // row p
+  const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c0 = 16 * w;
+  double v[16];
 #pragma unroll
-  for (int c = 0; c < kNB; ++c)
-    v[c] = (r < nb && c < nb) ? A[(size_t)(k0 + r) * n + k0 + c] : (r == c ? 1.0 : 0.0);
-  bool bad = false;
-  for (int p = 0; p < kNB; ++p) {
-    if (r == p) {
-#pragma unroll
-      for (int c = 0; c < kNB; ++c) row[c] = v[c];
-    }
-    __builtin_amdgcn_s_waitcnt(0xc07f);              // lgkmcnt(0): the row is in LDS
-    __builtin_amdgcn_wave_barrier();
-    const double pv = row[0];
-    bad |= !(pv > 0.0);
-    const double inv = 1.0 / pv;
-    const bool me = r == p;
-    const double g = v[0] * inv;                      // a_rp / a_pp
-    double w[kNB];
-    w[0] = me ? inv : -g;
-#pragma unroll
-    for (int c = 1; c < kNB; ++c) {
-      const double rc = row[c];
-      w[c] = me ? rc * inv : __builtin_fma(-g, rc, v[c]);
-    }
-    __builtin_amdgcn_wave_barrier();                  // row is rewritten next step
-#pragma unroll
-    for (int c = 0; c < kNB; ++c) v[c] = w[(c + 1) % kNB];   // rotate by one column
+  for (int c = 0; c < 16; ++c) {
+    const int col = c0 + c;
+    v[c] = (r < nb && col < nb) ? A[(size_t)(k0 + r) * n + k0 + col] : (r == col ? 1.0 : 0.0);
   }
-  if (bad && r == 0) *flag = 1;
+  bool bad = false;
+  for (int pw = 0; pw < 4; ++pw) {
 #pragma unroll
-  for (int c = 0; c < kNB; ++c) {
-    const bool in = r < nb && c < nb;
+    for (int sp = 0; sp < 16; ++sp) {
+      const int p = 16 * pw + sp, buf = sp & 1;
+      if (w == pw) colp[buf][r] = v[sp];
+      if (r == p) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) rowp[buf][c0 + c] = v[c];
+      }
+      __syncthreads();
+      const double pv = colp[buf][p];
+      bad |= !(pv > 0.0);
+      const double inv = 1.0 / pv;
+      const bool me = r == p;
+      const double g = colp[buf][r] * inv;            // a_rp / a_pp
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const double rc = rowp[buf][c0 + c];
+        const double upd = me ? rc * inv : __builtin_fma(-g, rc, v[c]);
+        v[c] = (w == pw && c == sp) ? (me ? inv : -g) : upd;
+      }
+    }
+  }
+  if (bad && threadIdx.x == 0) *flag = 1;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int col = c0 + c;
+    const bool in = r < nb && col < nb;
     const double x = in ? v[c] : 0.0;
-    Q[r * kNB + c] = x;
-    if (in) A[(size_t)(k0 + r) * n + k0 + c] = x;
+    Q[r * kNB + col] = x;
+    if (in) A[(size_t)(k0 + r) * n + k0 + col] = x;
   }
 }
 
@@ -269,7 +274,7 @@ int dense_spd_inverse(double* A, int n, double* scratch, int* d_flag, hipStream_
   for (int k0 = 0; k0 < n; k0 += kNB) {
     const int nb = (n - k0) < kNB ? (n - k0) : kNB;
     k_gj_copy_col<<<div_up((long)n * kNB, 256), 256, 0, s>>>(A, n, k0, nb, C);
-    k_gj_pivot<<<1, 64, 0, s>>>(A, n, k0, nb, Q, d_flag);
+    k_gj_pivot<<<1, 256, 0, s>>>(A, n, k0, nb, Q, d_flag);
     k_gj_rowpanel<<<div_up(n, 64), 256, 0, s>>>(A, n, k0, nb, Q);
     dim3 grid(div_up(n, kUpdTile), div_up(n, kUpdTile));
     k_gj_update<<<grid, 256, 0, s>>>(A, n, k0, nb, C, Q);
