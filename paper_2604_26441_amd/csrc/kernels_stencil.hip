@@ -119,13 +119,67 @@ void launch_galerkin_l1(const Grid& fine, const Grid& coarse, const double* E, c
 }
 
 // Deeper Galerkin product K^{l+1} = M P^T K^l P M on stencils (Sec. 3.3).
-// Thread (I, o): sum over fine nodes i interpolating from I (<= 3 per axis)
-// and fine stencil neighbours j of i of w(i,I) w(j,J) K^l[i, j].  K^l is
-// stored masked, so only the coarse mask is applied here.
-__global__ __launch_bounds__(256) void k_galerkin_stencil(Grid f, Grid c,
-                                                          const double* __restrict__ Sf,
-                                                          const uint8_t* __restrict__ cfix,
-                                                          double* __restrict__ Sc) {
+// Thread (I, o) sums w(i,I) w(j,J) K^l[i, j] over the fine nodes i that
+// interpolate from I and their stencil neighbours j.  The weights factor over
+// the axes, so each axis contributes a 3 x 3 table of pair weights
+// w1d(i,I) w1d(j,J) for i = 2I + a - 1, j = i + b - 1 (zero where a node is
+// outside the grid or outside the support).  The loops over the z and y pairs
+// skip zero weights before any load.  K^l is stored masked, so only the coarse mask is applied here.
+__device__ inline double axis_pair_weight(int I, int J, int nf, int k) {
+  const int i = 2 * I + k / 3 - 1, j = i + k % 3 - 1;
+  return ((unsigned)i <= (unsigned)nf && (unsigned)j <= (unsigned)nf) ? w1d(i, I, nf) * w1d(j, J, nf)
+                                                                      : 0.0;
+}
+
+// Sum over the pairs of one thread.  Of the nine x pairs, only those with
+// i and j both in the supports of I and J = I + OX can carry weight (the
+// support of a coarse node J is fine nodes 2J-1 .. 2J+1): pairs {0, 1, 3} for
+// OX = -1, {1, .., 7} for OX = 0 and {5, 7, 8} for OX = +1.  Those are loaded
+// without branches so that their loads are in flight together; a pair whose
+// weight is zero at the grid's edge reads an entry inside the grid and adds
+// 0 times it (every stencil entry is written, and finite).
+template <int OX>
+__device__ inline void galerkin_pairs(const Grid& f, const double* __restrict__ Sf, int Ix,
+                                      int Iy, int Iz, int Jy, int Jz, double (&acc)[9]) {
+  constexpr unsigned kMask = OX < 0 ? 0x00Bu : (OX == 0 ? 0x0FEu : 0x1A0u);
+  double wx[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+    wx[k] = (kMask >> k) & 1u ? axis_pair_weight(Ix, Ix + OX, f.nx, k) : 0.0;
+  // fine x index of each pair, clamped into the grid: where the clamp moves
+  // it the pair's weight is zero, and the load only has to stay in bounds
+  int ix[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) ix[k] = min(max(2 * Ix + k / 3 - 1, 0), f.nx);
+  const size_t blk = (size_t)9 * f.Nn;       // distance between stencil blocks q, q+1
+  for (int kz = 0; kz < 9; ++kz) {
+    const double wz = axis_pair_weight(Iz, Jz, f.nz, kz);
+    if (wz == 0.0) continue;
+    const int iz = 2 * Iz + kz / 3 - 1;
+    for (int ky = 0; ky < 9; ++ky) {
+      const double wyz = axis_pair_weight(Iy, Jy, f.ny, ky) * wz;
+      if (wyz == 0.0) continue;
+      const int iy = 2 * Iy + ky / 3 - 1;
+      // block of (qx = -1, qy, qz) at fine node (0, iy, iz)
+      const int q0 = 3 * (ky % 3) + 9 * (kz % 3);
+      const double* row = Sf + (size_t)q0 * blk + f.Nx * (iy + f.Ny * iz);
+#pragma unroll
+      for (int kx = 0; kx < 9; ++kx) {
+        if (!((kMask >> kx) & 1u)) continue;
+        const double w = wx[kx] * wyz;
+        const double* src = row + (size_t)(kx % 3) * blk + ix[kx];
+#pragma unroll
+        for (int de = 0; de < 9; ++de) acc[de] += w * src[(size_t)de * f.Nn];
+      }
+    }
+  }
+}
+
+// Two waves per SIMD: the register budget lets the scheduler keep a whole
+// y pair's loads in flight (the kernel is bound by their latency).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void
+k_galerkin_stencil(Grid f, Grid c, const double* __restrict__ Sf, const uint8_t* __restrict__ cfix,
+                   double* __restrict__ Sc) {
   const int I = blockIdx.x * 256 + threadIdx.x;
   const int o = blockIdx.y;
   if (I >= c.Nn) return;
@@ -138,34 +192,12 @@ __global__ __launch_bounds__(256) void k_galerkin_stencil(Grid f, Grid c,
   const bool jok = (unsigned)Jx < (unsigned)c.Nx && (unsigned)Jy < (unsigned)c.Ny &&
                    (unsigned)Jz < (unsigned)c.Nz;
   if (jok) {
-    for (int iz = 2 * Iz - 1; iz <= 2 * Iz + 1; ++iz) {
-      if (iz < 0 || iz >= f.Nz) continue;
-      const double wz = w1d(iz, Iz, f.nz);
-      if (wz == 0.0) continue;
-      for (int iy = 2 * Iy - 1; iy <= 2 * Iy + 1; ++iy) {
-        if (iy < 0 || iy >= f.Ny) continue;
-        const double wy = w1d(iy, Iy, f.ny);
-        if (wy == 0.0) continue;
-        for (int ix = 2 * Ix - 1; ix <= 2 * Ix + 1; ++ix) {
-          if (ix < 0 || ix >= f.Nx) continue;
-          const double wx = w1d(ix, Ix, f.nx);
-          if (wx == 0.0) continue;
-          const double wi = wx * wy * wz;
-          const int i = ix + f.Nx * (iy + f.Ny * iz);
-          for (int q = 0; q < 27; ++q) {
-            const int jx = ix + q % 3 - 1, jy = iy + (q / 3) % 3 - 1, jz = iz + q / 9 - 1;
-            if ((unsigned)jx >= (unsigned)f.Nx || (unsigned)jy >= (unsigned)f.Ny ||
-                (unsigned)jz >= (unsigned)f.Nz)
-              continue;
-            const double wj = w1d(jx, Jx, f.nx) * w1d(jy, Jy, f.ny) * w1d(jz, Jz, f.nz);
-            if (wj == 0.0) continue;
-            const double w = wi * wj;
-#pragma unroll
-            for (int de = 0; de < 9; ++de) acc[de] += w * Sf[(size_t)(q * 9 + de) * f.Nn + i];
-          }
-        }
-      }
-    }
+    if (ox < 0)
+      galerkin_pairs<-1>(f, Sf, Ix, Iy, Iz, Jy, Jz, acc);
+    else if (ox == 0)
+      galerkin_pairs<0>(f, Sf, Ix, Iy, Iz, Jy, Jz, acc);
+    else
+      galerkin_pairs<1>(f, Sf, Ix, Iy, Iz, Jy, Jz, acc);
   }
   const unsigned fI = cfix[I];
   const unsigned fJ = jok ? cfix[Jx + c.Nx * (Jy + c.Ny * Jz)] : 7u;
