@@ -249,19 +249,22 @@ void launch_stencil_to_f32(const double* S, float* S32, size_t n, hipStream_t s)
 //
 // Plane-split form, for small levels (level 2 of an 80^3 mesh has 9,261
 // nodes) that need many waves to cover memory latency: one thread per (node,
-// output component, stencil plane oz), wave = component + 3 plane; the nine
-// offsets of a plane are read unconditionally (offsets outside the grid read
-// the node itself, a valid address, and add zero) and the three plane
-// partials are added in LDS in a fixed order.
+// output component, stencil plane oz).  A block of three waves is one
+// component d of 64 nodes, wave = plane, so the grid has three blocks per
+// node tile (enough to reach every CU on such levels); the nine offsets of a
+// plane are read unconditionally (offsets outside the grid read the node
+// itself, a valid address, and add zero) and the three plane partials are
+// added in LDS in a fixed order.
 template <typename T>
-__global__ __launch_bounds__(576) void k_stencil_apply_c(Grid g, const T* __restrict__ S,
+__global__ __launch_bounds__(192) void k_stencil_apply_c(Grid g, const T* __restrict__ S,
                                                          const T* __restrict__ u,
                                                          const uint8_t* __restrict__ fixn,
                                                          Epi<T> ep) {
-  __shared__ double part[3][3][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int d = w % 3, pz = w / 3;
-  const int node0 = xcd_block(blockIdx.x, gridDim.x) * 64 + lane;
+  __shared__ double part[3][64];
+  const int lane = threadIdx.x & 63, pz = threadIdx.x >> 6;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int d = lb % 3;
+  const int node0 = (lb / 3) * 64 + lane;
   const bool in = node0 < g.Nn;
   // lanes past the grid work on the last node and store nothing
   const int node = in ? node0 : g.Nn - 1;
@@ -299,12 +302,12 @@ __global__ __launch_bounds__(576) void k_stencil_apply_c(Grid g, const T* __rest
       }
       acc += ok ? v : (T)0;
     }
-    part[pz][d][lane] = (double)acc;
+    part[pz][lane] = (double)acc;
   }
   __syncthreads();
   double dot = 0.0;
   if (epi) {
-    const double y = (part[0][d][lane] + part[1][d][lane]) + part[2][d][lane];
+    const double y = (part[0][lane] + part[1][lane]) + part[2][lane];
     dot = epilogue1(ep, dof, (fx >> d) & 1u, xown, y, ein);
   }
   if (ep.want_dot) {
@@ -406,17 +409,20 @@ __global__ __launch_bounds__(192) void k_stencil_apply_s(
 // levels with fewer nodes use the plane-split form
 constexpr int kStencilSplitNodes = 40000;
 
-size_t stencil_apply_blocks(const Grid& g) { return div_up(g.Nn, 64); }
+// the larger of the two forms' grids (the plane-split form runs three blocks
+// per 64-node tile)
+size_t stencil_apply_blocks(const Grid& g) { return 3 * div_up(g.Nn, 64); }
 
 template <typename T>
 void launch_stencil_apply(const Grid& g, const T* S, const T* u, const uint8_t* fixn,
                           const Epi<T>& ep, int form, hipStream_t s) {
-  const int nb = (int)stencil_apply_blocks(g);
+  const int tiles = (int)div_up(g.Nn, 64);
   const bool staged = form == 1 || (form == 0 && g.Nn >= kStencilSplitNodes);
+  const int nb = staged ? tiles : 3 * tiles;
   if (staged)
     k_stencil_apply_s<T><<<nb, 192, 0, s>>>(g, S, u, fixn, ep);
   else
-    k_stencil_apply_c<T><<<nb, 576, 0, s>>>(g, S, u, fixn, ep);
+    k_stencil_apply_c<T><<<nb, 192, 0, s>>>(g, S, u, fixn, ep);
   if (ep.want_dot && ep.dot_out) launch_finalize(ep.ws, nb, 1, ep.dot_out, s);
 }
 template void launch_stencil_apply<double>(const Grid&, const double*, const double*,

@@ -767,8 +767,10 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
   // block per 256 nodes; vector reductions use at most 2 x 1024 slots)
   // (the MFMA kernel's largest grid is its smallest tile shape: 4 rows, 1 plane)
   // (+ 4096: the PCG iteration keeps the r.r partials after the K p ones)
+  // (a Galerkin level's apply with a dot: at most three blocks per 64 nodes)
   const size_t npart = std::max({kMinPartials, (size_t)div_up(g0.Nn, 256) + 2048,
-                                 apply_fine_mfma_blocks(g0, 4, 1) + 4096});
+                                 apply_fine_mfma_blocks(g0, 4, 1) + 4096,
+                                 h->L > 1 ? stencil_apply_blocks(h->lev[1].g) : (size_t)0});
   h->npart = npart;
   if ((rc = dalloc_t(h, &h->ws.partials, npart)) || (rc = dalloc_t(h, &h->ws.counter, 1)) ||
       (rc = dalloc_t(h, &h->sc, SC_COUNT)) || (rc = dalloc_t(h, &h->d_flag, 1)))
