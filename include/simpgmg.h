@@ -79,7 +79,7 @@ typedef enum {
 } sgmg_status;
 
 typedef struct {
-  int nx, ny, nz;            /* elements per axis, each >= 1                         */
+  int nx, ny, nz;            /* elements per axis, each >= 2 (SGMG_EINVAL otherwise) */
   double nu, E0, Emin, penal;/* Poisson ratio 0.3, E0 1, Emin 1e-9, SIMP penalty p   */
   int input_is_modulus;      /* 0: the setup array is rho (SIMP map applied);
                                 1: it is E_e directly                                */

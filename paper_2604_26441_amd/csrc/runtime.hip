@@ -572,7 +572,8 @@ int vcycle_full(const sgmg_hierarchy* h, const double* r, double* z, hipStream_t
 
 int validate(const sgmg_options* o) {
   if (!o) { set_error("options is NULL"); return SGMG_EINVAL; }
-  if (o->nx < 1 || o->ny < 1 || o->nz < 1) { set_error("mesh dims must be >= 1"); return SGMG_EINVAL; }
+  // every hierarchy has at least two levels, so each axis must coarsen once
+  if (o->nx < 2 || o->ny < 2 || o->nz < 2) { set_error("mesh dims must be >= 2"); return SGMG_EINVAL; }
   if ((long)(o->nx + 1) * (o->ny + 1) * (o->nz + 1) * 3 > 0x7fffffffL) {
     set_error("mesh too large for 32-bit DOF indexing");
     return SGMG_EINVAL;
@@ -671,7 +672,7 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
     if (f.nx / 2 < 1 || f.ny / 2 < 1 || f.nz / 2 < 1) break;
     grids.push_back(make_grid(f.nx / 2, f.ny / 2, f.nz / 2));
   }
-  if (opts->n_levels && (int)grids.size() < opts->n_levels) {
+  if ((int)grids.size() < std::max(2, opts->n_levels)) {
     set_error("mesh cannot be coarsened to the requested number of levels");
     return fail(SGMG_EINVAL);
   }
@@ -1596,10 +1597,12 @@ int sgmg_autotune(sgmg_hierarchy* h, int* shape_out, void* stream) {
   hipStreamSynchronize(s);
   hipFree(u);
   hipFree(y);
-  // captured iteration graphs hold the old launch shape
+  // captured iteration graphs hold the old launch shape: capture them again
+  // here, so that no later solve has to capture
   for (auto& row : h->iter_graph)
     for (auto& g : row)
       if (g) { hipGraphExecDestroy(g); g = nullptr; }
+  if (!rc) rc = capture_vcycle_graphs(h, s);
   return rc;
 }
 
@@ -1967,6 +1970,10 @@ int sgmg_pcg_solve_batch_concurrent(sgmg_batch* b, int nitems, const int* item_s
   });
   int dev = 0;
   SGMG_HIP(hipGetDevice(&dev));
+  // Every system's iteration graphs are captured here, on the calling
+  // thread, before any worker starts (sgmg_set_launch_shape drops them): the
+  // workers only launch graphs and never capture concurrently.
+  for (int k : order) TRY(capture_vcycle_graphs(b->hs[k], as_stream(stream)));
   SGMG_HIP(hipStreamSynchronize(as_stream(stream)));   // the inputs are ready
   std::atomic<int> next{0};
   std::atomic<int> failed{0};

@@ -51,3 +51,21 @@ def test_struct_layout_matches_header(tmp_path):
     vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     assert vals == [ctypes.sizeof(simpgmg.Options), simpgmg.Options.seed.offset,
                     simpgmg.Options.use_graphs.offset, ctypes.sizeof(simpgmg.SolveInfo)]
+
+
+def test_setup_rejects_uncoarsenable_meshes_before_device_work():
+    """A mesh with an axis of one element has no coarse level: setup must
+    return SGMG_EINVAL from argument checking alone (no allocation, no
+    kernel), also when the depth is automatic (n_levels = 0).  The element
+    array pointer is never dereferenced on this path."""
+    from paper_2604_26441_amd import simpgmg
+    lib = ctypes.CDLL(simpgmg.library_path())
+    lib.sgmg_setup_hierarchy.restype = ctypes.c_int
+    lib.sgmg_last_error.restype = ctypes.c_char_p
+    for dims, L in [((1, 4, 4), 0), ((4, 1, 4), 0), ((4, 4, 1), 2), ((1, 1, 1), 4)]:
+        o = simpgmg.default_options(*dims, n_levels=L)
+        h = ctypes.c_void_p()
+        rc = lib.sgmg_setup_hierarchy(ctypes.byref(o), ctypes.c_void_p(64), None, None,
+                                      ctypes.byref(h))
+        assert rc == -1 and not h.value
+        assert b"dims" in lib.sgmg_last_error()

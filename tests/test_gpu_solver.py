@@ -183,23 +183,68 @@ def test_failure_statuses():
 
 
 def test_bf16_smoother_solve_reaches_fp64_tolerance():
-    """BF16 fine smoothing inside an FP64 outer PCG still meets the FP64 true
-    residual (flexible beta); compliance within 1e-4 of the FP64 solve."""
+    """BF16 fine smoothing inside an FP64 outer PCG (flexible beta) still meets
+    the FP64 true residual, judged by the oracle's K, and its compliance is
+    within 1e-4 of the oracle's FP64 PCG-GMG solve to 1e-10 (BF16 tolerance
+    of the precision study, Sec. 4.2 M7)."""
     from paper_2604_26441_amd import simpgmg
     dims = (24, 12, 12)
     rho = workloads.uniform_rho(dims)
     f = workloads.edge_load(dims)
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    E = mesh.simp_modulus(rho, 3)
+    K = mesh.assemble(dims, E, fixed=fixed)
+    oh = multigrid.build(dims, E, fixed, multigrid.Options(n_levels=3))
+    xo, st, _, _ = krylov.pcg(lambda v: K @ v, f, lambda r: multigrid.vcycle(oh, r), rtol=1e-10,
+                              maxit=200)
+    assert st == krylov.CONVERGED
     o = simpgmg.default_options(*dims, n_levels=3, fine_prec="bf16", flexible_beta=1)
     h = simpgmg.setup_hierarchy(o, t64(rho))
     u = t64(np.zeros_like(f))
     res = simpgmg.pcg_solve(h, t64(f), u, rtol=1e-6, maxit=200)
-    assert res["status"] == "converged" and res["rel_res_true"] < 1e-6
-    o64 = simpgmg.default_options(*dims, n_levels=3, fine_prec="f64")
-    h64 = simpgmg.setup_hierarchy(o64, t64(rho))
-    u64 = t64(np.zeros_like(f))
-    simpgmg.pcg_solve(h64, t64(f), u64, rtol=1e-10, maxit=200)
-    c, c64 = f @ np64(u), f @ np64(u64)
-    assert abs(c - c64) <= 1e-4 * abs(c64)
+    x = np64(u)
+    assert res["status"] == "converged"
+    assert krylov.true_rel_residual(lambda v: K @ v, f, x) < 1e-6
+    assert abs(f @ x - f @ xo) <= 1e-4 * abs(f @ xo)
+
+
+@pytest.mark.parametrize("use_graphs", [0, 1])
+@pytest.mark.parametrize("window", [3, 5])
+def test_stagnation_matches_oracle(window, use_graphs):
+    """Stagnation class of Sec. 3.6 (window rule, reading): Jacobi-PCG on the
+    uniform 16x8x8 cantilever reaches a residual minimum and then rises, so
+    the window trips; status, iteration and history equal the oracle's (the
+    rule's margin there is several percent, far above rounding)."""
+    from paper_2604_26441_amd import simpgmg
+    dims = (16, 8, 8)
+    rho = workloads.uniform_rho(dims)
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    f = workloads.edge_load(dims)
+    E = mesh.simp_modulus(rho, 3)
+    K = mesh.assemble(dims, E, fixed=fixed)
+    oh = multigrid.build(dims, E, fixed, multigrid.Options(n_levels=3))
+    _, st, it_o, hist_o = krylov.pcg(lambda v: K @ v, f, lambda r: oh.levels[0].dinv * r,
+                                     rtol=1e-12, maxit=200, stag_window=window)
+    assert st == krylov.STAGNATED
+    o = simpgmg.default_options(*dims, n_levels=3, fine_prec="f64", stag_window=window,
+                                use_graphs=use_graphs)
+    h = simpgmg.setup_hierarchy(o, t64(rho))
+    for _ in range(2):
+        u = t64(np.zeros_like(f))
+        res = simpgmg.pcg_solve(h, t64(f), u, rtol=1e-12, maxit=200, precond=1, history_cap=256)
+        assert res["status"] == "stagnated" and res["iters"] == it_o
+        np.testing.assert_allclose(res["history"], hist_o, rtol=1e-8)
+
+
+def test_setup_rejects_meshes_that_cannot_coarsen():
+    """Every hierarchy has at least two levels: an axis of one element is
+    rejected before any device work, also when the depth is chosen
+    automatically."""
+    from paper_2604_26441_amd import simpgmg
+    for dims, L in [((1, 4, 4), 0), ((4, 1, 4), 0), ((4, 4, 1), 2), ((1, 4, 4), 4)]:
+        o = simpgmg.default_options(*dims, n_levels=L)
+        with pytest.raises(simpgmg.SimpGmgError, match="dims"):
+            simpgmg.setup_hierarchy(o, t64(np.full(int(np.prod(dims)), 0.5)))
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
