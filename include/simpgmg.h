@@ -44,6 +44,7 @@
 #ifndef SIMPGMG_H
 #define SIMPGMG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -120,6 +121,21 @@ typedef struct {
                                 of >= 40000 nodes, the plane-split form below),
                                 1 the LDS-staged form on every level, 2 the
                                 plane-split form on every level                   */
+  int bf16_guard;            /* 1 (default): a PCG solve with the V-cycle and
+                                fine_prec BF16 watches its progress (Sec. 3.5:
+                                BF16 is used only under a guard, and Sec. 3.6:
+                                acceptance is on the FP64 true residual); if a
+                                step fails (p.q <= 0 or non-finite), r.z <= 0 or
+                                non-finite, or the relative residual has not
+                                dropped by guard_drop over the last guard_window
+                                iterations, the level-0 smoothing switches to
+                                BF16X3 (FP32-accurate) for the rest of the solve
+                                and the recurrence restarts from the current
+                                iterate with its FP64 true residual; the
+                                hierarchy is BF16 again after the solve.
+                                0: no guard                                       */
+  int guard_window;          /* iterations of the progress test (50)              */
+  double guard_drop;         /* required residual reduction over the window (10)  */
 } sgmg_options;
 
 typedef struct {
@@ -131,6 +147,8 @@ typedef struct {
                                 NULL; entry k = recursive ||r_k|| / ||f||            */
   int history_cap;
   double solve_ms;           /* wall time of the solve on the stream (HIP events)    */
+  int fallback_iter;         /* iteration at which the BF16 guard switched the
+                                smoothing to BF16X3, or -1                           */
 } sgmg_solve_info;
 
 typedef struct sgmg_hierarchy sgmg_hierarchy;
@@ -138,7 +156,8 @@ typedef struct sgmg_hierarchy sgmg_hierarchy;
 /* Fills *o with the paper's defaults (Table repro_defaults) for an nx*ny*nz
  * mesh: nu 0.3, E0 1, Emin 1e-9, p 3, 4 levels, Chebyshev degree 2, 2 coarse
  * sweeps, alpha 1/30, omega cap 0.5, 20/10 power iterations, level-0 F32,
- * level-1 F64, dense_max 5000, seed 0, lambda_safety 1.3. */
+ * level-1 F64, dense_max 5000, seed 0, lambda_safety 1.3, BF16 guard on (window
+ * 50, drop 10). */
 void sgmg_default_options(sgmg_options* o, int nx, int ny, int nz);
 
 /* Builds the hierarchy for one frozen modulus field (Sec. 3.3, 3.5).
@@ -306,6 +325,17 @@ int sgmg_pcg_solve_batch_concurrent(sgmg_batch* b, int nitems, const int* item_s
 sgmg_hierarchy* sgmg_batch_hierarchy(sgmg_batch* b, int s);
 /* Block size chosen by the autotuner (0 before the first solve). */
 int sgmg_batch_block_size(const sgmg_batch* b);
+/* Work memory of one batch item (host arithmetic only, no device work): for
+ * a hierarchy of L levels (2..8) with level_dofs[l] full-DOF vector lengths
+ * and nL free coarsest DOFs, the byte offset and size of each sub-buffer (in
+ * order: r, z, p, q, t in FP64 and b, d, r, x[0], x[1] in FP32 on level 0;
+ * b, x[0], x[1], r in FP64 on each level 1..L-1; the coarsest right-hand
+ * side, max(nL, 1) doubles) into offsets and sizes (10 + 4 (L - 1) + 1
+ * entries each, either may be NULL); every offset is a multiple of 256.
+ * Returns the allocation size the batched solve reserves per item, or 0 for
+ * invalid arguments. */
+size_t sgmg_batch_item_layout(int L, const int* level_dofs, int nL, size_t* offsets,
+                              size_t* sizes);
 void sgmg_batch_destroy(sgmg_batch* b);
 
 /* ---- Learned warm start (extension: a 3D U-Net predicts the initial guess) ----

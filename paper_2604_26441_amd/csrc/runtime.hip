@@ -589,6 +589,10 @@ int validate(const sgmg_options* o) {
   if (!(o->lambda_safety > 0.0)) { set_error("lambda_safety must be > 0"); return SGMG_EINVAL; }
   if (o->cycle_gamma != 1 && o->cycle_gamma != 2) { set_error("cycle_gamma must be 1 or 2"); return SGMG_EINVAL; }
   if (o->stencil_form < 0 || o->stencil_form > 2) { set_error("stencil_form must be 0, 1 or 2"); return SGMG_EINVAL; }
+  if (o->bf16_guard && (o->guard_window < 1 || !(o->guard_drop >= 1.0))) {
+    set_error("bf16_guard needs guard_window >= 1 and guard_drop >= 1");
+    return SGMG_EINVAL;
+  }
   return 0;
 }
 
@@ -626,6 +630,9 @@ void sgmg_default_options(sgmg_options* o, int nx, int ny, int nz) {
   o->use_graphs = 1;
   o->cycle_gamma = 1;
   o->stencil_form = 0;
+  o->bf16_guard = 1;
+  o->guard_window = 50;
+  o->guard_drop = 10.0;
 }
 
 void sgmg_destroy(sgmg_hierarchy* h) {
@@ -1074,6 +1081,35 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
     std::atomic_thread_fence(std::memory_order_acquire);
     return 0;
   };
+  // Guarded BF16 (Sec. 3.5, 3.6): on a failed step, a non-positive or
+  // non-finite r.z, or too little progress over guard_window iterations, the
+  // level-0 smoothing switches to the FP32-accurate BF16X3 split and the
+  // recurrence restarts (beta = 0) from the current iterate and its FP64
+  // true residual.  The captured V-cycle graphs hold the BF16 kernels, so
+  // they are dropped (and captured again when next launched).
+  const bool guard = h->o.bf16_guard && precond == 2 && h->o.fine_prec == SGMG_BF16;
+  int fallback_it = -1;
+  auto drop_graphs = [&]() -> int {
+    SGMG_HIP(hipStreamSynchronize(s));
+    for (auto& g : h->iter_graph[2])
+      if (g) { hipGraphExecDestroy(g); g = nullptr; }
+    return 0;
+  };
+  auto fallback = [&](int it, int nslot, double& rz) -> int {
+    TRY(drop_graphs());
+    h->o.fine_prec = SGMG_BF16X3;
+    fallback_it = it;
+    TRY(K64(xcur, h->tmp, nullptr));
+    launch_residual(f, h->tmp, h->tmp, n, h->ws, sc + SC_TRUE, s);
+    launch_copy(h->tmp, h->r, n, s);
+    TRY(precondition(h->r, h->z));
+    launch_pcg_dot_rz(h->r, h->z, nullptr, n, h->ws, sc + nslot, s);
+    launch_copy(h->z, h->p, n, s);
+    TRY(readsc());
+    rz = hs[nslot];
+    rel = std::sqrt(hs[SC_TRUE]) / nf;
+    return 0;
+  };
   hipEvent_t e_pro = nullptr;
   SGMG_HIP(hipEventCreateWithFlags(&e_pro, hipEventDisableTiming));
   launch_copy(u, xcur, n, s);
@@ -1132,13 +1168,23 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
       double* xin;
       pcg_iterates(h, slot, &xin, &xcur);     // a failed step copies x_{it-1} here
       const double pq = hi[SC_PQ];
-      if (!std::isfinite(pq)) { status = SGMG_NONFINITE; iters = it - 1; break; }
-      if (pq <= 0.0) { status = SGMG_BREAKDOWN; iters = it - 1; break; }
+      const bool can_fall = guard && fallback_it < 0;
+      // a failed step leaves x_it = x_{it-1} (the update kernel skips it)
+      const bool step_failed = !std::isfinite(pq) || pq <= 0.0;
+      if (step_failed && !can_fall) {
+        status = std::isfinite(pq) ? SGMG_BREAKDOWN : SGMG_NONFINITE;
+        iters = it - 1;
+        break;
+      }
       iters = it;
-      rel = std::sqrt(hi[SC_RR]) / nf;
-      if (!std::isfinite(rel)) { hist.push_back(rel); status = SGMG_NONFINITE; break; }
       double rz = hi[nslot];
-      if (rel < rtol) {
+      if (!step_failed) rel = std::sqrt(hi[SC_RR]) / nf;
+      if (!step_failed && !std::isfinite(rel) && !can_fall) {
+        hist.push_back(rel);
+        status = SGMG_NONFINITE;
+        break;
+      }
+      if (!step_failed && rel < rtol) {
         // (queued after a look-ahead iteration, which touches neither x_it
         // nor tmp)
         if ((rc = K64(xcur, h->tmp, nullptr))) break;
@@ -1158,6 +1204,15 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
         rz = hs[nslot];
         rel = rt;
       }
+      if (can_fall) {
+        bool trip = step_failed || !std::isfinite(rel) || !std::isfinite(rz) || rz <= 0.0;
+        const int gw = h->o.guard_window;
+        if (!trip && it >= gw) trip = !(rel * h->o.guard_drop <= hist[it - gw]);
+        if (trip) {
+          if ((rc = fallback(it, nslot, rz))) break;
+          queued = false;
+        }
+      }
       hist.push_back(rel);
       const int w = h->o.stag_window;
       if (w > 0 && it >= w) {
@@ -1172,6 +1227,11 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
     }
   } while (0);
   hipEventDestroy(e_pro);
+  if (fallback_it >= 0) {            // the hierarchy is BF16 again for later calls
+    const int rc2 = drop_graphs();
+    h->o.fine_prec = SGMG_BF16;
+    if (!rc) rc = rc2;
+  }
   if (rc) {
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -1196,12 +1256,14 @@ int sgmg_pcg_solve(sgmg_hierarchy* h, int precond, const double* f, double* u, d
     info->rel_res_true = rel_true;
     info->rel_res_recur = rel;
     info->solve_ms = ms;
+    info->fallback_iter = fallback_it;
     if (info->history && info->history_cap > 0) {
       const int m = std::min<int>(info->history_cap, (int)hist.size());
       for (int i = 0; i < m; ++i) info->history[i] = hist[i];
       for (int i = m; i < info->history_cap; ++i) info->history[i] = 0.0;
     }
   }
+  if (fallback_it >= 0) TRY(capture_vcycle_graphs(h, s));
   return 0;
 }
 
@@ -1370,6 +1432,7 @@ done:
     info->rel_res_true = rel_true;
     info->rel_res_recur = rel;
     info->solve_ms = ms;
+    info->fallback_iter = -1;
     if (info->history && info->history_cap > 0) {
       const int mm = std::min<int>(info->history_cap, (int)hist.size());
       for (int i = 0; i < mm; ++i) info->history[i] = hist[i];
@@ -1726,6 +1789,10 @@ BSys make_bsys(const sgmg_hierarchy* h) {
   return S;
 }
 
+// Sub-buffers of one batch item's work memory (see sgmg_batch_item_layout).
+constexpr int kMaxLevels = 8;
+constexpr int kItemBufs = 10 + 4 * (kMaxLevels - 1) + 1;
+
 // (Re)allocates the work vectors when the item set changes.
 int batch_prepare_items(sgmg_batch* b, int nitems, const int* item_sys, hipStream_t s) {
   std::vector<int> key(item_sys, item_sys + nitems);
@@ -1744,34 +1811,29 @@ int batch_prepare_items(sgmg_batch* b, int nitems, const int* item_sys, hipStrea
     const sgmg_hierarchy* h = b->hs[sys];
     BItem& I = b->h_items[k];
     I.sys = sys;
-    const size_t n0 = h->lev[0].g.n;
-    // every sub-buffer starts on a 256-byte boundary: size each one rounded
-    auto rounded = [](size_t nbytes) { return (nbytes + 255) & ~(size_t)255; };
-    size_t bytes = 5 * rounded(n0 * sizeof(double)) + 5 * rounded(n0 * sizeof(float));
-    for (int l = 1; l < h->L; ++l) bytes += 4 * rounded((size_t)h->lev[l].g.n * sizeof(double));
-    bytes += rounded((size_t)std::max(h->nL, 1) * sizeof(double));
+    int ndofs[kMaxLevels];
+    for (int l = 0; l < h->L; ++l) ndofs[l] = h->lev[l].g.n;
+    size_t off[kItemBufs], sz[kItemBufs];
+    const size_t bytes = sgmg_batch_item_layout(h->L, ndofs, h->nL, off, sz);
+    if (!bytes) { set_error("batch item layout: bad level sizes"); return SGMG_EINVAL; }
     void* mem = nullptr;
     if (hipMalloc(&mem, bytes) != hipSuccess) { set_error("batch work allocation failed"); return SGMG_ENOMEM; }
     b->item_mem.push_back(mem);
     SGMG_HIP(hipMemsetAsync(mem, 0, bytes, s));
     char* c = (char*)mem;
-    auto take = [&](size_t nbytes) { char* r = c; c += rounded(nbytes); return (void*)r; };
-    I.r = (double*)take(n0 * 8); I.z = (double*)take(n0 * 8); I.p = (double*)take(n0 * 8);
-    I.q = (double*)take(n0 * 8); I.t = (double*)take(n0 * 8);
-    I.b0 = (float*)take(n0 * 4); I.d0 = (float*)take(n0 * 4); I.r0 = (float*)take(n0 * 4);
-    I.x0[0] = (float*)take(n0 * 4); I.x0[1] = (float*)take(n0 * 4);
+    int k2 = 0;
+    auto take = [&]() { return (void*)(c + off[k2++]); };
+    I.r = (double*)take(); I.z = (double*)take(); I.p = (double*)take();
+    I.q = (double*)take(); I.t = (double*)take();
+    I.b0 = (float*)take(); I.d0 = (float*)take(); I.r0 = (float*)take();
+    I.x0[0] = (float*)take(); I.x0[1] = (float*)take();
     for (int l = 1; l < h->L; ++l) {
-      const size_t nl = h->lev[l].g.n;
-      I.lb[l] = (double*)take(nl * 8);
-      I.lx[l][0] = (double*)take(nl * 8);
-      I.lx[l][1] = (double*)take(nl * 8);
-      I.lr[l] = (double*)take(nl * 8);
+      I.lb[l] = (double*)take();
+      I.lx[l][0] = (double*)take();
+      I.lx[l][1] = (double*)take();
+      I.lr[l] = (double*)take();
     }
-    I.rc = (double*)take((size_t)std::max(h->nL, 1) * 8);
-    if ((size_t)(c - (char*)mem) > bytes) {
-      set_error("batch work layout exceeds its allocation");
-      return SGMG_EINVAL;
-    }
+    I.rc = (double*)take();
   }
   SGMG_HIP(hipMalloc(&b->d_items, nitems * sizeof(BItem)));
   SGMG_HIP(hipMalloc(&b->d_out, nitems * sizeof(BOut)));
@@ -1862,6 +1924,30 @@ sgmg_hierarchy* sgmg_batch_hierarchy(sgmg_batch* b, int sys) {
 
 int sgmg_batch_block_size(const sgmg_batch* b) { return b ? b->bs : 0; }
 
+size_t sgmg_batch_item_layout(int L, const int* level_dofs, int nL, size_t* offsets,
+                              size_t* sizes) {
+  if (L < 2 || L > kMaxLevels || !level_dofs) return 0;
+  for (int l = 0; l < L; ++l)
+    if (level_dofs[l] < 1) return 0;
+  // every sub-buffer starts on a 256-byte boundary: each one's size rounded
+  auto rounded = [](size_t nbytes) { return (nbytes + 255) & ~(size_t)255; };
+  size_t at = 0;
+  int k = 0;
+  auto take = [&](size_t nbytes) {
+    if (offsets) offsets[k] = at;
+    if (sizes) sizes[k] = nbytes;
+    ++k;
+    at += rounded(nbytes);
+  };
+  const size_t n0 = (size_t)level_dofs[0];
+  for (int i = 0; i < 5; ++i) take(n0 * sizeof(double));    // r, z, p, q, t
+  for (int i = 0; i < 5; ++i) take(n0 * sizeof(float));     // b0, d0, r0, x0[2]
+  for (int l = 1; l < L; ++l)
+    for (int i = 0; i < 4; ++i) take((size_t)level_dofs[l] * sizeof(double));   // b, x[2], r
+  take((size_t)std::max(nL, 1) * sizeof(double));           // coarsest right-hand side
+  return at;
+}
+
 int sgmg_pcg_solve_batch(sgmg_batch* b, int nitems, const int* item_sys, const double* const* f,
                          double* const* u, double rtol, int maxit, sgmg_solve_info* infos,
                          double* total_ms, void* stream) {
@@ -1937,6 +2023,7 @@ int sgmg_pcg_solve_batch(sgmg_batch* b, int nitems, const int* item_sys, const d
       inf.rel_res_true = b->h_out[k].rel_true;
       inf.rel_res_recur = b->h_out[k].rel_recur;
       inf.solve_ms = ms;
+      inf.fallback_iter = -1;
     }
   }
   return 0;

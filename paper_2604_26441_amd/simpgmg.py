@@ -44,6 +44,9 @@ class Options(ctypes.Structure):
         ("use_graphs", ctypes.c_int),
         ("cycle_gamma", ctypes.c_int),
         ("stencil_form", ctypes.c_int),
+        ("bf16_guard", ctypes.c_int),
+        ("guard_window", ctypes.c_int),
+        ("guard_drop", ctypes.c_double),
     ]
 
 
@@ -53,6 +56,7 @@ class SolveInfo(ctypes.Structure):
         ("rel_res_true", ctypes.c_double), ("rel_res_recur", ctypes.c_double),
         ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int),
         ("solve_ms", ctypes.c_double),
+        ("fallback_iter", ctypes.c_int),
     ]
 
 
@@ -80,7 +84,7 @@ EXPORTS = [
     "sgmg_copy_stencil", "sgmg_copy_diagonal", "sgmg_destroy", "sgmg_last_error",
     "sgmg_autotune", "sgmg_set_launch_shape", "sgmg_setup_batch", "sgmg_pcg_solve_batch",
     "sgmg_pcg_solve_batch_concurrent", "sgmg_batch_hierarchy",
-    "sgmg_batch_block_size", "sgmg_batch_destroy",
+    "sgmg_batch_block_size", "sgmg_batch_destroy", "sgmg_batch_item_layout",
     "sgmg_unet_create", "sgmg_unet_num_params", "sgmg_unet_set_params", "sgmg_unet_get_params",
     "sgmg_unet_forward", "sgmg_unet_grad", "sgmg_unet_train_step", "sgmg_unet_input",
     "sgmg_unet_output", "sgmg_unet_target", "sgmg_warm_start_scale", "sgmg_unet_destroy",
@@ -121,6 +125,9 @@ def _load():
     lib.sgmg_batch_block_size.argtypes = [H]
     lib.sgmg_batch_destroy.argtypes = [H]
     lib.sgmg_batch_destroy.restype = None
+    sz = ctypes.POINTER(ctypes.c_size_t)
+    lib.sgmg_batch_item_layout.argtypes = [i, ctypes.POINTER(ctypes.c_int), i, sz, sz]
+    lib.sgmg_batch_item_layout.restype = ctypes.c_size_t
     fp = ctypes.POINTER(ctypes.c_float)
     lib.sgmg_unet_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(H)]
     lib.sgmg_unet_num_params.argtypes = []
@@ -326,7 +333,8 @@ def pcg_solve(h, f, u, rtol=1e-6, maxit=200, precond=PRECOND_VCYCLE, history_cap
                                _stream(stream)))
     out = {"status": STATUS.get(info.status, info.status), "status_code": info.status,
            "iters": info.iters, "rel_res_true": info.rel_res_true,
-           "rel_res_recur": info.rel_res_recur, "solve_ms": info.solve_ms}
+           "rel_res_recur": info.rel_res_recur, "solve_ms": info.solve_ms,
+           "fallback_iter": info.fallback_iter}
     if hist is not None:
         out["history"] = list(hist)[: info.iters + 1]
     return out
@@ -450,6 +458,21 @@ def pcg_solve_batch_concurrent(batch, item_sys, f_list, u_list, rtol=1e-6, maxit
     out = [{"status": STATUS.get(i.status, i.status), "iters": i.iters,
             "rel_res_true": i.rel_res_true, "rel_res_recur": i.rel_res_recur} for i in infos]
     return out, ms.value
+
+
+def batch_item_layout(level_dofs, n_coarsest_free):
+    """(allocation bytes, [(offset, size)] per sub-buffer) of one batch item's
+    work memory for a hierarchy with the given full-DOF level lengths
+    (host arithmetic of the library, no device work)."""
+    L = len(level_dofs)
+    nb = 10 + 4 * (L - 1) + 1
+    dofs = (ctypes.c_int * L)(*level_dofs)
+    off = (ctypes.c_size_t * nb)()
+    size = (ctypes.c_size_t * nb)()
+    total = _lib.sgmg_batch_item_layout(L, dofs, n_coarsest_free, off, size)
+    if total == 0:
+        raise SimpGmgError("bad level sizes")
+    return total, list(zip(off, size))
 
 
 def padded_grid(opts, multiple=8):

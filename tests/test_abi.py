@@ -69,3 +69,43 @@ def test_setup_rejects_uncoarsenable_meshes_before_device_work():
                                       ctypes.byref(h))
         assert rc == -1 and not h.value
         assert b"dims" in lib.sgmg_last_error()
+
+
+def test_batch_item_layout_fits_its_allocation():
+    """The per-item work memory of the batched solve (the layout whose
+    256-byte rounding once overran its allocation) for every system of the
+    32-system batch workload at 4 levels, and for 2..8 level hierarchies of
+    odd meshes: sub-buffers are 256-byte aligned, each holds its vector,
+    none overlaps the next, and the last one ends inside the allocation."""
+    from paper_2604_26441_amd import simpgmg
+    import workloads
+
+    def levels(dims, L):
+        out = [dims]
+        for _ in range(L - 1):
+            out.append(tuple(d // 2 for d in out[-1]))
+        return out
+
+    cases = [(d, 4) for d in workloads.batch_config()[0]]
+    cases += [((17, 9, 5), 2), ((33, 17, 9), 3), ((255, 129, 129), 8), ((48, 24, 24), 5)]
+    for dims, L in cases:
+        lv = levels(dims, L)
+        assert min(lv[-1]) >= 1
+        ndofs = [3 * (a + 1) * (b + 1) * (c + 1) for a, b, c in lv]
+        nxL, nyL, nzL = lv[-1]
+        n_free = 3 * nxL * (nyL + 1) * (nzL + 1)
+        total, bufs = simpgmg.batch_item_layout(ndofs, n_free)
+        need = [8 * ndofs[0]] * 5 + [4 * ndofs[0]] * 5
+        for l in range(1, L):
+            need += [8 * ndofs[l]] * 4
+        need.append(8 * max(n_free, 1))
+        assert [s for _, s in bufs] == need
+        for k, (off, size) in enumerate(bufs):
+            assert off % 256 == 0
+            end = off + size
+            nxt = bufs[k + 1][0] if k + 1 < len(bufs) else total
+            assert end <= nxt
+        assert bufs[-1][0] + bufs[-1][1] <= total < bufs[-1][0] + bufs[-1][1] + 256
+    import pytest
+    with pytest.raises(simpgmg.SimpGmgError):
+        simpgmg.batch_item_layout([100], 10)

@@ -403,3 +403,48 @@ def test_degenerate_and_edge_cases():
     assert np.array_equal(np64(u1), ue)
     with pytest.raises(simpgmg.SimpGmgError):
         simpgmg.setup_hierarchy(simpgmg.default_options(1, 1, 1, n_levels=2), t64(np.ones(1)))
+
+
+@pytest.mark.parametrize("use_graphs", [1, 0])
+def test_bf16_guard_falls_back_and_meets_the_oracle(use_graphs):
+    """Guarded BF16 (reading of Sec. 3.5 and 3.6): the progress test forced to
+    trip at iteration 2 from the host (window 2, required drop 1e6) switches
+    the level-0 smoothing to BF16X3 and restarts from the current iterate;
+    the solve converges by the oracle's operator, with compliance within
+    1e-5 of the oracle's solve to 1e-10.  A second solve on the same
+    hierarchy repeats it bit for bit (the hierarchy is BF16 again after a
+    fallback).  The default guard does not trip here, and watching changes
+    nothing: bitwise the result of the unguarded solve."""
+    from paper_2604_26441_amd import simpgmg
+    dims = (24, 12, 12)
+    rho = workloads.uniform_rho(dims)
+    f = workloads.edge_load(dims)
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    E = mesh.simp_modulus(rho, 3)
+    K = mesh.assemble(dims, E, fixed=fixed)
+    oh = multigrid.build(dims, E, fixed, multigrid.Options(n_levels=3))
+    xo, st, _, _ = krylov.pcg(lambda v: K @ v, f, lambda r: multigrid.vcycle(oh, r), rtol=1e-10,
+                              maxit=200)
+    o = simpgmg.default_options(*dims, n_levels=3, fine_prec="bf16", flexible_beta=1,
+                                guard_window=2, guard_drop=1e6, use_graphs=use_graphs)
+    h = simpgmg.setup_hierarchy(o, t64(rho))
+    runs = []
+    for _ in range(2):
+        u = t64(np.zeros_like(f))
+        res = simpgmg.pcg_solve(h, t64(f), u, rtol=1e-6, maxit=200, history_cap=256)
+        assert res["status"] == "converged" and res["fallback_iter"] == 2, res
+        x = np64(u)
+        assert krylov.true_rel_residual(lambda v: K @ v, f, x) < 1e-6
+        assert abs(f @ x - f @ xo) <= 1e-5 * abs(f @ xo)
+        runs.append((res["iters"], x))
+    assert runs[0][0] == runs[1][0] and np.array_equal(runs[0][1], runs[1][1])
+    plain = []
+    for guard in (1, 0):
+        o = simpgmg.default_options(*dims, n_levels=3, fine_prec="bf16", flexible_beta=1,
+                                    bf16_guard=guard, use_graphs=use_graphs)
+        h = simpgmg.setup_hierarchy(o, t64(rho))
+        u = t64(np.zeros_like(f))
+        res = simpgmg.pcg_solve(h, t64(f), u, rtol=1e-6, maxit=200)
+        assert res["status"] == "converged" and res["fallback_iter"] == -1
+        plain.append((res["iters"], np64(u)))
+    assert plain[0][0] == plain[1][0] and np.array_equal(plain[0][1], plain[1][1])
