@@ -386,6 +386,23 @@ int sgmg_unet_target(const sgmg_hierarchy* h, const double* u, int Dp, int Hp, i
  * energy norm of the error along u0; *alpha (host, may be NULL). */
 int sgmg_warm_start_scale(sgmg_hierarchy* h, const double* f, double* u0, double* alpha,
                           void* stream);
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, serving loops, harnesses that forbid hipMalloc): the same scaling
+ * as sgmg_warm_start_scale, with the same kernels and summation order, so u0
+ * and alpha are bitwise those of sgmg_warm_start_scale.  Its reduction
+ * partials and scalars live in a fixed library array of 64 Ki + 32 doubles
+ * (512 KiB) per GPU, held until the process ends, instead of the hierarchy's
+ * workspace; K u0 is reduced without being stored.  Nothing is allocated and
+ * nothing synchronises: the call is stream-ordered and returns at once.
+ *   f, u0     device, 3*n_nodes FP64 of h's level 0; u0 is scaled in place.
+ *   alpha_dev device pointer to one double that receives alpha, or NULL.
+ *   Call with h's device current.  Calls that overlap on one GPU (another
+ *   stream, another thread, another hierarchy) share the array and race.
+ *   SGMG_EINVAL for NULL arguments or a mesh whose reductions need more than
+ *   65,536 block partials (about 255^3 elements with the vector-ALU FP64
+ *   operator); SGMG_EHIP if the array's device address cannot be obtained. */
+int sgmg_warm_start_scale_noalloc(const sgmg_hierarchy* h, const double* f, double* u0,
+                                  double* alpha_dev, void* stream);
 void sgmg_unet_destroy(sgmg_unet* u);
 
 void sgmg_destroy(sgmg_hierarchy* h);

@@ -125,7 +125,7 @@ __device__ inline double epilogue3(const Epi<T>& ep, int node, unsigned fx, cons
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const double v = (fx >> c) & 1u ? 0.0 : y[c];
-      ep.out[base + c] = (T)v;
+      if (ep.out) ep.out[base + c] = (T)v;   // NULL: only the dot is wanted
       dot += (double)x[c] * v;
     }
   } else if (ep.mode == EPI_RESID) {

@@ -66,6 +66,7 @@ void launch_prolong_add(const Grid& fine, const Grid& coarse, const TC* ec, cons
 void launch_finalize(RedWs ws, int nblocks, int nv, double* out, hipStream_t s);
 void launch_power_start(double* x, const uint8_t* fixn, int Nn, uint64_t seed, hipStream_t s);
 // out[0] = sum a*b (b == NULL: sum a*a; w != NULL: sum w*a*b)
+int vec_dot_blocks(int n);   // block partials launch_dot writes for length n
 void launch_dot(const double* a, const double* b, const double* w, int n, RedWs ws,
                 double* out, hipStream_t s);
 // y = Dinv * w ; out = ||y||^2

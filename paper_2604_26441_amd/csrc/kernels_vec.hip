@@ -65,6 +65,8 @@ static unsigned vec_grid(int n) {
   return g < (unsigned)kVecGrid ? (g ? g : 1u) : (unsigned)kVecGrid;
 }
 
+int vec_dot_blocks(int n) { return (int)vec_grid(n); }
+
 void launch_dot(const double* a, const double* b, const double* w, int n, RedWs ws, double* out,
                 hipStream_t s) {
   k_dot<<<vec_grid(n), kVecBlock, 0, s>>>(a, b, w, n, ws, out);

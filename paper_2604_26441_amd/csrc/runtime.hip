@@ -1717,6 +1717,78 @@ int sgmg_warm_start_scale(sgmg_hierarchy* h, const double* f, double* u0, double
 }  // extern "C"
 
 // ===========================================================================
+// Allocation-free warm-start scaling.  The reduction partials and the three
+// scalars of sgmg_warm_start_scale live in this fixed device array instead of
+// the hierarchy's workspace, and the product K u0 is reduced without being
+// stored, so the call allocates nothing and never synchronises.  Every GPU the
+// library runs on holds its own copy until the process ends; every slot a call
+// reads is written earlier in the same call (nothing needs clearing), and
+// calls that overlap on one GPU race on it.
+static constexpr size_t kScratchPartials = size_t(1) << 16;   // block partials (doubles)
+static constexpr size_t kScratchScalars = 32;                 // num, den, alpha, padding
+static __device__ __align__(256) double scratch[kScratchPartials + kScratchScalars];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kScratchDevices] = {};
+
+// Device address of the current device's copy of the array.  The array's
+// name is a host-side stand-in in host code: only this address may be passed
+// to kernels or copies.
+int scratch_address(double** out) {
+  int dev = -1;
+  SGMG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices) {
+    set_error("device index out of range for the static scratch table");
+    return SGMG_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      return SGMG_EHIP;
+    }
+    g_scratch_dev[dev] = (double*)p;
+  }
+  *out = g_scratch_dev[dev];
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sgmg_warm_start_scale_noalloc(const sgmg_hierarchy* h, const double* f, double* u0,
+                                  double* alpha_dev, void* stream) {
+  if (!h || !f || !u0) { set_error("NULL argument"); return SGMG_EINVAL; }
+  const int n = h->lev[0].g.n;
+  const size_t need = std::max<size_t>((size_t)k64_dot_partials(h), (size_t)vec_dot_blocks(n));
+  if (need > kScratchPartials) {
+    set_error("mesh too large for the static scratch: " + std::to_string(need) +
+              " reduction partials needed, at most " + std::to_string(kScratchPartials));
+    return SGMG_EINVAL;
+  }
+  double* ptr = nullptr;
+  TRY(scratch_address(&ptr));
+  hipStream_t s = as_stream(stream);
+  const RedWs ws{ptr, nullptr};
+  double* num = ptr + kScratchPartials;
+  double* den = num + 1;
+  double* alpha = num + 2;
+  launch_dot(f, u0, nullptr, n, ws, num, s);
+  // u0 . K u0 from the FP64 operator's block partials; its output is not stored
+  TRY(apply_level<double>(h, 0, SGMG_F64, u0, epi_store<double>(nullptr, ws, den), s));
+  launch_scale_by_ratio(u0, n, num, den, alpha_dev ? alpha_dev : alpha, s);
+  return check_launch();
+}
+
+}  // extern "C"
+
+// ===========================================================================
 // Batched persistent solver (BASELINE extension: many systems, one launch)
 struct sgmg_batch {
   std::vector<sgmg_hierarchy*> hs;

@@ -87,7 +87,8 @@ EXPORTS = [
     "sgmg_batch_block_size", "sgmg_batch_destroy", "sgmg_batch_item_layout",
     "sgmg_unet_create", "sgmg_unet_num_params", "sgmg_unet_set_params", "sgmg_unet_get_params",
     "sgmg_unet_forward", "sgmg_unet_grad", "sgmg_unet_train_step", "sgmg_unet_input",
-    "sgmg_unet_output", "sgmg_unet_target", "sgmg_warm_start_scale", "sgmg_unet_destroy",
+    "sgmg_unet_output", "sgmg_unet_target", "sgmg_warm_start_scale",
+    "sgmg_warm_start_scale_noalloc", "sgmg_unet_destroy",
     "sgmg_simp_default_params", "sgmg_simp_create", "sgmg_simp_destroy", "sgmg_simp_physical",
     "sgmg_simp_sensitivity", "sgmg_simp_oc_update", "sgmg_simp_step",
 ]
@@ -140,6 +141,7 @@ def _load():
     lib.sgmg_unet_output.argtypes = [H, vp, i, i, i, vp, vp]
     lib.sgmg_unet_target.argtypes = [H, vp, i, i, i, vp, vp, vp]
     lib.sgmg_warm_start_scale.argtypes = [H, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.sgmg_warm_start_scale_noalloc.argtypes = [H, vp, vp, vp, vp]
     lib.sgmg_unet_destroy.argtypes = [H]
     lib.sgmg_unet_destroy.restype = None
     SP = ctypes.POINTER(SimpParams)
@@ -574,6 +576,14 @@ def warm_start_scale(h, f, u0, stream=None):
     _check(_lib.sgmg_warm_start_scale(h.handle, _ptr(f, torch.float64, h.n_dof), _ptr(u0, torch.float64, h.n_dof),
                                       ctypes.byref(a), _stream(stream)))
     return a.value
+
+
+def warm_start_scale_noalloc(h, f, u0, alpha=None, stream=None):
+    """sgmg_warm_start_scale_noalloc: u0 scaled in place, alpha (a one-element
+    FP64 device tensor, optional) written on the stream; nothing allocated."""
+    _check(_lib.sgmg_warm_start_scale_noalloc(
+        h.handle, _ptr(f, torch.float64, h.n_dof), _ptr(u0, torch.float64, h.n_dof),
+        _ptr(alpha, torch.float64, 1) if alpha is not None else None, _stream(stream)))
 
 
 def simp_params(nx, ny, nz, **kw):
