@@ -24,7 +24,8 @@ void launch_apply_fine_mfma(const Grid& g, int nsplit, int rows, int zchunk, con
                             const Epi<float>& ep, hipStream_t s);
 size_t apply_fine_mfma_blocks(const Grid& g, int rows, int zchunk);
 bool mfma_shape_valid(int rows, int zchunk);
-// The MFMA kernel addresses vectors with 32-bit byte offsets (< 2^31).
+// The BF16-family MFMA kernel addresses vectors with 32-bit byte offsets
+// below 2^30 (about 89 M nodes).
 bool mfma_size_ok(const Grid& g);
 // FP64 fine operator on the FP64 MFMA (same launch shapes).
 void launch_apply_fine_mfma64(const Grid& g, int rows, int zchunk, const double* E,

@@ -1,34 +1,37 @@
 // Fine-level K.u on the gfx950 matrix cores (Eq. mf_matvec; Sec. 3.5 BF16
 // semantics).  The element matrix s*K_e is an integer matrix with entries of
-// magnitude <= 88, hence exact in BF16; the element input tile is rounded to
-// BF16 (NSPLIT = 1) or split into three BF16 terms that together carry the
-// FP32 significand (NSPLIT = 3).  Products are exact and accumulate in FP32 on
-// v_mfma_f32_16x16x32_bf16; E_e / s is applied in FP32 afterwards.
+// magnitude <= 88, hence exact in BF16; each input value is rounded to BF16
+// (NSPLIT = 1) or split into two or three BF16 terms (NSPLIT = 3 carries the
+// whole FP32 significand).  Products are exact and accumulate in FP32 on
+// v_mfma_f32_16x16x32_bf16; E_e / s is applied in FP32 afterwards.  The FP64
+// form runs the same tiles on v_mfma_f64_16x16x4_f64.
 //
 // Work decomposition: one wave owns a tile of 16 elements in x (the MFMA's
 // N dimension, one element per lane column) by YC element rows in y, and
 // marches along z over a chunk of node planes.  Nothing is shared between
-// waves: there is no LDS traffic and no barrier in the main loop.
-//   * MFMA h = 0 produces the rows of the element's dy = 0 nodes, h = 1 those
-//     of its dy = 1 nodes.  In both, lane group g = dx + 2 dz of column n
-//     holds the 3 components (row 4g + c, c = 3 is padding) of node
-//     (dx, dy, dz) of element n.
+// waves and there is no barrier.  MFMA h = 0 produces the element's dy = 0
+// nodes, h = 1 its dy = 1 nodes.  Node sums:
 //   * y: the dy = 1 rows of element row ey and the dy = 0 rows of row ey + 1
 //     sit in the same lanes: an in-register carry from row to row.
-//   * x: dx = 1 of element n - 1 meets dx = 0 of element n after one
-//     v_permlane16_swap (group 1 -> 0, 3 -> 2) and a DPP row shift by one
-//     lane fused into the add.
-//   * z: dz = 1 of plane ez meets dz = 0 of plane ez + 1 after one
-//     v_permlane32_swap (groups 2, 3 -> 0, 1) and a per-row carry across
-//     planes.
-//   After the three steps the 16 lanes of group 0 hold complete nodes.  A
-//   wave recomputes one halo element on the low side of each axis so that
-//   every node it writes is complete (15 owned nodes in x, YC - 1 node rows,
-//   all planes of its chunk).  Every node sums its 8 element contributions in
-//   the same order whatever the tile shape: results are bitwise independent
-//   of the launch shape.
+//   * x: dx = 1 of element n - 1 meets dx = 0 of element n through a DPP row
+//     shift by one lane fused into an add.
+//   * z: dz = 1 of plane ez meets dz = 0 of plane ez + 1 through a per-row
+//     carry across planes.
+// A wave recomputes one halo element on the low side of each axis so that
+// every node it writes is complete (15 owned nodes in x, YC - 1 node rows,
+// all planes of its chunk).  Every node sums its 8 element contributions in
+// the same order whatever the tile shape: results are bitwise independent of
+// the launch shape.
+//
+// BF16 family: each wave stages its node planes in LDS, split into BF16 terms
+// once per value, and output row m = 4 c + (dx + 2 dz) puts component c of
+// all four (dx, dz) nodes in lane group c.  FP64: element inputs are loaded
+// per element, and lane group dx + 2 dz holds the three components of node
+// (dx, dy, dz), so the x and z sums first move lane groups together with
+// v_permlane16_swap / v_permlane32_swap.
 #include <climits>
 #include <cstring>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -42,27 +45,6 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaWavesPerBlock = 4;
 
-// A operand table: [h][lane][8] BF16 bit patterns, built on the host.
-// Row m = lane % 16 = 4 (dx + 2 dz) + c of output node (dx, h, dz); slot j of
-// lane group q = lane / 16 is input node (j / 3, q & 1, q >> 1), component
-// j % 3 (slots 6, 7 and c = 3 are zero padding).
-
-// x-combination for lane groups 0 and 2: v + (v of group 1 / 3, one lane to
-// the left).  v_permlane16_swap(v, v) leaves v in the even rows of its first
-// result and moves the odd rows into the even rows of its second.
-__device__ inline float x_combine(float v) {
-  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false,
-                                                  false);
-  return __uint_as_float(r[0]) +
-         __int_as_float(__builtin_amdgcn_update_dpp(0, (int)r[1], 0x111, 0xf, 0xf, true));
-}
-// z-split: lo = v (valid in lanes 0..31), hi = lanes 32..63 of v moved to 0..31.
-__device__ inline void z_split(float v, float& lo, float& hi) {
-  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false,
-                                                  false);
-  lo = __uint_as_float(r[0]);
-  hi = __uint_as_float(r[1]);
-}
 __device__ inline double x_combine(double v) {
   const int h = __double2hiint(v), l = __double2loint(v);
   const auto rh = __builtin_amdgcn_permlane16_swap((unsigned)h, (unsigned)h, false, false);
@@ -91,6 +73,9 @@ struct EpIn { T x[3], b[3], di[3], dp[3]; unsigned fx; };
 // are 32-bit: the launcher rejects vectors of 2^31 bytes or more, and
 // kNoOffset (2^31) is past every buffer.
 constexpr int kNoOffset = INT_MIN;
+// Poison part of a two-part offset in the BF16-family kernel (vectors there
+// stay below 2^30 bytes).
+constexpr int kPoison = 1 << 30;
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, size_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
@@ -183,21 +168,68 @@ __device__ inline double store_ep(const Epi<T>& ep, const EpRsrc& rs, int off3, 
   return off3 == kNoOffset ? 0.0 : dot;
 }
 
+// Per-wave LDS of the BF16-family kernel:
+//   U: NSPLIT terms x a ring of 3 node planes x (YC + 1) node rows x 17 nodes
+//      x 4 BF16 (components 0, 1, 2 and a zero), so the two nodes of a lane's
+//      pair are 16 contiguous bytes;
+//   O: (YC - 1) owned node rows x 16 columns x 4 floats: the node sums of a
+//      plane, written in the matrix-core lane layout, read back per node.
+template <int NSPLIT, int YC>
+struct FineLds {
+  static constexpr int kRow = 17 * 8;
+  static constexpr int kPlane = (YC + 1) * kRow;
+  static constexpr int kTerm = 3 * kPlane;
+  static constexpr int kU = (NSPLIT * kTerm + 15) / 16 * 16;
+  static constexpr int kORow = 16 * 16;
+  static constexpr int kWave = kU + (YC - 1) * kORow;
+};
+
+__device__ inline float dpp_shr1(float v) {   // lane n-1 of the same 16-lane row (0 for n = 0)
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x111, 0xf, 0xf, true));
+}
+
+// BF16-family fine operator.
+//   * Node values are read once per wave with 12-byte loads (one node per
+//     lane), split into NSPLIT BF16 terms once and written to the wave's LDS
+//     ring of node planes; the B operand of every element is then two 8-byte
+//     LDS reads per term.
+//   * MFMA output rows are m = 4 c + (dx + 2 dz) (build_mfma_atab): lane
+//     group c holds component c of the four nodes (dx, dz) of its column's
+//     element, so the x-combination is one DPP-shifted add per dz, the
+//     z-combination a register carry across planes and the y-combination a
+//     carry across rows.  Lane group c < 3 of column n >= 1 then holds
+//     component c of node (ex, ey, ez), which goes to the wave's LDS O rows.
+//   * At the end of each plane the epilogue runs in node layout: one lane per
+//     owned node reads its three sums from O and applies the epilogue with
+//     operands loaded by 12-byte loads at the start of the plane, then
+//     stores 12 bytes.  Element moduli come with one 4-byte load per lane per
+//     four rows and reach their columns by ds_bpermute.
+//   Every vector-memory instruction thus moves 12 bytes per lane (4 for the
+//   moduli and 1 for the Dirichlet flags): the address unit processes a
+//   wave-wide memory instruction at a fixed rate, which per-step 4-byte
+//   accesses had made the limit.
+//   All loads for plane ez are issued at its start (node plane ez + 3,
+//   moduli of plane ez + 1, epilogue operands of plane ez) and consumed by
+//   its end or the start of the next plane, unconditionally (an unneeded
+//   load reads zeros), so the compiler's load-counter waits stay exact.
 template <int NSPLIT, int YC, int MODE>
 __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
     Grid g, const float* __restrict__ Es, const uint16_t* __restrict__ atab,
     const float* __restrict__ u, const uint8_t* __restrict__ fixn, Epi<float> ep, int zchunk,
     int ntx, int nty, int ntiles) {
+  using LD = FineLds<NSPLIT, YC>;
+  static_assert(YC == 4 || YC == 8, "tile rows");
+  __shared__ __attribute__((aligned(16))) unsigned char lds_all[kMfmaWavesPerBlock * LD::kWave];
   const int lane = threadIdx.x & 63;
   // wave index made wave-uniform, so all tile arithmetic stays scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  unsigned char* const lds = lds_all + wave * LD::kWave;
   const int tile = xcd_block(blockIdx.x, gridDim.x) * kMfmaWavesPerBlock + wave;
   const int tx = tile % ntx, tt = tile / ntx, ty = tt % nty, tz = tt / nty;
   const int grp = lane >> 4, n = lane & 15;
   const int xs = tx * 15, ys = ty * (YC - 1), zs = tz * zchunk;
   const int ex = xs - 1 + n;
   const int dy_in = grp & 1, dz_in = grp >> 1;
-  const bool x_ok = ex >= 0 && ex < g.nx;
 
   bf16x8 a0, a1;
   {
@@ -210,125 +242,230 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
     }
   }
 
-  struct In { float v[6]; float es; };
   const int zend = tile < ntiles ? min(zs + zchunk, g.Nz) : zs - 1;
-  // inputs of element (ex, ey, ez) for this lane's node pair; zero outside
   const size_t nvec = (size_t)g.n * sizeof(float);
   const __amdgpu_buffer_rsrc_t ru = make_rsrc(u, nvec);
   const __amdgpu_buffer_rsrc_t re = make_rsrc(Es, (size_t)g.nel * sizeof(float));
-  EpRsrc rs;
-  rs.u = ru;
-  rs.fix = make_rsrc(fixn, (size_t)g.Nn);
-  rs.b = make_rsrc(ep.b, MODE == EPI_RESID || MODE == EPI_SMOOTH ? nvec : 0);
-  rs.di = make_rsrc(ep.dinv, MODE == EPI_SMOOTH ? nvec : 0);
-  rs.d = make_rsrc(ep.d, MODE == EPI_SMOOTH ? nvec : 0);
-  rs.out = make_rsrc(ep.out, ep.out ? nvec : 0);   // no output: every store is dropped
-  // inputs of element (ex, ey, ez) for this lane's node pair; zero outside
-  auto load_in = [&](int ey, int ez, In& in) {
-    // row and plane tests are wave-uniform (one scalar condition); combining
-    // them with the lane's x test by a non-short-circuit & keeps the
-    // address selection a per-lane select instead of masked control flow
-    const bool yz_ok = (unsigned)ey < (unsigned)g.ny && (unsigned)ez < (unsigned)g.nz && ez < zend;
-    const bool ok = x_ok & yz_ok;
-    const int node = ex + g.Nx * ((ey + dy_in) + g.Ny * (ez + dz_in));
-    const int off = ok ? node * 12 : kNoOffset;
-    bload3(ru, off, in.v);
-    bload3(ru, ok ? off + 12 : kNoOffset, in.v + 3);
-    in.es = bload(re, ok ? 4 * (ex + g.nx * (ey + g.ny * ez)) : kNoOffset);
+  const __amdgpu_buffer_rsrc_t rfix = make_rsrc(fixn, (size_t)g.Nn);
+  const __amdgpu_buffer_rsrc_t rb = make_rsrc(ep.b, MODE == EPI_RESID || MODE == EPI_SMOOTH ? nvec : 0);
+  const __amdgpu_buffer_rsrc_t rdi = make_rsrc(ep.dinv, MODE == EPI_SMOOTH ? nvec : 0);
+  const __amdgpu_buffer_rsrc_t rd = make_rsrc(ep.d, MODE == EPI_SMOOTH ? nvec : 0);
+  const __amdgpu_buffer_rsrc_t rout = make_rsrc(ep.out, ep.out ? nvec : 0);   // NULL: stores dropped
+
+  // Offsets are the sum of a per-lane part fixed for the whole wave and a
+  // plane part; a part that must not be accessed is kPoison.  Vectors are
+  // below 2^30 bytes (mfma_size_ok) and valid parts are non-negative with a
+  // sum below that, so a sum holding one or two kPoison parts lies in
+  // [2^30, 2^31]: outside every buffer as an unsigned offset.
+  auto off2 = [](int a, int b) { return (int)((unsigned)a + (unsigned)b); };
+  auto part = [](bool ok, int v) { return ok ? v : kPoison; };
+
+  // node planes: load i, lane l < 51 carries node xs - 1 + l % 17 of node
+  // row k = 3 i + l / 17 (rows 0 .. YC of the tile)
+  constexpr int NU = (YC + 3) / 3;
+  const int um = lane % 17, uk = lane / 17;
+  int u_lane[NU];
+  bool u_on[NU];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) {
+    const int k = 3 * i + uk;
+    u_on[i] = lane < 51 && k <= YC;
+    u_lane[i] = part(u_on[i] && (unsigned)(xs - 1 + um) < (unsigned)g.Nx &&
+                         (unsigned)(ys - 1 + k) < (unsigned)g.Ny,
+                     12 * (xs - 1 + um + g.Nx * (ys - 1 + k)));
+  }
+  float uv[NU][3];
+  auto load_u = [&](int P, bool need) {
+    const int pp = part(need && (unsigned)P < (unsigned)g.Nz, 12 * g.Nx * g.Ny * P);
+#pragma unroll
+    for (int i = 0; i < NU; ++i) bload3(ru, off2(u_lane[i], pp), uv[i]);
   };
-  auto contract = [&](const In& in, f32x4& c0, f32x4& c1) {
+  // exact NSPLIT-term BF16 split (round to nearest even; each residual is
+  // exact in FP32) of the loaded node plane P into its ring slot
+  auto split_u = [&](int P) {
+    unsigned char* const slot = lds + ((P + 3) % 3) * LD::kPlane + uk * LD::kRow + um * 8;
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+      if (u_on[i]) {
+        float v0 = uv[i][0], v1 = uv[i][1], v2 = uv[i][2];
+#pragma unroll
+        for (int sp = 0; sp < NSPLIT; ++sp) {
+          const unsigned w0 = __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{v0, v1}, bf16x2));
+          const unsigned w1 = __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{v2, 0.f}, bf16x2));
+          *(uint2*)(slot + 3 * i * LD::kRow + sp * LD::kTerm) = uint2{w0, w1};
+          if (sp + 1 < NSPLIT) {
+            v0 -= __uint_as_float(w0 << 16);
+            v1 -= __uint_as_float(w0 & 0xffff0000u);
+            v2 -= __uint_as_float(w1 << 16);
+          }
+        }
+      }
+    }
+  };
+  // B operand of element row r: lane group (dy, dz) reads nodes (n, n + 1)
+  // of node row r + dy in the slot of plane ez + dz
+  auto read_b = [&](int base, int r, u32x4 (&b)[NSPLIT]) {
+#pragma unroll
+    for (int sp = 0; sp < NSPLIT; ++sp) {
+      const unsigned char* q = lds + base + r * LD::kRow + sp * LD::kTerm;
+      const uint2 lo = *(const uint2*)q;
+      const uint2 hi = *(const uint2*)(q + 8);
+      b[sp] = u32x4{lo.x, lo.y, hi.x, hi.y};
+    }
+  };
+  auto contract = [&](const u32x4 (&b)[NSPLIT], f32x4& c0, f32x4& c1) {
     c0 = f32x4{0.f, 0.f, 0.f, 0.f};
     c1 = f32x4{0.f, 0.f, 0.f, 0.f};
-    // split the 6 inputs, as 3 pairs, into NSPLIT packed BF16 terms: one
-    // v_cvt_pk_bf16_f32 per pair and term; the FP32 value of a packed term
-    // is its half shifted into the high bits, and the residual is exact
-    u32x4 w[NSPLIT];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      float lo = in.v[2 * q], hi = in.v[2 * q + 1];
-#pragma unroll
-      for (int sp = 0; sp < NSPLIT; ++sp) {
-        const f32x2 pr = {lo, hi};
-        const unsigned bits = __builtin_bit_cast(unsigned, __builtin_convertvector(pr, bf16x2));
-        w[sp][q] = bits;
-        if (sp + 1 < NSPLIT) {
-          lo -= __uint_as_float(bits << 16);
-          hi -= __uint_as_float(bits & 0xffff0000u);
-        }
-      }
-    }
 #pragma unroll
     for (int sp = NSPLIT - 1; sp >= 0; --sp) {    // smallest terms first
-      w[sp][3] = 0u;
-      const bf16x8 b = __builtin_bit_cast(bf16x8, w[sp]);
-      c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, c1, 0, 0, 0);
+      const bf16x8 bb = __builtin_bit_cast(bf16x8, b[sp]);
+      c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bb, c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bb, c1, 0, 0, 0);
     }
-    c0 *= in.es;   // column n is element n, whose E / s every lane of it loaded
-    c1 *= in.es;
   };
 
-  // node (ex, ys - 1 + r, ez) is written by this lane
-  const bool ep_lane = grp == 0 && n >= 1 && ex < g.Nx;
-  auto owns = [&](int r, int ez) {
-    const bool uni = r >= 1 && ez >= zs && ez < zend && ys - 1 + r < g.Ny;   // wave-uniform
-    return ep_lane & uni;
-  };
-
-  float zc[YC][3];
+  // element moduli E / s: load i, lane l holds column l & 15 of element row
+  // 4 i + l / 16; zero outside the mesh, which also cancels the products of
+  // elements that do not exist
+  constexpr int NE = YC / 4;
+  int e_lane[NE];
 #pragma unroll
-  for (int r = 0; r < YC; ++r) zc[r][0] = zc[r][1] = zc[r][2] = 0.f;
+  for (int i = 0; i < NE; ++i) {
+    const int ey = ys - 1 + 4 * i + grp;
+    e_lane[i] = part((unsigned)ex < (unsigned)g.nx && (unsigned)ey < (unsigned)g.ny,
+                     4 * (ex + g.nx * ey));
+  }
+  float ev[NE], esc[NE];
+  auto load_e = [&](int ez, bool need) {
+    const int pe = part(need && (unsigned)ez < (unsigned)g.nz, 4 * g.nx * g.ny * ez);
+#pragma unroll
+    for (int i = 0; i < NE; ++i) ev[i] = bload(re, off2(e_lane[i], pe));
+  };
+
+  // node-layout epilogue: group i, lane l < 60 owns node xs + l % 15 of node
+  // row 1 + 4 i + l / 15 (rows 1 .. YC - 1 of the tile)
+  constexpr int NG = (YC + 2) / 4;
+  constexpr int NV = MODE == EPI_SMOOTH ? 4 : (MODE == EPI_RESID || MODE == kStoreDot) ? 1 : 0;
+  const int oj = lane % 15, orr = lane / 15;
+  int o_lane[NG], f_lane[NG], o_lds[NG];
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    const int rr = 1 + 4 * i + orr;
+    const bool on = lane < 60 && rr <= YC - 1 && xs + oj < g.Nx && ys - 1 + rr < g.Ny;
+    o_lane[i] = part(on, 12 * (xs + oj + g.Nx * (ys - 1 + rr)));
+    f_lane[i] = part(on, xs + oj + g.Nx * (ys - 1 + rr));
+    o_lds[i] = LD::kU + (min(rr, YC - 1) - 1) * LD::kORow + (oj + 1) * 16;
+  }
+  float vv[NG][NV > 0 ? NV : 1][3];
+  unsigned fv[NG];
+  auto load_v = [&](int ez) {
+    const bool own = ez >= zs && ez < zend;
+    const int po = part(own, 12 * g.Nx * g.Ny * ez), pf = part(own, g.Nx * g.Ny * ez);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      fv[i] = __builtin_amdgcn_raw_buffer_load_b8(rfix, off2(f_lane[i], pf), 0, 0);
+      const int o = off2(o_lane[i], po);
+      if (MODE == EPI_SMOOTH) {
+        bload3(ru, o, vv[i][0]);
+        bload3(rb, o, vv[i][1]);
+        bload3(rdi, o, vv[i][2]);
+        bload3(rd, ep.c1 != 0.0 ? o : kNoOffset, vv[i][3]);
+      } else if (MODE == EPI_RESID) {
+        bload3(rb, o, vv[i][0]);
+      } else if (MODE == kStoreDot) {
+        bload3(ru, o, vv[i][0]);
+      }
+    }
+  };
   double dot = 0.0;
-  // Software pipeline over the (plane, row) steps, in rings of 4 slots
-  // indexed by row % 4 (YC is a multiple of 4, so slot indices are
-  // compile-time): element inputs are loaded 3 steps ahead of their use,
-  // epilogue operands 2 steps ahead.
-  In p[4];
-  EpIn<float> e[4];
-  auto fetch_in = [&](int r, int ez) {          // step (ez, r + 3)
-    const int rr = r + 3 < YC ? r + 3 : r + 3 - YC;
-    load_in(ys - 1 + rr, r + 3 < YC ? ez : ez + 1, p[(r + 3) & 3]);
-  };
-  auto fetch_ep = [&](int r, int ez) {          // step (ez, r + 2)
-    const int rr = r + 2 < YC ? r + 2 : r + 2 - YC;
-    const int zz = r + 2 < YC ? ez : ez + 1;
-    const int nd = ep_node(g, ex, ys - 1 + rr, zz);
-    load_ep<float, MODE>(ep, rs, nd, owns(rr, zz) ? 12 * nd : kNoOffset, e[(r + 2) & 3]);
-  };
+  auto finish_plane = [&](int ez) {
+    const int po = part(ez >= zs && ez < zend, 12 * g.Nx * g.Ny * ez);
 #pragma unroll
-  for (int r = 0; r < 3; ++r) load_in(ys - 1 + r, zs - 1, p[r]);
-  e[0].fx = e[1].fx = 7u;                       // plane zs - 1 owns no node
-  for (int ez = zs - 1; ez < zend; ++ez) {
-    float yc[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int r = 0; r < YC; ++r) {
-      fetch_in(r, ez);
-      fetch_ep(r, ez);
-      f32x4 v0, v1;
-      contract(p[r & 3], v0, v1);
-      float yv[3];
+    for (int i = 0; i < NG; ++i) {
+      const f32x4 yq = *(const f32x4*)(lds + o_lds[i]);
+      const int o = off2(o_lane[i], po);
+      const bool mine = (unsigned)o < (unsigned)kPoison;
+      float out[3], dd[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        yv[c] = v0[c] + yc[c];     // y: dy = 0 of this row + dy = 1 of the row below
-        yc[c] = v1[c];
-      }
-      if (r >= 1) {
-        float fin[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          float lo, hi;
-          z_split(x_combine(yv[c]), lo, hi);      // x, then z: plane ez + plane ez - 1
-          fin[c] = lo + zc[r][c];
-          zc[r][c] = hi;
+        const bool fixed = (fv[i] >> c) & 1u;
+        const float y = yq[c];
+        if (MODE == EPI_STORE || MODE == kStoreDot) {
+          out[c] = fixed ? 0.f : y;
+          if (MODE == kStoreDot && mine) dot += (double)vv[i][0][c] * (double)out[c];
+        } else if (MODE == EPI_RESID) {
+          out[c] = fixed ? 0.f : vv[i][0][c] - y;
+        } else {
+          const float r = vv[i][1][c] - y;
+          dd[c] = fixed ? 0.f : (float)ep.c1 * vv[i][3][c] + (float)ep.c2 * vv[i][2][c] * r;
+          out[c] = fixed ? 0.f : vv[i][0][c] + dd[c];
         }
-        const int nd = ep_node(g, ex, ys - 1 + r, ez);
-        dot += store_ep<float, MODE>(ep, rs, owns(r, ez) ? 12 * nd : kNoOffset, e[r & 3], fin);
+      }
+      bstore3(rout, o, out[0], out[1], out[2]);
+      if (MODE == EPI_SMOOTH) {
+        if (ep.store_d) bstore3(rd, o, dd[0], dd[1], dd[2]);
+        if (ep.out64 && mine) {
+          double* q = ep.out64 + (o >> 2);
+          q[0] = (double)out[0];
+          q[1] = (double)out[1];
+          q[2] = (double)out[2];
+        }
       }
     }
+  };
+
+  // lane (c, n) of the matrix-core layout writes its node sum to O column n
+  const int o_w = LD::kU + n * 16 + grp * 4;
+  float zc[YC];
+#pragma unroll
+  for (int r = 0; r < YC; ++r) zc[r] = 0.f;
+
+  load_u(zs - 1, true);
+  split_u(zs - 1);
+  load_u(zs, true);
+  split_u(zs);
+  load_u(zs + 1, zs + 1 <= zend);
+  load_e(zs - 1, true);
+  for (int ez = zs - 1; ez < zend; ++ez) {
+    split_u(ez + 2);                              // loaded during the previous plane
+#pragma unroll
+    for (int i = 0; i < NE; ++i) esc[i] = ev[i];
+    load_u(ez + 3, ez + 3 <= zend);
+    load_e(ez + 1, ez + 1 < zend);
+    load_v(ez);
+    const int base = ((ez + dz_in + 3) % 3) * LD::kPlane + dy_in * LD::kRow + n * 8;
+    u32x4 bc[NSPLIT], bn[NSPLIT];
+    read_b(base, 0, bc);
+    float yc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int r = 0; r < YC; ++r) {
+      if (r + 1 < YC) read_b(base, r + 1, bn);
+      const float sc = __int_as_float(
+          __builtin_amdgcn_ds_bpermute(4 * (n + 16 * (r & 3)), __float_as_int(esc[r >> 2])));
+      f32x4 c0, c1;
+      contract(bc, c0, c1);
+      float t[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        t[k] = c0[k] * sc + yc[k];    // y: dy = 0 of this row + dy = 1 of the row below
+        yc[k] = c1[k] * sc;
+      }
+      // x: dx = 0 of element n + dx = 1 of element n - 1; z: plane ez + plane ez - 1
+      const float w0 = t[0] + dpp_shr1(t[1]);
+      const float w1 = t[2] + dpp_shr1(t[3]);
+      const float fin = w0 + zc[r];
+      zc[r] = w1;
+      if (r >= 1) *(float*)(lds + o_w + (r - 1) * LD::kORow) = fin;
+      if (r + 1 < YC) {
+#pragma unroll
+        for (int sp = 0; sp < NSPLIT; ++sp) bc[sp] = bn[sp];
+      }
+    }
+    finish_plane(ez);
   }
   if (MODE == kStoreDot) {
-    const double vv[1] = {dot};
-    grid_sum<1>(vv, ep.ws);
+    const double vd[1] = {dot};
+    grid_sum<1>(vd, ep.ws);
   }
 }
 
@@ -472,7 +609,7 @@ MfmaLaunch mfma_launch(const Grid& g, int rows, int zchunk) {
 }  // namespace
 
 bool mfma_size_ok(const Grid& g) {
-  return (size_t)g.n * sizeof(float) < ((size_t)1 << 31) - 64;
+  return (size_t)g.n * sizeof(float) < ((size_t)1 << 30) - 64;
 }
 
 bool mfma_shape_valid(int rows, int zchunk) {
@@ -589,19 +726,23 @@ void launch_scale_E(const double* E, float* Es, int nel, double inv_s, hipStream
   k_scale_E<<<div_up(nel, 256), 256, 0, s>>>(E, Es, nel, inv_s);
 }
 
-// Host: A-operand table in BF16 bit patterns (integers <= 255 are exact).
+// Host: A-operand table in BF16 bit patterns (integers <= 255 are exact),
+// [h][lane][8]: row m = lane % 16 = 4 c + (dx + 2 dz) is component c (c = 3:
+// zero row) of output node (dx, h, dz); slot j of lane group q = lane / 16 is
+// component j % 4 (3: zero) of input node (j / 4, q & 1, q >> 1).
 void build_mfma_atab(const KeTables& kt, uint16_t* out /* 2*64*8 */) {
   for (int h = 0; h < 2; ++h)
     for (int lane = 0; lane < 64; ++lane) {
       const int m = lane & 15, q = lane >> 4;
-      const int go = m >> 2, c = m & 3;
-      const int dx = go & 1, dz = go >> 1;
+      const int c = m >> 2, k = m & 3;
+      const int dx = k & 1, dz = k >> 1;
       const int aout = dx + 2 * h + 4 * dz;
       for (int j = 0; j < 8; ++j) {
         float v = 0.f;
-        if (c < 3 && j < 6) {
-          const int bin = (j / 3) + 2 * (q & 1) + 4 * (q >> 1);
-          v = (float)kt.kint[(3 * aout + c) * 24 + 3 * bin + (j % 3)];
+        const int cin = j & 3;
+        if (c < 3 && cin < 3) {
+          const int bin = (j >> 2) + 2 * (q & 1) + 4 * (q >> 1);
+          v = (float)kt.kint[(3 * aout + c) * 24 + 3 * bin + cin];
         }
         uint32_t bits;
         std::memcpy(&bits, &v, 4);

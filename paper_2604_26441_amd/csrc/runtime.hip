@@ -280,7 +280,7 @@ int apply_level<float>(const sgmg_hierarchy* h, int l, sgmg_prec prec, const flo
         return SGMG_EINVAL;
       }
       if (!mfma_size_ok(L.g)) {
-        set_error("BF16 MFMA path: level-0 vector of 2^31 bytes or more; use F32");
+        set_error("BF16 MFMA path: level-0 vector of 2^30 bytes or more; use F32");
         return SGMG_EINVAL;
       }
       const int ns = prec == SGMG_BF16 ? 1 : prec == SGMG_BF16X2 ? 2 : 3;
