@@ -32,6 +32,7 @@ def parse():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ku256", action="store_true", help="skip the 256^3 K.u roofline")
     ap.add_argument("--no-compare", action="store_true", help="skip FP64-GMG and Jacobi-PCG comparisons")
     ap.add_argument("--warm-pairs", type=int, default=300,
                     help="solver-generated 32^3 training pairs for the warm-start comparison (0: skip)")
@@ -39,56 +40,117 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                               "fine_ku_bf16x3_80cube_traffic.md")
-KU_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2604_26441_amd", "csrc",
-                         "kernels_mfma.hip")
+PROFILE = os.path.join(ROOT, "profiles", "fine_ku_counters_256cube.md")
+KU_SOURCE = os.path.join(ROOT, "paper_2604_26441_amd", "csrc", "kernels_mfma.hip")
 
 
-def measured_traffic(shape):
-    """Calibrated HBM bytes per launch of the BF16X3 fine K.u at 80^3 for the
-    given launch shape, from the committed rocprofv3 counter summary; None if
-    the kernel source changed since the counters were taken, or the shape is
-    not in the table."""
+def measured_profile(prec, shape):
+    """Calibrated HBM bytes per launch and matrix-core busy fraction of the
+    BF16-family fine K.u at 256^3 for the given precision and launch shape,
+    from the committed rocprofv3 counter summary; None if the kernel source
+    changed since the counters were taken or the row is missing."""
     import hashlib
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(PROFILE).read()
         src = hashlib.sha1(open(KU_SOURCE, "rb").read()).hexdigest()
     except OSError:
         return None
-    if f"kernel_source_sha1: {src}" not in text:
+    if shape is None or f"kernel_source_sha1: {src}" not in text:
         return None
     for line in text.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) == 5 and cells[0].isdigit() and (int(cells[0]), int(cells[1])) == tuple(shape):
-            return int(cells[4])
+        if (len(cells) >= 9 and cells[0] == "256^3" and cells[1] == prec and cells[2].isdigit()
+                and (int(cells[2]), int(cells[3])) == tuple(shape)):
+            return {"traffic": int(cells[6]), "mfma_util": float(cells[8])}
     return None
 
 
-def cpu_baseline(n, iters_full, sample_iters=3):
-    """Oracle FP64 PCG-GMG on the same n^3 workload, one thread: the first
-    ``sample_iters`` PCG iterations are timed (hierarchy setup untimed) and the
-    per-iteration cost is scaled to ``iters_full`` iterations."""
+def cpu_baseline(n, gpu_u, gpu_iters):
+    """The oracle (FP64 PCG-GMG on assembled SciPy CSR, 4 levels, the same
+    Chebyshev / Jacobi smoothing and rtol 1e-6) solving the same n^3
+    cantilever on one host thread: setup and the full solve timed
+    separately.  Afterwards, untimed, the oracle's iterate is refined to rtol
+    1e-10 and the GPU solution's errors against that reference are
+    reported."""
+    import platform
     from threadpoolctl import threadpool_limits
     import workloads
     from oracle import krylov, mesh, multigrid
     dims = (n, n, n)
     with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
         rho = workloads.uniform_rho(dims)
         fixed = workloads.cantilever_fixed(dims).astype(bool)
         f = workloads.edge_load(dims)
         E = mesh.simp_modulus(rho, 3)
         oh = multigrid.build(dims, E, fixed, multigrid.Options(n_levels=4))
+        t1 = time.perf_counter()
         K = oh.levels[0].K
-        t0 = time.perf_counter()
-        krylov.pcg(lambda v: K @ v, f, lambda r: multigrid.vcycle(oh, r), rtol=1e-6,
-                   maxit=sample_iters)
-        t = time.perf_counter() - t0
-    per_it = t / sample_iters
-    return {"value": round(per_it * iters_full * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample_iters} iterations of the oracle FP64 PCG-GMG solve of the same "
-                      f"{n}^3 cantilever ({t:.1f} s, setup untimed), scaled per iteration to the "
-                      f"{iters_full} iterations of the measured solve"}
+        M = lambda r: multigrid.vcycle(oh, r)
+        xo, st, it, _ = krylov.pcg(lambda v: K @ v, f, M, rtol=1e-6, maxit=200)
+        t2 = time.perf_counter()
+        xr, st_r, it_r, _ = krylov.pcg(lambda v: K @ v, f, M, x0=xo, rtol=1e-10, maxit=200)
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    base = {"value": round((t2 - t1) * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": f"the whole oracle solve of the same {n}^3 cantilever to rtol 1e-6 "
+                      f"({it} iterations, status {st}; GPU: {gpu_iters}), setup timed apart",
+            "setup_ms": round((t1 - t0) * 1e3, 1), "iters": it, "cpu": cpu,
+            "nproc": os.cpu_count(), "host": platform.node()}
+
+    def errs(u):
+        d = u - xr
+        c, cr = float(f @ u), float(f @ xr)
+        return {"compliance_rel": abs(c - cr) / abs(cr),
+                "u_rel": float(np.linalg.norm(d) / np.linalg.norm(xr)),
+                "energy_rel": float(np.sqrt(max(d @ (K @ d), 0.0) / (xr @ (K @ xr))))}
+    err = {"reference": f"oracle PCG-GMG refined to rtol 1e-10 ({it + it_r} iterations)",
+           "gpu": errs(gpu_u), "oracle_rtol_1e-6": errs(xo)}
+    return base, err
+
+
+def ku_roofline(n, prec, reps, tune=True):
+    """The fine K.u in the smoother precision on an n^3 cantilever (2-level
+    hierarchy: only level 0 is used), launch shape from the library's
+    autotuner, timed with HIP events around reps back-to-back launches on the
+    stream they run on; algorithmic bytes = read u + write y + read E/s."""
+    import torch
+    import workloads
+    from paper_2604_26441_amd import simpgmg
+    dev = torch.device("cuda:0")
+    dims = (n, n, n)
+    rho = torch.tensor(workloads.uniform_rho(dims), dtype=torch.float64, device=dev)
+    h = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, n_levels=2 if n > 128 else 4,
+                                                        fine_prec=prec), rho)
+    shape = simpgmg.autotune(h) if tune else None
+    p = simpgmg.PRECISIONS[prec]
+    dt = torch.float64 if p == simpgmg.F64 else torch.float32
+    fixed = torch.tensor(workloads.cantilever_fixed(dims), device=dev).bool()
+    uk = torch.ones(3 * (n + 1) ** 3, dtype=dt, device=dev).masked_fill_(fixed, 0)
+    yk = torch.empty_like(uk)
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        simpgmg.apply_K(h, 0, p, uk, yk)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        simpgmg.apply_K(h, 0, p, uk, yk)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    us = ev0.elapsed_time(ev1) * 1e3 / reps
+    es = 8 if p == simpgmg.F64 else 4
+    nodes, nel = (n + 1) ** 3, n ** 3
+    byts = 2 * 3 * nodes * es + nel * es
+    h.close()
+    return {"mesh": f"{n}^3", "us": round(us, 3), "bytes": byts, "GBs": round(byts / us / 1e3, 1),
+            "GFLOPs": round(2 * 24 * 24 * nel / us / 1e3, 1),
+            "shape": shape[1 if prec == "bf16x3" else 0] if shape else None}
 
 
 def main():
@@ -121,6 +183,7 @@ def main():
         res = simpgmg.pcg_solve(h, f, u, rtol=1e-6, maxit=maxit, precond=precond)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        res["u"] = u
         return h, res, (t1 - t0) * 1e3, (t2 - t1) * 1e3
 
     o32 = opts(fine_prec=args.fine_prec)
@@ -142,13 +205,17 @@ def main():
         iters.append(res["iters"])
         status.append(res["status"])
         relres.append(res["rel_res_true"])
+        last_u = res["u"]
         if k != args.steps - 1:
             h.close()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t_start) * 1e3
 
-    # dominant-kernel timing: the fine K.u in the smoother precision, 200
-    # back-to-back launches on torch's current stream, HIP events around them
+    # the fine K.u in the smoother precision on the bench mesh: 200
+    # back-to-back launches on torch's current stream (the stream the library
+    # launches on), HIP events around them; then the same launches one at a
+    # time with 1 GiB written between them (the 256 MiB last-level cache holds
+    # none of the operands when a launch starts)
     prec = simpgmg.PRECISIONS[args.fine_prec]
     dt = torch.float64 if prec == simpgmg.F64 else torch.float32
     fixed = torch.tensor(workloads.cantilever_fixed(dims), device=dev).bool()
@@ -163,12 +230,25 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     ku_us = ev0.elapsed_time(ev1) * 1e3 / args.kernel_reps
+    flush = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+    cold = []
+    for k in range(20):
+        flush.fill_(float(k))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        simpgmg.apply_K(h, 0, prec, uk, yk)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        cold.append(e0.elapsed_time(e1) * 1e3)
+    del flush
+    ku_cold_us = float(np.mean(cold))
     es = 8 if prec == simpgmg.F64 else 4
     nodes, nel = (n + 1) ** 3, n ** 3
     ku_bytes = 2 * 3 * nodes * es + nel * es          # read u, write y, read E
     ku_flop = 2 * 24 * 24 * nel
     achieved = ku_bytes / (ku_us * 1e-6) / 1e9
     h.close()
+    ku_big = ku_roofline(256, args.fine_prec, 50) if not args.no_ku256 else None
 
     extra = {}
     if not args.no_compare:
@@ -192,9 +272,7 @@ def main():
         h.close()
         net.close()
 
-    traffic = None
-    if n == 80 and args.fine_prec == "bf16x3" and tuned is not None:
-        traffic = measured_traffic(tuned[1])
+    prof = measured_profile(args.fine_prec, ku_big["shape"]) if ku_big else None
 
     mean_solve = float(np.mean(solve_ms))
     line = {
@@ -214,15 +292,28 @@ def main():
         "solve_ms_std": round(float(np.std(solve_ms)), 3),
         "setup_ms": round(float(np.mean(setup_ms)), 3),
         "iters": iters, "status": status, "rel_res_true": relres,
-        "ku": {"kernel": "fine K.u (sgmg_apply_K level 0)", "us": round(ku_us, 3),
-               "GBs": round(achieved, 1), "GFLOPs": round(ku_flop / (ku_us * 1e-6) / 1e9, 1)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+        "ku": {"kernel": "fine K.u (sgmg_apply_K level 0)", "mesh": f"{n}^3", "us": round(ku_us, 3),
+               "GBs": round(achieved, 1), "GFLOPs": round(ku_flop / (ku_us * 1e-6) / 1e9, 1),
+               "cold_us": round(ku_cold_us, 3),
+               "cold_GBs": round(ku_bytes / (ku_cold_us * 1e-6) / 1e9, 1),
+               "note": "the 14.8 MB working set stays in the 8 x 4 MiB L2 and 256 MiB MALL between "
+                       "back-to-back launches; cold_* flush the MALL with a 1 GiB write first"},
         **extra,
     }
+    if ku_big:
+        a = ku_big["GBs"]
+        line["roofline"] = {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(a / HBM_PEAK_GBS, 4),
+                            "traffic": prof["traffic"] if prof else None,
+                            "kernel": f"fine K.u {args.fine_prec}", "mesh": ku_big["mesh"],
+                            "us": ku_big["us"], "bytes_per_launch": ku_big["bytes"],
+                            "shape": ku_big["shape"],
+                            "mfma_util": prof["mfma_util"] if prof else None,
+                            "note": "256^3 cantilever (16.8 M elements, 474 MB per launch): beyond "
+                                    "the caches, so HBM-bound; the bench mesh's figure is under ku"}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(n, int(round(np.mean(iters))))
+        u_host = last_u.cpu().numpy()
+        line["cpu_baseline"], line["error_vs_oracle"] = cpu_baseline(n, u_host, iters[-1])
     print(json.dumps(line), flush=True)
 
 

@@ -649,16 +649,15 @@ def traffic(n=80, reps=20):
 
 
 def kuprof(reps=20):
-    """Workload for counter profiles of the BF16-family fine K.u: for each of
-    the 80^3 and 256^3 cantilevers (rho = 0.5; the 256^3 one with 2 levels,
-    only its level 0 is used), BF16 and then BF16X3 STORE launches, reps
-    each, at the launch shape given on the command line as
-    ``80:rows:planes,256:rows:planes`` (default 80:4:8,256:4:16); then a
-    1 GiB device copy 4 times (counter calibration)."""
+    """Workload for counter profiles of the BF16-family fine K.u: on the 80^3
+    and 256^3 cantilevers (rho = 0.5; the 256^3 one with 2 levels, only its
+    level 0 is used), BF16 and then BF16X3 STORE launches, reps per launch
+    shape the autotuner can pick (TRAFFIC_SHAPES, in this order), all-ones
+    input on free DOFs; then a 1 GiB device copy 4 times (the counter
+    calibration: its FETCH_SIZE / WRITE_SIZE per dispatch are compared with
+    the 1 GiB it moves)."""
     dev = "cuda:0"
-    spec = sys.argv[2] if len(sys.argv) > 2 else "80:4:8,256:4:16"
-    shapes = {int(a): (int(b), int(c)) for a, b, c in (t.split(":") for t in spec.split(","))}
-    for n, (rows, planes) in shapes.items():
+    for n in (80, 256):
         dims = (n, n, n)
         rho = torch.tensor(workloads.uniform_rho(dims), dtype=torch.float64, device=dev)
         h = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, n_levels=2 if n > 128 else 4), rho)
@@ -666,12 +665,13 @@ def kuprof(reps=20):
         u = torch.ones(fixed.numel(), dtype=torch.float32, device=dev).masked_fill_(fixed, 0)
         y = torch.empty_like(u)
         for prec in ("bf16", "bf16x3"):
-            simpgmg.set_launch_shape(h, prec, rows, planes)
-            for _ in range(reps):
-                simpgmg.apply_K(h, 0, prec, u, y)
+            for rows, planes in TRAFFIC_SHAPES:
+                simpgmg.set_launch_shape(h, prec, rows, planes)
+                for _ in range(reps):
+                    simpgmg.apply_K(h, 0, prec, u, y)
         torch.cuda.synchronize()
         h.close()
-        print(json.dumps({"n": n, "shape": [rows, planes], "reps": reps}), flush=True)
+        print(json.dumps({"n": n, "reps": reps, "shapes": TRAFFIC_SHAPES}), flush=True)
     a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
     for _ in range(4):

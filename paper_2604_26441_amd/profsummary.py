@@ -3,6 +3,7 @@
   python -m paper_2604_26441_amd.profsummary RESULTS_DB [--match NAME --last N] [--solve]
   python -m paper_2604_26441_amd.profsummary --counters COUNTER_CSV
   python -m paper_2604_26441_amd.profsummary --traffic FETCH_CSV WRITE_CSV
+  python -m paper_2604_26441_amd.profsummary --kuprof FETCH_CSV WRITE_CSV SQ_CSV
 
 Prints the per-kernel totals (calls, total, average, share) and, with
 --match, the average duration of the last N dispatches whose kernel name
@@ -50,6 +51,46 @@ def traffic(fetch_csv, write_csv, reps, shapes):
             break
         fa, wb = sum(a) / reps, sum(b) / reps
         print(f"| {r} | {z} | {fa:.1f} | {wb:.1f} | {round(1024 * (fa * cf + wb * cw))} |")
+
+
+def kuprof(fetch_csv, write_csv, sq_csv, reps, shapes, meshes=(80, 256)):
+    """Counter summary of the kuprof workload: per mesh, precision and launch
+    shape (dispatch groups of the STORE fine K.u in workload order) the mean
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch), the calibrated HBM bytes
+    per launch and their ratio to the algorithmic bytes, and the matrix-core
+    busy fraction SQ_VALU_MFMA_BUSY_CYCLES / (32 SQ_BUSY_CYCLES): the first
+    sums over the 1024 SIMDs, the second over the 32 shader engines, so the
+    ratio is the mean share of a SIMD's cycles its matrix core was busy."""
+    f = _dispatches(fetch_csv, "FETCH_SIZE")
+    w = _dispatches(write_csv, "WRITE_SIZE")
+    mb = _dispatches(sq_csv, "SQ_VALU_MFMA_BUSY_CYCLES")
+    sb = _dispatches(sq_csv, "SQ_BUSY_CYCLES")
+    def pick(rows, pred):
+        return [float(r["Counter_Value"]) for r in rows if pred(r["Kernel_Name"], int(r["Grid_Size"]))]
+    big_copy = lambda n, g: "copyBuffer" in n and g >= 131072
+    cf = 1048576.0 / (sum(pick(f, big_copy)) / len(pick(f, big_copy)))
+    cw = 1048576.0 / (sum(pick(w, big_copy)) / len(pick(w, big_copy)))
+    print(f"calibration: 1 GiB copy, FETCH factor {cf:.4f}, WRITE factor {cw:.4f}")
+    ku = lambda n, g: "k_apply_fine_mfma<" in n and ", 0>" in n
+    fk, wk, mk, sk = pick(f, ku), pick(w, ku), pick(mb, ku), pick(sb, ku)
+    print("| mesh | prec | rows | planes | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | calibrated bytes per launch "
+          "| / algorithmic | MFMA busy |")
+    print("|---|---|---|---|---|---|---|---|---|")
+    i = 0
+    for n in meshes:
+        alg = 2 * 12 * (n + 1) ** 3 + 4 * n ** 3
+        for prec in ("bf16", "bf16x3"):
+            for r, z in shapes:
+                sl = slice(i * reps, (i + 1) * reps)
+                i += 1
+                a, b, m, q = fk[sl], wk[sl], mk[sl], sk[sl]
+                if min(len(a), len(b), len(m), len(q)) < reps:
+                    return
+                fa, wb = sum(a) / reps, sum(b) / reps
+                byts = round(1024 * (fa * cf + wb * cw))
+                util = sum(m) / (32.0 * sum(q))
+                print(f"| {n}^3 | {prec} | {r} | {z} | {fa:.1f} | {wb:.1f} | {byts} | {byts / alg:.3f} "
+                      f"| {util:.3f} |")
 
 
 def counters(path):
@@ -103,6 +144,7 @@ def main():
     ap.add_argument("db", nargs="?")
     ap.add_argument("--counters", default=None)
     ap.add_argument("--traffic", nargs=2, default=None, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--kuprof", nargs=3, default=None, metavar=("FETCH_CSV", "WRITE_CSV", "SQ_CSV"))
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--match", default=None)
     ap.add_argument("--last", type=int, default=200)
@@ -112,10 +154,13 @@ def main():
     if a.counters:
         counters(a.counters)
         return
+    # the shape order of experiments.TRAFFIC_SHAPES
+    shapes = [(r, z) for r in (4, 8) for z in (2, 4, 8, 16, 32)]
     if a.traffic:
-        # the shape order of experiments.TRAFFIC_SHAPES
-        shapes = [(r, z) for r in (4, 8) for z in (2, 4, 8, 16, 32)]
         traffic(a.traffic[0], a.traffic[1], a.reps, shapes)
+        return
+    if a.kuprof:
+        kuprof(a.kuprof[0], a.kuprof[1], a.kuprof[2], a.reps, shapes)
         return
     c = sqlite3.connect(a.db)
     rows = list(c.execute("select name, total_calls, total_duration, average, percentage "
