@@ -46,18 +46,20 @@ def test_batch_matches_single_solves_and_oracle():
         assert res[i]["rel_res_true"] < 1e-6
         xb, xs = np64(us[i]), np64(u1)
         assert np.linalg.norm(xb - xs) <= 1e-5 * np.linalg.norm(xs)
-    # oracle: compliance of the first item of the first system
-    d = dims[0]
-    fixed = workloads.cantilever_fixed(d).astype(bool)
-    E = mesh.simp_modulus(rhos[0], 3)
-    K = mesh.assemble(d, E, fixed=fixed)
-    fr = ~fixed
+    # oracle, for every item: the FP64 true residual of the returned u with the
+    # oracle's assembled operator, and its compliance against the direct solve
     import scipy.sparse.linalg as spla
-    ustar = np.zeros(fixed.size)
-    ustar[fr] = spla.spsolve(K[fr][:, fr].tocsc(), fs[0][fr])
-    x0 = np64(us[0])
-    assert abs(fs[0] @ x0 - fs[0] @ ustar) <= 1e-5 * abs(fs[0] @ ustar)
-    assert krylov.true_rel_residual(lambda v: K @ v, fs[0], x0) < 1e-6
+    for s, d in enumerate(dims):
+        fixed = workloads.cantilever_fixed(d).astype(bool)
+        K = mesh.assemble(d, mesh.simp_modulus(rhos[s], 3), fixed=fixed)
+        fr = ~fixed
+        lu = spla.splu(K[fr][:, fr].tocsc())
+        for i in [i for i, q in enumerate(item_sys) if q == s]:
+            ustar = np.zeros(fixed.size)
+            ustar[fr] = lu.solve(fs[i][fr])
+            x = np64(us[i])
+            assert krylov.true_rel_residual(lambda v: K @ v, fs[i], x) < 1e-6, (s, i)
+            assert abs(fs[i] @ x - fs[i] @ ustar) <= 1e-5 * abs(fs[i] @ ustar), (s, i)
 
 
 def test_batch_graph_replays_agree():
@@ -108,3 +110,31 @@ def test_concurrent_batch_equals_single_solves(workers):
         assert np.array_equal(np64(us[i]), np64(u1))
     with pytest.raises(simpgmg.SimpGmgError):
         simpgmg.pcg_solve_batch_concurrent(b, item_sys, [t64(f) for f in fs], us, workers=0)
+
+
+def test_batch_config3_every_item_meets_the_oracle():
+    """The whole batch workload (32 systems 2m x m x m, m in 8..24, up to the
+    48 x 24 x 24 system; random-field rho, p = 3; 1-4 random face loads each):
+    one persistent launch and the concurrent solve, every item converged with
+    the oracle's FP64 true residual of its u below rtol (matrix-free element
+    loop of the oracle)."""
+    from paper_2604_26441_amd import simpgmg
+    dims, rhos, item_sys, fs = workloads.batch_config()
+    assert max(d[0] for d in dims) == 48
+    opts = [simpgmg.default_options(*d, n_levels=0, dense_max=1000, fine_prec="f32") for d in dims]
+    b = simpgmg.setup_batch(opts, [t64(r) for r in rhos])
+    us = [t64(np.zeros_like(f)) for f in fs]
+    res, _ = simpgmg.pcg_solve_batch(b, item_sys, [t64(f) for f in fs], us, rtol=1e-6, maxit=300)
+    uc = [t64(np.zeros_like(f)) for f in fs]
+    resc, _ = simpgmg.pcg_solve_batch_concurrent(b, item_sys, [t64(f) for f in fs], uc,
+                                                 rtol=1e-6, maxit=300, workers=4)
+    for i, (s, f) in enumerate(zip(item_sys, fs)):
+        d = dims[s]
+        fixed = workloads.cantilever_fixed(d).astype(bool)
+        E = mesh.simp_modulus(rhos[s], 3)
+        for r, u in ((res[i], us[i]), (resc[i], uc[i])):
+            assert r["status"] == "converged", (i, d, r)
+            x = np64(u)
+            rel = np.linalg.norm(f - mesh.apply_K_elementwise(d, E, x, fixed=fixed)) / np.linalg.norm(f)
+            assert rel < 1e-6, (i, d, rel)
+            assert abs(rel - r["rel_res_true"]) < 1e-9, (i, d, rel, r)

@@ -144,3 +144,25 @@ def test_fullsize_heterogeneous_solves(p):
         r = f - mesh.apply_K_elementwise(dims, E, np64(u), fixed=fixed)
         rel = np.linalg.norm(r) / np.linalg.norm(f)
         assert rel < 1e-6 and abs(res["rel_res_true"] - rel) < 1e-9, (prec, rel, res)
+
+
+def test_fullsize_100cube_five_levels():
+    """The 100^3 cantilever of the warm-start workload (1 M elements, 3.09 M
+    DOF) with the automatic depth (5 levels: the 4-level coarsest would have
+    6,084 free DOFs, above the dense cutoff), FP32-GMG (BF16X3 fine level):
+    the oracle's residual of the returned u passes rtol and equals the
+    residual the solver reports."""
+    from paper_2604_26441_amd import simpgmg
+    dims = (100, 100, 100)
+    rho = workloads.uniform_rho(dims)
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    f = workloads.edge_load(dims)
+    h = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, n_levels=0, fine_prec="bf16x3"),
+                                t64(rho))
+    assert h.num_levels() == 5
+    u = t64(np.zeros_like(f))
+    res = simpgmg.pcg_solve(h, t64(f), u, rtol=1e-6, maxit=200)
+    assert res["status"] == "converged", res
+    r = f - mesh.apply_K_elementwise(dims, mesh.simp_modulus(rho, 3), np64(u), fixed=fixed)
+    rel = np.linalg.norm(r) / np.linalg.norm(f)
+    assert rel < 1e-6 and abs(res["rel_res_true"] - rel) < 1e-9, (rel, res)

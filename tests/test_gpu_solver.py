@@ -66,7 +66,7 @@ def test_vcycle_stencil_forms_match_oracle(dims, L, form):
     h = simpgmg.setup_hierarchy(o, t64(rho), lambda_override=lams)
     z = t64(np.zeros_like(r))
     simpgmg.vcycle(h, t64(r), z)
-    assert rel_err(np64(z), ref, ref) < 1e-4
+    assert rel_err(np64(z), ref, ref) < 1e-5     # FP32 level 1: the FP32 parity tolerance
     with pytest.raises(simpgmg.SimpGmgError, match="stencil_form"):
         simpgmg.setup_hierarchy(simpgmg.default_options(*dims, n_levels=L, stencil_form=3),
                                 t64(rho))
@@ -85,7 +85,9 @@ def test_vcycle_f32_close_to_oracle(prec):
     z = t64(np.zeros_like(r))
     simpgmg.vcycle(h, t64(r), z)
     ref = multigrid.vcycle(oh, r)
-    assert rel_err(np64(z), ref, ref) < 1e-4
+    # FP32 parity tolerance (max-norm, relative to max |z|); measured 0.3-2.6e-7
+    # for FP32 and BF16X3 on 24x12x12 to 40x20x20 random-field meshes
+    assert rel_err(np64(z), ref, ref) < 1e-5
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "bf16x2", "f64-mfma"])
