@@ -45,28 +45,6 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaWavesPerBlock = 4;
 
-__device__ inline double x_combine(double v) {
-  const int h = __double2hiint(v), l = __double2loint(v);
-  const auto rh = __builtin_amdgcn_permlane16_swap((unsigned)h, (unsigned)h, false, false);
-  const auto rl = __builtin_amdgcn_permlane16_swap((unsigned)l, (unsigned)l, false, false);
-  const int sh = __builtin_amdgcn_update_dpp(0, (int)rh[1], 0x111, 0xf, 0xf, true);
-  const int sl = __builtin_amdgcn_update_dpp(0, (int)rl[1], 0x111, 0xf, 0xf, true);
-  return __hiloint2double((int)rh[0], (int)rl[0]) + __hiloint2double(sh, sl);
-}
-__device__ inline void z_split(double v, double& lo, double& hi) {
-  const int h = __double2hiint(v), l = __double2loint(v);
-  const auto rh = __builtin_amdgcn_permlane32_swap((unsigned)h, (unsigned)h, false, false);
-  const auto rl = __builtin_amdgcn_permlane32_swap((unsigned)l, (unsigned)l, false, false);
-  lo = __hiloint2double((int)rh[0], (int)rl[0]);
-  hi = __hiloint2double((int)rh[1], (int)rl[1]);
-}
-
-__device__ inline int ep_node(const Grid& g, int x, int y, int z) { return x + g.Nx * (y + g.Ny * z); }
-
-// Epilogue operands of one owned node, fetched a step ahead of their use.
-template <typename T>
-struct EpIn { T x[3], b[3], di[3], dp[3]; unsigned fx; };
-
 // Raw buffer loads: an offset past the buffer's byte size returns zeros, so
 // halo and out-of-mesh operands need no branch (straight-line code keeps the
 // compiler's load-counter waits exact across the software pipeline).  Offsets
@@ -101,22 +79,6 @@ __device__ inline void bload3(__amdgpu_buffer_rsrc_t r, int off, double* v) {
 // Kernel-internal epilogue variant: EPI_STORE plus the x.y dot product.
 constexpr int kStoreDot = 3;
 
-struct EpRsrc { __amdgpu_buffer_rsrc_t u, fix, b, di, d, out; };
-
-// off3 = byte offset of the node's 3 components (kNoOffset: not owned)
-template <typename T, int MODE>
-__device__ inline void load_ep(const Epi<T>& ep, const EpRsrc& rs, int node, int off3,
-                               EpIn<T>& e) {
-  e.fx = __builtin_amdgcn_raw_buffer_load_b8(rs.fix, off3 == kNoOffset ? kNoOffset : node, 0, 0);
-  if (MODE == kStoreDot) bload3(rs.u, off3, e.x);
-  if (MODE == EPI_SMOOTH) bload3(rs.u, off3, e.x);
-  if (MODE == EPI_RESID || MODE == EPI_SMOOTH) bload3(rs.b, off3, e.b);
-  if (MODE == EPI_SMOOTH) {
-    bload3(rs.di, off3, e.di);
-    bload3(rs.d, ep.c1 != 0.0 ? off3 : kNoOffset, e.dp);
-  }
-}
-
 __device__ inline void bstore3(__amdgpu_buffer_rsrc_t r, int off, float a, float b, float c) {
   typedef unsigned u32x3 __attribute__((ext_vector_type(3)));
   const u32x3 v = {__float_as_uint(a), __float_as_uint(b), __float_as_uint(c)};
@@ -131,41 +93,6 @@ __device__ inline void bstore3(__amdgpu_buffer_rsrc_t r, int off, double a, doub
   const u32x2 w = {(unsigned)__double2loint(c), (unsigned)__double2hiint(c)};
   __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
   __builtin_amdgcn_raw_buffer_store_b64(w, r, off == kNoOffset ? kNoOffset : off + 16, 0, 0);
-}
-
-// Same arithmetic as the generic epilogue, specialised.  off3
-// = kNoOffset makes the stores fall outside the buffers (dropped) and the
-// returned dot term zero.
-template <typename T, int MODE>
-__device__ inline double store_ep(const Epi<T>& ep, const EpRsrc& rs, int off3, const EpIn<T>& e,
-                                  const T (&y)[3]) {
-  double dot = 0.0;
-  T o[3], dd[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const bool fixed = (e.fx >> c) & 1u;
-    if (MODE == EPI_STORE || MODE == kStoreDot) {
-      o[c] = fixed ? (T)0 : y[c];
-      if (MODE == kStoreDot) dot += (double)e.x[c] * (double)o[c];
-    } else if (MODE == EPI_RESID) {
-      o[c] = fixed ? (T)0 : e.b[c] - y[c];
-    } else {
-      const T r = e.b[c] - y[c];
-      dd[c] = fixed ? (T)0 : (T)ep.c1 * e.dp[c] + (T)ep.c2 * e.di[c] * r;
-      o[c] = fixed ? (T)0 : e.x[c] + dd[c];
-    }
-  }
-  bstore3(rs.out, off3, o[0], o[1], o[2]);
-  if (MODE == EPI_SMOOTH) {
-    if (ep.store_d) bstore3(rs.d, off3, dd[0], dd[1], dd[2]);
-    if (ep.out64 && off3 != kNoOffset) {
-      const size_t b3 = (size_t)(off3 / (int)sizeof(T));
-      ep.out64[b3] = (double)o[0];
-      ep.out64[b3 + 1] = (double)o[1];
-      ep.out64[b3 + 2] = (double)o[2];
-    }
-  }
-  return off3 == kNoOffset ? 0.0 : dot;
 }
 
 // Per-wave LDS of the BF16-family kernel:
@@ -471,28 +398,59 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
 
 // ---------------------------------------------------------------------------
 // FP64 fine operator on v_mfma_f64_16x16x4_f64 (outer PCG products, FP64
-// smoothing), same tiles, carries and ownership as the BF16 kernel.  K = 24
-// inputs take six k-steps of 4: at step s, lane group q supplies value s of
-// its node pair, so A holds K_e[row m][input (q, s)] per (h, s).  With the
-// row order of the A table (build_mfma_atab64), lane group g holds node g's
-// components in registers 0..2 as in the FP32 kernel, so the x/y/z
-// combination is the same.  Exact products, FP64 accumulation.
+// smoothing, power iteration): the tiles, carries and plane-level pipeline of
+// the BF16-family kernel with FP64 node records in LDS and no split.  K = 24
+// inputs take six k-steps of 4: at step st lane group q (node pair (dy, dz))
+// supplies value st of its pair, so A holds K_e[row m][input (q, st)] per
+// (h, st).  This MFMA returns row m in lane group m mod 4, register m / 4
+// (measured on gfx950), so the A-table rows m = 4 (dx + 2 dz) + c put
+// component c in lane group c and node (dx, dz) in register dx + 2 dz, as in
+// the BF16 kernel.  Exact products, FP64 accumulation.
+template <int YC>
+struct FineLds64 {
+  static constexpr int kRow = 17 * 24;               // 17 nodes x 3 doubles
+  static constexpr int kPlane = (YC + 1) * kRow;
+  static constexpr int kU = (3 * kPlane + 15) / 16 * 16;
+  static constexpr int kORow = 16 * 32;              // 16 columns x 4 doubles
+  static constexpr int kWave = kU + (YC - 1) * kORow;
+};
+
+__device__ inline double dpp_shr1(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x111, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x111, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ inline double bpermute(int addr, double v) {
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+__device__ inline double bload1d(__amdgpu_buffer_rsrc_t r, int off) {
+  const auto t = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  return __hiloint2double((int)t[1], (int)t[0]);
+}
+
 template <int YC, int MODE>
 __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma64(
     Grid g, const double* __restrict__ E, const double* __restrict__ atab,
     const double* __restrict__ u, const uint8_t* __restrict__ fixn, Epi<double> ep, int zchunk,
     int ntx, int nty, int ntiles) {
   typedef double f64x4 __attribute__((ext_vector_type(4)));
+  using LD = FineLds64<YC>;
+  static_assert(YC == 4 || YC == 8, "tile rows");
+  __shared__ __attribute__((aligned(16))) unsigned char lds_all[kMfmaWavesPerBlock * LD::kWave];
   const int lane = threadIdx.x & 63;
   // wave index made wave-uniform, so all tile arithmetic stays scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  unsigned char* const lds = lds_all + wave * LD::kWave;
   const int tile = xcd_block(blockIdx.x, gridDim.x) * kMfmaWavesPerBlock + wave;
   const int tx = tile % ntx, tt = tile / ntx, ty = tt % nty, tz = tt / nty;
   const int grp = lane >> 4, n = lane & 15;
   const int xs = tx * 15, ys = ty * (YC - 1), zs = tz * zchunk;
   const int ex = xs - 1 + n;
   const int dy_in = grp & 1, dz_in = grp >> 1;
-  const bool x_ok = ex >= 0 && ex < g.nx;
 
   double a0[6], a1[6];
 #pragma unroll
@@ -501,97 +459,210 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma64(
     a1[st] = atab[(6 + st) * 64 + lane];
   }
 
-  struct In { double v[6]; double es; };
   const int zend = tile < ntiles ? min(zs + zchunk, g.Nz) : zs - 1;
   const size_t nvec = (size_t)g.n * sizeof(double);
   const __amdgpu_buffer_rsrc_t ru = make_rsrc(u, nvec);
   const __amdgpu_buffer_rsrc_t re = make_rsrc(E, (size_t)g.nel * sizeof(double));
-  EpRsrc rs;
-  rs.u = ru;
-  rs.fix = make_rsrc(fixn, (size_t)g.Nn);
-  rs.b = make_rsrc(ep.b, MODE == EPI_RESID || MODE == EPI_SMOOTH ? nvec : 0);
-  rs.di = make_rsrc(ep.dinv, MODE == EPI_SMOOTH ? nvec : 0);
-  rs.d = make_rsrc(ep.d, MODE == EPI_SMOOTH ? nvec : 0);
-  rs.out = make_rsrc(ep.out, ep.out ? nvec : 0);   // no output: every store is dropped
-  auto load_in = [&](int ey, int ez, In& in) {
-    const bool yz_ok = (unsigned)ey < (unsigned)g.ny && (unsigned)ez < (unsigned)g.nz && ez < zend;
-    const bool ok = x_ok & yz_ok;     // as in the FP32 kernel: one per-lane select
-    const int node = ex + g.Nx * ((ey + dy_in) + g.Ny * (ez + dz_in));
-    const int off = ok ? node * 24 : kNoOffset;
-    bload3(ru, off, in.v);
-    bload3(ru, ok ? off + 24 : kNoOffset, in.v + 3);
-    const auto t = __builtin_amdgcn_raw_buffer_load_b64(
-        re, ok ? 8 * (ex + g.nx * (ey + g.ny * ez)) : kNoOffset, 0, 0);
-    in.es = __hiloint2double((int)t[1], (int)t[0]);
+  const __amdgpu_buffer_rsrc_t rfix = make_rsrc(fixn, (size_t)g.Nn);
+  const __amdgpu_buffer_rsrc_t rb = make_rsrc(ep.b, MODE == EPI_RESID || MODE == EPI_SMOOTH ? nvec : 0);
+  const __amdgpu_buffer_rsrc_t rdi = make_rsrc(ep.dinv, MODE == EPI_SMOOTH ? nvec : 0);
+  const __amdgpu_buffer_rsrc_t rd = make_rsrc(ep.d, MODE == EPI_SMOOTH ? nvec : 0);
+  const __amdgpu_buffer_rsrc_t rout = make_rsrc(ep.out, ep.out ? nvec : 0);   // NULL: stores dropped
+
+  // two-part offsets with kPoison parts, as in the BF16-family kernel
+  // (vectors below 2^30 bytes: mfma64_size_ok)
+  auto off2 = [](int a, int b) { return (int)((unsigned)a + (unsigned)b); };
+  auto part = [](bool ok, int v) { return ok ? v : kPoison; };
+
+  // node planes: load i, lane l < 51 carries node xs - 1 + l % 17 of node
+  // row k = 3 i + l / 17 (rows 0 .. YC of the tile)
+  constexpr int NU = (YC + 3) / 3;
+  const int um = lane % 17, uk = lane / 17;
+  int u_lane[NU];
+  bool u_on[NU];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) {
+    const int k = 3 * i + uk;
+    u_on[i] = lane < 51 && k <= YC;
+    u_lane[i] = part(u_on[i] && (unsigned)(xs - 1 + um) < (unsigned)g.Nx &&
+                         (unsigned)(ys - 1 + k) < (unsigned)g.Ny,
+                     24 * (xs - 1 + um + g.Nx * (ys - 1 + k)));
+  }
+  double uv[NU][3];
+  auto load_u = [&](int P, bool need) {
+    const int pp = part(need && (unsigned)P < (unsigned)g.Nz, 24 * g.Nx * g.Ny * P);
+#pragma unroll
+    for (int i = 0; i < NU; ++i) bload3(ru, off2(u_lane[i], pp), uv[i]);
   };
-  auto contract = [&](const In& in, f64x4& c0, f64x4& c1) {
+  auto store_u = [&](int P) {
+    unsigned char* const slot = lds + ((P + 3) % 3) * LD::kPlane + uk * LD::kRow + um * 24;
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+      if (u_on[i]) {
+        double* q = (double*)(slot + 3 * i * LD::kRow);
+        q[0] = uv[i][0];
+        q[1] = uv[i][1];
+        q[2] = uv[i][2];
+      }
+    }
+  };
+  // B operands of element row r: lane group (dy, dz) reads the six values of
+  // nodes (n, n + 1) of node row r + dy in the slot of plane ez + dz
+  auto read_b = [&](int base, int r, double (&b)[6]) {
+    const double* q = (const double*)(lds + base + r * LD::kRow);
+#pragma unroll
+    for (int st = 0; st < 6; ++st) b[st] = q[st];
+  };
+  auto contract = [&](const double (&b)[6], f64x4& c0, f64x4& c1) {
     c0 = f64x4{0.0, 0.0, 0.0, 0.0};
     c1 = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int st = 0; st < 6; ++st) {
-      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[st], in.v[st], c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[st], in.v[st], c1, 0, 0, 0);
+      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[st], b[st], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[st], b[st], c1, 0, 0, 0);
     }
-    c0 *= in.es;
-    c1 *= in.es;
-  };
-  const bool ep_lane = grp == 0 && n >= 1 && ex < g.Nx;
-  auto owns = [&](int r, int ez) {
-    const bool uni = r >= 1 && ez >= zs && ez < zend && ys - 1 + r < g.Ny;   // wave-uniform
-    return ep_lane & uni;
   };
 
-  double zc[YC][3];
+  // element moduli: load i, lane l holds column l & 15 of element row
+  // 4 i + l / 16; zero outside the mesh
+  constexpr int NE = YC / 4;
+  int e_lane[NE];
 #pragma unroll
-  for (int r = 0; r < YC; ++r) zc[r][0] = zc[r][1] = zc[r][2] = 0.0;
-  double dot = 0.0;
-  // inputs 2 steps ahead, epilogue operands 2 steps ahead (rings of 4 slots)
-  In p[4];
-  EpIn<double> e[4];
-  auto fetch_in = [&](int r, int ez) {
-    const int rr = r + 2 < YC ? r + 2 : r + 2 - YC;
-    load_in(ys - 1 + rr, r + 2 < YC ? ez : ez + 1, p[(r + 2) & 3]);
+  for (int i = 0; i < NE; ++i) {
+    const int ey = ys - 1 + 4 * i + grp;
+    e_lane[i] = part((unsigned)ex < (unsigned)g.nx && (unsigned)ey < (unsigned)g.ny,
+                     8 * (ex + g.nx * ey));
+  }
+  double ev[NE], esc[NE];
+  auto load_e = [&](int ez, bool need) {
+    const int pe = part(need && (unsigned)ez < (unsigned)g.nz, 8 * g.nx * g.ny * ez);
+#pragma unroll
+    for (int i = 0; i < NE; ++i) ev[i] = bload1d(re, off2(e_lane[i], pe));
   };
-  auto fetch_ep = [&](int r, int ez) {
-    const int rr = r + 2 < YC ? r + 2 : r + 2 - YC;
-    const int zz = r + 2 < YC ? ez : ez + 1;
-    const int nd = ep_node(g, ex, ys - 1 + rr, zz);
-    load_ep<double, MODE>(ep, rs, nd, owns(rr, zz) ? 24 * nd : kNoOffset, e[(r + 2) & 3]);
-  };
-  load_in(ys - 1, zs - 1, p[0]);
-  load_in(ys, zs - 1, p[1]);
-  e[0].fx = e[1].fx = 7u;
-  for (int ez = zs - 1; ez < zend; ++ez) {
-    double yc[3] = {0.0, 0.0, 0.0};
+
+  // node-layout epilogue: group i, lane l < 60 owns node xs + l % 15 of node
+  // row 1 + 4 i + l / 15
+  constexpr int NG = (YC + 2) / 4;
+  constexpr int NV = MODE == EPI_SMOOTH ? 4 : (MODE == EPI_RESID || MODE == kStoreDot) ? 1 : 0;
+  const int oj = lane % 15, orr = lane / 15;
+  int o_lane[NG], f_lane[NG], o_lds[NG];
 #pragma unroll
-    for (int r = 0; r < YC; ++r) {
-      fetch_in(r, ez);
-      fetch_ep(r, ez);
-      f64x4 v0, v1;
-      contract(p[r & 3], v0, v1);
-      double yv[3];
+  for (int i = 0; i < NG; ++i) {
+    const int rr = 1 + 4 * i + orr;
+    const bool on = lane < 60 && rr <= YC - 1 && xs + oj < g.Nx && ys - 1 + rr < g.Ny;
+    o_lane[i] = part(on, 24 * (xs + oj + g.Nx * (ys - 1 + rr)));
+    f_lane[i] = part(on, xs + oj + g.Nx * (ys - 1 + rr));
+    o_lds[i] = LD::kU + (min(rr, YC - 1) - 1) * LD::kORow + (oj + 1) * 32;
+  }
+  double vv[NG][NV > 0 ? NV : 1][3];
+  unsigned fv[NG];
+  auto load_v = [&](int ez) {
+    const bool own = ez >= zs && ez < zend;
+    const int po = part(own, 24 * g.Nx * g.Ny * ez), pf = part(own, g.Nx * g.Ny * ez);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        yv[c] = v0[c] + yc[c];
-        yc[c] = v1[c];
-      }
-      if (r >= 1) {
-        double fin[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          double lo, hi;
-          z_split(x_combine(yv[c]), lo, hi);
-          fin[c] = lo + zc[r][c];
-          zc[r][c] = hi;
-        }
-        const int nd = ep_node(g, ex, ys - 1 + r, ez);
-        dot += store_ep<double, MODE>(ep, rs, owns(r, ez) ? 24 * nd : kNoOffset, e[r & 3], fin);
+    for (int i = 0; i < NG; ++i) {
+      fv[i] = __builtin_amdgcn_raw_buffer_load_b8(rfix, off2(f_lane[i], pf), 0, 0);
+      const int o = off2(o_lane[i], po);
+      if (MODE == EPI_SMOOTH) {
+        bload3(ru, o, vv[i][0]);
+        bload3(rb, o, vv[i][1]);
+        bload3(rdi, o, vv[i][2]);
+        bload3(rd, ep.c1 != 0.0 ? o : kNoOffset, vv[i][3]);
+      } else if (MODE == EPI_RESID) {
+        bload3(rb, o, vv[i][0]);
+      } else if (MODE == kStoreDot) {
+        bload3(ru, o, vv[i][0]);
       }
     }
+  };
+  double dot = 0.0;
+  auto finish_plane = [&](int ez) {
+    const int po = part(ez >= zs && ez < zend, 24 * g.Nx * g.Ny * ez);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      const double* yq = (const double*)(lds + o_lds[i]);
+      const double yv[3] = {yq[0], yq[1], yq[2]};
+      const int o = off2(o_lane[i], po);
+      const bool mine = (unsigned)o < (unsigned)kPoison;
+      double out[3], dd[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const bool fixed = (fv[i] >> c) & 1u;
+        if (MODE == EPI_STORE || MODE == kStoreDot) {
+          out[c] = fixed ? 0.0 : yv[c];
+          if (MODE == kStoreDot && mine) dot += vv[i][0][c] * out[c];
+        } else if (MODE == EPI_RESID) {
+          out[c] = fixed ? 0.0 : vv[i][0][c] - yv[c];
+        } else {
+          const double r = vv[i][1][c] - yv[c];
+          dd[c] = fixed ? 0.0 : ep.c1 * vv[i][3][c] + ep.c2 * vv[i][2][c] * r;
+          out[c] = fixed ? 0.0 : vv[i][0][c] + dd[c];
+        }
+      }
+      bstore3(rout, o, out[0], out[1], out[2]);
+      if (MODE == EPI_SMOOTH) {
+        if (ep.store_d) bstore3(rd, o, dd[0], dd[1], dd[2]);
+        if (ep.out64 && mine) {
+          double* q = ep.out64 + (o >> 3);
+          q[0] = out[0];
+          q[1] = out[1];
+          q[2] = out[2];
+        }
+      }
+    }
+  };
+
+  // lane (c, n) of the matrix-core layout writes its node sum to O column n
+  const int o_w = LD::kU + n * 32 + grp * 8;
+  double zc[YC];
+#pragma unroll
+  for (int r = 0; r < YC; ++r) zc[r] = 0.0;
+
+  load_u(zs - 1, true);
+  store_u(zs - 1);
+  load_u(zs, true);
+  store_u(zs);
+  load_u(zs + 1, zs + 1 <= zend);
+  load_e(zs - 1, true);
+  for (int ez = zs - 1; ez < zend; ++ez) {
+    store_u(ez + 2);                              // loaded during the previous plane
+#pragma unroll
+    for (int i = 0; i < NE; ++i) esc[i] = ev[i];
+    load_u(ez + 3, ez + 3 <= zend);
+    load_e(ez + 1, ez + 1 < zend);
+    load_v(ez);
+    const int base = ((ez + dz_in + 3) % 3) * LD::kPlane + dy_in * LD::kRow + n * 24;
+    double bc[6], bn[6];
+    read_b(base, 0, bc);
+    double yc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < YC; ++r) {
+      if (r + 1 < YC) read_b(base, r + 1, bn);
+      const double sc = bpermute(4 * (n + 16 * (r & 3)), esc[r >> 2]);
+      f64x4 c0, c1;
+      contract(bc, c0, c1);
+      double t[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        t[k] = c0[k] * sc + yc[k];    // y: dy = 0 of this row + dy = 1 of the row below
+        yc[k] = c1[k] * sc;
+      }
+      // x: dx = 0 of element n + dx = 1 of element n - 1; z: plane ez + plane ez - 1
+      const double w0 = t[0] + dpp_shr1(t[1]);
+      const double w1 = t[2] + dpp_shr1(t[3]);
+      const double fin = w0 + zc[r];
+      zc[r] = w1;
+      if (r >= 1) *(double*)(lds + o_w + (r - 1) * LD::kORow) = fin;
+      if (r + 1 < YC) {
+#pragma unroll
+        for (int st = 0; st < 6; ++st) bc[st] = bn[st];
+      }
+    }
+    finish_plane(ez);
   }
   if (MODE == kStoreDot) {
-    const double vv[1] = {dot};
-    grid_sum<1>(vv, ep.ws);
+    const double vd[1] = {dot};
+    grid_sum<1>(vd, ep.ws);
   }
 }
 
@@ -692,22 +763,23 @@ void launch_apply_fine_mfma64(const Grid& g, int rows, int zchunk, const double*
 }
 
 bool mfma64_size_ok(const Grid& g) {
-  return (size_t)g.n * sizeof(double) < ((size_t)1 << 31) - 64;
+  return (size_t)g.n * sizeof(double) < ((size_t)1 << 30) - 64;
 }
 
 // Host: FP64 A operand, [h][step][lane]: row m = lane % 16 of half h, input
 // (q = lane / 16, step) = node (step / 3, q & 1, q >> 1) component step % 3.
 // The FP64 MFMA returns row m in lane group m % 4, register m / 4 (measured
 // on gfx950; the FP32 16x16 layout is group m / 4, register m % 4), so row
-// m = (dx + 2 dz) + 4 c carries node (dx, h, dz), component c: the lane group
-// then holds one node's 3 components, as in the BF16 kernel.
+// m = 4 (dx + 2 dz) + c carries component c of node (dx, h, dz): lane group c
+// then holds component c and register dx + 2 dz the node, as in the BF16
+// kernel (c = 3: zero row).
 void build_mfma_atab64(const KeTables& kt, double* out /* 2*6*64 */) {
   for (int h = 0; h < 2; ++h)
     for (int st = 0; st < 6; ++st)
       for (int lane = 0; lane < 64; ++lane) {
         const int m = lane & 15, q = lane >> 4;
-        const int go = m & 3, c = m >> 2;
-        const int dx = go & 1, dz = go >> 1;
+        const int c = m & 3, k = m >> 2;
+        const int dx = k & 1, dz = k >> 1;
         const int aout = dx + 2 * h + 4 * dz;
         const int bin = (st / 3) + 2 * (q & 1) + 4 * (q >> 1);
         out[(h * 6 + st) * 64 + lane] =
