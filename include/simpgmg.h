@@ -306,6 +306,26 @@ int sgmg_pcg_solve_batch(sgmg_batch* b, int nitems, const int* item_sys, const d
                          double* const* u, double rtol, int maxit, sgmg_solve_info* infos,
                          double* total_ms, void* stream);
 
+/* The same items solved stage by stage: every stage of the outer PCG (Sec.
+ * 3.6) and of the V-cycle (Eq. vcycle) is one launch over all items, with as
+ * many workgroups per item as its level has work (so the whole device works
+ * on each stage, whatever the item sizes).  Two captured graphs are replayed
+ * from a host loop: a prologue (r = f - K u in FP64, V-cycle, p = z, r.z)
+ * and one PCG iteration (q = K p, alpha, x and r, V-cycle, beta, p); per-item
+ * flags copied in before each replay select the items that take part.  After
+ * every iteration the host reads each item's scalars; an item whose
+ * recursive residual passes rtol runs the prologue, which is its FP64
+ * true-residual check and, if that fails, its restart (beta = 0).  Same
+ * operators and acceptance as sgmg_pcg_solve with Fletcher-Reeves beta; the
+ * level operators are those of sgmg_pcg_solve_batch (FP32 vector-ALU level
+ * 0 inside the V-cycle, FP64 elsewhere), reductions per item in a fixed
+ * order.  All systems must share the smoothing step counts.  Work vectors
+ * and graphs are built on the first call for an item set.  *total_ms: wall
+ * time of the whole solve on the stream.  Synchronises once per iteration. */
+int sgmg_pcg_solve_batch_staged(sgmg_batch* b, int nitems, const int* item_sys,
+                                const double* const* f, double* const* u, double rtol, int maxit,
+                                sgmg_solve_info* infos, double* total_ms, void* stream);
+
 /* The same items solved by nworkers host threads (1..16), each with a HIP
  * stream of its own: a worker takes whole systems, largest DOFs x load
  * cases first, and solves that system's items in item order with

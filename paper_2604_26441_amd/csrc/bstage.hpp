@@ -1,0 +1,58 @@
+// Host interface of the stage-batched PCG-GMG kernels (kernels_bstage.hip).
+#pragma once
+#include "batch.hpp"
+
+namespace sgmg {
+
+// Per-item device scalars, kBsScalars doubles per item.
+enum BsScalar {
+  kBsFF = 0,      // f.f
+  kBsRR = 1,      // r.r of the last update (prologue: of the true residual)
+  kBsPQ = 2,      // p.q
+  kBsAlpha = 3,   // rz / p.q (0 when p.q is not positive and finite)
+  kBsRZ = 4,      // r.z of the current search direction
+  kBsRZNew = 5,   // r.z of the last V-cycle
+  kBsBeta = 6,
+  kBsScalars = 8
+};
+
+// A stage grid: entry b = (item, local block) of workgroup b; the entries of
+// one item are contiguous, starting at start[item], count[item] of them.
+struct BsTable {
+  const int2* blk = nullptr;
+  int n = 0;
+  const int* start = nullptr;
+  const int* count = nullptr;
+};
+
+struct BsArgs {
+  const BSys* sys;
+  const BItem* items;
+};
+
+int bs_threads();
+int bs_coarse_rows();
+void bs_fine64_res(const BsArgs& a, const BsTable& t, const int* flags, double* part, hipStream_t s);
+void bs_fine64_store_dot(const BsArgs& a, const BsTable& t, const int* flags, double* part,
+                         hipStream_t s);
+void bs_finalize(const BsTable& t, int nitems, int nv, const double* part, const int* flags,
+                 int what, double* scal, hipStream_t s);
+void bs_update_xr(const BsArgs& a, const BsTable& t, const int* flags, const double* scal,
+                  double* part, hipStream_t s);
+void bs_entry(const BsArgs& a, const BsTable& t, const int* flags, hipStream_t s);
+void bs_dot_rz(const BsArgs& a, const BsTable& t, const int* flags, int set_p, double* part,
+               hipStream_t s);
+void bs_update_p(const BsArgs& a, const BsTable& t, const int* flags, const double* scal,
+                 hipStream_t s);
+void bs_smooth0(const BsArgs& a, const BsTable& t, const int* flags, int post, int k, int cin,
+                int last, hipStream_t s);
+void bs_resid0(const BsArgs& a, const BsTable& t, const int* flags, int cin, hipStream_t s);
+void bs_smoothL(const BsArgs& a, const BsTable& t, const int* flags, int l, int cin, hipStream_t s);
+void bs_residL(const BsArgs& a, const BsTable& t, const int* flags, int l, int cin, hipStream_t s);
+void bs_restrict(const BsArgs& a, const BsTable& t, const int* flags, int l, hipStream_t s);
+void bs_coarse(const BsArgs& a, const BsTable& tg, const BsTable& tm, const int* flags,
+               hipStream_t s);
+void bs_prolong(const BsArgs& a, const BsTable& t, const int* flags, int l, int cfine, int ccoarse,
+                hipStream_t s);
+
+}  // namespace sgmg

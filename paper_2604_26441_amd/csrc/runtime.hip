@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "batch.hpp"
+#include "bstage.hpp"
 #include "kernels.hpp"
 #include "unet.hpp"
 
@@ -1807,6 +1808,20 @@ struct sgmg_batch {
   hipGraphExec_t graph = nullptr;
   int g_nitems = -1, g_maxit = -1, g_bs = -1;
   double g_rtol = -1.0;
+  // stage-batched solve of the cached item set: stage tables, per-item
+  // partials, scalars and active flags, the prologue and iteration graphs
+  struct Staged {
+    bool ready = false;
+    void* dmem = nullptr;
+    BsTable tv, ts[8], tr[8], tcg, tcm;
+    double* part = nullptr;
+    double* scal = nullptr;
+    int* flags = nullptr;          // [0, n): prologue, [n, 2n): iteration
+    int* h_flags = nullptr;        // pinned mirror
+    double* h_scal = nullptr;      // pinned mirror
+    int Lmax = 0, steps0 = 0, stepsL = 0;
+    hipGraphExec_t g_pro = nullptr, g_it = nullptr;
+  } st;
 };
 
 namespace {
@@ -1816,7 +1831,18 @@ void batch_drop_graph(sgmg_batch* b) {
   b->graph = nullptr;
 }
 
+void batch_free_staged(sgmg_batch* b) {
+  auto& st = b->st;
+  if (st.g_pro) hipGraphExecDestroy(st.g_pro);
+  if (st.g_it) hipGraphExecDestroy(st.g_it);
+  if (st.dmem) hipFree(st.dmem);
+  if (st.h_flags) hipHostFree(st.h_flags);
+  if (st.h_scal) hipHostFree(st.h_scal);
+  st = sgmg_batch::Staged{};
+}
+
 void batch_free_items(sgmg_batch* b) {
+  batch_free_staged(b);
   for (void* p : b->item_mem) hipFree(p);
   b->item_mem.clear();
   b->h_items.clear();
@@ -1934,6 +1960,188 @@ int batch_launch(sgmg_batch* b, int nitems, double rtol, int maxit, int bs, hipS
     b->g_nitems = nitems; b->g_rtol = rtol; b->g_maxit = maxit; b->g_bs = bs;
   }
   SGMG_HIP(hipGraphLaunch(b->graph, s));
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Stage-batched solve.
+//   One V-cycle of every flagged item as a sequence of stage launches.  cur
+//   bit l = ping-pong buffer of level l's iterate; every item has the same
+//   smoothing step counts, so the sequence is the same for all of them; at
+//   each level only items for which the level is above their coarsest take
+//   part (tables ts, tr).
+void bs_vcycle(const sgmg_batch::Staged& st, const BsArgs& a, const int* flags, hipStream_t s) {
+  unsigned cur = 0u;
+  auto cb = [&](int l) { return (int)((cur >> l) & 1u); };
+  auto flip = [&](int l) { cur ^= 1u << l; };
+  for (int l = 0; l < st.Lmax - 1; ++l) {
+    const int steps = l == 0 ? st.steps0 : st.stepsL;
+    for (int k = 1; k < steps; ++k) {
+      if (l == 0) bs_smooth0(a, st.ts[0], flags, 0, k, cb(0), 0, s);
+      else bs_smoothL(a, st.ts[l], flags, l, cb(l), s);
+      flip(l);
+    }
+    if (l == 0) bs_resid0(a, st.ts[0], flags, cb(0), s);
+    else bs_residL(a, st.ts[l], flags, l, cb(l), s);
+    bs_restrict(a, st.tr[l], flags, l, s);
+    cur &= ~(1u << (l + 1));
+  }
+  bs_coarse(a, st.tcg, st.tcm, flags, s);
+  for (int l = st.Lmax - 2; l >= 0; --l) {
+    const int steps = l == 0 ? st.steps0 : st.stepsL;
+    bs_prolong(a, st.ts[l], flags, l, cb(l), cb(l + 1), s);
+    for (int k = 0; k < steps; ++k) {
+      if (l == 0) bs_smooth0(a, st.ts[0], flags, 1, k, cb(0), k == steps - 1, s);
+      else bs_smoothL(a, st.ts[l], flags, l, cb(l), s);
+      flip(l);
+    }
+  }
+}
+
+// Prologue (flags [0, n)): r = f - K u and (f.f, r.r), then z = V(r), p = z,
+// rz.  It is also the true-residual check and restart of the iteration.
+void bs_prologue(const sgmg_batch* b, const BsArgs& a, int n, hipStream_t s) {
+  const auto& st = b->st;
+  const int* fl = st.flags;
+  bs_fine64_res(a, st.ts[0], fl, st.part, s);
+  bs_finalize(st.ts[0], n, 2, st.part, fl, 0, st.scal, s);
+  bs_entry(a, st.tv, fl, s);
+  bs_vcycle(st, a, fl, s);
+  bs_dot_rz(a, st.tv, fl, 1, st.part, s);
+  bs_finalize(st.tv, n, 1, st.part, fl, 4, st.scal, s);
+}
+
+// One PCG iteration (flags [n, 2n)): q = K p, alpha, x and r, V-cycle, beta, p.
+void bs_iteration(const sgmg_batch* b, const BsArgs& a, int n, hipStream_t s) {
+  const auto& st = b->st;
+  const int* fl = st.flags + n;
+  bs_fine64_store_dot(a, st.ts[0], fl, st.part, s);
+  bs_finalize(st.ts[0], n, 1, st.part, fl, 1, st.scal, s);
+  bs_update_xr(a, st.tv, fl, st.scal, st.part, s);
+  bs_finalize(st.tv, n, 1, st.part, fl, 2, st.scal, s);
+  bs_vcycle(st, a, fl, s);
+  bs_dot_rz(a, st.tv, fl, 0, st.part, s);
+  bs_finalize(st.tv, n, 1, st.part, fl, 3, st.scal, s);
+  bs_update_p(a, st.tv, fl, st.scal, s);
+}
+
+int bs_capture(sgmg_batch* b, void (*body)(const sgmg_batch*, const BsArgs&, int, hipStream_t),
+               int n, hipGraphExec_t* out) {
+  if (!b->cap) SGMG_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+  SGMG_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+  body(b, BsArgs{b->d_sys, b->d_items}, n, b->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->cap, &g);
+  if (e != hipSuccess) { set_error(std::string("staged batch capture: ") + hipGetErrorString(e)); return SGMG_EHIP; }
+  const hipError_t e2 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e2 != hipSuccess) { *out = nullptr; set_error("staged batch graph instantiate failed"); return SGMG_EHIP; }
+  return 0;
+}
+
+// Stage tables, partials, scalars and flags of the cached item set, and the
+// two graphs.
+int bs_prepare(sgmg_batch* b, int n, hipStream_t s) {
+  auto& st = b->st;
+  if (st.ready) return 0;
+  const BSys* hs0 = nullptr;
+  std::vector<BSys> hsys(b->hs.size());
+  for (size_t k = 0; k < b->hs.size(); ++k) hsys[k] = make_bsys(b->hs[k]);
+  st.Lmax = 0;
+  for (int i = 0; i < n; ++i) {
+    const BSys& S = hsys[b->h_items[i].sys];
+    if (!hs0) hs0 = &S;
+    if (S.lev[0].steps != hs0->lev[0].steps || (S.L > 2 && hs0->L > 2 && S.lev[1].steps != hs0->lev[1].steps)) {
+      set_error("staged batch: all systems need the same smoothing step counts");
+      return SGMG_EINVAL;
+    }
+    st.Lmax = std::max(st.Lmax, S.L);
+  }
+  st.steps0 = hs0->lev[0].steps;
+  st.stepsL = 0;
+  for (int i = 0; i < n; ++i) {
+    const BSys& S = hsys[b->h_items[i].sys];
+    if (S.L > 2) { st.stepsL = S.lev[1].steps; break; }
+  }
+  const int TB = bs_threads();
+  // host tables: entries (item, local block), per-item start and count
+  struct HT { std::vector<int2> blk; std::vector<int> start, count; };
+  auto make = [&](auto nblocks) {
+    HT t;
+    t.start.resize(n);
+    t.count.resize(n);
+    for (int i = 0; i < n; ++i) {
+      const int c = nblocks(hsys[b->h_items[i].sys]);
+      t.start[i] = (int)t.blk.size();
+      t.count[i] = c;
+      for (int j = 0; j < c; ++j) t.blk.push_back(int2{i, j});
+    }
+    return t;
+  };
+  std::vector<HT> hts;
+  hts.push_back(make([&](const BSys& S) { return div_up(S.lev[0].g.n, TB); }));        // tv
+  for (int l = 0; l < st.Lmax - 1; ++l) {
+    hts.push_back(make([&](const BSys& S) { return S.L - 1 > l ? div_up(S.lev[l].g.Nn, TB) : 0; }));
+    hts.push_back(make([&](const BSys& S) { return S.L - 1 > l ? div_up(S.lev[l + 1].g.Nn, TB) : 0; }));
+  }
+  hts.push_back(make([&](const BSys& S) { return div_up(S.nL, TB); }));               // tcg
+  hts.push_back(make([&](const BSys& S) { return div_up(S.nL, bs_coarse_rows()); }));  // tcm
+  auto a16 = [](size_t v) { return (v + 15) & ~(size_t)15; };
+  size_t bytes = 0, maxblk = 0;
+  for (const HT& t : hts) {
+    bytes += a16(t.blk.size() * sizeof(int2)) + 2 * a16((size_t)n * sizeof(int));
+    maxblk = std::max(maxblk, t.blk.size());
+  }
+  bytes = (bytes + 255) & ~(size_t)255;
+  const size_t part_b = 2 * maxblk * sizeof(double);
+  const size_t scal_b = (size_t)n * kBsScalars * sizeof(double);
+  const size_t flag_b = 2 * (size_t)n * sizeof(int);
+  char* m = nullptr;
+  if (hipMalloc((void**)&m, bytes + part_b + scal_b + flag_b + 512) != hipSuccess) {
+    set_error("staged batch allocation failed");
+    return SGMG_ENOMEM;
+  }
+  st.dmem = m;
+  size_t at = 0;
+  std::vector<BsTable> dts;
+  for (const HT& t : hts) {
+    BsTable d;
+    d.n = (int)t.blk.size();
+    d.blk = (const int2*)(m + at);
+    if (!t.blk.empty())
+      SGMG_HIP(hipMemcpyAsync(m + at, t.blk.data(), t.blk.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    at += a16(t.blk.size() * sizeof(int2));
+    d.start = (const int*)(m + at);
+    SGMG_HIP(hipMemcpyAsync(m + at, t.start.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+    at += a16(n * sizeof(int));
+    d.count = (const int*)(m + at);
+    SGMG_HIP(hipMemcpyAsync(m + at, t.count.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+    at += a16(n * sizeof(int));
+    dts.push_back(d);
+  }
+  at = bytes;
+  st.part = (double*)(m + at);
+  at += (part_b + 255) & ~(size_t)255;
+  st.scal = (double*)(m + at);
+  at += (scal_b + 255) & ~(size_t)255;
+  st.flags = (int*)(m + at);
+  int k = 0;
+  st.tv = dts[k++];
+  for (int l = 0; l < st.Lmax - 1; ++l) {
+    st.ts[l] = dts[k++];
+    st.tr[l] = dts[k++];
+  }
+  st.tcg = dts[k++];
+  st.tcm = dts[k++];
+  if (hipHostMalloc((void**)&st.h_flags, flag_b, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&st.h_scal, scal_b, hipHostMallocDefault) != hipSuccess) {
+    set_error("staged batch host allocation failed");
+    return SGMG_ENOMEM;
+  }
+  SGMG_HIP(hipStreamSynchronize(s));
+  TRY(bs_capture(b, bs_prologue, n, &st.g_pro));
+  TRY(bs_capture(b, bs_iteration, n, &st.g_it));
+  st.ready = true;
   return 0;
 }
 
@@ -2094,6 +2302,141 @@ int sgmg_pcg_solve_batch(sgmg_batch* b, int nitems, const int* item_sys, const d
       inf.iters = b->h_out[k].iters;
       inf.rel_res_true = b->h_out[k].rel_true;
       inf.rel_res_recur = b->h_out[k].rel_recur;
+      inf.solve_ms = ms;
+      inf.fallback_iter = -1;
+    }
+  }
+  return 0;
+}
+
+int sgmg_pcg_solve_batch_staged(sgmg_batch* b, int nitems, const int* item_sys,
+                                const double* const* f, double* const* u, double rtol, int maxit,
+                                sgmg_solve_info* infos, double* total_ms, void* stream) {
+  if (!b || nitems < 1 || !item_sys || !f || !u || maxit < 0 || !(rtol > 0.0)) {
+    set_error("bad batch solve arguments");
+    return SGMG_EINVAL;
+  }
+  for (int i = 0; i < nitems; ++i)
+    if (item_sys[i] < 0 || item_sys[i] >= (int)b->hs.size() || !f[i] || !u[i]) {
+      set_error("bad item " + std::to_string(i));
+      return SGMG_EINVAL;
+    }
+  hipStream_t s = as_stream(stream);
+  TRY(batch_prepare_items(b, nitems, item_sys, s));
+  for (int k = 0; k < nitems; ++k) {
+    b->h_items[k].f = f[b->order[k]];
+    b->h_items[k].u = u[b->order[k]];
+  }
+  SGMG_HIP(hipMemcpyAsync(b->d_items, b->h_items.data(), nitems * sizeof(BItem), hipMemcpyHostToDevice, s));
+  TRY(bs_prepare(b, nitems, s));
+  auto& st = b->st;
+  const int n = nitems;
+  int* hf = st.h_flags;
+  double* hs = st.h_scal;
+  std::vector<int> status(n, -1), iters(n, 0);
+  std::vector<double> nf(n, 0.0), rel(n, 0.0), rel_true(n, -1.0);
+  hipEvent_t e0, e1;
+  SGMG_HIP(hipEventCreate(&e0));
+  SGMG_HIP(hipEventCreate(&e1));
+  SGMG_HIP(hipEventRecord(e0, s));
+  // one graph replay with the given prologue / iteration flags, then the scalars
+  auto run = [&](hipGraphExec_t g) -> int {
+    SGMG_HIP(hipMemcpyAsync(st.flags, hf, 2 * (size_t)n * sizeof(int), hipMemcpyHostToDevice, s));
+    SGMG_HIP(hipGraphLaunch(g, s));
+    SGMG_HIP(hipMemcpyAsync(hs, st.scal, (size_t)n * kBsScalars * sizeof(double), hipMemcpyDeviceToHost, s));
+    SGMG_HIP(hipStreamSynchronize(s));
+    return 0;
+  };
+  auto sc = [&](int i, int k) { return hs[(size_t)i * kBsScalars + k]; };
+  // prologue for every item: true residual from x0, first V-cycle
+  for (int i = 0; i < n; ++i) { hf[i] = 1; hf[n + i] = 0; }
+  TRY(run(st.g_pro));
+  for (int i = 0; i < n; ++i) {
+    nf[i] = std::sqrt(sc(i, kBsFF));
+    if (nf[i] == 0.0) {
+      // f = 0: the solution is u = 0
+      const size_t nn = b->hs[b->h_items[i].sys]->lev[0].g.n;
+      SGMG_HIP(hipMemsetAsync(b->h_items[i].u, 0, nn * sizeof(double), s));
+      status[i] = SGMG_CONVERGED;
+      rel[i] = rel_true[i] = 0.0;
+      continue;
+    }
+    rel[i] = std::sqrt(sc(i, kBsRR)) / nf[i];
+    if (!std::isfinite(rel[i])) { status[i] = SGMG_NONFINITE; continue; }
+    if (rel[i] < rtol) { status[i] = SGMG_CONVERGED; rel_true[i] = rel[i]; continue; }
+    if (maxit == 0) { status[i] = SGMG_MAXIT; continue; }
+    const double rz = sc(i, kBsRZ);
+    if (!std::isfinite(rz)) { status[i] = SGMG_NONFINITE; continue; }
+    if (rz <= 0.0) { status[i] = SGMG_BREAKDOWN; continue; }
+  }
+  for (int it = 1; it <= maxit; ++it) {
+    int nact = 0;
+    for (int i = 0; i < n; ++i) {
+      hf[i] = 0;
+      hf[n + i] = status[i] < 0;
+      nact += hf[n + i];
+    }
+    if (!nact) break;
+    TRY(run(st.g_it));
+    int ncheck = 0;
+    for (int i = 0; i < n; ++i) {
+      hf[n + i] = 0;
+      if (status[i] >= 0) continue;
+      iters[i] = it;
+      const double pq = sc(i, kBsPQ);
+      if (!std::isfinite(pq)) { status[i] = SGMG_NONFINITE; iters[i] = it - 1; continue; }
+      if (pq <= 0.0) { status[i] = SGMG_BREAKDOWN; iters[i] = it - 1; continue; }
+      rel[i] = std::sqrt(sc(i, kBsRR)) / nf[i];
+      if (!std::isfinite(rel[i])) { status[i] = SGMG_NONFINITE; continue; }
+      if (rel[i] < rtol) { hf[i] = 1; ++ncheck; continue; }   // true-residual check
+      const double rz = sc(i, kBsRZNew);
+      if (!std::isfinite(rz)) { status[i] = SGMG_NONFINITE; continue; }
+      if (rz <= 0.0) { status[i] = SGMG_BREAKDOWN; continue; }
+      if (it == maxit) status[i] = SGMG_MAXIT;
+    }
+    if (ncheck) {
+      // the prologue recomputes r = f - K x in FP64 and restarts the
+      // recurrence from it (beta = 0) for the items that continue
+      TRY(run(st.g_pro));
+      for (int i = 0; i < n; ++i) {
+        if (!hf[i]) continue;
+        const double rt = std::sqrt(sc(i, kBsRR)) / nf[i];
+        if (rt < rtol) { status[i] = SGMG_CONVERGED; rel_true[i] = rt; continue; }
+        rel[i] = rt;
+        const double rz = sc(i, kBsRZ);
+        if (!std::isfinite(rz)) status[i] = SGMG_NONFINITE;
+        else if (rz <= 0.0) status[i] = SGMG_BREAKDOWN;
+        else if (it == maxit) status[i] = SGMG_MAXIT;
+      }
+    }
+  }
+  // true residual of the items that stopped without one
+  int nleft = 0;
+  for (int i = 0; i < n; ++i) {
+    if (status[i] < 0) status[i] = SGMG_MAXIT;
+    hf[i] = rel_true[i] < 0.0;
+    hf[n + i] = 0;
+    nleft += hf[i];
+  }
+  if (nleft) {
+    TRY(run(st.g_pro));
+    for (int i = 0; i < n; ++i)
+      if (hf[i]) rel_true[i] = std::sqrt(sc(i, kBsRR)) / (nf[i] > 0.0 ? nf[i] : 1.0);
+  }
+  SGMG_HIP(hipEventRecord(e1, s));
+  SGMG_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (total_ms) *total_ms = ms;
+  if (infos) {
+    for (int k = 0; k < n; ++k) {
+      sgmg_solve_info& inf = infos[b->order[k]];
+      inf.status = status[k];
+      inf.iters = iters[k];
+      inf.rel_res_true = rel_true[k];
+      inf.rel_res_recur = rel[k];
       inf.solve_ms = ms;
       inf.fallback_iter = -1;
     }

@@ -83,6 +83,7 @@ EXPORTS = [
     "sgmg_vcycle", "sgmg_pcg_solve", "sgmg_fgmres_solve", "sgmg_lanczos", "sgmg_num_levels", "sgmg_level_info",
     "sgmg_copy_stencil", "sgmg_copy_diagonal", "sgmg_destroy", "sgmg_last_error",
     "sgmg_autotune", "sgmg_set_launch_shape", "sgmg_setup_batch", "sgmg_pcg_solve_batch",
+    "sgmg_pcg_solve_batch_staged",
     "sgmg_pcg_solve_batch_concurrent", "sgmg_batch_hierarchy",
     "sgmg_batch_block_size", "sgmg_batch_destroy", "sgmg_batch_item_layout",
     "sgmg_unet_create", "sgmg_unet_num_params", "sgmg_unet_set_params", "sgmg_unet_get_params",
@@ -117,6 +118,10 @@ def _load():
     lib.sgmg_pcg_solve_batch.argtypes = [H, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp),
                                          ctypes.POINTER(vp), d, i, ctypes.POINTER(SolveInfo),
                                          ctypes.POINTER(ctypes.c_double), vp]
+    lib.sgmg_pcg_solve_batch_staged.argtypes = [H, i, ctypes.POINTER(ctypes.c_int),
+                                                ctypes.POINTER(vp), ctypes.POINTER(vp), d, i,
+                                                ctypes.POINTER(SolveInfo),
+                                                ctypes.POINTER(ctypes.c_double), vp]
     lib.sgmg_pcg_solve_batch_concurrent.argtypes = [H, i, ctypes.POINTER(ctypes.c_int),
                                                     ctypes.POINTER(vp), ctypes.POINTER(vp), d, i, i,
                                                     ctypes.POINTER(SolveInfo),
@@ -426,8 +431,11 @@ def setup_batch(opts_list, rho_list, fixed_list=None, stream=None):
     return Batch(b, opts_list)
 
 
-def pcg_solve_batch(batch, item_sys, f_list, u_list, rtol=1e-6, maxit=200, stream=None):
-    """Solves every item (system index, f, u); returns (list of dicts, total ms)."""
+def pcg_solve_batch(batch, item_sys, f_list, u_list, rtol=1e-6, maxit=200, stream=None,
+                    staged=False):
+    """Solves every item (system index, f, u); returns (list of dicts, total ms).
+    staged: sgmg_pcg_solve_batch_staged (one launch per stage over all items)
+    instead of the persistent launch."""
     m = len(item_sys)
     sysarr = (ctypes.c_int * m)(*item_sys)
     fa = (ctypes.c_void_p * m)(*[_ptr(f, torch.float64, 3 * n_nodes(batch.opts[s]), "f").value
@@ -436,8 +444,8 @@ def pcg_solve_batch(batch, item_sys, f_list, u_list, rtol=1e-6, maxit=200, strea
                                  for u, s in zip(u_list, item_sys)])
     infos = (SolveInfo * m)()
     ms = ctypes.c_double()
-    _check(_lib.sgmg_pcg_solve_batch(batch.handle, m, sysarr, fa, ua, rtol, maxit, infos,
-                                     ctypes.byref(ms), _stream(stream)))
+    fn = _lib.sgmg_pcg_solve_batch_staged if staged else _lib.sgmg_pcg_solve_batch
+    _check(fn(batch.handle, m, sysarr, fa, ua, rtol, maxit, infos, ctypes.byref(ms), _stream(stream)))
     out = [{"status": STATUS.get(i.status, i.status), "iters": i.iters,
             "rel_res_true": i.rel_res_true, "rel_res_recur": i.rel_res_recur} for i in infos]
     return out, ms.value

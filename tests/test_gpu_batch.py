@@ -115,7 +115,8 @@ def test_concurrent_batch_equals_single_solves(workers):
 def test_batch_config3_every_item_meets_the_oracle():
     """The whole batch workload (32 systems 2m x m x m, m in 8..24, up to the
     48 x 24 x 24 system; random-field rho, p = 3; 1-4 random face loads each):
-    one persistent launch and the concurrent solve, every item converged with
+    one persistent launch, the concurrent and the stage-batched solves, every
+    item converged with
     the oracle's FP64 true residual of its u below rtol (matrix-free element
     loop of the oracle)."""
     from paper_2604_26441_amd import simpgmg
@@ -128,13 +129,79 @@ def test_batch_config3_every_item_meets_the_oracle():
     uc = [t64(np.zeros_like(f)) for f in fs]
     resc, _ = simpgmg.pcg_solve_batch_concurrent(b, item_sys, [t64(f) for f in fs], uc,
                                                  rtol=1e-6, maxit=300, workers=4)
+    ug = [t64(np.zeros_like(f)) for f in fs]
+    resg, _ = simpgmg.pcg_solve_batch(b, item_sys, [t64(f) for f in fs], ug, rtol=1e-6, maxit=300,
+                                      staged=True)
     for i, (s, f) in enumerate(zip(item_sys, fs)):
         d = dims[s]
         fixed = workloads.cantilever_fixed(d).astype(bool)
         E = mesh.simp_modulus(rhos[s], 3)
-        for r, u in ((res[i], us[i]), (resc[i], uc[i])):
+        for r, u in ((res[i], us[i]), (resc[i], uc[i]), (resg[i], ug[i])):
             assert r["status"] == "converged", (i, d, r)
             x = np64(u)
             rel = np.linalg.norm(f - mesh.apply_K_elementwise(d, E, x, fixed=fixed)) / np.linalg.norm(f)
             assert rel < 1e-6, (i, d, rel)
             assert abs(rel - r["rel_res_true"]) < 1e-9, (i, d, rel, r)
+
+
+def test_staged_batch_matches_persistent_batch_and_oracle():
+    """The stage-batched solve (one launch per stage over all items, two
+    graphs replayed from a host loop): every item converged, iterations within
+    one of the persistent launch's (same operators, per-item reductions in
+    another order), the oracle's true residual below rtol and equal to the
+    one reported, solutions within the solver tolerance of the persistent
+    launch's; a second solve with the same item set replays the graphs."""
+    from paper_2604_26441_amd import simpgmg
+    dims, rhos = _systems()
+    opts = [simpgmg.default_options(*d, n_levels=0, dense_max=1000, fine_prec="f32") for d in dims]
+    b = simpgmg.setup_batch(opts, [t64(r) for r in rhos])
+    rng = np.random.default_rng(9)
+    item_sys, fs = [], []
+    for s, d in enumerate(dims):
+        for k in range(1 + (s + 2) % 3):
+            item_sys.append(s)
+            fs.append(workloads.random_face_load(d, rng) if k else workloads.edge_load(d))
+    up = [t64(np.zeros_like(f)) for f in fs]
+    rp, _ = simpgmg.pcg_solve_batch(b, item_sys, [t64(f) for f in fs], up, rtol=1e-6, maxit=300)
+    for rep in range(2):
+        us = [t64(np.zeros_like(f)) for f in fs]
+        rs, ms = simpgmg.pcg_solve_batch(b, item_sys, [t64(f) for f in fs], us, rtol=1e-6,
+                                         maxit=300, staged=True)
+        assert ms > 0
+        for i, (s, f) in enumerate(zip(item_sys, fs)):
+            d = dims[s]
+            assert rs[i]["status"] == "converged" == rp[i]["status"], (i, rs[i], rp[i])
+            assert abs(rs[i]["iters"] - rp[i]["iters"]) <= 1, (i, rs[i], rp[i])
+            fixed = workloads.cantilever_fixed(d).astype(bool)
+            x = np64(us[i])
+            Kx = mesh.apply_K_elementwise(d, mesh.simp_modulus(rhos[s], 3), x, fixed=fixed)
+            rel = np.linalg.norm(f - Kx) / np.linalg.norm(f)
+            assert rel < 1e-6 and abs(rel - rs[i]["rel_res_true"]) < 1e-9, (i, rel, rs[i])
+            xp = np64(up[i])
+            assert np.linalg.norm(x - xp) <= 1e-5 * np.linalg.norm(xp), i
+
+
+def test_staged_batch_edge_cases():
+    """Zero right-hand side (u = 0 at once), a start at the solution
+    (converged at iteration 0), maxit 0, and argument checks."""
+    from paper_2604_26441_amd import simpgmg
+    dims, rhos = _systems()
+    opts = [simpgmg.default_options(*d, n_levels=0, dense_max=1000, fine_prec="f32") for d in dims[:2]]
+    b = simpgmg.setup_batch(opts, [t64(r) for r in rhos[:2]])
+    f0 = workloads.edge_load(dims[0])
+    f1 = workloads.edge_load(dims[1])
+    u1 = t64(np.zeros_like(f1))
+    simpgmg.pcg_solve(b.hierarchy(1), t64(f1), u1, rtol=1e-10, maxit=300)
+    fs = [np.zeros_like(f0), f1]
+    us = [t64(np.ones_like(f0) * (1 - workloads.cantilever_fixed(dims[0]))), u1]
+    res, _ = simpgmg.pcg_solve_batch(b, [0, 1], [t64(f) for f in fs], us, rtol=1e-6, staged=True)
+    assert res[0]["status"] == "converged" and np.all(np64(us[0]) == 0)
+    assert res[1]["status"] == "converged" and res[1]["iters"] == 0
+    us = [t64(np.zeros_like(f0)), t64(np.zeros_like(f1))]
+    res, _ = simpgmg.pcg_solve_batch(b, [0, 1], [t64(f0), t64(f1)], us, rtol=1e-6, maxit=0,
+                                     staged=True)
+    assert [r["status"] for r in res] == ["maxit", "maxit"] and all(r["iters"] == 0 for r in res)
+    assert all(abs(r["rel_res_true"] - 1.0) < 1e-12 for r in res)
+    for kw in ({"maxit": -1}, {"rtol": 0.0}):
+        with pytest.raises(simpgmg.SimpGmgError):
+            simpgmg.pcg_solve_batch(b, [0, 1], [t64(f0), t64(f1)], us, staged=True, **kw)
