@@ -366,7 +366,9 @@ void sgmg_batch_destroy(sgmg_batch* b);
  * d1 = relu(c7(up d2)) + e1, y = c8(d1); c1..c7 3x3x3 convolutions with
  * channels 5->16->32->64->128->64->32->16, c8 1x1x1 16->3, pool = 2x2x2 mean,
  * up = nearest x2.  Weights are rounded to BF16 for compute (FP32 master
- * copy for Adam), accumulation is FP32.  Input channels: density averaged to
+ * copy for Adam), accumulation is FP32; the 3x3x3 convolutions run on the
+ * matrix cores with the FP32 activations split exactly into three BF16
+ * terms, so every product is exact and only the FP32 sums round.  Input channels: density averaged to
  * nodes, load / max|f| (3), clamp mask.  The prediction's scale is set by
  * sgmg_warm_start_scale, and PCG-GMG to the same tolerance is both fallback
  * and judge of the result. */
@@ -389,6 +391,23 @@ int sgmg_unet_grad(sgmg_unet* u, int N, int D, int H, int W, const float* in, co
 int sgmg_unet_train_step(sgmg_unet* u, int N, int D, int H, int W, const float* in,
                          const float* target, const float* mask, float lr, float* loss,
                          void* stream);
+/* Energy-norm training score (the error the scaled warm start leaves):
+ * for sample n, u_n = the output's 3 channels on the first Nz x Ny x Nx
+ * voxels of h's node grid as a DOF vector (zero on clamped DOFs); with
+ * a = f_n.u_n, b = u_n.K_n u_n and c = cstar[n] = f_n.u*_n (the compliance),
+ * score 1 - a^2 / (b c) = ||(a/b) u_n - u*_n||_K^2 / ||u*_n||_K^2 (1 when
+ * b <= 0).  *loss (host) = mean score before the update.  K_n is h's fine
+ * operator with the element field rho_or_E + n * n_elements, read as
+ * sgmg_setup_hierarchy reads its input (h's SIMP map).  in (device,
+ * N x 5 x D x H x W, D, H, W >= h's node counts z, y, x), rho_or_E (device,
+ * N x n_elements), f (device, N x 3 n_nodes), cstar (device, N), grads_host
+ * (host, parameter layout, may be NULL).  lr > 0: one Adam step follows;
+ * lr = 0: gradients only.  Synchronises.  SGMG_EINVAL for NULL inputs, a
+ * negative lr or a volume smaller than the node grid. */
+int sgmg_unet_energy_step(sgmg_unet* u, const sgmg_hierarchy* h, int N, int D, int H, int W,
+                          const float* in, const double* rho_or_E, const double* f,
+                          const double* cstar, float lr, float* loss, float* grads_host,
+                          void* stream);
 /* Network input for hierarchy h's mesh: rho (device, elements), f (device,
  * DOFs) -> in (device, 5 x Dp x Hp x Wp, zero padded). */
 int sgmg_unet_input(const sgmg_hierarchy* h, const double* rho, const double* f, int Dp, int Hp,

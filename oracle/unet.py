@@ -155,3 +155,49 @@ def backward(params, cache, dy):
     _, dw, db = conv3d_backward(c["x0"], P[0][0], dr1)
     g[0] = (dw, db)
     return g
+
+
+def output_to_dofs(y_n, dims, fixed):
+    """Sample output (3, D, H, W) -> DOF vector of the (nx, ny, nz) mesh: the
+    channels on the first Nz x Ny x Nx voxels (node (i, j, k) at voxel
+    (k, j, i), DOF 3 node + c from channel c), zero on the clamped DOFs."""
+    nx, ny, nz = dims
+    u = y_n[:, :nz + 1, :ny + 1, :nx + 1].transpose(1, 2, 3, 0).reshape(-1).astype(np.float64)
+    u[np.asarray(fixed, dtype=bool)] = 0.0
+    return u
+
+
+def dofs_to_output(g, dims, shape):
+    """Adjoint of output_to_dofs for one sample (fixed DOFs already zero in g)."""
+    nx, ny, nz = dims
+    out = np.zeros(shape)
+    out[:, :nz + 1, :ny + 1, :nx + 1] = g.reshape(nz + 1, ny + 1, nx + 1, 3).transpose(3, 0, 1, 2)
+    return out
+
+
+def loss_energy(y, Ks, fs, cstars, dims, fixed):
+    """Energy-norm score of the predicted displacement shapes and its output
+    gradient.  For sample n, u = output_to_dofs(y[n]); the best multiple of u
+    in the energy norm of K (the free-DOF stiffness) is alpha u with
+    alpha = f.u / u.K u, and its squared error against the solution u* is
+    ||u*||_K^2 - (f.u)^2 / u.K u, where ||u*||_K^2 = f.u* = c (the
+    compliance).  Score 1 - (f.u)^2 / (u.K u c): 0 for the exact shape,
+    1 for u = 0 (score 1 and gradient -f / c when u.K u is not positive).
+    Returns (mean score, gradient of the mean with respect to y)."""
+    N = y.shape[0]
+    dy = np.zeros(y.shape)
+    total = 0.0
+    for n in range(N):
+        u = output_to_dofs(y[n], dims, fixed)
+        Ku = Ks[n] @ u
+        a, b, c = fs[n] @ u, u @ Ku, cstars[n]
+        if b > 0:
+            total += 1.0 - a * a / (b * c)
+            g = -(2.0 * a / (b * c)) * (fs[n] - (a / b) * Ku)
+        else:
+            total += 1.0
+            g = -np.asarray(fs[n], dtype=np.float64) / c
+        g = np.array(g, dtype=np.float64)
+        g[np.asarray(fixed, dtype=bool)] = 0.0
+        dy[n] = dofs_to_output(g / N, dims, y.shape[1:])
+    return total / N, dy

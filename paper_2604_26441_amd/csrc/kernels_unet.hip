@@ -5,6 +5,7 @@
 // w[(ci * K^3 + tap) * Cop + co], Cop = output channels padded to 16, so the
 // 16 weights of one (ci, tap) are contiguous and read with uniform loads.
 #include "kernels.hpp"
+#include "node_ops.hpp"
 #include "unet.hpp"
 
 namespace sgmg {
@@ -73,6 +74,204 @@ void launch_conv_fwd(int K, const float* x, int N, int Ci, int Co, int D, int H,
     k_conv_fwd<1><<<grid, 256, 0, s>>>(x, Ci, Co, Cop, D, H, W, w, b, relu, rpre, add, y);
 }
 
+// ---------------------------------------------------------------------------
+// 3x3x3 convolution as an implicit GEMM on the matrix cores
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  Per MFMA the A operand is
+// 16 output channels x 32 reduction slots and the B operand 32 reduction
+// slots x 16 output voxels (one x-run of a tile row); the 32 slots are 4 taps
+// x 8 input channels: lane group q = lane / 16 takes tap 4 s + q of k-step s
+// (7 steps cover the 27 taps, tap 27 has zero weights) and channels
+// 8 ch .. 8 ch + 7 of channel chunk ch.  The activations are FP32: each value
+// is split exactly into three BF16 terms (truncation: hi, then the
+// remainder's hi, then what is left, 8 + 8 + 8 significand bits), and the
+// three products with the BF16 weight are exact in FP32, so the result is an
+// FP32 sum of the exact products (the accuracy of the FP32 vector-ALU form).
+//
+// Block: an output tile of 16 (x) x 4 (y) x 4 (z) voxels of one sample and
+// COT tiles of 16 output channels; wave w owns the 4 tile rows of z = w.
+// Per channel chunk the 18 x 6 x 6 input halo is staged once in LDS as the
+// three term planes, 8 channels (16 B) per voxel, so one ds_read_b128 is a
+// lane's B operand; zero outside the volume (the padding).
+constexpr int kCTX = 16, kCTY = 4, kCTZ = 4;
+constexpr int kCHX = kCTX + 2, kCHY = kCTY + 2, kCHZ = kCTZ + 2;
+constexpr int kCHV = kCHX * kCHY * kCHZ;       // 648 staged voxels
+constexpr int kCSteps = 7;                     // k-steps of 4 taps
+
+typedef __bf16 cbf16x8 __attribute__((ext_vector_type(8)));
+typedef float cf32x4 __attribute__((ext_vector_type(4)));
+
+// exact three-term BF16 split of v; returns the terms' bit patterns
+__device__ inline void split3(float v, unsigned& t0, unsigned& t1, unsigned& t2) {
+  const unsigned b = __float_as_uint(v);
+  const unsigned h = b & 0xffff0000u;
+  const float r1 = v - __uint_as_float(h);
+  const unsigned m = __float_as_uint(r1) & 0xffff0000u;
+  const float r2 = r1 - __uint_as_float(m);
+  t0 = h >> 16;
+  t1 = m >> 16;
+  t2 = __float_as_uint(r2) >> 16;
+}
+
+template <int COT>
+__global__ __launch_bounds__(256) void k_conv3_mfma(const float* __restrict__ x, int up, int Ci,
+                                                    int Co, int Cop, int D, int H, int W, int tx,
+                                                    int ty, const uint4* __restrict__ wp,
+                                                    const float* __restrict__ bias, int relu,
+                                                    float* __restrict__ rpre,
+                                                    const float* __restrict__ add,
+                                                    float* __restrict__ y) {
+  __shared__ uint4 lds[3][kCHV];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int col = lane & 15, q = lane >> 4;
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const int n = blockIdx.y, ct0 = blockIdx.z * COT;
+  const int bx = tile % tx, by = (tile / tx) % ty, bz = tile / (tx * ty);
+  const int x0 = bx * kCTX, y0 = by * kCTY, z0 = bz * kCTZ;
+  const long HW = (long)H * W, DHW = (long)D * HW;
+  // with up = 1 the input is stored at half resolution and read as its
+  // nearest-neighbour upsampling (voxel v of the output grid reads v / 2)
+  const int Wi = W >> up, Hi = H >> up;
+  const long HWi = (long)Hi * Wi, DHWi = (long)(D >> up) * HWi;
+  const float* xn = x + (size_t)n * Ci * DHWi;
+  const int nchunk = (Ci + 7) >> 3;
+  cf32x4 acc[kCTY][COT];
+#pragma unroll
+  for (int r = 0; r < kCTY; ++r)
+#pragma unroll
+    for (int c = 0; c < COT; ++c) acc[r][c] = cf32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int ch = 0; ch < nchunk; ++ch) {
+    __syncthreads();                       // the previous chunk's reads are done
+    for (int v = threadIdx.x; v < kCHV; v += 256) {
+      const int hx = v % kCHX, hy = (v / kCHX) % kCHY, hz = v / (kCHX * kCHY);
+      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+      const bool in = (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H &&
+                      (unsigned)gz < (unsigned)D;
+      const size_t off = in ? (size_t)(gz >> up) * HWi + (size_t)(gy >> up) * Wi + (gx >> up) : 0;
+      unsigned p0[4], p1[4], p2[4];
+#pragma unroll
+      for (int j = 0; j < 8; j += 2) {
+        const int c = 8 * ch + j;
+        const float a = in && c < Ci ? xn[(size_t)c * DHWi + off] : 0.f;
+        const float b = in && c + 1 < Ci ? xn[(size_t)(c + 1) * DHWi + off] : 0.f;
+        unsigned a0, a1, a2, b0, b1, b2;
+        split3(a, a0, a1, a2);
+        split3(b, b0, b1, b2);
+        p0[j >> 1] = a0 | (b0 << 16);
+        p1[j >> 1] = a1 | (b1 << 16);
+        p2[j >> 1] = a2 | (b2 << 16);
+      }
+      lds[0][v] = uint4{p0[0], p0[1], p0[2], p0[3]};
+      lds[1][v] = uint4{p1[0], p1[1], p1[2], p1[3]};
+      lds[2][v] = uint4{p2[0], p2[1], p2[2], p2[3]};
+    }
+    __syncthreads();
+    const uint4* wc = wp + (size_t)ch * kCSteps * Cop * 4;
+#pragma unroll 1
+    for (int s = 0; s < kCSteps; ++s) {
+      uint4 a[COT];
+#pragma unroll
+      for (int c = 0; c < COT; ++c) a[c] = wc[((size_t)s * Cop + (ct0 + c) * 16 + col) * 4 + q];
+      // tap 27 (weights zero) reads tap 26's voxel, a staged finite value
+      const int t = 4 * s + q < 27 ? 4 * s + q : 26;
+      const int dx = t % 3, dy = (t / 3) % 3, dz = t / 9;
+#pragma unroll
+      for (int r = 0; r < kCTY; ++r) {
+        const int v = ((w + dz) * kCHY + (r + dy)) * kCHX + col + dx;
+        const cbf16x8 b2 = __builtin_bit_cast(cbf16x8, lds[2][v]);
+        const cbf16x8 b1 = __builtin_bit_cast(cbf16x8, lds[1][v]);
+        const cbf16x8 b0 = __builtin_bit_cast(cbf16x8, lds[0][v]);
+#pragma unroll
+        for (int c = 0; c < COT; ++c) {       // smallest terms first
+          const cbf16x8 av = __builtin_bit_cast(cbf16x8, a[c]);
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b2, acc[r][c], 0, 0, 0);
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b1, acc[r][c], 0, 0, 0);
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b0, acc[r][c], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // epilogue: lane holds output channels 16 c + 4 q + i of voxel column col
+  const int gx = x0 + col, gz = z0 + w;
+  if (gx >= W || gz >= D) return;
+#pragma unroll
+  for (int r = 0; r < kCTY; ++r) {
+    const int gy = y0 + r;
+    if (gy >= H) break;
+    const size_t vox = (size_t)gz * HW + (size_t)gy * W + gx;
+#pragma unroll
+    for (int c = 0; c < COT; ++c)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int co = (ct0 + c) * 16 + 4 * q + i;
+        if (co >= Co) continue;
+        float val = acc[r][c][i] + (bias ? bias[co] : 0.f);
+        if (relu) val = fmaxf(val, 0.f);
+        const size_t o = ((size_t)n * Co + co) * DHW + vox;
+        if (rpre) rpre[o] = val;
+        if (add) val += add[o];
+        y[o] = val;
+      }
+  }
+}
+
+// Packed A operands: wp[((ch * 7 + s) * Cop + co) * 4 + q] holds the BF16
+// weights of input channels 8 ch .. 8 ch + 7 at tap 4 s + q for output
+// channel co (zero past Ci and for tap 27), from the BF16-exact FP32 layout
+// w[(ci * 27 + tap) * Cop + co].
+__global__ void k_pack_conv3(const float* __restrict__ w, int Ci, int Cop, int total,
+                             uint4* __restrict__ wp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int q = i & 3, co = (i >> 2) % Cop, s = (i / (4 * Cop)) % kCSteps,
+            ch = i / (4 * Cop * kCSteps);
+  const int t = 4 * s + q;
+  unsigned p[4];
+#pragma unroll
+  for (int j = 0; j < 8; j += 2) {
+    const int c = 8 * ch + j;
+    const float a = t < 27 && c < Ci ? w[((size_t)c * 27 + t) * Cop + co] : 0.f;
+    const float b = t < 27 && c + 1 < Ci ? w[((size_t)(c + 1) * 27 + t) * Cop + co] : 0.f;
+    p[j >> 1] = (__float_as_uint(a) >> 16) | (__float_as_uint(b) & 0xffff0000u);
+  }
+  wp[i] = uint4{p[0], p[1], p[2], p[3]};
+}
+
+size_t conv3_packed_words(int Ci, int Co) {
+  const int Cop = (Co + kCOB - 1) / kCOB * kCOB;
+  return (size_t)((Ci + 7) / 8) * kCSteps * Cop * 4;
+}
+
+void launch_pack_conv3(const float* w, int Ci, int Co, uint4* wp, hipStream_t s) {
+  const int Cop = (Co + kCOB - 1) / kCOB * kCOB;
+  const int total = (int)conv3_packed_words(Ci, Co);
+  k_pack_conv3<<<div_up(total, 256), 256, 0, s>>>(w, Ci, Cop, total, wp);
+}
+
+void launch_conv3_mfma(const float* x, int up, int N, int Ci, int Co, int D, int H, int W,
+                       const uint4* wp, const float* b, int relu, float* rpre, const float* add,
+                       float* y, hipStream_t s) {
+  const int Cop = (Co + kCOB - 1) / kCOB * kCOB, ntile = Cop / 16;
+  const int tx = div_up(W, kCTX), ty = div_up(H, kCTY), tz = div_up(D, kCTZ);
+  const long tiles = (long)tx * ty * tz;
+  // channel tiles per block: the largest power of two dividing ntile (<= 8),
+  // halved while the grid has fewer than 1024 blocks
+  int cot = 1;
+  while (cot < 8 && ntile % (2 * cot) == 0) cot *= 2;
+  while (cot > 1 && tiles * N * (ntile / cot) < 1024) cot /= 2;
+  dim3 grid((unsigned)tiles, N, ntile / cot);
+#define SGMG_CONV3(C)                                                                      \
+  k_conv3_mfma<C><<<grid, 256, 0, s>>>(x, up, Ci, Co, Cop, D, H, W, tx, ty, wp, b, relu, rpre, \
+                                       add, y)
+  switch (cot) {
+    case 8: SGMG_CONV3(8); break;
+    case 4: SGMG_CONV3(4); break;
+    case 2: SGMG_CONV3(2); break;
+    default: SGMG_CONV3(1); break;
+  }
+#undef SGMG_CONV3
+}
+
 // Weights for the data gradient: wt[(co * K3 + (K3 - 1 - t)) * Cip + ci] =
 // w[(ci * K3 + t) * Cop + co]  (channels swapped, taps flipped).
 __global__ void k_weight_transpose(const float* __restrict__ w, int Ci, int Co, int Cop, int K3,
@@ -97,7 +296,7 @@ void launch_weight_transpose(const float* w, int Ci, int Co, int K, float* wt, h
 constexpr int kWGChunk = 4096;
 
 template <int K>
-__global__ __launch_bounds__(256) void k_conv_wgrad(const float* __restrict__ x,
+__global__ __launch_bounds__(256) void k_conv_wgrad(const float* __restrict__ x, int up,
                                                     const float* __restrict__ dy, int N, int Ci,
                                                     int Co, int D, int H, int W,
                                                     float* __restrict__ part) {
@@ -126,14 +325,16 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const float* __restrict__ x,
 #pragma unroll
     for (int c = 0; c < 4; ++c)
       gy[c] = co0 + c < Co ? dy[((size_t)n * Co + co0 + c) * DHW + v] : 0.f;
-    const float* xc = x + ((size_t)n * Ci + ci) * DHW;
+    // up = 1: x is stored at half resolution and read as its upsampling
+    const int Wi = W >> up, HWi = (H >> up) * Wi;
+    const float* xc = x + ((size_t)n * Ci + ci) * (size_t)((D >> up) * HWi);
 #pragma unroll
     for (int t = 0; t < K3; ++t) {
       const int dz = t / (K * K) - R, dyy = (t / K) % K - R, dx = t % K - R;
       const int zz = d + dz, yy = hh + dyy, xx = ww + dx;
       const bool ok = (unsigned)zz < (unsigned)D && (unsigned)yy < (unsigned)H &&
                       (unsigned)xx < (unsigned)W;
-      const float xv = ok ? xc[(size_t)zz * HW + yy * W + xx] : 0.f;
+      const float xv = ok ? xc[(size_t)(zz >> up) * HWi + (yy >> up) * Wi + (xx >> up)] : 0.f;
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[c][t] += gy[c] * xv;
     }
@@ -187,14 +388,14 @@ size_t conv_wgrad_part_floats(int N, int Ci, int Co, int D, int H, int W, int K)
   return (size_t)nchunks * Ci * ((Co + 3) / 4) * (4 * K * K * K + 4);
 }
 
-void launch_conv_wgrad(int K, const float* x, const float* dy, int N, int Ci, int Co, int D, int H,
-                       int W, float* part, float* dw, float* db, hipStream_t s) {
+void launch_conv_wgrad(int K, const float* x, int up, const float* dy, int N, int Ci, int Co, int D,
+                       int H, int W, float* part, float* dw, float* db, hipStream_t s) {
   const long total = (long)N * D * H * W;
   const int nchunks = (int)((total + kWGChunk - 1) / kWGChunk);
   const int nq = (Co + 3) / 4;
   dim3 grid(Ci, nq, nchunks);
-  if (K == 3) k_conv_wgrad<3><<<grid, 256, 0, s>>>(x, dy, N, Ci, Co, D, H, W, part);
-  else k_conv_wgrad<1><<<grid, 256, 0, s>>>(x, dy, N, Ci, Co, D, H, W, part);
+  if (K == 3) k_conv_wgrad<3><<<grid, 256, 0, s>>>(x, up, dy, N, Ci, Co, D, H, W, part);
+  else k_conv_wgrad<1><<<grid, 256, 0, s>>>(x, up, dy, N, Ci, Co, D, H, W, part);
   const int Cop = (Co + kCOB - 1) / kCOB * kCOB;
   const int K3 = K * K * K;
   k_conv_wgrad_sum<<<div_up((long)Ci * nq * (4 * K3 + 4), 256), 256, 0, s>>>(part, nchunks, Ci, Co,
@@ -202,53 +403,53 @@ void launch_conv_wgrad(int K, const float* x, const float* dy, int N, int Ci, in
 }
 
 // 2x2x2 mean pooling and its adjoint; nearest x2 upsampling and its adjoint.
-__global__ void k_pool(const float* __restrict__ x, int NC, int D, int H, int W,
-                       float* __restrict__ y) {
-  const int Do = D / 2, Ho = H / 2, Wo = W / 2;
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long)NC * Do * Ho * Wo) return;
-  const int wo = i % Wo, ho = (i / Wo) % Ho, dd = (i / ((long)Wo * Ho)) % Do;
-  const long nc = i / ((long)Wo * Ho * Do);
-  const float* b = x + nc * D * H * W;
+// Grid: x over (volume nc, output plane d), y over the voxels of the plane;
+// the plane and volume indices are uniform over a block.
+__global__ void k_pool(const float* __restrict__ x, int D, int H, int W, float* __restrict__ y) {
+  const int Do = D >> 1, Ho = H >> 1, Wo = W >> 1;
+  const int j = blockIdx.y * blockDim.x + threadIdx.x;
+  if (j >= Ho * Wo) return;
+  const int dd = blockIdx.x % Do, nc = blockIdx.x / Do;
+  const int ho = j / Wo, wo = j - ho * Wo;
+  const float* b = x + ((size_t)nc * D + 2 * dd) * H * W + (size_t)(2 * ho) * W + 2 * wo;
   float s = 0.f;
-  for (int a = 0; a < 8; ++a)
-    s += b[((size_t)(2 * dd + (a >> 2)) * H + 2 * ho + ((a >> 1) & 1)) * W + 2 * wo + (a & 1)];
-  y[i] = s * 0.125f;
+  for (int a = 0; a < 8; ++a) s += b[(size_t)(a >> 2) * H * W + ((a >> 1) & 1) * W + (a & 1)];
+  y[((size_t)nc * Do + dd) * Ho * Wo + j] = s * 0.125f;
 }
 
 // pool adjoint (scale 1/8) or upsampling (scale 1): y(fine) = scale * x(coarse)
-__global__ void k_expand(const float* __restrict__ x, int NC, int D, int H, int W, float scale,
+__global__ void k_expand(const float* __restrict__ x, int D, int H, int W, float scale,
                          float* __restrict__ y) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long)NC * D * H * W) return;
-  const int w = i % W, h = (i / W) % H, d = (i / ((long)W * H)) % D;
-  const long nc = i / ((long)W * H * D);
-  y[i] = scale * x[((nc * (D / 2) + d / 2) * (H / 2) + h / 2) * (W / 2) + w / 2];
+  const int j = blockIdx.y * blockDim.x + threadIdx.x;
+  if (j >= H * W) return;
+  const int d = blockIdx.x % D, nc = blockIdx.x / D;
+  const int h = j / W, w = j - h * W;
+  const int Hc = H >> 1, Wc = W >> 1;
+  y[((size_t)nc * D + d) * H * W + j] =
+      scale * x[(((size_t)nc * (D >> 1) + (d >> 1)) * Hc + (h >> 1)) * Wc + (w >> 1)];
 }
 
 // upsampling adjoint: y(coarse) = sum of the 8 children
-__global__ void k_sum8(const float* __restrict__ x, int NC, int D, int H, int W,
-                       float* __restrict__ y) {
-  const int Do = D / 2, Ho = H / 2, Wo = W / 2;
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long)NC * Do * Ho * Wo) return;
-  const int wo = i % Wo, ho = (i / Wo) % Ho, dd = (i / ((long)Wo * Ho)) % Do;
-  const long nc = i / ((long)Wo * Ho * Do);
-  const float* b = x + nc * D * H * W;
+__global__ void k_sum8(const float* __restrict__ x, int D, int H, int W, float* __restrict__ y) {
+  const int Do = D >> 1, Ho = H >> 1, Wo = W >> 1;
+  const int j = blockIdx.y * blockDim.x + threadIdx.x;
+  if (j >= Ho * Wo) return;
+  const int dd = blockIdx.x % Do, nc = blockIdx.x / Do;
+  const int ho = j / Wo, wo = j - ho * Wo;
+  const float* b = x + ((size_t)nc * D + 2 * dd) * H * W + (size_t)(2 * ho) * W + 2 * wo;
   float s = 0.f;
-  for (int a = 0; a < 8; ++a)
-    s += b[((size_t)(2 * dd + (a >> 2)) * H + 2 * ho + ((a >> 1) & 1)) * W + 2 * wo + (a & 1)];
-  y[i] = s;
+  for (int a = 0; a < 8; ++a) s += b[(size_t)(a >> 2) * H * W + ((a >> 1) & 1) * W + (a & 1)];
+  y[((size_t)nc * Do + dd) * Ho * Wo + j] = s;
 }
 
 void launch_pool(const float* x, int NC, int D, int H, int W, float* y, hipStream_t s) {
-  k_pool<<<div_up((long)NC * (D / 2) * (H / 2) * (W / 2), 256), 256, 0, s>>>(x, NC, D, H, W, y);
+  k_pool<<<dim3(NC * (D / 2), div_up((H / 2) * (W / 2), 256)), 256, 0, s>>>(x, D, H, W, y);
 }
 void launch_expand(const float* x, int NC, int D, int H, int W, float scale, float* y, hipStream_t s) {
-  k_expand<<<div_up((long)NC * D * H * W, 256), 256, 0, s>>>(x, NC, D, H, W, scale, y);
+  k_expand<<<dim3(NC * D, div_up(H * W, 256)), 256, 0, s>>>(x, D, H, W, scale, y);
 }
 void launch_sum8(const float* x, int NC, int D, int H, int W, float* y, hipStream_t s) {
-  k_sum8<<<div_up((long)NC * (D / 2) * (H / 2) * (W / 2), 256), 256, 0, s>>>(x, NC, D, H, W, y);
+  k_sum8<<<dim3(NC * (D / 2), div_up((H / 2) * (W / 2), 256)), 256, 0, s>>>(x, D, H, W, y);
 }
 
 // dr = dy * (r > 0) [+ extra]; extra may be NULL
@@ -433,6 +634,112 @@ void launch_unet_target(const Grid& g, const double* u, double* umax_scratch, in
   k_zero_u64<<<1, 1, 0, s>>>((unsigned long long*)umax_scratch);
   k_absmax<<<256, 256, 0, s>>>(u, g.n, (unsigned long long*)umax_scratch);
   k_unet_target<<<div_up((long)Dp * Hp * Wp, 256), 256, 0, s>>>(g, u, umax_scratch, Dp, Hp, Wp, t, m);
+}
+
+// ---------------------------------------------------------------------------
+// Energy-norm training score of the network's displacement shapes.  Sample
+// n's output channels on the node voxels give u (zero on clamped DOFs); with
+// a = f.u, b = u.K u and the compliance c = f.u* the best multiple (a / b) u
+// leaves the squared energy-norm error c - a^2 / b, so the score
+// 1 - a^2 / (b c) is 0 for the exact shape and 1 for u = 0.  The batch loss is
+// the mean score; its output gradient is -(2 a / (b c N)) (f - (a / b) K u) on
+// free DOFs.
+__global__ void k_energy_u(EnergyBatch e, const float* __restrict__ y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const Grid& g = e.g;
+  if (i >= (long)e.N * g.Nn) return;
+  const int n = (int)(i / g.Nn), node = (int)(i % g.Nn);
+  const int x = node % g.Nx, yy = (node / g.Nx) % g.Ny, z = node / (g.Nx * g.Ny);
+  const long vol = (long)e.Dp * e.Hp * e.Wp;
+  const long v = ((long)z * e.Hp + yy) * e.Wp + x;
+  const unsigned fx = e.fixn[node];
+  double* u = e.u + (size_t)n * g.n + 3 * (size_t)node;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    u[c] = (fx >> c) & 1u ? 0.0 : (double)y[((size_t)n * 3 + c) * vol + v];
+}
+
+__global__ __launch_bounds__(256) void k_energy_Ku(EnergyBatch e) {
+  __shared__ double lds[32];
+  const Grid& g = e.g;
+  const int n = blockIdx.y;
+  const int node = blockIdx.x * 256 + threadIdx.x;
+  double a = 0.0, b = 0.0;
+  if (node < g.Nn) {
+    const size_t off = (size_t)n * g.n, base = off + 3 * (size_t)node;
+    double acc[3], xo[3];
+    fine_node_Ku<double>(g, e.E + (size_t)n * g.nel, e.ke, e.u + off, node, acc, xo);
+    const unsigned fx = e.fixn[node];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double kv = (fx >> c) & 1u ? 0.0 : acc[c];
+      e.Ku[base + c] = kv;
+      a += e.f[base + c] * xo[c];
+      b += xo[c] * kv;
+    }
+  }
+  a = block_sum(a, lds);
+  b = block_sum(b, lds + 16);
+  if (threadIdx.x == 0) {
+    double* p = e.part + ((size_t)n * e.nb + blockIdx.x) * 2;
+    p[0] = a;
+    p[1] = b;
+  }
+}
+
+// one block per sample: the block partials in a fixed order, then the score
+// and the gradient factors (score 1 and the gradient -f / (c N) when u.K u is
+// not positive)
+__global__ __launch_bounds__(256) void k_energy_final(EnergyBatch e) {
+  __shared__ double lds[32];
+  const int n = blockIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < e.nb; i += 256) {
+    a += e.part[((size_t)n * e.nb + i) * 2];
+    b += e.part[((size_t)n * e.nb + i) * 2 + 1];
+  }
+  a = block_sum(a, lds);
+  b = block_sum(b, lds + 16);
+  if (threadIdx.x != 0) return;
+  const double c = e.cstar[n];
+  double* sc = e.scal + 4 * (size_t)n;
+  if (b > 0.0 && c > 0.0 && isfinite(a) && isfinite(b)) {
+    sc[0] = 1.0 - a * a / (b * c);
+    sc[1] = -2.0 * a / (b * c * e.N);
+    sc[2] = a / b;
+  } else {
+    sc[0] = 1.0;
+    sc[1] = c > 0.0 ? -1.0 / (c * e.N) : 0.0;
+    sc[2] = 0.0;
+  }
+  sc[3] = 0.0;
+}
+
+__global__ void k_energy_grad(EnergyBatch e, float* __restrict__ gy) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long vol = (long)e.Dp * e.Hp * e.Wp;
+  if (i >= (long)e.N * 3 * vol) return;
+  const Grid& g = e.g;
+  const int n = (int)(i / (3 * vol)), c = (int)((i / vol) % 3);
+  const long v = i % vol;
+  const int x = (int)(v % e.Wp), yy = (int)((v / e.Wp) % e.Hp), z = (int)(v / ((long)e.Wp * e.Hp));
+  double val = 0.0;
+  if (x < g.Nx && yy < g.Ny && z < g.Nz) {
+    const int node = x + g.Nx * (yy + g.Ny * z);
+    if (!((e.fixn[node] >> c) & 1u)) {
+      const size_t d = (size_t)n * g.n + 3 * (size_t)node + c;
+      const double* sc = e.scal + 4 * (size_t)n;
+      val = sc[1] * (e.f[d] - sc[2] * e.Ku[d]);
+    }
+  }
+  gy[i] = (float)val;
+}
+
+void launch_energy_loss(const EnergyBatch& e, const float* y, float* gy, hipStream_t s) {
+  k_energy_u<<<div_up((long)e.N * e.g.Nn, 256), 256, 0, s>>>(e, y);
+  k_energy_Ku<<<dim3(e.nb, e.N), 256, 0, s>>>(e);
+  k_energy_final<<<e.N, 256, 0, s>>>(e);
+  k_energy_grad<<<div_up((long)e.N * 3 * e.Dp * e.Hp * e.Wp, 256), 256, 0, s>>>(e, gy);
 }
 
 // x0 = alpha u0 with alpha = (f . u0) / (u0 . K u0) (sums[0], sums[1]).

@@ -600,6 +600,20 @@ int validate(const sgmg_options* o) {
 }  // namespace
 
 // ===========================================================================
+namespace sgmg {
+int hierarchy_fine_view(const ::sgmg_hierarchy* h, FineView* v) {
+  if (!h || !v) return SGMG_EINVAL;
+  v->g = h->lev[0].g;
+  v->fixn = h->lev[0].fixn;
+  v->ke = h->ke64;
+  v->is_modulus = h->o.input_is_modulus;
+  v->E0 = h->o.E0;
+  v->Emin = h->o.Emin;
+  v->penal = h->o.penal;
+  return 0;
+}
+}  // namespace sgmg
+
 extern "C" {
 
 const char* sgmg_last_error(void) { return g_err.c_str(); }

@@ -516,16 +516,20 @@ def batch():
 
 
 def train_warm_start(n_train=2000, train_seconds=120.0, batch_size=8, lr=1e-3, seed=2024,
-                     progress=True):
+                     progress=True, loss="energy"):
     """U-Net trained on solver-generated 32^3 random-field pairs (GRF seeds
-    10000+, p = 3, random face loads, FP32-GMG-PCG to 1e-8).  Returns the
-    network and a record of the data generation and training."""
+    10000+, p = 3, random face loads, FP32-GMG-PCG to 1e-8).  loss "energy":
+    the library's energy-norm score (the squared energy-norm error the
+    scaled prediction leaves, relative to the zero start's); "mse": the
+    masked MSE against u / max|u|.  Returns the network and a record of the
+    data generation and training."""
     dev = "cuda:0"
     rng = np.random.default_rng(seed)
     dims = (32, 32, 32)
     t0 = time.perf_counter()
-    X, T, M = [], [], []
+    X, T, M, R, F, C = [], [], [], [], [], []
     iters = []
+    h_keep = None
     for k in range(n_train):
         rho = torch.tensor(workloads.grf_rho(dims, 10000 + k), dtype=torch.float64, device=dev)
         f = torch.tensor(workloads.random_face_load(dims, rng), dtype=torch.float64, device=dev)
@@ -537,10 +541,17 @@ def train_warm_start(n_train=2000, train_seconds=120.0, batch_size=8, lr=1e-3, s
         t, m = simpgmg.unet_target(h, u)
         T.append(t)
         M.append(m)
-        h.close()
+        R.append(rho)
+        F.append(f)
+        C.append(torch.dot(f, u).reshape(1))            # compliance f.u*, the score's scale
+        if h_keep is None:
+            h_keep = h                                  # the mesh and clamps of every sample
+        else:
+            h.close()
         if progress and (k + 1) % 250 == 0:
             print(json.dumps({"pairs": k + 1, "s": round(time.perf_counter() - t0, 1)}), flush=True)
     X, T, M = torch.cat(X), torch.cat(T), torch.cat(M)
+    R, F, C = torch.stack(R), torch.stack(F), torch.cat(C)
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
     net = simpgmg.UNet(seed=0)
@@ -548,12 +559,18 @@ def train_warm_start(n_train=2000, train_seconds=120.0, batch_size=8, lr=1e-3, s
     losses, steps = [], 0
     while time.perf_counter() - t0 < train_seconds:
         idx = torch.as_tensor(rng.choice(n_train, size=batch_size, replace=False), device=dev)
-        losses.append(net.train_step(X[idx].contiguous(), T[idx].contiguous(), M[idx].contiguous(), lr=lr))
+        if loss == "energy":
+            losses.append(net.energy_step(h_keep, X[idx].contiguous(), R[idx].contiguous(),
+                                          F[idx].contiguous(), C[idx].contiguous(), lr=lr))
+        else:
+            losses.append(net.train_step(X[idx].contiguous(), T[idx].contiguous(),
+                                         M[idx].contiguous(), lr=lr))
         steps += 1
         if progress and steps % 500 == 0:
             print(json.dumps({"step": steps, "loss": float(np.mean(losses[-50:]))}), flush=True)
     train_s = time.perf_counter() - t0
-    rec = {"n_train": n_train, "train_pairs_gen_s": round(gen_s, 2),
+    h_keep.close()
+    rec = {"loss": loss, "n_train": n_train, "train_pairs_gen_s": round(gen_s, 2),
            "train_solve_iters_mean": float(np.mean(iters)), "train_steps": steps,
            "train_s": round(train_s, 2), "batch": batch_size,
            "loss_first10": float(np.mean(losses[:10])), "loss_last10": float(np.mean(losses[-10:])),
@@ -585,7 +602,13 @@ def warm_vs_cold(net, h, rho, f, rtol=1e-6, maxit=500, reps=3):
         torch.cuda.synchronize()
         warm_ms.append((time.perf_counter() - t1) * 1e3)
         net_ms.append((t2 - t1) * 1e3)
-    return {"cold_iters": cold["iters"], "cold_status": cold["status"],
+    # the prediction's energy-norm score on this case (compliance of the cold
+    # solution as the scale): the squared energy-norm error of the scaled
+    # start relative to the zero start's
+    c = torch.dot(f, u).reshape(1)
+    score = net.energy_step(h, x, rho.reshape(1, -1), f.reshape(1, -1), c, lr=0.0)
+    return {"energy_score": score, "energy_err_ratio": float(np.sqrt(max(score, 0.0))),
+            "cold_iters": cold["iters"], "cold_status": cold["status"],
             "cold_ms": round(float(np.mean(cold_ms)), 3),
             "warm_iters": warm["iters"], "warm_status": warm["status"],
             "warm_rel_res_true": warm["rel_res_true"],
@@ -594,12 +617,17 @@ def warm_vs_cold(net, h, rho, f, rtol=1e-6, maxit=500, reps=3):
             "warm_initial_rel_res": warm["history"][0], "alpha": alpha}
 
 
-def warmstart(n_train=2000, train_seconds=120.0):
-    """Learned warm start: the network of train_warm_start, then 100^3
-    uniform and random-field cantilevers (edge load) solved by
-    FP32-GMG-PCG to 1e-6 from zero and from the scaled prediction."""
+def warmstart(n_train=2000, train_seconds=120.0, loss="energy"):
+    """Learned warm start: the network of train_warm_start (trained on the
+    given loss), then 100^3 uniform and random-field cantilevers (edge load)
+    solved by FP32-GMG-PCG to 1e-6 from zero and from the scaled prediction.
+    Command line: warmstart [energy|mse] [training seconds]."""
     dev = "cuda:0"
-    net, rec = train_warm_start(n_train, train_seconds)
+    if len(sys.argv) > 2 and sys.argv[1] == "warmstart":
+        loss = sys.argv[2]
+        if len(sys.argv) > 3:
+            train_seconds = float(sys.argv[3])
+    net, rec = train_warm_start(n_train, train_seconds, loss=loss)
     rec["tests"] = []
     n = 100
     tdims = (n, n, n)

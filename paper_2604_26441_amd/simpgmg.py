@@ -87,7 +87,8 @@ EXPORTS = [
     "sgmg_pcg_solve_batch_concurrent", "sgmg_batch_hierarchy",
     "sgmg_batch_block_size", "sgmg_batch_destroy", "sgmg_batch_item_layout",
     "sgmg_unet_create", "sgmg_unet_num_params", "sgmg_unet_set_params", "sgmg_unet_get_params",
-    "sgmg_unet_forward", "sgmg_unet_grad", "sgmg_unet_train_step", "sgmg_unet_input",
+    "sgmg_unet_forward", "sgmg_unet_grad", "sgmg_unet_train_step", "sgmg_unet_energy_step",
+    "sgmg_unet_input",
     "sgmg_unet_output", "sgmg_unet_target", "sgmg_warm_start_scale",
     "sgmg_warm_start_scale_noalloc", "sgmg_unet_destroy",
     "sgmg_simp_default_params", "sgmg_simp_create", "sgmg_simp_destroy", "sgmg_simp_physical",
@@ -142,6 +143,7 @@ def _load():
     lib.sgmg_unet_forward.argtypes = [H, i, i, i, i, vp, vp, vp]
     lib.sgmg_unet_grad.argtypes = [H, i, i, i, i, vp, vp, vp, fp, fp, vp]
     lib.sgmg_unet_train_step.argtypes = [H, i, i, i, i, vp, vp, vp, ctypes.c_float, fp, vp]
+    lib.sgmg_unet_energy_step.argtypes = [H, H, i, i, i, i, vp, vp, vp, vp, ctypes.c_float, fp, fp, vp]
     lib.sgmg_unet_input.argtypes = [H, vp, vp, i, i, i, vp, vp]
     lib.sgmg_unet_output.argtypes = [H, vp, i, i, i, vp, vp]
     lib.sgmg_unet_target.argtypes = [H, vp, i, i, i, vp, vp, vp]
@@ -552,6 +554,20 @@ class UNet:
                                          None if mask is None else _ptr(mask, torch.float32), lr,
                                          ctypes.byref(loss), _stream(stream)))
         return loss.value
+
+    def energy_step(self, h, x, rho_or_E, f, cstar, lr=0.0, grads=False, stream=None):
+        """Energy-norm score of the batch (mean over samples) and, with lr > 0,
+        one Adam step; with grads=True also returns the gradients."""
+        import numpy as np
+        N, C, D, H, W = x.shape
+        g = np.zeros(self.num_params(), dtype=np.float32) if grads else None
+        loss = ctypes.c_float()
+        _check(_lib.sgmg_unet_energy_step(
+            self._u, h.handle, N, D, H, W, _ptr(x, torch.float32, name="in"),
+            _ptr(rho_or_E, torch.float64, name="rho_or_E"), _ptr(f, torch.float64, name="f"),
+            _ptr(cstar, torch.float64, name="cstar"), float(lr), ctypes.byref(loss),
+            None if g is None else g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream(stream)))
+        return (loss.value, g) if grads else loss.value
 
 
 def unet_input(h, rho, f, stream=None):

@@ -127,3 +127,51 @@ def test_training_and_warm_start():
     np.testing.assert_allclose(x0, a_ref * raw, rtol=1e-9, atol=1e-300)
     # ||u* - x0||_K^2 - ||u*||_K^2 = x0.K.x0 - 2 f.x0 = -(f.raw)^2 / raw.K.raw <= 0
     assert x0 @ (K @ x0) - 2 * f @ x0 <= 1e-12 * abs(f @ x0)
+
+
+def test_energy_score_gradients_match_oracle():
+    """Energy-norm training score: the device loss and parameter gradients
+    against the oracle's score (sparse K of each sample, compliance from a
+    direct solve) pushed through the oracle network's backward pass."""
+    import torch
+    import scipy.sparse.linalg as spla
+    from paper_2604_26441_amd import simpgmg
+    dims = (16, 8, 8)
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    rng = np.random.default_rng(21)
+    rhos = [workloads.grf_rho(dims, seed=700 + k) for k in range(2)]
+    fs = [workloads.random_face_load(dims, rng) for _ in range(2)]
+    Ks, cs = [], []
+    for rho, f in zip(rhos, fs):
+        K = mesh.assemble(dims, mesh.simp_modulus(rho, 3), fixed=fixed)
+        fr = ~fixed
+        us = np.zeros(fixed.size)
+        us[fr] = spla.spsolve(K[fr][:, fr].tocsc(), f[fr])
+        Ks.append(K)
+        cs.append(float(f @ us))
+    h = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, n_levels=2), t64(rhos[0]))
+    X = torch.cat([simpgmg.unet_input(h, t64(r), t64(f)) for r, f in zip(rhos, fs)])
+    params = _rounded_params(12)
+    net = simpgmg.UNet(seed=1)
+    net.set_params(_flat(params))
+    loss, grads = net.energy_step(h, X, t64(np.stack(rhos)), t64(np.stack(fs)), t64(np.array(cs)),
+                                  lr=0.0, grads=True)
+    x = np64(X)
+    y, cache = unet.forward(params, x)
+    lref, dy = unet.loss_energy(y, Ks, fs, cs, dims, fixed)
+    gref = unet.backward(params, cache, dy)
+    assert 0.0 < lref <= 1.0
+    assert abs(loss - lref) <= 1e-5 * abs(lref), (loss, lref)
+    off = 0
+    for (dw, db) in gref:
+        gw = grads[off:off + dw.size].reshape(dw.shape)
+        off += dw.size
+        gb = grads[off:off + db.size]
+        off += db.size
+        assert np.linalg.norm(gw - dw) <= 1e-3 * np.linalg.norm(dw)
+        assert np.linalg.norm(gb - db) <= 1e-3 * max(np.linalg.norm(db), 1e-12)
+    # an Adam step on this score lowers it
+    l0 = net.energy_step(h, X, t64(np.stack(rhos)), t64(np.stack(fs)), t64(np.array(cs)), lr=1e-3)
+    for _ in range(30):
+        l1 = net.energy_step(h, X, t64(np.stack(rhos)), t64(np.stack(fs)), t64(np.array(cs)), lr=1e-3)
+    assert l1 < l0
