@@ -21,6 +21,8 @@ struct BSys {               // one system (its hierarchy's operators)
   int L;
   BLevel lev[8];
   const float* E32;
+  const float* E32s;        // E / s for the BF16-family MFMA operator
+  const uint16_t* atab;     // its A-operand table
   const float* ke32;
   const double* E64;
   const double* ke64;
@@ -41,6 +43,28 @@ struct BItem {              // one (system, load case) solve and its work vector
   double* lr[8];
   double* rc;
 };
+
+// Chebyshev (Saad 12.1) or damped-Jacobi coefficients of smoothing step k
+// (pre: k >= 1, the step from zero being done elsewhere; post: k >= 0).
+__device__ inline void smooth_coef(const BLevel& V, bool post, int k, double& c1, double& c2) {
+  if (!V.cheb) {
+    c1 = 0.0;
+    c2 = V.omega;
+    return;
+  }
+  if (post && k == 0) {
+    c1 = 0.0;
+    c2 = 1.0 / V.theta;
+    return;
+  }
+  double rho = 1.0 / V.sigma1, rn = rho;
+  for (int j = 0; j < k; ++j) {
+    rn = 1.0 / (2.0 * V.sigma1 - rho);
+    c1 = rn * rho;
+    rho = rn;
+  }
+  c2 = 2.0 * rn / V.delta;
+}
 
 struct BOut {
   int status, iters;

@@ -54,5 +54,12 @@ void bs_coarse(const BsArgs& a, const BsTable& tg, const BsTable& tm, const int*
                hipStream_t s);
 void bs_prolong(const BsArgs& a, const BsTable& t, const int* flags, int l, int cfine, int ccoarse,
                 hipStream_t s);
+// Level 0 on the BF16X3 MFMA operator: the tile grid of a mesh for launch
+// shape (rows, zchunk) as (ntx, nty, ntiles, blocks), and the stage launch
+// (mode EPI_SMOOTH with post / k / last as bs_smooth0, or EPI_RESID) over a
+// table of (item, block) entries with geo[item] = that item's grid.
+int4 bs_mfma_geometry(const Grid& g, int rows, int zchunk);
+void bs_fine_mfma(const BsArgs& a, const BsTable& t, const int4* geo, const int* flags, int rows,
+                  int zchunk, int mode, int post, int k, int cin, int last, hipStream_t s);
 
 }  // namespace sgmg

@@ -114,6 +114,8 @@ struct Epi {
   RedWs ws;
   double* dot_out;     // finalized by the launcher after the kernel (NULL: the
                        // block partials stay in ws.partials)
+  const double* dot64 = nullptr;   // SMOOTH with out64 on the BF16-family MFMA operator:
+                                   // block partials of dot64 . out64 into ws.partials
 };
 
 template <typename T>

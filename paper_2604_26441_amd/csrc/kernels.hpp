@@ -103,13 +103,14 @@ void launch_pcg_dot_rz(const double* r, const double* z, const double* r_old, in
                        double* sc_out2, hipStream_t s);
 // Block count (= partials per reduced value) of the vector kernels above.
 int pcg_vec_partials(int n);
-// p = z + beta p with the r.z partials added in every block (no finalize
-// launch); block 0 stores r.z [and r_old.z] at sc[slot_num] [slot_num + 1]
-// and the sum of the r.r partials at sc[slot_rr]; with host not NULL (a
+// p = z + beta p with the nrz r.z partials (then nrz r_old.z partials with
+// flex) added in every block (no finalize launch); block 0 stores r.z [and
+// r_old.z] at sc[slot_num] [slot_num + 1] and the sum of the r.r partials
+// (pcg_vec_partials(n) of them) at sc[slot_rr]; with host not NULL (a
 // device-mapped, coherent host array in sc's layout) it also writes those
 // and sc[slot_pq] there, then increments the launch counter sc[slot_seq] and
 // writes its new value to *host_seq (mapped too) after the scalars.
-void launch_pcg_update_p_red(double* p, const double* z, const double* rz_part,
+void launch_pcg_update_p_red(double* p, const double* z, const double* rz_part, int nrz,
                              const double* rr_part, double* sc, int slot_num, int flex,
                              int slot_den, int slot_rr, int slot_pq, int slot_seq, double* host,
                              double* host_seq, int n, hipStream_t s);

@@ -28,28 +28,6 @@ __device__ inline bool active_block(const int2* __restrict__ tab, const int* __r
   return flags[s.item] != 0;
 }
 
-// Chebyshev (Saad 12.1) or damped-Jacobi coefficients of smoothing step k
-// (pre: k >= 1, the step from zero being done elsewhere; post: k >= 0).
-__device__ inline void smooth_coef(const BLevel& V, bool post, int k, double& c1, double& c2) {
-  if (!V.cheb) {
-    c1 = 0.0;
-    c2 = V.omega;
-    return;
-  }
-  if (post && k == 0) {
-    c1 = 0.0;
-    c2 = 1.0 / V.theta;
-    return;
-  }
-  double rho = 1.0 / V.sigma1, rn = rho;
-  for (int j = 0; j < k; ++j) {
-    rn = 1.0 / (2.0 * V.sigma1 - rho);
-    c1 = rn * rho;
-    rho = rn;
-  }
-  c2 = 2.0 * rn / V.delta;
-}
-
 template <int NV>
 __device__ inline void block_partials(const double (&v)[NV], double* __restrict__ part) {
   __shared__ double lds[16 * NV];

@@ -33,6 +33,8 @@
 #include <cstring>
 #include <type_traits>
 
+#include "batch.hpp"
+#include "bstage.hpp"
 #include "kernels.hpp"
 
 namespace sgmg {
@@ -76,8 +78,11 @@ __device__ inline void bload3(__amdgpu_buffer_rsrc_t r, int off, double* v) {
   v[2] = __hiloint2double((int)w[1], (int)w[0]);
 }
 
-// Kernel-internal epilogue variant: EPI_STORE plus the x.y dot product.
+// Kernel-internal epilogue variants: EPI_STORE plus the x.y dot product;
+// EPI_SMOOTH with the FP64 copy of x_out plus the dot of that copy with the
+// FP64 vector ep.dot64 (the cycle's last step and the PCG's r.z in one pass).
 constexpr int kStoreDot = 3;
+constexpr int kSmoothDot = 4;
 
 __device__ inline void bstore3(__amdgpu_buffer_rsrc_t r, int off, float a, float b, float c) {
   typedef unsigned u32x3 __attribute__((ext_vector_type(3)));
@@ -139,11 +144,16 @@ __device__ inline float dpp_shr1(float v) {   // lane n-1 of the same 16-lane ro
 //   moduli of plane ez + 1, epilogue operands of plane ez) and consumed by
 //   its end or the start of the next plane, unconditionally (an unneeded
 //   load reads zeros), so the compiler's load-counter waits stay exact.
+//   The body takes the block's index in the mesh's tile grid (blk), so the
+//   same code serves one mesh (blk from the launch grid) and the stage-
+//   batched solver (blk from its table of (item, block) entries).
 template <int NSPLIT, int YC, int MODE>
-__global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
-    Grid g, const float* __restrict__ Es, const uint16_t* __restrict__ atab,
-    const float* __restrict__ u, const uint8_t* __restrict__ fixn, Epi<float> ep, int zchunk,
-    int ntx, int nty, int ntiles) {
+__device__ __forceinline__ void fine_mfma_body(Grid g, const float* __restrict__ Es,
+                                               const uint16_t* __restrict__ atab,
+                                               const float* __restrict__ u,
+                                               const uint8_t* __restrict__ fixn,
+                                               Epi<float> ep, int zchunk, int ntx, int nty,
+                                               int ntiles, int blk) {
   using LD = FineLds<NSPLIT, YC>;
   static_assert(YC == 4 || YC == 8, "tile rows");
   __shared__ __attribute__((aligned(16))) unsigned char lds_all[kMfmaWavesPerBlock * LD::kWave];
@@ -151,7 +161,7 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
   // wave index made wave-uniform, so all tile arithmetic stays scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   unsigned char* const lds = lds_all + wave * LD::kWave;
-  const int tile = xcd_block(blockIdx.x, gridDim.x) * kMfmaWavesPerBlock + wave;
+  const int tile = blk * kMfmaWavesPerBlock + wave;
   const int tx = tile % ntx, tt = tile / ntx, ty = tt % nty, tz = tt / nty;
   const int grp = lane >> 4, n = lane & 15;
   const int xs = tx * 15, ys = ty * (YC - 1), zs = tz * zchunk;
@@ -174,10 +184,12 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
   const __amdgpu_buffer_rsrc_t ru = make_rsrc(u, nvec);
   const __amdgpu_buffer_rsrc_t re = make_rsrc(Es, (size_t)g.nel * sizeof(float));
   const __amdgpu_buffer_rsrc_t rfix = make_rsrc(fixn, (size_t)g.Nn);
-  const __amdgpu_buffer_rsrc_t rb = make_rsrc(ep.b, MODE == EPI_RESID || MODE == EPI_SMOOTH ? nvec : 0);
-  const __amdgpu_buffer_rsrc_t rdi = make_rsrc(ep.dinv, MODE == EPI_SMOOTH ? nvec : 0);
-  const __amdgpu_buffer_rsrc_t rd = make_rsrc(ep.d, MODE == EPI_SMOOTH ? nvec : 0);
+  constexpr bool kSm = MODE == EPI_SMOOTH || MODE == kSmoothDot;
+  const __amdgpu_buffer_rsrc_t rb = make_rsrc(ep.b, MODE == EPI_RESID || kSm ? nvec : 0);
+  const __amdgpu_buffer_rsrc_t rdi = make_rsrc(ep.dinv, kSm ? nvec : 0);
+  const __amdgpu_buffer_rsrc_t rd = make_rsrc(ep.d, kSm ? nvec : 0);
   const __amdgpu_buffer_rsrc_t rout = make_rsrc(ep.out, ep.out ? nvec : 0);   // NULL: stores dropped
+  const __amdgpu_buffer_rsrc_t rr = make_rsrc(ep.dot64, MODE == kSmoothDot ? 2 * nvec : 0);
 
   // Offsets are the sum of a per-lane part fixed for the whole wave and a
   // plane part; a part that must not be accessed is kPoison.  Vectors are
@@ -272,7 +284,7 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
   // node-layout epilogue: group i, lane l < 60 owns node xs + l % 15 of node
   // row 1 + 4 i + l / 15 (rows 1 .. YC - 1 of the tile)
   constexpr int NG = (YC + 2) / 4;
-  constexpr int NV = MODE == EPI_SMOOTH ? 4 : (MODE == EPI_RESID || MODE == kStoreDot) ? 1 : 0;
+  constexpr int NV = kSm ? 4 : (MODE == EPI_RESID || MODE == kStoreDot) ? 1 : 0;
   const int oj = lane % 15, orr = lane / 15;
   int o_lane[NG], f_lane[NG], o_lds[NG];
 #pragma unroll
@@ -284,6 +296,7 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
     o_lds[i] = LD::kU + (min(rr, YC - 1) - 1) * LD::kORow + (oj + 1) * 16;
   }
   float vv[NG][NV > 0 ? NV : 1][3];
+  double rv[MODE == kSmoothDot ? NG : 1][3];    // the FP64 dot partner of owned nodes
   unsigned fv[NG];
   auto load_v = [&](int ez) {
     const bool own = ez >= zs && ez < zend;
@@ -292,11 +305,14 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
     for (int i = 0; i < NG; ++i) {
       fv[i] = __builtin_amdgcn_raw_buffer_load_b8(rfix, off2(f_lane[i], pf), 0, 0);
       const int o = off2(o_lane[i], po);
-      if (MODE == EPI_SMOOTH) {
+      if (kSm) {
         bload3(ru, o, vv[i][0]);
         bload3(rb, o, vv[i][1]);
         bload3(rdi, o, vv[i][2]);
         bload3(rd, ep.c1 != 0.0 ? o : kNoOffset, vv[i][3]);
+        // 24 B per node at twice the float offset (below 2^31 for owned nodes)
+        if (MODE == kSmoothDot)
+          bload3(rr, (unsigned)o < (unsigned)kPoison ? 2 * o : kNoOffset, rv[i]);
       } else if (MODE == EPI_RESID) {
         bload3(rb, o, vv[i][0]);
       } else if (MODE == kStoreDot) {
@@ -329,7 +345,7 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
         }
       }
       bstore3(rout, o, out[0], out[1], out[2]);
-      if (MODE == EPI_SMOOTH) {
+      if (kSm) {
         if (ep.store_d) bstore3(rd, o, dd[0], dd[1], dd[2]);
         if (ep.out64 && mine) {
           double* q = ep.out64 + (o >> 2);
@@ -337,6 +353,8 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
           q[1] = (double)out[1];
           q[2] = (double)out[2];
         }
+        if (MODE == kSmoothDot && mine)
+          dot += rv[i][0] * (double)out[0] + rv[i][1] * (double)out[1] + rv[i][2] * (double)out[2];
       }
     }
   };
@@ -390,10 +408,55 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
     }
     finish_plane(ez);
   }
-  if (MODE == kStoreDot) {
+  if (MODE == kStoreDot || MODE == kSmoothDot) {
     const double vd[1] = {dot};
     grid_sum<1>(vd, ep.ws);
   }
+}
+
+template <int NSPLIT, int YC, int MODE>
+__global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma(
+    Grid g, const float* __restrict__ Es, const uint16_t* __restrict__ atab,
+    const float* __restrict__ u, const uint8_t* __restrict__ fixn, Epi<float> ep, int zchunk,
+    int ntx, int nty, int ntiles) {
+  fine_mfma_body<NSPLIT, YC, MODE>(g, Es, atab, u, fixn, ep, zchunk, ntx, nty, ntiles,
+                                   xcd_block(blockIdx.x, gridDim.x));
+}
+
+// Stage-batched form: one launch applies the level-0 smoothing step or
+// residual of every active item.  Block b is entry tab[b] = (item, block of
+// the item's tile grid); geo[item] holds that grid (ntx, nty, ntiles) for
+// the launch shape (YC rows, zchunk planes).  The epilogue's vectors and
+// smoothing coefficients are the item's (those of k_bs_apply0).
+template <int YC, int MODE>
+__global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_bs_fine_mfma(
+    const BSys* __restrict__ sys, const BItem* __restrict__ items, const int2* __restrict__ tab,
+    const int4* __restrict__ geo, const int* __restrict__ flags, int post, int k, int cin,
+    int last, int zchunk) {
+  const int2 e = tab[blockIdx.x];
+  if (!flags[e.x]) return;                     // uniform over the block
+  const BItem& I = items[e.x];
+  const BSys& S = sys[I.sys];
+  const BLevel& V = S.lev[0];
+  const int4 gm = geo[e.x];
+  Epi<float> ep{};
+  ep.mode = MODE;
+  ep.b = I.b0;
+  if (MODE == EPI_RESID) {
+    ep.out = I.r0;
+  } else {
+    double c1 = 0.0, c2 = 0.0;
+    smooth_coef(V, post != 0, k, c1, c2);
+    ep.out = I.x0[1 - cin];
+    ep.dinv = V.dinv32;
+    ep.d = I.d0;
+    ep.c1 = c1;
+    ep.c2 = c2;
+    ep.store_d = 1;
+    ep.out64 = last ? I.z : nullptr;
+  }
+  fine_mfma_body<3, YC, MODE>(V.g, S.E32s, S.atab, I.x0[cin], V.fixn, ep, zchunk, gm.x, gm.y,
+                              gm.z, e.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -705,6 +768,9 @@ static void launch_shape(const Grid& g, const MfmaLaunch& m, int zchunk, const f
   else if (ep.mode == EPI_RESID)
     k_apply_fine_mfma<NSPLIT, YC, EPI_RESID><<<grid, block, 0, s>>>(g, Es, at, u, fixn, ep, zchunk,
                                                                    m.ntx, m.nty, m.ntiles);
+  else if (ep.dot64)
+    k_apply_fine_mfma<NSPLIT, YC, kSmoothDot><<<grid, block, 0, s>>>(
+        g, Es, at, u, fixn, ep, zchunk, m.ntx, m.nty, m.ntiles);
   else
     k_apply_fine_mfma<NSPLIT, YC, EPI_SMOOTH><<<grid, block, 0, s>>>(
         g, Es, at, u, fixn, ep, zchunk, m.ntx, m.nty, m.ntiles);
@@ -821,6 +887,28 @@ void build_mfma_atab(const KeTables& kt, uint16_t* out /* 2*64*8 */) {
         out[(h * 64 + lane) * 8 + j] = (uint16_t)(bits >> 16);
       }
     }
+}
+
+int4 bs_mfma_geometry(const Grid& g, int rows, int zchunk) {
+  const MfmaLaunch m = mfma_launch(g, rows, zchunk);
+  return int4{m.ntx, m.nty, m.ntiles, m.blocks};
+}
+
+void bs_fine_mfma(const BsArgs& a, const BsTable& t, const int4* geo, const int* flags, int rows,
+                  int zchunk, int mode, int post, int k, int cin, int last, hipStream_t s) {
+  if (t.n == 0) return;
+  const dim3 grid(t.n), block(64 * kMfmaWavesPerBlock);
+#define SGMG_BSF(YC, M)                                                                       \
+  k_bs_fine_mfma<YC, M><<<grid, block, 0, s>>>(a.sys, a.items, t.blk, geo, flags, post, k, cin, \
+                                               last, zchunk)
+  if (rows == 4) {
+    if (mode == EPI_RESID) SGMG_BSF(4, EPI_RESID);
+    else SGMG_BSF(4, EPI_SMOOTH);
+  } else {
+    if (mode == EPI_RESID) SGMG_BSF(8, EPI_RESID);
+    else SGMG_BSF(8, EPI_SMOOTH);
+  }
+#undef SGMG_BSF
 }
 
 }  // namespace sgmg

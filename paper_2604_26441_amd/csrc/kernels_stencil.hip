@@ -247,21 +247,25 @@ void launch_stencil_to_f32(const double* S, float* S32, size_t n, hipStream_t s)
 // load of a wave is 64 consecutive values of one slot) and the block index
 // remapped per XCD so each L2 sees a contiguous node range.
 //
-// Plane-split form, for small levels (level 2 of an 80^3 mesh has 9,261
+// Row-split form, for small levels (level 2 of an 80^3 mesh has 9,261
 // nodes) that need many waves to cover memory latency: one thread per (node,
-// output component, stencil plane oz).  A block of three waves is one
-// component d of 64 nodes, wave = plane, so the grid has three blocks per
-// node tile (enough to reach every CU on such levels); the nine offsets of a
-// plane are read unconditionally (offsets outside the grid read the node
-// itself, a valid address, and add zero) and the three plane partials are
-// added in LDS in a fixed order.
+// output component, stencil row (oy, oz)).  A block of nine waves is one
+// component d of 64 nodes, wave = row, so the grid has three blocks per node
+// tile (enough to reach every CU on such levels) and each thread has only
+// the three offsets of its row in flight; the offsets are read
+// unconditionally (offsets outside the grid read the node itself, a valid
+// address, and add zero) and the nine row partials are added in LDS in a
+// fixed order.
+constexpr int kRowSplitThreads = 9 * 64;
+
 template <typename T>
-__global__ __launch_bounds__(192) void k_stencil_apply_c(Grid g, const T* __restrict__ S,
-                                                         const T* __restrict__ u,
-                                                         const uint8_t* __restrict__ fixn,
-                                                         Epi<T> ep) {
-  __shared__ double part[3][64];
-  const int lane = threadIdx.x & 63, pz = threadIdx.x >> 6;
+__global__ __launch_bounds__(kRowSplitThreads) void k_stencil_apply_c(Grid g,
+                                                                      const T* __restrict__ S,
+                                                                      const T* __restrict__ u,
+                                                                      const uint8_t* __restrict__ fixn,
+                                                                      Epi<T> ep) {
+  __shared__ double part[9][64];
+  const int lane = threadIdx.x & 63, pr = threadIdx.x >> 6;
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int d = lb % 3;
   const int node0 = (lb / 3) * 64 + lane;
@@ -270,7 +274,7 @@ __global__ __launch_bounds__(192) void k_stencil_apply_c(Grid g, const T* __rest
   const int node = in ? node0 : g.Nn - 1;
   // the epilogue's operands are loaded first (one memory round trip less)
   const size_t dof = 3 * (size_t)node + d;
-  const bool epi = in && pz == 1;
+  const bool epi = in && pr == 4;
   Epi1In<T> ein{(T)0, (T)0, (T)0};
   unsigned fx = 0;
   T xown = (T)0;
@@ -284,8 +288,8 @@ __global__ __launch_bounds__(192) void k_stencil_apply_c(Grid g, const T* __rest
     const size_t Nn = g.Nn;
     T acc = (T)0;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      const int o = 9 * pz + q;
+    for (int q = 0; q < 3; ++q) {
+      const int o = 3 * pr + q;
       const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
       const bool ok = (unsigned)(i + ox) < (unsigned)g.Nx && (unsigned)(j + oy) < (unsigned)g.Ny &&
                       (unsigned)(k + oz) < (unsigned)g.Nz;
@@ -302,12 +306,14 @@ __global__ __launch_bounds__(192) void k_stencil_apply_c(Grid g, const T* __rest
       }
       acc += ok ? v : (T)0;
     }
-    part[pz][lane] = (double)acc;
+    part[pr][lane] = (double)acc;
   }
   __syncthreads();
   double dot = 0.0;
   if (epi) {
-    const double y = (part[0][lane] + part[1][lane]) + part[2][lane];
+    double y = 0.0;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) y += part[r][lane];
     dot = epilogue1(ep, dof, (fx >> d) & 1u, xown, y, ein);
   }
   if (ep.want_dot) {
@@ -422,7 +428,7 @@ void launch_stencil_apply(const Grid& g, const T* S, const T* u, const uint8_t* 
   if (staged)
     k_stencil_apply_s<T><<<nb, 192, 0, s>>>(g, S, u, fixn, ep);
   else
-    k_stencil_apply_c<T><<<nb, 192, 0, s>>>(g, S, u, fixn, ep);
+    k_stencil_apply_c<T><<<nb, kRowSplitThreads, 0, s>>>(g, S, u, fixn, ep);
   if (ep.want_dot && ep.dot_out) launch_finalize(ep.ws, nb, 1, ep.dot_out, s);
 }
 template void launch_stencil_apply<double>(const Grid&, const double*, const double*,
@@ -543,42 +549,70 @@ __device__ inline void prolong_w1d(int i, int nf, int (&ci)[2], double (&w)[2]) 
   else { ci[0] = ci[1] = nc; w[0] = 1.0; w[1] = 0.0; }
 }
 
-// Thread per fine node (all three components); the fine values and the mask
-// are loaded together with the coarse values, and only free components are
-// stored.
+// Row form: a block owns (a chunk of up to 256 nodes of) one fine x-row.
+// The row's y and z candidates are uniform over the block, so the <= 4
+// coarse rows it reads are first combined with their y-z weights into one
+// coarse row segment in LDS (coalesced loads, zero weights skipped); each
+// thread then interpolates its node from two segment entries and updates
+// the node's three components (a free component gets its correction, a
+// masked one is stored back unchanged).
+constexpr int kProlongChunk = 256;                 // fine nodes per block (at most)
+constexpr int kProlongSeg = kProlongChunk / 2 + 1;  // coarse nodes per chunk (at most)
+
 template <typename TF, typename TC>
-__global__ __launch_bounds__(256) void k_prolong_add(Grid f, Grid c, const TC* __restrict__ ec,
-                                                     const uint8_t* __restrict__ ffix,
-                                                     TF* __restrict__ xf) {
-  const int i = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  if (i >= f.Nn) return;
-  const int ix = i % f.Nx, t = i / f.Nx, iy = t % f.Ny, iz = t / f.Ny;
-  TF* xi = xf + 3 * (size_t)i;
-  const TF x0 = xi[0], x1 = xi[1], x2 = xi[2];
-  const unsigned fx = ffix[i];
-  int cx[2], cy[2], cz[2];
-  double wx[2], wy[2], wz[2];
-  prolong_w1d(ix, f.nx, cx, wx);
+__global__ __launch_bounds__(kProlongChunk) void k_prolong_add(Grid f, Grid c, int chunks,
+                                                               const TC* __restrict__ ec,
+                                                               const uint8_t* __restrict__ ffix,
+                                                               TF* __restrict__ xf) {
+  __shared__ double seg[3 * kProlongSeg];
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk / chunks, x0 = (blk - row * chunks) * kProlongChunk;
+  const int iy = row % f.Ny, iz = row / f.Ny;
+  int cy[2], cz[2];
+  double wy[2], wz[2];
   prolong_w1d(iy, f.ny, cy, wy);
   prolong_w1d(iz, f.nz, cz, wz);
-  double acc[3] = {0.0, 0.0, 0.0};
+  const int cx0 = x0 >> 1;
+  const int nseg = min(kProlongSeg, c.Nx - cx0);
+  // the node's values and mask are loaded first, so their latency overlaps
+  // the segment's loads
+  const int ix = x0 + threadIdx.x;
+  const bool act = ix < f.Nx;
+  const size_t node = (size_t)(act ? ix : f.Nx - 1) + (size_t)f.Nx * row;
+  TF* xn = xf + 3 * node;
+  TF xv[3] = {xn[0], xn[1], xn[2]};
+  const unsigned fx = ffix[node];
+  for (int q = threadIdx.x; q < 3 * nseg; q += blockDim.x) {
+    double v = 0.0;
 #pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    const double w = wx[a & 1] * wy[(a >> 1) & 1] * wz[a >> 2];
-    const size_t b = 3 * (size_t)(cx[a & 1] + c.Nx * (cy[(a >> 1) & 1] + (size_t)c.Ny * cz[a >> 2]));
-    acc[0] += w * (double)ec[b];
-    acc[1] += w * (double)ec[b + 1];
-    acc[2] += w * (double)ec[b + 2];
+    for (int a = 0; a < 4; ++a) {
+      const double w = wy[a & 1] * wz[a >> 1];
+      if (w != 0.0)
+        v += w * (double)ec[3 * ((size_t)cx0 + (size_t)c.Nx * (cy[a & 1] + (size_t)c.Ny * cz[a >> 1])) + q];
+    }
+    seg[q] = v;
   }
-  if (!(fx & 1u)) xi[0] = (TF)((double)x0 + acc[0]);
-  if (!(fx & 2u)) xi[1] = (TF)((double)x1 + acc[1]);
-  if (!(fx & 4u)) xi[2] = (TF)((double)x2 + acc[2]);
+  __syncthreads();
+  if (!act) return;
+  int cx[2];
+  double wx[2];
+  prolong_w1d(ix, f.nx, cx, wx);
+  const int s0 = 3 * (cx[0] - cx0), s1 = 3 * (cx[1] - cx0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (!((fx >> k) & 1u)) xv[k] = (TF)((double)xv[k] + (wx[0] * seg[s0 + k] + wx[1] * seg[s1 + k]));
+  xn[0] = xv[0];
+  xn[1] = xv[1];
+  xn[2] = xv[2];
 }
 
 template <typename TF, typename TC>
 void launch_prolong_add(const Grid& fine, const Grid& coarse, const TC* ec, const uint8_t* ffix,
                         TF* xf, hipStream_t s) {
-  k_prolong_add<TF, TC><<<div_up(fine.Nn, 256), 256, 0, s>>>(fine, coarse, ec, ffix, xf);
+  const int chunks = div_up(fine.Nx, kProlongChunk);
+  const int threads = fine.Nx >= kProlongChunk ? kProlongChunk : div_up(fine.Nx, 64) * 64;
+  k_prolong_add<TF, TC><<<chunks * fine.Ny * fine.Nz, threads, 0, s>>>(fine, coarse, chunks, ec,
+                                                                       ffix, xf);
 }
 template void launch_prolong_add<float, double>(const Grid&, const Grid&, const double*,
                                                 const uint8_t*, float*, hipStream_t);

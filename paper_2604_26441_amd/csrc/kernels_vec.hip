@@ -308,14 +308,16 @@ void launch_pcg_dot_rz(const double* r, const double* z, const double* r_old, in
 
 int pcg_vec_partials(int n) { return (int)vec_grid(n); }
 
-// p = z + beta p where the block partials of r.z (and r_old.z) from
-// k_pcg_dot_rz are added here, by every block in the same order, instead of
+// p = z + beta p where the block partials of r.z (nrz of them, then as many
+// of r_old.z) are added here, by every block in the same order, instead of
 // by a separate finalize launch: beta = (rz - [r_old.z]) / sc[slot_den].
+// The nb r.r partials are those of the preceding update.
 // Block 0 also stores rz (and r_old.z) into sc[slot_num] (sc[slot_num + 1])
 // and the sum of the r.r partials of the preceding update into sc[slot_rr].
 __global__ __launch_bounds__(kVecBlock) void k_pcg_update_p_red(
     double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ rz_part,
-    const double* __restrict__ rr_part, int nb, double* __restrict__ sc, int slot_num, int flex,
+    int nrz, const double* __restrict__ rr_part, int nb, double* __restrict__ sc, int slot_num,
+    int flex,
     int slot_den, int slot_rr, int slot_pq, int slot_seq, double* host, double* host_seq, int n) {
   __shared__ double lds[3][16];
   __shared__ double tot[3];
@@ -329,11 +331,12 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_p_red(
     p0 = p[i0];
   }
   double a = 0.0, b = 0.0, c = 0.0;
-  for (int i = threadIdx.x; i < nb; i += kVecBlock) {
+  for (int i = threadIdx.x; i < nrz; i += kVecBlock) {
     a += rz_part[i];
-    if (flex) b += rz_part[nb + i];
-    if (blockIdx.x == 0) c += rr_part[i];
+    if (flex) b += rz_part[nrz + i];
   }
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < nb; i += kVecBlock) c += rr_part[i];
   a = block_sum(a, lds[0]);
   b = block_sum(b, lds[1]);
   c = block_sum(c, lds[2]);
@@ -366,13 +369,14 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_p_red(
   for (int i = i0 + stride; i < n; i += stride) p[i] = z[i] + beta * p[i];
 }
 
-void launch_pcg_update_p_red(double* p, const double* z, const double* rz_part,
+void launch_pcg_update_p_red(double* p, const double* z, const double* rz_part, int nrz,
                              const double* rr_part, double* sc, int slot_num, int flex,
                              int slot_den, int slot_rr, int slot_pq, int slot_seq, double* host,
                              double* host_seq, int n, hipStream_t s) {
-  k_pcg_update_p_red<<<vec_grid(n), kVecBlock, 0, s>>>(p, z, rz_part, rr_part, (int)vec_grid(n),
-                                                       sc, slot_num, flex, slot_den, slot_rr,
-                                                       slot_pq, slot_seq, host, host_seq, n);
+  k_pcg_update_p_red<<<vec_grid(n), kVecBlock, 0, s>>>(p, z, rz_part, nrz, rr_part,
+                                                       (int)vec_grid(n), sc, slot_num, flex,
+                                                       slot_den, slot_rr, slot_pq, slot_seq, host,
+                                                       host_seq, n);
 }
 
 // Largest value of a (non-negative entries, or masked by fixn when given).

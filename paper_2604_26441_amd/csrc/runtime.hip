@@ -88,6 +88,12 @@ struct sgmg_hierarchy {
   int* cpcg_done = nullptr;
   RedWs ws{};
   size_t npart = 0;          // doubles in ws.partials
+  // the PCG's r.z fused into the V-cycle's last fine smoothing step (BF16-
+  // family MFMA operator): the dot partner, set while an iteration graph is
+  // recorded, and that kernel's block partials (size: its largest grid)
+  const double* vc_dot64 = nullptr;
+  double* rz_part = nullptr;
+  size_t n_rz_part = 0;
   double* sc = nullptr;
   double* h_sc = nullptr;    // pinned mirror of sc
   double* h_it = nullptr;    // coherent, device-mapped: the scalars of the last PCG
@@ -526,8 +532,13 @@ int smooth_and_recurse(const sgmg_hierarchy* h, int l, int* cur, double* out64, 
     // the cycle's result leaves through out64 only: the level's own copy of
     // the last iterate is not written
     T* xout = last && out64 ? nullptr : (T*)L.x[1 - c];
-    TRY(apply_level<T>(h, l, prec, (const T*)L.x[c],
-                       epi_smooth<T>(xout, b, dinv, d, c1, c2, sm.cheb && !last, o64), s));
+    Epi<T> e = epi_smooth<T>(xout, b, dinv, d, c1, c2, sm.cheb && !last, o64);
+    if (l == 0 && last && out64 && h->vc_dot64) {
+      // the PCG's r.z: block partials of r . out64 (see pcg_body)
+      e.dot64 = h->vc_dot64;
+      e.ws.partials = h->rz_part;
+    }
+    TRY(apply_level<T>(h, l, prec, (const T*)L.x[c], e, s));
     c = 1 - c;
   }
   *cur = c;
@@ -795,6 +806,8 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
                                  apply_fine_mfma_blocks(g0, 4, 1) + 4096,
                                  h->L > 1 ? stencil_apply_blocks(h->lev[1].g) : (size_t)0});
   h->npart = npart;
+  h->n_rz_part = apply_fine_mfma_blocks(g0, 4, 1);
+  if ((rc = dalloc_t(h, &h->rz_part, h->n_rz_part))) return fail(rc);
   if ((rc = dalloc_t(h, &h->ws.partials, npart)) || (rc = dalloc_t(h, &h->ws.counter, 1)) ||
       (rc = dalloc_t(h, &h->sc, SC_COUNT)) || (rc = dalloc_t(h, &h->d_flag, 1)))
     return fail(rc);
@@ -923,6 +936,22 @@ static int pcg_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
     return SGMG_EINVAL;
   }
   TRY(apply_level<double>(h, 0, SGMG_F64, h->p, epi_store_partials<double>(h->q, h->ws), s));
+  // With the V-cycle as preconditioner, a fixed beta and a BF16-family MFMA
+  // fine level, the cycle's last smoothing step also forms r.z (the r.z
+  // launch and its reading of r and z drop out)
+  const sgmg_prec p0 = level_prec(h, 0);
+  const bool fuse_rz = precond == 2 && !flex && h->L > 1 && L0.f32 && smoother_of(h, 0).steps >= 1 &&
+                       (p0 == SGMG_BF16 || p0 == SGMG_BF16X3 || p0 == SGMG_BF16X2);
+  int nrz = 0;
+  if (fuse_rz) {
+    const int ns = p0 == SGMG_BF16 ? 1 : p0 == SGMG_BF16X2 ? 2 : 3;
+    const int rows = h->mfma_rows[ns >= 2] == 4 ? 4 : 8;
+    nrz = (int)apply_fine_mfma_blocks(L0.g, rows, std::max(1, h->mfma_zchunk[ns >= 2]));
+    if ((size_t)nrz > h->n_rz_part) {
+      set_error("fused r.z partials exceed their workspace");
+      return SGMG_EINVAL;
+    }
+  }
   if (precond == 2) {
     // the update also writes the V-cycle's entry (its first smoothing step)
     const Smoother sm = smoother_of(h, 0);
@@ -939,7 +968,10 @@ static int pcg_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
                                          sm.cheb ? (double*)L0.dv : nullptr, s);
     TRY(check_launch());
     int cur = 0;
-    TRY(vcycle_level(h, 0, &cur, h->z, true, s));
+    if (fuse_rz) h->vc_dot64 = h->r;
+    const int rc = vcycle_level(h, 0, &cur, h->z, true, s);
+    h->vc_dot64 = nullptr;
+    TRY(rc);
   } else {
     launch_pcg_update_xr_entry<double>(xin, xout, h->r, flex ? h->r_old : nullptr, h->p, h->q,
                                        sc, slot, SC_PQ, h->ws.partials, npq, n, ws_rr, nullptr, nullptr, nullptr, 0.0,
@@ -947,9 +979,10 @@ static int pcg_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
     if (precond == 1) launch_apply_dinv(L0.dinv64, h->r, h->z, n, s);
     else launch_copy(h->r, h->z, n, s);
   }
-  launch_pcg_dot_rz(h->r, h->z, flex ? h->r_old : nullptr, n, h->ws, nullptr, s);
-  launch_pcg_update_p_red(h->p, h->z, h->ws.partials, ws_rr.partials, sc, nslot, flex ? 1 : 0,
-                          slot, SC_RR, SC_PQ, SC_SEQ, h->d_it + SC_COUNT * (slot == SC_RZ0 ? 0 : 1),
+  if (!fuse_rz) launch_pcg_dot_rz(h->r, h->z, flex ? h->r_old : nullptr, n, h->ws, nullptr, s);
+  launch_pcg_update_p_red(h->p, h->z, fuse_rz ? h->rz_part : h->ws.partials,
+                          fuse_rz ? nrz : nb, ws_rr.partials, sc, nslot, flex ? 1 : 0, slot, SC_RR,
+                          SC_PQ, SC_SEQ, h->d_it + SC_COUNT * (slot == SC_RZ0 ? 0 : 1),
                           h->d_it + 2 * SC_COUNT, n, s);
   return check_launch();
 }
@@ -1835,6 +1868,13 @@ struct sgmg_batch {
     double* h_scal = nullptr;      // pinned mirror
     int Lmax = 0, steps0 = 0, stepsL = 0;
     hipGraphExec_t g_pro = nullptr, g_it = nullptr;
+    // level 0 on the BF16X3 MFMA operator: launch shape, (item, block)
+    // table and per-item tile grids
+    bool mfma0 = false;
+    int mrows = 0, mz = 0;
+    BsTable tm0;
+    const int4* geo = nullptr;
+    void* mdmem = nullptr;
   } st;
 };
 
@@ -1850,6 +1890,7 @@ void batch_free_staged(sgmg_batch* b) {
   if (st.g_pro) hipGraphExecDestroy(st.g_pro);
   if (st.g_it) hipGraphExecDestroy(st.g_it);
   if (st.dmem) hipFree(st.dmem);
+  if (st.mdmem) hipFree(st.mdmem);
   if (st.h_flags) hipHostFree(st.h_flags);
   if (st.h_scal) hipHostFree(st.h_scal);
   st = sgmg_batch::Staged{};
@@ -1892,6 +1933,8 @@ BSys make_bsys(const sgmg_hierarchy* h) {
     }
   }
   S.E32 = h->E32;
+  S.E32s = h->E32s;
+  S.atab = h->atab;
   S.ke32 = h->ke32;
   S.E64 = h->E64;
   S.ke64 = h->ke64;
@@ -1988,14 +2031,22 @@ void bs_vcycle(const sgmg_batch::Staged& st, const BsArgs& a, const int* flags, 
   unsigned cur = 0u;
   auto cb = [&](int l) { return (int)((cur >> l) & 1u); };
   auto flip = [&](int l) { cur ^= 1u << l; };
+  // level-0 smoothing step and residual: MFMA or vector-ALU operator
+  auto smooth0 = [&](int post, int k, int cin, int last) {
+    if (st.mfma0)
+      bs_fine_mfma(a, st.tm0, st.geo, flags, st.mrows, st.mz, EPI_SMOOTH, post, k, cin, last, s);
+    else
+      bs_smooth0(a, st.ts[0], flags, post, k, cin, last, s);
+  };
   for (int l = 0; l < st.Lmax - 1; ++l) {
     const int steps = l == 0 ? st.steps0 : st.stepsL;
     for (int k = 1; k < steps; ++k) {
-      if (l == 0) bs_smooth0(a, st.ts[0], flags, 0, k, cb(0), 0, s);
+      if (l == 0) smooth0(0, k, cb(0), 0);
       else bs_smoothL(a, st.ts[l], flags, l, cb(l), s);
       flip(l);
     }
-    if (l == 0) bs_resid0(a, st.ts[0], flags, cb(0), s);
+    if (l == 0 && st.mfma0) bs_fine_mfma(a, st.tm0, st.geo, flags, st.mrows, st.mz, EPI_RESID, 0, 0, cb(0), 0, s);
+    else if (l == 0) bs_resid0(a, st.ts[0], flags, cb(0), s);
     else bs_residL(a, st.ts[l], flags, l, cb(l), s);
     bs_restrict(a, st.tr[l], flags, l, s);
     cur &= ~(1u << (l + 1));
@@ -2005,7 +2056,7 @@ void bs_vcycle(const sgmg_batch::Staged& st, const BsArgs& a, const int* flags, 
     const int steps = l == 0 ? st.steps0 : st.stepsL;
     bs_prolong(a, st.ts[l], flags, l, cb(l), cb(l + 1), s);
     for (int k = 0; k < steps; ++k) {
-      if (l == 0) bs_smooth0(a, st.ts[0], flags, 1, k, cb(0), k == steps - 1, s);
+      if (l == 0) smooth0(1, k, cb(0), k == steps - 1);
       else bs_smoothL(a, st.ts[l], flags, l, cb(l), s);
       flip(l);
     }
@@ -2050,6 +2101,74 @@ int bs_capture(sgmg_batch* b, void (*body)(const sgmg_batch*, const BsArgs&, int
   const hipError_t e2 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
   if (e2 != hipSuccess) { *out = nullptr; set_error("staged batch graph instantiate failed"); return SGMG_EHIP; }
+  return 0;
+}
+
+// Level 0 of the staged solve on the BF16X3 MFMA operator: for each
+// candidate launch shape the (item, block) table and tile grids are built
+// and the smoothing stage over all items is timed (HIP events, three
+// launches after one warm-up, into the items' scratch vectors); the fastest
+// shape's table stays.  st.flags[0, n) must be allocated.
+int bs_tune_mfma(sgmg_batch* b, int n, hipStream_t s) {
+  auto& st = b->st;
+  const int shapes[4][2] = {{4, 2}, {4, 4}, {8, 2}, {8, 4}};
+  std::vector<int2> tabs[4];
+  std::vector<int4> geos[4];
+  size_t maxe = 0;
+  for (int c = 0; c < 4; ++c) {
+    for (int i = 0; i < n; ++i) {
+      const int4 gm = bs_mfma_geometry(b->hs[b->h_items[i].sys]->lev[0].g, shapes[c][0], shapes[c][1]);
+      geos[c].push_back(gm);
+      for (int j = 0; j < gm.w; ++j) tabs[c].push_back(int2{i, j});
+    }
+    maxe = std::max(maxe, tabs[c].size());
+  }
+  const size_t tb = (maxe * sizeof(int2) + 255) & ~(size_t)255;
+  const size_t gb = ((size_t)n * sizeof(int4) + 255) & ~(size_t)255;
+  char* m = nullptr;
+  if (hipMalloc((void**)&m, tb + gb) != hipSuccess) {
+    set_error("staged batch allocation failed");
+    return SGMG_ENOMEM;
+  }
+  st.mdmem = m;
+  int2* dtab = (int2*)m;
+  int4* dgeo = (int4*)(m + tb);
+  std::vector<int> ones(n, 1);
+  SGMG_HIP(hipMemcpyAsync(st.flags, ones.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+  hipEvent_t e0, e1;
+  SGMG_HIP(hipEventCreate(&e0));
+  SGMG_HIP(hipEventCreate(&e1));
+  const BsArgs a{b->d_sys, b->d_items};
+  float best = 0.f;
+  int bc = -1;
+  for (int c = 0; c < 4; ++c) {
+    SGMG_HIP(hipMemcpyAsync(dtab, tabs[c].data(), tabs[c].size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    SGMG_HIP(hipMemcpyAsync(dgeo, geos[c].data(), n * sizeof(int4), hipMemcpyHostToDevice, s));
+    BsTable t;
+    t.blk = dtab;
+    t.n = (int)tabs[c].size();
+    bs_fine_mfma(a, t, dgeo, st.flags, shapes[c][0], shapes[c][1], EPI_SMOOTH, 1, 1, 0, 0, s);
+    SGMG_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < 3; ++r)
+      bs_fine_mfma(a, t, dgeo, st.flags, shapes[c][0], shapes[c][1], EPI_SMOOTH, 1, 1, 0, 0, s);
+    SGMG_HIP(hipEventRecord(e1, s));
+    SGMG_HIP(hipEventSynchronize(e1));
+    TRY(check_launch());
+    float ms = 0.f;
+    SGMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (bc < 0 || ms < best) { best = ms; bc = c; }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  SGMG_HIP(hipMemcpyAsync(dtab, tabs[bc].data(), tabs[bc].size() * sizeof(int2), hipMemcpyHostToDevice, s));
+  SGMG_HIP(hipMemcpyAsync(dgeo, geos[bc].data(), n * sizeof(int4), hipMemcpyHostToDevice, s));
+  SGMG_HIP(hipStreamSynchronize(s));
+  st.tm0 = BsTable{};
+  st.tm0.blk = dtab;
+  st.tm0.n = (int)tabs[bc].size();
+  st.geo = dgeo;
+  st.mrows = shapes[bc][0];
+  st.mz = shapes[bc][1];
   return 0;
 }
 
@@ -2153,6 +2272,16 @@ int bs_prepare(sgmg_batch* b, int n, hipStream_t s) {
     return SGMG_ENOMEM;
   }
   SGMG_HIP(hipStreamSynchronize(s));
+  // level 0 on the matrix cores when every item's system runs its fine
+  // level in BF16X3 on the MFMA operator
+  bool mf = true;
+  for (int i = 0; i < n; ++i) {
+    const sgmg_hierarchy* h = b->hs[b->h_items[i].sys];
+    mf = mf && h->L > 1 && h->lev[0].f32 && level_prec(h, 0) == SGMG_BF16X3 && h->kt.integral &&
+         mfma_size_ok(h->lev[0].g);
+  }
+  st.mfma0 = mf;
+  if (mf) TRY(bs_tune_mfma(b, n, s));
   TRY(bs_capture(b, bs_prologue, n, &st.g_pro));
   TRY(bs_capture(b, bs_iteration, n, &st.g_it));
   st.ready = true;

@@ -513,6 +513,43 @@ def batch():
         rec[f"concurrent{nw}_ms"] = float(np.median(times))
         rec[f"concurrent{nw}_all_converged"] = all(r["status"] == "converged" for r in res)
     print(json.dumps(rec), flush=True)
+    # the same items with the fine level in BF16X3 on the matrix cores (the
+    # FP32-GMG schedule of the single solves): staged, sequential, concurrent
+    b.close()
+    opts = [simpgmg.default_options(*d, n_levels=0, dense_max=1000, fine_prec="bf16x3") for d in dims]
+    b = simpgmg.setup_batch(opts, [torch.tensor(r, dtype=torch.float64, device=dev) for r in rhos])
+    rec2 = {"fine_prec": "bf16x3"}
+    sruns = []
+    for rep in range(4):                                   # first run tunes the shape, captures
+        us = [torch.zeros_like(f) for f in ft]
+        sres, ms = simpgmg.pcg_solve_batch(b, item_sys, ft, us, rtol=1e-6, maxit=300, staged=True)
+        sruns.append(ms)
+    rec2["staged_ms_runs"] = sruns
+    rec2["staged_ms"] = float(np.mean(sruns[1:]))
+    rec2["staged_all_converged"] = all(r["status"] == "converged" for r in sres)
+    rec2["staged_iters"] = [r["iters"] for r in sres]
+    rec2["staged_max_rel_res_true"] = max(r["rel_res_true"] for r in sres)
+    hs = [b.hierarchy(q) for q in range(len(dims))]
+    tot = []
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for q, f in zip(item_sys, ft):
+            u = torch.zeros_like(f)
+            simpgmg.pcg_solve(hs[q], f, u, rtol=1e-6, maxit=300)
+        torch.cuda.synchronize()
+        tot.append((time.perf_counter() - t0) * 1e3)
+    rec2["sequential_ms"] = tot[-1]
+    for nw in (4, 8):
+        times = []
+        for rep in range(3):
+            us = [torch.zeros_like(f) for f in ft]
+            res, ms = simpgmg.pcg_solve_batch_concurrent(b, item_sys, ft, us, rtol=1e-6, maxit=300,
+                                                         workers=nw)
+            times.append(ms)
+        rec2[f"concurrent{nw}_ms"] = float(np.median(times))
+        rec2[f"concurrent{nw}_all_converged"] = all(r["status"] == "converged" for r in res)
+    print(json.dumps(rec2), flush=True)
 
 
 def train_warm_start(n_train=2000, train_seconds=120.0, batch_size=8, lr=1e-3, seed=2024,

@@ -181,6 +181,49 @@ def test_staged_batch_matches_persistent_batch_and_oracle():
             assert np.linalg.norm(x - xp) <= 1e-5 * np.linalg.norm(xp), i
 
 
+def test_staged_batch_mfma_level0_matches_single_solves_and_oracle():
+    """With every system's fine level in BF16X3, the staged solve runs level 0
+    on the batched MFMA operator (launch shape tuned on the item set, odd and
+    ragged meshes (ragged against the 15-element tiles) with 1-3 load cases).  Each item against the single solve of
+    its hierarchy, which runs the same BF16X3 operator one mesh at a time:
+    same status, iterations within one (per-item reductions in another
+    order), solutions within the solver tolerance; and against the oracle:
+    true residual below rtol and equal to the one reported.  A second solve
+    replays the graphs."""
+    from paper_2604_26441_amd import simpgmg
+    dims = [(16, 8, 8), (20, 10, 10), (12, 6, 6), (30, 14, 14), (22, 12, 10)]
+    rhos = [workloads.grf_rho(d, seed=300 + i) for i, d in enumerate(dims)]
+    opts = [simpgmg.default_options(*d, n_levels=0, dense_max=1000, fine_prec="bf16x3") for d in dims]
+    b = simpgmg.setup_batch(opts, [t64(r) for r in rhos])
+    rng = np.random.default_rng(13)
+    item_sys, fs = [], []
+    for s, d in enumerate(dims):
+        for k in range(1 + s % 3):
+            item_sys.append(s)
+            fs.append(workloads.random_face_load(d, rng) if k else workloads.edge_load(d))
+    singles = []
+    for s, f in zip(item_sys, fs):
+        u = t64(np.zeros_like(f))
+        r = simpgmg.pcg_solve(b.hierarchy(s), t64(f), u, rtol=1e-6, maxit=300)
+        singles.append((r, np64(u)))
+    for rep in range(2):
+        us = [t64(np.zeros_like(f)) for f in fs]
+        rs, ms = simpgmg.pcg_solve_batch(b, item_sys, [t64(f) for f in fs], us, rtol=1e-6,
+                                         maxit=300, staged=True)
+        assert ms > 0
+        for i, (s, f) in enumerate(zip(item_sys, fs)):
+            d = dims[s]
+            r1, x1 = singles[i]
+            assert rs[i]["status"] == "converged" == r1["status"], (i, rs[i], r1)
+            assert abs(rs[i]["iters"] - r1["iters"]) <= 1, (i, rs[i], r1)
+            fixed = workloads.cantilever_fixed(d).astype(bool)
+            x = np64(us[i])
+            Kx = mesh.apply_K_elementwise(d, mesh.simp_modulus(rhos[s], 3), x, fixed=fixed)
+            rel = np.linalg.norm(f - Kx) / np.linalg.norm(f)
+            assert rel < 1e-6 and abs(rel - rs[i]["rel_res_true"]) < 1e-9, (i, rel, rs[i])
+            assert np.linalg.norm(x - x1) <= 1e-5 * np.linalg.norm(x1), i
+
+
 def test_staged_batch_edge_cases():
     """Zero right-hand side (u = 0 at once), a start at the solution
     (converged at iteration 0), maxit 0, and argument checks."""
