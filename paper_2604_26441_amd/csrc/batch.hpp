@@ -25,6 +25,7 @@ struct BSys {               // one system (its hierarchy's operators)
   const uint16_t* atab;     // its A-operand table
   const float* ke32;
   const double* E64;
+  const double* atab64;     // A-operand table of the FP64 MFMA operator
   const double* ke64;
   int nL;
   const int* free_idx;

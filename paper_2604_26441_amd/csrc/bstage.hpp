@@ -47,8 +47,6 @@ void bs_update_p(const BsArgs& a, const BsTable& t, const int* flags, const doub
 void bs_smooth0(const BsArgs& a, const BsTable& t, const int* flags, int post, int k, int cin,
                 int last, hipStream_t s);
 void bs_resid0(const BsArgs& a, const BsTable& t, const int* flags, int cin, hipStream_t s);
-void bs_smoothL(const BsArgs& a, const BsTable& t, const int* flags, int l, int cin, hipStream_t s);
-void bs_residL(const BsArgs& a, const BsTable& t, const int* flags, int l, int cin, hipStream_t s);
 void bs_restrict(const BsArgs& a, const BsTable& t, const int* flags, int l, hipStream_t s);
 void bs_coarse(const BsArgs& a, const BsTable& tg, const BsTable& tm, const int* flags,
                hipStream_t s);
@@ -59,7 +57,17 @@ void bs_prolong(const BsArgs& a, const BsTable& t, const int* flags, int l, int 
 // (mode EPI_SMOOTH with post / k / last as bs_smooth0, or EPI_RESID) over a
 // table of (item, block) entries with geo[item] = that item's grid.
 int4 bs_mfma_geometry(const Grid& g, int rows, int zchunk);
+// Galerkin level l on the row-split stencil form: blocks of a level grid, and
+// the stage launch (mode EPI_SMOOTH: damped-Jacobi step, or EPI_RESID) over a
+// table of (item, block) entries.
+int bs_stencil_blocks(const Grid& g);
+void bs_stencil(const BsArgs& a, const BsTable& t, const int* flags, int l, int mode, int cin,
+                hipStream_t s);
 void bs_fine_mfma(const BsArgs& a, const BsTable& t, const int4* geo, const int* flags, int rows,
                   int zchunk, int mode, int post, int k, int cin, int last, hipStream_t s);
+// The outer FP64 q = K p on the FP64 MFMA operator with the p.q block
+// partials in part (one per table entry).
+void bs_fine_mfma64_store_dot(const BsArgs& a, const BsTable& t, const int4* geo, const int* flags,
+                              int rows, int zchunk, double* part, hipStream_t s);
 
 }  // namespace sgmg

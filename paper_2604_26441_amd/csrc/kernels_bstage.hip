@@ -252,38 +252,6 @@ __global__ __launch_bounds__(kB) void k_bs_apply0(const BSys* __restrict__ sys,
   epilogue3(ep, node, V.fixn[node], xo, y);
 }
 
-// Galerkin level l >= 1: damped-Jacobi step or residual.
-template <int MODE>
-__global__ __launch_bounds__(kB) void k_bs_applyL(const BSys* __restrict__ sys,
-                                                  const BItem* __restrict__ items,
-                                                  const int2* __restrict__ tab,
-                                                  const int* __restrict__ flags, int l, int cin) {
-  Slot sl;
-  if (!active_block(tab, flags, sl)) return;
-  const BItem& I = items[sl.item];
-  const BSys& S = sys[I.sys];
-  const BLevel& V = S.lev[l];
-  const int node = sl.lb * kB + threadIdx.x;
-  if (node >= V.g.Nn) return;
-  Epi<double> ep{};
-  ep.mode = MODE;
-  ep.b = I.lb[l];
-  if (MODE == EPI_RESID) {
-    ep.out = I.lr[l];
-  } else {
-    ep.out = I.lx[l][1 - cin];
-    ep.dinv = V.dinv64;
-    ep.c2 = V.omega;
-  }
-  const double* x = I.lx[l][cin];
-  double acc[3];
-  stencil_node_Ku<double>(V.g, V.S64, x, node, acc);
-  const size_t b = 3 * (size_t)node;
-  const double xo[3] = {x[b], x[b + 1], x[b + 2]};
-  const double y[3] = {acc[0], acc[1], acc[2]};
-  epilogue3(ep, node, V.fixn[node], xo, y);
-}
-
 // Restriction of level l's residual to level l + 1 over the coarse nodes,
 // with the first Jacobi step of level l + 1 from zero unless it is the item's
 // coarsest level.
@@ -416,12 +384,6 @@ void bs_smooth0(const BsArgs& a, const BsTable& t, const int* flags, int post, i
 }
 void bs_resid0(const BsArgs& a, const BsTable& t, const int* flags, int cin, hipStream_t s) {
   if (t.n) k_bs_apply0<EPI_RESID><<<t.n, kB, 0, s>>>(a.sys, a.items, t.blk, flags, 0, 0, cin, 0);
-}
-void bs_smoothL(const BsArgs& a, const BsTable& t, const int* flags, int l, int cin, hipStream_t s) {
-  if (t.n) k_bs_applyL<EPI_SMOOTH><<<t.n, kB, 0, s>>>(a.sys, a.items, t.blk, flags, l, cin);
-}
-void bs_residL(const BsArgs& a, const BsTable& t, const int* flags, int l, int cin, hipStream_t s) {
-  if (t.n) k_bs_applyL<EPI_RESID><<<t.n, kB, 0, s>>>(a.sys, a.items, t.blk, flags, l, cin);
 }
 void bs_restrict(const BsArgs& a, const BsTable& t, const int* flags, int l, hipStream_t s) {
   if (t.n) k_bs_restrict<<<t.n, kB, 0, s>>>(a.sys, a.items, t.blk, flags, l);

@@ -496,10 +496,12 @@ __device__ inline double bload1d(__amdgpu_buffer_rsrc_t r, int off) {
 }
 
 template <int YC, int MODE>
-__global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma64(
-    Grid g, const double* __restrict__ E, const double* __restrict__ atab,
-    const double* __restrict__ u, const uint8_t* __restrict__ fixn, Epi<double> ep, int zchunk,
-    int ntx, int nty, int ntiles) {
+__device__ __forceinline__ void fine_mfma64_body(Grid g, const double* __restrict__ E,
+                                                 const double* __restrict__ atab,
+                                                 const double* __restrict__ u,
+                                                 const uint8_t* __restrict__ fixn,
+                                                 Epi<double> ep, int zchunk, int ntx, int nty,
+                                                 int ntiles, int blk) {
   typedef double f64x4 __attribute__((ext_vector_type(4)));
   using LD = FineLds64<YC>;
   static_assert(YC == 4 || YC == 8, "tile rows");
@@ -508,7 +510,7 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma64(
   // wave index made wave-uniform, so all tile arithmetic stays scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   unsigned char* const lds = lds_all + wave * LD::kWave;
-  const int tile = xcd_block(blockIdx.x, gridDim.x) * kMfmaWavesPerBlock + wave;
+  const int tile = blk * kMfmaWavesPerBlock + wave;
   const int tx = tile % ntx, tt = tile / ntx, ty = tt % nty, tz = tt / nty;
   const int grp = lane >> 4, n = lane & 15;
   const int xs = tx * 15, ys = ty * (YC - 1), zs = tz * zchunk;
@@ -729,6 +731,38 @@ __global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma64(
   }
 }
 
+template <int YC, int MODE>
+__global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_apply_fine_mfma64(
+    Grid g, const double* __restrict__ E, const double* __restrict__ atab,
+    const double* __restrict__ u, const uint8_t* __restrict__ fixn, Epi<double> ep, int zchunk,
+    int ntx, int nty, int ntiles) {
+  fine_mfma64_body<YC, MODE>(g, E, atab, u, fixn, ep, zchunk, ntx, nty, ntiles,
+                             xcd_block(blockIdx.x, gridDim.x));
+}
+
+// Stage-batched FP64 q = K p of every active item with the block partials of
+// p.q (part[b] for table entry b = (item, block of the item's tile grid),
+// geo[item] the grid for the launch shape).
+template <int YC>
+__global__ __launch_bounds__(64 * kMfmaWavesPerBlock) void k_bs_fine_mfma64(
+    const BSys* __restrict__ sys, const BItem* __restrict__ items, const int2* __restrict__ tab,
+    const int4* __restrict__ geo, const int* __restrict__ flags, double* __restrict__ part,
+    int zchunk) {
+  const int2 e = tab[blockIdx.x];
+  if (!flags[e.x]) return;                     // uniform over the block
+  const BItem& I = items[e.x];
+  const BSys& S = sys[I.sys];
+  const BLevel& V = S.lev[0];
+  const int4 gm = geo[e.x];
+  Epi<double> ep{};
+  ep.mode = EPI_STORE;
+  ep.out = I.q;
+  ep.want_dot = 1;
+  ep.ws.partials = part;
+  fine_mfma64_body<YC, kStoreDot>(V.g, S.E64, S.atab64, I.p, V.fixn, ep, zchunk, gm.x, gm.y, gm.z,
+                                  e.y);
+}
+
 namespace {
 struct MfmaLaunch { int ntx, nty, ntz, ntiles, blocks; };
 MfmaLaunch mfma_launch(const Grid& g, int rows, int zchunk) {
@@ -909,6 +943,16 @@ void bs_fine_mfma(const BsArgs& a, const BsTable& t, const int4* geo, const int*
     else SGMG_BSF(8, EPI_SMOOTH);
   }
 #undef SGMG_BSF
+}
+
+void bs_fine_mfma64_store_dot(const BsArgs& a, const BsTable& t, const int4* geo, const int* flags,
+                              int rows, int zchunk, double* part, hipStream_t s) {
+  if (t.n == 0) return;
+  const dim3 grid(t.n), block(64 * kMfmaWavesPerBlock);
+  if (rows == 4)
+    k_bs_fine_mfma64<4><<<grid, block, 0, s>>>(a.sys, a.items, t.blk, geo, flags, part, zchunk);
+  else
+    k_bs_fine_mfma64<8><<<grid, block, 0, s>>>(a.sys, a.items, t.blk, geo, flags, part, zchunk);
 }
 
 }  // namespace sgmg

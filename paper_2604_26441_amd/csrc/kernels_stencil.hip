@@ -1,5 +1,7 @@
 // Galerkin levels (l >= 1): assembly into a structured 27-point block
 // stencil, its application, and the trilinear transfer kernels.
+#include "batch.hpp"
+#include "bstage.hpp"
 #include "kernels.hpp"
 #include "node_ops.hpp"
 
@@ -256,17 +258,18 @@ void launch_stencil_to_f32(const double* S, float* S32, size_t n, hipStream_t s)
 // unconditionally (offsets outside the grid read the node itself, a valid
 // address, and add zero) and the nine row partials are added in LDS in a
 // fixed order.
+// The body takes the block's index lb (component lb % 3 of node tile
+// lb / 3), so one mesh (lb from the launch grid) and the stage-batched
+// solver (lb from its table of (item, block) entries) share it.
 constexpr int kRowSplitThreads = 9 * 64;
 
 template <typename T>
-__global__ __launch_bounds__(kRowSplitThreads) void k_stencil_apply_c(Grid g,
-                                                                      const T* __restrict__ S,
-                                                                      const T* __restrict__ u,
-                                                                      const uint8_t* __restrict__ fixn,
-                                                                      Epi<T> ep) {
+__device__ __forceinline__ void stencil_c_body(Grid g, const T* __restrict__ S,
+                                               const T* __restrict__ u,
+                                               const uint8_t* __restrict__ fixn, Epi<T> ep,
+                                               int lb) {
   __shared__ double part[9][64];
   const int lane = threadIdx.x & 63, pr = threadIdx.x >> 6;
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int d = lb % 3;
   const int node0 = (lb / 3) * 64 + lane;
   const bool in = node0 < g.Nn;
@@ -320,6 +323,54 @@ __global__ __launch_bounds__(kRowSplitThreads) void k_stencil_apply_c(Grid g,
     const double v[1] = {dot};
     grid_sum<1>(v, ep.ws);
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRowSplitThreads) void k_stencil_apply_c(Grid g,
+                                                                      const T* __restrict__ S,
+                                                                      const T* __restrict__ u,
+                                                                      const uint8_t* __restrict__ fixn,
+                                                                      Epi<T> ep) {
+  stencil_c_body<T>(g, S, u, fixn, ep, xcd_block(blockIdx.x, gridDim.x));
+}
+
+// Stage-batched form on Galerkin level l: the damped-Jacobi step (MODE
+// EPI_SMOOTH) or the residual (EPI_RESID) of every active item, block b being
+// entry tab[b] = (item, block of the item's level-l grid); the vectors and
+// the damping are the item's (damped Jacobi with the level's omega).
+template <int MODE>
+__global__ __launch_bounds__(kRowSplitThreads) void k_bs_stencil(const BSys* __restrict__ sys,
+                                                                 const BItem* __restrict__ items,
+                                                                 const int2* __restrict__ tab,
+                                                                 const int* __restrict__ flags,
+                                                                 int l, int cin) {
+  const int2 e = tab[blockIdx.x];
+  if (!flags[e.x]) return;                     // uniform over the block
+  const BItem& I = items[e.x];
+  const BSys& Sy = sys[I.sys];
+  const BLevel& V = Sy.lev[l];
+  Epi<double> ep{};
+  ep.mode = MODE;
+  ep.b = I.lb[l];
+  if (MODE == EPI_RESID) {
+    ep.out = I.lr[l];
+  } else {
+    ep.out = I.lx[l][1 - cin];
+    ep.dinv = V.dinv64;
+    ep.c2 = V.omega;
+  }
+  stencil_c_body<double>(V.g, V.S64, I.lx[l][cin], V.fixn, ep, e.y);
+}
+
+int bs_stencil_blocks(const Grid& g) { return 3 * (int)div_up(g.Nn, 64); }
+
+void bs_stencil(const BsArgs& a, const BsTable& t, const int* flags, int l, int mode, int cin,
+                hipStream_t s) {
+  if (t.n == 0) return;
+  if (mode == EPI_RESID)
+    k_bs_stencil<EPI_RESID><<<t.n, kRowSplitThreads, 0, s>>>(a.sys, a.items, t.blk, flags, l, cin);
+  else
+    k_bs_stencil<EPI_SMOOTH><<<t.n, kRowSplitThreads, 0, s>>>(a.sys, a.items, t.blk, flags, l, cin);
 }
 
 // LDS-staged form, for large levels (from kStencilSplitNodes nodes on): one

@@ -1861,6 +1861,7 @@ struct sgmg_batch {
     bool ready = false;
     void* dmem = nullptr;
     BsTable tv, ts[8], tr[8], tcg, tcm;
+    BsTable tsc[8];                // levels >= 1: row-split stencil blocks
     double* part = nullptr;
     double* scal = nullptr;
     int* flags = nullptr;          // [0, n): prologue, [n, 2n): iteration
@@ -1875,6 +1876,13 @@ struct sgmg_batch {
     BsTable tm0;
     const int4* geo = nullptr;
     void* mdmem = nullptr;
+    // the outer FP64 K p on the FP64 MFMA operator: launch shape, table
+    // (with per-item start / count for the p.q finalize) and tile grids
+    bool mfma64 = false;
+    int k64rows = 0, k64z = 0;
+    BsTable tk64;
+    const int4* geo64 = nullptr;
+    void* m64dmem = nullptr;
   } st;
 };
 
@@ -1891,6 +1899,7 @@ void batch_free_staged(sgmg_batch* b) {
   if (st.g_it) hipGraphExecDestroy(st.g_it);
   if (st.dmem) hipFree(st.dmem);
   if (st.mdmem) hipFree(st.mdmem);
+  if (st.m64dmem) hipFree(st.m64dmem);
   if (st.h_flags) hipHostFree(st.h_flags);
   if (st.h_scal) hipHostFree(st.h_scal);
   st = sgmg_batch::Staged{};
@@ -1937,6 +1946,7 @@ BSys make_bsys(const sgmg_hierarchy* h) {
   S.atab = h->atab;
   S.ke32 = h->ke32;
   S.E64 = h->E64;
+  S.atab64 = h->atab64;
   S.ke64 = h->ke64;
   S.nL = h->nL;
   S.free_idx = h->free_idx;
@@ -2042,12 +2052,12 @@ void bs_vcycle(const sgmg_batch::Staged& st, const BsArgs& a, const int* flags, 
     const int steps = l == 0 ? st.steps0 : st.stepsL;
     for (int k = 1; k < steps; ++k) {
       if (l == 0) smooth0(0, k, cb(0), 0);
-      else bs_smoothL(a, st.ts[l], flags, l, cb(l), s);
+      else bs_stencil(a, st.tsc[l], flags, l, EPI_SMOOTH, cb(l), s);
       flip(l);
     }
     if (l == 0 && st.mfma0) bs_fine_mfma(a, st.tm0, st.geo, flags, st.mrows, st.mz, EPI_RESID, 0, 0, cb(0), 0, s);
     else if (l == 0) bs_resid0(a, st.ts[0], flags, cb(0), s);
-    else bs_residL(a, st.ts[l], flags, l, cb(l), s);
+    else bs_stencil(a, st.tsc[l], flags, l, EPI_RESID, cb(l), s);
     bs_restrict(a, st.tr[l], flags, l, s);
     cur &= ~(1u << (l + 1));
   }
@@ -2057,7 +2067,7 @@ void bs_vcycle(const sgmg_batch::Staged& st, const BsArgs& a, const int* flags, 
     bs_prolong(a, st.ts[l], flags, l, cb(l), cb(l + 1), s);
     for (int k = 0; k < steps; ++k) {
       if (l == 0) smooth0(1, k, cb(0), k == steps - 1);
-      else bs_smoothL(a, st.ts[l], flags, l, cb(l), s);
+      else bs_stencil(a, st.tsc[l], flags, l, EPI_SMOOTH, cb(l), s);
       flip(l);
     }
   }
@@ -2080,8 +2090,13 @@ void bs_prologue(const sgmg_batch* b, const BsArgs& a, int n, hipStream_t s) {
 void bs_iteration(const sgmg_batch* b, const BsArgs& a, int n, hipStream_t s) {
   const auto& st = b->st;
   const int* fl = st.flags + n;
-  bs_fine64_store_dot(a, st.ts[0], fl, st.part, s);
-  bs_finalize(st.ts[0], n, 1, st.part, fl, 1, st.scal, s);
+  if (st.mfma64) {
+    bs_fine_mfma64_store_dot(a, st.tk64, st.geo64, fl, st.k64rows, st.k64z, st.part, s);
+    bs_finalize(st.tk64, n, 1, st.part, fl, 1, st.scal, s);
+  } else {
+    bs_fine64_store_dot(a, st.ts[0], fl, st.part, s);
+    bs_finalize(st.ts[0], n, 1, st.part, fl, 1, st.scal, s);
+  }
   bs_update_xr(a, st.tv, fl, st.scal, st.part, s);
   bs_finalize(st.tv, n, 1, st.part, fl, 2, st.scal, s);
   bs_vcycle(st, a, fl, s);
@@ -2219,6 +2234,21 @@ int bs_prepare(sgmg_batch* b, int n, hipStream_t s) {
   }
   hts.push_back(make([&](const BSys& S) { return div_up(S.nL, TB); }));               // tcg
   hts.push_back(make([&](const BSys& S) { return div_up(S.nL, bs_coarse_rows()); }));  // tcm
+  for (int l = 1; l < st.Lmax - 1; ++l)                                                  // tsc
+    hts.push_back(make([&](const BSys& S) { return S.L - 1 > l ? bs_stencil_blocks(S.lev[l].g) : 0; }));
+  // the outer K p on the FP64 MFMA operator when every item's fine level
+  // fits it: one table per candidate launch shape (tuned below)
+  static const int k64_shapes[4][2] = {{4, 2}, {4, 4}, {4, 8}, {8, 4}};
+  bool mf64 = true;
+  for (int i = 0; i < n; ++i) {
+    const sgmg_hierarchy* h = b->hs[b->h_items[i].sys];
+    mf64 = mf64 && h->atab64 && mfma64_size_ok(h->lev[0].g);
+  }
+  if (mf64)
+    for (int c = 0; c < 4; ++c)
+      hts.push_back(make([&](const BSys& S) {
+        return bs_mfma_geometry(S.lev[0].g, k64_shapes[c][0], k64_shapes[c][1]).w;
+      }));
   auto a16 = [](size_t v) { return (v + 15) & ~(size_t)15; };
   size_t bytes = 0, maxblk = 0;
   for (const HT& t : hts) {
@@ -2266,6 +2296,10 @@ int bs_prepare(sgmg_batch* b, int n, hipStream_t s) {
   }
   st.tcg = dts[k++];
   st.tcm = dts[k++];
+  for (int l = 1; l < st.Lmax - 1; ++l) st.tsc[l] = dts[k++];
+  BsTable k64t[4];
+  if (mf64)
+    for (int c = 0; c < 4; ++c) k64t[c] = dts[k++];
   if (hipHostMalloc((void**)&st.h_flags, flag_b, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&st.h_scal, scal_b, hipHostMallocDefault) != hipSuccess) {
     set_error("staged batch host allocation failed");
@@ -2282,6 +2316,49 @@ int bs_prepare(sgmg_batch* b, int n, hipStream_t s) {
   }
   st.mfma0 = mf;
   if (mf) TRY(bs_tune_mfma(b, n, s));
+  if (mf64) {
+    // per-item tile grids of each candidate shape; time the K p stage of
+    // every item (three launches after one warm-up) and keep the fastest
+    std::vector<int4> g64((size_t)4 * n);
+    for (int c = 0; c < 4; ++c)
+      for (int i = 0; i < n; ++i)
+        g64[(size_t)c * n + i] = bs_mfma_geometry(b->hs[b->h_items[i].sys]->lev[0].g,
+                                                  k64_shapes[c][0], k64_shapes[c][1]);
+    if (hipMalloc(&st.m64dmem, g64.size() * sizeof(int4)) != hipSuccess) {
+      set_error("staged batch allocation failed");
+      return SGMG_ENOMEM;
+    }
+    int4* dg = (int4*)st.m64dmem;
+    SGMG_HIP(hipMemcpyAsync(dg, g64.data(), g64.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+    std::vector<int> ones(n, 1);
+    SGMG_HIP(hipMemcpyAsync(st.flags, ones.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+    hipEvent_t e0, e1;
+    SGMG_HIP(hipEventCreate(&e0));
+    SGMG_HIP(hipEventCreate(&e1));
+    const BsArgs a{b->d_sys, b->d_items};
+    float best = 0.f;
+    int bc = -1;
+    for (int c = 0; c < 4; ++c) {
+      const int4* gc = dg + (size_t)c * n;
+      bs_fine_mfma64_store_dot(a, k64t[c], gc, st.flags, k64_shapes[c][0], k64_shapes[c][1], st.part, s);
+      SGMG_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r)
+        bs_fine_mfma64_store_dot(a, k64t[c], gc, st.flags, k64_shapes[c][0], k64_shapes[c][1], st.part, s);
+      SGMG_HIP(hipEventRecord(e1, s));
+      SGMG_HIP(hipEventSynchronize(e1));
+      TRY(check_launch());
+      float ms = 0.f;
+      SGMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (bc < 0 || ms < best) { best = ms; bc = c; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    st.mfma64 = true;
+    st.tk64 = k64t[bc];
+    st.geo64 = dg + (size_t)bc * n;
+    st.k64rows = k64_shapes[bc][0];
+    st.k64z = k64_shapes[bc][1];
+  }
   TRY(bs_capture(b, bs_prologue, n, &st.g_pro));
   TRY(bs_capture(b, bs_iteration, n, &st.g_it));
   st.ready = true;

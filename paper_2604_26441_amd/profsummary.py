@@ -21,6 +21,11 @@ import sqlite3
 from collections import defaultdict
 
 
+def _short(name):
+    """Kernel name without namespaces and parameter list."""
+    return name.replace("sgmg::", "").replace("(anonymous namespace)::", "").split("(")[0]
+
+
 def _dispatches(path, counter):
     rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
     rows.sort(key=lambda r: int(r["Dispatch_Id"]))
@@ -97,7 +102,7 @@ def counters(path):
     acc = defaultdict(lambda: defaultdict(list))
     with open(path) as fh:
         for row in csv.DictReader(fh):
-            name = row.get("Kernel_Name", "").replace("sgmg::", "").split("(")[0]
+            name = _short(row.get("Kernel_Name", ""))
             acc[name][row["Counter_Name"]].append(float(row["Counter_Value"]))
     cols = sorted({c for k in acc.values() for c in k})
     print("| kernel | dispatches | " + " | ".join(f"mean {c}" for c in cols) + " |")
@@ -128,7 +133,7 @@ def last_solve(c):
     span = seg[-1][2] - seg[0][1]
     tot = defaultdict(lambda: [0, 0])
     for n, s, e in seg:
-        k = n.replace("sgmg::", "").split("(")[0]
+        k = _short(n)
         tot[k][0] += 1
         tot[k][1] += e - s
     print(f"\nLast solve: {len(seg)} kernels, {busy / 1e3:.0f} us of kernel time in "
@@ -168,7 +173,7 @@ def main():
     print("| kernel | calls | total (ms) | average (us) | share |")
     print("|---|---|---|---|---|")
     for name, calls, tot, avg, pct in rows[: a.top]:
-        short = name.replace("sgmg::", "").split("(")[0]
+        short = _short(name)
         print(f"| `{short}` | {calls} | {tot / 1e3:.3f} | {avg:.3f} | {pct:.1f}% |")
     if a.solve:
         last_solve(c)
