@@ -621,6 +621,7 @@ def warm_vs_cold(net, h, rho, f, rtol=1e-6, maxit=500, reps=3):
     for _ in range(2):                                     # warm-up (graph capture)
         u = torch.zeros_like(f)
         simpgmg.pcg_solve(h, f, u, rtol=rtol, maxit=maxit)
+    net.forward(simpgmg.unet_input(h, rho, f))             # warm-up (activation buffers)
     cold_ms, warm_ms, net_ms = [], [], []
     for _ in range(reps):
         u = torch.zeros_like(f)
@@ -679,6 +680,55 @@ def warmstart(n_train=2000, train_seconds=120.0, loss="energy"):
         rec["tests"].append(r)
         h.close()
         print(json.dumps(r), flush=True)
+    print(json.dumps(rec), flush=True)
+
+
+def batchprof(fine_prec="bf16x3", reps=3):
+    """Workload for a kernel trace of the stage-batched solve: the config-3
+    batch (32 systems, 84 load cases) with the given fine-level precision,
+    solved reps times after set-up (the first solve tunes the launch shapes
+    and captures the graphs).  Command line: batchprof [bf16x3|f32]."""
+    dev = "cuda:0"
+    if len(sys.argv) > 2 and sys.argv[1] == "batchprof":
+        fine_prec = sys.argv[2]
+    dims, rhos, item_sys, fs = workloads.batch_config()
+    opts = [simpgmg.default_options(*d, n_levels=0, dense_max=1000, fine_prec=fine_prec) for d in dims]
+    b = simpgmg.setup_batch(opts, [torch.tensor(r, dtype=torch.float64, device=dev) for r in rhos])
+    ft = [torch.tensor(f, dtype=torch.float64, device=dev) for f in fs]
+    for rep in range(reps + 1):
+        us = [torch.zeros_like(f) for f in ft]
+        res, ms = simpgmg.pcg_solve_batch(b, item_sys, ft, us, rtol=1e-6, maxit=300, staged=True)
+        print(json.dumps({"fine_prec": fine_prec, "rep": rep, "ms": round(ms, 3),
+                          "converged": sum(r["status"] == "converged" for r in res),
+                          "max_iters": max(r["iters"] for r in res)}), flush=True)
+
+
+def unetprof():
+    """Workload for a kernel trace of the warm-start network: 13 forward
+    passes at 1 x 5 x 104^3 (the 100^3 mesh's padded node grid), then 13
+    MSE training steps at 8 x 5 x 32^3, with the wall time of the last 10 of
+    each."""
+    dev = "cuda:0"
+    net = simpgmg.UNet(seed=0)
+    g = torch.Generator(device=dev).manual_seed(0)
+    rec = {}
+    x = torch.randn((1, 5, 104, 104, 104), dtype=torch.float32, device=dev, generator=g)
+    for k in range(13):
+        if k == 3:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        net.forward(x)
+    torch.cuda.synchronize()
+    rec["forward_104cube_ms"] = round((time.perf_counter() - t0) / 10 * 1e3, 3)
+    x = torch.randn((8, 5, 32, 32, 32), dtype=torch.float32, device=dev, generator=g)
+    t = torch.randn((8, 3, 32, 32, 32), dtype=torch.float32, device=dev, generator=g)
+    for k in range(13):
+        if k == 3:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        net.train_step(x, t, None, lr=1e-4)
+    torch.cuda.synchronize()
+    rec["train_step_8x32cube_ms"] = round((time.perf_counter() - t0) / 10 * 1e3, 3)
     print(json.dumps(rec), flush=True)
 
 
@@ -761,4 +811,5 @@ if __name__ == "__main__":
     {"sizes": sizes, "hetero": hetero, "large": large, "kernels": kernels, "batch": batch,
      "e1": e1, "spectral_proxy": spectral_proxy, "robustness": robustness,
      "ablations": ablations, "sensitivity": sensitivity, "simp_schedule": simp_schedule,
-     "warmstart": warmstart, "traffic": traffic, "kuprof": kuprof}[sys.argv[1]]()
+     "warmstart": warmstart, "traffic": traffic, "kuprof": kuprof, "batchprof": batchprof,
+     "unetprof": unetprof}[sys.argv[1]]()
