@@ -213,15 +213,20 @@ __device__ __forceinline__ void fine_mfma_body(Grid g, const float* __restrict__
                          (unsigned)(ys - 1 + k) < (unsigned)g.Ny,
                      12 * (xs - 1 + um + g.Nx * (ys - 1 + k)));
   }
-  float uv[NU][3];
-  auto load_u = [&](int P, bool need) {
+  // register buffers of raw node planes: in the store modes (HBM-bound on
+  // large meshes) a plane's loads are issued two planes before it is split
+  // into LDS, so each wave keeps two planes of loads in flight; the smoothing
+  // and residual modes (more live registers) keep one
+  constexpr int kAhead = (MODE == EPI_STORE || MODE == kStoreDot) ? 2 : 1;
+  float uvA[NU][3], uvB[NU][3];
+  auto load_u = [&](float (&uv)[NU][3], int P, bool need) {
     const int pp = part(need && (unsigned)P < (unsigned)g.Nz, 12 * g.Nx * g.Ny * P);
 #pragma unroll
     for (int i = 0; i < NU; ++i) bload3(ru, off2(u_lane[i], pp), uv[i]);
   };
   // exact NSPLIT-term BF16 split (round to nearest even; each residual is
   // exact in FP32) of the loaded node plane P into its ring slot
-  auto split_u = [&](int P) {
+  auto split_u = [&](const float (&uv)[NU][3], int P) {
     unsigned char* const slot = lds + ((P + 3) % 3) * LD::kPlane + uk * LD::kRow + um * 8;
 #pragma unroll
     for (int i = 0; i < NU; ++i) {
@@ -365,17 +370,20 @@ __device__ __forceinline__ void fine_mfma_body(Grid g, const float* __restrict__
 #pragma unroll
   for (int r = 0; r < YC; ++r) zc[r] = 0.f;
 
-  load_u(zs - 1, true);
-  split_u(zs - 1);
-  load_u(zs, true);
-  split_u(zs);
-  load_u(zs + 1, zs + 1 <= zend);
+  load_u(uvA, zs - 1, true);
+  split_u(uvA, zs - 1);
+  load_u(uvA, zs, true);
+  split_u(uvA, zs);
+  load_u(uvA, zs + 1, zs + 1 <= zend);
+  if (kAhead == 2) load_u(uvB, zs + 2, zs + 2 <= zend);
   load_e(zs - 1, true);
-  for (int ez = zs - 1; ez < zend; ++ez) {
-    split_u(ez + 2);                              // loaded during the previous plane
+  // plane ez: its node plane ez + 2 (loaded kAhead planes earlier, in uv)
+  // goes to LDS and uv takes the loads of plane ez + 2 + kAhead
+  auto plane = [&](int ez, float (&uv)[NU][3]) {
+    split_u(uv, ez + 2);
 #pragma unroll
     for (int i = 0; i < NE; ++i) esc[i] = ev[i];
-    load_u(ez + 3, ez + 3 <= zend);
+    load_u(uv, ez + 2 + kAhead, ez + 2 + kAhead <= zend);
     load_e(ez + 1, ez + 1 < zend);
     load_v(ez);
     const int base = ((ez + dz_in + 3) % 3) * LD::kPlane + dy_in * LD::kRow + n * 8;
@@ -407,6 +415,14 @@ __device__ __forceinline__ void fine_mfma_body(Grid g, const float* __restrict__
       }
     }
     finish_plane(ez);
+  };
+  if (kAhead == 2) {
+    for (int ez = zs - 1; ez < zend; ez += 2) {
+      plane(ez, uvA);
+      if (ez + 1 < zend) plane(ez + 1, uvB);
+    }
+  } else {
+    for (int ez = zs - 1; ez < zend; ++ez) plane(ez, uvA);
   }
   if (MODE == kStoreDot || MODE == kSmoothDot) {
     const double vd[1] = {dot};

@@ -109,6 +109,43 @@ def hetero(n=60, seeds=9, maxit=500):
             print(json.dumps(rec), flush=True)
 
 
+def hetero_oracle(maxit=500):
+    """The precision schedules on the heterogeneous 60^3 cases whose oracle
+    reference solves are stored in tests/golden/config2_oracle.json (the
+    oracle's FP64 PCG-GMG to rtol 1e-10, written by
+    tests/golden/make_config2_reference.py): per schedule and case, the
+    iterations beside the oracle's at rtol 1e-6, the compliance error
+    |f.u - c*| / c* and the energy-norm error ||u - u*||_K / ||u*||_K from
+    u.K u - 2 f.u + c* (K u* = f, c* = f.u*), with K u from the library's FP64
+    fine operator."""
+    import os
+    dev = "cuda:0"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    G = json.load(open(os.path.join(root, "tests", "golden", "config2_oracle.json")))
+    dims = tuple(G["dims"])
+    f = torch.tensor(workloads.edge_load(dims), dtype=torch.float64, device=dev)
+    schedules = {"fp64_gmg": {"fine_prec": "f64"}, "fp32_gmg_bf16x3": {"fine_prec": "bf16x3"},
+                 "bf16_gmg_flex": {"fine_prec": "bf16", "flexible_beta": 1}}
+    for case in G["cases"]:
+        p, seed, cstar = case["p"], case["seed"], case["compliance"]
+        rho = torch.tensor(workloads.grf_rho(dims, seed), dtype=torch.float64, device=dev)
+        rec = {"p": p, "seed": seed, "oracle_iters": case["iters_rtol_1e-6"]}
+        for name, kw in schedules.items():
+            h = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, penal=float(p),
+                                                                **_schedule(dict(kw))), rho)
+            u = torch.zeros_like(f)
+            r = simpgmg.pcg_solve(h, f, u, rtol=1e-6, maxit=maxit)
+            y = torch.empty_like(u)
+            simpgmg.apply_K(h, 0, "f64", u, y)
+            h.close()
+            c = float(torch.dot(f, u))
+            e2 = max(float(torch.dot(u, y)) - 2.0 * c + cstar, 0.0)
+            rec[name] = {"status": r["status"], "iters": r["iters"],
+                         "compliance_rel_err": abs(c - cstar) / abs(cstar),
+                         "energy_rel_err": (e2 / cstar) ** 0.5}
+        print(json.dumps(rec), flush=True)
+
+
 EPS_BF16 = 2.0 ** -8      # BF16 unit roundoff (8-bit significand, round to nearest)
 
 
@@ -808,7 +845,7 @@ def kuprof(reps=20):
 
 
 if __name__ == "__main__":
-    {"sizes": sizes, "hetero": hetero, "large": large, "kernels": kernels, "batch": batch,
+    {"sizes": sizes, "hetero": hetero, "hetero_oracle": hetero_oracle, "large": large, "kernels": kernels, "batch": batch,
      "e1": e1, "spectral_proxy": spectral_proxy, "robustness": robustness,
      "ablations": ablations, "sensitivity": sensitivity, "simp_schedule": simp_schedule,
      "warmstart": warmstart, "traffic": traffic, "kuprof": kuprof, "batchprof": batchprof,
