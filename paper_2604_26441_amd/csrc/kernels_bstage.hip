@@ -265,20 +265,43 @@ __global__ __launch_bounds__(kB) void k_bs_restrict(const BSys* __restrict__ sys
   const BSys& S = sys[I.sys];
   const BLevel& V = S.lev[l];
   const BLevel& W = S.lev[l + 1];
-  const int Ic = sl.lb * kB + threadIdx.x;
-  if (Ic >= W.g.Nn) return;
-  double acc[3];
-  if (l == 0) restrict_node<float>(V.g, W.g, I.r0, Ic, acc);
-  else restrict_node<double>(V.g, W.g, I.lr[l], Ic, acc);
-  const bool first = l + 1 < S.L - 1;
-  const unsigned fx = W.fixn[Ic];
+  // thread per coarse DOF: the 27 fine values are read unconditionally at
+  // clamped indices and weighted (zero weights outside the fine grid), in
+  // the order of the node-level definition (z, y, x)
+  const int q = sl.lb * kB + threadIdx.x;
+  if (q >= 3 * W.g.Nn) return;
+  const int Ic = q / 3, k = q - 3 * Ic;
+  const int Ix = Ic % W.g.Nx, t = Ic / W.g.Nx, Iy = t % W.g.Ny, Iz = t / W.g.Ny;
+  double wx[3], wy[3], wz[3];
+  int ix[3], iy[3], iz[3];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const size_t b = 3 * (size_t)Ic + q;
-    const double v = (fx >> q) & 1u ? 0.0 : acc[q];
-    I.lb[l + 1][b] = v;
-    if (first) I.lx[l + 1][0][b] = W.omega * W.dinv64[b] * v;
+  for (int j = 0; j < 3; ++j) {
+    const int fx = 2 * Ix - 1 + j, fy = 2 * Iy - 1 + j, fz = 2 * Iz - 1 + j;
+    wx[j] = fx >= 0 && fx < V.g.Nx ? w1d(fx, Ix, V.g.nx) : 0.0;
+    wy[j] = fy >= 0 && fy < V.g.Ny ? w1d(fy, Iy, V.g.ny) : 0.0;
+    wz[j] = fz >= 0 && fz < V.g.Nz ? w1d(fz, Iz, V.g.nz) : 0.0;
+    ix[j] = min(max(fx, 0), V.g.Nx - 1);
+    iy[j] = min(max(fy, 0), V.g.Ny - 1);
+    iz[j] = min(max(fz, 0), V.g.Nz - 1);
   }
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const size_t row = (size_t)V.g.Nx * (iy[b] + (size_t)V.g.Ny * iz[c]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const size_t f = 3 * (row + ix[a]) + k;
+        const double r = l == 0 ? (double)I.r0[f] : I.lr[l][f];
+        acc += wx[a] * (wy[b] * wz[c]) * r;
+      }
+    }
+  const bool first = l + 1 < S.L - 1;
+  const size_t dof = 3 * (size_t)Ic + k;
+  const double v = (W.fixn[Ic] >> k) & 1u ? 0.0 : acc;
+  I.lb[l + 1][dof] = v;
+  if (first) I.lx[l + 1][0][dof] = W.omega * W.dinv64[dof] * v;
 }
 
 // Coarsest level (each item's own): gather the free right-hand side.

@@ -2230,7 +2230,7 @@ int bs_prepare(sgmg_batch* b, int n, hipStream_t s) {
   hts.push_back(make([&](const BSys& S) { return div_up(S.lev[0].g.n, TB); }));        // tv
   for (int l = 0; l < st.Lmax - 1; ++l) {
     hts.push_back(make([&](const BSys& S) { return S.L - 1 > l ? div_up(S.lev[l].g.Nn, TB) : 0; }));
-    hts.push_back(make([&](const BSys& S) { return S.L - 1 > l ? div_up(S.lev[l + 1].g.Nn, TB) : 0; }));
+    hts.push_back(make([&](const BSys& S) { return S.L - 1 > l ? div_up(3 * S.lev[l + 1].g.Nn, TB) : 0; }));
   }
   hts.push_back(make([&](const BSys& S) { return div_up(S.nL, TB); }));               // tcg
   hts.push_back(make([&](const BSys& S) { return div_up(S.nL, bs_coarse_rows()); }));  // tcm
