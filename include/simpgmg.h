@@ -316,12 +316,16 @@ int sgmg_pcg_solve_batch(sgmg_batch* b, int nitems, const int* item_sys, const d
  * every iteration the host reads each item's scalars; an item whose
  * recursive residual passes rtol runs the prologue, which is its FP64
  * true-residual check and, if that fails, its restart (beta = 0).  Same
- * operators and acceptance as sgmg_pcg_solve with Fletcher-Reeves beta; the
- * level operators are those of sgmg_pcg_solve_batch (FP32 vector-ALU level
- * 0 inside the V-cycle, FP64 elsewhere), reductions per item in a fixed
- * order.  All systems must share the smoothing step counts.  Work vectors
- * and graphs are built on the first call for an item set.  *total_ms: wall
- * time of the whole solve on the stream.  Synchronises once per iteration. */
+ * algorithm and acceptance as sgmg_pcg_solve with Fletcher-Reeves beta.
+ * Level operators: level 0 inside the V-cycle on the BF16X3 MFMA operator
+ * when every item's system has fine_prec BF16X3 (else the FP32 vector-ALU
+ * node operator), the Galerkin levels on the FP64 stored stencils, the
+ * outer q = K p on the FP64 MFMA operator; the two MFMA launch shapes are
+ * timed on the item set at its first call and the fastest kept.  Reductions
+ * per item in a fixed order.  All systems must share the smoothing step
+ * counts.  Work vectors, tables and graphs are built on the first call for
+ * an item set.  *total_ms: wall time of the whole solve on the stream.
+ * Synchronises once per iteration. */
 int sgmg_pcg_solve_batch_staged(sgmg_batch* b, int nitems, const int* item_sys,
                                 const double* const* f, double* const* u, double rtol, int maxit,
                                 sgmg_solve_info* infos, double* total_ms, void* stream);
