@@ -170,6 +170,12 @@ def test_energy_score_gradients_match_oracle():
         off += db.size
         assert np.linalg.norm(gw - dw) <= 1e-3 * np.linalg.norm(dw)
         assert np.linalg.norm(gb - db) <= 1e-3 * max(np.linalg.norm(db), 1e-12)
+    # argument checks: a volume smaller than the node grid, a negative rate
+    with pytest.raises(simpgmg.SimpGmgError):
+        net.energy_step(h, X[:, :, :8].contiguous(), t64(np.stack(rhos)), t64(np.stack(fs)),
+                        t64(np.array(cs)))
+    with pytest.raises(simpgmg.SimpGmgError):
+        net.energy_step(h, X, t64(np.stack(rhos)), t64(np.stack(fs)), t64(np.array(cs)), lr=-1.0)
     # an Adam step on this score lowers it
     l0 = net.energy_step(h, X, t64(np.stack(rhos)), t64(np.stack(fs)), t64(np.array(cs)), lr=1e-3)
     for _ in range(30):
