@@ -320,8 +320,9 @@ int sgmg_pcg_solve_batch(sgmg_batch* b, int nitems, const int* item_sys, const d
  * Level operators: level 0 inside the V-cycle on the BF16X3 MFMA operator
  * when every item's system has fine_prec BF16X3 (else the FP32 vector-ALU
  * node operator), the Galerkin levels on the FP64 stored stencils, the
- * outer q = K p on the FP64 MFMA operator; the two MFMA launch shapes are
- * timed on the item set at its first call and the fastest kept.  Reductions
+ * outer q = K p on the FP64 MFMA operator; the two MFMA launch shapes and the
+ * stencil form of each Galerkin level are timed on the item set at its first
+ * call and the fastest kept.  Reductions
  * per item in a fixed order.  All systems must share the smoothing step
  * counts.  Work vectors, tables and graphs are built on the first call for
  * an item set.  *total_ms: wall time of the whole solve on the stream.

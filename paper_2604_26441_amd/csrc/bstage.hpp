@@ -63,6 +63,10 @@ int4 bs_mfma_geometry(const Grid& g, int rows, int zchunk);
 int bs_stencil_blocks(const Grid& g);
 void bs_stencil(const BsArgs& a, const BsTable& t, const int* flags, int l, int mode, int cin,
                 hipStream_t s);
+// The same stages on the LDS-staged stencil form (one block per 64 nodes).
+int bs_stencil_s_blocks(const Grid& g);
+void bs_stencil_s(const BsArgs& a, const BsTable& t, const int* flags, int l, int mode, int cin,
+                  hipStream_t s);
 void bs_fine_mfma(const BsArgs& a, const BsTable& t, const int4* geo, const int* flags, int rows,
                   int zchunk, int mode, int post, int k, int cin, int last, hipStream_t s);
 // The outer FP64 q = K p on the FP64 MFMA operator with the p.q block

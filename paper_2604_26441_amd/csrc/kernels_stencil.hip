@@ -386,13 +386,14 @@ void bs_stencil(const BsArgs& a, const BsTable& t, const int* flags, int l, int 
 // stride-3 neighbour reads that would otherwise triple the vector-memory
 // instructions go to LDS.
 template <typename T>
-__global__ __launch_bounds__(192) void k_stencil_apply_s(
-    Grid g, const T* __restrict__ S, const T* __restrict__ u, const uint8_t* __restrict__ fixn,
-    Epi<T> ep) {
+__device__ __forceinline__ void stencil_s_body(Grid g, const T* __restrict__ S,
+                                               const T* __restrict__ u,
+                                               const uint8_t* __restrict__ fixn, Epi<T> ep,
+                                               int lb) {
   constexpr int kRow = 66 * 3;
   __shared__ T us[9][kRow];
   const int lane = threadIdx.x & 63, d = threadIdx.x >> 6;
-  const long node0 = (long)xcd_block(blockIdx.x, gridDim.x) * 64;
+  const long node0 = (long)lb * 64;
   const bool in = node0 + lane < g.Nn;
   const int node = in ? (int)node0 + lane : g.Nn - 1;
   // the epilogue's operands are loaded first (one memory round trip less)
@@ -461,6 +462,51 @@ __global__ __launch_bounds__(192) void k_stencil_apply_s(
     const double v[1] = {dot};
     grid_sum<1>(v, ep.ws);
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(192) void k_stencil_apply_s(
+    Grid g, const T* __restrict__ S, const T* __restrict__ u, const uint8_t* __restrict__ fixn,
+    Epi<T> ep) {
+  stencil_s_body<T>(g, S, u, fixn, ep, xcd_block(blockIdx.x, gridDim.x));
+}
+
+// Stage-batched LDS-staged form (one block per 64-node tile of an item's
+// level l, three waves for the output components): the same stages as
+// k_bs_stencil.
+template <int MODE>
+__global__ __launch_bounds__(192) void k_bs_stencil_s(const BSys* __restrict__ sys,
+                                                      const BItem* __restrict__ items,
+                                                      const int2* __restrict__ tab,
+                                                      const int* __restrict__ flags, int l,
+                                                      int cin) {
+  const int2 e = tab[blockIdx.x];
+  if (!flags[e.x]) return;                     // uniform over the block
+  const BItem& I = items[e.x];
+  const BSys& Sy = sys[I.sys];
+  const BLevel& V = Sy.lev[l];
+  Epi<double> ep{};
+  ep.mode = MODE;
+  ep.b = I.lb[l];
+  if (MODE == EPI_RESID) {
+    ep.out = I.lr[l];
+  } else {
+    ep.out = I.lx[l][1 - cin];
+    ep.dinv = V.dinv64;
+    ep.c2 = V.omega;
+  }
+  stencil_s_body<double>(V.g, V.S64, I.lx[l][cin], V.fixn, ep, e.y);
+}
+
+int bs_stencil_s_blocks(const Grid& g) { return (int)div_up(g.Nn, 64); }
+
+void bs_stencil_s(const BsArgs& a, const BsTable& t, const int* flags, int l, int mode, int cin,
+                  hipStream_t s) {
+  if (t.n == 0) return;
+  if (mode == EPI_RESID)
+    k_bs_stencil_s<EPI_RESID><<<t.n, 192, 0, s>>>(a.sys, a.items, t.blk, flags, l, cin);
+  else
+    k_bs_stencil_s<EPI_SMOOTH><<<t.n, 192, 0, s>>>(a.sys, a.items, t.blk, flags, l, cin);
 }
 
 // levels with fewer nodes use the plane-split form

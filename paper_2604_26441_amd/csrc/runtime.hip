@@ -1862,6 +1862,8 @@ struct sgmg_batch {
     void* dmem = nullptr;
     BsTable tv, ts[8], tr[8], tcg, tcm;
     BsTable tsc[8];                // levels >= 1: row-split stencil blocks
+    BsTable tss[8];                // levels >= 1: LDS-staged stencil blocks
+    int lform[8] = {};             // per level: 1 = LDS-staged form (timed faster)
     double* part = nullptr;
     double* scal = nullptr;
     int* flags = nullptr;          // [0, n): prologue, [n, 2n): iteration
@@ -2041,6 +2043,11 @@ void bs_vcycle(const sgmg_batch::Staged& st, const BsArgs& a, const int* flags, 
   unsigned cur = 0u;
   auto cb = [&](int l) { return (int)((cur >> l) & 1u); };
   auto flip = [&](int l) { cur ^= 1u << l; };
+  // Galerkin level l: the stencil form timed faster on the item set
+  auto stencil = [&](int l, int mode, int cin) {
+    if (st.lform[l]) bs_stencil_s(a, st.tss[l], flags, l, mode, cin, s);
+    else bs_stencil(a, st.tsc[l], flags, l, mode, cin, s);
+  };
   // level-0 smoothing step and residual: MFMA or vector-ALU operator
   auto smooth0 = [&](int post, int k, int cin, int last) {
     if (st.mfma0)
@@ -2052,12 +2059,12 @@ void bs_vcycle(const sgmg_batch::Staged& st, const BsArgs& a, const int* flags, 
     const int steps = l == 0 ? st.steps0 : st.stepsL;
     for (int k = 1; k < steps; ++k) {
       if (l == 0) smooth0(0, k, cb(0), 0);
-      else bs_stencil(a, st.tsc[l], flags, l, EPI_SMOOTH, cb(l), s);
+      else stencil(l, EPI_SMOOTH, cb(l));
       flip(l);
     }
     if (l == 0 && st.mfma0) bs_fine_mfma(a, st.tm0, st.geo, flags, st.mrows, st.mz, EPI_RESID, 0, 0, cb(0), 0, s);
     else if (l == 0) bs_resid0(a, st.ts[0], flags, cb(0), s);
-    else bs_stencil(a, st.tsc[l], flags, l, EPI_RESID, cb(l), s);
+    else stencil(l, EPI_RESID, cb(l));
     bs_restrict(a, st.tr[l], flags, l, s);
     cur &= ~(1u << (l + 1));
   }
@@ -2067,7 +2074,7 @@ void bs_vcycle(const sgmg_batch::Staged& st, const BsArgs& a, const int* flags, 
     bs_prolong(a, st.ts[l], flags, l, cb(l), cb(l + 1), s);
     for (int k = 0; k < steps; ++k) {
       if (l == 0) smooth0(1, k, cb(0), k == steps - 1);
-      else bs_stencil(a, st.tsc[l], flags, l, EPI_SMOOTH, cb(l), s);
+      else stencil(l, EPI_SMOOTH, cb(l));
       flip(l);
     }
   }
@@ -2187,6 +2194,40 @@ int bs_tune_mfma(sgmg_batch* b, int n, hipStream_t s) {
   return 0;
 }
 
+// Per Galerkin level, the smoothing stage over all items is timed in the
+// row-split and the LDS-staged stencil forms (HIP events, three launches
+// after one warm-up, into the items' scratch vectors) and the faster kept.
+// st.flags[0, n) and the tables must be in place.
+int bs_tune_stencil(sgmg_batch* b, int n, hipStream_t s) {
+  auto& st = b->st;
+  std::vector<int> ones(n, 1);
+  SGMG_HIP(hipMemcpyAsync(st.flags, ones.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+  hipEvent_t e0, e1;
+  SGMG_HIP(hipEventCreate(&e0));
+  SGMG_HIP(hipEventCreate(&e1));
+  const BsArgs a{b->d_sys, b->d_items};
+  for (int l = 1; l < st.Lmax - 1; ++l) {
+    float ms[2] = {0.f, 0.f};
+    for (int form = 0; form < 2; ++form) {
+      auto launch = [&]() {
+        if (form) bs_stencil_s(a, st.tss[l], st.flags, l, EPI_SMOOTH, 0, s);
+        else bs_stencil(a, st.tsc[l], st.flags, l, EPI_SMOOTH, 0, s);
+      };
+      launch();
+      SGMG_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r) launch();
+      SGMG_HIP(hipEventRecord(e1, s));
+      SGMG_HIP(hipEventSynchronize(e1));
+      TRY(check_launch());
+      SGMG_HIP(hipEventElapsedTime(&ms[form], e0, e1));
+    }
+    st.lform[l] = ms[1] < ms[0] ? 1 : 0;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return 0;
+}
+
 // Stage tables, partials, scalars and flags of the cached item set, and the
 // two graphs.
 int bs_prepare(sgmg_batch* b, int n, hipStream_t s) {
@@ -2234,8 +2275,10 @@ int bs_prepare(sgmg_batch* b, int n, hipStream_t s) {
   }
   hts.push_back(make([&](const BSys& S) { return div_up(S.nL, TB); }));               // tcg
   hts.push_back(make([&](const BSys& S) { return div_up(S.nL, bs_coarse_rows()); }));  // tcm
-  for (int l = 1; l < st.Lmax - 1; ++l)                                                  // tsc
+  for (int l = 1; l < st.Lmax - 1; ++l) {                                                // tsc, tss
     hts.push_back(make([&](const BSys& S) { return S.L - 1 > l ? bs_stencil_blocks(S.lev[l].g) : 0; }));
+    hts.push_back(make([&](const BSys& S) { return S.L - 1 > l ? bs_stencil_s_blocks(S.lev[l].g) : 0; }));
+  }
   // the outer K p on the FP64 MFMA operator when every item's fine level
   // fits it: one table per candidate launch shape (tuned below)
   static const int k64_shapes[4][2] = {{4, 2}, {4, 4}, {4, 8}, {8, 4}};
@@ -2296,7 +2339,10 @@ int bs_prepare(sgmg_batch* b, int n, hipStream_t s) {
   }
   st.tcg = dts[k++];
   st.tcm = dts[k++];
-  for (int l = 1; l < st.Lmax - 1; ++l) st.tsc[l] = dts[k++];
+  for (int l = 1; l < st.Lmax - 1; ++l) {
+    st.tsc[l] = dts[k++];
+    st.tss[l] = dts[k++];
+  }
   BsTable k64t[4];
   if (mf64)
     for (int c = 0; c < 4; ++c) k64t[c] = dts[k++];
@@ -2316,6 +2362,7 @@ int bs_prepare(sgmg_batch* b, int n, hipStream_t s) {
   }
   st.mfma0 = mf;
   if (mf) TRY(bs_tune_mfma(b, n, s));
+  TRY(bs_tune_stencil(b, n, s));
   if (mf64) {
     // per-item tile grids of each candidate shape; time the K p stage of
     // every item (three launches after one warm-up) and keep the fastest

@@ -115,10 +115,10 @@ def test_concurrent_batch_equals_single_solves(workers):
 def test_batch_config3_every_item_meets_the_oracle():
     """The whole batch workload (32 systems 2m x m x m, m in 8..24, up to the
     48 x 24 x 24 system; random-field rho, p = 3; 1-4 random face loads each):
-    one persistent launch, the concurrent and the stage-batched solves, every
-    item converged with
-    the oracle's FP64 true residual of its u below rtol (matrix-free element
-    loop of the oracle)."""
+    one persistent launch, the concurrent and the stage-batched solves (FP32
+    fine levels), and the stage-batched solve with BF16X3 fine levels on the
+    matrix cores; every item converged with the oracle's FP64 true residual of
+    its u below rtol (matrix-free element loop of the oracle)."""
     from paper_2604_26441_amd import simpgmg
     dims, rhos, item_sys, fs = workloads.batch_config()
     assert max(d[0] for d in dims) == 48
@@ -132,11 +132,18 @@ def test_batch_config3_every_item_meets_the_oracle():
     ug = [t64(np.zeros_like(f)) for f in fs]
     resg, _ = simpgmg.pcg_solve_batch(b, item_sys, [t64(f) for f in fs], ug, rtol=1e-6, maxit=300,
                                       staged=True)
+    b.close()
+    # the staged solve again with BF16X3 fine levels (MFMA level 0, tuned shapes)
+    opts = [simpgmg.default_options(*d, n_levels=0, dense_max=1000, fine_prec="bf16x3") for d in dims]
+    b = simpgmg.setup_batch(opts, [t64(r) for r in rhos])
+    um = [t64(np.zeros_like(f)) for f in fs]
+    resm, _ = simpgmg.pcg_solve_batch(b, item_sys, [t64(f) for f in fs], um, rtol=1e-6, maxit=300,
+                                      staged=True)
     for i, (s, f) in enumerate(zip(item_sys, fs)):
         d = dims[s]
         fixed = workloads.cantilever_fixed(d).astype(bool)
         E = mesh.simp_modulus(rhos[s], 3)
-        for r, u in ((res[i], us[i]), (resc[i], uc[i]), (resg[i], ug[i])):
+        for r, u in ((res[i], us[i]), (resc[i], uc[i]), (resg[i], ug[i]), (resm[i], um[i])):
             assert r["status"] == "converged", (i, d, r)
             x = np64(u)
             rel = np.linalg.norm(f - mesh.apply_K_elementwise(d, E, x, fixed=fixed)) / np.linalg.norm(f)
