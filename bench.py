@@ -65,30 +65,49 @@ def measured_profile(prec, shape):
     return None
 
 
-def cpu_baseline(n, gpu_u, gpu_iters):
+def oracle_solve(dims, levels, maxit=200):
+    """The oracle's setup and PCG-GMG solve (rtol 1e-6) of the rho = 0.5
+    cantilever of the given shape, on the calling thread; returns the timings
+    (ms), the iterate, the outcome and the hierarchy."""
+    import workloads
+    from oracle import krylov, mesh, multigrid
+    t0 = time.perf_counter()
+    rho = workloads.uniform_rho(dims)
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    f = workloads.edge_load(dims)
+    E = mesh.simp_modulus(rho, 3)
+    oh = multigrid.build(dims, E, fixed, multigrid.Options(n_levels=levels))
+    t1 = time.perf_counter()
+    K = oh.levels[0].K
+    M = lambda r: multigrid.vcycle(oh, r)
+    xo, st, it, _ = krylov.pcg(lambda v: K @ v, f, M, rtol=1e-6, maxit=maxit)
+    t2 = time.perf_counter()
+    return (t1 - t0) * 1e3, (t2 - t1) * 1e3, xo, st, it, oh, f
+
+
+def cpu_baseline(n, gpu_u, gpu_iters, small):
     """The oracle (FP64 PCG-GMG on assembled SciPy CSR, 4 levels, the same
     Chebyshev / Jacobi smoothing and rtol 1e-6) solving the same n^3
     cantilever on one host thread: setup and the full solve timed
     separately.  Afterwards, untimed, the oracle's iterate is refined to rtol
     1e-10 and the GPU solution's errors against that reference are
-    reported."""
+    reported.  ``small`` lists the smaller meshes (shape, levels, GPU
+    record) on which the oracle's setup and solve are timed the same way and
+    set beside the GPU's."""
     import platform
     from threadpoolctl import threadpool_limits
-    import workloads
-    from oracle import krylov, mesh, multigrid
+    from oracle import krylov, multigrid
     dims = (n, n, n)
+    others = []
     with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        rho = workloads.uniform_rho(dims)
-        fixed = workloads.cantilever_fixed(dims).astype(bool)
-        f = workloads.edge_load(dims)
-        E = mesh.simp_modulus(rho, 3)
-        oh = multigrid.build(dims, E, fixed, multigrid.Options(n_levels=4))
-        t1 = time.perf_counter()
+        for sdims, lv, g in small:
+            su, so, _, st, it, _, _ = oracle_solve(sdims, lv)
+            others.append({"mesh": "x".join(map(str, sdims)), "levels": lv,
+                           "setup_ms": round(su, 1), "solve_ms": round(so, 1), "iters": it,
+                           "status": st, "gpu": g})
+        su, so, xo, st, it, oh, f = oracle_solve(dims, 4)
         K = oh.levels[0].K
         M = lambda r: multigrid.vcycle(oh, r)
-        xo, st, it, _ = krylov.pcg(lambda v: K @ v, f, M, rtol=1e-6, maxit=200)
-        t2 = time.perf_counter()
         xr, st_r, it_r, _ = krylov.pcg(lambda v: K @ v, f, M, x0=xo, rtol=1e-10, maxit=200)
     cpu = "unknown"
     try:
@@ -98,11 +117,11 @@ def cpu_baseline(n, gpu_u, gpu_iters):
                 break
     except OSError:
         pass
-    base = {"value": round((t2 - t1) * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+    base = {"value": round(so, 1), "unit": "ms", "cores": 1, "kind": "oracle",
             "sample": f"the whole oracle solve of the same {n}^3 cantilever to rtol 1e-6 "
                       f"({it} iterations, status {st}; GPU: {gpu_iters}), setup timed apart",
-            "setup_ms": round((t1 - t0) * 1e3, 1), "iters": it, "cpu": cpu,
-            "nproc": os.cpu_count(), "host": platform.node()}
+            "setup_ms": round(su, 1), "iters": it, "cpu": cpu,
+            "nproc": os.cpu_count(), "host": platform.node(), "other_sizes": others}
 
     def errs(u):
         d = u - xr
@@ -135,7 +154,9 @@ def ku_roofline(n, prec, reps, tune=True):
     uk = torch.ones(3 * (n + 1) ** 3, dtype=dt, device=dev).masked_fill_(fixed, 0)
     yk = torch.empty_like(uk)
     stream = torch.cuda.current_stream()
-    for _ in range(5):
+    # steady state: the first launches on freshly allocated buffers of this
+    # size run up to 20 % slower (clocks and address translation warming up)
+    for _ in range(100):
         simpgmg.apply_K(h, 0, p, uk, yk)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
@@ -151,6 +172,40 @@ def ku_roofline(n, prec, reps, tune=True):
     return {"mesh": f"{n}^3", "us": round(us, 3), "bytes": byts, "GBs": round(byts / us / 1e3, 1),
             "GFLOPs": round(2 * 24 * 24 * nel / us / 1e3, 1),
             "shape": shape[1 if prec == "bf16x3" else 0] if shape else None}
+
+
+def gpu_solve(dims, levels, fine_prec, reps=3):
+    """Setup and PCG-GMG solve (rtol 1e-6, cap 200) of the rho = 0.5
+    cantilever of the given shape on the GPU: one untimed warm-up, then the
+    mean over reps of the setup wall time and of the solve time the library
+    reports."""
+    import torch
+    import workloads
+    from paper_2604_26441_amd import simpgmg
+    dev = torch.device("cuda:0")
+    rho = torch.tensor(workloads.uniform_rho(dims), dtype=torch.float64, device=dev)
+    f = torch.tensor(workloads.edge_load(dims), dtype=torch.float64, device=dev)
+    o = simpgmg.default_options(*dims, n_levels=levels, fine_prec=fine_prec)
+    su, so = [], []
+    for k in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = simpgmg.setup_hierarchy(o, rho)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        u = torch.zeros_like(f)
+        res = simpgmg.pcg_solve(h, f, u, rtol=1e-6, maxit=200)
+        h.close()
+        if k:
+            su.append((t1 - t0) * 1e3)
+            so.append(res["solve_ms"])
+    return {"setup_ms": round(float(np.mean(su)), 3), "solve_ms": round(float(np.mean(so)), 3),
+            "iters": res["iters"], "status": res["status"], "fine_prec": fine_prec}
+
+
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -210,6 +265,7 @@ def main():
             h.close()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t_start) * 1e3
+    progress(f"{args.steps} timed solves done, {float(np.mean(solve_ms)):.3f} ms each")
 
     # the fine K.u in the smoother precision on the bench mesh: 200
     # back-to-back launches on torch's current stream (the stream the library
@@ -248,8 +304,9 @@ def main():
     ku_flop = 2 * 24 * 24 * nel
     achieved = ku_bytes / (ku_us * 1e-6) / 1e9
     h.close()
-    ku_big = ku_roofline(256, args.fine_prec, 50) if not args.no_ku256 else None
+    ku_big = ku_roofline(256, args.fine_prec, 200) if not args.no_ku256 else None
 
+    progress("K.u timings done")
     extra = {}
     if not args.no_compare:
         h, r64, su64, _ = step(opts(fine_prec="f64"))
@@ -262,6 +319,7 @@ def main():
                                        "status": rj["status"], "rel_res_true": rj["rel_res_true"]}}
 
     if args.warm_pairs > 0:
+        progress("warm-start training")
         # learned warm start on the same solve: network trained here on
         # solver-generated 32^3 random-field pairs, then zero start vs scaled
         # prediction, same tolerance
@@ -313,7 +371,12 @@ def main():
                                     "the caches, so HBM-bound; the bench mesh's figure is under ku"}
     if not args.no_cpu_baseline:
         u_host = last_u.cpu().numpy()
-        line["cpu_baseline"], line["error_vs_oracle"] = cpu_baseline(n, u_host, iters[-1])
+        progress("oracle timings (one host thread)")
+        small = []
+        for sdims, lv in (((16, 8, 8), 3), ((40, 40, 40), 4), ((60, 60, 60), 4)):
+            g = gpu_solve(sdims, lv, args.fine_prec)
+            small.append((sdims, lv, g))
+        line["cpu_baseline"], line["error_vs_oracle"] = cpu_baseline(n, u_host, iters[-1], small)
     print(json.dumps(line), flush=True)
 
 

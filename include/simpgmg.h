@@ -252,15 +252,19 @@ int sgmg_lanczos(sgmg_hierarchy* h, int precond, int m, const double* g, double 
  * variant) that later setups of the same mesh read.  shape_out (host, 6
  * ints, may be NULL) receives (rows, planes) for BF16, BF16X3, then FP64;
  * for FP64 the vector-ALU node kernel is a candidate too, reported as (0, 0)
- * (also the FP64 choice of an untuned mesh).
- * Allocates four temporary vectors and synchronises the stream.  The launch
- * shape changes only which wave computes a node, never the arithmetic:
- * results are bitwise identical. */
+ * (also the FP64 choice of an untuned mesh), and so are the vector-ALU
+ * sum-factorised tiles with 2 .. 32 planes, reported as (1, planes).
+ * Allocates four temporary vectors and synchronises the stream.  Within one
+ * kernel the launch shape changes only which wave computes a node, never the
+ * arithmetic: results are bitwise identical.  The three FP64 kernels agree
+ * to rounding (the sum-factorised product and the node kernel order the
+ * element sums differently from the matrix-core one). */
 int sgmg_autotune(sgmg_hierarchy* h, int* shape_out, void* stream);
 /* Pins the launch shape of one fine-operator variant (0 BF16, 1 BF16X3, 2
  * FP64) on h, e.g. to reuse a shape tuned earlier: rows 4 or 8, planes >= 1;
- * FP64 also accepts (0, 0), the vector-ALU node kernel.  Returns SGMG_EINVAL
- * for other values.  No device work. */
+ * FP64 also accepts (0, 0), the vector-ALU node kernel, and (1, planes >= 1),
+ * the vector-ALU kernel with the element product in sum-factorised form.
+ * Returns SGMG_EINVAL for other values.  No device work. */
 int sgmg_set_launch_shape(sgmg_hierarchy* h, int variant, int rows, int planes);
 
 /* Introspection for tests and reports. */

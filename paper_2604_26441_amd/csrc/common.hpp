@@ -257,6 +257,7 @@ struct KeTables {
   double kscale;       // s with K_e = kint / s exactly when integral != 0
   int kint[576];
   int integral;        // 1 if s*K_e is an integer matrix with |entries| <= 255
+  double lam, mu;      // Lame parameters of K_e (E = 1)
 };
 void compute_ke(double nu, KeTables* t);
 

@@ -33,6 +33,13 @@ void launch_apply_fine_mfma64(const Grid& g, int rows, int zchunk, const double*
                               const Epi<double>& ep, hipStream_t s);
 bool mfma64_size_ok(const Grid& g);
 void build_mfma_atab64(const KeTables& kt, double* out /* 2 * 6 * 64 */);
+// FP64 fine operator on the vector ALU, element product in sum-factorised
+// form (kernels_sf64.hip); zchunk = owned node planes per wave tile.
+void launch_apply_fine_sf64(const Grid& g, int zchunk, const double* E, double lam, double mu,
+                            const double* u, const uint8_t* fixn, const Epi<double>& ep,
+                            hipStream_t s);
+size_t apply_fine_sf64_blocks(const Grid& g, int zchunk);
+bool sf64_size_ok(const Grid& g);
 void launch_scale_E(const double* E, float* Es, int nel, double inv_s, hipStream_t s);
 void build_mfma_atab(const KeTables& kt, uint16_t* out /* 2 * 64 * 8 */);
 

@@ -38,6 +38,8 @@ void compute_ke(double nu, KeTables* t) {
   const double cl = 720.0 * nu / 216.0, cm = 360.0 * (1.0 - 2.0 * nu) / 216.0;
   t->kscale = s;
   t->integral = 1;
+  t->lam = lam;
+  t->mu = mu;
   for (int a = 0; a < 8; ++a)
     for (int b = 0; b < 8; ++b) {
       int lap = 0;

@@ -438,8 +438,14 @@ __device__ __forceinline__ void stencil_s_body(Grid g, const T* __restrict__ S,
   const int i = node % g.Nx, tt = node / g.Nx, j = tt % g.Ny, k = tt / g.Ny;
   const size_t Nn = g.Nn;
   T acc = (T)0;
+  // offsets in the order 13, 12, 14, 11, 15, ..., 0, 26: the entries of a
+  // lower offset 13 - p are the neighbour's entries of the upper offset
+  // 13 + p, the same array this block reads for its own nodes at the next
+  // step and the neighbouring blocks read at about the same time, so the
+  // second read of each line finds it in L2
 #pragma unroll
-  for (int o = 0; o < 27; ++o) {
+  for (int q = 0; q < 27; ++q) {
+    const int o = (q & 1) ? 13 - ((q + 1) >> 1) : 13 + (q >> 1);
     const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
     const bool ok = (unsigned)(i + ox) < (unsigned)g.Nx && (unsigned)(j + oy) < (unsigned)g.Ny &&
                     (unsigned)(k + oz) < (unsigned)g.Nz;

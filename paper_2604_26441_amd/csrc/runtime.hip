@@ -264,7 +264,9 @@ int apply_level<double>(const sgmg_hierarchy* h, int l, sgmg_prec prec, const do
     set_error("double vectors require SGMG_F64");
     return SGMG_EINVAL;
   }
-  if (l == 0 && h->mfma_rows[2] > 0 && mfma64_size_ok(L.g))
+  if (l == 0 && h->mfma_rows[2] == 1 && sf64_size_ok(L.g))
+    launch_apply_fine_sf64(L.g, h->mfma_zchunk[2], h->E64, h->kt.lam, h->kt.mu, x, L.fixn, ep, s);
+  else if (l == 0 && h->mfma_rows[2] > 1 && mfma64_size_ok(L.g))
     launch_apply_fine_mfma64(L.g, h->mfma_rows[2], h->mfma_zchunk[2], h->E64, h->atab64, x, L.fixn,
                              ep, s);
   else if (l == 0)
@@ -311,7 +313,9 @@ int apply_level<float>(const sgmg_hierarchy* h, int l, sgmg_prec prec, const flo
 // size: the MFMA tile grid or one block per 256 nodes).
 int k64_dot_partials(const sgmg_hierarchy* h) {
   const Level& L = h->lev[0];
-  if (h->mfma_rows[2] > 0 && mfma64_size_ok(L.g))
+  if (h->mfma_rows[2] == 1 && sf64_size_ok(L.g))
+    return (int)apply_fine_sf64_blocks(L.g, h->mfma_zchunk[2]);
+  if (h->mfma_rows[2] > 1 && mfma64_size_ok(L.g))
     return (int)apply_fine_mfma_blocks(L.g, h->mfma_rows[2] == 4 ? 4 : 8,
                                        h->mfma_zchunk[2] < 1 ? 1 : h->mfma_zchunk[2]);
   return div_up(L.g.Nn, 256);
@@ -799,7 +803,8 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
   // reductions, scalars, PCG vectors
   // one partial per block of the largest reduction grid (fused dots run one
   // block per 256 nodes; vector reductions use at most 2 x 1024 slots)
-  // (the MFMA kernel's largest grid is its smallest tile shape: 4 rows, 1 plane)
+  // (the MFMA kernel's largest grid is its smallest tile shape: 4 rows, 1 plane;
+  // the FP64 sum-factorised kernel's tiles have the same geometry)
   // (+ 4096: the PCG iteration keeps the r.r partials after the K p ones)
   // (a Galerkin level's apply with a dot: at most three blocks per 64 nodes)
   const size_t npart = std::max({kMinPartials, (size_t)div_up(g0.Nn, 256) + 2048,
@@ -1494,8 +1499,9 @@ int sgmg_set_launch_shape(sgmg_hierarchy* h, int variant, int rows, int planes) 
   if (!h) { set_error("NULL argument"); return SGMG_EINVAL; }
   if (variant < 0 || variant > 2) { set_error("variant must be 0 (BF16), 1 (BF16X3) or 2 (FP64)"); return SGMG_EINVAL; }
   const bool node64 = variant == 2 && rows == 0 && planes == 0;
-  if (!node64 && !mfma_shape_valid(rows, planes)) {
-    set_error("shape must have rows 4 or 8 and planes >= 1 (FP64 also (0, 0))");
+  const bool sf64 = variant == 2 && rows == 1 && planes >= 1;
+  if (!node64 && !sf64 && !mfma_shape_valid(rows, planes)) {
+    set_error("shape must have rows 4 or 8 and planes >= 1 (FP64 also (0, 0) and (1, planes >= 1))");
     return SGMG_EINVAL;
   }
   h->mfma_rows[variant] = rows;
@@ -1665,6 +1671,28 @@ int sgmg_autotune(sgmg_hierarchy* h, int* shape_out, void* stream) {
       }
       hipEventElapsedTime(&best_ms, e0, e1);
       best_r = best_z = 0;
+      // vector-ALU sum-factorised tiles (rows 1)
+      for (int z : z_c) {
+        if (z > L0.g.Nz && z != z_c[0]) continue;
+        for (int w = 0; w < 3; ++w)
+          launch_apply_fine_sf64(L0.g, z, h->E64, h->kt.lam, h->kt.mu, u64, L0.fixn,
+                                 epi_store<double>(y64), s);
+        hipEventRecord(e0, s);
+        for (int r = 0; r < 20; ++r)
+          launch_apply_fine_sf64(L0.g, z, h->E64, h->kt.lam, h->kt.mu, u64, L0.fixn,
+                                 epi_store<double>(y64), s);
+        hipEventRecord(e1, s);
+        if ((rc = check_launch())) break;
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          rc = SGMG_EHIP;
+          set_error("autotune sync failed");
+          break;
+        }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) { best_ms = ms; best_r = 1; best_z = z; }
+      }
+      if (rc) break;
     }
     for (int rows : rows_c) {
       for (int z : z_c) {

@@ -56,6 +56,17 @@ def traffic(fetch_csv, write_csv, reps, shapes):
             break
         fa, wb = sum(a) / reps, sum(b) / reps
         print(f"| {r} | {z} | {fa:.1f} | {wb:.1f} | {round(1024 * (fa * cf + wb * cw))} |")
+    # the level-1 stencil applies of the workload: its last reps dispatches
+    # (the earlier ones belong to the hierarchy setup)
+    st = lambda n, g: "k_stencil_apply_s<double>" in n
+    fs, ws = pick(f, st)[-reps:], pick(w, st)[-reps:]
+    if len(fs) == reps and len(ws) == reps:
+        fa, wb = sum(fs) / reps, sum(ws) / reps
+        print()
+        print("| kernel | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | calibrated bytes per launch |")
+        print("|---|---|---|---|")
+        print(f"| `k_stencil_apply_s<double>` level 1 | {fa:.1f} | {wb:.1f} | "
+              f"{round(1024 * (fa * cf + wb * cw))} |")
 
 
 def kuprof(fetch_csv, write_csv, sq_csv, reps, shapes, meshes=(80, 256)):

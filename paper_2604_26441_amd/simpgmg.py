@@ -294,8 +294,9 @@ def setup_hierarchy(opts, rho_or_E, fixed_dof=None, lambda_override=None, stream
 
 
 def autotune(h, stream=None):
-    """Tune the MFMA fine operators' launch shapes for this mesh; returns
-    ((rows, planes) for bf16, for bf16x3, for f64)."""
+    """Tune the fine operators' launch shapes for this mesh; returns
+    ((rows, planes) for bf16, for bf16x3, for f64); the f64 entry may also be
+    (0, 0) (node kernel) or (1, planes) (sum-factorised tiles)."""
     z = (ctypes.c_int * 6)()
     _check(_lib.sgmg_autotune(h.handle, z, _stream(stream)))
     return tuple((int(z[2 * q]), int(z[2 * q + 1])) for q in range(3))
@@ -306,7 +307,8 @@ VARIANTS = {"bf16": 0, "bf16x3": 1, "f64": 2}
 
 def set_launch_shape(h, variant, rows, planes):
     """Pin the fine operator's launch shape for variant 'bf16', 'bf16x3' or
-    'f64' ((0, 0) selects the FP64 vector-ALU node kernel)."""
+    'f64' ((0, 0) selects the FP64 vector-ALU node kernel, (1, planes) the
+    FP64 vector-ALU sum-factorised tile kernel)."""
     _check(_lib.sgmg_set_launch_shape(h.handle, VARIANTS[variant], rows, planes))
 
 

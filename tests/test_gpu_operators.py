@@ -130,9 +130,10 @@ def test_fine_apply_mfma_bf16x3_and_bf16(dims, seed):
     simpgmg.apply_K(h, 0, "bf16x2", t32(u), y2)
     e2 = rel_err(np64(y2), K @ u, scale)
     assert e2 < 2.0 ** -15 and np.all(np64(y2)[fixed] == 0)
-    # FP64 operator on the FP64 matrix cores, same tiles (two shapes)
+    # FP64 operator on the FP64 matrix cores, same tiles (two shapes), and
+    # the sum-factorised vector-ALU tiles (two chunk lengths)
     u64 = workloads.random_vector(fixed.size, seed + 30, fixed)
-    for shape in ((4, 2), (8, 5)):
+    for shape in ((4, 2), (8, 5), (1, 2), (1, 7)):
         simpgmg.set_launch_shape(h, "f64", *shape)
         y64 = t64(np.zeros_like(u64))
         simpgmg.apply_K(h, 0, "f64", t64(u64), y64)
@@ -154,6 +155,27 @@ def test_fine_apply_deterministic():
         assert np.array_equal(np64(a), np64(b)), prec
 
 
+def test_sf64_chunk_length_keeps_results_bitwise():
+    """FP64 sum-factorised tiles: the chunk length moves work between waves
+    only (every node sums its eight elements in one order), on a mesh with
+    ragged tiles in every axis; one chunk length also against the oracle's
+    assembled K."""
+    from paper_2604_26441_amd import simpgmg
+    dims = (31, 7, 20)
+    rho, fixed = _inputs(dims, 13)
+    h = _gpu_h(dims, 2, rho)
+    u = workloads.random_vector(fixed.size, 14, fixed)
+    out = []
+    for planes in (1, 3, 32):
+        simpgmg.set_launch_shape(h, "f64", 1, planes)
+        y = t64(np.zeros(fixed.size))
+        simpgmg.apply_K(h, 0, "f64", t64(u), y)
+        out.append(np64(y))
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+    K = mesh.assemble(dims, mesh.simp_modulus(rho, 3), fixed=fixed)
+    assert rel_err(out[0], K @ u, abs(K) @ np.abs(u)) < 1e-13
+
+
 def test_autotune_keeps_results_bitwise():
     """The tuned launch shape moves work between workgroups only."""
     from paper_2604_26441_amd import simpgmg
@@ -170,8 +192,8 @@ def test_autotune_keeps_results_bitwise():
         before[prec] = np64(y)
     z = simpgmg.autotune(h)
     assert all(r in (4, 8) and p in (2, 4, 8, 16, 32) for r, p in z[:2])
-    assert z[2] == (0, 0) or (z[2][0] in (4, 8) and z[2][1] in (2, 4, 8, 16, 32))
-    if z[2] == (0, 0):                      # the tuner chose the node kernel:
+    assert z[2] == (0, 0) or (z[2][0] in (1, 4, 8) and z[2][1] in (2, 4, 8, 16, 32))
+    if z[2][0] in (0, 1):                   # the tuner chose a vector-ALU kernel:
         simpgmg.set_launch_shape(h, "f64", 8, 16)   # compare another MFMA shape
     for prec in ("bf16", "bf16x3", "f64"):
         y = t64(np.zeros(fixed.size)) if prec == "f64" else t32(np.zeros(fixed.size))

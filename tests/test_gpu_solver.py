@@ -19,10 +19,13 @@ def _setup(dims, L, rho, fine_prec, fine_smoother=0, lambdas=None, level1_prec="
 @pytest.mark.parametrize("dims,L,smoother,shape", [((16, 8, 8), 3, 0, None), ((24, 12, 12), 4, 0, None),
                                                    ((16, 8, 8), 3, 1, None), ((9, 7, 5), 3, 0, None),
                                                    ((24, 12, 12), 4, 0, (4, 3)), ((16, 8, 8), 3, 1, (8, 4)),
-                                                   ((32, 16, 16), 3, 0, None)])
+                                                   ((32, 16, 16), 3, 0, None),
+                                                   ((24, 12, 12), 4, 0, (1, 3)), ((16, 8, 8), 3, 1, (1, 2)),
+                                                   ((9, 7, 5), 3, 0, (1, 1))])
 def test_vcycle_f64_matches_oracle(dims, L, smoother, shape):
-    """shape None: FP64 vector-ALU fine operator; (rows, planes): the FP64
-    MFMA fine operator (residual and smoothing epilogues).  (32, 16, 16) on 3
+    """shape None: FP64 vector-ALU node operator; (rows 4 or 8, planes): the
+    FP64 MFMA fine operator; (1, planes): the FP64 sum-factorised tile
+    operator (residual and smoothing epilogues).  (32, 16, 16) on 3
     levels has 600 free coarsest DOFs: ten 64-column Gauss-Jordan panels,
     five 128-row update tiles with a ragged last one."""
     from paper_2604_26441_amd import simpgmg
@@ -90,7 +93,7 @@ def test_vcycle_f32_close_to_oracle(prec):
     assert rel_err(np64(z), ref, ref) < 1e-5
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "bf16x2", "f64-mfma"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "bf16x2", "f64-mfma", "f64-sf"])
 def test_config0_pcg(prec):
     """16x8x8 cantilever, rho = 0.5, p = 3, 3 levels, rtol 1e-6, cap 200."""
     from paper_2604_26441_amd import simpgmg
@@ -102,11 +105,11 @@ def test_config0_pcg(prec):
     K = mesh.assemble(dims, E, fixed=fixed)
     oh = multigrid.build(dims, E, fixed, multigrid.Options(n_levels=3))
     xo, st, it_o, _ = krylov.pcg(lambda v: K @ v, f, lambda r: multigrid.vcycle(oh, r), rtol=1e-6, maxit=200)
-    mfma64 = prec == "f64-mfma"
-    prec = "f64" if mfma64 else prec
+    shape64 = {"f64-mfma": (4, 4), "f64-sf": (1, 4)}.get(prec)
+    prec = "f64" if shape64 else prec
     h = _setup(dims, 3, rho, prec)
-    if mfma64:                           # FP64 MFMA for the outer K.p and FP64 smoothing
-        simpgmg.set_launch_shape(h, "f64", 4, 4)
+    if shape64:                          # FP64 MFMA or sum-factorised tiles for the
+        simpgmg.set_launch_shape(h, "f64", *shape64)   # outer K.p and FP64 smoothing
     u = t64(np.zeros_like(f))
     res = simpgmg.pcg_solve(h, t64(f), u, rtol=1e-6, maxit=200, history_cap=256)
     assert res["status"] == "converged"

@@ -33,7 +33,8 @@ def _case(simpgmg, dims, f64_shape, seed):
 
 def test_noalloc_scale_equals_existing_entry_point():
     from paper_2604_26441_amd import simpgmg
-    for dims, shape, seed in [((24, 12, 12), (4, 3), 11), ((16, 8, 8), (0, 0), 12)]:
+    for dims, shape, seed in [((24, 12, 12), (4, 3), 11), ((16, 8, 8), (0, 0), 12),
+                              ((20, 10, 10), (1, 3), 14)]:
         h, rho, fixed, f, u0 = _case(simpgmg, dims, shape, seed)
         ua, ub = t64(u0), t64(u0)
         alpha_ref = simpgmg.warm_start_scale(h, t64(f), ua)
