@@ -26,6 +26,7 @@ struct BSys {               // one system (its hierarchy's operators)
   const float* ke32;
   const double* E64;
   const double* atab64;     // A-operand table of the FP64 MFMA operator
+  double lam, mu;           // Lame parameters of K_e (E = 1)
   const double* ke64;
   int nL;
   const int* free_idx;

@@ -69,9 +69,12 @@ void bs_stencil_s(const BsArgs& a, const BsTable& t, const int* flags, int l, in
                   hipStream_t s);
 void bs_fine_mfma(const BsArgs& a, const BsTable& t, const int4* geo, const int* flags, int rows,
                   int zchunk, int mode, int post, int k, int cin, int last, hipStream_t s);
-// The outer FP64 q = K p on the FP64 MFMA operator with the p.q block
-// partials in part (one per table entry).
+// The outer FP64 q = K p on the FP64 MFMA operator (rows 4 or 8) or the
+// vector-ALU sum/difference-basis operator (rows 1, tiles of rows 4), with
+// the p.q block partials in part (one per table entry).
 void bs_fine_mfma64_store_dot(const BsArgs& a, const BsTable& t, const int4* geo, const int* flags,
                               int rows, int zchunk, double* part, hipStream_t s);
+void bs_fine_sf64_store_dot(const BsArgs& a, const BsTable& t, const int4* geo, const int* flags,
+                            int zchunk, double* part, hipStream_t s);
 
 }  // namespace sgmg

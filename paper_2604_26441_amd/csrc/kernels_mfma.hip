@@ -892,6 +892,10 @@ void bs_fine_mfma(const BsArgs& a, const BsTable& t, const int4* geo, const int*
 void bs_fine_mfma64_store_dot(const BsArgs& a, const BsTable& t, const int4* geo, const int* flags,
                               int rows, int zchunk, double* part, hipStream_t s) {
   if (t.n == 0) return;
+  if (rows == 1) {
+    bs_fine_sf64_store_dot(a, t, geo, flags, zchunk, part, s);
+    return;
+  }
   const dim3 grid(t.n), block(64 * kMfmaWavesPerBlock);
   if (rows == 4)
     k_bs_fine_mfma64<4><<<grid, block, 0, s>>>(a.sys, a.items, t.blk, geo, flags, part, zchunk);

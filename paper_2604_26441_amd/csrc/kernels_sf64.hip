@@ -37,6 +37,8 @@
 // - 16 by ds_bpermute.  One halo element on the low side of x and y is
 // recomputed, so the tile owns 15 x 3 nodes per plane; every node sums its
 // eight element contributions in the same order whatever the chunk length.
+#include "batch.hpp"
+#include "bstage.hpp"
 #include "bufops.hpp"
 #include "kernels.hpp"
 
@@ -57,6 +59,11 @@ struct SfCoef {
   double e;    // mu / 48: (xy_w, xz_v, yz_u), sum and own
   double f;    // (lam + 4 mu) / 144: xyz
 };
+
+// the coefficients for E = 1 from the Lame parameters
+__host__ __device__ inline SfCoef sf_coef(double lam, double mu) {
+  return SfCoef{lam / 16.0, mu / 8.0, mu / 16.0, lam / 48.0, mu / 48.0, (lam + 4.0 * mu) / 144.0};
+}
 
 // (x, y) transform of one node face: v[dx][dy] -> F[cx][cy] (0 constant,
 // 1 linear)
@@ -355,6 +362,28 @@ __global__ __launch_bounds__(64 * kSfWaves) void k_apply_fine_sf64(
                        xcd_block(blockIdx.x, gridDim.x));
 }
 
+// Stage-batched outer q = K p with the p.q block partials: block b is entry
+// tab[b] = (item, block of the item's tile grid); geo[item] holds that grid
+// (ntx, nty, ntiles) for zchunk planes (the tiles of the MFMA operator with 4
+// rows).
+__global__ __launch_bounds__(64 * kSfWaves) void k_bs_fine_sf64(
+    const BSys* __restrict__ sys, const BItem* __restrict__ items, const int2* __restrict__ tab,
+    const int4* __restrict__ geo, const int* __restrict__ flags, double* __restrict__ part,
+    int zchunk) {
+  const int2 e = tab[blockIdx.x];
+  if (!flags[e.x]) return;                     // uniform over the block
+  const BItem& I = items[e.x];
+  const BSys& S = sys[I.sys];
+  const BLevel& V = S.lev[0];
+  const int4 gm = geo[e.x];
+  Epi<double> ep{};
+  ep.mode = EPI_STORE;
+  ep.out = I.q;
+  ep.want_dot = 1;
+  ep.ws.partials = part;
+  fine_sf64_body<kStoreDot>(V.g, S.E64, sf_coef(S.lam, S.mu), I.p, V.fixn, ep, zchunk, gm.x, gm.y, gm.z, e.y);
+}
+
 struct SfLaunch { int ntx, nty, ntiles, blocks; };
 SfLaunch sf_launch(const Grid& g, int zchunk) {
   SfLaunch m;
@@ -371,6 +400,12 @@ bool sf64_size_ok(const Grid& g) {
   return (size_t)g.n * sizeof(double) < ((size_t)1 << 30) - 64;
 }
 
+void bs_fine_sf64_store_dot(const BsArgs& a, const BsTable& t, const int4* geo, const int* flags,
+                            int zchunk, double* part, hipStream_t s) {
+  if (t.n == 0) return;
+  k_bs_fine_sf64<<<t.n, 64 * kSfWaves, 0, s>>>(a.sys, a.items, t.blk, geo, flags, part, zchunk);
+}
+
 size_t apply_fine_sf64_blocks(const Grid& g, int zchunk) {
   return (size_t)sf_launch(g, zchunk < 1 ? 1 : zchunk).blocks;
 }
@@ -380,7 +415,7 @@ void launch_apply_fine_sf64(const Grid& g, int zchunk, const double* E, double l
                             hipStream_t s) {
   if (zchunk < 1) zchunk = 1;
   const SfLaunch m = sf_launch(g, zchunk);
-  const SfCoef cf{lam / 16.0, mu / 8.0, mu / 16.0, lam / 48.0, mu / 48.0, (lam + 4.0 * mu) / 144.0};
+  const SfCoef cf = sf_coef(lam, mu);
   const dim3 grid(m.blocks), block(64 * kSfWaves);
   if (ep.mode == EPI_STORE && ep.want_dot)
     k_apply_fine_sf64<kStoreDot><<<grid, block, 0, s>>>(g, E, cf, u, fixn, ep, zchunk, m.ntx,

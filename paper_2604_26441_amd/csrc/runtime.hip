@@ -1977,6 +1977,8 @@ BSys make_bsys(const sgmg_hierarchy* h) {
   S.ke32 = h->ke32;
   S.E64 = h->E64;
   S.atab64 = h->atab64;
+  S.lam = h->kt.lam;
+  S.mu = h->kt.mu;
   S.ke64 = h->ke64;
   S.nL = h->nL;
   S.free_idx = h->free_idx;
@@ -2309,16 +2311,20 @@ int bs_prepare(sgmg_batch* b, int n, hipStream_t s) {
   }
   // the outer K p on the FP64 MFMA operator when every item's fine level
   // fits it: one table per candidate launch shape (tuned below)
-  static const int k64_shapes[4][2] = {{4, 2}, {4, 4}, {4, 8}, {8, 4}};
+  // (rows 1: the vector-ALU sum/difference-basis operator, whose tiles are
+  // those of rows 4)
+  static constexpr int kK64 = 7;
+  static const int k64_shapes[kK64][2] = {{4, 2}, {4, 4}, {4, 8}, {8, 4}, {1, 2}, {1, 4}, {1, 8}};
+  auto geo_rows = [](int r) { return r == 1 ? 4 : r; };
   bool mf64 = true;
   for (int i = 0; i < n; ++i) {
     const sgmg_hierarchy* h = b->hs[b->h_items[i].sys];
     mf64 = mf64 && h->atab64 && mfma64_size_ok(h->lev[0].g);
   }
   if (mf64)
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < kK64; ++c)
       hts.push_back(make([&](const BSys& S) {
-        return bs_mfma_geometry(S.lev[0].g, k64_shapes[c][0], k64_shapes[c][1]).w;
+        return bs_mfma_geometry(S.lev[0].g, geo_rows(k64_shapes[c][0]), k64_shapes[c][1]).w;
       }));
   auto a16 = [](size_t v) { return (v + 15) & ~(size_t)15; };
   size_t bytes = 0, maxblk = 0;
@@ -2371,9 +2377,9 @@ int bs_prepare(sgmg_batch* b, int n, hipStream_t s) {
     st.tsc[l] = dts[k++];
     st.tss[l] = dts[k++];
   }
-  BsTable k64t[4];
+  BsTable k64t[kK64];
   if (mf64)
-    for (int c = 0; c < 4; ++c) k64t[c] = dts[k++];
+    for (int c = 0; c < kK64; ++c) k64t[c] = dts[k++];
   if (hipHostMalloc((void**)&st.h_flags, flag_b, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&st.h_scal, scal_b, hipHostMallocDefault) != hipSuccess) {
     set_error("staged batch host allocation failed");
@@ -2394,11 +2400,11 @@ int bs_prepare(sgmg_batch* b, int n, hipStream_t s) {
   if (mf64) {
     // per-item tile grids of each candidate shape; time the K p stage of
     // every item (three launches after one warm-up) and keep the fastest
-    std::vector<int4> g64((size_t)4 * n);
-    for (int c = 0; c < 4; ++c)
+    std::vector<int4> g64((size_t)kK64 * n);
+    for (int c = 0; c < kK64; ++c)
       for (int i = 0; i < n; ++i)
         g64[(size_t)c * n + i] = bs_mfma_geometry(b->hs[b->h_items[i].sys]->lev[0].g,
-                                                  k64_shapes[c][0], k64_shapes[c][1]);
+                                                  geo_rows(k64_shapes[c][0]), k64_shapes[c][1]);
     if (hipMalloc(&st.m64dmem, g64.size() * sizeof(int4)) != hipSuccess) {
       set_error("staged batch allocation failed");
       return SGMG_ENOMEM;
@@ -2413,7 +2419,7 @@ int bs_prepare(sgmg_batch* b, int n, hipStream_t s) {
     const BsArgs a{b->d_sys, b->d_items};
     float best = 0.f;
     int bc = -1;
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < kK64; ++c) {
       const int4* gc = dg + (size_t)c * n;
       bs_fine_mfma64_store_dot(a, k64t[c], gc, st.flags, k64_shapes[c][0], k64_shapes[c][1], st.part, s);
       SGMG_HIP(hipEventRecord(e0, s));
