@@ -120,7 +120,14 @@ typedef struct {
                                 (default: the LDS-staged 27-offset form on levels
                                 of >= 40000 nodes, the plane-split form below),
                                 1 the LDS-staged form on every level, 2 the
-                                plane-split form on every level                   */
+                                plane-split form on every level, 3 as 0 except
+                                that an FP64 level 1 above the coarsest applies
+                                its operator from the child moduli of each
+                                coarse element (Eq. galerkin_level1 evaluated
+                                per element, sum/difference basis) and reads
+                                the stored stencil only for the rows next to
+                                Dirichlet DOFs or odd-axis ends (the stencil is
+                                still assembled for the coarser products)       */
   int bf16_guard;            /* 1 (default): a PCG solve with the V-cycle and
                                 fine_prec BF16 watches its progress (Sec. 3.5:
                                 BF16 is used only under a guard, and Sec. 3.6:
@@ -245,9 +252,10 @@ int sgmg_fgmres_solve(sgmg_hierarchy* h, int precond, int restart, const double*
 int sgmg_lanczos(sgmg_hierarchy* h, int precond, int m, const double* g, double breakdown,
                  double* alpha, double* beta, int* steps, double* ritz, void* stream);
 
-/* Autotuner of the MFMA fine operators' launch shape: times each candidate
+/* Autotuner of the fine operators' launch shape: times each candidate
  * (element rows per wave tile: 4, 8; owned node planes per wave: 2, 4, 8,
- * 16, 32) on this hierarchy's mesh for the BF16, BF16X3 and FP64 kernels,
+ * 16, 32) on this hierarchy's mesh for the BF16, BF16X3 and FP64 kernels
+ * (the BF16 family in the smoothing epilogue, FP64 as a plain product),
  * keeps the fastest in h and in a process-wide cache keyed by (nx, ny, nz,
  * variant) that later setups of the same mesh read.  shape_out (host, 6
  * ints, may be NULL) receives (rows, planes) for BF16, BF16X3, then FP64;

@@ -54,15 +54,26 @@ constexpr int kSfWave = 3 * kSfPlane;        // ring of three node planes
 struct SfCoef {
   double a;    // lam / 16: (x_u, y_v, z_w) sum
   double b;    // mu / 8: (x_u, y_v, z_w) own
-  double c;    // mu / 16: shear pairs; own term of the bilinear pairs
+  double c;    // mu / 16: shear pairs
   double d;    // lam / 48: bilinear pairs, sum
   double e;    // mu / 48: (xy_w, xz_v, yz_u), sum and own
   double f;    // (lam + 4 mu) / 144: xyz
+  double g;    // mu / 16: bilinear pairs, own
 };
 
 // the coefficients for E = 1 from the Lame parameters
 __host__ __device__ inline SfCoef sf_coef(double lam, double mu) {
-  return SfCoef{lam / 16.0, mu / 8.0, mu / 16.0, lam / 48.0, mu / 48.0, (lam + 4.0 * mu) / 144.0};
+  return SfCoef{lam / 16.0, mu / 8.0, mu / 16.0, lam / 48.0, mu / 48.0, (lam + 4.0 * mu) / 144.0,
+                mu / 16.0};
+}
+
+// The same coefficients for the children of a coarse element in the scaled
+// representation of the level-1 product (each coefficient with k linear
+// axes carried times 2^k on the input side and 2^-k on the output side): a
+// block with k linear axes is divided by 4^k.
+__host__ __device__ inline SfCoef l1_coef(double lam, double mu) {
+  const SfCoef f = sf_coef(lam, mu);
+  return SfCoef{f.a / 4.0, f.b / 4.0, f.c / 4.0, f.d / 16.0, f.e / 16.0, f.f / 64.0, f.g / 16.0};
 }
 
 // (x, y) transform of one node face: v[dx][dy] -> F[cx][cy] (0 constant,
@@ -86,24 +97,10 @@ __device__ inline void face_bwd(const double (&P)[2][2], double (&w)[2][2]) {
   w[1][1] = a1 + b1;
 }
 
-// One element in the transformed basis: from the (x, y) transforms of its
-// bottom and top node faces (F0, F1; [c][cx][cy]) to the (x, y) transforms of
-// its bottom and top output faces (P0, P1), coefficients scaled by E.
-__device__ __forceinline__ void haar_element(const double (&F0)[3][2][2], const double (&F1)[3][2][2],
-                                             const SfCoef& k, double (&P0)[3][2][2],
-                                             double (&P1)[3][2][2]) {
-  // z butterflies: h[c][cx][cy][cz]
-  double h[3][2][2][2];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int cx = 0; cx < 2; ++cx)
-#pragma unroll
-      for (int cy = 0; cy < 2; ++cy) {
-        h[c][cx][cy][0] = F0[c][cx][cy] + F1[c][cx][cy];
-        h[c][cx][cy][1] = F1[c][cx][cy] - F0[c][cx][cy];
-      }
-  double o[3][2][2][2];
+// The element matrix in the transformed basis: h[c][cx][cy][cz] -> o, the
+// coefficients scaled by the element modulus.
+__device__ __forceinline__ void haar_op(const double (&h)[3][2][2][2], const SfCoef& k,
+                                        double (&o)[3][2][2][2]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) o[c][0][0][0] = 0.0;    // rigid translations
   {  // (x_u, y_v, z_w)
@@ -126,18 +123,18 @@ __device__ __forceinline__ void haar_element(const double (&F0)[3][2][2], const 
   }
   {  // bilinear pairs (xy_u, yz_w), (xy_v, xz_w), (xz_u, yz_v)
     double a = h[0][1][1][0], b = h[2][0][1][1], t = k.d * (a + b);
-    o[0][1][1][0] = t + k.c * a;
-    o[2][0][1][1] = t + k.c * b;
+    o[0][1][1][0] = t + k.g * a;
+    o[2][0][1][1] = t + k.g * b;
     a = h[1][1][1][0];
     b = h[2][1][0][1];
     t = k.d * (a + b);
-    o[1][1][1][0] = t + k.c * a;
-    o[2][1][0][1] = t + k.c * b;
+    o[1][1][1][0] = t + k.g * a;
+    o[2][1][0][1] = t + k.g * b;
     a = h[0][1][0][1];
     b = h[1][0][1][1];
     t = k.d * (a + b);
-    o[0][1][0][1] = t + k.c * a;
-    o[1][0][1][1] = t + k.c * b;
+    o[0][1][0][1] = t + k.g * a;
+    o[1][0][1][1] = t + k.g * b;
   }
   {  // (xy_w, xz_v, yz_u)
     const double p = h[2][1][1][0], q = h[1][1][0][1], r = h[0][0][1][1];
@@ -148,7 +145,29 @@ __device__ __forceinline__ void haar_element(const double (&F0)[3][2][2], const 
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) o[c][1][1][1] = k.f * h[c][1][1][1];
-  // inverse z butterflies
+}
+
+__device__ inline SfCoef scaled(const SfCoef& k, double E) {
+  return SfCoef{k.a * E, k.b * E, k.c * E, k.d * E, k.e * E, k.f * E, k.g * E};
+}
+
+// z butterflies of the two node faces: h[c][cx][cy][cz]
+__device__ inline void z_fwd(const double (&F0)[3][2][2], const double (&F1)[3][2][2],
+                             double (&h)[3][2][2][2]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int cx = 0; cx < 2; ++cx)
+#pragma unroll
+      for (int cy = 0; cy < 2; ++cy) {
+        h[c][cx][cy][0] = F0[c][cx][cy] + F1[c][cx][cy];
+        h[c][cx][cy][1] = F1[c][cx][cy] - F0[c][cx][cy];
+      }
+}
+
+// inverse z butterflies: the (x, y) transforms of the bottom and top output faces
+__device__ inline void z_bwd(const double (&o)[3][2][2][2], double (&P0)[3][2][2],
+                             double (&P1)[3][2][2]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -160,10 +179,87 @@ __device__ __forceinline__ void haar_element(const double (&F0)[3][2][2], const 
       }
 }
 
-template <int MODE>
+// One fine element: from the (x, y) transforms of its bottom and top node
+// faces (F0, F1; [c][cx][cy]) to those of its bottom and top output faces.
+__device__ __forceinline__ void haar_element(const double (&F0)[3][2][2], const double (&F1)[3][2][2],
+                                             const SfCoef& k, double (&P0)[3][2][2],
+                                             double (&P1)[3][2][2]) {
+  double h[3][2][2][2], o[3][2][2][2];
+  z_fwd(F0, F1, h);
+  haar_op(h, k, o);
+  z_bwd(o, P0, P1);
+}
+
+// One coarse element of the level-1 Galerkin operator (Eq. galerkin_level1,
+// children free of Dirichlet DOFs): sum over its eight children p of
+// E_p P_p^T K_e P_p.  Along each axis the trilinear interpolation onto a
+// child maps the parent's (sum, difference) pair (S, D) to the child's
+// (S -/+ D / 2, D / 2) (- for the lower child), and its transpose maps the
+// child's output pair (s, d) to (s, (d -/+ s) / 2).  Carrying every
+// difference at twice its value on the input side and at half on the output
+// side leaves one multiply-add per pair and folds the factors into the
+// coefficients (l1_coef).  E8[p], p = px + 2 py + 4 pz.
+__device__ __forceinline__ void l1_element(const double (&F0)[3][2][2], const double (&F1)[3][2][2],
+                                           const double (&E8)[8], const SfCoef& k,
+                                           double (&P0)[3][2][2], double (&P1)[3][2][2]) {
+  double h[3][2][2][2], O[3][2][2][2];
+  z_fwd(F0, F1, h);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) O[c][i & 1][(i >> 1) & 1][i >> 2] = 0.0;
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const double sx = (p & 1) ? 0.5 : -0.5, sy = (p & 2) ? 0.5 : -0.5, sz = (p & 4) ? 0.5 : -0.5;
+    double ch[3][2][2][2], o[3][2][2][2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) ch[c][i & 1][(i >> 1) & 1][i >> 2] = h[c][i & 1][(i >> 1) & 1][i >> 2];
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int z = 0; z < 2; ++z) ch[c][0][y][z] += sx * ch[c][1][y][z];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int z = 0; z < 2; ++z) ch[c][x][0][z] += sy * ch[c][x][1][z];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) ch[c][x][y][0] += sz * ch[c][x][y][1];
+    }
+    haar_op(ch, scaled(k, E8[p]), o);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) o[c][x][y][1] += sz * o[c][x][y][0];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int z = 0; z < 2; ++z) o[c][x][1][z] += sy * o[c][x][0][z];
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int z = 0; z < 2; ++z) o[c][1][y][z] += sx * o[c][0][y][z];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) O[c][i & 1][(i >> 1) & 1][i >> 2] += o[c][i & 1][(i >> 1) & 1][i >> 2];
+    }
+  }
+  z_bwd(O, P0, P1);
+}
+
+// L1 = false: the fine operator (E: one modulus per element).  L1 = true: the
+// level-1 Galerkin operator on the coarse grid g (E: the eight child moduli
+// of each coarse element, zero for coarse elements the product does not
+// cover; nodes with skip[node] != 0 are left to another kernel).
+template <int MODE, bool L1>
 __device__ __forceinline__ void fine_sf64_body(Grid g, const double* __restrict__ E, SfCoef cf,
                                                const double* __restrict__ u,
-                                               const uint8_t* __restrict__ fixn, Epi<double> ep,
+                                               const uint8_t* __restrict__ fixn,
+                                               const uint8_t* __restrict__ skip, Epi<double> ep,
                                                int zchunk, int ntx, int nty, int ntiles,
                                                int blk) {
   __shared__ __attribute__((aligned(16))) unsigned char lds_all[kSfWaves * kSfWave];
@@ -178,8 +274,10 @@ __device__ __forceinline__ void fine_sf64_body(Grid g, const double* __restrict_
   const int zend = tile < ntiles ? min(zs + zchunk, g.Nz) : zs - 1;
   const size_t nvec = (size_t)g.n * sizeof(double);
   const __amdgpu_buffer_rsrc_t ru = make_rsrc(u, nvec);
-  const __amdgpu_buffer_rsrc_t re = make_rsrc(E, (size_t)g.nel * sizeof(double));
+  constexpr int kEs = L1 ? 64 : 8;                 // modulus bytes per element
+  const __amdgpu_buffer_rsrc_t re = make_rsrc(E, (size_t)g.nel * kEs);
   const __amdgpu_buffer_rsrc_t rfix = make_rsrc(fixn, (size_t)g.Nn);
+  const __amdgpu_buffer_rsrc_t rskip = make_rsrc(skip, L1 ? (size_t)g.Nn : 0);
   const __amdgpu_buffer_rsrc_t rb = make_rsrc(ep.b, MODE == EPI_RESID || MODE == EPI_SMOOTH ? nvec : 0);
   const __amdgpu_buffer_rsrc_t rdi = make_rsrc(ep.dinv, MODE == EPI_SMOOTH ? nvec : 0);
   const __amdgpu_buffer_rsrc_t rd = make_rsrc(ep.d, MODE == EPI_SMOOTH ? nvec : 0);
@@ -223,13 +321,24 @@ __device__ __forceinline__ void fine_sf64_body(Grid g, const double* __restrict_
     }
   };
 
-  // element modulus of this lane, one plane ahead; zero outside the mesh
+  // element modulus (moduli) of this lane, one plane ahead; zero outside the mesh
   const int e_lane = part((unsigned)ex < (unsigned)g.nx && (unsigned)ey < (unsigned)g.ny,
-                          8 * (ex + g.nx * ey));
-  double ev = 0.0;
+                          kEs * (ex + g.nx * ey));
+  constexpr int NEv = L1 ? 8 : 1;
+  double ev[NEv];
   auto load_e = [&](int ez, bool need) {
-    const int pe = part(need && (unsigned)ez < (unsigned)g.nz, 8 * g.nx * g.ny * ez);
-    ev = bload1d(re, off2(e_lane, pe));
+    const int pe = part(need && (unsigned)ez < (unsigned)g.nz, kEs * g.nx * g.ny * ez);
+    const int o = off2(e_lane, pe);
+    if (L1) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const auto t = __builtin_amdgcn_raw_buffer_load_b128(re, off2(o, 16 * q), 0, 0);
+        ev[2 * q] = __hiloint2double((int)t[1], (int)t[0]);
+        ev[2 * q + 1] = __hiloint2double((int)t[3], (int)t[2]);
+      }
+    } else {
+      ev[0] = bload1d(re, o);
+    }
   };
 
   // owned node (ex, ey) of each plane: lanes n >= 1, gr >= 1 inside the grid
@@ -238,11 +347,12 @@ __device__ __forceinline__ void fine_sf64_body(Grid g, const double* __restrict_
   const int f_lane = part(own_xy, ex + g.Nx * ey);
   constexpr int NV = MODE == EPI_SMOOTH ? 3 : MODE == EPI_RESID ? 1 : 0;
   double vv[NV > 0 ? NV : 1][3];
-  unsigned fv = 0;
+  unsigned fv = 0, sv = 0;
   auto load_v = [&](int ez) {
     const bool own = ez >= zs && ez < zend;
     const int po = part(own, 24 * g.Nx * g.Ny * ez), pf = part(own, g.Nx * g.Ny * ez);
     fv = __builtin_amdgcn_raw_buffer_load_b8(rfix, off2(f_lane, pf), 0, 0);
+    if (L1) sv = __builtin_amdgcn_raw_buffer_load_b8(rskip, off2(f_lane, pf), 0, 0);
     const int o = off2(o_lane, po);
     if (MODE == EPI_SMOOTH) {
       bload3(rb, o, vv[0]);
@@ -291,15 +401,19 @@ __device__ __forceinline__ void fine_sf64_body(Grid g, const double* __restrict_
   read_face(zs - 1, F0);
   for (int ez = zs - 1; ez < zend; ++ez) {
     store_u(ez + 2);                               // loaded during the previous plane
-    const double esc = ev;
+    double esc[NEv];
+#pragma unroll
+    for (int q = 0; q < NEv; ++q) esc[q] = ev[q];
     load_u(ez + 3, ez + 3 <= zend);
     load_e(ez + 1, ez + 1 < zend);
     load_v(ez);
     double x[3] = {xown[0], xown[1], xown[2]};     // the owned node's input (plane ez)
     read_face(ez + 1, F1);
-    const SfCoef ce{cf.a * esc, cf.b * esc, cf.c * esc, cf.d * esc, cf.e * esc, cf.f * esc};
     double P0[3][2][2], P1[3][2][2];
-    haar_element(F0, F1, ce, P0, P1);
+    if constexpr (L1)
+      l1_element(F0, F1, esc, cf, P0, P1);
+    else
+      haar_element(F0, F1, scaled(cf, esc[0]), P0, P1);
     // node plane ez: this element's bottom face + the top face of the one
     // below, then the inverse (x, y) butterflies, then x and y sums
     double y[3];
@@ -319,7 +433,7 @@ __device__ __forceinline__ void fine_sf64_body(Grid g, const double* __restrict_
       const double x1 = w[0][1] + dpp_shr1(w[1][1]);
       y[c] = x0 + bpermute(up, x1);                    // dy = 1 of lane - 16
     }
-    const int o = off2(o_lane, part(ez >= zs && ez < zend, 24 * g.Nx * g.Ny * ez));
+    const int o = off2(o_lane, part(ez >= zs && ez < zend && sv == 0, 24 * g.Nx * g.Ny * ez));
     const bool mine = (unsigned)o < (unsigned)kPoison;
     double out[3], dd[3];
 #pragma unroll
@@ -358,8 +472,17 @@ template <int MODE>
 __global__ __launch_bounds__(64 * kSfWaves) void k_apply_fine_sf64(
     Grid g, const double* __restrict__ E, SfCoef cf, const double* __restrict__ u,
     const uint8_t* __restrict__ fixn, Epi<double> ep, int zchunk, int ntx, int nty, int ntiles) {
-  fine_sf64_body<MODE>(g, E, cf, u, fixn, ep, zchunk, ntx, nty, ntiles,
-                       xcd_block(blockIdx.x, gridDim.x));
+  fine_sf64_body<MODE, false>(g, E, cf, u, fixn, nullptr, ep, zchunk, ntx, nty, ntiles,
+                              xcd_block(blockIdx.x, gridDim.x));
+}
+
+template <int MODE>
+__global__ __launch_bounds__(64 * kSfWaves) void k_apply_l1_haar(
+    Grid g, const double* __restrict__ E8, SfCoef cf, const double* __restrict__ u,
+    const uint8_t* __restrict__ fixn, const uint8_t* __restrict__ skip, Epi<double> ep, int zchunk,
+    int ntx, int nty, int ntiles) {
+  fine_sf64_body<MODE, true>(g, E8, cf, u, fixn, skip, ep, zchunk, ntx, nty, ntiles,
+                             xcd_block(blockIdx.x, gridDim.x));
 }
 
 // Stage-batched outer q = K p with the p.q block partials: block b is entry
@@ -381,7 +504,8 @@ __global__ __launch_bounds__(64 * kSfWaves) void k_bs_fine_sf64(
   ep.out = I.q;
   ep.want_dot = 1;
   ep.ws.partials = part;
-  fine_sf64_body<kStoreDot>(V.g, S.E64, sf_coef(S.lam, S.mu), I.p, V.fixn, ep, zchunk, gm.x, gm.y, gm.z, e.y);
+  fine_sf64_body<kStoreDot, false>(V.g, S.E64, sf_coef(S.lam, S.mu), I.p, V.fixn, nullptr, ep,
+                                   zchunk, gm.x, gm.y, gm.z, e.y);
 }
 
 struct SfLaunch { int ntx, nty, ntiles, blocks; };
@@ -395,6 +519,78 @@ SfLaunch sf_launch(const Grid& g, int zchunk) {
 }
 
 }  // namespace
+
+// Child moduli of each coarse element (p = px + 2 py + 4 pz) and whether the
+// element is left out: a Dirichlet DOF on one of its 27 fine nodes, or the
+// last element along an odd fine axis (three children there).
+__global__ void k_l1_child_moduli(Grid f, Grid c, const double* __restrict__ E,
+                                  const uint8_t* __restrict__ ffix, double* __restrict__ E8,
+                                  uint8_t* __restrict__ el_out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= c.nel) return;
+  const int cx = e % c.nx, t = e / c.nx, cy = t % c.ny, cz = t / c.ny;
+  bool out = (2 * cx + 2 < f.nx && cx == c.nx - 1) || (2 * cy + 2 < f.ny && cy == c.ny - 1) ||
+             (2 * cz + 2 < f.nz && cz == c.nz - 1);
+  for (int a = 0; a < 27 && !out; ++a) {
+    const int x = 2 * cx + a % 3, y = 2 * cy + (a / 3) % 3, z = 2 * cz + a / 9;
+    out = ffix[x + f.Nx * (y + f.Ny * z)] != 0;
+  }
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const int x = 2 * cx + (p & 1), y = 2 * cy + ((p >> 1) & 1), z = 2 * cz + (p >> 2);
+    E8[8 * (size_t)e + p] = out ? 0.0 : E[x + f.nx * (y + f.ny * z)];
+  }
+  el_out[e] = out ? 1 : 0;
+}
+
+// Coarse nodes whose row the matrix-free product does not complete: next to
+// a left-out element, or with a Dirichlet DOF.
+__global__ void k_l1_skip_nodes(Grid c, const uint8_t* __restrict__ el_out,
+                                const uint8_t* __restrict__ cfix, uint8_t* __restrict__ skip) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= c.Nn) return;
+  const int i = n % c.Nx, t = n / c.Nx, j = t % c.Ny, k = t / c.Ny;
+  bool sk = cfix[n] != 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int ex = i - 1 + (q & 1), ey = j - 1 + ((q >> 1) & 1), ez = k - 1 + (q >> 2);
+    if ((unsigned)ex < (unsigned)c.nx && (unsigned)ey < (unsigned)c.ny && (unsigned)ez < (unsigned)c.nz)
+      sk = sk || el_out[ex + c.nx * (ey + c.ny * ez)] != 0;
+  }
+  skip[n] = sk ? 1 : 0;
+}
+
+void launch_l1_child_moduli(const Grid& fine, const Grid& coarse, const double* E,
+                            const uint8_t* ffix, double* E8, uint8_t* el_out, hipStream_t s) {
+  k_l1_child_moduli<<<div_up(coarse.nel, 256), 256, 0, s>>>(fine, coarse, E, ffix, E8, el_out);
+}
+
+void launch_l1_skip_nodes(const Grid& coarse, const uint8_t* el_out, const uint8_t* cfix,
+                          uint8_t* skip, hipStream_t s) {
+  k_l1_skip_nodes<<<div_up(coarse.Nn, 256), 256, 0, s>>>(coarse, el_out, cfix, skip);
+}
+
+bool l1_haar_size_ok(const Grid& c) {
+  return (size_t)c.nel * 64 < ((size_t)1 << 30) - 64 && (size_t)c.n * sizeof(double) < ((size_t)1 << 30) - 64;
+}
+
+void launch_apply_l1_haar(const Grid& c, int zchunk, const double* E8, double lam, double mu,
+                          const double* u, const uint8_t* fixn, const uint8_t* skip,
+                          const Epi<double>& ep, hipStream_t s) {
+  if (zchunk < 1) zchunk = 1;
+  const SfLaunch m = sf_launch(c, zchunk);
+  const SfCoef cf = l1_coef(lam, mu);
+  const dim3 grid(m.blocks), block(64 * kSfWaves);
+  if (ep.mode == EPI_STORE)
+    k_apply_l1_haar<EPI_STORE><<<grid, block, 0, s>>>(c, E8, cf, u, fixn, skip, ep, zchunk, m.ntx,
+                                                      m.nty, m.ntiles);
+  else if (ep.mode == EPI_RESID)
+    k_apply_l1_haar<EPI_RESID><<<grid, block, 0, s>>>(c, E8, cf, u, fixn, skip, ep, zchunk, m.ntx,
+                                                      m.nty, m.ntiles);
+  else
+    k_apply_l1_haar<EPI_SMOOTH><<<grid, block, 0, s>>>(c, E8, cf, u, fixn, skip, ep, zchunk, m.ntx,
+                                                       m.nty, m.ntiles);
+}
 
 bool sf64_size_ok(const Grid& g) {
   return (size_t)g.n * sizeof(double) < ((size_t)1 << 30) - 64;

@@ -515,6 +515,56 @@ void bs_stencil_s(const BsArgs& a, const BsTable& t, const int* flags, int l, in
     k_bs_stencil_s<EPI_SMOOTH><<<t.n, 192, 0, s>>>(a.sys, a.items, t.blk, flags, l, cin);
 }
 
+// Listed nodes only (the rows a matrix-free product leaves out): thread per
+// (listed node, component); the 27 blocks of the row are read as in the
+// LDS-staged form (upper half stored at the node, lower half the transposed
+// upper blocks of the neighbour), the neighbour values from memory.
+template <typename T>
+__global__ __launch_bounds__(256) void k_stencil_apply_list(Grid g, const T* __restrict__ S,
+                                                            const T* __restrict__ u,
+                                                            const uint8_t* __restrict__ fixn,
+                                                            Epi<T> ep, const int* __restrict__ list,
+                                                            int nlist) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= 3 * nlist) return;
+  const int node = list[t / 3], d = t - 3 * (t / 3);
+  const size_t dof = 3 * (size_t)node + d;
+  const Epi1In<T> ein = epilogue1_load(ep, dof);
+  const unsigned fx = fixn[node];
+  const int i = node % g.Nx, tt = node / g.Nx, j = tt % g.Ny, k = tt / g.Ny;
+  const size_t Nn = g.Nn;
+  T acc = (T)0;
+#pragma unroll
+  for (int q = 0; q < 27; ++q) {
+    const int o = (q & 1) ? 13 - ((q + 1) >> 1) : 13 + (q >> 1);
+    const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+    const bool ok = (unsigned)(i + ox) < (unsigned)g.Nx && (unsigned)(j + oy) < (unsigned)g.Ny &&
+                    (unsigned)(k + oz) < (unsigned)g.Nz;
+    const int nb = ok ? node + ox + g.Nx * (oy + g.Ny * oz) : node;
+    const T* un = u + 3 * (size_t)nb;
+    T v;
+    if (o >= 13) {
+      const T* Sb = S + ((size_t)o * 9 + 3 * d) * Nn + node;
+      v = Sb[0] * un[0] + Sb[Nn] * un[1] + Sb[2 * Nn] * un[2];
+    } else {
+      const T* Sb = S + ((size_t)(26 - o) * 9 + d) * Nn + nb;
+      v = Sb[0] * un[0] + Sb[3 * Nn] * un[1] + Sb[6 * Nn] * un[2];
+    }
+    acc += ok ? v : (T)0;
+  }
+  epilogue1(ep, dof, (fx >> d) & 1u, u[dof], (double)acc, ein);
+}
+
+template <typename T>
+void launch_stencil_apply_list(const Grid& g, const T* S, const T* u, const uint8_t* fixn,
+                               const Epi<T>& ep, const int* list, int nlist, hipStream_t s) {
+  if (nlist <= 0) return;
+  k_stencil_apply_list<T><<<div_up(3 * nlist, 256), 256, 0, s>>>(g, S, u, fixn, ep, list, nlist);
+}
+template void launch_stencil_apply_list<double>(const Grid&, const double*, const double*,
+                                                const uint8_t*, const Epi<double>&, const int*,
+                                                int, hipStream_t);
+
 // levels with fewer nodes use the plane-split form
 constexpr int kStencilSplitNodes = 40000;
 

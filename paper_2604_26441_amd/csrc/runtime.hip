@@ -75,6 +75,16 @@ struct sgmg_hierarchy {
   int mfma_zchunk[3] = {4, 4, 0};
   uint16_t* atab = nullptr;  // MFMA A-operand table (BF16 bits)
   double* atab64 = nullptr;  // FP64 MFMA A-operand table
+  // level 1 without its stored stencil (FP64 level 1 above the coarsest):
+  // the child moduli of each coarse element, the elements and nodes the
+  // product leaves to the stencil, and the list of those nodes
+  double* l1_E8 = nullptr;
+  uint8_t* l1_el = nullptr;
+  uint8_t* l1_skip = nullptr;
+  int* l1_list = nullptr;
+  int l1_nlist = 0;
+  bool l1_mf = false;        // level-1 applies use it (else the stencil)
+  int l1_zchunk = 2;         // its node planes per wave tile
   double maxE_lambda = 0.0;  // max E when lambdas were estimated
   int nL = 0;
   int* free_idx = nullptr;
@@ -264,15 +274,23 @@ int apply_level<double>(const sgmg_hierarchy* h, int l, sgmg_prec prec, const do
     set_error("double vectors require SGMG_F64");
     return SGMG_EINVAL;
   }
-  if (l == 0 && h->mfma_rows[2] == 1 && sf64_size_ok(L.g))
+  if (l == 0 && h->mfma_rows[2] == 1 && sf64_size_ok(L.g)) {
     launch_apply_fine_sf64(L.g, h->mfma_zchunk[2], h->E64, h->kt.lam, h->kt.mu, x, L.fixn, ep, s);
-  else if (l == 0 && h->mfma_rows[2] > 1 && mfma64_size_ok(L.g))
+  } else if (l == 0 && h->mfma_rows[2] > 1 && mfma64_size_ok(L.g)) {
     launch_apply_fine_mfma64(L.g, h->mfma_rows[2], h->mfma_zchunk[2], h->E64, h->atab64, x, L.fixn,
                              ep, s);
-  else if (l == 0)
+  } else if (l == 0) {
     launch_apply_fine_node<double>(L.g, h->E64, h->ke64, x, L.fixn, ep, s);
-  else
-    launch_stencil_apply<double>(L.g, L.S64, x, L.fixn, ep, h->o.stencil_form, s);
+  } else if (l == 1 && h->l1_mf && !ep.want_dot) {
+    // rows next to Dirichlet DOFs (or odd-axis ends) from the stencil, the
+    // rest from the element products
+    launch_stencil_apply_list<double>(L.g, L.S64, x, L.fixn, ep, h->l1_list, h->l1_nlist, s);
+    launch_apply_l1_haar(L.g, h->l1_zchunk, h->l1_E8, h->kt.lam, h->kt.mu, x, L.fixn, h->l1_skip,
+                         ep, s);
+  } else {
+    launch_stencil_apply<double>(L.g, L.S64, x, L.fixn, ep,
+                                 h->o.stencil_form == 3 ? 0 : h->o.stencil_form, s);
+  }
   return check_launch();
 }
 
@@ -304,7 +322,8 @@ int apply_level<float>(const sgmg_hierarchy* h, int l, sgmg_prec prec, const flo
       set_error("level is not stored in FP32");
       return SGMG_EINVAL;
     }
-    launch_stencil_apply<float>(L.g, L.S32, x, L.fixn, ep, h->o.stencil_form, s);
+    launch_stencil_apply<float>(L.g, L.S32, x, L.fixn, ep,
+                                h->o.stencil_form == 3 ? 0 : h->o.stencil_form, s);
   }
   return check_launch();
 }
@@ -373,6 +392,8 @@ int assemble_operators(sgmg_hierarchy* h, const double* rho_or_E, hipStream_t s)
     launch_stencil_diag(C.g, C.S64, C.d64, s);
     if (C.S32) launch_stencil_to_f32(C.S64, C.S32, (size_t)kStencil * C.g.Nn, s);
   }
+  if (h->l1_E8)
+    launch_l1_child_moduli(L0.g, h->lev[1].g, h->E64, L0.fixn, h->l1_E8, h->l1_el, s);
   TRY(check_launch());
   // D^-1 with the floor max(D, 1e-30 max D) on free DOFs, 0 on fixed DOFs.
   for (int l = 0; l < h->L; ++l) {
@@ -604,7 +625,7 @@ int validate(const sgmg_options* o) {
   if (!(o->cheb_alpha > 0.0 && o->cheb_alpha < 1.0)) { set_error("cheb_alpha must be in (0,1)"); return SGMG_EINVAL; }
   if (!(o->lambda_safety > 0.0)) { set_error("lambda_safety must be > 0"); return SGMG_EINVAL; }
   if (o->cycle_gamma != 1 && o->cycle_gamma != 2) { set_error("cycle_gamma must be 1 or 2"); return SGMG_EINVAL; }
-  if (o->stencil_form < 0 || o->stencil_form > 2) { set_error("stencil_form must be 0, 1 or 2"); return SGMG_EINVAL; }
+  if (o->stencil_form < 0 || o->stencil_form > 3) { set_error("stencil_form must be 0, 1, 2 or 3"); return SGMG_EINVAL; }
   if (o->bf16_guard && (o->guard_window < 1 || !(o->guard_drop >= 1.0))) {
     set_error("bf16_guard needs guard_window >= 1 and guard_drop >= 1");
     return SGMG_EINVAL;
@@ -862,7 +883,37 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
         (rc = dalloc_t(h, &h->cpcg_done, (size_t)it + 1)))
       return fail(rc);
   }
+  // level 1 without its stored stencil: FP64 level 1 above the coarsest
+  const bool l1mf = L > 2 && !h->lev[1].f32 && (opts->stencil_form == 3) &&
+                    l1_haar_size_ok(h->lev[1].g);
+  if (l1mf) {
+    const Grid& c1 = h->lev[1].g;
+    if ((rc = dalloc_t(h, &h->l1_E8, (size_t)c1.nel * 8)) ||
+        (rc = dalloc_t(h, &h->l1_el, (size_t)c1.nel)) ||
+        (rc = dalloc_t(h, &h->l1_skip, (size_t)c1.Nn)))
+      return fail(rc);
+  }
   if ((rc = assemble_operators(h, rho_or_E, s))) return fail(rc);
+  if (l1mf) {
+    // the nodes left to the stencil depend on the Dirichlet masks only
+    const Grid& c1 = h->lev[1].g;
+    launch_l1_skip_nodes(c1, h->l1_el, h->lev[1].fixn, h->l1_skip, s);
+    if ((rc = check_launch())) return fail(rc);
+    std::vector<uint8_t> sk((size_t)c1.Nn);
+    if (hipMemcpyAsync(sk.data(), h->l1_skip, sk.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      set_error("level-1 node flags copy failed");
+      return fail(SGMG_EHIP);
+    }
+    std::vector<int> list;
+    for (int i = 0; i < c1.Nn; ++i)
+      if (sk[i]) list.push_back(i);
+    h->l1_nlist = (int)list.size();
+    if ((rc = dalloc_t(h, &h->l1_list, std::max<size_t>(list.size(), 1)))) return fail(rc);
+    if (!list.empty())
+      hipMemcpyAsync(h->l1_list, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    h->l1_mf = true;
+  }
   if (opts->lambda_override) h->o.lambda_override = opts->lambda_override;
   rc = estimate_lambdas(h, s);
   h->o.lambda_override = nullptr;
@@ -1649,6 +1700,7 @@ int sgmg_autotune(sgmg_hierarchy* h, int* shape_out, void* stream) {
     rc = SGMG_ENOMEM;
   } else {
     hipMemsetAsync(u64, 0, (size_t)L0.g.n * sizeof(double), s);
+    hipMemsetAsync(y64, 0, (size_t)L0.g.n * sizeof(double), s);
   }
   // variant q: 0 BF16, 1 BF16X3, 2 FP64
   for (int q = 0; q < 3 && !rc; ++q) {
@@ -1701,13 +1753,15 @@ int sgmg_autotune(sgmg_hierarchy* h, int* shape_out, void* stream) {
           if (q == 2)
             launch_apply_fine_mfma64(L0.g, rows, z, h->E64, h->atab64, u64, L0.fixn,
                                      epi_store<double>(y64), s);
-          else
+          else   // a Chebyshev smoothing step: the epilogue of most V-cycle applications
             launch_apply_fine_mfma(L0.g, key, rows, z, h->E32s, h->atab, u, L0.fixn,
-                                   epi_store<float>(y), s);
+                                   epi_smooth<float>(y, u, (const float*)u64, (float*)y64, 0.5,
+                                                     0.5, 1, nullptr),
+                                   s);
         };
         for (int w = 0; w < 3; ++w) launch();
         hipEventRecord(e0, s);
-        for (int r = 0; r < 20; ++r) launch();
+        for (int r = 0; r < 30; ++r) launch();
         hipEventRecord(e1, s);
         if ((rc = check_launch())) break;
         if (hipEventSynchronize(e1) != hipSuccess) {

@@ -70,11 +70,13 @@ def test_galerkin_levels_and_diagonals(dims, L, seed):
         assert np.abs(S - ref).max() <= 1e-13 * np.abs(ref).max(), l
 
 
-@pytest.mark.parametrize("form", [0, 1, 2])
+@pytest.mark.parametrize("form", [0, 1, 2, 3])
 @pytest.mark.parametrize("dims,L,seed", CASES)
 def test_stencil_apply(dims, L, seed, form):
     """form 1: LDS-staged 27-offset kernel, 2: plane-split kernel, 0: chosen
-    by level size (the plane-split kernel at these sizes)."""
+    by level size (the plane-split kernel at these sizes), 3: level 1 from
+    the child moduli of its elements (rows next to Dirichlet DOFs and odd-axis
+    ends from the stencil), the other levels as 0."""
     from paper_2604_26441_amd import simpgmg
     rho, fixed = _inputs(dims, seed)
     E = mesh.simp_modulus(rho, 3)
@@ -86,6 +88,35 @@ def test_stencil_apply(dims, L, seed, form):
         y = t64(np.zeros_like(u))
         simpgmg.apply_K(h, l, "f64", t64(u), y)
         assert rel_err(np64(y), K @ u, abs(K) @ np.abs(u)) < 1e-13
+
+
+@pytest.mark.parametrize("dims", [(20, 12, 10), (21, 9, 11)])
+def test_level1_element_products_with_scattered_dirichlet(dims):
+    """Level 1 from the child moduli (stencil_form 3) with Dirichlet DOFs
+    inside the mesh, single components included, and (second mesh) odd
+    axes: every row against the oracle's Galerkin operator, and the same
+    level applied from the stored stencil."""
+    import torch
+    from paper_2604_26441_amd import simpgmg
+    rho, _ = _inputs(dims, 17)
+    g = np.random.default_rng(18)
+    fixed = workloads.cantilever_fixed(dims).astype(bool)
+    fixed |= g.uniform(size=fixed.size) < 0.01
+    E = mesh.simp_modulus(rho, 3)
+    oh = multigrid.build(dims, E, fixed, multigrid.Options(n_levels=3, lambdas=[1.0] * 2))
+    fd = torch.as_tensor(fixed.astype(np.uint8), device="cuda:0")
+    h3 = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, n_levels=3, stencil_form=3),
+                                 t64(rho), fixed_dof=fd)
+    h0 = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, n_levels=3), t64(rho), fixed_dof=fd)
+    K = oh.levels[1].K
+    u = workloads.random_vector(K.shape[0], 19, oh.levels[1].fixed)
+    y3, y0 = t64(np.zeros_like(u)), t64(np.zeros_like(u))
+    simpgmg.apply_K(h3, 1, "f64", t64(u), y3)
+    simpgmg.apply_K(h0, 1, "f64", t64(u), y0)
+    scale = abs(K) @ np.abs(u)
+    assert rel_err(np64(y3), K @ u, scale) < 1e-13
+    assert rel_err(np64(y3), np64(y0), scale) < 1e-13
+    assert np.all(np64(y3)[oh.levels[1].fixed] == 0)
 
 
 @pytest.mark.parametrize("dims,L,seed", CASES)

@@ -47,11 +47,11 @@ def test_vcycle_f64_matches_oracle(dims, L, smoother, shape):
 
 
 @pytest.mark.parametrize("dims,L", [((24, 12, 12), 4), ((9, 7, 5), 3), ((32, 16, 16), 3)])
-@pytest.mark.parametrize("form", [1, 2])
+@pytest.mark.parametrize("form", [1, 2, 3])
 def test_vcycle_stencil_forms_match_oracle(dims, L, form):
     """Both Galerkin-level kernels inside the V-cycle (smoothing, residual and
     restriction epilogues) at FP64, and the LDS-staged one with level 1 in
-    FP32."""
+    FP32; form 3: level 1 from the child moduli of its elements."""
     from paper_2604_26441_amd import simpgmg
     rho = np.random.default_rng(7).uniform(0.1, 1.0, np.prod(dims))
     fixed = workloads.cantilever_fixed(dims).astype(bool)
@@ -71,7 +71,7 @@ def test_vcycle_stencil_forms_match_oracle(dims, L, form):
     simpgmg.vcycle(h, t64(r), z)
     assert rel_err(np64(z), ref, ref) < 1e-5     # FP32 level 1: the FP32 parity tolerance
     with pytest.raises(simpgmg.SimpGmgError, match="stencil_form"):
-        simpgmg.setup_hierarchy(simpgmg.default_options(*dims, n_levels=L, stencil_form=3),
+        simpgmg.setup_hierarchy(simpgmg.default_options(*dims, n_levels=L, stencil_form=4),
                                 t64(rho))
 
 
