@@ -261,7 +261,12 @@ int sgmg_lanczos(sgmg_hierarchy* h, int precond, int m, const double* g, double 
  * ints, may be NULL) receives (rows, planes) for BF16, BF16X3, then FP64;
  * for FP64 the vector-ALU node kernel is a candidate too, reported as (0, 0)
  * (also the FP64 choice of an untuned mesh), and so are the vector-ALU
- * sum-factorised tiles with 2 .. 32 planes, reported as (1, planes).
+ * sum-factorised tiles with 2 .. 32 planes, reported as (1, planes).  When
+ * the hierarchy holds the level-1 element products (stencil_form 0 or 3,
+ * FP64 level 1 above the coarsest) it also times level 1 from the stored
+ * stencil against the products with 2, 4, 8 planes and keeps the faster
+ * (with stencil_form 3 the products stay); that choice is kept in the same
+ * cache (later stencil_form 0 setups of the mesh read it) and not reported.
  * Allocates four temporary vectors and synchronises the stream.  Within one
  * kernel the launch shape changes only which wave computes a node, never the
  * arithmetic: results are bitwise identical.  The three FP64 kernels agree
@@ -272,7 +277,10 @@ int sgmg_autotune(sgmg_hierarchy* h, int* shape_out, void* stream);
  * FP64) on h, e.g. to reuse a shape tuned earlier: rows 4 or 8, planes >= 1;
  * FP64 also accepts (0, 0), the vector-ALU node kernel, and (1, planes >= 1),
  * the vector-ALU kernel with the element product in sum-factorised form.
- * Returns SGMG_EINVAL for other values.  No device work. */
+ * Variant 3 selects how level 1 is applied on a hierarchy that holds its
+ * element products (stencil_form 0 or 3, FP64 level 1 above the coarsest):
+ * (0, any) the stored stencil, (1, planes >= 1) the products.  Returns
+ * SGMG_EINVAL for other values.  No device work. */
 int sgmg_set_launch_shape(sgmg_hierarchy* h, int variant, int rows, int planes);
 
 /* Introspection for tests and reports. */

@@ -49,9 +49,12 @@ void launch_l1_child_moduli(const Grid& fine, const Grid& coarse, const double* 
                             const uint8_t* ffix, double* E8, uint8_t* el_out, hipStream_t s);
 void launch_l1_skip_nodes(const Grid& coarse, const uint8_t* el_out, const uint8_t* cfix,
                           uint8_t* skip, hipStream_t s);
+// One launch: the element products on the tiles and, in extra blocks, the
+// listed rows (Sd, list) from their gathered stencil rows.
 void launch_apply_l1_haar(const Grid& coarse, int zchunk, const double* E8, double lam, double mu,
                           const double* u, const uint8_t* fixn, const uint8_t* skip,
-                          const Epi<double>& ep, hipStream_t s);
+                          const double* Sd, const int* list, int nlist, const Epi<double>& ep,
+                          hipStream_t s);
 bool l1_haar_size_ok(const Grid& coarse);
 void launch_scale_E(const double* E, float* Es, int nel, double inv_s, hipStream_t s);
 void build_mfma_atab(const KeTables& kt, uint16_t* out /* 2 * 64 * 8 */);
@@ -72,10 +75,11 @@ template <typename T>
 void launch_stencil_apply(const Grid& g, const T* S, const T* u, const uint8_t* fixn,
                           const Epi<T>& ep, int form, hipStream_t s);
 size_t stencil_apply_blocks(const Grid& g);
-// The same rows for the listed nodes only.
+// The rows of the listed nodes gathered, once per assembly, into Sd
+// (kStencil x nlist, entry-major) for launch_apply_l1_haar.
 template <typename T>
-void launch_stencil_apply_list(const Grid& g, const T* S, const T* u, const uint8_t* fixn,
-                               const Epi<T>& ep, const int* list, int nlist, hipStream_t s);
+void launch_stencil_gather_rows(const Grid& g, const T* S, const int* list, int nlist, T* Sd,
+                                hipStream_t s);
 // Restriction b_c = M_c P^T r_f; optionally x_c = c0 * Dinv_c * b_c (first
 // smoothing step from zero) and d_c = x_c.
 template <typename TF, typename TC>

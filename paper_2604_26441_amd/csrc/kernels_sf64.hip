@@ -37,6 +37,8 @@
 // - 16 by ds_bpermute.  One halo element on the low side of x and y is
 // recomputed, so the tile owns 15 x 3 nodes per plane; every node sums its
 // eight element contributions in the same order whatever the chunk length.
+#include <algorithm>
+
 #include "batch.hpp"
 #include "bstage.hpp"
 #include "bufops.hpp"
@@ -476,13 +478,47 @@ __global__ __launch_bounds__(64 * kSfWaves) void k_apply_fine_sf64(
                               xcd_block(blockIdx.x, gridDim.x));
 }
 
+// Thread t = (listed node i, component d): the gathered stencil row
+// (Sd[(o * 9 + 3 d + e) * nlist + i]) times the 27 neighbour values, then
+// the epilogue.
+__device__ inline void l1_list_row(const Grid& g, const double* __restrict__ Sd,
+                                   const double* __restrict__ u, const uint8_t* __restrict__ fixn,
+                                   const Epi<double>& ep, const int* __restrict__ list, int nlist,
+                                   int t) {
+  if (t >= 3 * nlist) return;
+  const int i = t / 3, d = t - 3 * i;
+  const int node = list[i];
+  const size_t dof = 3 * (size_t)node + d;
+  const Epi1In<double> ein = epilogue1_load(ep, dof);
+  const unsigned fx = fixn[node];
+  const int x = node % g.Nx, tt = node / g.Nx, y = tt % g.Ny, z = tt / g.Ny;
+  double acc = 0.0;
+#pragma unroll
+  for (int o = 0; o < 27; ++o) {
+    const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+    const bool ok = (unsigned)(x + ox) < (unsigned)g.Nx && (unsigned)(y + oy) < (unsigned)g.Ny &&
+                    (unsigned)(z + oz) < (unsigned)g.Nz;
+    const double* un = u + 3 * (size_t)(ok ? node + ox + g.Nx * (oy + g.Ny * oz) : node);
+    const double* Sb = Sd + ((size_t)o * 9 + 3 * d) * nlist + i;
+    acc += Sb[0] * un[0] + Sb[nlist] * un[1] + Sb[2 * (size_t)nlist] * un[2];
+  }
+  epilogue1(ep, dof, (fx >> d) & 1u, u[dof], acc, ein);
+}
+
+// Blocks [0, nlb): the listed rows; the rest: the element-product tiles.
 template <int MODE>
 __global__ __launch_bounds__(64 * kSfWaves) void k_apply_l1_haar(
     Grid g, const double* __restrict__ E8, SfCoef cf, const double* __restrict__ u,
     const uint8_t* __restrict__ fixn, const uint8_t* __restrict__ skip, Epi<double> ep, int zchunk,
-    int ntx, int nty, int ntiles) {
+    int ntx, int nty, int ntiles, const double* __restrict__ Sd, const int* __restrict__ list,
+    int nlist, int nlb) {
+  if ((int)blockIdx.x < nlb) {                 // uniform over the block
+    l1_list_row(g, Sd, u, fixn, ep, list, nlist, blockIdx.x * 64 * kSfWaves + threadIdx.x);
+    return;
+  }
+  const int nt = gridDim.x - nlb;
   fine_sf64_body<MODE, true>(g, E8, cf, u, fixn, skip, ep, zchunk, ntx, nty, ntiles,
-                             xcd_block(blockIdx.x, gridDim.x));
+                             xcd_block(blockIdx.x - nlb, nt));
 }
 
 // Stage-batched outer q = K p with the p.q block partials: block b is entry
@@ -576,20 +612,20 @@ bool l1_haar_size_ok(const Grid& c) {
 
 void launch_apply_l1_haar(const Grid& c, int zchunk, const double* E8, double lam, double mu,
                           const double* u, const uint8_t* fixn, const uint8_t* skip,
-                          const Epi<double>& ep, hipStream_t s) {
+                          const double* Sd, const int* list, int nlist, const Epi<double>& ep,
+                          hipStream_t s) {
   if (zchunk < 1) zchunk = 1;
   const SfLaunch m = sf_launch(c, zchunk);
   const SfCoef cf = l1_coef(lam, mu);
-  const dim3 grid(m.blocks), block(64 * kSfWaves);
-  if (ep.mode == EPI_STORE)
-    k_apply_l1_haar<EPI_STORE><<<grid, block, 0, s>>>(c, E8, cf, u, fixn, skip, ep, zchunk, m.ntx,
-                                                      m.nty, m.ntiles);
-  else if (ep.mode == EPI_RESID)
-    k_apply_l1_haar<EPI_RESID><<<grid, block, 0, s>>>(c, E8, cf, u, fixn, skip, ep, zchunk, m.ntx,
-                                                      m.nty, m.ntiles);
-  else
-    k_apply_l1_haar<EPI_SMOOTH><<<grid, block, 0, s>>>(c, E8, cf, u, fixn, skip, ep, zchunk, m.ntx,
-                                                       m.nty, m.ntiles);
+  const int nlb = div_up(3 * std::max(nlist, 0), 64 * kSfWaves);
+  const dim3 grid(nlb + m.blocks), block(64 * kSfWaves);
+#define SGMG_L1(M)                                                                          \
+  k_apply_l1_haar<M><<<grid, block, 0, s>>>(c, E8, cf, u, fixn, skip, ep, zchunk, m.ntx, m.nty, \
+                                            m.ntiles, Sd, list, nlist, nlb)
+  if (ep.mode == EPI_STORE) SGMG_L1(EPI_STORE);
+  else if (ep.mode == EPI_RESID) SGMG_L1(EPI_RESID);
+  else SGMG_L1(EPI_SMOOTH);
+#undef SGMG_L1
 }
 
 bool sf64_size_ok(const Grid& g) {

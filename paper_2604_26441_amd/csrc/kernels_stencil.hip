@@ -515,55 +515,42 @@ void bs_stencil_s(const BsArgs& a, const BsTable& t, const int* flags, int l, in
     k_bs_stencil_s<EPI_SMOOTH><<<t.n, 192, 0, s>>>(a.sys, a.items, t.blk, flags, l, cin);
 }
 
-// Listed nodes only (the rows a matrix-free product leaves out): thread per
-// (listed node, component); the 27 blocks of the row are read as in the
-// LDS-staged form (upper half stored at the node, lower half the transposed
-// upper blocks of the neighbour), the neighbour values from memory.
+// Listed nodes only (the rows a matrix-free product leaves out).  Their
+// rows are first gathered, entry-major, into Sd[(o * 9 + 3 d + e) * nlist +
+// i] (the upper blocks from the node, the lower blocks transposed from the
+// neighbour, zero outside the grid), so that the product reads them with
+// consecutive lanes on consecutive listed nodes.
 template <typename T>
-__global__ __launch_bounds__(256) void k_stencil_apply_list(Grid g, const T* __restrict__ S,
-                                                            const T* __restrict__ u,
-                                                            const uint8_t* __restrict__ fixn,
-                                                            Epi<T> ep, const int* __restrict__ list,
-                                                            int nlist) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= 3 * nlist) return;
-  const int node = list[t / 3], d = t - 3 * (t / 3);
-  const size_t dof = 3 * (size_t)node + d;
-  const Epi1In<T> ein = epilogue1_load(ep, dof);
-  const unsigned fx = fixn[node];
-  const int i = node % g.Nx, tt = node / g.Nx, j = tt % g.Ny, k = tt / g.Ny;
-  const size_t Nn = g.Nn;
-  T acc = (T)0;
-#pragma unroll
-  for (int q = 0; q < 27; ++q) {
-    const int o = (q & 1) ? 13 - ((q + 1) >> 1) : 13 + (q >> 1);
-    const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-    const bool ok = (unsigned)(i + ox) < (unsigned)g.Nx && (unsigned)(j + oy) < (unsigned)g.Ny &&
-                    (unsigned)(k + oz) < (unsigned)g.Nz;
-    const int nb = ok ? node + ox + g.Nx * (oy + g.Ny * oz) : node;
-    const T* un = u + 3 * (size_t)nb;
-    T v;
-    if (o >= 13) {
-      const T* Sb = S + ((size_t)o * 9 + 3 * d) * Nn + node;
-      v = Sb[0] * un[0] + Sb[Nn] * un[1] + Sb[2 * Nn] * un[2];
-    } else {
-      const T* Sb = S + ((size_t)(26 - o) * 9 + d) * Nn + nb;
-      v = Sb[0] * un[0] + Sb[3 * Nn] * un[1] + Sb[6 * Nn] * un[2];
-    }
-    acc += ok ? v : (T)0;
+__global__ __launch_bounds__(256) void k_stencil_gather_rows(Grid g, const T* __restrict__ S,
+                                                             const int* __restrict__ list, int nlist,
+                                                             T* __restrict__ Sd) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int q = blockIdx.y;                    // entry (o, d, e) = q
+  if (i >= nlist) return;
+  const int o = q / 9, d = (q / 3) % 3, e = q % 3;
+  const int node = list[i];
+  const int x = node % g.Nx, t = node / g.Nx, y = t % g.Ny, z = t / g.Ny;
+  const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+  const bool ok = (unsigned)(x + ox) < (unsigned)g.Nx && (unsigned)(y + oy) < (unsigned)g.Ny &&
+                  (unsigned)(z + oz) < (unsigned)g.Nz;
+  T v = (T)0;
+  if (ok) {
+    const size_t Nn = g.Nn;
+    const int nb = node + ox + g.Nx * (oy + g.Ny * oz);
+    v = o >= 13 ? S[((size_t)o * 9 + 3 * d + e) * Nn + node]
+                : S[((size_t)(26 - o) * 9 + 3 * e + d) * Nn + nb];
   }
-  epilogue1(ep, dof, (fx >> d) & 1u, u[dof], (double)acc, ein);
+  Sd[(size_t)q * nlist + i] = v;
 }
 
 template <typename T>
-void launch_stencil_apply_list(const Grid& g, const T* S, const T* u, const uint8_t* fixn,
-                               const Epi<T>& ep, const int* list, int nlist, hipStream_t s) {
+void launch_stencil_gather_rows(const Grid& g, const T* S, const int* list, int nlist, T* Sd,
+                                hipStream_t s) {
   if (nlist <= 0) return;
-  k_stencil_apply_list<T><<<div_up(3 * nlist, 256), 256, 0, s>>>(g, S, u, fixn, ep, list, nlist);
+  k_stencil_gather_rows<T><<<dim3(div_up(nlist, 256), kStencil), 256, 0, s>>>(g, S, list, nlist, Sd);
 }
-template void launch_stencil_apply_list<double>(const Grid&, const double*, const double*,
-                                                const uint8_t*, const Epi<double>&, const int*,
-                                                int, hipStream_t);
+template void launch_stencil_gather_rows<double>(const Grid&, const double*, const int*, int,
+                                                 double*, hipStream_t);
 
 // levels with fewer nodes use the plane-split form
 constexpr int kStencilSplitNodes = 40000;

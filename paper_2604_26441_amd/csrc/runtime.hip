@@ -83,6 +83,7 @@ struct sgmg_hierarchy {
   uint8_t* l1_skip = nullptr;
   int* l1_list = nullptr;
   int l1_nlist = 0;
+  double* l1_Sd = nullptr;   // their stencil rows, gathered entry-major
   bool l1_mf = false;        // level-1 applies use it (else the stencil)
   int l1_zchunk = 2;         // its node planes per wave tile
   double maxE_lambda = 0.0;  // max E when lambdas were estimated
@@ -283,10 +284,9 @@ int apply_level<double>(const sgmg_hierarchy* h, int l, sgmg_prec prec, const do
     launch_apply_fine_node<double>(L.g, h->E64, h->ke64, x, L.fixn, ep, s);
   } else if (l == 1 && h->l1_mf && !ep.want_dot) {
     // rows next to Dirichlet DOFs (or odd-axis ends) from the stencil, the
-    // rest from the element products
-    launch_stencil_apply_list<double>(L.g, L.S64, x, L.fixn, ep, h->l1_list, h->l1_nlist, s);
+    // rest from the element products, in one launch
     launch_apply_l1_haar(L.g, h->l1_zchunk, h->l1_E8, h->kt.lam, h->kt.mu, x, L.fixn, h->l1_skip,
-                         ep, s);
+                         h->l1_Sd, h->l1_list, h->l1_nlist, ep, s);
   } else {
     launch_stencil_apply<double>(L.g, L.S64, x, L.fixn, ep,
                                  h->o.stencil_form == 3 ? 0 : h->o.stencil_form, s);
@@ -394,6 +394,9 @@ int assemble_operators(sgmg_hierarchy* h, const double* rho_or_E, hipStream_t s)
   }
   if (h->l1_E8)
     launch_l1_child_moduli(L0.g, h->lev[1].g, h->E64, L0.fixn, h->l1_E8, h->l1_el, s);
+  if (h->l1_Sd)
+    launch_stencil_gather_rows<double>(h->lev[1].g, h->lev[1].S64, h->l1_list, h->l1_nlist,
+                                       h->l1_Sd, s);
   TRY(check_launch());
   // D^-1 with the floor max(D, 1e-30 max D) on free DOFs, 0 on fixed DOFs.
   for (int l = 0; l < h->L; ++l) {
@@ -884,7 +887,7 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
       return fail(rc);
   }
   // level 1 without its stored stencil: FP64 level 1 above the coarsest
-  const bool l1mf = L > 2 && !h->lev[1].f32 && (opts->stencil_form == 3) &&
+  const bool l1mf = L > 2 && !h->lev[1].f32 && (opts->stencil_form == 3 || opts->stencil_form == 0) &&
                     l1_haar_size_ok(h->lev[1].g);
   if (l1mf) {
     const Grid& c1 = h->lev[1].g;
@@ -909,10 +912,21 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
     for (int i = 0; i < c1.Nn; ++i)
       if (sk[i]) list.push_back(i);
     h->l1_nlist = (int)list.size();
-    if ((rc = dalloc_t(h, &h->l1_list, std::max<size_t>(list.size(), 1)))) return fail(rc);
+    if ((rc = dalloc_t(h, &h->l1_list, std::max<size_t>(list.size(), 1))) ||
+        (rc = dalloc_t(h, &h->l1_Sd, (size_t)kStencil * std::max<size_t>(list.size(), 1))))
+      return fail(rc);
     if (!list.empty())
       hipMemcpyAsync(h->l1_list, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice, s);
-    h->l1_mf = true;
+    launch_stencil_gather_rows<double>(c1, h->lev[1].S64, h->l1_list, h->l1_nlist, h->l1_Sd, s);
+    if ((rc = check_launch())) return fail(rc);
+    // form 3 asks for it; with form 0 the autotuner's choice for this mesh
+    // (kept with the launch shapes, key 101), else the stencil
+    h->l1_mf = opts->stencil_form == 3;
+    const auto l1 = tuned_shape(opts->nx, opts->ny, opts->nz, 101, std::make_pair(-1, 0));
+    if (l1.first >= 0) {
+      if (opts->stencil_form == 0) h->l1_mf = l1.first == 1;
+      if (l1.second > 0) h->l1_zchunk = l1.second;
+    }
   }
   if (opts->lambda_override) h->o.lambda_override = opts->lambda_override;
   rc = estimate_lambdas(h, s);
@@ -1548,7 +1562,21 @@ done:
 
 int sgmg_set_launch_shape(sgmg_hierarchy* h, int variant, int rows, int planes) {
   if (!h) { set_error("NULL argument"); return SGMG_EINVAL; }
-  if (variant < 0 || variant > 2) { set_error("variant must be 0 (BF16), 1 (BF16X3) or 2 (FP64)"); return SGMG_EINVAL; }
+  if (variant == 3) {
+    // level 1: rows 0 the stored stencil, rows 1 the element products
+    if (!h->l1_E8 || rows < 0 || rows > 1 || (rows == 1 && planes < 1)) {
+      set_error("level-1 shape must be (0, any) or (1, planes >= 1) on a hierarchy with the "
+                "level-1 element products (FP64 level 1 above the coarsest, stencil_form 0 or 3)");
+      return SGMG_EINVAL;
+    }
+    h->l1_mf = rows == 1;
+    if (rows == 1) h->l1_zchunk = planes;
+    for (auto& row : h->iter_graph)
+      for (auto& g : row)
+        if (g) { hipGraphExecDestroy(g); g = nullptr; }
+    return 0;
+  }
+  if (variant < 0 || variant > 2) { set_error("variant must be 0 (BF16), 1 (BF16X3), 2 (FP64) or 3 (level 1)"); return SGMG_EINVAL; }
   const bool node64 = variant == 2 && rows == 0 && planes == 0;
   const bool sf64 = variant == 2 && rows == 1 && planes >= 1;
   if (!node64 && !sf64 && !mfma_shape_valid(rows, planes)) {
@@ -1781,6 +1809,41 @@ int sgmg_autotune(sgmg_hierarchy* h, int* shape_out, void* stream) {
     if (shape_out) { shape_out[2 * q] = best_r; shape_out[2 * q + 1] = best_z; }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[std::make_tuple(L0.g.nx, L0.g.ny, L0.g.nz, key)] = std::make_pair(best_r, best_z);
+  }
+  // level 1: the stored stencil against the element products (2, 4, 8
+  // planes); with stencil_form 3 the products stay and only their chunk
+  // length is chosen
+  if (!rc && h->l1_E8) {
+    const Level& L1 = h->lev[1];
+    const bool keep_mf = h->o.stencil_form == 3;
+    float best_ms = 1e30f;
+    int best = 0, best_z = h->l1_zchunk;
+    const int zl[] = {0, 2, 4, 8};        // 0: the stencil
+    for (int z : zl) {
+      if (z == 0 && keep_mf) continue;
+      if (z > L1.g.Nz && z != 2) continue;
+      h->l1_mf = z > 0;
+      if (z > 0) h->l1_zchunk = z;
+      for (int w = 0; w < 3 && !rc; ++w)
+        rc = apply_level<double>(h, 1, SGMG_F64, u64, epi_store<double>(y64), s);
+      hipEventRecord(e0, s);
+      for (int r = 0; r < 20 && !rc; ++r)
+        rc = apply_level<double>(h, 1, SGMG_F64, u64, epi_store<double>(y64), s);
+      hipEventRecord(e1, s);
+      if (rc) break;
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        rc = SGMG_EHIP;
+        set_error("autotune sync failed");
+        break;
+      }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best_ms) { best_ms = ms; best = z > 0; best_z = z > 0 ? z : best_z; }
+    }
+    h->l1_mf = best == 1;
+    h->l1_zchunk = best_z;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[std::make_tuple(L0.g.nx, L0.g.ny, L0.g.nz, 101)] = std::make_pair(best, best_z);
   }
   hipStreamSynchronize(s);
   if (u64) hipFree(u64);

@@ -302,13 +302,14 @@ def autotune(h, stream=None):
     return tuple((int(z[2 * q]), int(z[2 * q + 1])) for q in range(3))
 
 
-VARIANTS = {"bf16": 0, "bf16x3": 1, "f64": 2}
+VARIANTS = {"bf16": 0, "bf16x3": 1, "f64": 2, "level1": 3}
 
 
 def set_launch_shape(h, variant, rows, planes):
     """Pin the fine operator's launch shape for variant 'bf16', 'bf16x3' or
     'f64' ((0, 0) selects the FP64 vector-ALU node kernel, (1, planes) the
-    FP64 vector-ALU sum-factorised tile kernel)."""
+    FP64 vector-ALU sum-factorised tile kernel); 'level1' chooses between the
+    stored stencil (0, 0) and the element products (1, planes)."""
     _check(_lib.sgmg_set_launch_shape(h.handle, VARIANTS[variant], rows, planes))
 
 

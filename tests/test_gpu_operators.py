@@ -117,6 +117,23 @@ def test_level1_element_products_with_scattered_dirichlet(dims):
     assert rel_err(np64(y3), K @ u, scale) < 1e-13
     assert rel_err(np64(y3), np64(y0), scale) < 1e-13
     assert np.all(np64(y3)[oh.levels[1].fixed] == 0)
+    # the default form holds the products too; pinning them (any chunk
+    # length) gives the same bits as the form that asks for them
+    for planes in (1, 4):
+        simpgmg.set_launch_shape(h0, "level1", 1, planes)
+        y1 = t64(np.zeros_like(u))
+        simpgmg.apply_K(h0, 1, "f64", t64(u), y1)
+        assert np.array_equal(np64(y1), np64(y3)), planes
+    simpgmg.set_launch_shape(h0, "level1", 0, 0)
+    y1 = t64(np.zeros_like(u))
+    simpgmg.apply_K(h0, 1, "f64", t64(u), y1)
+    assert np.array_equal(np64(y1), np64(y0))
+    with pytest.raises(simpgmg.SimpGmgError):
+        simpgmg.set_launch_shape(h0, "level1", 1, 0)
+    h2 = simpgmg.setup_hierarchy(simpgmg.default_options(*dims, n_levels=3, stencil_form=1),
+                                 t64(rho), fixed_dof=fd)
+    with pytest.raises(simpgmg.SimpGmgError):     # form 1 keeps no element products
+        simpgmg.set_launch_shape(h2, "level1", 1, 2)
 
 
 @pytest.mark.parametrize("dims,L,seed", CASES)
