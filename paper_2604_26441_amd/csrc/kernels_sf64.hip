@@ -231,7 +231,7 @@ __device__ __forceinline__ void l1_element(const double (&F0)[3][2][2], const do
 #pragma unroll
         for (int y = 0; y < 2; ++y) ch[c][x][y][0] += sz * ch[c][x][y][1];
     }
-    haar_op(ch, scaled(k, E8[p]), o);
+    haar_op(ch, k, o);                 // E_p enters with the accumulation below
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
 #pragma unroll
@@ -247,7 +247,8 @@ __device__ __forceinline__ void l1_element(const double (&F0)[3][2][2], const do
 #pragma unroll
         for (int z = 0; z < 2; ++z) o[c][1][y][z] += sx * o[c][0][y][z];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) O[c][i & 1][(i >> 1) & 1][i >> 2] += o[c][i & 1][(i >> 1) & 1][i >> 2];
+      for (int i = 0; i < 8; ++i)
+        O[c][i & 1][(i >> 1) & 1][i >> 2] += E8[p] * o[c][i & 1][(i >> 1) & 1][i >> 2];
     }
   }
   z_bwd(O, P0, P1);
