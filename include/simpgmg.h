@@ -259,9 +259,9 @@ int sgmg_lanczos(sgmg_hierarchy* h, int precond, int m, const double* g, double 
  * keeps the fastest in h and in a process-wide cache keyed by (nx, ny, nz,
  * variant) that later setups of the same mesh read.  shape_out (host, 6
  * ints, may be NULL) receives (rows, planes) for BF16, BF16X3, then FP64;
- * for FP64 the vector-ALU node kernel is a candidate too, reported as (0, 0)
- * (also the FP64 choice of an untuned mesh), and so are the vector-ALU
- * sum-factorised tiles with 2 .. 32 planes, reported as (1, planes).  When
+ * for FP64 the vector-ALU node kernel is a candidate too, reported as (0, 0),
+ * and so are the vector-ALU sum-factorised tiles with 2 .. 32 planes,
+ * reported as (1, planes) ((1, 4) is the FP64 choice of an untuned mesh).  When
  * the hierarchy holds the level-1 element products (stencil_form 0 or 3,
  * FP64 level 1 above the coarsest) it also times level 1 from the stored
  * stencil against the products with 2, 4, 8 planes and keeps the faster

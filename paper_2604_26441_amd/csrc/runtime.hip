@@ -71,8 +71,8 @@ struct sgmg_hierarchy {
   float* E32s = nullptr;     // E / s for the MFMA kernel
   // MFMA launch shape [nsplit == 3]: element rows per wave tile, node planes
   // per wave (tuned per mesh, or the default)
-  int mfma_rows[3] = {4, 4, 0};     // [BF16, BF16X3, FP64]; FP64 rows 0: node kernel
-  int mfma_zchunk[3] = {4, 4, 0};
+  int mfma_rows[3] = {4, 4, 1};     // [BF16, BF16X3, FP64]; FP64 rows 0: node kernel,
+  int mfma_zchunk[3] = {4, 4, 4};   // rows 1: sum/difference-basis tiles
   uint16_t* atab = nullptr;  // MFMA A-operand table (BF16 bits)
   double* atab64 = nullptr;  // FP64 MFMA A-operand table
   // level 1 without its stored stencil (FP64 level 1 above the coarsest):
@@ -718,9 +718,10 @@ int sgmg_setup_hierarchy(const sgmg_options* opts, const double* rho_or_E, const
 
   compute_ke(opts->nu, &h->kt);
   for (int q = 0; q < 3; ++q) {
-    // FP64 defaults to the vector-ALU node kernel (rows 0) until tuned
+    // FP64 defaults to the vector-ALU sum/difference-basis tiles (rows 1, 4
+    // planes) until tuned
     const auto sh = tuned_shape(opts->nx, opts->ny, opts->nz, q == 2 ? 64 : (q ? 3 : 1),
-                                q == 2 ? std::make_pair(0, 0) : std::make_pair(4, 4));
+                                q == 2 ? std::make_pair(1, 4) : std::make_pair(4, 4));
     h->mfma_rows[q] = sh.first;
     h->mfma_zchunk[q] = sh.second;
   }

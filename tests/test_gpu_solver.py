@@ -21,11 +21,13 @@ def _setup(dims, L, rho, fine_prec, fine_smoother=0, lambdas=None, level1_prec="
                                                    ((24, 12, 12), 4, 0, (4, 3)), ((16, 8, 8), 3, 1, (8, 4)),
                                                    ((32, 16, 16), 3, 0, None),
                                                    ((24, 12, 12), 4, 0, (1, 3)), ((16, 8, 8), 3, 1, (1, 2)),
-                                                   ((9, 7, 5), 3, 0, (1, 1))])
+                                                   ((9, 7, 5), 3, 0, (1, 1)), ((24, 12, 12), 4, 0, (0, 0)),
+                                                   ((16, 8, 8), 3, 1, (0, 0))])
 def test_vcycle_f64_matches_oracle(dims, L, smoother, shape):
-    """shape None: FP64 vector-ALU node operator; (rows 4 or 8, planes): the
-    FP64 MFMA fine operator; (1, planes): the FP64 sum-factorised tile
-    operator (residual and smoothing epilogues).  (32, 16, 16) on 3
+    """shape None: the untuned default (the FP64 sum/difference-basis tiles,
+    4 planes); (0, 0): the FP64 vector-ALU node operator; (rows 4 or 8,
+    planes): the FP64 MFMA fine operator; (1, planes): the sum/difference-
+    basis tiles (residual and smoothing epilogues).  (32, 16, 16) on 3
     levels has 600 free coarsest DOFs: ten 64-column Gauss-Jordan panels,
     five 128-row update tiles with a ragged last one."""
     from paper_2604_26441_amd import simpgmg
