@@ -462,6 +462,12 @@ struct Smoother {
   double omega, theta, delta, sigma1;
 };
 
+// Whether the first smoothing step from zero (fused into the PCG update or
+// the cycle entry) must also write its direction d = x_1 for the second
+// step: only when that step stores a direction of its own into d (more than
+// two Chebyshev steps); with two the second step reads x_1 in place of d.
+bool entry_writes_d(const Smoother& sm) { return sm.cheb && sm.steps > 2; }
+
 Smoother smoother_of(const sgmg_hierarchy* h, int l) {
   Smoother sm{};
   const double lam = h->o.lambda_safety * h->lev[l].lam;
@@ -523,8 +529,11 @@ int smooth_and_recurse(const sgmg_hierarchy* h, int l, int* cur, double* out64, 
     // the pass's last direction is never read again (the next pass starts
     // with c1 = 0), so it is not stored
     const int store_d = sm.cheb && k < sm.steps - 1;
+    // the second step from zero reads its direction d = x_1 - 0 from x_1
+    // itself when nothing stores a direction there (entry_writes_d)
+    T* dk = (from_zero && k == 1 && !entry_writes_d(sm)) ? (T*)L.x[c] : d;
     TRY(apply_level<T>(h, l, prec, (const T*)L.x[c],
-                       epi_smooth<T>((T*)L.x[1 - c], b, dinv, d, c1, c2, store_d, nullptr), s));
+                       epi_smooth<T>((T*)L.x[1 - c], b, dinv, dk, c1, c2, store_d, nullptr), s));
     c = 1 - c;
   }
   // residual, restriction, coarse correction
@@ -601,10 +610,10 @@ int vcycle_full(const sgmg_hierarchy* h, const double* r, double* z, hipStream_t
   const double c0 = first_step_coef(sm);
   if (L.f32)
     launch_vcycle_entry<float>(r, (float*)L.b, L.dinv32, c0, (float*)L.x[0],
-                               sm.cheb ? (float*)L.dv : nullptr, L.g.n, s);
+                               entry_writes_d(sm) ? (float*)L.dv : nullptr, L.g.n, s);
   else
     launch_vcycle_entry<double>(r, (double*)L.b, L.dinv64, c0, (double*)L.x[0],
-                                sm.cheb ? (double*)L.dv : nullptr, L.g.n, s);
+                                entry_writes_d(sm) ? (double*)L.dv : nullptr, L.g.n, s);
   TRY(check_launch());
   int cur = 0;
   return vcycle_level(h, 0, &cur, z, true, s);
@@ -1031,12 +1040,12 @@ static int pcg_body(sgmg_hierarchy* h, int precond, int slot, hipStream_t s) {
       launch_pcg_update_xr_entry<float>(xin, xout, h->r, flex ? h->r_old : nullptr, h->p, h->q,
                                         sc, slot, SC_PQ, h->ws.partials, npq, n, ws_rr, nullptr, (float*)L0.b,
                                         L0.dinv32, c0, (float*)L0.x[0],
-                                        sm.cheb ? (float*)L0.dv : nullptr, s);
+                                        entry_writes_d(sm) ? (float*)L0.dv : nullptr, s);
     else
       launch_pcg_update_xr_entry<double>(xin, xout, h->r, flex ? h->r_old : nullptr, h->p, h->q,
                                          sc, slot, SC_PQ, h->ws.partials, npq, n, ws_rr, nullptr, (double*)L0.b,
                                          L0.dinv64, c0, (double*)L0.x[0],
-                                         sm.cheb ? (double*)L0.dv : nullptr, s);
+                                         entry_writes_d(sm) ? (double*)L0.dv : nullptr, s);
     TRY(check_launch());
     int cur = 0;
     if (fuse_rz) h->vc_dot64 = h->r;
