@@ -351,6 +351,30 @@ int sgmg_pcg_solve_batch_staged(sgmg_batch* b, int nitems, const int* item_sys,
                                 const double* const* f, double* const* u, double rtol, int maxit,
                                 sgmg_solve_info* infos, double* total_ms, void* stream);
 
+/* The stage-by-stage solve of sgmg_pcg_solve_batch_staged with the
+ * iteration control on the device, so that one graph launch runs the whole
+ * solve: the launch holds the prologue, a decision kernel (|f|, the first
+ * residual test, u = 0 where f = 0) and steps PCG iterations, each followed
+ * by a decision kernel (breakdown and residual tests), the prologue for the
+ * items whose recursive residual passed (their FP64 true-residual check and
+ * restart) and a second decision kernel (the outcome of the check, the next
+ * iteration's flags); at its end, once no item iterates, the prologue gives
+ * the true residual of the items that stopped without one.  Items that
+ * stopped keep no flag: their blocks return at once.  The tests are those of
+ * the host loop of the staged solve, item by item, so every item's status,
+ * iterations, residuals and u are bitwise those of
+ * sgmg_pcg_solve_batch_staged.  steps: iterations per launch (even, 2..1024);
+ * when an item still iterates after them, a further launch of steps
+ * iterations follows (*launches, may be NULL, receives the number of
+ * launches).  The two graphs (first launch, further launches) are captured
+ * on the first call for an item set, rtol, maxit and steps, and kept.
+ * Arguments otherwise as sgmg_pcg_solve_batch_staged; *total_ms covers all
+ * launches.  Synchronises once per launch. */
+int sgmg_pcg_solve_batch_graph(sgmg_batch* b, int nitems, const int* item_sys,
+                               const double* const* f, double* const* u, double rtol, int maxit,
+                               int steps, sgmg_solve_info* infos, int* launches, double* total_ms,
+                               void* stream);
+
 /* The same items solved by nworkers host threads (1..16), each with a HIP
  * stream of its own: a worker takes whole systems, largest DOFs x load
  * cases first, and solves that system's items in item order with

@@ -77,4 +77,41 @@ void bs_fine_mfma64_store_dot(const BsArgs& a, const BsTable& t, const int4* geo
 void bs_fine_sf64_store_dot(const BsArgs& a, const BsTable& t, const int4* geo, const int* flags,
                             int zchunk, double* part, hipStream_t s);
 
+// Device-side iteration control of the one-launch solve: per item the
+// status (-1 while iterating, else the sgmg_status), the iteration count, |f|,
+// the recurrence and the true relative residual (-1 until computed), a flag
+// for f = 0 (u is then zeroed), and the iteration index in two slots (slot
+// s & 1 is current in step s; the step's last kernel writes the other).
+struct BsLoop {
+  int* status;
+  int* iters;
+  double* nf;
+  double* rel;
+  double* rel_true;
+  int* zero;
+  int* it;
+};
+// Sets every item up for the prologue (flags [0, n) = 1, [n, 2n) = 0).
+void bs_loop_init(int n, int* flags, const BsLoop& lp, hipStream_t s);
+// After the prologue: |f|, the first residual test, the flags of iteration 1.
+void bs_decide_start(int n, const double* scal, int* flags, const BsLoop& lp, double rtol,
+                     int maxit, hipStream_t s);
+// u = 0 for the items with f = 0 (over the level-0 vector table).
+void bs_zero_u(const BsArgs& a, const BsTable& t, const BsLoop& lp, hipStream_t s);
+// After an iteration (step parity cur): breakdown and residual tests; the
+// items whose recurrence residual passed get the prologue flag (the true-
+// residual check and restart).
+void bs_decide_iter(int n, const double* scal, int* flags, const BsLoop& lp, int cur, double rtol,
+                    int maxit, hipStream_t s);
+// After the (flag-gated) prologue: the checked items' outcome, the flags of
+// the next iteration and the next iteration index.
+void bs_decide_check(int n, const double* scal, int* flags, const BsLoop& lp, int cur, double rtol,
+                     int maxit, hipStream_t s);
+// After the last step of a launch: when no item is still iterating, the
+// prologue flag of every item without a true residual; the iteration flags
+// stay set for the next launch (one block).
+void bs_decide_final(int n, int* flags, const BsLoop& lp, hipStream_t s);
+// After that prologue: those items' true relative residual.
+void bs_final_rel(int n, const double* scal, int* flags, const BsLoop& lp, hipStream_t s);
+
 }  // namespace sgmg

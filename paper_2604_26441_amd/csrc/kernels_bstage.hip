@@ -424,4 +424,171 @@ void bs_prolong(const BsArgs& a, const BsTable& t, const int* flags, int l, int 
 int bs_threads() { return kB; }
 int bs_coarse_rows() { return kCoarseRows; }
 
+// ---------------------------------------------------------------------------
+// Device-side iteration control (the one-launch solve).  The tests are those
+// of the host loop of sgmg_pcg_solve_batch_staged, item by item, so that the
+// same stages run for the same items in the same order.
+namespace {
+
+__global__ void k_bs_loop_init(int n, int* __restrict__ flags, BsLoop lp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    lp.it[0] = 1;
+    lp.it[1] = 1;
+  }
+  if (i >= n) return;
+  flags[i] = 1;
+  flags[n + i] = 0;
+  lp.status[i] = -1;
+  lp.iters[i] = 0;
+  lp.nf[i] = 0.0;
+  lp.rel[i] = 0.0;
+  lp.rel_true[i] = -1.0;
+  lp.zero[i] = 0;
+}
+
+__global__ void k_bs_decide_start(int n, const double* __restrict__ scal, int* __restrict__ flags,
+                                  BsLoop lp, double rtol, int maxit) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* sc = scal + (size_t)i * kBsScalars;
+  const double nf = sqrt(sc[kBsFF]);
+  lp.nf[i] = nf;
+  int st = -1;
+  if (nf == 0.0) {                              // f = 0: the solution is u = 0
+    lp.zero[i] = 1;
+    st = SGMG_CONVERGED;
+    lp.rel[i] = 0.0;
+    lp.rel_true[i] = 0.0;
+  } else {
+    const double rel = sqrt(sc[kBsRR]) / nf;
+    lp.rel[i] = rel;
+    const double rz = sc[kBsRZ];
+    if (!isfinite(rel)) st = SGMG_NONFINITE;
+    else if (rel < rtol) { st = SGMG_CONVERGED; lp.rel_true[i] = rel; }
+    else if (maxit == 0) st = SGMG_MAXIT;
+    else if (!isfinite(rz)) st = SGMG_NONFINITE;
+    else if (rz <= 0.0) st = SGMG_BREAKDOWN;
+  }
+  lp.status[i] = st;
+  flags[i] = 0;
+  flags[n + i] = st < 0;
+}
+
+__global__ __launch_bounds__(kB) void k_bs_zero_u(const BItem* __restrict__ items,
+                                                  const BSys* __restrict__ sys,
+                                                  const int2* __restrict__ tab, BsLoop lp) {
+  Slot sl;
+  if (!active_block(tab, lp.zero, sl)) return;
+  const BItem& I = items[sl.item];
+  const size_t i = (size_t)sl.lb * kB + threadIdx.x;
+  if (i < (size_t)sys[I.sys].lev[0].g.n) I.u[i] = 0.0;
+}
+
+__global__ void k_bs_decide_iter(int n, const double* __restrict__ scal, int* __restrict__ flags,
+                                 BsLoop lp, int cur, double rtol, int maxit) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int it = lp.it[cur];
+  int check = 0;
+  if (flags[n + i]) {
+    const double* sc = scal + (size_t)i * kBsScalars;
+    int st = -1, its = it;
+    const double pq = sc[kBsPQ];
+    if (!isfinite(pq)) { st = SGMG_NONFINITE; its = it - 1; }
+    else if (pq <= 0.0) { st = SGMG_BREAKDOWN; its = it - 1; }
+    else {
+      const double rel = sqrt(sc[kBsRR]) / lp.nf[i];
+      lp.rel[i] = rel;
+      const double rz = sc[kBsRZNew];
+      if (!isfinite(rel)) st = SGMG_NONFINITE;
+      else if (rel < rtol) check = 1;             // true-residual check
+      else if (!isfinite(rz)) st = SGMG_NONFINITE;
+      else if (rz <= 0.0) st = SGMG_BREAKDOWN;
+      else if (it == maxit) st = SGMG_MAXIT;
+    }
+    lp.iters[i] = its;
+    lp.status[i] = st;
+  }
+  flags[n + i] = 0;
+  flags[i] = check;
+}
+
+__global__ void k_bs_decide_check(int n, const double* __restrict__ scal, int* __restrict__ flags,
+                                  BsLoop lp, int cur, double rtol, int maxit) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int it = lp.it[cur];
+  if (i == 0) lp.it[cur ^ 1] = it + 1;
+  if (i >= n) return;
+  if (flags[i]) {
+    const double* sc = scal + (size_t)i * kBsScalars;
+    const double rt = sqrt(sc[kBsRR]) / lp.nf[i];
+    int st = -1;
+    if (rt < rtol) {
+      st = SGMG_CONVERGED;
+      lp.rel_true[i] = rt;
+    } else {
+      lp.rel[i] = rt;
+      const double rz = sc[kBsRZ];
+      if (!isfinite(rz)) st = SGMG_NONFINITE;
+      else if (rz <= 0.0) st = SGMG_BREAKDOWN;
+      else if (it == maxit) st = SGMG_MAXIT;
+    }
+    lp.status[i] = st;
+  }
+  flags[i] = 0;
+  flags[n + i] = lp.status[i] < 0;
+}
+
+__global__ __launch_bounds__(256) void k_bs_decide_final(int n, int* __restrict__ flags,
+                                                          BsLoop lp) {
+  __shared__ int active;
+  if (threadIdx.x == 0) active = 0;
+  __syncthreads();
+  int a = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) a |= lp.status[i] < 0;
+  if (a) active = 1;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    flags[i] = !active && lp.rel_true[i] < 0.0;
+    flags[n + i] = lp.status[i] < 0;      // kept for the next launch's first step
+  }
+}
+
+__global__ void k_bs_final_rel(int n, const double* __restrict__ scal, int* __restrict__ flags,
+                               BsLoop lp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !flags[i]) return;
+  const double nf = lp.nf[i];
+  lp.rel_true[i] = sqrt(scal[(size_t)i * kBsScalars + kBsRR]) / (nf > 0.0 ? nf : 1.0);
+  flags[i] = 0;
+}
+
+}  // namespace
+
+void bs_decide_final(int n, int* flags, const BsLoop& lp, hipStream_t s) {
+  k_bs_decide_final<<<1, 256, 0, s>>>(n, flags, lp);
+}
+void bs_final_rel(int n, const double* scal, int* flags, const BsLoop& lp, hipStream_t s) {
+  k_bs_final_rel<<<div_up(n, 256), 256, 0, s>>>(n, scal, flags, lp);
+}
+void bs_loop_init(int n, int* flags, const BsLoop& lp, hipStream_t s) {
+  k_bs_loop_init<<<div_up(n, 256), 256, 0, s>>>(n, flags, lp);
+}
+void bs_decide_start(int n, const double* scal, int* flags, const BsLoop& lp, double rtol,
+                     int maxit, hipStream_t s) {
+  k_bs_decide_start<<<div_up(n, 256), 256, 0, s>>>(n, scal, flags, lp, rtol, maxit);
+}
+void bs_zero_u(const BsArgs& a, const BsTable& t, const BsLoop& lp, hipStream_t s) {
+  if (t.n) k_bs_zero_u<<<t.n, kB, 0, s>>>(a.items, a.sys, t.blk, lp);
+}
+void bs_decide_iter(int n, const double* scal, int* flags, const BsLoop& lp, int cur, double rtol,
+                    int maxit, hipStream_t s) {
+  k_bs_decide_iter<<<div_up(n, 256), 256, 0, s>>>(n, scal, flags, lp, cur, rtol, maxit);
+}
+void bs_decide_check(int n, const double* scal, int* flags, const BsLoop& lp, int cur, double rtol,
+                     int maxit, hipStream_t s) {
+  k_bs_decide_check<<<div_up(n, 256), 256, 0, s>>>(n, scal, flags, lp, cur, rtol, maxit);
+}
+
 }  // namespace sgmg

@@ -2040,6 +2040,16 @@ struct sgmg_batch {
     BsTable tk64;
     const int4* geo64 = nullptr;
     void* m64dmem = nullptr;
+    // one-launch solve: device-side iteration control (arrays in lmem, a
+    // pinned mirror) and the loop graphs: g_first = prologue + decision +
+    // l_steps iterations, g_more = l_steps further iterations
+    BsLoop lp{};
+    void* lmem = nullptr;
+    void* h_lmem = nullptr;
+    size_t lbytes = 0;
+    hipGraphExec_t g_first = nullptr, g_more = nullptr;
+    int l_steps = 0, l_maxit = -1;
+    double l_rtol = -1.0;
   } st;
 };
 
@@ -2054,6 +2064,10 @@ void batch_free_staged(sgmg_batch* b) {
   auto& st = b->st;
   if (st.g_pro) hipGraphExecDestroy(st.g_pro);
   if (st.g_it) hipGraphExecDestroy(st.g_it);
+  if (st.g_first) hipGraphExecDestroy(st.g_first);
+  if (st.g_more) hipGraphExecDestroy(st.g_more);
+  if (st.lmem) hipFree(st.lmem);
+  if (st.h_lmem) hipHostFree(st.h_lmem);
   if (st.dmem) hipFree(st.dmem);
   if (st.mdmem) hipFree(st.mdmem);
   if (st.m64dmem) hipFree(st.m64dmem);
@@ -2269,17 +2283,79 @@ void bs_iteration(const sgmg_batch* b, const BsArgs& a, int n, hipStream_t s) {
   bs_update_p(a, st.tv, fl, st.scal, s);
 }
 
-int bs_capture(sgmg_batch* b, void (*body)(const sgmg_batch*, const BsArgs&, int, hipStream_t),
-               int n, hipGraphExec_t* out) {
+template <class F>
+int bs_capture_fn(sgmg_batch* b, F&& body, hipGraphExec_t* out) {
   if (!b->cap) SGMG_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
   SGMG_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-  body(b, BsArgs{b->d_sys, b->d_items}, n, b->cap);
+  body(BsArgs{b->d_sys, b->d_items}, b->cap);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(b->cap, &g);
   if (e != hipSuccess) { set_error(std::string("staged batch capture: ") + hipGetErrorString(e)); return SGMG_EHIP; }
   const hipError_t e2 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
   if (e2 != hipSuccess) { *out = nullptr; set_error("staged batch graph instantiate failed"); return SGMG_EHIP; }
+  return 0;
+}
+
+int bs_capture(sgmg_batch* b, void (*body)(const sgmg_batch*, const BsArgs&, int, hipStream_t),
+               int n, hipGraphExec_t* out) {
+  return bs_capture_fn(b, [&](const BsArgs& a, hipStream_t s) { body(b, a, n, s); }, out);
+}
+
+// steps PCG iterations under device-side control: after each iteration the
+// decision kernel flags the items whose recurrence residual passed, the
+// prologue (the true-residual check and restart) runs for them, and the
+// second decision sets the next iteration's flags; items that stopped have
+// no flag and their blocks return at once.  The launch ends with the true
+// residual of the items that stopped without one, once no item iterates.
+void bs_loop_steps(const sgmg_batch* b, const BsArgs& a, int n, int steps, double rtol, int maxit,
+                   hipStream_t s) {
+  const auto& st = b->st;
+  for (int k = 0; k < steps; ++k) {
+    bs_iteration(b, a, n, s);
+    bs_decide_iter(n, st.scal, st.flags, st.lp, k & 1, rtol, maxit, s);
+    bs_prologue(b, a, n, s);
+    bs_decide_check(n, st.scal, st.flags, st.lp, k & 1, rtol, maxit, s);
+  }
+  bs_decide_final(n, st.flags, st.lp, s);
+  bs_prologue(b, a, n, s);
+  bs_final_rel(n, st.scal, st.flags, st.lp, s);
+}
+
+// The loop state and the two loop graphs of the one-launch solve (kept while
+// the item set, rtol, maxit and steps stay the same).
+int bs_prepare_loop(sgmg_batch* b, int n, double rtol, int maxit, int steps, hipStream_t s) {
+  auto& st = b->st;
+  if (!st.lmem) {
+    const size_t ib = ((3 * (size_t)n + 2) * sizeof(int) + 255) & ~(size_t)255;
+    st.lbytes = ib + 3 * (size_t)n * sizeof(double);
+    if (hipMalloc(&st.lmem, st.lbytes) != hipSuccess ||
+        hipHostMalloc(&st.h_lmem, st.lbytes, hipHostMallocDefault) != hipSuccess) {
+      set_error("batch loop allocation failed");
+      return SGMG_ENOMEM;
+    }
+    int* ip = (int*)st.lmem;
+    double* dp = (double*)((char*)st.lmem + ib);
+    st.lp = BsLoop{ip, ip + n, dp, dp + n, dp + 2 * n, ip + 2 * n, ip + 3 * n};
+  }
+  if (st.g_first && st.l_steps == steps && st.l_maxit == maxit && st.l_rtol == rtol) return 0;
+  if (st.g_first) hipGraphExecDestroy(st.g_first);
+  if (st.g_more) hipGraphExecDestroy(st.g_more);
+  st.g_first = st.g_more = nullptr;
+  SGMG_HIP(hipStreamSynchronize(s));
+  TRY(bs_capture_fn(b, [&](const BsArgs& a, hipStream_t cs) {
+    bs_loop_init(n, st.flags, st.lp, cs);
+    bs_prologue(b, a, n, cs);
+    bs_decide_start(n, st.scal, st.flags, st.lp, rtol, maxit, cs);
+    bs_zero_u(a, st.tv, st.lp, cs);
+    bs_loop_steps(b, a, n, steps, rtol, maxit, cs);
+  }, &st.g_first));
+  TRY(bs_capture_fn(b, [&](const BsArgs& a, hipStream_t cs) {
+    bs_loop_steps(b, a, n, steps, rtol, maxit, cs);
+  }, &st.g_more));
+  st.l_steps = steps;
+  st.l_maxit = maxit;
+  st.l_rtol = rtol;
   return 0;
 }
 
@@ -2865,6 +2941,79 @@ int sgmg_pcg_solve_batch_staged(sgmg_batch* b, int nitems, const int* item_sys,
       inf.iters = iters[k];
       inf.rel_res_true = rel_true[k];
       inf.rel_res_recur = rel[k];
+      inf.solve_ms = ms;
+      inf.fallback_iter = -1;
+    }
+  }
+  return 0;
+}
+
+int sgmg_pcg_solve_batch_graph(sgmg_batch* b, int nitems, const int* item_sys,
+                               const double* const* f, double* const* u, double rtol, int maxit,
+                               int steps, sgmg_solve_info* infos, int* launches, double* total_ms,
+                               void* stream) {
+  if (!b || nitems < 1 || !item_sys || !f || !u || maxit < 0 || !(rtol > 0.0) || steps < 2 ||
+      steps > 1024 || (steps & 1)) {
+    set_error("bad batch solve arguments");
+    return SGMG_EINVAL;
+  }
+  for (int i = 0; i < nitems; ++i)
+    if (item_sys[i] < 0 || item_sys[i] >= (int)b->hs.size() || !f[i] || !u[i]) {
+      set_error("bad item " + std::to_string(i));
+      return SGMG_EINVAL;
+    }
+  hipStream_t s = as_stream(stream);
+  TRY(batch_prepare_items(b, nitems, item_sys, s));
+  for (int k = 0; k < nitems; ++k) {
+    b->h_items[k].f = f[b->order[k]];
+    b->h_items[k].u = u[b->order[k]];
+  }
+  SGMG_HIP(hipMemcpyAsync(b->d_items, b->h_items.data(), nitems * sizeof(BItem), hipMemcpyHostToDevice, s));
+  TRY(bs_prepare(b, nitems, s));
+  TRY(bs_prepare_loop(b, nitems, rtol, maxit, steps, s));
+  auto& st = b->st;
+  const int n = nitems;
+  const int* hst = (const int*)st.h_lmem;           // the mirror of st.lp
+  const size_t ib = (const char*)st.lp.nf - (const char*)st.lmem;
+  const double* hd = (const double*)((const char*)st.h_lmem + ib);
+  hipEvent_t e0, e1;
+  SGMG_HIP(hipEventCreate(&e0));
+  SGMG_HIP(hipEventCreate(&e1));
+  SGMG_HIP(hipEventRecord(e0, s));
+  // one launch covers steps iterations; another follows only while an item
+  // still iterates after them
+  int nl = 0;
+  for (;;) {
+    const hipError_t e = hipGraphLaunch(nl ? st.g_more : st.g_first, s);
+    if (e != hipSuccess) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      set_error(std::string("batch loop launch: ") + hipGetErrorString(e));
+      return SGMG_EHIP;
+    }
+    ++nl;
+    SGMG_HIP(hipMemcpyAsync(st.h_lmem, st.lmem, st.lbytes, hipMemcpyDeviceToHost, s));
+    SGMG_HIP(hipStreamSynchronize(s));
+    bool active = false;
+    for (int i = 0; i < n; ++i) active = active || hst[i] < 0;
+    if (!active) break;
+  }
+  SGMG_HIP(hipEventRecord(e1, s));
+  SGMG_HIP(hipEventSynchronize(e1));
+  TRY(check_launch());
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = nl;
+  if (infos) {
+    for (int k = 0; k < n; ++k) {
+      sgmg_solve_info& inf = infos[b->order[k]];
+      inf.status = hst[k];
+      inf.iters = hst[n + k];
+      inf.rel_res_true = hd[2 * n + k];
+      inf.rel_res_recur = hd[n + k];
       inf.solve_ms = ms;
       inf.fallback_iter = -1;
     }

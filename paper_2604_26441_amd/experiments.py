@@ -444,6 +444,45 @@ def kernels():
         print(json.dumps(rec), flush=True)
 
 
+def _graph_runs(b, item_sys, ft, sres, steps=128, reps=4):
+    """The staged solve in one graph launch per `steps` iterations (the first
+    run captures the graphs): mean wall time of the later runs, launches, and
+    whether every item's result equals the staged solve's `sres`."""
+    runs, res, nl = [], None, 0
+    for rep in range(reps):
+        us = [torch.zeros_like(f) for f in ft]
+        res, ms, nl = simpgmg.pcg_solve_batch_graph(b, item_sys, ft, us, rtol=1e-6, maxit=300,
+                                                    steps=steps)
+        runs.append(ms)
+    return {"graph_steps": steps, "graph_ms_runs": runs, "graph_ms": float(np.mean(runs[1:])),
+            "graph_launches": nl, "graph_equals_staged": res == sres}
+
+
+def batch_graph():
+    """The 84-item batch (as batch()) with BF16X3 and FP32 fine levels: the
+    staged solve by host loop and in one graph launch."""
+    dev = "cuda:0"
+    dims, rhos, item_sys, fs = workloads.batch_config()
+    ft = [torch.tensor(f, dtype=torch.float64, device=dev) for f in fs]
+    for prec in ("bf16x3", "f32"):
+        opts = [simpgmg.default_options(*d, n_levels=0, dense_max=1000, fine_prec=prec) for d in dims]
+        b = simpgmg.setup_batch(opts, [torch.tensor(r, dtype=torch.float64, device=dev) for r in rhos])
+        rec = {"fine_prec": prec, "n_items": len(item_sys)}
+        sruns = []
+        for rep in range(4):
+            us = [torch.zeros_like(f) for f in ft]
+            sres, ms = simpgmg.pcg_solve_batch(b, item_sys, ft, us, rtol=1e-6, maxit=300, staged=True)
+            sruns.append(ms)
+        rec["staged_ms"] = float(np.mean(sruns[1:]))
+        rec["max_iters"] = max(r["iters"] for r in sres)
+        t0 = time.perf_counter()
+        rec.update(_graph_runs(b, item_sys, ft, sres))
+        rec["graph_wall_s_incl_capture"] = time.perf_counter() - t0
+        rec["max_rel_res_true"] = max(r["rel_res_true"] for r in sres)
+        print(json.dumps(rec), flush=True)
+        b.close()
+
+
 def batch():
     """32 uneven cantilevers (2m x m x m, m in 8..24), random-field rho, p = 3,
     1-4 face load cases each, FP32 smoothing, rtol 1e-6: one persistent launch
@@ -480,6 +519,7 @@ def batch():
     rec["staged_all_converged"] = all(r["status"] == "converged" for r in sres)
     rec["staged_iters"] = [r["iters"] for r in sres]
     rec["staged_max_rel_res_true"] = max(r["rel_res_true"] for r in sres)
+    rec.update(_graph_runs(b, item_sys, ft, sres))
     rec["block_size"] = b.block_size()
     rec["batched_all_converged"] = all(r["status"] == "converged" for r in res)
     rec["batched_iters"] = [r["iters"] for r in res]
@@ -567,6 +607,7 @@ def batch():
     rec2["staged_all_converged"] = all(r["status"] == "converged" for r in sres)
     rec2["staged_iters"] = [r["iters"] for r in sres]
     rec2["staged_max_rel_res_true"] = max(r["rel_res_true"] for r in sres)
+    rec2.update(_graph_runs(b, item_sys, ft, sres))
     hs = [b.hierarchy(q) for q in range(len(dims))]
     tot = []
     for rep in range(2):
@@ -846,7 +887,7 @@ def kuprof(reps=20):
 
 
 if __name__ == "__main__":
-    {"sizes": sizes, "hetero": hetero, "hetero_oracle": hetero_oracle, "large": large, "kernels": kernels, "batch": batch,
+    {"sizes": sizes, "hetero": hetero, "hetero_oracle": hetero_oracle, "large": large, "kernels": kernels, "batch": batch, "batch_graph": batch_graph,
      "e1": e1, "spectral_proxy": spectral_proxy, "robustness": robustness,
      "ablations": ablations, "sensitivity": sensitivity, "simp_schedule": simp_schedule,
      "warmstart": warmstart, "traffic": traffic, "kuprof": kuprof, "batchprof": batchprof,

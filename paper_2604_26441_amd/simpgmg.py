@@ -83,7 +83,7 @@ EXPORTS = [
     "sgmg_vcycle", "sgmg_pcg_solve", "sgmg_fgmres_solve", "sgmg_lanczos", "sgmg_num_levels", "sgmg_level_info",
     "sgmg_copy_stencil", "sgmg_copy_diagonal", "sgmg_destroy", "sgmg_last_error",
     "sgmg_autotune", "sgmg_set_launch_shape", "sgmg_setup_batch", "sgmg_pcg_solve_batch",
-    "sgmg_pcg_solve_batch_staged",
+    "sgmg_pcg_solve_batch_staged", "sgmg_pcg_solve_batch_graph",
     "sgmg_pcg_solve_batch_concurrent", "sgmg_batch_hierarchy",
     "sgmg_batch_block_size", "sgmg_batch_destroy", "sgmg_batch_item_layout",
     "sgmg_unet_create", "sgmg_unet_num_params", "sgmg_unet_set_params", "sgmg_unet_get_params",
@@ -123,6 +123,11 @@ def _load():
                                                 ctypes.POINTER(vp), ctypes.POINTER(vp), d, i,
                                                 ctypes.POINTER(SolveInfo),
                                                 ctypes.POINTER(ctypes.c_double), vp]
+    lib.sgmg_pcg_solve_batch_graph.argtypes = [H, i, ctypes.POINTER(ctypes.c_int),
+                                               ctypes.POINTER(vp), ctypes.POINTER(vp), d, i, i,
+                                               ctypes.POINTER(SolveInfo),
+                                               ctypes.POINTER(ctypes.c_int),
+                                               ctypes.POINTER(ctypes.c_double), vp]
     lib.sgmg_pcg_solve_batch_concurrent.argtypes = [H, i, ctypes.POINTER(ctypes.c_int),
                                                     ctypes.POINTER(vp), ctypes.POINTER(vp), d, i, i,
                                                     ctypes.POINTER(SolveInfo),
@@ -454,6 +459,28 @@ def pcg_solve_batch(batch, item_sys, f_list, u_list, rtol=1e-6, maxit=200, strea
     out = [{"status": STATUS.get(i.status, i.status), "iters": i.iters,
             "rel_res_true": i.rel_res_true, "rel_res_recur": i.rel_res_recur} for i in infos]
     return out, ms.value
+
+
+def pcg_solve_batch_graph(batch, item_sys, f_list, u_list, rtol=1e-6, maxit=200, steps=128,
+                          stream=None):
+    """The staged solve with device-side iteration control (see
+    sgmg_pcg_solve_batch_graph): one graph launch per `steps` iterations;
+    returns (list of dicts, total ms, number of launches)."""
+    m = len(item_sys)
+    sysarr = (ctypes.c_int * m)(*item_sys)
+    fa = (ctypes.c_void_p * m)(*[_ptr(f, torch.float64, 3 * n_nodes(batch.opts[s]), "f").value
+                                 for f, s in zip(f_list, item_sys)])
+    ua = (ctypes.c_void_p * m)(*[_ptr(u, torch.float64, 3 * n_nodes(batch.opts[s]), "u").value
+                                 for u, s in zip(u_list, item_sys)])
+    infos = (SolveInfo * m)()
+    ms = ctypes.c_double()
+    nl = ctypes.c_int()
+    _check(_lib.sgmg_pcg_solve_batch_graph(batch.handle, m, sysarr, fa, ua, rtol, maxit, steps,
+                                           infos, ctypes.byref(nl), ctypes.byref(ms),
+                                           _stream(stream)))
+    out = [{"status": STATUS.get(i.status, i.status), "iters": i.iters,
+            "rel_res_true": i.rel_res_true, "rel_res_recur": i.rel_res_recur} for i in infos]
+    return out, ms.value, nl.value
 
 
 def pcg_solve_batch_concurrent(batch, item_sys, f_list, u_list, rtol=1e-6, maxit=200, workers=4,

@@ -117,7 +117,8 @@ def test_batch_config3_every_item_meets_the_oracle():
     48 x 24 x 24 system; random-field rho, p = 3; 1-4 random face loads each):
     one persistent launch, the concurrent and the stage-batched solves (FP32
     fine levels), and the stage-batched solve with BF16X3 fine levels on the
-    matrix cores; every item converged with the oracle's FP64 true residual of
+    matrix cores, by host loop and in one graph launch (bitwise equal); every
+    item converged with the oracle's FP64 true residual of
     its u below rtol (matrix-free element loop of the oracle)."""
     from paper_2604_26441_amd import simpgmg
     dims, rhos, item_sys, fs = workloads.batch_config()
@@ -139,11 +140,18 @@ def test_batch_config3_every_item_meets_the_oracle():
     um = [t64(np.zeros_like(f)) for f in fs]
     resm, _ = simpgmg.pcg_solve_batch(b, item_sys, [t64(f) for f in fs], um, rtol=1e-6, maxit=300,
                                       staged=True)
+    # and in one graph launch (iteration control on the device): bitwise the staged solve
+    uq = [t64(np.zeros_like(f)) for f in fs]
+    resq, _, nl = simpgmg.pcg_solve_batch_graph(b, item_sys, [t64(f) for f in fs], uq, rtol=1e-6,
+                                                maxit=300, steps=128)
+    assert nl == 1
+    _same_results(resm, um, resq, uq)
     for i, (s, f) in enumerate(zip(item_sys, fs)):
         d = dims[s]
         fixed = workloads.cantilever_fixed(d).astype(bool)
         E = mesh.simp_modulus(rhos[s], 3)
-        for r, u in ((res[i], us[i]), (resc[i], uc[i]), (resg[i], ug[i]), (resm[i], um[i])):
+        for r, u in ((res[i], us[i]), (resc[i], uc[i]), (resg[i], ug[i]), (resm[i], um[i]),
+                     (resq[i], uq[i])):
             assert r["status"] == "converged", (i, d, r)
             x = np64(u)
             rel = np.linalg.norm(f - mesh.apply_K_elementwise(d, E, x, fixed=fixed)) / np.linalg.norm(f)
@@ -255,3 +263,87 @@ def test_staged_batch_edge_cases():
     for kw in ({"maxit": -1}, {"rtol": 0.0}):
         with pytest.raises(simpgmg.SimpGmgError):
             simpgmg.pcg_solve_batch(b, [0, 1], [t64(f0), t64(f1)], us, staged=True, **kw)
+
+
+def _graph_case(dims, seed, prec):
+    from paper_2604_26441_amd import simpgmg
+    rhos = [workloads.grf_rho(d, seed=seed + i) for i, d in enumerate(dims)]
+    opts = [simpgmg.default_options(*d, n_levels=0, dense_max=1000, fine_prec=prec) for d in dims]
+    b = simpgmg.setup_batch(opts, [t64(r) for r in rhos])
+    rng = np.random.default_rng(seed)
+    item_sys, fs = [], []
+    for s, d in enumerate(dims):
+        for k in range(1 + s % 3):
+            item_sys.append(s)
+            fs.append(workloads.random_face_load(d, rng) if k else workloads.edge_load(d))
+    return b, rhos, item_sys, fs
+
+
+def _same_results(ra, ua, rb, ub):
+    for i in range(len(ra)):
+        assert ra[i] == rb[i], (i, ra[i], rb[i])
+        assert np.array_equal(np64(ua[i]), np64(ub[i])), i
+
+
+def test_graph_batch_bitwise_equals_staged_and_passes_oracle():
+    """The one-launch solve (iteration control on the device) takes the same
+    decisions as the staged solve's host loop, item by item, so every item's
+    status, iterations, residuals and u are bitwise equal to the staged
+    solve's; with 128 steps per launch the whole solve is one launch, with 4
+    steps it takes several and stays bitwise equal.  The oracle's FP64 true
+    residual of every returned u is below rtol and equal to the reported one.
+    BF16X3 fine levels (MFMA level 0) on odd and ragged meshes, 1-3 load
+    cases per system."""
+    from paper_2604_26441_amd import simpgmg
+    dims = [(16, 8, 8), (20, 10, 10), (12, 6, 6), (30, 14, 14), (22, 12, 10)]
+    b, rhos, item_sys, fs = _graph_case(dims, 500, "bf16x3")
+    ft = [t64(f) for f in fs]
+    us = [t64(np.zeros_like(f)) for f in fs]
+    rs, _ = simpgmg.pcg_solve_batch(b, item_sys, ft, us, rtol=1e-6, maxit=300, staged=True)
+    assert all(r["status"] == "converged" for r in rs)
+    its = max(r["iters"] for r in rs)
+    assert 4 < its <= 128
+    for steps in (128, 4, 128):
+        ug = [t64(np.zeros_like(f)) for f in fs]
+        rg, ms, nl = simpgmg.pcg_solve_batch_graph(b, item_sys, ft, ug, rtol=1e-6, maxit=300,
+                                                   steps=steps)
+        assert ms > 0 and nl == -(-its // steps), (steps, nl, its)
+        _same_results(rs, us, rg, ug)
+    for i, (s, f) in enumerate(zip(item_sys, fs)):
+        d = dims[s]
+        fixed = workloads.cantilever_fixed(d).astype(bool)
+        x = np64(ug[i])
+        Kx = mesh.apply_K_elementwise(d, mesh.simp_modulus(rhos[s], 3), x, fixed=fixed)
+        rel = np.linalg.norm(f - Kx) / np.linalg.norm(f)
+        assert rel < 1e-6 and abs(rel - rg[i]["rel_res_true"]) < 1e-9, (i, rel, rg[i])
+
+
+def test_graph_batch_edge_cases_match_staged():
+    """Zero right-hand side (u = 0), a start at the solution (converged at
+    iteration 0), maxit 0, a maxit that stops the items mid-solve (status
+    maxit, the true residual from the final prologue) over several launches:
+    each bitwise equal to the staged solve; argument checks on steps."""
+    from paper_2604_26441_amd import simpgmg
+    dims = [(16, 8, 8), (20, 10, 10)]
+    b, rhos, _, _ = _graph_case(dims, 100, "f32")
+    f0 = workloads.edge_load(dims[0])
+    f1 = workloads.edge_load(dims[1])
+    u1 = t64(np.zeros_like(f1))
+    simpgmg.pcg_solve(b.hierarchy(1), t64(f1), u1, rtol=1e-10, maxit=300)
+    start0 = np.ones_like(f0) * (1 - workloads.cantilever_fixed(dims[0]))
+    cases = [([np.zeros_like(f0), f1], [start0, np64(u1)], {"rtol": 1e-6}),
+             ([f0, f1], [np.zeros_like(f0), np.zeros_like(f1)], {"rtol": 1e-6, "maxit": 0}),
+             ([f0, f1], [np.zeros_like(f0), np.zeros_like(f1)], {"rtol": 1e-12, "maxit": 5})]
+    for fs, u0, kw in cases:
+        ft = [t64(f) for f in fs]
+        us = [t64(u.copy()) for u in u0]
+        rs, _ = simpgmg.pcg_solve_batch(b, [0, 1], ft, us, staged=True, **kw)
+        ug = [t64(u.copy()) for u in u0]
+        rg, _, nl = simpgmg.pcg_solve_batch_graph(b, [0, 1], ft, ug, steps=2, **kw)
+        _same_results(rs, us, rg, ug)
+        assert nl == (3 if kw.get("maxit") == 5 else 1), (kw, nl)
+    assert rg[0]["status"] == rg[1]["status"] == "maxit" and rg[0]["iters"] == 5
+    assert rg[0]["rel_res_true"] > 1e-12
+    for steps in (0, 3, 1026):
+        with pytest.raises(simpgmg.SimpGmgError):
+            simpgmg.pcg_solve_batch_graph(b, [0, 1], ft, ug, steps=steps)
