@@ -6,6 +6,7 @@ namespace sgmg {
 
 constexpr int kVecBlock = 256;
 constexpr int kVecGrid = 1024;  // grid-stride: fixed grid -> fixed summation order
+constexpr int kVecUnroll = 8;   // elements per thread loaded together
 
 // SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): output i of the stream with
 // seed s is the variant-13 finaliser of s + (i+1) * golden.  Mapped to
@@ -196,21 +197,29 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(const double* x_in,
                                                              const double* __restrict__ pq_part,
                                                              int npq, int n, RedWs ws,
                                                              VEntry<T> e) {
-  // The first element's operands are loaded before the p.q partials are
-  // summed (that sum is a memory round trip of its own).
+  // A thread's elements are i0 + k stride; their operands are loaded kVecUnroll
+  // at a time before any is used (one memory round trip per group instead of
+  // one per element), the first group before the p.q partials are summed
+  // (that sum is a memory round trip of its own).
   const int i0 = blockIdx.x * kVecBlock + threadIdx.x;
   const int stride = gridDim.x * kVecBlock;
-  const bool has0 = i0 < n;
-  double r0 = 0.0, x0 = 0.0, p0 = 0.0, q0 = 0.0;
-  T d0 = (T)0;
+  double rg[kVecUnroll], xg[kVecUnroll], pg[kVecUnroll], qg[kVecUnroll];
+  T dg[kVecUnroll];
+  auto load = [&](int base) {
+#pragma unroll
+    for (int k = 0; k < kVecUnroll; ++k) {
+      const int i = base + k * stride;
+      if (i < n) {
+        rg[k] = r[i];
+        xg[k] = x_in[i];
+        pg[k] = p[i];
+        qg[k] = q[i];
+        dg[k] = e.b ? e.dinv[i] : (T)0;
+      }
+    }
+  };
   const double rz = sc[slot_rz];
-  if (has0) {
-    r0 = r[i0];
-    x0 = x_in[i0];
-    p0 = p[i0];
-    q0 = q[i0];
-    if (e.b) d0 = e.dinv[i0];
-  }
+  load(i0);
   // p.q: from sc, or summed here from the K p kernel's block partials by
   // every block in the same order (block 0 also stores it in sc)
   double pq;
@@ -218,6 +227,8 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(const double* x_in,
     __shared__ double lds[16];
     __shared__ double tot;
     double a = 0.0;
+    // unrolled so that the loads go out together; the adds keep their order
+#pragma unroll 8
     for (int i = threadIdx.x; i < npq; i += kVecBlock) a += pq_part[i];
     a = block_sum(a, lds);
     if (threadIdx.x == 0) {
@@ -252,9 +263,14 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_xr(const double* x_in,
       if (e.d) e.d[i] = xv;
     }
   };
-  if (has0) element(i0, r0, x0, p0, q0, d0);
-  for (int i = i0 + stride; i < n; i += stride)
-    element(i, r[i], x_in[i], p[i], q[i], e.b ? e.dinv[i] : (T)0);
+  for (int base = i0; base < n; base += kVecUnroll * stride) {
+    if (base != i0) load(base);
+#pragma unroll
+    for (int k = 0; k < kVecUnroll; ++k) {
+      const int i = base + k * stride;
+      if (i < n) element(i, rg[k], xg[k], pg[k], qg[k], dg[k]);
+    }
+  }
   const double v[1] = {rr};
   grid_sum<1>(v, ws);
 }
@@ -321,21 +337,32 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_p_red(
     int slot_den, int slot_rr, int slot_pq, int slot_seq, double* host, double* host_seq, int n) {
   __shared__ double lds[3][16];
   __shared__ double tot[3];
-  // the first element's operands are loaded before the partial sums
+  // the operands of a thread's elements are loaded kVecUnroll at a time, the
+  // first group before the partial sums
   const int i0 = blockIdx.x * kVecBlock + threadIdx.x;
   const int stride = gridDim.x * kVecBlock;
-  double z0 = 0.0, p0 = 0.0;
+  double zg[kVecUnroll], pg[kVecUnroll];
+  auto load = [&](int base) {
+#pragma unroll
+    for (int k = 0; k < kVecUnroll; ++k) {
+      const int i = base + k * stride;
+      if (i < n) {
+        zg[k] = z[i];
+        pg[k] = p[i];
+      }
+    }
+  };
   const double den = sc[slot_den];     // written by the previous iteration
-  if (i0 < n) {
-    z0 = z[i0];
-    p0 = p[i0];
-  }
+  load(i0);
   double a = 0.0, b = 0.0, c = 0.0;
+  // unrolled so that the loads go out together; the adds keep their order
+#pragma unroll 8
   for (int i = threadIdx.x; i < nrz; i += kVecBlock) {
     a += rz_part[i];
     if (flex) b += rz_part[nrz + i];
   }
   if (blockIdx.x == 0)
+#pragma unroll 8
     for (int i = threadIdx.x; i < nb; i += kVecBlock) c += rr_part[i];
   a = block_sum(a, lds[0]);
   b = block_sum(b, lds[1]);
@@ -365,8 +392,14 @@ __global__ __launch_bounds__(kVecBlock) void k_pcg_update_p_red(
   }
   __syncthreads();
   const double beta = (tot[0] - (flex ? tot[1] : 0.0)) / den;
-  if (i0 < n) p[i0] = z0 + beta * p0;
-  for (int i = i0 + stride; i < n; i += stride) p[i] = z[i] + beta * p[i];
+  for (int base = i0; base < n; base += kVecUnroll * stride) {
+    if (base != i0) load(base);
+#pragma unroll
+    for (int k = 0; k < kVecUnroll; ++k) {
+      const int i = base + k * stride;
+      if (i < n) p[i] = zg[k] + beta * pg[k];
+    }
+  }
 }
 
 void launch_pcg_update_p_red(double* p, const double* z, const double* rz_part, int nrz,

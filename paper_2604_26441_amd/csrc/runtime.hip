@@ -1820,7 +1820,7 @@ int sgmg_autotune(sgmg_hierarchy* h, int* shape_out, void* stream) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[std::make_tuple(L0.g.nx, L0.g.ny, L0.g.nz, key)] = std::make_pair(best_r, best_z);
   }
-  // level 1: the stored stencil against the element products (2, 4, 8
+  // level 1: the stored stencil against the element products (1, 2, 4, 8
   // planes); with stencil_form 3 the products stay and only their chunk
   // length is chosen
   if (!rc && h->l1_E8) {
@@ -1828,7 +1828,7 @@ int sgmg_autotune(sgmg_hierarchy* h, int* shape_out, void* stream) {
     const bool keep_mf = h->o.stencil_form == 3;
     float best_ms = 1e30f;
     int best = 0, best_z = h->l1_zchunk;
-    const int zl[] = {0, 2, 4, 8};        // 0: the stencil
+    const int zl[] = {0, 1, 2, 4, 8};     // 0: the stencil
     for (int z : zl) {
       if (z == 0 && keep_mf) continue;
       if (z > L1.g.Nz && z != 2) continue;

@@ -458,13 +458,13 @@ def _graph_runs(b, item_sys, ft, sres, steps=128, reps=4):
             "graph_launches": nl, "graph_equals_staged": res == sres}
 
 
-def batch_graph():
+def batch_graph(precs=("bf16x3", "f32"), steps=128):
     """The 84-item batch (as batch()) with BF16X3 and FP32 fine levels: the
-    staged solve by host loop and in one graph launch."""
+    staged solve by host loop and in one graph launch of `steps` steps."""
     dev = "cuda:0"
     dims, rhos, item_sys, fs = workloads.batch_config()
     ft = [torch.tensor(f, dtype=torch.float64, device=dev) for f in fs]
-    for prec in ("bf16x3", "f32"):
+    for prec in precs:
         opts = [simpgmg.default_options(*d, n_levels=0, dense_max=1000, fine_prec=prec) for d in dims]
         b = simpgmg.setup_batch(opts, [torch.tensor(r, dtype=torch.float64, device=dev) for r in rhos])
         rec = {"fine_prec": prec, "n_items": len(item_sys)}
@@ -476,7 +476,7 @@ def batch_graph():
         rec["staged_ms"] = float(np.mean(sruns[1:]))
         rec["max_iters"] = max(r["iters"] for r in sres)
         t0 = time.perf_counter()
-        rec.update(_graph_runs(b, item_sys, ft, sres))
+        rec.update(_graph_runs(b, item_sys, ft, sres, steps=steps))
         rec["graph_wall_s_incl_capture"] = time.perf_counter() - t0
         rec["max_rel_res_true"] = max(r["rel_res_true"] for r in sres)
         print(json.dumps(rec), flush=True)
@@ -887,6 +887,9 @@ def kuprof(reps=20):
 
 
 if __name__ == "__main__":
+    if len(sys.argv) > 2 and sys.argv[1] == "batch_graph":     # batch_graph PRECS [STEPS]
+        batch_graph(tuple(sys.argv[2].split(",")), int(sys.argv[3]) if len(sys.argv) > 3 else 128)
+        sys.exit(0)
     {"sizes": sizes, "hetero": hetero, "hetero_oracle": hetero_oracle, "large": large, "kernels": kernels, "batch": batch, "batch_graph": batch_graph,
      "e1": e1, "spectral_proxy": spectral_proxy, "robustness": robustness,
      "ablations": ablations, "sensitivity": sensitivity, "simp_schedule": simp_schedule,

@@ -1,6 +1,6 @@
 """Summarise a rocprofv3 kernel-trace database (rocpd SQLite) as Markdown.
 
-  python -m paper_2604_26441_amd.profsummary RESULTS_DB [--match NAME --last N] [--solve]
+  python -m paper_2604_26441_amd.profsummary RESULTS_DB [--match NAME --last N] [--solve] [--loop]
   python -m paper_2604_26441_amd.profsummary --counters COUNTER_CSV
   python -m paper_2604_26441_amd.profsummary --traffic FETCH_CSV WRITE_CSV
   python -m paper_2604_26441_amd.profsummary --kuprof FETCH_CSV WRITE_CSV SQ_CSV
@@ -12,6 +12,7 @@ With --solve, also the kernels of the last PCG solve in the trace (from its
 k_pcg_init dispatch up to the first later dispatch that is not the
 library's, a new k_pcg_init, or a STORE-mode K.u timing launch):
 their count, kernel time and first-start to last-end span, per kernel.
+With --loop, the same for the last one-launch batch solve, step by step.
 With --counters, reads a rocprofv3 --pmc CSV (counter_collection.csv) and
 prints, per kernel, the dispatch count and the mean of each counter.
 """
@@ -124,7 +125,7 @@ def counters(path):
         print(f"| `{name}` | {nd} | " + " | ".join(f"{v:.1f}" for v in vals) + " |")
 
 
-def last_solve(c):
+def last_solve(c, marker="k_apply_fine_sf64<3>"):
     rows = list(c.execute("select name, start, end from kernels order by start"))
     starts = [i for i, r in enumerate(rows) if "k_pcg_init" in r[0]]
     if not starts:
@@ -153,6 +154,47 @@ def last_solve(c):
     print("|---|---|---|---|---|")
     for k, (n, t) in sorted(tot.items(), key=lambda kv: -kv[1][1]):
         print(f"| `{k}` | {n} | {t / 1e3:.1f} | {t / n / 1e3:.2f} | {100 * t / busy:.1f}% |")
+    # per PCG iteration: the kernel time from one outer K p dispatch (marker)
+    # to the next; the last one runs to the end of the solve and also holds
+    # the final true-residual check
+    kp = [i for i, r in enumerate(seg) if marker in r[0]]
+    if len(kp) > 1:
+        its = [sum(e - s for _, s, e in seg[a:b]) / 1e3 for a, b in zip(kp, kp[1:])]
+        print(f"\nKernel time per PCG iteration (from one `{_short(marker)}` dispatch to the next): "
+              + ", ".join(f"{x:.1f}" for x in its) + f" us; mean {sum(its) / len(its):.1f} us. "
+              f"Before the first: {sum(e - s for _, s, e in seg[:kp[0]]) / 1e3:.1f} us; "
+              f"from the last to the end: {sum(e - s for _, s, e in seg[kp[-1]:]) / 1e3:.1f} us.")
+
+
+def last_loop(c, every=10):
+    """The last one-launch batch solve in the trace (from its k_bs_loop_init
+    to the k_bs_final_rel that ends the launch): kernel count, kernel time
+    and span, then per PCG step (the dispatches up to and including that
+    step's k_bs_decide_check) the dispatch count, kernel time and span for
+    every `every`-th step and the last one."""
+    rows = list(c.execute("select name, start, end from kernels order by start"))
+    starts = [i for i, r in enumerate(rows) if "k_bs_loop_init" in r[0]]
+    if not starts:
+        return
+    seg = rows[starts[-1]:]
+    ends = [i for i, r in enumerate(seg) if "k_bs_final_rel" in r[0]]
+    seg = seg[:ends[0] + 1]
+    busy = sum(e - s for _, s, e in seg)
+    print(f"\nLast one-launch solve: {len(seg)} kernels, {busy / 1e3:.0f} us of kernel time in "
+          f"{(seg[-1][2] - seg[0][1]) / 1e3:.0f} us from the first kernel's start to the last "
+          "one's end.\n")
+    cuts = [i for i, r in enumerate(seg) if "k_bs_decide_check" in r[0]]
+    first = [i for i, r in enumerate(seg) if "k_bs_decide_start" in r[0]][0]
+    bounds = [first] + cuts
+    print("| step | dispatches | kernel time (us) | span (us) | mean dispatch (us) |")
+    print("|---|---|---|---|---|")
+    for k in range(1, len(bounds)):
+        if k % every and k != 1 and k != len(bounds) - 1:
+            continue
+        st = seg[bounds[k - 1] + 1:bounds[k] + 1]
+        kt = sum(e - s for _, s, e in st)
+        print(f"| {k} | {len(st)} | {kt / 1e3:.1f} | {(st[-1][2] - st[0][1]) / 1e3:.1f} | "
+              f"{kt / len(st) / 1e3:.2f} |")
 
 
 def main():
@@ -166,6 +208,7 @@ def main():
     ap.add_argument("--last", type=int, default=200)
     ap.add_argument("--top", type=int, default=25)
     ap.add_argument("--solve", action="store_true")
+    ap.add_argument("--loop", action="store_true")
     a = ap.parse_args()
     if a.counters:
         counters(a.counters)
@@ -188,6 +231,8 @@ def main():
         print(f"| `{short}` | {calls} | {tot / 1e3:.3f} | {avg:.3f} | {pct:.1f}% |")
     if a.solve:
         last_solve(c)
+    if a.loop:
+        last_loop(c)
     if a.match:
         durs = [r[0] for r in c.execute(
             "select duration from kernels where name like ? order by start", (f"%{a.match}%",))]
