@@ -253,8 +253,8 @@ int sgmg_lanczos(sgmg_hierarchy* h, int precond, int m, const double* g, double 
                  double* alpha, double* beta, int* steps, double* ritz, void* stream);
 
 /* Autotuner of the fine operators' launch shape: times each candidate
- * (element rows per wave tile: 4, 8; owned node planes per wave: 2, 4, 8,
- * 16, 32) on this hierarchy's mesh for the BF16, BF16X3 and FP64 kernels
+ * (element rows per wave tile: 4, 8; owned node planes per wave: 2, 3, 4,
+ * 6, 8, 16, 32) on this hierarchy's mesh for the BF16, BF16X3 and FP64 kernels
  * (the BF16 family in the smoothing epilogue, FP64 as a plain product),
  * keeps the fastest in h and in a process-wide cache keyed by (nx, ny, nz,
  * variant) that later setups of the same mesh read.  shape_out (host, 6
@@ -264,7 +264,7 @@ int sgmg_lanczos(sgmg_hierarchy* h, int precond, int m, const double* g, double 
  * reported as (1, planes) ((1, 4) is the FP64 choice of an untuned mesh).  When
  * the hierarchy holds the level-1 element products (stencil_form 0 or 3,
  * FP64 level 1 above the coarsest) it also times level 1 from the stored
- * stencil against the products with 1, 2, 4, 8 planes and keeps the faster
+ * stencil against the products with 1 to 6 and 8 planes and keeps the faster
  * (with stencil_form 3 the products stay); that choice is kept in the same
  * cache (later stencil_form 0 setups of the mesh read it) and not reported.
  * Allocates four temporary vectors and synchronises the stream.  Within one

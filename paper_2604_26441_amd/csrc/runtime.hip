@@ -1728,7 +1728,7 @@ int sgmg_autotune(sgmg_hierarchy* h, int* shape_out, void* stream) {
   hipEventCreate(&e0);
   hipEventCreate(&e1);
   const int rows_c[] = {4, 8};
-  const int z_c[] = {2, 4, 8, 16, 32};
+  const int z_c[] = {2, 3, 4, 6, 8, 16, 32};
   double* u64 = nullptr;
   double* y64 = nullptr;
   int rc = 0;
@@ -1820,15 +1820,15 @@ int sgmg_autotune(sgmg_hierarchy* h, int* shape_out, void* stream) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[std::make_tuple(L0.g.nx, L0.g.ny, L0.g.nz, key)] = std::make_pair(best_r, best_z);
   }
-  // level 1: the stored stencil against the element products (1, 2, 4, 8
-  // planes); with stencil_form 3 the products stay and only their chunk
+  // level 1: the stored stencil against the element products (1 to 6 and
+  // 8 planes); with stencil_form 3 the products stay and only their chunk
   // length is chosen
   if (!rc && h->l1_E8) {
     const Level& L1 = h->lev[1];
     const bool keep_mf = h->o.stencil_form == 3;
     float best_ms = 1e30f;
     int best = 0, best_z = h->l1_zchunk;
-    const int zl[] = {0, 1, 2, 4, 8};     // 0: the stencil
+    const int zl[] = {0, 1, 2, 3, 4, 5, 6, 8};   // 0: the stencil
     for (int z : zl) {
       if (z == 0 && keep_mf) continue;
       if (z > L1.g.Nz && z != 2) continue;

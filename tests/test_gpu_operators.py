@@ -224,6 +224,28 @@ def test_sf64_chunk_length_keeps_results_bitwise():
     assert rel_err(out[0], K @ u, abs(K) @ np.abs(u)) < 1e-13
 
 
+def test_bf16_family_chunk_lengths_keep_results_bitwise():
+    """BF16 and BF16X3 MFMA tiles: every candidate chunk length of the
+    autotuner, odd ones included (3 planes; 6 against a mesh of 20 node
+    planes leaves a short last chunk), gives the bits of the default shape:
+    a chunk moves work between waves only."""
+    from paper_2604_26441_amd import simpgmg
+    dims = (31, 6, 19)
+    rho, fixed = _inputs(dims, 21)
+    h = _gpu_h(dims, 2, rho)
+    u = t32(workloads.random_vector(fixed.size, 22, fixed))
+    for prec in ("bf16", "bf16x3"):
+        ref = None
+        for rows in (4, 8):
+            for planes in (2, 3, 4, 6, 8, 16, 32):
+                simpgmg.set_launch_shape(h, prec, rows, planes)
+                y = t32(np.zeros(fixed.size))
+                simpgmg.apply_K(h, 0, prec, u, y)
+                if ref is None:
+                    ref = np64(y)
+                assert np.array_equal(np64(y), ref), (prec, rows, planes)
+
+
 def test_autotune_keeps_results_bitwise():
     """The tuned launch shape moves work between workgroups only."""
     from paper_2604_26441_amd import simpgmg
@@ -239,8 +261,9 @@ def test_autotune_keeps_results_bitwise():
         simpgmg.apply_K(h, 0, prec, u64 if prec == "f64" else u, y)
         before[prec] = np64(y)
     z = simpgmg.autotune(h)
-    assert all(r in (4, 8) and p in (2, 4, 8, 16, 32) for r, p in z[:2])
-    assert z[2] == (0, 0) or (z[2][0] in (1, 4, 8) and z[2][1] in (2, 4, 8, 16, 32))
+    zc = (2, 3, 4, 6, 8, 16, 32)
+    assert all(r in (4, 8) and p in zc for r, p in z[:2])
+    assert z[2] == (0, 0) or (z[2][0] in (1, 4, 8) and z[2][1] in zc)
     if z[2][0] in (0, 1):                   # the tuner chose a vector-ALU kernel:
         simpgmg.set_launch_shape(h, "f64", 8, 16)   # compare another MFMA shape
     for prec in ("bf16", "bf16x3", "f64"):
