@@ -2366,11 +2366,12 @@ int bs_prepare_loop(sgmg_batch* b, int n, double rtol, int maxit, int steps, hip
 // shape's table stays.  st.flags[0, n) must be allocated.
 int bs_tune_mfma(sgmg_batch* b, int n, hipStream_t s) {
   auto& st = b->st;
-  const int shapes[4][2] = {{4, 2}, {4, 4}, {8, 2}, {8, 4}};
-  std::vector<int2> tabs[4];
-  std::vector<int4> geos[4];
+  constexpr int kShapes = 6;
+  const int shapes[kShapes][2] = {{4, 2}, {4, 3}, {4, 4}, {8, 2}, {8, 3}, {8, 4}};
+  std::vector<int2> tabs[kShapes];
+  std::vector<int4> geos[kShapes];
   size_t maxe = 0;
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < kShapes; ++c) {
     for (int i = 0; i < n; ++i) {
       const int4 gm = bs_mfma_geometry(b->hs[b->h_items[i].sys]->lev[0].g, shapes[c][0], shapes[c][1]);
       geos[c].push_back(gm);
@@ -2396,7 +2397,7 @@ int bs_tune_mfma(sgmg_batch* b, int n, hipStream_t s) {
   const BsArgs a{b->d_sys, b->d_items};
   float best = 0.f;
   int bc = -1;
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < kShapes; ++c) {
     SGMG_HIP(hipMemcpyAsync(dtab, tabs[c].data(), tabs[c].size() * sizeof(int2), hipMemcpyHostToDevice, s));
     SGMG_HIP(hipMemcpyAsync(dgeo, geos[c].data(), n * sizeof(int4), hipMemcpyHostToDevice, s));
     BsTable t;
@@ -2516,8 +2517,9 @@ int bs_prepare(sgmg_batch* b, int n, hipStream_t s) {
   // fits it: one table per candidate launch shape (tuned below)
   // (rows 1: the vector-ALU sum/difference-basis operator, whose tiles are
   // those of rows 4)
-  static constexpr int kK64 = 7;
-  static const int k64_shapes[kK64][2] = {{4, 2}, {4, 4}, {4, 8}, {8, 4}, {1, 2}, {1, 4}, {1, 8}};
+  static constexpr int kK64 = 9;
+  static const int k64_shapes[kK64][2] = {{4, 2}, {4, 4}, {4, 8}, {8, 4}, {1, 2}, {1, 3}, {1, 4},
+                                          {1, 6}, {1, 8}};
   auto geo_rows = [](int r) { return r == 1 ? 4 : r; };
   bool mf64 = true;
   for (int i = 0; i < n; ++i) {
