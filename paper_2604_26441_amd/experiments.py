@@ -855,6 +855,38 @@ def traffic(n=80, reps=20):
                       "bf16x3_shapes": TRAFFIC_SHAPES, "level1_nodes": n1 // 3}), flush=True)
 
 
+def l1prof(reps=20):
+    """Workload for counter profiles of the level-1 Galerkin operator from
+    the element products: on the 80^3 and 128^3 cantilevers (rho = 0.5, the
+    bench's 4 levels), reps STORE applications of level 1 at each chunk
+    length in L1PROF_PLANES (3 and 8 planes: the tuned lengths at 80^3 and
+    128^3), random input; then a 1 GiB device copy 4 times (the counter
+    calibration, as in kuprof)."""
+    dev = "cuda:0"
+    for n in (80, 128):
+        rho = torch.full((n * n * n,), 0.5, dtype=torch.float64, device=dev)
+        h = simpgmg.setup_hierarchy(simpgmg.default_options(n, n, n), rho)
+        m = 3 * (n // 2 + 1) ** 3
+        g = torch.Generator(device=dev).manual_seed(n)
+        u = torch.randn(m, dtype=torch.float64, device=dev, generator=g)
+        y = torch.empty_like(u)
+        for planes in L1PROF_PLANES:
+            simpgmg.set_launch_shape(h, "level1", 1, planes)
+            for _ in range(reps):
+                simpgmg.apply_K(h, 1, "f64", u, y)
+        torch.cuda.synchronize()
+        h.close()
+        print(json.dumps({"n": n, "reps": reps, "planes": L1PROF_PLANES}), flush=True)
+    a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(4):
+        b.copy_(a)
+    torch.cuda.synchronize()
+
+
+L1PROF_PLANES = (3, 8)
+
+
 def kuprof(reps=20):
     """Workload for counter profiles of the BF16-family fine K.u: on the 80^3
     and 256^3 cantilevers (rho = 0.5; the 256^3 one with 2 levels, only its
@@ -893,5 +925,6 @@ if __name__ == "__main__":
     {"sizes": sizes, "hetero": hetero, "hetero_oracle": hetero_oracle, "large": large, "kernels": kernels, "batch": batch, "batch_graph": batch_graph,
      "e1": e1, "spectral_proxy": spectral_proxy, "robustness": robustness,
      "ablations": ablations, "sensitivity": sensitivity, "simp_schedule": simp_schedule,
-     "warmstart": warmstart, "traffic": traffic, "kuprof": kuprof, "batchprof": batchprof,
+     "warmstart": warmstart, "traffic": traffic, "kuprof": kuprof, "l1prof": l1prof,
+     "batchprof": batchprof,
      "unetprof": unetprof}[sys.argv[1]]()

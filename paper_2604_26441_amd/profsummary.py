@@ -4,6 +4,7 @@
   python -m paper_2604_26441_amd.profsummary --counters COUNTER_CSV
   python -m paper_2604_26441_amd.profsummary --traffic FETCH_CSV WRITE_CSV
   python -m paper_2604_26441_amd.profsummary --kuprof FETCH_CSV WRITE_CSV SQ_CSV
+  python -m paper_2604_26441_amd.profsummary --l1prof FETCH_CSV WRITE_CSV SQ_CSV
 
 Prints the per-kernel totals (calls, total, average, share) and, with
 --match, the average duration of the last N dispatches whose kernel name
@@ -110,6 +111,46 @@ def kuprof(fetch_csv, write_csv, sq_csv, reps, shapes, meshes=(80, 256)):
                       f"| {util:.3f} |")
 
 
+L1_SQ = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM", "SQ_INSTS_LDS",
+         "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES")
+
+
+def l1prof(fetch_csv, write_csv, sq_csv, reps, planes=(3, 8), meshes=(80, 128)):
+    """Counter summary of the l1prof workload: per mesh and chunk length
+    (dispatch groups of the level-1 element-product kernel in workload
+    order) the calibrated HBM bytes per launch (as kuprof) and the mean of
+    each SQ counter of L1_SQ per dispatch, with the VALU instructions per
+    coarse element (per wave, so per 64 elements)."""
+    f = _dispatches(fetch_csv, "FETCH_SIZE")
+    w = _dispatches(write_csv, "WRITE_SIZE")
+    sq = {c: _dispatches(sq_csv, c) for c in L1_SQ}
+    def pick(rows, pred):
+        return [float(r["Counter_Value"]) for r in rows if pred(r["Kernel_Name"], int(r["Grid_Size"]))]
+    big_copy = lambda n, g: "copyBuffer" in n and g >= 131072
+    cf = 1048576.0 / (sum(pick(f, big_copy)) / len(pick(f, big_copy)))
+    cw = 1048576.0 / (sum(pick(w, big_copy)) / len(pick(w, big_copy)))
+    print(f"calibration: 1 GiB copy, FETCH factor {cf:.4f}, WRITE factor {cw:.4f}")
+    l1 = lambda n, g: "k_apply_l1_haar<" in n
+    fk, wk = pick(f, l1), pick(w, l1)
+    sk = {c: pick(v, l1) for c, v in sq.items()}
+    print("| mesh | planes | calibrated bytes per launch | " + " | ".join(L1_SQ) +
+          " | VALU instructions per coarse element x 64 |")
+    print("|---|---|---|" + "---|" * len(L1_SQ) + "---|")
+    i = 0
+    for n in meshes:
+        ne = (n // 2) ** 3
+        for z in planes:
+            sl = slice(i * reps, (i + 1) * reps)
+            i += 1
+            a, b = fk[sl], wk[sl]
+            if min(len(a), len(b)) < reps or any(len(v[sl]) < reps for v in sk.values()):
+                return
+            byts = round(1024 * (sum(a) / reps * cf + sum(b) / reps * cw))
+            means = [sum(sk[c][sl]) / reps for c in L1_SQ]
+            print(f"| {n}^3 | {z} | {byts} | " + " | ".join(f"{m:.0f}" for m in means) +
+                  f" | {means[1] * 64 / ne:.0f} |")
+
+
 def counters(path):
     acc = defaultdict(lambda: defaultdict(list))
     with open(path) as fh:
@@ -203,6 +244,7 @@ def main():
     ap.add_argument("--counters", default=None)
     ap.add_argument("--traffic", nargs=2, default=None, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--kuprof", nargs=3, default=None, metavar=("FETCH_CSV", "WRITE_CSV", "SQ_CSV"))
+    ap.add_argument("--l1prof", nargs=3, default=None, metavar=("FETCH_CSV", "WRITE_CSV", "SQ_CSV"))
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--match", default=None)
     ap.add_argument("--last", type=int, default=200)
@@ -217,6 +259,9 @@ def main():
     shapes = [(r, z) for r in (4, 8) for z in (2, 4, 8, 16, 32)]
     if a.traffic:
         traffic(a.traffic[0], a.traffic[1], a.reps, shapes)
+        return
+    if a.l1prof:
+        l1prof(a.l1prof[0], a.l1prof[1], a.l1prof[2], a.reps)
         return
     if a.kuprof:
         kuprof(a.kuprof[0], a.kuprof[1], a.kuprof[2], a.reps, shapes)
