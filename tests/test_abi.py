@@ -109,3 +109,29 @@ def test_batch_item_layout_fits_its_allocation():
     import pytest
     with pytest.raises(simpgmg.SimpGmgError):
         simpgmg.batch_item_layout([100], 10)
+
+
+def test_one_launch_batch_solve_checks_arguments_before_device_work():
+    """sgmg_pcg_solve_batch_graph rejects a missing batch and a step count
+    that is odd, below 2 or above 1024 with SGMG_EINVAL from its argument
+    checks alone: the batch pointer (here a dummy) is not dereferenced."""
+    from paper_2604_26441_amd import simpgmg
+    lib = ctypes.CDLL(simpgmg.library_path())
+    fn = lib.sgmg_pcg_solve_batch_graph
+    fn.restype = ctypes.c_int
+    vp = ctypes.c_void_p
+    fn.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp),
+                   ctypes.POINTER(vp), ctypes.c_double, ctypes.c_int, ctypes.c_int, vp,
+                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), vp]
+    lib.sgmg_last_error.restype = ctypes.c_char_p
+    sysarr = (ctypes.c_int * 1)(0)
+    fa = (vp * 1)(64)
+    ua = (vp * 1)(128)
+    nl, ms = ctypes.c_int(-7), ctypes.c_double(-1.0)
+    cases = [(None, 2), (vp(64), 0), (vp(64), 3), (vp(64), 1026), (vp(64), -2)]
+    for b, steps in cases:
+        rc = fn(b, 1, sysarr, fa, ua, 1e-6, 10, steps, None, ctypes.byref(nl), ctypes.byref(ms),
+                None)
+        assert rc == -1, (b, steps)
+        assert b"bad batch solve arguments" in lib.sgmg_last_error()
+    assert nl.value == -7 and ms.value == -1.0       # outputs untouched on rejection
