@@ -133,6 +133,12 @@ def test_batch_config3_every_item_meets_the_oracle():
     ug = [t64(np.zeros_like(f)) for f in fs]
     resg, _ = simpgmg.pcg_solve_batch(b, item_sys, [t64(f) for f in fs], ug, rtol=1e-6, maxit=300,
                                       staged=True)
+    # the FP32 staged solve in one graph launch: bitwise the host-loop one
+    ugg = [t64(np.zeros_like(f)) for f in fs]
+    resgg, _, nl = simpgmg.pcg_solve_batch_graph(b, item_sys, [t64(f) for f in fs], ugg,
+                                                 rtol=1e-6, maxit=300, steps=128)
+    assert nl == 1
+    _same_results(resg, ug, resgg, ugg)
     b.close()
     # the staged solve again with BF16X3 fine levels (MFMA level 0, tuned shapes)
     opts = [simpgmg.default_options(*d, n_levels=0, dense_max=1000, fine_prec="bf16x3") for d in dims]
